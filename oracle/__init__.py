@@ -1,0 +1,180 @@
+"""CPU oracle for the temporal path-motif sieve.
+
+TEST INFRASTRUCTURE ONLY: imported by tests, by the smoke check and by the
+bench's CPU-baseline leg.  The product package never imports it, and it imports
+nothing from the product package.
+
+Two independent layers live here:
+  * `liboracle.so` (tpm_oracle.c): the edge-by-edge evaluation of the temporal
+    generating polynomial, Eq. (3), at sieve points, with the constrained
+    substitution of Eq. (motif); plus an exact colourful-path existence check.
+  * `pyref` (pure Python): brute-force walk enumeration, the literal t-by-n
+    recursion of Eq. (3), GF(2^8) by polynomial long division, determinants,
+    the path checker and the closed-form false-negative rate.  These pin the C
+    oracle.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_lib = None
+
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_u8p = ctypes.POINTER(ctypes.c_uint8)
+_u32p = ctypes.POINTER(ctypes.c_uint32)
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = os.path.join(_HERE, "liboracle.so")
+        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(
+                os.path.join(_HERE, "tpm_oracle.c")):
+            _build.build()
+        L = ctypes.CDLL(path)
+        L.or_init.restype = None
+        L.or_gf_mul_bits.restype = ctypes.c_uint8
+        L.or_gf_mul_bits.argtypes = [ctypes.c_uint8, ctypes.c_uint8]
+        L.or_gf_mul.restype = ctypes.c_uint8
+        L.or_gf_mul.argtypes = [ctypes.c_uint8, ctypes.c_uint8]
+        L.or_mul_table.argtypes = [_u8p]
+        L.or_mix64.restype = ctypes.c_uint64
+        L.or_mix64.argtypes = [ctypes.c_uint64]
+        L.or_fp.restype = ctypes.c_uint8
+        L.or_fp.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32]
+        L.or_slots.argtypes = [_i32p, ctypes.c_int32, ctypes.c_int32, _i32p, _i32p]
+        L.or_z.argtypes = [ctypes.c_int32, _i32p, ctypes.c_int32, _i32p, ctypes.c_int32,
+                           ctypes.c_uint64, _u8p, _u8p]
+        L.or_index_build.restype = ctypes.c_void_p
+        L.or_index_build.argtypes = [ctypes.c_int32, ctypes.c_int64, _i32p, _i32p, _i32p]
+        L.or_index_free.argtypes = [ctypes.c_void_p]
+        L.or_eval.argtypes = [ctypes.c_void_p, _u8p, ctypes.c_int32, ctypes.c_uint64, _u32p,
+                              ctypes.c_int64, _u8p, _u8p, ctypes.c_int]
+        L.or_sieve.argtypes = [ctypes.c_int32, ctypes.c_int64, _i32p, _i32p, _i32p, _i32p,
+                               ctypes.c_int32, _i32p, ctypes.c_int32, ctypes.c_uint64, _u8p,
+                               _u32p, ctypes.c_int64, _u8p, _u8p, ctypes.c_int]
+        L.or_colorful_exists.argtypes = [ctypes.c_int32, ctypes.c_int64, _i32p, _i32p, _i32p,
+                                         _i32p, ctypes.c_int32, _i32p, ctypes.c_int32]
+        L.or_init()
+        _lib = L
+    return _lib
+
+
+def _p(a, t):
+    return a.ctypes.data_as(t) if a is not None else ctypes.cast(None, t)
+
+
+def _c32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def gf_mul_bits(a: int, b: int) -> int:
+    return int(lib().or_gf_mul_bits(a, b))
+
+
+def mul_table() -> np.ndarray:
+    t = np.empty((256, 256), dtype=np.uint8)
+    lib().or_mul_table(t.ctypes.data_as(_u8p))
+    return t
+
+
+def mix64(x: int) -> int:
+    return int(lib().or_mix64(x & 0xFFFFFFFFFFFFFFFF))
+
+
+def fp(seed: int, tag: int, a: int, b: int) -> int:
+    return int(lib().or_fp(seed & 0xFFFFFFFFFFFFFFFF, tag, a, b))
+
+
+def slots(M, q: int):
+    M = _c32(M)
+    off = np.empty(q, dtype=np.int32)
+    mu = np.empty(q, dtype=np.int32)
+    rc = lib().or_slots(_p(M, _i32p), len(M), q, _p(off, _i32p), _p(mu, _i32p))
+    if rc:
+        raise ValueError("multiset names a colour outside [0, q)")
+    return off, mu
+
+
+def zvals(g, M, seed: int, mask=None) -> np.ndarray:
+    M = _c32(M)
+    k = len(M)
+    z = np.empty((g.n, k), dtype=np.uint8)
+    color = _c32(g.color)
+    mk = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8)
+    rc = lib().or_z(g.n, _p(color, _i32p), g.num_colors, _p(M, _i32p), k,
+                    seed & 0xFFFFFFFFFFFFFFFF, _p(mk, _u8p), _p(z, _u8p))
+    if rc:
+        raise ValueError("bad query")
+    return z
+
+
+def sieve(g, M, seed: int, points=None, mask=None, loc: bool = False, nthreads: int = 0):
+    """P(A) for the given sieve points (default: all 2^k).  Returns the per-point
+    array, or (per_point, per_edge_localisation) when loc=True (localisation is
+    XOR-ed over the given points)."""
+    M = _c32(M)
+    k = len(M)
+    if points is None:
+        points = np.arange(1 << k, dtype=np.uint32)
+    points = np.ascontiguousarray(points, dtype=np.uint32)
+    out = np.empty(points.shape[0], dtype=np.uint8)
+    lc = np.empty(g.m, dtype=np.uint8) if loc else None
+    src, dst, tau, color = _c32(g.src), _c32(g.dst), _c32(g.tau), _c32(g.color)
+    mk = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8)
+    rc = lib().or_sieve(g.n, g.m, _p(src, _i32p), _p(dst, _i32p), _p(tau, _i32p),
+                        _p(color, _i32p), g.num_colors, _p(M, _i32p), k,
+                        seed & 0xFFFFFFFFFFFFFFFF, _p(mk, _u8p), _p(points, _u32p),
+                        points.shape[0], _p(out, _u8p), _p(lc, _u8p), nthreads)
+    if rc:
+        raise RuntimeError(f"oracle failed ({rc})")
+    return (out, lc) if loc else out
+
+
+def sieve_total(g, M, seed: int, mask=None, nthreads: int = 0) -> int:
+    pp = sieve(g, M, seed, mask=mask, nthreads=nthreads)
+    return int(np.bitwise_xor.reduce(pp)) if pp.size else 0
+
+
+class Index:
+    """Reusable oracle index (in-lists sorted by time) for repeated evaluations;
+    keeps references to the arrays it borrows."""
+
+    def __init__(self, g):
+        self.g = g
+        self._src, self._dst, self._tau = _c32(g.src), _c32(g.dst), _c32(g.tau)
+        self._h = lib().or_index_build(g.n, g.m, _p(self._src, _i32p), _p(self._dst, _i32p),
+                                       _p(self._tau, _i32p))
+        if not self._h:
+            raise MemoryError("oracle index")
+
+    def eval(self, M, seed: int, points, mask=None, nthreads: int = 0) -> np.ndarray:
+        z = zvals(self.g, M, seed, mask)
+        points = np.ascontiguousarray(points, dtype=np.uint32)
+        out = np.empty(points.shape[0], dtype=np.uint8)
+        rc = lib().or_eval(ctypes.c_void_p(self._h), _p(z, _u8p), len(M),
+                           seed & 0xFFFFFFFFFFFFFFFF, _p(points, _u32p), points.shape[0],
+                           _p(out, _u8p), None, nthreads)
+        if rc:
+            raise RuntimeError(f"oracle failed ({rc})")
+        return out
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            lib().or_index_free(ctypes.c_void_p(self._h))
+            self._h = None
+
+
+def colorful_exists(g, M) -> int:
+    M = _c32(M)
+    src, dst, tau, color = _c32(g.src), _c32(g.dst), _c32(g.tau), _c32(g.color)
+    return int(lib().or_colorful_exists(g.n, g.m, _p(src, _i32p), _p(dst, _i32p),
+                                        _p(tau, _i32p), _p(color, _i32p), g.num_colors,
+                                        _p(M, _i32p), len(M)))

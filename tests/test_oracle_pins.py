@@ -1,0 +1,313 @@
+"""Pins for the CPU oracle's sieve values (CPU only).
+
+The oracle evaluates Eq. (3) edge by edge.  It is checked here against what the
+paper and the mathematics fix: the worked example of the temporal generating
+polynomial, brute-force enumeration of temporal walks, the literal t-by-n
+recursion, the sieve-equals-determinant identity, no false positives, the
+closed-form false-negative rate, an exact colourful-path decision and the
+NP-hardness construction with a known answer.
+"""
+
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import pyref
+from synth import graphs as G
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_toy_walks.txt")
+
+
+# --------------------------------------------------------------------------- sieve identity
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 6])
+def test_sieve_sum_is_determinant(k):
+    """sum_A prod_s (sum_{j in A} Z[s][j]) = det Z over GF(2^8) (char. 2)."""
+    rng = np.random.default_rng(100 + k)
+    T = pyref.mul_table()
+    for _ in range(20):
+        Z = rng.integers(0, 256, (k, k))
+        tot = 0
+        for A in range(1 << k):
+            p = 1
+            for s in range(k):
+                v = 0
+                for j in range(k):
+                    if (A >> j) & 1:
+                        v ^= int(Z[s, j])
+                p = int(T[p, v])
+            tot ^= p
+        assert tot == pyref.det(Z)
+        if k >= 2:
+            Z2 = Z.copy()
+            Z2[1] = Z2[0]
+            assert pyref.det(Z2) == 0
+
+
+def test_det_multiplicative():
+    rng = np.random.default_rng(5)
+    T = pyref.mul_table()
+    for k in (2, 3, 4):
+        for _ in range(10):
+            V = rng.integers(0, 256, (k, k))
+            W = rng.integers(0, 256, (k, k))
+            VW = np.zeros((k, k), dtype=np.int64)
+            for i in range(k):
+                for j in range(k):
+                    s = 0
+                    for d in range(k):
+                        s ^= int(T[V[i, d], W[d, j]])
+                    VW[i, j] = s
+            assert pyref.det(VW) == pyref.gmul(pyref.det(V), pyref.det(W))
+
+
+# --------------------------------------------------------------------------- z, slots
+def test_slots_and_z_match_python():
+    rng = np.random.default_rng(3)
+    g = G.random_tiny_graph(rng, n_max=30, q_max=5)
+    for M in ([0, 0, 1], [2], [1, 3, 3, 0], [0, 1, 2, 3, 4]):
+        M = [c % g.num_colors for c in M]
+        off, mu = oracle.slots(M, g.num_colors)
+        poff, pmu = pyref.slots(M, g.num_colors)
+        assert list(mu) == pmu
+        assert [o for o, u in zip(off, mu) if u] == [o for o, u in zip(poff, pmu) if u]
+        assert sum(pmu) == len(M)
+        for seed in (1, 99):
+            assert np.array_equal(oracle.zvals(g, M, seed), pyref.zvals(g, M, seed))
+
+
+def test_z_zero_outside_multiset_and_masked():
+    rng = np.random.default_rng(4)
+    g = G.random_tiny_graph(rng, n_max=20, q_max=4)
+    M = [0, 0]
+    mask = (rng.random(g.n) < 0.7).astype(np.uint8)
+    z = oracle.zvals(g, M, 11, mask)
+    for u in range(g.n):
+        if g.color[u] != 0 or not mask[u]:
+            assert not z[u].any()
+
+
+# --------------------------------------------------------------------------- worked example
+def _parse_golden():
+    P, paths = {}, None
+    for line in open(GOLDEN):
+        line = line.strip()
+        if not line or line.startswith("#"):
+            continue
+        lhs, rhs = line.split("=")
+        toks = lhs.split()
+        walks = [] if rhs.strip() == "empty" else [w.split() for w in rhs.split("|")]
+        if toks[0] == "P":
+            P[(int(toks[1]), int(toks[2]), int(toks[3]))] = walks
+        else:
+            paths = walks
+    return P, paths
+
+
+def _arc_id(g, a, b, j):
+    ids = [e for e in range(g.m) if g.src[e] == a and g.dst[e] == b and g.tau[e] == j]
+    assert len(ids) == 1
+    return ids[0]
+
+
+def test_worked_example_polynomials():
+    """Every P_{u,l,i} of the paper's figure, evaluated at random points, equals
+    the literal Eq. (3) recursion on the same graph."""
+    g = G.paper_toy_graph()
+    Pg, _ = _parse_golden()
+    T = pyref.mul_table()
+    rng = np.random.default_rng(0)
+    for seed in (1, 2, 3):
+        X = rng.integers(0, 256, (3, 64)).astype(np.uint8)  # arbitrary vertex values
+        P = pyref.literal_eq3_table(g, [0, 0, 0], seed, X=X)
+        for (u, l, i), walks in Pg.items():
+            val = np.zeros(64, dtype=np.uint8)
+            for w in walks:
+                if l == 1:
+                    val ^= X[int(w[0]) - 1]
+                    continue
+                arcs = [(int(a.split(">")[0]), int(a.split(">")[1].split("@")[0]),
+                         int(a.split("@")[1])) for a in w]
+                assert len(arcs) == l - 1
+                v = X[arcs[0][0] - 1].copy()
+                for pos, (a, b, j) in enumerate(arcs, start=1):
+                    v = T[v, pyref.fp(seed, pyref.TAG_Y, pos, _arc_id(g, a - 1, b - 1, j))]
+                    v = T[v, X[b - 1]]
+                val ^= v
+            assert np.array_equal(P[l, u - 1, i], val), (u, l, i)
+
+
+def test_worked_example_paths_and_sieve():
+    g = G.paper_toy_graph()
+    _, paths = _parse_golden()
+    walks3 = pyref.temporal_walks(g, 3)
+    multilinear = sorted(tuple(e for e in edges) for verts, edges in walks3
+                         if len(set(verts)) == 3)
+    listed = sorted(tuple(_arc_id(g, int(a.split(">")[0]) - 1,
+                                  int(a.split(">")[1].split("@")[0]) - 1,
+                                  int(a.split("@")[1])) for a in w) for w in paths)
+    assert multilinear == listed
+    for seed in range(1, 40):
+        pp = oracle.sieve(g, [0, 0, 0], seed)
+        assert np.array_equal(pp, pyref.literal_eq3_per_point(g, [0, 0, 0], seed))
+        assert int(np.bitwise_xor.reduce(pp)) == pyref.brute_paths_total(g, [0, 0, 0], seed)
+        # times are only 1 and 2: no temporal path has 4 vertices, for every seed
+        assert oracle.sieve_total(g, [0, 0, 0, 0], seed) == 0
+
+
+# --------------------------------------------------------------------------- brute force
+def test_oracle_equals_walk_enumeration_random_tiny():
+    rng = np.random.default_rng(2024)
+    for it in range(600):
+        g = G.random_tiny_graph(rng, n_max=10, m_max=30, t_max=5, q_max=3)
+        k = int(rng.integers(1, 6))
+        M = [int(c) for c in rng.integers(0, g.num_colors, k)]
+        seed = int(rng.integers(0, 2**62))
+        mask = None if it % 3 else (rng.random(g.n) < 0.8).astype(np.uint8)
+        got = oracle.sieve(g, M, seed, mask=mask)
+        want = pyref.brute_per_point(g, M, seed, mask)
+        assert np.array_equal(got, want), (it, k)
+        assert int(np.bitwise_xor.reduce(got)) == pyref.brute_paths_total(g, M, seed, mask)
+
+
+def test_oracle_equals_literal_recursion():
+    rng = np.random.default_rng(77)
+    for it in range(60):
+        g = G.random_tiny_graph(rng, n_max=8, m_max=20, t_max=5, q_max=3)
+        k = int(rng.integers(1, 5))
+        M = [int(c) for c in rng.integers(0, g.num_colors, k)]
+        seed = int(rng.integers(0, 2**62))
+        assert np.array_equal(oracle.sieve(g, M, seed), pyref.literal_eq3_per_point(g, M, seed))
+
+
+def test_localisation_sums_to_total():
+    rng = np.random.default_rng(8)
+    for _ in range(50):
+        g = G.random_tiny_graph(rng, n_max=10, m_max=30)
+        k = int(rng.integers(2, 5))
+        M = [int(c) for c in rng.integers(0, g.num_colors, k)]
+        pp, loc = oracle.sieve(g, M, 5, loc=True)
+        assert int(np.bitwise_xor.reduce(pp)) == (int(np.bitwise_xor.reduce(loc)) if g.m else 0)
+        # localisation = sum over paths whose last edge is e
+        z = pyref.zvals(g, M, 5)
+        want = np.zeros(g.m, dtype=np.uint8)
+        for verts, edges in pyref.temporal_walks(g, k):
+            if len(set(verts)) != k:
+                continue
+            y = 1
+            for l, e in enumerate(edges, start=1):
+                y = pyref.gmul(y, pyref.fp(5, 1, l, e))
+            want[edges[-1]] ^= pyref.gmul(y, pyref.det([z[u] for u in verts]))
+        assert np.array_equal(loc, want)
+
+
+# --------------------------------------------------------------------------- one-sided error
+def test_no_false_positives():
+    rng = np.random.default_rng(31)
+    checked = 0
+    while checked < 60:
+        g = G.random_tiny_graph(rng, n_max=9, m_max=14, t_max=4, q_max=3)
+        k = int(rng.integers(2, 5))
+        M = [int(c) for c in rng.integers(0, g.num_colors, k)]
+        if pyref.has_matching_path(g, M):
+            continue
+        checked += 1
+        for seed in range(1, 30):
+            assert oracle.sieve_total(g, M, seed) == 0
+
+
+def _unique_path_graph(M):
+    k = len(M)
+    src = np.arange(k - 1, dtype=np.int32)
+    dst = np.arange(1, k, dtype=np.int32)
+    tau = np.arange(1, k, dtype=np.int32)
+    # a decoy edge going backwards in time adds walks but no second path
+    src = np.append(src, k - 1).astype(np.int32)
+    dst = np.append(dst, 0).astype(np.int32)
+    tau = np.append(tau, 1).astype(np.int32)
+    return G.TemporalGraph(k, src, dst, tau, np.array(M, dtype=np.int32), max(M) + 1)
+
+
+@pytest.mark.parametrize("M", [[0, 0, 1, 2], [0, 1, 2, 3, 4]])
+def test_false_negative_rate_unique_witness(M):
+    g = _unique_path_graph(M)
+    assert sum(1 for v, e in pyref.temporal_walks(g, len(M))
+               if len(set(v)) == len(M) and sorted(g.color[list(v)]) == sorted(M)) == 1
+    N = 12000
+    hits = sum(1 for s in range(N) if oracle.sieve_total(g, M, 10_000 + s) != 0)
+    p = pyref.unique_witness_detect_prob(M)
+    sd = (p * (1 - p) / N) ** 0.5
+    assert abs(hits / N - p) < 4.5 * sd, (hits / N, p)
+
+
+# --------------------------------------------------------------------------- exact deciders
+def test_colorful_dp_matches_brute_force():
+    rng = np.random.default_rng(12)
+    for _ in range(300):
+        g = G.random_tiny_graph(rng, n_max=9, m_max=25, t_max=5, q_max=5)
+        k = int(rng.integers(1, min(5, g.num_colors) + 1))
+        M = [int(c) for c in rng.choice(g.num_colors, k, replace=False)]
+        assert oracle.colorful_exists(g, M) == int(pyref.has_matching_path(g, M))
+
+
+def test_decide_agrees_with_colorful_dp_medium():
+    rng = np.random.default_rng(13)
+    for _ in range(20):
+        g = G.uniform_graph(200, 600, 30, 6, int(rng.integers(0, 2**31)))
+        M = [int(c) for c in rng.choice(6, 4, replace=False)]
+        exists = oracle.colorful_exists(g, M)
+        found = any(oracle.sieve_total(g, M, s) for s in range(1, 6))
+        if found:
+            assert exists == 1  # a nonzero sieve is a certificate
+        if not exists:
+            assert not found
+
+
+def test_hardness_construction_known_answers():
+    # static path 0-1-2-3 (has a 4-vertex path) vs a star (no 4-vertex path)
+    yes = G.static_to_temporal_layers(4, [(0, 1), (1, 2), (2, 3)], 4)
+    no = G.static_to_temporal_layers(4, [(0, 1), (0, 2), (0, 3)], 4)
+    assert any(oracle.sieve_total(yes, [0] * 4, s) for s in range(1, 8))
+    for s in range(1, 30):
+        assert oracle.sieve_total(no, [0] * 4, s) == 0
+
+
+# --------------------------------------------------------------------------- invariants
+def test_invariants_bit_exact():
+    rng = np.random.default_rng(21)
+    for _ in range(40):
+        g = G.random_tiny_graph(rng, n_max=10, m_max=30)
+        k = int(rng.integers(1, 5))
+        M = [int(c) for c in rng.integers(0, g.num_colors, k)]
+        base = oracle.sieve(g, M, 9)
+        assert np.array_equal(oracle.sieve(G.relabel_timestamps(g, rng), M, 9), base)
+        if k >= 2:  # for k = 1 every vertex is itself a one-vertex path
+            assert np.array_equal(oracle.sieve(G.append_isolated(g, 5, rng), M, 9), base)
+        # masking a vertex == giving it a colour outside the multiset
+        u = int(rng.integers(0, g.n))
+        mask = np.ones(g.n, dtype=np.uint8)
+        mask[u] = 0
+        h = g.copy()
+        h.num_colors = g.num_colors + 1
+        h.color[u] = g.num_colors
+        assert np.array_equal(oracle.sieve(g, M, 9, mask=mask), oracle.sieve(h, M, 9))
+
+
+def test_path_checker():
+    rng = np.random.default_rng(41)
+    n_ok = 0
+    for _ in range(100):
+        g = G.random_tiny_graph(rng, n_max=8, m_max=25)
+        k = int(rng.integers(2, 5))
+        for verts, edges in pyref.temporal_walks(g, k):
+            M = [int(g.color[v]) for v in verts]
+            ok = pyref.check_path(g, M, verts, edges)
+            assert ok == (len(set(verts)) == k)
+            n_ok += ok
+            if ok and k > 2:
+                assert not pyref.check_path(g, M, verts[::-1], edges[::-1])
+                bad = list(M)
+                bad[0] = (bad[0] + 1) % (g.num_colors + 1)
+                assert not pyref.check_path(g, bad, verts, edges)
+    assert n_ok > 50
