@@ -1,0 +1,200 @@
+/*
+ * tpm.h -- C ABI of the MI355X temporal path-motif sieve (libtpm.so).
+ *
+ * Problem (paper: Thejaswi, Gionis, Lauri, "Finding path motifs in large
+ * temporal graphs using algebraic fingerprints", section "Path problems in
+ * temporal graphs", problem PATH-MOTIF): given a directed temporal graph whose
+ * vertices carry colours and a multiset M of k colours, decide whether a
+ * temporal path (k distinct vertices, k-1 edges with strictly increasing
+ * timestamps) exists whose vertex colours are exactly M, and extract one.
+ *
+ * Method (section "Algebraic algorithm"): evaluate the temporal generating
+ * polynomial of Eq. (3) at the 2^k points of the constrained multilinear sieve
+ * (Lemma "constrained multilinear sieving", Eq. (motif)) over GF(2^8) with
+ * random fingerprints, and XOR the 2^k values into one field element Q.
+ * Q != 0 certifies a matching path (no false positives); Q == 0 may be a false
+ * negative with probability at most (3k-1)/256 per seed, so decisions repeat
+ * with derived seeds.
+ *
+ * Conventions shared by every call:
+ *   - Edge e is (src[e] -> dst[e]) at time tau[e] >= 1; e is its index in the
+ *     caller's arrays.  Walks follow edges forward; consecutive edges need
+ *     strictly increasing timestamps.  Duplicate edges and self-loops are
+ *     accepted (each edge is its own variable; self-loops never lie on a path).
+ *   - Field GF(2^8), modulus x^8 + x^4 + x^3 + x^2 + 1 (0x11D).
+ *   - Sieve point A in [0, 2^k): bit j of A set <=> label j in A.
+ *   - Fingerprints: fp(seed, tag, a, b) = low 8 bits of
+ *       mix64(seed ^ mix64((tag << 56) ^ (a << 32) ^ b)),
+ *     mix64 = the SplitMix64 output function.  y_{e,l} = fp(seed, 1, l, e)
+ *     (walk position l = 1..k-1), v_{u,d} = fp(seed, 2, d, u), w_{d,j} =
+ *     fp(seed, 3, d, j).  Slots: the distinct colours of M in ascending order,
+ *     colour s owning mu(s) consecutive slot indices d.
+ *   - Status codes: 0 = OK, > 0 = a non-error outcome, < 0 = error; on error
+ *     tpm_last_error() describes it.  No C++ exception crosses this ABI.
+ *   - Host pointers unless stated otherwise.  `hip_stream` arguments take a
+ *     hipStream_t (NULL = the default stream).
+ *   - A graph handle is immutable after creation; calls on one handle from
+ *     several host threads are allowed (each call brings its own workspace).
+ */
+#ifndef TPM_H
+#define TPM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t tpm_status;
+
+#define TPM_OK 0
+#define TPM_NOTFOUND 1   /* extraction: no path found within the repetitions */
+#define TPM_PENDING 2    /* server poll: no result ready */
+#define TPM_EINVAL (-1)  /* invalid argument or malformed input */
+#define TPM_ENOMEM (-2)  /* device or host allocation failed */
+#define TPM_EDEVICE (-3) /* HIP runtime error or a kernel-reported fault */
+#define TPM_ECANCELLED (-4)
+#define TPM_ECLOSED (-5) /* server is shutting down */
+
+/* graph creation flags */
+#define TPM_DEVICE_PTRS 0x1u /* src/dst/tau/color are device pointers */
+
+typedef struct tpm_graph tpm_graph;
+
+/* Work-tile shape of the in-edge index, fixed at graph creation.
+ * tile_edges: most CSR positions per tile (1..64, default 64).
+ * tile_held:  most stored state rows in a tile that continues a segment begun
+ *             in an earlier tile (1..16, default 8).  Zero = default. */
+typedef struct {
+    int32_t tile_edges;
+    int32_t tile_held;
+} tpm_graph_options;
+
+typedef struct {
+    int32_t n;
+    int64_t m;
+    int32_t num_colors;
+    int32_t tmax;
+    int64_t rows;          /* R: CSR positions whose running value a later edge reads */
+    int64_t tiles;         /* work tiles */
+    int64_t slots;         /* tiles that publish a running value to a successor */
+    int64_t max_in_degree;
+    int64_t device_bytes;  /* device memory held by the index */
+} tpm_graph_stats;
+
+/* Per-call tuning.  chunk: sieve points per pass (power of two, 4..1024; 0 =
+ * min(2^k, 1024)).  waves_per_cu: reserved (0).  Every admissible setting gives
+ * bit-identical results. */
+typedef struct {
+    int32_t chunk;
+    int32_t waves_per_cu;
+} tpm_tuning;
+
+/* ---------------------------------------------------------------- graph --- */
+/* Build the device-resident in-edge index of a temporal graph (the edge list of
+ * the paper's terminology section, plus the vertex colouring of PATH-MOTIF).
+ * n >= 1 vertices, m >= 0 edges (m < 2^31), arrays src/dst/tau of length m,
+ * color of length n, 0 <= src, dst < n, tau >= 1, 0 <= color < num_colors.
+ * Inputs are copied; with TPM_DEVICE_PTRS they are device pointers on the current
+ * device.  `opt` may be NULL.  On success *out owns all device memory.
+ * Errors: TPM_EINVAL (bad sizes or values), TPM_ENOMEM, TPM_EDEVICE. */
+tpm_status tpm_graph_create(int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                            const int32_t *tau, const int32_t *color, int32_t num_colors,
+                            uint32_t flags, tpm_graph **out);
+tpm_status tpm_graph_create_ex(int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                               const int32_t *tau, const int32_t *color, int32_t num_colors,
+                               uint32_t flags, const tpm_graph_options *opt, tpm_graph **out);
+
+/* Free a graph and everything it owns.  NULL is accepted. */
+void tpm_graph_destroy(tpm_graph *g);
+
+/* Sizes of a built index.  Errors: TPM_EINVAL. */
+tpm_status tpm_graph_stats_get(const tpm_graph *g, tpm_graph_stats *out);
+
+/* ---------------------------------------------------------------- sieve --- */
+/* Evaluate the sieve for one query (Lemma "constrained multilinear sieving"):
+ * per_point[A] = P_{k,t}(z^A) for A in [0, 2^k) (nullable, 2^k bytes) and
+ * *total = XOR of all of them (nullable).  multiset: k colour ids, 1 <= k <= 16.
+ * vertex_mask (nullable, n bytes): 0 deletes the vertex (its variable x_u = 0).
+ * Blocks until the results are on the host.
+ * Errors: TPM_EINVAL (k out of range, colour out of range), TPM_ENOMEM,
+ * TPM_EDEVICE. */
+tpm_status tpm_sieve(const tpm_graph *g, const int32_t *multiset, int32_t k, uint64_t seed,
+                     const uint8_t *vertex_mask, uint8_t *per_point, uint8_t *total,
+                     void *hip_stream);
+
+/* As tpm_sieve, plus tuning (nullable) and the per-edge localisation
+ * loc[e] = sum over A of the level-k term of edge e (nullable, m bytes, indexed by
+ * input edge id): loc[e] != 0 certifies a matching path whose last edge is e
+ * (the edge-level form of the paper's vertex-localisation). */
+tpm_status tpm_sieve_ex(const tpm_graph *g, const int32_t *multiset, int32_t k, uint64_t seed,
+                        const uint8_t *vertex_mask, const tpm_tuning *tune, uint8_t *per_point,
+                        uint8_t *total, uint8_t *loc, void *hip_stream);
+
+/* Decide PATH-MOTIF: run up to `reps` sieves with seeds seed_r = seed + r *
+ * 0x9E3779B97F4A7C15 and stop at the first nonzero total.  *found = 1 is
+ * certain; *found = 0 means no sieve detected a path.  reps >= 1. */
+tpm_status tpm_decide(const tpm_graph *g, const int32_t *multiset, int32_t k, uint64_t seed,
+                      int32_t reps, int32_t *found);
+
+/* Extract a matching temporal path by self-reduction (section "Extracting a
+ * solution"): localise the last edge (u' -> u, tau), delete u, drop c(u) from
+ * M, and repeat on the in-edges of u' earlier than tau until one vertex is left.
+ * On TPM_OK, path_vertices[0..k) and path_edges[0..k-1) (input edge ids) hold a
+ * path that the library has verified (strictly increasing times, distinct
+ * vertices, colours = M).  TPM_NOTFOUND: no path found within max_reps seeds
+ * per step.  Deterministic for a fixed seed. */
+tpm_status tpm_extract(const tpm_graph *g, const int32_t *multiset, int32_t k, uint64_t seed,
+                       int32_t max_reps, int32_t *path_vertices, int64_t *path_edges);
+
+/* ---------------------------------------------------------------- batch --- */
+typedef struct {
+    const int32_t *multiset; /* k colours */
+    int32_t k;
+    uint64_t seed;
+    int32_t want_path;       /* 1: extract a path when the sieve is nonzero */
+} tpm_query;
+
+typedef struct {
+    int32_t found;           /* 1 iff the sieve total was nonzero */
+    uint8_t total;
+    int32_t path_status;     /* TPM_OK / TPM_NOTFOUND / 0 when not requested */
+    int32_t path_vertices[16];
+    int64_t path_edges[15];
+    uint64_t ticket;         /* server: the submit ticket */
+    double t_submit_ms, t_start_ms, t_done_ms; /* server: host clock, ms */
+} tpm_result;
+
+/* Run nq queries against one graph.  Each result is bit-identical to the same
+ * query run alone through tpm_sieve (same seed).  tune may be NULL. */
+tpm_status tpm_batch_run(const tpm_graph *g, int32_t nq, const tpm_query *q, tpm_result *out,
+                         const tpm_tuning *tune);
+
+/* ---------------------------------------------------------------- serve --- */
+typedef struct tpm_server tpm_server;
+
+typedef struct {
+    int64_t state_bytes;   /* device memory the server may use for query state (0 = auto) */
+    int32_t max_lanes;     /* most sieve lanes resident at once (0 = auto) */
+    int32_t extract_paths; /* 1: extract a witness for every YES */
+} tpm_server_config;
+
+tpm_status tpm_server_create(const tpm_graph *g, const tpm_server_config *cfg, tpm_server **out);
+tpm_status tpm_server_submit(tpm_server *s, const tpm_query *q, uint64_t *ticket);
+/* Copy up to max finished results into out; *n_out = how many. TPM_PENDING if
+ * none is ready yet. */
+tpm_status tpm_server_poll(tpm_server *s, tpm_result *out, int32_t max, int32_t *n_out);
+void tpm_server_destroy(tpm_server *s);
+
+/* ---------------------------------------------------------------- misc --- */
+/* Description of the last error on the calling thread ("" if none). */
+const char *tpm_last_error(void);
+
+/* Library version string. */
+const char *tpm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TPM_H */

@@ -1,0 +1,311 @@
+// C ABI entry points (include/tpm.h): argument checks, error reporting, decide and
+// extraction by self-reduction.  No exception crosses the ABI.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+#include <set>
+#include <string>
+
+#include "tpm_internal.h"
+
+namespace tpm {
+
+namespace {
+thread_local std::string t_last_error;
+std::mutex g_pool_mu;
+std::set<int> g_pool_ready;
+
+// Keep freed stream-ordered allocations in the device pool so that repeated
+// queries do not return multi-gigabyte level buffers to the driver each time.
+void configure_pool(int device) {
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    if (g_pool_ready.count(device)) return;
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess) {
+        uint64_t thr = UINT64_MAX;
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+    }
+    g_pool_ready.insert(device);
+}
+
+template <class F>
+tpm_status guarded(F &&f) {
+    try {
+        clear_error();
+        return f();
+    } catch (const Error &e) {
+        set_error(e.msg);
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        set_error("host allocation failed");
+        return TPM_ENOMEM;
+    } catch (const std::exception &e) {
+        set_error(e.what());
+        return TPM_EDEVICE;
+    } catch (...) {
+        set_error("unknown error");
+        return TPM_EDEVICE;
+    }
+}
+
+struct DeviceScope {
+    int prev = -1;
+    explicit DeviceScope(int dev) {
+        if (hipGetDevice(&prev) == hipSuccess && prev != dev) TPM_HIP(hipSetDevice(dev));
+        else prev = -1;
+    }
+    ~DeviceScope() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+constexpr uint64_t kGamma = 0x9E3779B97F4A7C15ull;
+
+uint64_t rep_seed(uint64_t seed, int64_t r) { return seed + (uint64_t)r * kGamma; }
+
+// seeds of extraction step s (s = 0 is the first localised sieve), attempt r
+uint64_t step_seed(uint64_t seed, int64_t s, int64_t r) {
+    return seed + (uint64_t)(s * 1000003 + r) * kGamma;
+}
+
+}  // namespace
+
+void set_error(const std::string &msg) { t_last_error = msg; }
+void clear_error() { t_last_error.clear(); }
+
+// Verify a path using the device index (strictly increasing times, consecutive
+// endpoints, distinct vertices, colours = M).
+bool verify_path(const Graph &G, const int32_t *M, int32_t k, const int32_t *verts,
+                 const int64_t *edges_pos) {
+    std::vector<int32_t> want(M, M + k), have;
+    std::set<int32_t> seen;
+    for (int i = 0; i < k; ++i) {
+        if (verts[i] < 0 || verts[i] >= G.n || !seen.insert(verts[i]).second) return false;
+        have.push_back(G.h_color[verts[i]]);
+    }
+    std::sort(want.begin(), want.end());
+    std::sort(have.begin(), have.end());
+    if (want != have) return false;
+    int32_t prev_tau = 0;
+    for (int i = 0; i + 1 < k; ++i) {
+        int32_t s, d, t;
+        int64_t p = edges_pos[i];
+        if (p < 0 || p >= G.m) return false;
+        TPM_HIP(hipMemcpy(&s, G.psrc + p, 4, hipMemcpyDeviceToHost));
+        TPM_HIP(hipMemcpy(&d, G.pdst + p, 4, hipMemcpyDeviceToHost));
+        TPM_HIP(hipMemcpy(&t, G.ptau + p, 4, hipMemcpyDeviceToHost));
+        if (s != verts[i] || d != verts[i + 1]) return false;
+        if (i > 0 && !(t > prev_tau)) return false;
+        prev_tau = t;
+    }
+    return true;
+}
+
+// Self-reduction by per-edge localisation.  A nonzero localisation at position p
+// (edge v -> u at time tau) certifies a matching path ending with that edge, hence a
+// path ending at v before tau with colours M - {c(u)} that avoids u.  Each step sieves
+// the smaller problem on the graph with the suffix's vertices deleted, counting only
+// v's in-edges earlier than tau at the last level.  A zero answer can be a false
+// negative, so each step retries with fresh seeds.
+tpm_status extract_path(const Graph &G, const int32_t *M, int32_t k, uint64_t seed,
+                        int32_t max_reps, int32_t *path_vertices, int64_t *path_edges,
+                        hipStream_t st) {
+    TPM_REQUIRE(k >= 1 && k <= 16, "k must be in [1, 16]");
+    TPM_REQUIRE(max_reps >= 1, "max_reps must be >= 1");
+    for (int i = 0; i < k; ++i) TPM_REQUIRE(M[i] >= 0 && M[i] < G.q, "multiset colour out of range");
+    if (k == 1) {
+        for (int32_t u = 0; u < G.n; ++u)
+            if (G.h_color[u] == M[0]) {
+                path_vertices[0] = u;
+                return TPM_OK;
+            }
+        return TPM_NOTFOUND;
+    }
+    std::vector<uint8_t> mask((size_t)G.n, 1);
+    std::vector<int32_t> cur(M, M + k);
+    std::vector<int32_t> rverts;   // reversed path
+    std::vector<int64_t> rpos;     // reversed edge positions
+    std::vector<int64_t> reids;
+    int64_t lo = 0, hi = 0;        // positions counted at the last level (all at step 0)
+    int32_t end_v = -1;
+    for (int step = 0; (int)cur.size() >= 2; ++step) {
+        SieveResult res;
+        bool got = false;
+        for (int r = 0; r < max_reps && !got; ++r) {
+            SieveRequest req;
+            req.multiset = cur.data();
+            req.k = (int32_t)cur.size();
+            req.seed = step_seed(seed, step, r);
+            req.vertex_mask = mask.data();
+            req.fin_lo = lo;
+            req.fin_hi = hi;
+            req.want_pick = true;
+            run_sieve(G, req, res, st);
+            got = res.pick_pos >= 0;
+        }
+        if (!got) return TPM_NOTFOUND;
+        int32_t v, u, tau;
+        TPM_HIP(hipMemcpy(&v, G.psrc + res.pick_pos, 4, hipMemcpyDeviceToHost));
+        TPM_HIP(hipMemcpy(&u, G.pdst + res.pick_pos, 4, hipMemcpyDeviceToHost));
+        TPM_HIP(hipMemcpy(&tau, G.ptau + res.pick_pos, 4, hipMemcpyDeviceToHost));
+        if (end_v < 0) rverts.push_back(u);
+        rpos.push_back(res.pick_pos);
+        reids.push_back(res.pick_eid);
+        rverts.push_back(v);
+        end_v = v;
+        // delete u, drop its colour
+        mask[(size_t)u] = 0;
+        auto it = std::find(cur.begin(), cur.end(), G.h_color[u]);
+        if (it == cur.end()) return TPM_NOTFOUND;  // cannot happen for a certified edge
+        cur.erase(it);
+        // next: v's in-edges earlier than tau
+        lo = G.h_inptr[v];
+        int64_t a = G.h_inptr[v], b = G.h_inptr[v + 1];
+        if (b > a) {
+            std::vector<int32_t> taus((size_t)(b - a));
+            TPM_HIP(hipMemcpy(taus.data(), G.ptau + a, sizeof(int32_t) * (b - a), hipMemcpyDeviceToHost));
+            hi = a + (int64_t)(std::lower_bound(taus.begin(), taus.end(), tau) - taus.begin());
+        } else {
+            hi = a;
+        }
+        if ((int)cur.size() >= 2 && hi <= lo) return TPM_NOTFOUND;
+    }
+    // cur has one colour left: it must be v's colour
+    if (cur.size() != 1 || G.h_color[end_v] != cur[0]) return TPM_NOTFOUND;
+    std::reverse(rverts.begin(), rverts.end());
+    std::reverse(rpos.begin(), rpos.end());
+    std::reverse(reids.begin(), reids.end());
+    if (!verify_path(G, M, k, rverts.data(), rpos.data()))
+        throw Error{TPM_EDEVICE, "extracted path failed verification"};
+    for (int i = 0; i < k; ++i) path_vertices[i] = rverts[i];
+    for (int i = 0; i + 1 < k; ++i) path_edges[i] = reids[i];
+    return TPM_OK;
+}
+
+}  // namespace tpm
+
+using namespace tpm;
+
+extern "C" {
+
+const char *tpm_last_error(void) { return t_last_error.c_str(); }
+
+const char *tpm_version(void) { return "tpm 0.1 (gfx950)"; }
+
+tpm_status tpm_graph_create_ex(int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                               const int32_t *tau, const int32_t *color, int32_t num_colors,
+                               uint32_t flags, const tpm_graph_options *opt, tpm_graph **out) {
+    return guarded([&]() -> tpm_status {
+        TPM_REQUIRE(out != nullptr, "out must not be NULL");
+        *out = nullptr;
+        auto *g = new tpm_graph();
+        try {
+            build_graph(g->G, n, m, src, dst, tau, color, num_colors, flags, opt);
+            configure_pool(g->G.device);
+        } catch (...) {
+            delete g;
+            throw;
+        }
+        *out = g;
+        return TPM_OK;
+    });
+}
+
+tpm_status tpm_graph_create(int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                            const int32_t *tau, const int32_t *color, int32_t num_colors,
+                            uint32_t flags, tpm_graph **out) {
+    return tpm_graph_create_ex(n, m, src, dst, tau, color, num_colors, flags, nullptr, out);
+}
+
+void tpm_graph_destroy(tpm_graph *g) {
+    if (!g) return;
+    int prev = -1;
+    if (hipGetDevice(&prev) == hipSuccess && prev != g->G.device) (void)hipSetDevice(g->G.device);
+    (void)hipDeviceSynchronize();
+    free_graph(g->G);
+    if (prev >= 0 && prev != g->G.device) (void)hipSetDevice(prev);
+    delete g;
+}
+
+tpm_status tpm_graph_stats_get(const tpm_graph *g, tpm_graph_stats *out) {
+    return guarded([&]() -> tpm_status {
+        TPM_REQUIRE(g && out, "NULL argument");
+        const Graph &G = g->G;
+        out->n = G.n;
+        out->m = G.m;
+        out->num_colors = G.q;
+        out->tmax = G.tmax;
+        out->rows = G.R;
+        out->tiles = G.ntiles;
+        out->slots = G.nslots;
+        out->max_in_degree = G.max_in_degree;
+        out->device_bytes = G.device_bytes;
+        return TPM_OK;
+    });
+}
+
+tpm_status tpm_sieve_ex(const tpm_graph *g, const int32_t *multiset, int32_t k, uint64_t seed,
+                        const uint8_t *vertex_mask, const tpm_tuning *tune, uint8_t *per_point,
+                        uint8_t *total, uint8_t *loc, void *hip_stream) {
+    return guarded([&]() -> tpm_status {
+        TPM_REQUIRE(g != nullptr, "graph must not be NULL");
+        DeviceScope ds(g->G.device);
+        SieveRequest req;
+        req.multiset = multiset;
+        req.k = k;
+        req.seed = seed;
+        req.vertex_mask = vertex_mask;
+        req.chunk = tune ? tune->chunk : 0;
+        SieveResult res;
+        hipStream_t st = (hipStream_t)hip_stream;
+        if (loc) run_sieve_loc_all(g->G, req, res, loc, st);
+        else run_sieve(g->G, req, res, st);
+        if (per_point) std::memcpy(per_point, res.per_point.data(), res.per_point.size());
+        if (total) *total = res.total;
+        return TPM_OK;
+    });
+}
+
+tpm_status tpm_sieve(const tpm_graph *g, const int32_t *multiset, int32_t k, uint64_t seed,
+                     const uint8_t *vertex_mask, uint8_t *per_point, uint8_t *total,
+                     void *hip_stream) {
+    return tpm_sieve_ex(g, multiset, k, seed, vertex_mask, nullptr, per_point, total, nullptr,
+                        hip_stream);
+}
+
+tpm_status tpm_decide(const tpm_graph *g, const int32_t *multiset, int32_t k, uint64_t seed,
+                      int32_t reps, int32_t *found) {
+    return guarded([&]() -> tpm_status {
+        TPM_REQUIRE(g && found, "NULL argument");
+        TPM_REQUIRE(reps >= 1, "reps must be >= 1");
+        DeviceScope ds(g->G.device);
+        *found = 0;
+        for (int32_t r = 0; r < reps; ++r) {
+            SieveRequest req;
+            req.multiset = multiset;
+            req.k = k;
+            req.seed = rep_seed(seed, r);
+            SieveResult res;
+            run_sieve(g->G, req, res, nullptr);
+            if (res.total) {
+                *found = 1;
+                break;
+            }
+        }
+        return TPM_OK;
+    });
+}
+
+tpm_status tpm_extract(const tpm_graph *g, const int32_t *multiset, int32_t k, uint64_t seed,
+                       int32_t max_reps, int32_t *path_vertices, int64_t *path_edges) {
+    return guarded([&]() -> tpm_status {
+        TPM_REQUIRE(g && multiset && path_vertices && (k < 2 || path_edges), "NULL argument");
+        DeviceScope ds(g->G.device);
+        return extract_path(g->G, multiset, k, seed, max_reps, path_vertices, path_edges, nullptr);
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,378 @@
+// Graph ingest and the device-resident in-edge index.
+//
+// The temporal graph (section "Terminology": temporal edges (u, v, j), j a positive
+// integer) is stored as an in-edge CSR: positions sorted by (dst, tau, input id).
+// Eq. (3) makes P_{u,l,.} a step function of time that changes only at u's in-edge
+// times, so the running value after position p of u's in-list is P_{u,l,tau_p}.
+// For the edge e = (v -> u, tau) at position p the recursion reads P_{v,l-1,tau-1}:
+// the running value at the last position of v's in-list with tau' < tau, found here
+// once per graph by binary search.  Only positions some edge reads ("rows") are ever
+// stored by the sieve kernels; rows are numbered in CSR order.
+//
+// Work tiles: consecutive CSR positions (<= tile_edges).  Whole in-lists are packed
+// into tiles; an in-list longer than a tile is cut into pieces, and every piece after
+// the first additionally holds at most tile_held rows, because those rows wait in
+// registers for the running value (carry) of the earlier pieces.  Pieces of one
+// in-list publish their running values to consecutive "slots" for the look-back.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+
+#include <rocprim/rocprim.hpp>
+
+#include "tpm_internal.h"
+
+namespace tpm {
+
+namespace {
+
+__global__ void k_validate(int64_t m, int32_t n, const int32_t *src, const int32_t *dst,
+                           const int32_t *tau, int32_t *bad, int32_t *tmax) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int32_t local_max = 0;
+    for (; i < m; i += stride) {
+        int32_t s = src[i], d = dst[i], t = tau[i];
+        if (s < 0 || s >= n || d < 0 || d >= n || t < 1) atomicOr(bad, 1);
+        local_max = max(local_max, t);
+    }
+    atomicMax(tmax, local_max);
+}
+
+__global__ void k_validate_color(int32_t n, int32_t q, const int32_t *color, int32_t *bad) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && (color[i] < 0 || color[i] >= q)) atomicOr(bad, 2);
+}
+
+__global__ void k_keys(int64_t m, const int32_t *dst, const int32_t *tau, int tbits,
+                       uint64_t *keys, int32_t *vals) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < m) {
+        keys[e] = ((uint64_t)(uint32_t)dst[e] << tbits) | (uint64_t)(uint32_t)tau[e];
+        vals[e] = (int32_t)e;
+    }
+}
+
+__global__ void k_apply(int64_t m, const int32_t *order, const int32_t *src, const int32_t *dst,
+                        const int32_t *tau, int32_t *psrc, int32_t *pdst, int32_t *ptau,
+                        int32_t *peid) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < m) {
+        int32_t e = order[p];
+        peid[p] = e;
+        psrc[p] = src[e];
+        pdst[p] = dst[e];
+        ptau[p] = tau[e];
+    }
+}
+
+// inptr[u] = first position whose dst >= u; every position writes the entries of
+// the vertices between its predecessor's dst and its own (deterministic, no atomics).
+__global__ void k_inptr(int64_t m, int32_t n, const int32_t *pdst, int32_t *inptr) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p > m) return;
+    int32_t lo = (p == 0) ? 0 : pdst[p - 1] + 1;
+    int32_t hi = (p == m) ? n : pdst[p];
+    for (int32_t u = lo; u <= hi; ++u) inptr[u] = (int32_t)p;
+}
+
+// gpos[p] = last position q of src's in-list with tau[q] < tau[p], or -1.
+__global__ void k_gpos(int64_t m, const int32_t *psrc, const int32_t *ptau, const int32_t *inptr,
+                       int32_t *gpos, int32_t *needed) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= m) return;
+    int32_t v = psrc[p], t = ptau[p];
+    int32_t lo = inptr[v], hi = inptr[v + 1], base = lo;
+    while (lo < hi) {
+        int32_t mid = lo + ((hi - lo) >> 1);
+        if (ptau[mid] < t) lo = mid + 1; else hi = mid;
+    }
+    int32_t q = (lo > base) ? lo - 1 : -1;
+    gpos[p] = q;
+    if (q >= 0) needed[q] = 1;  // every writer stores the same value
+}
+
+__global__ void k_rows(int64_t m, const int32_t *gpos, const int32_t *needed,
+                       const int32_t *rowof, int32_t *orow, int32_t *gsrc) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= m) return;
+    orow[p] = needed[p] ? rowof[p] : -1;
+    int32_t q = gpos[p];
+    gsrc[p] = q >= 0 ? rowof[q] : -1;
+}
+
+inline unsigned grid_for(int64_t work, int block = 256) {
+    int64_t g = (work + block - 1) / block;
+    return (unsigned)std::max<int64_t>(1, g);
+}
+
+template <class T>
+T *dalloc(int64_t count, int64_t &acct) {
+    void *p = nullptr;
+    size_t bytes = (size_t)std::max<int64_t>(1, count) * sizeof(T);
+    TPM_HIP(hipMalloc(&p, bytes));
+    acct += (int64_t)bytes;
+    return (T *)p;
+}
+
+int bits_for(uint64_t v) {  // bits needed to represent values 0..v
+    int b = 0;
+    while (b < 64 && (v >> b) != 0) ++b;
+    return std::max(b, 1);
+}
+
+// Host-side tile builder (see the file comment).
+void build_tiles(const std::vector<int32_t> &inptr, const std::vector<uint8_t> &needed,
+                 int32_t T, int32_t H, std::vector<int32_t> &p0, std::vector<int32_t> &pub,
+                 std::vector<int32_t> &lb, int64_t &nslots) {
+    const int32_t n = (int32_t)inptr.size() - 1;
+    p0.clear();
+    pub.clear();
+    lb.clear();
+    nslots = 0;
+    int32_t cur_start = -1, cur_len = 0;
+    auto close_pack = [&]() {
+        if (cur_len > 0) {
+            p0.push_back(cur_start);
+            pub.push_back(-1);
+            lb.push_back(-1);
+        }
+        cur_len = 0;
+        cur_start = -1;
+    };
+    for (int32_t u = 0; u < n; ++u) {
+        int32_t a = inptr[u], b = inptr[u + 1], L = b - a;
+        if (L == 0) continue;
+        if (L <= T) {
+            if (cur_len > 0 && cur_len + L > T) close_pack();
+            if (cur_len == 0) cur_start = a;
+            cur_len += L;
+            continue;
+        }
+        close_pack();
+        // first piece: starts at the in-list head, publishes its running value
+        int32_t prev_slot = (int32_t)nslots++;
+        p0.push_back(a);
+        pub.push_back(prev_slot);
+        lb.push_back(-1);
+        int32_t q = a + T;
+        while (q < b) {
+            int32_t start = q, cnt = 0;
+            while (q < b && q - start < T) {
+                if (needed[q]) {
+                    if (cnt == H) break;
+                    ++cnt;
+                }
+                ++q;
+            }
+            bool last = (q >= b);
+            int32_t slot = last ? -1 : (int32_t)nslots++;
+            p0.push_back(start);
+            pub.push_back(slot);
+            lb.push_back(prev_slot);
+            prev_slot = slot;
+        }
+    }
+    close_pack();
+    p0.push_back(inptr[n]);
+}
+
+}  // namespace
+
+void free_graph(Graph &G) {
+    int32_t **ptrs[] = {&G.color, &G.pdst, &G.psrc, &G.ptau, &G.peid, &G.gsrc,
+                        &G.orow,  &G.inptr, &G.tile_p0, &G.tile_pub, &G.tile_lb};
+    for (auto pp : ptrs) {
+        if (*pp) (void)hipFree(*pp);
+        *pp = nullptr;
+    }
+    if (G.lds_image) (void)hipFree(G.lds_image);
+    G.lds_image = nullptr;
+}
+
+void build_graph(Graph &G, int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                 const int32_t *tau, const int32_t *color, int32_t num_colors, uint32_t flags,
+                 const tpm_graph_options *opt) {
+    TPM_REQUIRE(n >= 1, "n must be >= 1");
+    TPM_REQUIRE(m >= 0 && m < (int64_t(1) << 31) - 1, "m must be in [0, 2^31 - 1)");
+    TPM_REQUIRE(num_colors >= 1, "num_colors must be >= 1");
+    TPM_REQUIRE(m == 0 || (src && dst && tau), "edge arrays must not be NULL");
+    TPM_REQUIRE(color != nullptr, "color must not be NULL");
+    int T = 64, H = 8;
+    if (opt) {
+        if (opt->tile_edges) T = opt->tile_edges;
+        if (opt->tile_held) H = opt->tile_held;
+    }
+    TPM_REQUIRE(T >= 1 && T <= 64, "tile_edges must be in [1, 64]");
+    TPM_REQUIRE(H >= 1 && H <= 8, "tile_held must be in [1, 8]");
+    const bool on_dev = (flags & TPM_DEVICE_PTRS) != 0;
+    TPM_REQUIRE((flags & ~TPM_DEVICE_PTRS) == 0, "unknown flag bits");
+
+    // ---- validation of host arrays happens before any device work
+    int32_t tmax = 0;
+    if (!on_dev) {
+        for (int64_t e = 0; e < m; ++e) {
+            int32_t s = src[e], d = dst[e], t = tau[e];
+            TPM_REQUIRE(s >= 0 && s < n && d >= 0 && d < n, "edge endpoint out of range");
+            TPM_REQUIRE(t >= 1, "timestamps must be >= 1");
+            tmax = std::max(tmax, t);
+        }
+        for (int32_t u = 0; u < n; ++u)
+            TPM_REQUIRE(color[u] >= 0 && color[u] < num_colors, "colour out of range");
+    }
+
+    TPM_HIP(hipGetDevice(&G.device));
+    hipDeviceProp_t prop;
+    TPM_HIP(hipGetDeviceProperties(&prop, G.device));
+    G.num_cu = prop.multiProcessorCount;
+    G.n = n;
+    G.m = m;
+    G.q = num_colors;
+    G.tile_edges = T;
+    G.tile_held = H;
+    int64_t acct = 0;
+    hipStream_t st = nullptr;
+
+    int32_t *d_src = nullptr, *d_dst = nullptr, *d_tau = nullptr;
+    int64_t tmp = 0;
+    uint64_t *keys = nullptr, *keys2 = nullptr;
+    int32_t *vals = nullptr, *vals2 = nullptr, *gpos = nullptr, *needed = nullptr,
+            *rowof = nullptr;
+    void *scratch = nullptr;
+    auto cleanup_tmp = [&]() {
+        for (void *p : {(void *)d_src, (void *)d_dst, (void *)d_tau, (void *)keys, (void *)keys2,
+                        (void *)vals, (void *)vals2, (void *)gpos, (void *)needed, (void *)rowof,
+                        scratch})
+            if (p) (void)hipFree(p);
+    };
+    try {
+        G.color = dalloc<int32_t>(n, acct);
+        d_src = dalloc<int32_t>(m, tmp);
+        d_dst = dalloc<int32_t>(m, tmp);
+        d_tau = dalloc<int32_t>(m, tmp);
+        hipMemcpyKind kind = on_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+        TPM_HIP(hipMemcpy(G.color, color, sizeof(int32_t) * n, kind));
+        if (m) {
+            TPM_HIP(hipMemcpy(d_src, src, sizeof(int32_t) * m, kind));
+            TPM_HIP(hipMemcpy(d_dst, dst, sizeof(int32_t) * m, kind));
+            TPM_HIP(hipMemcpy(d_tau, tau, sizeof(int32_t) * m, kind));
+        }
+        if (on_dev) {
+            int32_t *flagbuf = dalloc<int32_t>(2, tmp);
+            TPM_HIP(hipMemset(flagbuf, 0, 2 * sizeof(int32_t)));
+            if (m)
+                k_validate<<<std::min<unsigned>(grid_for(m), 4096), 256, 0, st>>>(
+                    m, n, d_src, d_dst, d_tau, flagbuf, flagbuf + 1);
+            k_validate_color<<<grid_for(n), 256, 0, st>>>(n, num_colors, G.color, flagbuf);
+            int32_t h[2];
+            TPM_HIP(hipMemcpy(h, flagbuf, sizeof(h), hipMemcpyDeviceToHost));
+            (void)hipFree(flagbuf);
+            TPM_REQUIRE(!(h[0] & 1), "edge endpoint out of range or timestamp < 1");
+            TPM_REQUIRE(!(h[0] & 2), "colour out of range");
+            tmax = h[1];
+        }
+        G.tmax = tmax;
+
+        G.pdst = dalloc<int32_t>(m, acct);
+        G.psrc = dalloc<int32_t>(m, acct);
+        G.ptau = dalloc<int32_t>(m, acct);
+        G.peid = dalloc<int32_t>(m, acct);
+        G.gsrc = dalloc<int32_t>(m, acct);
+        G.orow = dalloc<int32_t>(m, acct);
+        G.inptr = dalloc<int32_t>((int64_t)n + 1, acct);
+
+        std::vector<uint8_t> h_needed(m);
+        if (m) {
+            // ---- sort positions by (dst, tau, id): stable radix sort of (dst, tau) keys
+            const int tbits = bits_for((uint64_t)tmax);
+            const int nbits = bits_for((uint64_t)(n - 1));
+            keys = dalloc<uint64_t>(m, tmp);
+            keys2 = dalloc<uint64_t>(m, tmp);
+            vals = dalloc<int32_t>(m, tmp);
+            vals2 = dalloc<int32_t>(m, tmp);
+            k_keys<<<grid_for(m), 256, 0, st>>>(m, d_dst, d_tau, tbits, keys, vals);
+            size_t sbytes = 0;
+            TPM_HIP(rocprim::radix_sort_pairs(nullptr, sbytes, keys, keys2, vals, vals2, (size_t)m,
+                                              0, (unsigned)(tbits + nbits), st));
+            TPM_HIP(hipMalloc(&scratch, std::max<size_t>(sbytes, 16)));
+            TPM_HIP(rocprim::radix_sort_pairs(scratch, sbytes, keys, keys2, vals, vals2, (size_t)m,
+                                              0, (unsigned)(tbits + nbits), st));
+            k_apply<<<grid_for(m), 256, 0, st>>>(m, vals2, d_src, d_dst, d_tau, G.psrc, G.pdst,
+                                                 G.ptau, G.peid);
+            (void)hipFree(keys);
+            keys = nullptr;
+            (void)hipFree(keys2);
+            keys2 = nullptr;
+            (void)hipFree(scratch);
+            scratch = nullptr;
+        }
+        k_inptr<<<grid_for(m + 1), 256, 0, st>>>(m, n, G.pdst, G.inptr);
+        if (m) {
+            gpos = vals;  // reuse
+            vals = nullptr;
+            needed = dalloc<int32_t>(m, tmp);
+            rowof = dalloc<int32_t>(m, tmp);
+            TPM_HIP(hipMemsetAsync(needed, 0, sizeof(int32_t) * m, st));
+            k_gpos<<<grid_for(m), 256, 0, st>>>(m, G.psrc, G.ptau, G.inptr, gpos, needed);
+            size_t sbytes = 0;
+            TPM_HIP(rocprim::exclusive_scan(nullptr, sbytes, needed, rowof, 0, (size_t)m,
+                                            rocprim::plus<int32_t>(), st));
+            TPM_HIP(hipMalloc(&scratch, std::max<size_t>(sbytes, 16)));
+            TPM_HIP(rocprim::exclusive_scan(scratch, sbytes, needed, rowof, 0, (size_t)m,
+                                            rocprim::plus<int32_t>(), st));
+            k_rows<<<grid_for(m), 256, 0, st>>>(m, gpos, needed, rowof, G.orow, G.gsrc);
+            int32_t last_row = 0, last_needed = 0;
+            TPM_HIP(hipMemcpy(&last_row, rowof + (m - 1), sizeof(int32_t), hipMemcpyDeviceToHost));
+            TPM_HIP(hipMemcpy(&last_needed, needed + (m - 1), sizeof(int32_t),
+                              hipMemcpyDeviceToHost));
+            G.R = (int64_t)last_row + last_needed;
+            std::vector<int32_t> nd(m);
+            TPM_HIP(hipMemcpy(nd.data(), needed, sizeof(int32_t) * m, hipMemcpyDeviceToHost));
+            for (int64_t i = 0; i < m; ++i) h_needed[i] = (uint8_t)nd[i];
+        }
+        G.h_color.resize((size_t)n);
+        TPM_HIP(hipMemcpy(G.h_color.data(), G.color, sizeof(int32_t) * (size_t)n,
+                          hipMemcpyDeviceToHost));
+        G.h_inptr.resize((size_t)n + 1);
+        TPM_HIP(hipMemcpy(G.h_inptr.data(), G.inptr, sizeof(int32_t) * ((size_t)n + 1),
+                          hipMemcpyDeviceToHost));
+        for (int32_t u = 0; u < n; ++u)
+            G.max_in_degree = std::max<int64_t>(G.max_in_degree, G.h_inptr[u + 1] - G.h_inptr[u]);
+
+        std::vector<int32_t> tp0, tpub, tlb;
+        build_tiles(G.h_inptr, h_needed, T, H, tp0, tpub, tlb, G.nslots);
+        G.ntiles = (int64_t)tpub.size();
+        G.h_tile_p0 = tp0;
+        G.tile_p0 = dalloc<int32_t>(G.ntiles + 1, acct);
+        G.tile_pub = dalloc<int32_t>(G.ntiles, acct);
+        G.tile_lb = dalloc<int32_t>(G.ntiles, acct);
+        TPM_HIP(hipMemcpy(G.tile_p0, tp0.data(), sizeof(int32_t) * tp0.size(),
+                          hipMemcpyHostToDevice));
+        if (G.ntiles) {
+            TPM_HIP(hipMemcpy(G.tile_pub, tpub.data(), sizeof(int32_t) * tpub.size(),
+                              hipMemcpyHostToDevice));
+            TPM_HIP(hipMemcpy(G.tile_lb, tlb.data(), sizeof(int32_t) * tlb.size(),
+                              hipMemcpyHostToDevice));
+        }
+
+        // ---- LDS table image (see kLdsBytes)
+        std::vector<uint8_t> img(kLdsBytes);
+        for (int v = 0; v < 256; ++v) img[v] = kGf.log[v];
+        for (int r = 1; r < 512; ++r)
+            for (int gl = 0; gl < 256; ++gl)
+                img[(size_t)r * 256 + gl] = (gl == 255) ? 0 : kGf.exp[(r - 1 + gl) % 255];
+        G.lds_image = (uint8_t *)dalloc<uint8_t>(kLdsBytes, acct);
+        TPM_HIP(hipMemcpy(G.lds_image, img.data(), kLdsBytes, hipMemcpyHostToDevice));
+        TPM_HIP(hipDeviceSynchronize());
+        G.device_bytes = acct;
+    } catch (...) {
+        cleanup_tmp();
+        free_graph(G);
+        throw;
+    }
+    cleanup_tmp();
+}
+
+}  // namespace tpm

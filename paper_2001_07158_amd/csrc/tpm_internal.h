@@ -1,0 +1,144 @@
+// Internal declarations shared by the libtpm translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/tpm.h"
+
+namespace tpm {
+
+// ------------------------------------------------------------------ errors
+void set_error(const std::string &msg);
+void clear_error();
+
+struct Error {
+    tpm_status code;
+    std::string msg;
+};
+
+#define TPM_HIP(expr)                                                                 \
+    do {                                                                              \
+        hipError_t _e = (expr);                                                       \
+        if (_e != hipSuccess)                                                         \
+            throw ::tpm::Error{_e == hipErrorOutOfMemory ? TPM_ENOMEM : TPM_EDEVICE,  \
+                               std::string(#expr) + ": " + hipGetErrorString(_e)};   \
+    } while (0)
+
+#define TPM_REQUIRE(cond, msg)                                                        \
+    do {                                                                              \
+        if (!(cond))                                                                  \
+            throw ::tpm::Error{TPM_EINVAL, (msg)};                                    \
+    } while (0)
+
+// ------------------------------------------------------------------ GF(2^8)
+// Power and logarithm tables of the generator alpha = x (0x02) of GF(2^8) with
+// modulus x^8 + x^4 + x^3 + x^2 + 1, generated at compile time by repeated
+// multiplication by x (shift, and fold x^8 back as 0x1D).
+struct GfTables {
+    uint8_t exp[512];  // exp[i] = alpha^(i mod 255)
+    uint8_t log[256];  // log[v] = i with alpha^i = v; log[0] = 255 (marks zero)
+};
+
+constexpr GfTables make_gf_tables() {
+    GfTables t{};
+    unsigned v = 1;
+    for (int i = 0; i < 255; ++i) {
+        t.exp[i] = (uint8_t)v;
+        t.log[v] = (uint8_t)i;
+        v <<= 1;
+        if (v & 0x100u) v ^= 0x11Du;
+    }
+    for (int i = 255; i < 512; ++i) t.exp[i] = t.exp[i - 255];
+    t.log[0] = 255;
+    return t;
+}
+
+inline constexpr GfTables kGf = make_gf_tables();
+
+// Layout of the per-workgroup LDS table used by the sieve kernels (bytes):
+//   [0, 256)          LOG8[v]   = log(v), 255 for v = 0
+//   [256*r + g]       r in [1, 512), g in [0, 256):
+//                     = 0 if g == 255 (log of zero), else alpha^((r - 1 + g) mod 255)
+// so that the product of field elements with logs a (in [0, 508]) and g is the byte
+// at address ((a + 1) << 8) | g.
+constexpr int kLdsBytes = 512 * 256;
+
+// ------------------------------------------------------------------ graph
+struct Graph {
+    int device = 0;
+    int32_t n = 0;
+    int64_t m = 0;
+    int32_t q = 0;
+    int32_t tmax = 0;
+    int32_t tile_edges = 64;
+    int32_t tile_held = 8;
+    int64_t R = 0;        // stored rows per level
+    int64_t ntiles = 0;
+    int64_t nslots = 0;
+    int64_t max_in_degree = 0;
+    int64_t device_bytes = 0;
+    int num_cu = 0;
+
+    // device arrays (CSR order = edges sorted by (dst, tau, input id))
+    int32_t *color = nullptr;  // [n]
+    int32_t *pdst = nullptr;   // [m] dst of the edge at each position
+    int32_t *psrc = nullptr;   // [m] src
+    int32_t *ptau = nullptr;   // [m] timestamp
+    int32_t *peid = nullptr;   // [m] input edge id
+    int32_t *gsrc = nullptr;   // [m] state row read by the edge (last in-edge of src
+                               //     earlier than tau), -1 if none
+    int32_t *orow = nullptr;   // [m] state row written at this position, -1 if none
+    int32_t *inptr = nullptr;  // [n+1]
+    int32_t *tile_p0 = nullptr;   // [ntiles+1]
+    int32_t *tile_pub = nullptr;  // [ntiles] slot this tile publishes to, -1 if none
+    int32_t *tile_lb = nullptr;   // [ntiles] slot its look-back starts at, -1 if none
+    uint8_t *lds_image = nullptr; // [kLdsBytes]
+
+    // host copies used by extraction
+    std::vector<int32_t> h_inptr;   // [n+1]
+    std::vector<int32_t> h_color;   // [n]
+    std::vector<int32_t> h_tile_p0; // [ntiles+1]
+};
+
+// Builds all of the above; throws Error.
+void build_graph(Graph &G, int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                 const int32_t *tau, const int32_t *color, int32_t num_colors, uint32_t flags,
+                 const tpm_graph_options *opt);
+void free_graph(Graph &G);
+
+// ------------------------------------------------------------------ sieve
+struct SieveRequest {
+    const int32_t *multiset = nullptr;
+    int32_t k = 0;
+    uint64_t seed = 0;
+    const uint8_t *vertex_mask = nullptr;  // host, n bytes, nullable
+    int32_t chunk = 0;
+    // restrict the last level's contributions to CSR positions [fin_lo, fin_hi)
+    // (all positions if fin_lo >= fin_hi)
+    int64_t fin_lo = 0, fin_hi = 0;
+    // localise over the contributing positions and pick the one with nonzero
+    // localisation and the smallest input edge id
+    bool want_pick = false;
+};
+
+struct SieveResult {
+    std::vector<uint8_t> per_point;  // 2^k
+    uint8_t total = 0;
+    int64_t pick_eid = -1, pick_pos = -1;
+};
+
+void run_sieve(const Graph &G, const SieveRequest &req, SieveResult &res, hipStream_t stream);
+
+// Per-edge localisation over all edges, indexed by input edge id.
+void run_sieve_loc_all(const Graph &G, const SieveRequest &req, SieveResult &res,
+                       uint8_t *loc_by_edge, hipStream_t stream);
+
+}  // namespace tpm
+
+struct tpm_graph {
+    tpm::Graph G;
+};

@@ -1,0 +1,669 @@
+// Sieve kernels: evaluation of the temporal generating polynomial (Eq. (3)) at the
+// points of the constrained multilinear sieve (Lemma "constrained multilinear
+// sieving", Eq. (motif)) over GF(2^8), edge by edge over the in-edge CSR.
+//
+// Notation.  c_l[p] = x_u * y_{e,l-1} * H_{l-1}(p) for the edge e = (v -> u, tau) at
+// CSR position p, where H_1 = x_v and, for l-1 >= 2, H_{l-1} = running XOR of c_{l-1}
+// over v's in-list up to the last position earlier than tau (= P_{v,l-1,tau-1}).
+// The running XOR after position p of u's in-list is P_{u,l,tau_p}; it is stored
+// only at positions some later edge reads (its "row").  P_{k,t} = XOR_p c_k[p].
+//
+// Mapping.  One wavefront walks one tile of consecutive CSR positions; its 64 lanes
+// hold the sieve points of the current chunk, 4*W points per lane (lanes = points,
+// the paper's SIMD lanes over the 2^k evaluations).  For each edge all lanes gather
+// the C-byte row of the predecessor value, multiply by x_u*y_e per point, and keep a
+// per-lane running XOR (the segmented prefix over the in-list).
+//
+// Number format.  Stored rows and the per-vertex values x_u hold discrete logs
+// (base alpha = 0x02; 255 encodes zero), so a product costs one table read: the byte
+// at LDS address ((log x_u + log y_e + 1) << 8 | log g) is x_u * y_e * g.  The
+// running XOR is linear; a row is converted back to logs when stored.
+//
+// Long in-lists span several tiles.  Each tile of such a list publishes its running
+// value as 64-bit words (epoch, status, value) — first AGGREGATE (this tile only),
+// then INCLUSIVE (from the list head) — and later tiles add the values of earlier
+// ones by walking back until an INCLUSIVE word (decoupled look-back, Merrill and
+// Garland 2016).  Tiles are claimed from an atomic ticket, so a tile only ever waits
+// for tiles claimed before it.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+
+#include "tpm_internal.h"
+
+namespace tpm {
+
+namespace {
+
+__constant__ GfTables c_gf = make_gf_tables();
+
+constexpr uint32_t kSkip = 0xFFFFu;  // y = 0: the edge adds nothing at this level
+constexpr int kU = 8;                // edges whose gathers are in flight together
+constexpr int kHeldMax = 8;          // rows a continuation tile keeps for its carry
+constexpr uint32_t kAgg = 1, kInc = 2;
+constexpr uint32_t kSpinLimit = 1u << 24;
+
+struct Ctl {
+    uint32_t ticket;
+    uint32_t epoch;
+    uint32_t err;
+    uint32_t pad;
+};
+
+struct QuerySlots {
+    int32_t ncol;        // distinct colours of the multiset
+    int32_t col[16];     // ascending
+    int32_t off[16];     // first slot of the colour
+    int32_t mu[16];      // multiplicity
+};
+
+struct LevelParams {
+    const int32_t *gidx;   // row gathered by the edge at each position (-1: none)
+    const uint8_t *gbase;  // gathered rows (log domain), rowb bytes each
+    const int32_t *pdst;
+    const int32_t *peid;
+    const int32_t *orow;   // row stored at each position (-1: none)
+    uint8_t *sout;         // stored rows
+    const uint8_t *lxt;    // per-vertex rows of log x_u^A
+    const int32_t *tile_p0;
+    const int32_t *tile_pub;
+    const int32_t *tile_lb;
+    int32_t tile_lo, tile_hi;
+    int32_t pos_lo, pos_hi;  // last level: positions that contribute
+    unsigned long long *pub;
+    Ctl *ctl;
+    uint32_t *fin;           // last level: per-point XOR accumulators (rowb/4 dwords)
+    uint8_t *loc;            // last level: per-position localisation, index p - pos_lo
+    const uint8_t *lds_image;
+    uint64_t seed;
+    uint32_t ylevel;         // walk position of y used at this level (= l - 1)
+    int32_t rowb;            // bytes per row = sieve points per chunk
+    int32_t lanes;           // lanes holding points = rowb / (4 W)
+};
+
+// SplitMix64 output function (Steele, Lea, Flood 2014).
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ uint32_t fp8(uint64_t seed, uint32_t tag, uint32_t a, uint32_t b) {
+    uint64_t key = ((uint64_t)tag << 56) ^ ((uint64_t)a << 32) ^ (uint64_t)b;
+    return (uint32_t)(mix64(seed ^ mix64(key)) & 0xFFu);
+}
+
+__device__ __forceinline__ uint32_t gmul(uint32_t a, uint32_t b) {
+    return (a && b) ? c_gf.exp[c_gf.log[a] + c_gf.log[b]] : 0u;
+}
+
+// 4 packed log-domain bytes g times per-point logs (two 16-bit values per word,
+// each already offset by +1): returns the 4 linear products.
+__device__ __forceinline__ uint32_t mul4(const uint8_t *lds, uint32_t g, uint32_t la01,
+                                         uint32_t la23) {
+    uint32_t a0 = __builtin_amdgcn_perm(la01, g, 0x0C050400u);
+    uint32_t a1 = __builtin_amdgcn_perm(la01, g, 0x0C070601u);
+    uint32_t a2 = __builtin_amdgcn_perm(la23, g, 0x0C050402u);
+    uint32_t a3 = __builtin_amdgcn_perm(la23, g, 0x0C070603u);
+    return (uint32_t)lds[a0] | ((uint32_t)lds[a1] << 8) | ((uint32_t)lds[a2] << 16) |
+           ((uint32_t)lds[a3] << 24);
+}
+
+// linear bytes -> log bytes
+__device__ __forceinline__ uint32_t tolog4(const uint8_t *lds, uint32_t v) {
+    return (uint32_t)lds[v & 0xFFu] | ((uint32_t)lds[(v >> 8) & 0xFFu] << 8) |
+           ((uint32_t)lds[(v >> 16) & 0xFFu] << 16) | ((uint32_t)lds[v >> 24] << 24);
+}
+
+// 0xFF in every byte of w that is not 0xFF (log of a nonzero value)
+__device__ __forceinline__ uint32_t nonzero_mask(uint32_t w) {
+    uint32_t t = ~w;
+    uint32_t y = (((t & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | t) & 0x80808080u;
+    return (y >> 7) * 0xFFu;
+}
+
+template <int W>
+__device__ __forceinline__ void load_row(const uint8_t *base, int64_t row, int rowb, int lane,
+                                         uint32_t (&v)[W]) {
+    const uint8_t *p = base + row * (int64_t)rowb + (int64_t)lane * (4 * W);
+    if constexpr (W == 4) {
+        uint4 t = *(const uint4 *)p;
+        v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
+    } else if constexpr (W == 2) {
+        uint2 t = *(const uint2 *)p;
+        v[0] = t.x; v[1] = t.y;
+    } else {
+        v[0] = *(const uint32_t *)p;
+    }
+}
+
+template <int W>
+__device__ __forceinline__ void store_row(uint8_t *base, int64_t row, int rowb, int lane,
+                                          const uint32_t (&v)[W]) {
+    uint8_t *p = base + row * (int64_t)rowb + (int64_t)lane * (4 * W);
+    if constexpr (W == 4) {
+        *(uint4 *)p = make_uint4(v[0], v[1], v[2], v[3]);
+    } else if constexpr (W == 2) {
+        *(uint2 *)p = make_uint2(v[0], v[1]);
+    } else {
+        *(uint32_t *)p = v[0];
+    }
+}
+
+template <int W>
+__device__ __forceinline__ void publish(unsigned long long *pub, int32_t slot, int rowd, int lane,
+                                        uint32_t status, uint32_t epoch, const uint32_t (&v)[W]) {
+    const unsigned long long hi = (unsigned long long)((epoch << 2) | status) << 32;
+    unsigned long long *p = pub + (int64_t)slot * rowd + (int64_t)lane * W;
+#pragma unroll
+    for (int w = 0; w < W; ++w)
+        __hip_atomic_store(p + w, hi | v[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int W>
+__device__ __forceinline__ void lookback(unsigned long long *pub, int32_t slot, int rowd, int lane,
+                                         uint32_t epoch, Ctl *ctl, uint32_t (&carry)[W]) {
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        uint32_t c = 0;
+        int32_t s = slot;
+        for (;;) {
+            unsigned long long *p = pub + (int64_t)s * rowd + (int64_t)lane * W + w;
+            unsigned long long v;
+            uint32_t spins = 0;
+            bool ok = true;
+            for (;;) {
+                v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                uint32_t hi = (uint32_t)(v >> 32);
+                if ((hi >> 2) == (epoch & 0x3FFFFFFFu) && (hi & 3u) != 0) break;
+                if (++spins > kSpinLimit) {
+                    atomicOr(&ctl->err, 2u);
+                    ok = false;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+            if (!ok) break;
+            c ^= (uint32_t)v;
+            if (((uint32_t)(v >> 32) & 3u) == kInc) break;
+            if (s == 0) {
+                atomicOr(&ctl->err, 4u);
+                break;
+            }
+            --s;
+        }
+        carry[w] = c;
+    }
+}
+
+template <int W, bool FIN>
+__global__ void __launch_bounds__(1024) k_level(LevelParams P) {
+    __shared__ __attribute__((aligned(16))) uint8_t lds[kLdsBytes];
+    {
+        const uint4 *src = (const uint4 *)P.lds_image;
+        uint4 *dst = (uint4 *)lds;
+        for (int i = threadIdx.x; i < kLdsBytes / 16; i += blockDim.x) dst[i] = src[i];
+    }
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63;
+    const bool act = lane < P.lanes;
+    const int rowd = P.rowb >> 2;
+    const uint32_t epoch = __hip_atomic_load(&P.ctl->epoch, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT) & 0x3FFFFFFFu;
+    uint32_t fin[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) fin[w] = 0;
+
+    for (;;) {
+        uint32_t t = 0;
+        if (lane == 0) t = atomicAdd(&P.ctl->ticket, 1u);
+        t = __builtin_amdgcn_readfirstlane(__shfl(t, 0));
+        const int32_t tile = P.tile_lo + (int32_t)t;
+        if (tile >= P.tile_hi) break;
+
+        const int32_t p0 = P.tile_p0[tile], p1 = P.tile_p0[tile + 1];
+        int32_t pubslot = -1, lbslot = -1;
+        if constexpr (!FIN) {
+            pubslot = P.tile_pub[tile];
+            lbslot = P.tile_lb[tile];
+        }
+        const bool cont = lbslot >= 0;
+
+        // log y_{e, ylevel} of the tile's positions: lane i <-> position p0 + i
+        uint32_t ly_vec = kSkip;
+        if (p0 + lane < p1) {
+            uint32_t y = fp8(P.seed, 1u, P.ylevel, (uint32_t)P.peid[p0 + lane]);
+            ly_vec = y ? (uint32_t)lds[y] : kSkip;
+        }
+
+        int32_t cur_dst = -1;
+        uint32_t lx01[W], lx23[W], xm[W], acc[W];
+        uint32_t held[kHeldMax][W];
+        int32_t held_row[kHeldMax];
+        int nheld = 0;
+#pragma unroll
+        for (int w = 0; w < W; ++w) lx01[w] = lx23[w] = xm[w] = acc[w] = 0;
+
+        for (int32_t pb = p0; pb < p1; pb += kU) {
+            const int nb = min(kU, p1 - pb);
+            uint32_t g[kU][W];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int32_t r = (u < nb) ? P.gidx[pb + u] : -1;
+                if (r >= 0 && act) {
+                    load_row<W>(P.gbase, r, P.rowb, lane, g[u]);
+                } else {
+#pragma unroll
+                    for (int w = 0; w < W; ++w) g[u][w] = 0xFFFFFFFFu;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                if (u >= nb) break;
+                const int32_t p = pb + u;
+                const int32_t d = P.pdst[p];
+                if (d != cur_dst) {  // new in-list (or the start of a continuation tile)
+                    cur_dst = d;
+                    uint32_t lw[W];
+                    if (act) {
+                        load_row<W>(P.lxt, d, P.rowb, lane, lw);
+                    } else {
+#pragma unroll
+                        for (int w = 0; w < W; ++w) lw[w] = 0xFFFFFFFFu;
+                    }
+#pragma unroll
+                    for (int w = 0; w < W; ++w) {
+                        lx01[w] = __builtin_amdgcn_perm(0u, lw[w], 0x0C010C00u) + 0x00010001u;
+                        lx23[w] = __builtin_amdgcn_perm(0u, lw[w], 0x0C030C02u) + 0x00010001u;
+                        xm[w] = nonzero_mask(lw[w]);
+                        acc[w] = 0;
+                    }
+                }
+                const uint32_t ly = __builtin_amdgcn_readlane(ly_vec, p - p0);
+                uint32_t c[W];
+                if (ly != kSkip) {
+                    const uint32_t lyy = ly * 0x00010001u;
+#pragma unroll
+                    for (int w = 0; w < W; ++w)
+                        c[w] = mul4(lds, g[u][w], lx01[w] + lyy, lx23[w] + lyy) & xm[w];
+                } else {
+#pragma unroll
+                    for (int w = 0; w < W; ++w) c[w] = 0;
+                }
+                if constexpr (FIN) {
+                    if (p >= P.pos_lo && p < P.pos_hi) {
+#pragma unroll
+                        for (int w = 0; w < W; ++w) fin[w] ^= c[w];
+                        if (P.loc) {
+                            uint32_t x = 0;
+#pragma unroll
+                            for (int w = 0; w < W; ++w) x ^= c[w];
+                            x ^= x >> 16;
+                            x ^= x >> 8;
+                            x &= 0xFFu;
+#pragma unroll
+                            for (int off = 32; off >= 1; off >>= 1) x ^= __shfl_xor(x, off);
+                            if (lane == 0) P.loc[p - P.pos_lo] ^= (uint8_t)x;
+                        }
+                    }
+                } else {
+#pragma unroll
+                    for (int w = 0; w < W; ++w) acc[w] ^= c[w];
+                    const int32_t orow = P.orow[p];
+                    if (orow >= 0) {
+                        if (cont) {
+#pragma unroll
+                            for (int h = 0; h < kHeldMax; ++h) {
+                                if (h == nheld) {
+#pragma unroll
+                                    for (int w = 0; w < W; ++w) held[h][w] = acc[w];
+                                    held_row[h] = orow;
+                                }
+                            }
+                            ++nheld;
+                        } else if (act) {
+                            uint32_t o[W];
+#pragma unroll
+                            for (int w = 0; w < W; ++w) o[w] = tolog4(lds, acc[w]);
+                            store_row<W>(P.sout, orow, P.rowb, lane, o);
+                        }
+                    }
+                }
+            }
+        }
+
+        if constexpr (!FIN) {
+            if (act) {
+                if (pubslot >= 0)
+                    publish<W>(P.pub, pubslot, rowd, lane, cont ? kAgg : kInc, epoch, acc);
+                if (cont) {
+                    uint32_t carry[W];
+                    lookback<W>(P.pub, lbslot, rowd, lane, epoch, P.ctl, carry);
+#pragma unroll
+                    for (int h = 0; h < kHeldMax; ++h) {
+                        if (h < nheld) {
+                            uint32_t o[W];
+#pragma unroll
+                            for (int w = 0; w < W; ++w) o[w] = tolog4(lds, held[h][w] ^ carry[w]);
+                            store_row<W>(P.sout, held_row[h], P.rowb, lane, o);
+                        }
+                    }
+                    if (pubslot >= 0) {
+                        uint32_t inc[W];
+#pragma unroll
+                        for (int w = 0; w < W; ++w) inc[w] = acc[w] ^ carry[w];
+                        publish<W>(P.pub, pubslot, rowd, lane, kInc, epoch, inc);
+                    }
+                }
+            }
+        }
+    }
+
+    if constexpr (FIN) {
+        if (act) {
+#pragma unroll
+            for (int w = 0; w < W; ++w)
+                if (fin[w]) atomicXor(&P.fin[lane * W + w], fin[w]);
+        }
+    }
+}
+
+__global__ void k_prep(Ctl *ctl, int bump_epoch) {
+    ctl->ticket = 0;
+    if (bump_epoch) ctl->epoch = (ctl->epoch + 1u) & 0x3FFFFFFFu;
+}
+
+// z[u*k + j] = sum over slots d of colour c(u) of v_{u,d} * w_{d,j} (Eq. (motif));
+// zero for a deleted vertex or a colour outside the multiset.
+__global__ void k_z(int32_t n, int32_t k, const int32_t *color, QuerySlots qs, const uint8_t *mask,
+                    uint64_t seed, uint8_t *z) {
+    int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= n) return;
+    int32_t c = color[u];
+    int32_t off = -1, mu = 0;
+    for (int i = 0; i < qs.ncol; ++i)
+        if (qs.col[i] == c) {
+            off = qs.off[i];
+            mu = qs.mu[i];
+        }
+    const bool live = (mask == nullptr || mask[u] != 0) && mu > 0;
+    for (int j = 0; j < k; ++j) {
+        uint32_t acc = 0;
+        if (live)
+            for (int d = off; d < off + mu; ++d)
+                acc ^= gmul(fp8(seed, 2u, (uint32_t)d, (uint32_t)u), fp8(seed, 3u, (uint32_t)d, (uint32_t)j));
+        z[u * k + j] = (uint8_t)acc;
+    }
+}
+
+// Row of log x_u^A for the chunk's points A = base + b, x_u^A = sum_{j in A} z_{u,j}.
+__global__ void k_lxt(int32_t n, int32_t k, int32_t rowb, uint32_t base, const uint8_t *z,
+                      uint8_t *lxt) {
+    const int32_t rowd = rowb >> 2;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)n * rowd) return;
+    int64_t u = i / rowd;
+    int32_t dw = (int32_t)(i - u * rowd);
+    uint8_t zz[16];
+    for (int j = 0; j < k; ++j) zz[j] = z[u * k + j];
+    uint32_t out = 0;
+    for (int b = 0; b < 4; ++b) {
+        uint32_t A = base + (uint32_t)(dw * 4 + b);
+        uint32_t x = 0;
+        for (int j = 0; j < k; ++j)
+            if ((A >> j) & 1u) x ^= zz[j];
+        out |= (uint32_t)c_gf.log[x] << (8 * b);
+    }
+    ((uint32_t *)lxt)[i] = out;
+}
+
+// k = 1: P(A) = sum_u x_u^A, A in {0, 1}; x^0 = 0, x^1 = z_{u,0}.
+__global__ void k_single(int32_t n, const uint8_t *z, uint32_t *out) {
+    int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t v = (u < n) ? ((uint32_t)z[u] << 8) : 0u;
+    for (int off = 32; off >= 1; off >>= 1) v ^= __shfl_xor(v, off);
+    if ((threadIdx.x & 63) == 0 && v) atomicXor(out, v);
+}
+
+// total = XOR of all per-point bytes
+__global__ void k_total(int32_t npts, const uint8_t *pp, uint8_t *total) {
+    uint32_t v = 0;
+    for (int32_t i = threadIdx.x; i < npts; i += blockDim.x) v ^= pp[i];
+    for (int off = 32; off >= 1; off >>= 1) v ^= __shfl_xor(v, off);
+    __shared__ uint32_t part[16];
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t ^= part[i];
+        *total = (uint8_t)t;
+    }
+}
+
+// smallest (input edge id, position) over positions whose localisation is nonzero
+__global__ void k_pick(int32_t lo, int32_t hi, const uint8_t *loc, const int32_t *peid,
+                       unsigned long long *best) {
+    int64_t p = (int64_t)lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < hi && loc[p - lo])
+        atomicMin(best, ((unsigned long long)(uint32_t)peid[p] << 32) | (unsigned long long)p);
+}
+
+inline unsigned grid_for(int64_t work, int block = 256) {
+    return (unsigned)std::max<int64_t>(1, (work + block - 1) / block);
+}
+
+struct DevBuf {
+    void *p = nullptr;
+    hipStream_t s = nullptr;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    void alloc(size_t bytes, hipStream_t st) {
+        s = st;
+        TPM_HIP(hipMallocAsync(&p, std::max<size_t>(bytes, 16), st));
+    }
+    ~DevBuf() {
+        if (p) (void)hipFreeAsync(p, s);
+    }
+    template <class T>
+    T *as() const { return (T *)p; }
+};
+
+QuerySlots make_slots(const Graph &G, const int32_t *M, int32_t k) {
+    TPM_REQUIRE(M != nullptr, "multiset must not be NULL");
+    TPM_REQUIRE(k >= 1 && k <= 16, "k must be in [1, 16]");
+    int32_t cols[16];
+    for (int i = 0; i < k; ++i) {
+        TPM_REQUIRE(M[i] >= 0 && M[i] < G.q, "multiset colour out of range");
+        cols[i] = M[i];
+    }
+    std::sort(cols, cols + k);
+    QuerySlots qs{};
+    int next = 0;
+    for (int i = 0; i < k;) {
+        int j = i;
+        while (j < k && cols[j] == cols[i]) ++j;
+        qs.col[qs.ncol] = cols[i];
+        qs.off[qs.ncol] = next;
+        qs.mu[qs.ncol] = j - i;
+        next += j - i;
+        ++qs.ncol;
+        i = j;
+    }
+    return qs;
+}
+
+template <int W, bool FIN>
+void launch_level(const Graph &G, const LevelParams &P, hipStream_t st) {
+    hipLaunchKernelGGL((k_level<W, FIN>), dim3((unsigned)G.num_cu), dim3(1024), 0, st, P);
+}
+
+void launch_level_w(int W, bool fin, const Graph &G, const LevelParams &P, hipStream_t st) {
+    if (W == 4) fin ? launch_level<4, true>(G, P, st) : launch_level<4, false>(G, P, st);
+    else if (W == 2) fin ? launch_level<2, true>(G, P, st) : launch_level<2, false>(G, P, st);
+    else fin ? launch_level<1, true>(G, P, st) : launch_level<1, false>(G, P, st);
+}
+
+int pick_chunk(const Graph &G, int32_t k, int32_t requested) {
+    const int64_t npts = int64_t(1) << k;
+    int64_t c = requested > 0 ? requested : std::min<int64_t>(npts, 1024);
+    TPM_REQUIRE((c & (c - 1)) == 0 && c >= 4 && c <= 1024, "chunk must be a power of two in [4, 1024]");
+    c = std::min<int64_t>(c, std::max<int64_t>(npts, 4));
+    // fit the two level buffers into free device memory
+    size_t freeb = 0, totalb = 0;
+    if (hipMemGetInfo(&freeb, &totalb) == hipSuccess && requested <= 0) {
+        while (c > 4 && (double)(2 * G.R + G.n + 2 * G.nslots) * c > 0.85 * (double)freeb) c >>= 1;
+    }
+    return (int)c;
+}
+
+}  // namespace
+
+// Positions [lo, hi) of the last level contribute (all when fin_lo >= fin_hi).  With
+// want_loc, the per-position localisation over that range is computed on the device;
+// loc_host (nullable, hi - lo bytes) receives it, and res.pick_eid / res.pick_pos get
+// the contributing position with nonzero localisation and the smallest input edge id
+// (-1 if none).
+void run_sieve_impl(const Graph &G, const SieveRequest &req, SieveResult &res, bool want_loc,
+                    uint8_t *loc_host, hipStream_t st) {
+    const int32_t k = req.k;
+    QuerySlots qs = make_slots(G, req.multiset, k);
+    const int64_t npts = int64_t(1) << k;
+    const int rowb = (k == 1) ? 4 : pick_chunk(G, k, req.chunk);
+    const int W = rowb >= 1024 ? 4 : (rowb >= 512 ? 2 : 1);
+    const int lanes = rowb / (4 * W);
+    const int rowd = rowb / 4;
+    const int64_t ppbytes = std::max<int64_t>(npts, 4);
+
+    DevBuf ctl, z, lxt, s0, s1, pub, pp, tot, mask, loc;
+    ctl.alloc(sizeof(Ctl), st);
+    TPM_HIP(hipMemsetAsync(ctl.p, 0, sizeof(Ctl), st));
+    z.alloc((size_t)G.n * k, st);
+    pp.alloc((size_t)ppbytes, st);
+    TPM_HIP(hipMemsetAsync(pp.p, 0, (size_t)ppbytes, st));
+    tot.alloc(4, st);
+    const uint8_t *dmask = nullptr;
+    if (req.vertex_mask) {
+        mask.alloc((size_t)G.n, st);
+        TPM_HIP(hipMemcpyAsync(mask.p, req.vertex_mask, (size_t)G.n, hipMemcpyHostToDevice, st));
+        dmask = mask.as<uint8_t>();
+    }
+    k_z<<<grid_for(G.n), 256, 0, st>>>(G.n, k, G.color, qs, dmask, req.seed, z.as<uint8_t>());
+
+    int64_t lo = 0, hi = G.m;
+    if (req.fin_lo < req.fin_hi) {
+        lo = std::max<int64_t>(0, req.fin_lo);
+        hi = std::min<int64_t>(G.m, req.fin_hi);
+    }
+    DevBuf pick;
+    if (want_loc) {
+        loc.alloc((size_t)std::max<int64_t>(1, hi - lo), st);
+        TPM_HIP(hipMemsetAsync(loc.p, 0, (size_t)std::max<int64_t>(1, hi - lo), st));
+        pick.alloc(sizeof(unsigned long long), st);
+        TPM_HIP(hipMemsetAsync(pick.p, 0xFF, sizeof(unsigned long long), st));
+    }
+
+    if (k == 1) {
+        k_single<<<grid_for(G.n), 256, 0, st>>>(G.n, z.as<uint8_t>(), pp.as<uint32_t>());
+    } else if (G.m > 0) {
+        lxt.alloc((size_t)G.n * rowb, st);
+        s0.alloc((size_t)std::max<int64_t>(1, G.R) * rowb, st);
+        if (k > 2) s1.alloc((size_t)std::max<int64_t>(1, G.R) * rowb, st);
+        if (k > 2 && G.nslots) {
+            // published words carry a per-launch epoch; start every query from zero so
+            // that a reused allocation never holds a word with a current epoch
+            pub.alloc((size_t)G.nslots * rowd * 8, st);
+            TPM_HIP(hipMemsetAsync(pub.p, 0, (size_t)G.nslots * rowd * 8, st));
+        }
+        // tiles covering the contributing positions of the last level
+        const auto &tp = G.h_tile_p0;
+        int32_t fin_tlo = 0, fin_thi = (int32_t)G.ntiles;
+        if (lo > 0 || hi < G.m) {
+            fin_tlo = (int32_t)(std::upper_bound(tp.begin(), tp.end(), (int32_t)lo) - tp.begin()) - 1;
+            fin_thi = (int32_t)(std::lower_bound(tp.begin(), tp.end(), (int32_t)hi) - tp.begin());
+            fin_tlo = std::max(0, fin_tlo);
+            fin_thi = std::min<int32_t>((int32_t)G.ntiles, fin_thi);
+        }
+        for (int64_t base = 0; base < npts; base += rowb) {
+            k_lxt<<<grid_for((int64_t)G.n * rowd), 256, 0, st>>>(G.n, k, rowb, (uint32_t)base,
+                                                                 z.as<uint8_t>(), lxt.as<uint8_t>());
+            for (int l = 2; l <= k; ++l) {
+                const bool fin = (l == k);
+                LevelParams P{};
+                P.gidx = (l == 2) ? G.psrc : G.gsrc;
+                P.gbase = (l == 2) ? lxt.as<uint8_t>() : ((l & 1) ? s0.as<uint8_t>() : s1.as<uint8_t>());
+                P.pdst = G.pdst;
+                P.peid = G.peid;
+                P.orow = G.orow;
+                P.sout = (l & 1) ? s1.as<uint8_t>() : s0.as<uint8_t>();
+                P.lxt = lxt.as<uint8_t>();
+                P.tile_p0 = G.tile_p0;
+                P.tile_pub = G.tile_pub;
+                P.tile_lb = G.tile_lb;
+                P.tile_lo = fin ? fin_tlo : 0;
+                P.tile_hi = fin ? fin_thi : (int32_t)G.ntiles;
+                P.pos_lo = (int32_t)lo;
+                P.pos_hi = (int32_t)hi;
+                P.pub = pub.as<unsigned long long>();
+                P.ctl = ctl.as<Ctl>();
+                P.fin = (uint32_t *)(pp.as<uint8_t>() + base);
+                P.loc = want_loc ? loc.as<uint8_t>() : nullptr;
+                P.lds_image = G.lds_image;
+                P.seed = req.seed;
+                P.ylevel = (uint32_t)(l - 1);
+                P.rowb = rowb;
+                P.lanes = lanes;
+                k_prep<<<1, 1, 0, st>>>(ctl.as<Ctl>(), fin ? 0 : 1);
+                launch_level_w(W, fin, G, P, st);
+            }
+        }
+    }
+    k_total<<<1, 256, 0, st>>>((int32_t)npts, pp.as<uint8_t>(), tot.as<uint8_t>());
+    unsigned long long hpick = ~0ull;
+    if (want_loc && hi > lo) {
+        k_pick<<<grid_for(hi - lo), 256, 0, st>>>((int32_t)lo, (int32_t)hi, loc.as<uint8_t>(), G.peid,
+                                                  pick.as<unsigned long long>());
+        TPM_HIP(hipMemcpyAsync(&hpick, pick.p, sizeof(hpick), hipMemcpyDeviceToHost, st));
+    }
+    TPM_HIP(hipGetLastError());
+    res.per_point.resize((size_t)npts);
+    Ctl hctl{};
+    TPM_HIP(hipMemcpyAsync(res.per_point.data(), pp.p, (size_t)npts, hipMemcpyDeviceToHost, st));
+    TPM_HIP(hipMemcpyAsync(&res.total, tot.p, 1, hipMemcpyDeviceToHost, st));
+    TPM_HIP(hipMemcpyAsync(&hctl, ctl.p, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+    if (want_loc && loc_host && hi > lo)
+        TPM_HIP(hipMemcpyAsync(loc_host, loc.p, (size_t)(hi - lo), hipMemcpyDeviceToHost, st));
+    TPM_HIP(hipStreamSynchronize(st));
+    res.pick_eid = -1;
+    res.pick_pos = -1;
+    if (hpick != ~0ull) {
+        res.pick_eid = (int64_t)(hpick >> 32);
+        res.pick_pos = (int64_t)(hpick & 0xFFFFFFFFull);
+    }
+    if (hctl.err)
+        throw Error{TPM_EDEVICE, "sieve kernel reported a look-back failure (code " +
+                                     std::to_string(hctl.err) + ")"};
+}
+
+void run_sieve(const Graph &G, const SieveRequest &req, SieveResult &res, hipStream_t st) {
+    run_sieve_impl(G, req, res, req.want_pick, nullptr, st);
+}
+
+void run_sieve_loc_all(const Graph &G, const SieveRequest &req, SieveResult &res,
+                       uint8_t *loc_by_edge, hipStream_t st) {
+    std::vector<uint8_t> bypos((size_t)std::max<int64_t>(1, G.m));
+    SieveRequest r2 = req;
+    r2.fin_lo = 0;
+    r2.fin_hi = 0;
+    run_sieve_impl(G, r2, res, true, bypos.data(), st);
+    if (G.m) {
+        std::vector<int32_t> peid((size_t)G.m);
+        TPM_HIP(hipMemcpy(peid.data(), G.peid, sizeof(int32_t) * G.m, hipMemcpyDeviceToHost));
+        for (int64_t p = 0; p < G.m; ++p) loc_by_edge[peid[p]] = bypos[p];
+    }
+}
+
+}  // namespace tpm

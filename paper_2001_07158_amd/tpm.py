@@ -1,0 +1,305 @@
+"""ctypes binding of libtpm.so (include/tpm.h), argument marshalling only.
+
+Every computation runs in the HIP library; if the library is missing this module
+raises at import time -- there is no CPU fallback.  Functions keep the C names;
+`Graph` and `Server` are thin owners of the handles.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtpm.so")
+
+TPM_OK = 0
+TPM_NOTFOUND = 1
+TPM_PENDING = 2
+TPM_EINVAL = -1
+TPM_ENOMEM = -2
+TPM_EDEVICE = -3
+TPM_ECANCELLED = -4
+TPM_ECLOSED = -5
+TPM_DEVICE_PTRS = 0x1
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                      "(paper_2001_07158_amd/build.py) first")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_u8p = ctypes.POINTER(ctypes.c_uint8)
+_u64p = ctypes.POINTER(ctypes.c_uint64)
+
+
+class tpm_graph_options(ctypes.Structure):
+    _fields_ = [("tile_edges", ctypes.c_int32), ("tile_held", ctypes.c_int32)]
+
+
+class tpm_graph_stats(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("m", ctypes.c_int64), ("num_colors", ctypes.c_int32),
+                ("tmax", ctypes.c_int32), ("rows", ctypes.c_int64), ("tiles", ctypes.c_int64),
+                ("slots", ctypes.c_int64), ("max_in_degree", ctypes.c_int64),
+                ("device_bytes", ctypes.c_int64)]
+
+
+class tpm_tuning(ctypes.Structure):
+    _fields_ = [("chunk", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32)]
+
+
+class tpm_query(ctypes.Structure):
+    _fields_ = [("multiset", _i32p), ("k", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("want_path", ctypes.c_int32)]
+
+
+class tpm_result(ctypes.Structure):
+    _fields_ = [("found", ctypes.c_int32), ("total", ctypes.c_uint8),
+                ("path_status", ctypes.c_int32), ("path_vertices", ctypes.c_int32 * 16),
+                ("path_edges", ctypes.c_int64 * 15), ("ticket", ctypes.c_uint64),
+                ("t_submit_ms", ctypes.c_double), ("t_start_ms", ctypes.c_double),
+                ("t_done_ms", ctypes.c_double)]
+
+
+class tpm_server_config(ctypes.Structure):
+    _fields_ = [("state_bytes", ctypes.c_int64), ("max_lanes", ctypes.c_int32),
+                ("extract_paths", ctypes.c_int32)]
+
+
+def _sig(name, res, args):
+    f = getattr(_lib, name)
+    f.restype = res
+    f.argtypes = args
+    return f
+
+
+_vp = ctypes.c_void_p
+_sig("tpm_graph_create", ctypes.c_int32, [ctypes.c_int32, ctypes.c_int64, _vp, _vp, _vp, _vp,
+                                         ctypes.c_int32, ctypes.c_uint32, ctypes.POINTER(_vp)])
+_sig("tpm_graph_create_ex", ctypes.c_int32,
+     [ctypes.c_int32, ctypes.c_int64, _vp, _vp, _vp, _vp, ctypes.c_int32, ctypes.c_uint32,
+      ctypes.POINTER(tpm_graph_options), ctypes.POINTER(_vp)])
+_sig("tpm_graph_destroy", None, [_vp])
+_sig("tpm_graph_stats_get", ctypes.c_int32, [_vp, ctypes.POINTER(tpm_graph_stats)])
+_sig("tpm_sieve", ctypes.c_int32, [_vp, _i32p, ctypes.c_int32, ctypes.c_uint64, _u8p, _u8p, _u8p,
+                                  _vp])
+_sig("tpm_sieve_ex", ctypes.c_int32, [_vp, _i32p, ctypes.c_int32, ctypes.c_uint64, _u8p,
+                                     ctypes.POINTER(tpm_tuning), _u8p, _u8p, _u8p, _vp])
+_sig("tpm_decide", ctypes.c_int32, [_vp, _i32p, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int32,
+                                   _i32p])
+_sig("tpm_extract", ctypes.c_int32, [_vp, _i32p, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int32,
+                                    _i32p, _i64p])
+_sig("tpm_batch_run", ctypes.c_int32, [_vp, ctypes.c_int32, ctypes.POINTER(tpm_query),
+                                      ctypes.POINTER(tpm_result), ctypes.POINTER(tpm_tuning)])
+_sig("tpm_server_create", ctypes.c_int32, [_vp, ctypes.POINTER(tpm_server_config),
+                                          ctypes.POINTER(_vp)])
+_sig("tpm_server_submit", ctypes.c_int32, [_vp, ctypes.POINTER(tpm_query), _u64p])
+_sig("tpm_server_poll", ctypes.c_int32, [_vp, ctypes.POINTER(tpm_result), ctypes.c_int32, _i32p])
+_sig("tpm_server_destroy", None, [_vp])
+_sig("tpm_last_error", ctypes.c_char_p, [])
+_sig("tpm_version", ctypes.c_char_p, [])
+
+EXPORTED = ["tpm_graph_create", "tpm_graph_create_ex", "tpm_graph_destroy", "tpm_graph_stats_get",
+            "tpm_sieve", "tpm_sieve_ex", "tpm_decide", "tpm_extract", "tpm_batch_run",
+            "tpm_server_create", "tpm_server_submit", "tpm_server_poll", "tpm_server_destroy",
+            "tpm_last_error", "tpm_version"]
+
+
+class TpmError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"tpm error {code}: {msg}")
+        self.code = code
+
+
+def tpm_last_error() -> str:
+    return (_lib.tpm_last_error() or b"").decode()
+
+
+def tpm_version() -> str:
+    return _lib.tpm_version().decode()
+
+
+def _check(rc: int, ok=(TPM_OK,)) -> int:
+    if rc not in ok:
+        raise TpmError(rc, tpm_last_error())
+    return rc
+
+
+def _i32(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _ptr(a, t=_vp):
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data_as(t) if t is not _vp else ctypes.c_void_p(a.ctypes.data)
+    return a
+
+
+def _stream_handle(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(int(stream.cuda_stream))  # torch.cuda.Stream
+
+
+# ------------------------------------------------------------------ C-named wrappers
+def tpm_graph_create(n, src, dst, tau, color, num_colors, flags=0, tile_edges=0, tile_held=0):
+    """Host numpy arrays, or raw device pointers (ints) with flags=TPM_DEVICE_PTRS."""
+    h = ctypes.c_void_p()
+    if flags & TPM_DEVICE_PTRS:
+        m = int(src[1])
+        ptrs = [ctypes.c_void_p(int(x[0])) for x in (src, dst, tau, color)]
+    else:
+        src, dst, tau, color = _i32(src), _i32(dst), _i32(tau), _i32(color)
+        m = int(src.shape[0])
+        if not (dst.shape[0] == m and tau.shape[0] == m and color.shape[0] == n):
+            raise ValueError("array lengths do not match n/m")
+        ptrs = [_ptr(x) for x in (src, dst, tau, color)]
+    opt = tpm_graph_options(int(tile_edges), int(tile_held))
+    _check(_lib.tpm_graph_create_ex(int(n), m, *ptrs, int(num_colors), int(flags),
+                                    ctypes.byref(opt), ctypes.byref(h)))
+    return h
+
+
+def tpm_graph_destroy(h) -> None:
+    _lib.tpm_graph_destroy(h)
+
+
+def tpm_graph_stats_get(h) -> dict:
+    st = tpm_graph_stats()
+    _check(_lib.tpm_graph_stats_get(h, ctypes.byref(st)))
+    return {f: getattr(st, f) for f, _ in tpm_graph_stats._fields_}
+
+
+def tpm_sieve(h, multiset, seed, mask=None, chunk=0, loc_m=None, stream=None):
+    """Returns (per_point uint8[2^k], total int) or, with loc_m = number of edges,
+    (per_point, total, loc uint8[m])."""
+    M = _i32(multiset)
+    k = int(M.shape[0])
+    pp = np.zeros(1 << k, dtype=np.uint8)
+    tot = np.zeros(1, dtype=np.uint8)
+    mk = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8)
+    loc = None if loc_m is None else np.zeros(max(1, int(loc_m)), dtype=np.uint8)
+    tune = tpm_tuning(int(chunk), 0)
+    _check(_lib.tpm_sieve_ex(h, M.ctypes.data_as(_i32p), k, int(seed) & (2**64 - 1),
+                             _ptr(mk, _u8p), ctypes.byref(tune), pp.ctypes.data_as(_u8p),
+                             tot.ctypes.data_as(_u8p), _ptr(loc, _u8p), _stream_handle(stream)))
+    if loc is not None:
+        return pp, int(tot[0]), loc[: int(loc_m)]
+    return pp, int(tot[0])
+
+
+def tpm_decide(h, multiset, seed, reps=1) -> bool:
+    M = _i32(multiset)
+    found = ctypes.c_int32(0)
+    _check(_lib.tpm_decide(h, M.ctypes.data_as(_i32p), int(M.shape[0]), int(seed) & (2**64 - 1),
+                           int(reps), ctypes.byref(found)))
+    return bool(found.value)
+
+
+def tpm_extract(h, multiset, seed, max_reps=8):
+    """Returns (status, vertices[k], edges[k-1]); status TPM_OK or TPM_NOTFOUND."""
+    M = _i32(multiset)
+    k = int(M.shape[0])
+    pv = np.full(k, -1, dtype=np.int32)
+    pe = np.full(max(1, k - 1), -1, dtype=np.int64)
+    rc = _check(_lib.tpm_extract(h, M.ctypes.data_as(_i32p), k, int(seed) & (2**64 - 1),
+                                 int(max_reps), pv.ctypes.data_as(_i32p), pe.ctypes.data_as(_i64p)),
+                ok=(TPM_OK, TPM_NOTFOUND))
+    return rc, pv, pe[: k - 1]
+
+
+def _make_queries(queries):
+    keep = []
+    arr = (tpm_query * len(queries))()
+    for i, q in enumerate(queries):
+        M = _i32(q["multiset"])
+        keep.append(M)
+        arr[i].multiset = M.ctypes.data_as(_i32p)
+        arr[i].k = int(M.shape[0])
+        arr[i].seed = int(q.get("seed", 0)) & (2**64 - 1)
+        arr[i].want_path = int(q.get("want_path", 0))
+    return arr, keep
+
+
+def _result_dict(r: tpm_result) -> dict:
+    return {"found": bool(r.found), "total": int(r.total), "path_status": int(r.path_status),
+            "path_vertices": list(r.path_vertices), "path_edges": list(r.path_edges),
+            "ticket": int(r.ticket), "t_submit_ms": r.t_submit_ms, "t_start_ms": r.t_start_ms,
+            "t_done_ms": r.t_done_ms}
+
+
+def tpm_batch_run(h, queries, chunk=0):
+    arr, _keep = _make_queries(queries)
+    out = (tpm_result * len(queries))()
+    tune = tpm_tuning(int(chunk), 0)
+    _check(_lib.tpm_batch_run(h, len(queries), arr, out, ctypes.byref(tune)))
+    return [_result_dict(out[i]) for i in range(len(queries))]
+
+
+def tpm_server_create(h, state_bytes=0, max_lanes=0, extract_paths=0):
+    cfg = tpm_server_config(int(state_bytes), int(max_lanes), int(extract_paths))
+    s = ctypes.c_void_p()
+    _check(_lib.tpm_server_create(h, ctypes.byref(cfg), ctypes.byref(s)))
+    return s
+
+
+def tpm_server_submit(s, multiset, seed, want_path=0) -> int:
+    arr, keep = _make_queries([{"multiset": multiset, "seed": seed, "want_path": want_path}])
+    t = ctypes.c_uint64(0)
+    _check(_lib.tpm_server_submit(s, ctypes.byref(arr[0]), ctypes.byref(t)))
+    del keep
+    return int(t.value)
+
+
+def tpm_server_poll(s, max_results=64):
+    out = (tpm_result * max_results)()
+    n = ctypes.c_int32(0)
+    _check(_lib.tpm_server_poll(s, out, int(max_results), ctypes.byref(n)), ok=(TPM_OK, TPM_PENDING))
+    return [_result_dict(out[i]) for i in range(n.value)]
+
+
+def tpm_server_destroy(s) -> None:
+    _lib.tpm_server_destroy(s)
+
+
+# ------------------------------------------------------------------ owners
+class Graph:
+    def __init__(self, n, src, dst, tau, color, num_colors, tile_edges=0, tile_held=0):
+        self.n = int(n)
+        self.m = int(len(src))
+        self.h = tpm_graph_create(n, src, dst, tau, color, num_colors, 0, tile_edges, tile_held)
+
+    @classmethod
+    def from_temporal(cls, g, **kw):
+        return cls(g.n, g.src, g.dst, g.tau, g.color, g.num_colors, **kw)
+
+    def stats(self) -> dict:
+        return tpm_graph_stats_get(self.h)
+
+    def sieve(self, multiset, seed, mask=None, chunk=0, loc=False, stream=None):
+        return tpm_sieve(self.h, multiset, seed, mask, chunk, self.m if loc else None, stream)
+
+    def decide(self, multiset, seed, reps=1) -> bool:
+        return tpm_decide(self.h, multiset, seed, reps)
+
+    def extract(self, multiset, seed, max_reps=8):
+        return tpm_extract(self.h, multiset, seed, max_reps)
+
+    def batch(self, queries, chunk=0):
+        return tpm_batch_run(self.h, queries, chunk)
+
+    def close(self):
+        if getattr(self, "h", None):
+            tpm_graph_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()

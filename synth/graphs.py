@@ -62,20 +62,32 @@ def uniform_graph(n: int, m: int, t: int, q: int, seed: int,
                          tau.astype(np.int32), color.astype(np.int32), q)
 
 
-def _inverse_cdf_sampler(rng, weights: np.ndarray):
-    cdf = np.cumsum(weights, dtype=np.float64)
-    cdf /= cdf[-1]
+def _alias_sampler(rng, weights: np.ndarray):
+    """Draws indices with probability proportional to `weights` (Walker's alias
+    method, Vose's construction)."""
     n = weights.shape[0]
+    prob = weights.astype(np.float64) * (n / weights.sum())
+    accept = np.ones(n, dtype=np.float64)
+    alias = np.arange(n, dtype=np.int64)
+    small = list(np.nonzero(prob < 1.0)[0])
+    large = list(np.nonzero(prob >= 1.0)[0])
+    p = prob.tolist()
+    while small and large:
+        s = small.pop()
+        l = large.pop()
+        accept[s] = p[s]
+        alias[s] = l
+        p[l] -= 1.0 - p[s]
+        (small if p[l] < 1.0 else large).append(l)
 
     def draw(size: int) -> np.ndarray:
         out = np.empty(size, dtype=np.int64)
         step = 1 << 24
         for lo in range(0, size, step):
             hi = min(size, lo + step)
+            i = rng.integers(0, n, hi - lo)
             u = rng.random(hi - lo)
-            idx = np.searchsorted(cdf, u, side="right")
-            np.minimum(idx, n - 1, out=idx)
-            out[lo:hi] = idx
+            out[lo:hi] = np.where(u < accept[i], i, alias[i])
         return out
 
     return draw
@@ -87,14 +99,14 @@ def chung_lu_graph(n: int, m: int, beta: float, t: int, q: int, seed: int) -> Te
     Vertex weights w_i = (i+1)^(-1/(beta-1)); the out-weights and the in-weights
     are two independent random permutations of them.  Each edge draws its source
     with probability proportional to the out-weight and its destination with
-    probability proportional to the in-weight; a self-loop is redrawn.  Timestamps
+    probability proportional to the in-weight (alias tables); a self-loop is redrawn.  Timestamps
     are uniform on [1, t] and colours uniform on [0, q)."""
     rng = np.random.default_rng(seed)
     base = np.power(np.arange(1, n + 1, dtype=np.float64), -1.0 / (beta - 1.0))
     w_out = base[rng.permutation(n)]
     w_in = base[rng.permutation(n)]
-    draw_src = _inverse_cdf_sampler(rng, w_out)
-    draw_dst = _inverse_cdf_sampler(rng, w_in)
+    draw_src = _alias_sampler(rng, w_out)
+    draw_dst = _alias_sampler(rng, w_in)
     src = draw_src(m)
     dst = draw_dst(m)
     src, dst = _redraw_self_loops(rng, src, dst, draw_src, draw_dst)
