@@ -1,0 +1,220 @@
+#!/usr/bin/env python3
+"""Throughput of the GF(2^8) temporal path-motif sieve on one MI355X.
+
+One step = one full sieve query (all 2^k sieve points, levels 2..k, XOR reduction)
+through the C ABI, on the k = 10 directed Chung-Lu workload (n = 1e6, m = 1e8,
+beta = 2.5, timestamps U[1, 1e4], 16 colours, a multiset of 10 i.i.d. colours).
+The graph index is built before timing (inputs resident in HBM).
+
+Prints one JSON line: edge-updates/s (m * k * 2^k per query), per-query latency,
+the roofline of the dominant kernel (measured with HIP events on its stream) and
+the CPU oracle timed on a bounded sample of the same workload.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "GF(2^8) sieve edge-updates/s (m·k·2^k) at k=10; HBM GB/s; p50/p99 query ms"
+HBM_PEAK_GBPS = 8000.0
+PMC_FILE = os.path.join(ROOT, "profiles", "k10_level_middle_pmc.txt")
+KERNEL_SRC = os.path.join(ROOT, "paper_2001_07158_amd", "csrc", "tpm_sieve.hip")
+
+
+def kernel_hash() -> str:
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def read_traffic(bytes_alg: float):
+    """HBM bytes per launch of the middle-level kernel from committed rocprofv3 PMC
+    summaries, if they were taken on the current kernel source."""
+    if not os.path.exists(PMC_FILE):
+        return None
+    kv = {}
+    for line in open(PMC_FILE):
+        if "=" in line and not line.lstrip().startswith("#"):
+            a, b = line.split("=", 1)
+            kv[a.strip()] = b.strip()
+    if kv.get("kernel_hash") != kernel_hash():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="k10", choices=["k10", "k5", "tiny"])
+    ap.add_argument("--chunk", type=int, default=0)
+    ap.add_argument("--cpu-points", type=int, default=16)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a 1 GiB device copy (for profiler counter scaling)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the sieve's "
+              "multi-GPU form (sieve points sharded, one XOR exchange) is not built.",
+              file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    from paper_2001_07158_amd import tpm
+    from synth import CONFIGS, make_config_graph, make_config_query
+
+    cfg = CONFIGS[args.workload]
+    t_gen = time.perf_counter()
+    g = make_config_graph(args.workload)
+    M = make_config_query(args.workload)
+    k = len(M)
+    t_gen = time.perf_counter() - t_gen
+    print(f"# workload {args.workload}: n={g.n} m={g.m} k={k} M={list(M)} (generated in "
+          f"{t_gen:.1f}s)", file=sys.stderr, flush=True)
+
+    t_idx = time.perf_counter()
+    G = tpm.Graph.from_temporal(g)
+    st = G.stats()
+    t_idx = time.perf_counter() - t_idx
+    print(f"# index built in {t_idx:.2f}s: rows={st['rows']} tiles={st['tiles']} "
+          f"slots={st['slots']} gathers={st['gathers']} segments={st['segments']}",
+          file=sys.stderr, flush=True)
+
+    stream = torch.cuda.current_stream()
+    seed0 = 20010715
+    for w in range(args.warmup):
+        G.sieve(M, seed0 + 1000 + w, chunk=args.chunk, stream=stream)
+        print(f"# warmup {w} done", file=sys.stderr, flush=True)
+
+    tpm.tpm_profile_read()  # drain
+    tpm.tpm_profile_enable(True)
+    lat = []
+    per_point = None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        ts = time.perf_counter()
+        pp, tot = G.sieve(M, seed0 + s, chunk=args.chunk, stream=stream)
+        lat.append((time.perf_counter() - ts) * 1e3)
+        if s == 0:
+            per_point = pp
+        print(f"# step {s}: {lat[-1]:.1f} ms total={tot}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    tpm.tpm_profile_enable(False)
+    ktimes = tpm.tpm_profile_read()
+
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    units = float(g.m) * k * (1 << k)
+    value = units / (ms_per_step / 1e3)
+    chunk_pts = ktimes[0]["chunk_points"] if ktimes else min(1 << k, 1024)
+
+    # ---- roofline of the dominant kernel (middle levels; level 2 when k == 3)
+    kinds = {}
+    for t in ktimes:
+        kinds.setdefault(t["kind"], []).append(t["ms"])
+    dom = "middle" if "middle" in kinds else ("level2" if "level2" in kinds else "last")
+    avg_ms = float(np.mean(kinds[dom])) if dom in kinds else float("nan")
+    C = chunk_pts
+    struct = 16.0 * g.m + 12.0 * st["tiles"] + float(st["segments"]) * C
+    if dom == "middle":
+        alg = (st["gathers"] + st["rows"]) * float(C) + struct
+    elif dom == "level2":
+        alg = (g.m + st["rows"]) * float(C) + struct
+    else:
+        alg = st["gathers"] * float(C) + struct
+    achieved = alg / (avg_ms / 1e3) / 1e9
+    traffic = read_traffic(alg)
+    # whole-query algorithmic bytes (all levels, all chunks)
+    nchunks = max(1, (1 << k) // C)
+    q_bytes = nchunks * ((g.m + st["rows"]) * float(C) + struct
+                         + max(0, k - 3) * ((st["gathers"] + st["rows"]) * float(C) + struct)
+                         + (st["gathers"] * float(C) + struct))
+    hbm_alg = q_bytes / (ms_per_step / 1e3) / 1e9
+
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "edge-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"{args.workload}: directed Chung-Lu n={g.n} m={g.m} beta=2.5 "
+                         f"t=[1,{cfg['t']}] q={cfg['q']} k={k}") if cfg["kind"] == "chung_lu"
+            else f"{args.workload}: uniform n={g.n} m={g.m} t=[1,{cfg['t']}] q={cfg['q']} k={k}",
+            "k": k, "n": g.n, "m": g.m, "sieve_points": 1 << k, "chunk_points": C,
+            "rows_stored": st["rows"], "tiles": st["tiles"],
+        },
+        "query_ms_p50": float(np.percentile(lat, 50)),
+        "query_ms_p99": float(np.percentile(lat, 99)),
+        "hbm_gbps_algorithmic_query": hbm_alg,
+        "roofline": {
+            "bound": "hbm", "kernel": f"k_level (W={4 if C >= 1024 else (2 if C >= 512 else 1)}, {dom})",
+            "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
+            "alg_bytes_per_launch": alg, "avg_launch_ms": avg_ms, "launches": len(kinds.get(dom, [])),
+            "kernel_hash": kernel_hash(),
+        },
+        "cpu_baseline": None,
+    }
+
+    if args.copy_calibration:
+        a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    if not args.no_cpu_baseline:
+        import oracle
+        nthreads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
+        rng = np.random.default_rng(7)
+        P = min(args.cpu_points, 1 << k)
+        pts = np.sort(rng.choice(1 << k, P, replace=False)).astype(np.uint32)
+        t_oi = time.perf_counter()
+        idx = oracle.Index(g)
+        t_oi = time.perf_counter() - t_oi
+        print(f"# oracle index {t_oi:.1f}s; evaluating {P} points on {nthreads} threads",
+              file=sys.stderr, flush=True)
+        tc = time.perf_counter()
+        want = idx.eval(M, seed0, pts, nthreads=nthreads)
+        tc = time.perf_counter() - tc
+        parity = bool(np.array_equal(per_point[pts], want))
+        line["cpu_baseline"] = {
+            "value": float(g.m) * k * P / tc, "unit": "edge-updates/s", "cores": nthreads,
+            "kind": "oracle",
+            "sample": f"{P} of {1 << k} sieve points over the full graph, all levels "
+                      f"({tc:.1f}s; index build {t_oi:.1f}s not timed)",
+            "parity_on_sample": parity,
+        }
+        print(f"# oracle sample parity: {parity}", file=sys.stderr, flush=True)
+
+    print(json.dumps(line), flush=True)
+    G.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

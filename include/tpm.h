@@ -62,9 +62,10 @@ typedef int32_t tpm_status;
 typedef struct tpm_graph tpm_graph;
 
 /* Work-tile shape of the in-edge index, fixed at graph creation.
- * tile_edges: most CSR positions per tile (1..64, default 64).
- * tile_held:  most stored state rows in a tile that continues a segment begun
- *             in an earlier tile (1..16, default 8).  Zero = default. */
+ * tile_edges: most CSR positions per tile (1..4096, default 256).  In-lists no
+ *             longer than a tile are packed whole; longer ones are cut into pieces
+ *             that add the running value of their predecessors by look-back.
+ * tile_held:  reserved, must be 0.  Zero fields take the default. */
 typedef struct {
     int32_t tile_edges;
     int32_t tile_held;
@@ -80,6 +81,8 @@ typedef struct {
     int64_t slots;         /* tiles that publish a running value to a successor */
     int64_t max_in_degree;
     int64_t device_bytes;  /* device memory held by the index */
+    int64_t gathers;       /* edges whose source has an earlier in-edge (rows read per level) */
+    int64_t segments;      /* non-empty in-lists */
 } tpm_graph_stats;
 
 /* Per-call tuning.  chunk: sieve points per pass (power of two, 4..1024; 0 =
@@ -185,6 +188,22 @@ tpm_status tpm_server_submit(tpm_server *s, const tpm_query *q, uint64_t *ticket
  * none is ready yet. */
 tpm_status tpm_server_poll(tpm_server *s, tpm_result *out, int32_t max, int32_t *n_out);
 void tpm_server_destroy(tpm_server *s);
+
+/* ---------------------------------------------------------- diagnostics --- */
+/* When enabled (process-wide), every sieve level kernel is bracketed by HIP events
+ * recorded on the stream it is launched on; tpm_profile_read drains the measured
+ * durations.  kind: 0 = level 2 (reads the per-vertex rows), 1 = a middle level
+ * (3..k-1), 2 = the last level (reduction).  Timing adds no device work. */
+typedef struct {
+    int32_t kind;
+    int32_t level;
+    int32_t chunk_points;  /* sieve points per pass */
+    int32_t pad;
+    double ms;
+} tpm_kernel_time;
+
+tpm_status tpm_profile_enable(int32_t on);
+tpm_status tpm_profile_read(tpm_kernel_time *out, int32_t max, int32_t *n_out);
 
 /* ---------------------------------------------------------------- misc --- */
 /* Description of the last error on the calling thread ("" if none). */

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstring>
 #include <mutex>
 #include <set>
@@ -72,6 +73,49 @@ uint64_t step_seed(uint64_t seed, int64_t s, int64_t r) {
 }
 
 }  // namespace
+
+// ------------------------------------------------------------------ profiling
+namespace {
+std::atomic<int> g_profile{0};
+std::mutex g_prof_mu;
+std::vector<tpm_kernel_time> g_prof_done;
+struct Pending {
+    hipEvent_t a, b;
+    int kind, level, chunk;
+};
+thread_local std::vector<Pending> t_pending;
+}  // namespace
+
+bool profile_on() { return g_profile.load() != 0; }
+
+ProfileScope::ProfileScope(hipStream_t st, int kind_, int level_, int chunk_)
+    : s(st), kind(kind_), level(level_), chunk(chunk_) {
+    if (!profile_on()) return;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+        a = b = nullptr;
+        return;
+    }
+    (void)hipEventRecord(a, s);
+}
+
+ProfileScope::~ProfileScope() {
+    if (!a) return;
+    (void)hipEventRecord(b, s);
+    t_pending.push_back({a, b, kind, level, chunk});
+}
+
+void profile_collect() {
+    if (t_pending.empty()) return;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    for (auto &p : t_pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess)
+            g_prof_done.push_back({p.kind, p.level, p.chunk, 0, (double)ms});
+        (void)hipEventDestroy(p.a);
+        (void)hipEventDestroy(p.b);
+    }
+    t_pending.clear();
+}
 
 void set_error(const std::string &msg) { t_last_error = msg; }
 void clear_error() { t_last_error.clear(); }
@@ -195,6 +239,23 @@ const char *tpm_last_error(void) { return t_last_error.c_str(); }
 
 const char *tpm_version(void) { return "tpm 0.1 (gfx950)"; }
 
+tpm_status tpm_profile_enable(int32_t on) {
+    g_profile.store(on ? 1 : 0);
+    return TPM_OK;
+}
+
+tpm_status tpm_profile_read(tpm_kernel_time *out, int32_t max, int32_t *n_out) {
+    return guarded([&]() -> tpm_status {
+        TPM_REQUIRE(n_out && (max == 0 || out), "NULL argument");
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        int32_t n = std::min<int32_t>(max, (int32_t)g_prof_done.size());
+        for (int32_t i = 0; i < n; ++i) out[i] = g_prof_done[i];
+        g_prof_done.erase(g_prof_done.begin(), g_prof_done.begin() + n);
+        *n_out = n;
+        return TPM_OK;
+    });
+}
+
 tpm_status tpm_graph_create_ex(int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
                                const int32_t *tau, const int32_t *color, int32_t num_colors,
                                uint32_t flags, const tpm_graph_options *opt, tpm_graph **out) {
@@ -243,6 +304,8 @@ tpm_status tpm_graph_stats_get(const tpm_graph *g, tpm_graph_stats *out) {
         out->slots = G.nslots;
         out->max_in_degree = G.max_in_degree;
         out->device_bytes = G.device_bytes;
+        out->gathers = G.gathers;
+        out->segments = G.segments;
         return TPM_OK;
     });
 }

@@ -10,10 +10,9 @@
 // stored by the sieve kernels; rows are numbered in CSR order.
 //
 // Work tiles: consecutive CSR positions (<= tile_edges).  Whole in-lists are packed
-// into tiles; an in-list longer than a tile is cut into pieces, and every piece after
-// the first additionally holds at most tile_held rows, because those rows wait in
-// registers for the running value (carry) of the earlier pieces.  Pieces of one
-// in-list publish their running values to consecutive "slots" for the look-back.
+// into tiles; an in-list longer than a tile is cut into pieces of tile_edges
+// positions.  Pieces of one in-list publish their running values to consecutive
+// "slots" for the look-back.
 
 #include <hip/hip_runtime.h>
 
@@ -124,9 +123,8 @@ int bits_for(uint64_t v) {  // bits needed to represent values 0..v
 }
 
 // Host-side tile builder (see the file comment).
-void build_tiles(const std::vector<int32_t> &inptr, const std::vector<uint8_t> &needed,
-                 int32_t T, int32_t H, std::vector<int32_t> &p0, std::vector<int32_t> &pub,
-                 std::vector<int32_t> &lb, int64_t &nslots) {
+void build_tiles(const std::vector<int32_t> &inptr, int32_t T, std::vector<int32_t> &p0,
+                 std::vector<int32_t> &pub, std::vector<int32_t> &lb, int64_t &nslots) {
     const int32_t n = (int32_t)inptr.size() - 1;
     p0.clear();
     pub.clear();
@@ -152,24 +150,16 @@ void build_tiles(const std::vector<int32_t> &inptr, const std::vector<uint8_t> &
             continue;
         }
         close_pack();
-        // first piece: starts at the in-list head, publishes its running value
+        // first piece: starts at the in-list head and publishes its running value;
+        // every later piece looks back, and all but the last publish as well
         int32_t prev_slot = (int32_t)nslots++;
         p0.push_back(a);
         pub.push_back(prev_slot);
         lb.push_back(-1);
-        int32_t q = a + T;
-        while (q < b) {
-            int32_t start = q, cnt = 0;
-            while (q < b && q - start < T) {
-                if (needed[q]) {
-                    if (cnt == H) break;
-                    ++cnt;
-                }
-                ++q;
-            }
-            bool last = (q >= b);
+        for (int32_t q = a + T; q < b; q += T) {
+            bool last = (q + T >= b);
             int32_t slot = last ? -1 : (int32_t)nslots++;
-            p0.push_back(start);
+            p0.push_back(q);
             pub.push_back(slot);
             lb.push_back(prev_slot);
             prev_slot = slot;
@@ -182,8 +172,8 @@ void build_tiles(const std::vector<int32_t> &inptr, const std::vector<uint8_t> &
 }  // namespace
 
 void free_graph(Graph &G) {
-    int32_t **ptrs[] = {&G.color, &G.pdst, &G.psrc, &G.ptau, &G.peid, &G.gsrc,
-                        &G.orow,  &G.inptr, &G.tile_p0, &G.tile_pub, &G.tile_lb};
+    int32_t **ptrs[] = {&G.color, &G.pdst,  &G.psrc,    &G.ptau,     &G.peid,   &G.gsrc,
+                        &G.orow,  &G.inptr, &G.segnext, &G.tile_p0, &G.tile_pub, &G.tile_lb};
     for (auto pp : ptrs) {
         if (*pp) (void)hipFree(*pp);
         *pp = nullptr;
@@ -200,13 +190,10 @@ void build_graph(Graph &G, int32_t n, int64_t m, const int32_t *src, const int32
     TPM_REQUIRE(num_colors >= 1, "num_colors must be >= 1");
     TPM_REQUIRE(m == 0 || (src && dst && tau), "edge arrays must not be NULL");
     TPM_REQUIRE(color != nullptr, "color must not be NULL");
-    int T = 64, H = 8;
-    if (opt) {
-        if (opt->tile_edges) T = opt->tile_edges;
-        if (opt->tile_held) H = opt->tile_held;
-    }
-    TPM_REQUIRE(T >= 1 && T <= 64, "tile_edges must be in [1, 64]");
-    TPM_REQUIRE(H >= 1 && H <= 8, "tile_held must be in [1, 8]");
+    int T = 256;
+    if (opt && opt->tile_edges) T = opt->tile_edges;
+    TPM_REQUIRE(T >= 1 && T <= 4096, "tile_edges must be in [1, 4096]");
+    TPM_REQUIRE(!opt || opt->tile_held == 0, "tile_held is reserved and must be 0");
     const bool on_dev = (flags & TPM_DEVICE_PTRS) != 0;
     TPM_REQUIRE((flags & ~TPM_DEVICE_PTRS) == 0, "unknown flag bits");
 
@@ -231,7 +218,6 @@ void build_graph(Graph &G, int32_t n, int64_t m, const int32_t *src, const int32
     G.m = m;
     G.q = num_colors;
     G.tile_edges = T;
-    G.tile_held = H;
     int64_t acct = 0;
     hipStream_t st = nullptr;
 
@@ -283,7 +269,6 @@ void build_graph(Graph &G, int32_t n, int64_t m, const int32_t *src, const int32
         G.orow = dalloc<int32_t>(m, acct);
         G.inptr = dalloc<int32_t>((int64_t)n + 1, acct);
 
-        std::vector<uint8_t> h_needed(m);
         if (m) {
             // ---- sort positions by (dst, tau, id): stable radix sort of (dst, tau) keys
             const int tbits = bits_for((uint64_t)tmax);
@@ -328,9 +313,6 @@ void build_graph(Graph &G, int32_t n, int64_t m, const int32_t *src, const int32
             TPM_HIP(hipMemcpy(&last_needed, needed + (m - 1), sizeof(int32_t),
                               hipMemcpyDeviceToHost));
             G.R = (int64_t)last_row + last_needed;
-            std::vector<int32_t> nd(m);
-            TPM_HIP(hipMemcpy(nd.data(), needed, sizeof(int32_t) * m, hipMemcpyDeviceToHost));
-            for (int64_t i = 0; i < m; ++i) h_needed[i] = (uint8_t)nd[i];
         }
         G.h_color.resize((size_t)n);
         TPM_HIP(hipMemcpy(G.h_color.data(), G.color, sizeof(int32_t) * (size_t)n,
@@ -338,11 +320,29 @@ void build_graph(Graph &G, int32_t n, int64_t m, const int32_t *src, const int32
         G.h_inptr.resize((size_t)n + 1);
         TPM_HIP(hipMemcpy(G.h_inptr.data(), G.inptr, sizeof(int32_t) * ((size_t)n + 1),
                           hipMemcpyDeviceToHost));
-        for (int32_t u = 0; u < n; ++u)
-            G.max_in_degree = std::max<int64_t>(G.max_in_degree, G.h_inptr[u + 1] - G.h_inptr[u]);
+        for (int32_t u = 0; u < n; ++u) {
+            int64_t d = G.h_inptr[u + 1] - G.h_inptr[u];
+            G.max_in_degree = std::max<int64_t>(G.max_in_degree, d);
+            G.segments += d > 0;
+        }
+        if (m) {
+            std::vector<int32_t> gs((size_t)m);
+            TPM_HIP(hipMemcpy(gs.data(), G.gsrc, sizeof(int32_t) * m, hipMemcpyDeviceToHost));
+            for (int64_t i = 0; i < m; ++i) G.gathers += gs[i] >= 0;
+        }
 
+        {
+            std::vector<int32_t> sn((size_t)n, -1);
+            int32_t nextv = -1;
+            for (int32_t u = n - 1; u >= 0; --u) {
+                sn[u] = nextv;
+                if (G.h_inptr[u + 1] > G.h_inptr[u]) nextv = u;
+            }
+            G.segnext = dalloc<int32_t>(n, acct);
+            TPM_HIP(hipMemcpy(G.segnext, sn.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice));
+        }
         std::vector<int32_t> tp0, tpub, tlb;
-        build_tiles(G.h_inptr, h_needed, T, H, tp0, tpub, tlb, G.nslots);
+        build_tiles(G.h_inptr, T, tp0, tpub, tlb, G.nslots);
         G.ntiles = (int64_t)tpub.size();
         G.h_tile_p0 = tp0;
         G.tile_p0 = dalloc<int32_t>(G.ntiles + 1, acct);
@@ -358,11 +358,16 @@ void build_graph(Graph &G, int32_t n, int64_t m, const int32_t *src, const int32
         }
 
         // ---- LDS table image (see kLdsBytes)
-        std::vector<uint8_t> img(kLdsBytes);
-        for (int v = 0; v < 256; ++v) img[v] = kGf.log[v];
-        for (int r = 1; r < 512; ++r)
-            for (int gl = 0; gl < 256; ++gl)
-                img[(size_t)r * 256 + gl] = (gl == 255) ? 0 : kGf.exp[(r - 1 + gl) % 255];
+        std::vector<uint8_t> img(kLdsBytes, 0);
+        auto put32 = [&](size_t off, uint32_t v) { std::memcpy(img.data() + off, &v, 4); };
+        for (int v = 0; v < 256; ++v) {
+            uint32_t l7 = v ? ((uint32_t)kGf.log[v] << 7) : kZero7;
+            for (int c = 0; c < 32; ++c) put32((size_t)v * 256 + c * 4, l7);
+        }
+        for (int s = 0; s < kExpRows; ++s) {
+            uint32_t e = (s <= 762) ? kGf.exp[s % 255] : 0u;
+            for (int c = 0; c < 32; ++c) put32((size_t)kExpBase + (size_t)s * 128 + c * 4, e);
+        }
         G.lds_image = (uint8_t *)dalloc<uint8_t>(kLdsBytes, acct);
         TPM_HIP(hipMemcpy(G.lds_image, img.data(), kLdsBytes, hipMemcpyHostToDevice));
         TPM_HIP(hipDeviceSynchronize());

@@ -59,13 +59,21 @@ constexpr GfTables make_gf_tables() {
 
 inline constexpr GfTables kGf = make_gf_tables();
 
-// Layout of the per-workgroup LDS table used by the sieve kernels (bytes):
-//   [0, 256)          LOG8[v]   = log(v), 255 for v = 0
-//   [256*r + g]       r in [1, 512), g in [0, 256):
-//                     = 0 if g == 255 (log of zero), else alpha^((r - 1 + g) mod 255)
-// so that the product of field elements with logs a (in [0, 508]) and g is the byte
-// at address ((a + 1) << 8) | g.
-constexpr int kLdsBytes = 512 * 256;
+// Per-workgroup LDS tables of the sieve kernels.  gfx950's LDS serves 32 dword banks,
+// so every entry is stored 32 times, once per bank, and lane L reads the copy in
+// bank L mod 32: lookups never conflict whatever the looked-up values are.
+//   LOG region, [0, 65536): row g (256 bytes) holds, in its first 128 bytes, 32
+//     copies of the dword LOG7[g] = log(g) << 7 (kZero7 for g = 0); the second
+//     half of each row is unused.
+//   EXP region, [kExpBase, kExpBase + kExpRows * 128): row s holds 32 copies of the
+//     dword alpha^(s mod 255) for s <= 762 and 0 for s = 763 (the clamp row).
+// The product x * y * g of three field elements is then the low byte of EXP row
+// min(log x + log y + log g, 763): one LOG read of g, one EXP read.
+constexpr int kExpBase = 65536;
+constexpr int kExpRows = 764;
+constexpr int kClampRow = 763;
+constexpr uint32_t kZero7 = 0x00100000u;  // LOG7 of zero: pushes any sum past the clamp
+constexpr int kLdsBytes = kExpBase + kExpRows * 128;  // 163328 <= 160 KiB
 
 // ------------------------------------------------------------------ graph
 struct Graph {
@@ -74,12 +82,13 @@ struct Graph {
     int64_t m = 0;
     int32_t q = 0;
     int32_t tmax = 0;
-    int32_t tile_edges = 64;
-    int32_t tile_held = 8;
+    int32_t tile_edges = 256;
     int64_t R = 0;        // stored rows per level
     int64_t ntiles = 0;
     int64_t nslots = 0;
     int64_t max_in_degree = 0;
+    int64_t gathers = 0;
+    int64_t segments = 0;
     int64_t device_bytes = 0;
     int num_cu = 0;
 
@@ -93,6 +102,7 @@ struct Graph {
                                //     earlier than tau), -1 if none
     int32_t *orow = nullptr;   // [m] state row written at this position, -1 if none
     int32_t *inptr = nullptr;  // [n+1]
+    int32_t *segnext = nullptr;  // [n] next vertex (in CSR order) with in-edges, -1 if none
     int32_t *tile_p0 = nullptr;   // [ntiles+1]
     int32_t *tile_pub = nullptr;  // [ntiles] slot this tile publishes to, -1 if none
     int32_t *tile_lb = nullptr;   // [ntiles] slot its look-back starts at, -1 if none
@@ -136,6 +146,19 @@ void run_sieve(const Graph &G, const SieveRequest &req, SieveResult &res, hipStr
 // Per-edge localisation over all edges, indexed by input edge id.
 void run_sieve_loc_all(const Graph &G, const SieveRequest &req, SieveResult &res,
                        uint8_t *loc_by_edge, hipStream_t stream);
+
+// ------------------------------------------------------------------ profiling
+bool profile_on();
+// brackets a level kernel launch with events when profiling is enabled
+struct ProfileScope {
+    hipEvent_t a = nullptr, b = nullptr;
+    hipStream_t s = nullptr;
+    int kind = 0, level = 0, chunk = 0;
+    ProfileScope(hipStream_t st, int kind, int level, int chunk);
+    ~ProfileScope();
+};
+// resolves the pending events of this thread (call after the stream is synchronised)
+void profile_collect();
 
 }  // namespace tpm
 

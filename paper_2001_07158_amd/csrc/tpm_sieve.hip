@@ -14,17 +14,20 @@
 // the C-byte row of the predecessor value, multiply by x_u*y_e per point, and keep a
 // per-lane running XOR (the segmented prefix over the in-list).
 //
-// Number format.  Stored rows and the per-vertex values x_u hold discrete logs
-// (base alpha = 0x02; 255 encodes zero), so a product costs one table read: the byte
-// at LDS address ((log x_u + log y_e + 1) << 8 | log g) is x_u * y_e * g.  The
-// running XOR is linear; a row is converted back to logs when stored.
+// Arithmetic.  Rows hold field elements (bytes).  The product x_u * y_e * g costs two
+// LDS reads from bank-replicated tables: LOG7[g] (= log g << 7), then the EXP row
+// min(log g + log x_u + log y_e, 763), where row 763 is zero and log 0 is so large
+// that a zero factor always lands there.  log x_u is read once per in-list and
+// log y_e once per edge, so a point costs one perm, one add3, one min and two
+// conflict-free table reads.
 //
 // Long in-lists span several tiles.  Each tile of such a list publishes its running
 // value as 64-bit words (epoch, status, value) — first AGGREGATE (this tile only),
 // then INCLUSIVE (from the list head) — and later tiles add the values of earlier
 // ones by walking back until an INCLUSIVE word (decoupled look-back, Merrill and
 // Garland 2016).  Tiles are claimed from an atomic ticket, so a tile only ever waits
-// for tiles claimed before it.
+// for tiles claimed before it.  A continuation tile stores its rows without the
+// carry, then adds the carry to them once the look-back has produced it.
 
 #include <hip/hip_runtime.h>
 
@@ -39,9 +42,7 @@ namespace {
 
 __constant__ GfTables c_gf = make_gf_tables();
 
-constexpr uint32_t kSkip = 0xFFFFu;  // y = 0: the edge adds nothing at this level
-constexpr int kU = 8;                // edges whose gathers are in flight together
-constexpr int kHeldMax = 8;          // rows a continuation tile keeps for its carry
+constexpr int kU = 8;                // edges per batch; two batches of gathers in flight
 constexpr uint32_t kAgg = 1, kInc = 2;
 constexpr uint32_t kSpinLimit = 1u << 24;
 
@@ -64,9 +65,10 @@ struct LevelParams {
     const uint8_t *gbase;  // gathered rows (log domain), rowb bytes each
     const int32_t *pdst;
     const int32_t *peid;
+    const int32_t *segnext;  // per vertex: the next vertex with in-edges (-1: none)
     const int32_t *orow;   // row stored at each position (-1: none)
     uint8_t *sout;         // stored rows
-    const uint8_t *lxt;    // per-vertex rows of log x_u^A
+    const uint8_t *xt;     // per-vertex rows of x_u^A (bytes)
     const int32_t *tile_p0;
     const int32_t *tile_pub;
     const int32_t *tile_lb;
@@ -99,29 +101,27 @@ __device__ __forceinline__ uint32_t gmul(uint32_t a, uint32_t b) {
     return (a && b) ? c_gf.exp[c_gf.log[a] + c_gf.log[b]] : 0u;
 }
 
-// 4 packed log-domain bytes g times per-point logs (two 16-bit values per word,
-// each already offset by +1): returns the 4 linear products.
-__device__ __forceinline__ uint32_t mul4(const uint8_t *lds, uint32_t g, uint32_t la01,
-                                         uint32_t la23) {
-    uint32_t a0 = __builtin_amdgcn_perm(la01, g, 0x0C050400u);
-    uint32_t a1 = __builtin_amdgcn_perm(la01, g, 0x0C070601u);
-    uint32_t a2 = __builtin_amdgcn_perm(la23, g, 0x0C050402u);
-    uint32_t a3 = __builtin_amdgcn_perm(la23, g, 0x0C070603u);
-    return (uint32_t)lds[a0] | ((uint32_t)lds[a1] << 8) | ((uint32_t)lds[a2] << 16) |
-           ((uint32_t)lds[a3] << 24);
+// LDS address of the LOG7 entry of byte i of g, in this lane's bank column:
+// (g_i << 8) | lanebits (lanebits = (lane & 31) << 2).
+template <int I>
+__device__ __forceinline__ uint32_t log_addr(uint32_t lanebits, uint32_t g) {
+    return __builtin_amdgcn_perm(lanebits, g, 0x0C0C0004u | ((uint32_t)I << 8));
 }
 
-// linear bytes -> log bytes
-__device__ __forceinline__ uint32_t tolog4(const uint8_t *lds, uint32_t v) {
-    return (uint32_t)lds[v & 0xFFu] | ((uint32_t)lds[(v >> 8) & 0xFFu] << 8) |
-           ((uint32_t)lds[(v >> 16) & 0xFFu] << 16) | ((uint32_t)lds[v >> 24] << 24);
+__device__ __forceinline__ uint32_t lds32(const uint8_t *lds, uint32_t addr) {
+    return *(const uint32_t *)(lds + addr);
 }
 
-// 0xFF in every byte of w that is not 0xFF (log of a nonzero value)
-__device__ __forceinline__ uint32_t nonzero_mask(uint32_t w) {
-    uint32_t t = ~w;
-    uint32_t y = (((t & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | t) & 0x80808080u;
-    return (y >> 7) * 0xFFu;
+// x*y*g for the 4 points of dword g: lx7[i] = LOG7[x_i] + kExpBase + lanebits,
+// ly7 = LOG7[y] (uniform), zc = clamp address of this lane.
+__device__ __forceinline__ uint32_t mul4(const uint8_t *lds, uint32_t lanebits, uint32_t g,
+                                         const uint32_t *lx7, uint32_t ly7, uint32_t zc) {
+    uint32_t s0 = min(lds32(lds, log_addr<0>(lanebits, g)) + lx7[0] + ly7, zc);
+    uint32_t s1 = min(lds32(lds, log_addr<1>(lanebits, g)) + lx7[1] + ly7, zc);
+    uint32_t s2 = min(lds32(lds, log_addr<2>(lanebits, g)) + lx7[2] + ly7, zc);
+    uint32_t s3 = min(lds32(lds, log_addr<3>(lanebits, g)) + lx7[3] + ly7, zc);
+    return (uint32_t)lds[s0] | ((uint32_t)lds[s1] << 8) | ((uint32_t)lds[s2] << 16) |
+           ((uint32_t)lds[s3] << 24);
 }
 
 template <int W>
@@ -152,25 +152,28 @@ __device__ __forceinline__ void store_row(uint8_t *base, int64_t row, int rowb, 
     }
 }
 
+// Published words: slot s, dword w of the row, lane L at index s*rowd + w*lanes + L, so
+// that one store instruction of a wave covers consecutive words.
 template <int W>
-__device__ __forceinline__ void publish(unsigned long long *pub, int32_t slot, int rowd, int lane,
-                                        uint32_t status, uint32_t epoch, const uint32_t (&v)[W]) {
+__device__ __forceinline__ void publish(unsigned long long *pub, int32_t slot, int rowd, int lanes,
+                                        int lane, uint32_t status, uint32_t epoch,
+                                        const uint32_t (&v)[W]) {
     const unsigned long long hi = (unsigned long long)((epoch << 2) | status) << 32;
-    unsigned long long *p = pub + (int64_t)slot * rowd + (int64_t)lane * W;
+    unsigned long long *p = pub + (int64_t)slot * rowd + lane;
 #pragma unroll
     for (int w = 0; w < W; ++w)
-        __hip_atomic_store(p + w, hi | v[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(p + w * lanes, hi | v[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 template <int W>
-__device__ __forceinline__ void lookback(unsigned long long *pub, int32_t slot, int rowd, int lane,
-                                         uint32_t epoch, Ctl *ctl, uint32_t (&carry)[W]) {
+__device__ __forceinline__ void lookback(unsigned long long *pub, int32_t slot, int rowd, int lanes,
+                                         int lane, uint32_t epoch, Ctl *ctl, uint32_t (&carry)[W]) {
 #pragma unroll
     for (int w = 0; w < W; ++w) {
         uint32_t c = 0;
         int32_t s = slot;
         for (;;) {
-            unsigned long long *p = pub + (int64_t)s * rowd + (int64_t)lane * W + w;
+            unsigned long long *p = pub + (int64_t)s * rowd + w * lanes + lane;
             unsigned long long v;
             uint32_t spins = 0;
             bool ok = true;
@@ -198,6 +201,22 @@ __device__ __forceinline__ void lookback(unsigned long long *pub, int32_t slot, 
     }
 }
 
+template <int W>
+__device__ __forceinline__ void gather_batch(const LevelParams &P, int32_t pb, int32_t p1, bool act,
+                                             int lane, uint32_t (&g)[kU][W]) {
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+        const int32_t q = pb + u;
+        const int32_t r = (q < p1) ? P.gidx[q] : -1;
+        if (r >= 0 && act) {
+            load_row<W>(P.gbase, r, P.rowb, lane, g[u]);
+        } else {
+#pragma unroll
+            for (int w = 0; w < W; ++w) g[u][w] = 0;
+        }
+    }
+}
+
 template <int W, bool FIN>
 __global__ void __launch_bounds__(1024) k_level(LevelParams P) {
     __shared__ __attribute__((aligned(16))) uint8_t lds[kLdsBytes];
@@ -211,18 +230,29 @@ __global__ void __launch_bounds__(1024) k_level(LevelParams P) {
     const int lane = threadIdx.x & 63;
     const bool act = lane < P.lanes;
     const int rowd = P.rowb >> 2;
+    const uint32_t lanebits = (uint32_t)(lane & 31) << 2;
+    const uint32_t xbase = (uint32_t)kExpBase + lanebits;
+    const uint32_t zc = (uint32_t)kExpBase + ((uint32_t)kClampRow << 7) + lanebits;
     const uint32_t epoch = __hip_atomic_load(&P.ctl->epoch, __ATOMIC_RELAXED,
                                              __HIP_MEMORY_SCOPE_AGENT) & 0x3FFFFFFFu;
     uint32_t fin[W];
 #pragma unroll
     for (int w = 0; w < W; ++w) fin[w] = 0;
 
+    // Tiles are claimed in ticket order.  The last level claims the next tile while
+    // working on the current one (it has no look-back).  The scan levels claim a tile
+    // only when they start it: a tile claimed early but not started would hold up the
+    // look-back of every later piece of its in-list.
+    uint32_t tk = 0;
+    if (lane == 0) tk = atomicAdd(&P.ctl->ticket, 1u);
+    tk = __builtin_amdgcn_readfirstlane(__shfl(tk, 0));
     for (;;) {
-        uint32_t t = 0;
-        if (lane == 0) t = atomicAdd(&P.ctl->ticket, 1u);
-        t = __builtin_amdgcn_readfirstlane(__shfl(t, 0));
-        const int32_t tile = P.tile_lo + (int32_t)t;
+        const int32_t tile = P.tile_lo + (int32_t)tk;
         if (tile >= P.tile_hi) break;
+        uint32_t tk_next = 0;
+        if constexpr (FIN) {
+            if (lane == 0) tk_next = atomicAdd(&P.ctl->ticket, 1u);
+        }
 
         const int32_t p0 = P.tile_p0[tile], p1 = P.tile_p0[tile + 1];
         int32_t pubslot = -1, lbslot = -1;
@@ -232,64 +262,58 @@ __global__ void __launch_bounds__(1024) k_level(LevelParams P) {
         }
         const bool cont = lbslot >= 0;
 
-        // log y_{e, ylevel} of the tile's positions: lane i <-> position p0 + i
-        uint32_t ly_vec = kSkip;
-        if (p0 + lane < p1) {
-            uint32_t y = fp8(P.seed, 1u, P.ylevel, (uint32_t)P.peid[p0 + lane]);
-            ly_vec = y ? (uint32_t)lds[y] : kSkip;
+        // x row of the in-list being processed (as LOG7 + base, per point) and the raw
+        // x row of the next in-list, loaded ahead
+        int32_t cur_dst = -1, nxt_dst = P.pdst[p0];
+        uint32_t lx7[4 * W], acc[W], xn[W];
+        if (act) {
+            load_row<W>(P.xt, nxt_dst, P.rowb, lane, xn);
+        } else {
+#pragma unroll
+            for (int w = 0; w < W; ++w) xn[w] = 0;
         }
+#pragma unroll
+        for (int w = 0; w < W; ++w) acc[w] = 0;
+#pragma unroll
+        for (int i = 0; i < 4 * W; ++i) lx7[i] = kZero7;
+        uint32_t ly_vec = kZero7;
 
-        int32_t cur_dst = -1;
-        uint32_t lx01[W], lx23[W], xm[W], acc[W];
-        uint32_t held[kHeldMax][W];
-        int32_t held_row[kHeldMax];
-        int nheld = 0;
-#pragma unroll
-        for (int w = 0; w < W; ++w) lx01[w] = lx23[w] = xm[w] = acc[w] = 0;
-
-        for (int32_t pb = p0; pb < p1; pb += kU) {
-            const int nb = min(kU, p1 - pb);
-            uint32_t g[kU][W];
-#pragma unroll
-            for (int u = 0; u < kU; ++u) {
-                const int32_t r = (u < nb) ? P.gidx[pb + u] : -1;
-                if (r >= 0 && act) {
-                    load_row<W>(P.gbase, r, P.rowb, lane, g[u]);
-                } else {
-#pragma unroll
-                    for (int w = 0; w < W; ++w) g[u][w] = 0xFFFFFFFFu;
+        auto process = [&](const uint32_t (&g)[kU][W], int32_t pb) {
+            if (((pb - p0) & 63) == 0) {
+                // LOG7 of y_{e, ylevel} for the next 64 positions: lane i <-> pb + i
+                ly_vec = kZero7;
+                if (pb + lane < p1) {
+                    uint32_t y = fp8(P.seed, 1u, P.ylevel, (uint32_t)P.peid[pb + lane]);
+                    ly_vec = lds32(lds, (y << 8) | lanebits);
                 }
             }
+            const int nb = min(kU, p1 - pb);
 #pragma unroll
             for (int u = 0; u < kU; ++u) {
                 if (u >= nb) break;
                 const int32_t p = pb + u;
                 const int32_t d = P.pdst[p];
-                if (d != cur_dst) {  // new in-list (or the start of a continuation tile)
-                    cur_dst = d;
-                    uint32_t lw[W];
-                    if (act) {
-                        load_row<W>(P.lxt, d, P.rowb, lane, lw);
-                    } else {
-#pragma unroll
-                        for (int w = 0; w < W; ++w) lw[w] = 0xFFFFFFFFu;
-                    }
+                if (d != cur_dst) {  // a new in-list (or the start of a continuation tile)
+                    if (d != nxt_dst && act) load_row<W>(P.xt, d, P.rowb, lane, xn);
 #pragma unroll
                     for (int w = 0; w < W; ++w) {
-                        lx01[w] = __builtin_amdgcn_perm(0u, lw[w], 0x0C010C00u) + 0x00010001u;
-                        lx23[w] = __builtin_amdgcn_perm(0u, lw[w], 0x0C030C02u) + 0x00010001u;
-                        xm[w] = nonzero_mask(lw[w]);
+                        lx7[4 * w + 0] = lds32(lds, log_addr<0>(lanebits, xn[w])) + xbase;
+                        lx7[4 * w + 1] = lds32(lds, log_addr<1>(lanebits, xn[w])) + xbase;
+                        lx7[4 * w + 2] = lds32(lds, log_addr<2>(lanebits, xn[w])) + xbase;
+                        lx7[4 * w + 3] = lds32(lds, log_addr<3>(lanebits, xn[w])) + xbase;
                         acc[w] = 0;
                     }
+                    cur_dst = d;
+                    nxt_dst = P.segnext[d];
+                    if (nxt_dst >= 0 && act) load_row<W>(P.xt, nxt_dst, P.rowb, lane, xn);
                 }
-                const uint32_t ly = __builtin_amdgcn_readlane(ly_vec, p - p0);
+                const uint32_t ly7 = __builtin_amdgcn_readlane(ly_vec, (p - p0) & 63);
                 uint32_t c[W];
-                if (ly != kSkip) {
-                    const uint32_t lyy = ly * 0x00010001u;
+                if (ly7 < kZero7) {
 #pragma unroll
                     for (int w = 0; w < W; ++w)
-                        c[w] = mul4(lds, g[u][w], lx01[w] + lyy, lx23[w] + lyy) & xm[w];
-                } else {
+                        c[w] = mul4(lds, lanebits, g[u][w], &lx7[4 * w], ly7, zc);
+                } else {  // y = 0: the edge adds nothing at this level
 #pragma unroll
                     for (int w = 0; w < W; ++w) c[w] = 0;
                 }
@@ -313,53 +337,57 @@ __global__ void __launch_bounds__(1024) k_level(LevelParams P) {
 #pragma unroll
                     for (int w = 0; w < W; ++w) acc[w] ^= c[w];
                     const int32_t orow = P.orow[p];
-                    if (orow >= 0) {
-                        if (cont) {
-#pragma unroll
-                            for (int h = 0; h < kHeldMax; ++h) {
-                                if (h == nheld) {
-#pragma unroll
-                                    for (int w = 0; w < W; ++w) held[h][w] = acc[w];
-                                    held_row[h] = orow;
-                                }
-                            }
-                            ++nheld;
-                        } else if (act) {
-                            uint32_t o[W];
-#pragma unroll
-                            for (int w = 0; w < W; ++w) o[w] = tolog4(lds, acc[w]);
-                            store_row<W>(P.sout, orow, P.rowb, lane, o);
-                        }
-                    }
+                    if (orow >= 0 && act) store_row<W>(P.sout, orow, P.rowb, lane, acc);
                 }
             }
+        };
+
+        // two batches of gathers in flight: while one is multiplied, the next loads
+        uint32_t ga[kU][W], gb[kU][W];
+        gather_batch<W>(P, p0, p1, act, lane, ga);
+        for (int32_t pb = p0; pb < p1;) {
+            gather_batch<W>(P, pb + kU, p1, act, lane, gb);
+            process(ga, pb);
+            pb += kU;
+            if (pb >= p1) break;
+            gather_batch<W>(P, pb + kU, p1, act, lane, ga);
+            process(gb, pb);
+            pb += kU;
         }
 
         if constexpr (!FIN) {
             if (act) {
                 if (pubslot >= 0)
-                    publish<W>(P.pub, pubslot, rowd, lane, cont ? kAgg : kInc, epoch, acc);
+                    publish<W>(P.pub, pubslot, rowd, P.lanes, lane, cont ? kAgg : kInc, epoch, acc);
                 if (cont) {
                     uint32_t carry[W];
-                    lookback<W>(P.pub, lbslot, rowd, lane, epoch, P.ctl, carry);
-#pragma unroll
-                    for (int h = 0; h < kHeldMax; ++h) {
-                        if (h < nheld) {
-                            uint32_t o[W];
-#pragma unroll
-                            for (int w = 0; w < W; ++w) o[w] = tolog4(lds, held[h][w] ^ carry[w]);
-                            store_row<W>(P.sout, held_row[h], P.rowb, lane, o);
-                        }
-                    }
+                    lookback<W>(P.pub, lbslot, rowd, P.lanes, lane, epoch, P.ctl, carry);
                     if (pubslot >= 0) {
                         uint32_t inc[W];
 #pragma unroll
                         for (int w = 0; w < W; ++w) inc[w] = acc[w] ^ carry[w];
-                        publish<W>(P.pub, pubslot, rowd, lane, kInc, epoch, inc);
+                        publish<W>(P.pub, pubslot, rowd, P.lanes, lane, kInc, epoch, inc);
+                    }
+                    // rows of a continuation tile were stored without the carry of the
+                    // earlier pieces: add it now (this wave's own stores are complete)
+                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+                    for (int32_t p = p0; p < p1; ++p) {
+                        const int32_t orow = P.orow[p];
+                        if (orow >= 0) {
+                            uint32_t v[W];
+                            load_row<W>(P.sout, orow, P.rowb, lane, v);
+#pragma unroll
+                            for (int w = 0; w < W; ++w) v[w] ^= carry[w];
+                            store_row<W>(P.sout, orow, P.rowb, lane, v);
+                        }
                     }
                 }
             }
         }
+        if constexpr (!FIN) {
+            if (lane == 0) tk_next = atomicAdd(&P.ctl->ticket, 1u);
+        }
+        tk = __builtin_amdgcn_readfirstlane(__shfl(tk_next, 0));
     }
 
     if constexpr (FIN) {
@@ -376,8 +404,8 @@ __global__ void k_prep(Ctl *ctl, int bump_epoch) {
     if (bump_epoch) ctl->epoch = (ctl->epoch + 1u) & 0x3FFFFFFFu;
 }
 
-// z[u*k + j] = sum over slots d of colour c(u) of v_{u,d} * w_{d,j} (Eq. (motif));
-// zero for a deleted vertex or a colour outside the multiset.
+// z[u][j] = sum over slots d of colour c(u) of v_{u,d} * w_{d,j} (Eq. (motif)), rows
+// padded to 16 bytes; zero for a deleted vertex or a colour outside the multiset.
 __global__ void k_z(int32_t n, int32_t k, const int32_t *color, QuerySlots qs, const uint8_t *mask,
                     uint64_t seed, uint8_t *z) {
     int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -390,40 +418,58 @@ __global__ void k_z(int32_t n, int32_t k, const int32_t *color, QuerySlots qs, c
             mu = qs.mu[i];
         }
     const bool live = (mask == nullptr || mask[u] != 0) && mu > 0;
+    uint32_t out[4] = {0, 0, 0, 0};
     for (int j = 0; j < k; ++j) {
         uint32_t acc = 0;
         if (live)
             for (int d = off; d < off + mu; ++d)
                 acc ^= gmul(fp8(seed, 2u, (uint32_t)d, (uint32_t)u), fp8(seed, 3u, (uint32_t)d, (uint32_t)j));
-        z[u * k + j] = (uint8_t)acc;
+        out[j >> 2] |= acc << (8 * (j & 3));
     }
+    ((uint4 *)z)[u] = make_uint4(out[0], out[1], out[2], out[3]);
 }
 
-// Row of log x_u^A for the chunk's points A = base + b, x_u^A = sum_{j in A} z_{u,j}.
-__global__ void k_lxt(int32_t n, int32_t k, int32_t rowb, uint32_t base, const uint8_t *z,
-                      uint8_t *lxt) {
-    const int32_t rowd = rowb >> 2;
+// Row of x_u^A = sum_{j in A} z_{u,j} for the chunk's points A = base + b.  A thread
+// writes 16 points: x^A = x^(A with its low 4 bits cleared) + x^(A's low 4 bits).
+__global__ void k_xt(int32_t n, int32_t k, int32_t rowb, uint32_t base, const uint8_t *z,
+                     uint8_t *xt) {
+    const int32_t per_row = (rowb + 15) >> 4;  // threads per vertex row
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (int64_t)n * rowd) return;
-    int64_t u = i / rowd;
-    int32_t dw = (int32_t)(i - u * rowd);
-    uint8_t zz[16];
-    for (int j = 0; j < k; ++j) zz[j] = z[u * k + j];
-    uint32_t out = 0;
-    for (int b = 0; b < 4; ++b) {
-        uint32_t A = base + (uint32_t)(dw * 4 + b);
-        uint32_t x = 0;
-        for (int j = 0; j < k; ++j)
-            if ((A >> j) & 1u) x ^= zz[j];
-        out |= (uint32_t)c_gf.log[x] << (8 * b);
+    if (i >= (int64_t)n * per_row) return;
+    int64_t u = i / per_row;
+    int32_t part = (int32_t)(i - u * per_row);
+    const uint4 zz4 = ((const uint4 *)z)[u];
+    const uint32_t zw[4] = {zz4.x, zz4.y, zz4.z, zz4.w};
+    auto zj = [&](int j) -> uint32_t { return (zw[j >> 2] >> (8 * (j & 3))) & 0xFFu; };
+    const uint32_t A0 = base + (uint32_t)part * 16u;
+    uint32_t hi = 0;
+    for (int j = 4; j < k; ++j)
+        if ((A0 >> j) & 1u) hi ^= zj(j);
+    uint32_t lo[16];
+    lo[0] = 0;
+    for (int b = 1; b < 16; ++b) {
+        int j = __builtin_ctz(b);
+        lo[b] = lo[b & (b - 1)] ^ (j < k ? zj(j) : 0u);
     }
-    ((uint32_t *)lxt)[i] = out;
+    const int npts = min(16, rowb - part * 16);
+    uint32_t out[4] = {0, 0, 0, 0};
+    for (int b = 0; b < npts; ++b) {
+        uint32_t A = A0 + (uint32_t)b;
+        uint32_t x = ((A >> 4) == (A0 >> 4)) ? (hi ^ lo[A & 15u]) : 0u;
+        out[b >> 2] |= x << (8 * (b & 3));
+    }
+    uint8_t *row = xt + u * (int64_t)rowb + (int64_t)part * 16;
+    if (npts == 16) {
+        *(uint4 *)row = make_uint4(out[0], out[1], out[2], out[3]);
+    } else {
+        for (int b = 0; b < npts; b += 4) *(uint32_t *)(row + b) = out[b >> 2];
+    }
 }
 
 // k = 1: P(A) = sum_u x_u^A, A in {0, 1}; x^0 = 0, x^1 = z_{u,0}.
 __global__ void k_single(int32_t n, const uint8_t *z, uint32_t *out) {
     int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    uint32_t v = (u < n) ? ((uint32_t)z[u] << 8) : 0u;
+    uint32_t v = (u < n) ? ((uint32_t)z[u * 16] << 8) : 0u;
     for (int off = 32; off >= 1; off >>= 1) v ^= __shfl_xor(v, off);
     if ((threadIdx.x & 63) == 0 && v) atomicXor(out, v);
 }
@@ -538,10 +584,10 @@ void run_sieve_impl(const Graph &G, const SieveRequest &req, SieveResult &res, b
     const int rowd = rowb / 4;
     const int64_t ppbytes = std::max<int64_t>(npts, 4);
 
-    DevBuf ctl, z, lxt, s0, s1, pub, pp, tot, mask, loc;
+    DevBuf ctl, z, xt, s0, s1, pub, pp, tot, mask, loc;
     ctl.alloc(sizeof(Ctl), st);
     TPM_HIP(hipMemsetAsync(ctl.p, 0, sizeof(Ctl), st));
-    z.alloc((size_t)G.n * k, st);
+    z.alloc((size_t)G.n * 16, st);
     pp.alloc((size_t)ppbytes, st);
     TPM_HIP(hipMemsetAsync(pp.p, 0, (size_t)ppbytes, st));
     tot.alloc(4, st);
@@ -569,7 +615,7 @@ void run_sieve_impl(const Graph &G, const SieveRequest &req, SieveResult &res, b
     if (k == 1) {
         k_single<<<grid_for(G.n), 256, 0, st>>>(G.n, z.as<uint8_t>(), pp.as<uint32_t>());
     } else if (G.m > 0) {
-        lxt.alloc((size_t)G.n * rowb, st);
+        xt.alloc((size_t)G.n * rowb, st);
         s0.alloc((size_t)std::max<int64_t>(1, G.R) * rowb, st);
         if (k > 2) s1.alloc((size_t)std::max<int64_t>(1, G.R) * rowb, st);
         if (k > 2 && G.nslots) {
@@ -588,18 +634,19 @@ void run_sieve_impl(const Graph &G, const SieveRequest &req, SieveResult &res, b
             fin_thi = std::min<int32_t>((int32_t)G.ntiles, fin_thi);
         }
         for (int64_t base = 0; base < npts; base += rowb) {
-            k_lxt<<<grid_for((int64_t)G.n * rowd), 256, 0, st>>>(G.n, k, rowb, (uint32_t)base,
-                                                                 z.as<uint8_t>(), lxt.as<uint8_t>());
+            k_xt<<<grid_for((int64_t)G.n * ((rowb + 15) / 16)), 256, 0, st>>>(
+                G.n, k, rowb, (uint32_t)base, z.as<uint8_t>(), xt.as<uint8_t>());
             for (int l = 2; l <= k; ++l) {
                 const bool fin = (l == k);
                 LevelParams P{};
                 P.gidx = (l == 2) ? G.psrc : G.gsrc;
-                P.gbase = (l == 2) ? lxt.as<uint8_t>() : ((l & 1) ? s0.as<uint8_t>() : s1.as<uint8_t>());
+                P.gbase = (l == 2) ? xt.as<uint8_t>() : ((l & 1) ? s0.as<uint8_t>() : s1.as<uint8_t>());
                 P.pdst = G.pdst;
+                P.segnext = G.segnext;
                 P.peid = G.peid;
                 P.orow = G.orow;
                 P.sout = (l & 1) ? s1.as<uint8_t>() : s0.as<uint8_t>();
-                P.lxt = lxt.as<uint8_t>();
+                P.xt = xt.as<uint8_t>();
                 P.tile_p0 = G.tile_p0;
                 P.tile_pub = G.tile_pub;
                 P.tile_lb = G.tile_lb;
@@ -617,7 +664,10 @@ void run_sieve_impl(const Graph &G, const SieveRequest &req, SieveResult &res, b
                 P.rowb = rowb;
                 P.lanes = lanes;
                 k_prep<<<1, 1, 0, st>>>(ctl.as<Ctl>(), fin ? 0 : 1);
-                launch_level_w(W, fin, G, P, st);
+                {
+                    ProfileScope prof(st, fin ? 2 : (l == 2 ? 0 : 1), l, rowb);
+                    launch_level_w(W, fin, G, P, st);
+                }
             }
         }
     }
@@ -637,6 +687,7 @@ void run_sieve_impl(const Graph &G, const SieveRequest &req, SieveResult &res, b
     if (want_loc && loc_host && hi > lo)
         TPM_HIP(hipMemcpyAsync(loc_host, loc.p, (size_t)(hi - lo), hipMemcpyDeviceToHost, st));
     TPM_HIP(hipStreamSynchronize(st));
+    profile_collect();
     res.pick_eid = -1;
     res.pick_pos = -1;
     if (hpick != ~0ull) {

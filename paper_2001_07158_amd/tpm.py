@@ -45,7 +45,13 @@ class tpm_graph_stats(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("m", ctypes.c_int64), ("num_colors", ctypes.c_int32),
                 ("tmax", ctypes.c_int32), ("rows", ctypes.c_int64), ("tiles", ctypes.c_int64),
                 ("slots", ctypes.c_int64), ("max_in_degree", ctypes.c_int64),
-                ("device_bytes", ctypes.c_int64)]
+                ("device_bytes", ctypes.c_int64), ("gathers", ctypes.c_int64),
+                ("segments", ctypes.c_int64)]
+
+
+class tpm_kernel_time(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("level", ctypes.c_int32),
+                ("chunk_points", ctypes.c_int32), ("pad", ctypes.c_int32), ("ms", ctypes.c_double)]
 
 
 class tpm_tuning(ctypes.Structure):
@@ -100,13 +106,15 @@ _sig("tpm_server_create", ctypes.c_int32, [_vp, ctypes.POINTER(tpm_server_config
 _sig("tpm_server_submit", ctypes.c_int32, [_vp, ctypes.POINTER(tpm_query), _u64p])
 _sig("tpm_server_poll", ctypes.c_int32, [_vp, ctypes.POINTER(tpm_result), ctypes.c_int32, _i32p])
 _sig("tpm_server_destroy", None, [_vp])
+_sig("tpm_profile_enable", ctypes.c_int32, [ctypes.c_int32])
+_sig("tpm_profile_read", ctypes.c_int32, [ctypes.POINTER(tpm_kernel_time), ctypes.c_int32, _i32p])
 _sig("tpm_last_error", ctypes.c_char_p, [])
 _sig("tpm_version", ctypes.c_char_p, [])
 
 EXPORTED = ["tpm_graph_create", "tpm_graph_create_ex", "tpm_graph_destroy", "tpm_graph_stats_get",
             "tpm_sieve", "tpm_sieve_ex", "tpm_decide", "tpm_extract", "tpm_batch_run",
             "tpm_server_create", "tpm_server_submit", "tpm_server_poll", "tpm_server_destroy",
-            "tpm_last_error", "tpm_version"]
+            "tpm_profile_enable", "tpm_profile_read", "tpm_last_error", "tpm_version"]
 
 
 class TpmError(RuntimeError):
@@ -268,6 +276,21 @@ def tpm_server_poll(s, max_results=64):
 
 def tpm_server_destroy(s) -> None:
     _lib.tpm_server_destroy(s)
+
+
+KERNEL_KINDS = {0: "level2", 1: "middle", 2: "last"}
+
+
+def tpm_profile_enable(on: bool) -> None:
+    _check(_lib.tpm_profile_enable(1 if on else 0))
+
+
+def tpm_profile_read(max_items: int = 4096):
+    out = (tpm_kernel_time * max_items)()
+    n = ctypes.c_int32(0)
+    _check(_lib.tpm_profile_read(out, int(max_items), ctypes.byref(n)))
+    return [{"kind": KERNEL_KINDS[out[i].kind], "level": out[i].level,
+             "chunk_points": out[i].chunk_points, "ms": out[i].ms} for i in range(n.value)]
 
 
 # ------------------------------------------------------------------ owners

@@ -30,10 +30,10 @@ def tpm():
     return _tpm
 
 
-def _check(tpm, g, M, seed, mask=None, chunk=0, tile_edges=0, tile_held=0, label=""):
+def _check(tpm, g, M, seed, mask=None, chunk=0, tile_edges=0, label=""):
     say(f"case {label}: n={g.n} m={g.m} k={len(M)} seed={seed} chunk={chunk} "
-        f"T={tile_edges} H={tile_held} mask={'y' if mask is not None else 'n'}")
-    Gd = tpm.Graph.from_temporal(g, tile_edges=tile_edges, tile_held=tile_held)
+        f"T={tile_edges} mask={'y' if mask is not None else 'n'}")
+    Gd = tpm.Graph.from_temporal(g, tile_edges=tile_edges)
     pp, tot = Gd.sieve(M, seed, mask=mask, chunk=chunk)
     want = oracle.sieve(g, M, seed, mask=mask)
     assert np.array_equal(pp, want), f"{label}: per-point mismatch at {np.nonzero(pp != want)[0][:8]}"
@@ -92,12 +92,12 @@ def test_empty_and_degenerate(tpm):
     del rng
 
 
-@pytest.mark.parametrize("T,H", [(1, 1), (2, 1), (7, 3), (16, 8), (64, 1), (64, 8)])
-def test_tile_shapes_with_hubs(tpm, T, H):
+@pytest.mark.parametrize("T", [1, 2, 7, 16, 64, 256, 1000, 4096])
+def test_tile_shapes_with_hubs(tpm, T):
     # power-law in-degrees: long in-lists split over many tiles (look-back path)
     g = G.chung_lu_graph(3000, 60000, 2.5, 50, 3, 1234)
     M = [0, 1, 2, 0, 1, 2]
-    _check(tpm, g, M, 42, tile_edges=T, tile_held=H, label=f"hubs T={T} H={H}")
+    _check(tpm, g, M, 42, tile_edges=T, label=f"hubs T={T}")
 
 
 @pytest.mark.parametrize("chunk", [4, 16, 64, 256, 512, 1024])
@@ -120,7 +120,7 @@ def test_localisation_matches_oracle(tpm):
         g = G.chung_lu_graph(400, 5000, 2.5, 30, 3, 100 + it)
         M = [int(c) for c in rng.integers(0, 3, int(rng.integers(2, 7)))]
         say(f"case loc{it}: k={len(M)}")
-        Gd = tpm.Graph.from_temporal(g, tile_edges=int(rng.integers(1, 65)))
+        Gd = tpm.Graph.from_temporal(g, tile_edges=int(rng.integers(1, 300)))
         pp, tot, loc = Gd.sieve(M, 5 + it, loc=True)
         wpp, wloc = oracle.sieve(g, M, 5 + it, loc=True)
         assert np.array_equal(pp, wpp)

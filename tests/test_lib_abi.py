@@ -74,7 +74,7 @@ def test_bad_tile_options_rejected():
     from paper_2001_07158_amd import tpm
     z = np.zeros(1, dtype=np.int32)
     with pytest.raises(tpm.TpmError) as ei:
-        tpm.tpm_graph_create(2, z, z + 1, z + 1, np.zeros(2, dtype=np.int32), 1, tile_edges=65)
+        tpm.tpm_graph_create(2, z, z + 1, z + 1, np.zeros(2, dtype=np.int32), 1, tile_edges=5000)
     assert ei.value.code == tpm.TPM_EINVAL
 
 
