@@ -16,22 +16,6 @@ namespace tpm {
 
 namespace {
 thread_local std::string t_last_error;
-std::mutex g_pool_mu;
-std::set<int> g_pool_ready;
-
-// Keep freed stream-ordered allocations in the device pool so that repeated
-// queries do not return multi-gigabyte level buffers to the driver each time.
-void configure_pool(int device) {
-    std::lock_guard<std::mutex> lk(g_pool_mu);
-    if (g_pool_ready.count(device)) return;
-    hipMemPool_t pool;
-    if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess) {
-        uint64_t thr = UINT64_MAX;
-        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
-    }
-    g_pool_ready.insert(device);
-}
-
 template <class F>
 tpm_status guarded(F &&f) {
     try {
@@ -116,6 +100,51 @@ void profile_collect() {
     }
     t_pending.clear();
 }
+
+// ------------------------------------------------------------------ workspaces
+struct WorkspacePool {
+    std::mutex mu;
+    std::vector<Workspace *> all, free_list;
+    ~WorkspacePool() {
+        for (Workspace *w : all) delete w;
+    }
+};
+
+void DBuf::alloc(size_t bytes, hipStream_t st) {
+    bytes = std::max<size_t>(bytes, 16);
+    if (bytes <= cap) return;
+    if (p) {
+        TPM_HIP(hipStreamSynchronize(st));
+        (void)hipFree(p);
+        p = nullptr;
+        cap = 0;
+    }
+    TPM_HIP(hipMalloc(&p, bytes));
+    cap = bytes;
+}
+
+DBuf::~DBuf() {
+    if (p) (void)hipFree(p);
+}
+
+WorkspaceLease::WorkspaceLease(const Graph &G) : pool(G.pool), ws(nullptr) {
+    std::lock_guard<std::mutex> lk(pool->mu);
+    if (!pool->free_list.empty()) {
+        ws = pool->free_list.back();
+        pool->free_list.pop_back();
+    } else {
+        ws = new Workspace();
+        pool->all.push_back(ws);
+    }
+}
+
+WorkspaceLease::~WorkspaceLease() {
+    std::lock_guard<std::mutex> lk(pool->mu);
+    pool->free_list.push_back(ws);
+}
+
+WorkspacePool *new_workspace_pool() { return new WorkspacePool(); }
+void delete_workspace_pool(WorkspacePool *p) { delete p; }
 
 void set_error(const std::string &msg) { t_last_error = msg; }
 void clear_error() { t_last_error.clear(); }
@@ -265,7 +294,7 @@ tpm_status tpm_graph_create_ex(int32_t n, int64_t m, const int32_t *src, const i
         auto *g = new tpm_graph();
         try {
             build_graph(g->G, n, m, src, dst, tau, color, num_colors, flags, opt);
-            configure_pool(g->G.device);
+            g->G.pool = new_workspace_pool();
         } catch (...) {
             delete g;
             throw;
@@ -286,6 +315,8 @@ void tpm_graph_destroy(tpm_graph *g) {
     int prev = -1;
     if (hipGetDevice(&prev) == hipSuccess && prev != g->G.device) (void)hipSetDevice(g->G.device);
     (void)hipDeviceSynchronize();
+    delete_workspace_pool(g->G.pool);
+    g->G.pool = nullptr;
     free_graph(g->G);
     if (prev >= 0 && prev != g->G.device) (void)hipSetDevice(prev);
     delete g;

@@ -75,6 +75,38 @@ constexpr int kClampRow = 763;
 constexpr uint32_t kZero7 = 0x00100000u;  // LOG7 of zero: pushes any sum past the clamp
 constexpr int kLdsBytes = kExpBase + kExpRows * 128;  // 163328 <= 160 KiB
 
+// ------------------------------------------------------------------ workspaces
+// A device buffer that keeps its allocation across calls and only grows.
+struct DBuf {
+    void *p = nullptr;
+    size_t cap = 0;
+    DBuf() = default;
+    DBuf(const DBuf &) = delete;
+    DBuf &operator=(const DBuf &) = delete;
+    void alloc(size_t bytes, hipStream_t st);  // ensures capacity (synchronises on growth)
+    ~DBuf();
+    template <class T>
+    T *as() const { return (T *)p; }
+};
+
+// Device memory of one sieve call: level buffers, per-vertex rows, control words.
+struct Workspace {
+    DBuf ctl, z, xt, s0, s1, pub, pp, tot, mask, loc, pick;
+};
+
+// Workspaces of a graph: a call takes one (creating it if none is free) and
+// returns it when its stream is synchronised, so concurrent calls never share one.
+struct WorkspacePool;
+struct Graph;
+struct WorkspaceLease {
+    explicit WorkspaceLease(const Graph &G);
+    ~WorkspaceLease();
+    WorkspaceLease(const WorkspaceLease &) = delete;
+    WorkspaceLease &operator=(const WorkspaceLease &) = delete;
+    WorkspacePool *pool;
+    Workspace *ws;
+};
+
 // ------------------------------------------------------------------ graph
 struct Graph {
     int device = 0;
@@ -107,6 +139,8 @@ struct Graph {
     int32_t *tile_pub = nullptr;  // [ntiles] slot this tile publishes to, -1 if none
     int32_t *tile_lb = nullptr;   // [ntiles] slot its look-back starts at, -1 if none
     uint8_t *lds_image = nullptr; // [kLdsBytes]
+
+    WorkspacePool *pool = nullptr;  // owned
 
     // host copies used by extraction
     std::vector<int32_t> h_inptr;   // [n+1]

@@ -201,13 +201,49 @@ __device__ __forceinline__ void lookback(unsigned long long *pub, int32_t slot, 
     }
 }
 
+// Per-position metadata of a window of 64 consecutive CSR positions, one position per
+// lane: gathered row, destination vertex, stored row, LOG7 of the edge's y.  Windows
+// are loaded one ahead so that no per-edge scalar value ever waits on memory.
+struct Win {
+    int32_t g, d, o;
+    uint32_t y;  // input edge id until finish_win, then LOG7 of y_{e, ylevel}
+};
+
+template <bool FIN>
+__device__ __forceinline__ Win load_win(const LevelParams &P, int32_t wb, int32_t p1, int lane) {
+    Win m{-1, -1, -1, 0};
+    const int32_t q = wb + lane;
+    if (q < p1) {
+        m.g = P.gidx[q];
+        m.d = P.pdst[q];
+        if constexpr (!FIN) m.o = P.orow[q];
+        m.y = (uint32_t)P.peid[q];
+    }
+    return m;
+}
+
+__device__ __forceinline__ void finish_win(const LevelParams &P, const uint8_t *lds, Win &m,
+                                           int32_t wb, int32_t p1, int lane, uint32_t lanebits) {
+    if (wb + lane < p1) {
+        uint32_t y = fp8(P.seed, 1u, P.ylevel, m.y);
+        m.y = lds32(lds, (y << 8) | lanebits);
+    } else {
+        m.y = kZero7;
+    }
+}
+
 template <int W>
-__device__ __forceinline__ void gather_batch(const LevelParams &P, int32_t pb, int32_t p1, bool act,
+__device__ __forceinline__ void gather_batch(const LevelParams &P, const Win &cw, const Win &nw,
+                                             int32_t wb, int32_t pb, int32_t p1, bool act,
                                              int lane, uint32_t (&g)[kU][W]) {
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
         const int32_t q = pb + u;
-        const int32_t r = (q < p1) ? P.gidx[q] : -1;
+        int32_t r = -1;
+        if (q < p1) {
+            const int32_t i = q - wb;  // uniform
+            r = (i < 64) ? __builtin_amdgcn_readlane(cw.g, i) : __builtin_amdgcn_readlane(nw.g, i - 64);
+        }
         if (r >= 0 && act) {
             load_row<W>(P.gbase, r, P.rowb, lane, g[u]);
         } else {
@@ -262,12 +298,18 @@ __global__ void __launch_bounds__(1024) k_level(LevelParams P) {
         }
         const bool cont = lbslot >= 0;
 
-        // x row of the in-list being processed (as LOG7 + base, per point) and the raw
+        int32_t wb = p0;  // first position of the current window
+        Win cw = load_win<FIN>(P, wb, p1, lane);
+        Win nw = load_win<FIN>(P, wb + 64, p1, lane);
+        finish_win(P, lds, cw, wb, p1, lane, lanebits);
+
+        // x row (as LOG7 + base, per point) of the in-list being processed, and the raw
         // x row of the next in-list, loaded ahead
-        int32_t cur_dst = -1, nxt_dst = P.pdst[p0];
+        const int32_t d0 = __builtin_amdgcn_readfirstlane(cw.d);
+        int32_t cur_dst = -1, nxt_dst = d0;
         uint32_t lx7[4 * W], acc[W], xn[W];
         if (act) {
-            load_row<W>(P.xt, nxt_dst, P.rowb, lane, xn);
+            load_row<W>(P.xt, d0, P.rowb, lane, xn);
         } else {
 #pragma unroll
             for (int w = 0; w < W; ++w) xn[w] = 0;
@@ -276,23 +318,15 @@ __global__ void __launch_bounds__(1024) k_level(LevelParams P) {
         for (int w = 0; w < W; ++w) acc[w] = 0;
 #pragma unroll
         for (int i = 0; i < 4 * W; ++i) lx7[i] = kZero7;
-        uint32_t ly_vec = kZero7;
 
         auto process = [&](const uint32_t (&g)[kU][W], int32_t pb) {
-            if (((pb - p0) & 63) == 0) {
-                // LOG7 of y_{e, ylevel} for the next 64 positions: lane i <-> pb + i
-                ly_vec = kZero7;
-                if (pb + lane < p1) {
-                    uint32_t y = fp8(P.seed, 1u, P.ylevel, (uint32_t)P.peid[pb + lane]);
-                    ly_vec = lds32(lds, (y << 8) | lanebits);
-                }
-            }
             const int nb = min(kU, p1 - pb);
 #pragma unroll
             for (int u = 0; u < kU; ++u) {
                 if (u >= nb) break;
                 const int32_t p = pb + u;
-                const int32_t d = P.pdst[p];
+                const int32_t i = p - wb;  // lane of this position in the current window
+                const int32_t d = __builtin_amdgcn_readlane(cw.d, i);
                 if (d != cur_dst) {  // a new in-list (or the start of a continuation tile)
                     if (d != nxt_dst && act) load_row<W>(P.xt, d, P.rowb, lane, xn);
 #pragma unroll
@@ -304,10 +338,19 @@ __global__ void __launch_bounds__(1024) k_level(LevelParams P) {
                         acc[w] = 0;
                     }
                     cur_dst = d;
-                    nxt_dst = P.segnext[d];
-                    if (nxt_dst >= 0 && act) load_row<W>(P.xt, nxt_dst, P.rowb, lane, xn);
+                    // the next in-list of this tile, if it starts in this window or the next
+                    uint64_t later = __ballot(cw.d != d && cw.d >= 0 && lane > i);
+                    int32_t nd = -1;
+                    if (later) {
+                        nd = __builtin_amdgcn_readlane(cw.d, __ffsll((long long)later) - 1);
+                    } else {
+                        uint64_t l2 = __ballot(nw.d != d && nw.d >= 0);
+                        if (l2) nd = __builtin_amdgcn_readlane(nw.d, __ffsll((long long)l2) - 1);
+                    }
+                    nxt_dst = nd;
+                    if (nd >= 0 && act) load_row<W>(P.xt, nd, P.rowb, lane, xn);
                 }
-                const uint32_t ly7 = __builtin_amdgcn_readlane(ly_vec, (p - p0) & 63);
+                const uint32_t ly7 = __builtin_amdgcn_readlane(cw.y, i);
                 uint32_t c[W];
                 if (ly7 < kZero7) {
 #pragma unroll
@@ -336,21 +379,28 @@ __global__ void __launch_bounds__(1024) k_level(LevelParams P) {
                 } else {
 #pragma unroll
                     for (int w = 0; w < W; ++w) acc[w] ^= c[w];
-                    const int32_t orow = P.orow[p];
+                    const int32_t orow = __builtin_amdgcn_readlane(cw.o, i);
                     if (orow >= 0 && act) store_row<W>(P.sout, orow, P.rowb, lane, acc);
                 }
+            }
+            // advance the window after its last batch
+            if (pb + kU - wb == 64 && pb + kU < p1) {
+                wb += 64;
+                cw = nw;
+                finish_win(P, lds, cw, wb, p1, lane, lanebits);
+                nw = load_win<FIN>(P, wb + 64, p1, lane);
             }
         };
 
         // two batches of gathers in flight: while one is multiplied, the next loads
         uint32_t ga[kU][W], gb[kU][W];
-        gather_batch<W>(P, p0, p1, act, lane, ga);
+        gather_batch<W>(P, cw, nw, wb, p0, p1, act, lane, ga);
         for (int32_t pb = p0; pb < p1;) {
-            gather_batch<W>(P, pb + kU, p1, act, lane, gb);
+            gather_batch<W>(P, cw, nw, wb, pb + kU, p1, act, lane, gb);
             process(ga, pb);
             pb += kU;
             if (pb >= p1) break;
-            gather_batch<W>(P, pb + kU, p1, act, lane, ga);
+            gather_batch<W>(P, cw, nw, wb, pb + kU, p1, act, lane, ga);
             process(gb, pb);
             pb += kU;
         }
@@ -501,23 +551,6 @@ inline unsigned grid_for(int64_t work, int block = 256) {
     return (unsigned)std::max<int64_t>(1, (work + block - 1) / block);
 }
 
-struct DevBuf {
-    void *p = nullptr;
-    hipStream_t s = nullptr;
-    DevBuf() = default;
-    DevBuf(const DevBuf &) = delete;
-    DevBuf &operator=(const DevBuf &) = delete;
-    void alloc(size_t bytes, hipStream_t st) {
-        s = st;
-        TPM_HIP(hipMallocAsync(&p, std::max<size_t>(bytes, 16), st));
-    }
-    ~DevBuf() {
-        if (p) (void)hipFreeAsync(p, s);
-    }
-    template <class T>
-    T *as() const { return (T *)p; }
-};
-
 QuerySlots make_slots(const Graph &G, const int32_t *M, int32_t k) {
     TPM_REQUIRE(M != nullptr, "multiset must not be NULL");
     TPM_REQUIRE(k >= 1 && k <= 16, "k must be in [1, 16]");
@@ -584,7 +617,10 @@ void run_sieve_impl(const Graph &G, const SieveRequest &req, SieveResult &res, b
     const int rowd = rowb / 4;
     const int64_t ppbytes = std::max<int64_t>(npts, 4);
 
-    DevBuf ctl, z, xt, s0, s1, pub, pp, tot, mask, loc;
+    WorkspaceLease lease(G);
+    Workspace &ws = *lease.ws;
+    DBuf &ctl = ws.ctl, &z = ws.z, &xt = ws.xt, &s0 = ws.s0, &s1 = ws.s1, &pub = ws.pub,
+         &pp = ws.pp, &tot = ws.tot, &mask = ws.mask, &loc = ws.loc, &pick = ws.pick;
     ctl.alloc(sizeof(Ctl), st);
     TPM_HIP(hipMemsetAsync(ctl.p, 0, sizeof(Ctl), st));
     z.alloc((size_t)G.n * 16, st);
@@ -604,7 +640,6 @@ void run_sieve_impl(const Graph &G, const SieveRequest &req, SieveResult &res, b
         lo = std::max<int64_t>(0, req.fin_lo);
         hi = std::min<int64_t>(G.m, req.fin_hi);
     }
-    DevBuf pick;
     if (want_loc) {
         loc.alloc((size_t)std::max<int64_t>(1, hi - lo), st);
         TPM_HIP(hipMemsetAsync(loc.p, 0, (size_t)std::max<int64_t>(1, hi - lo), st));
