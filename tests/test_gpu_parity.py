@@ -200,3 +200,27 @@ def test_graph_stats(tpm):
     assert st["m"] == g.m and st["n"] == g.n
     assert st["max_in_degree"] == np.bincount(g.dst, minlength=g.n).max()
     Gd.close()
+
+
+@pytest.mark.timeout(600)
+def test_k10_full_size_sampled_points(tpm):
+    """The k = 10 workload at full size (n = 1e6, m = 1e8), in the launch
+    configuration the bench times (one 1024-point chunk), against the oracle on a
+    sample of sieve points computed one by one."""
+    import os
+    g = make_config_graph("k10")
+    M = make_config_query("k10")
+    seed = 20010715
+    say(f"case k10 full: n={g.n} m={g.m} M={list(M)}")
+    Gd = tpm.Graph.from_temporal(g)
+    pp, tot = Gd.sieve(M, seed)
+    assert tot == int(np.bitwise_xor.reduce(pp))
+    st = Gd.stats()
+    Gd.close()
+    rng = np.random.default_rng(11)
+    pts = np.unique(np.concatenate([[0, 1, 512, 1023], rng.choice(1024, 8, replace=False)]))
+    nthreads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
+    say(f"oracle on {pts.size} points, {nthreads} threads (rows={st['rows']})")
+    idx = oracle.Index(g)
+    want = idx.eval(M, seed, pts.astype(np.uint32), nthreads=nthreads)
+    assert np.array_equal(pp[pts], want), (pts, pp[pts], want)
