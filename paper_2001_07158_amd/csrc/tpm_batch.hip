@@ -1,16 +1,30 @@
 // Batched queries and the serving loop (C ABI: tpm_batch_run, tpm_server_*).
 //
-// First form: queries run one after another through the single-query path; the
-// packed multi-query kernel replaces this loop.
+// Both run on multi-query rows (tpm_sieve.hip: k_step): a row of up to 64 lanes holds
+// lane groups, each a (query, chunk of sieve points) with its own seed and level.
+//   * Batch: queries of equal k are packed side by side and advance level by level
+//     together, so a small query no longer pays a whole sweep over the graph for a
+//     handful of lanes.  Queries with 2^k >= 1024 points already fill a row and take
+//     the single-query path.
+//   * Server: the row stays resident; every step advances each group one level, a
+//     group that finished its last level frees its lanes, and queued requests are
+//     admitted into free lanes at the next step (continuous batching).  A request
+//     whose sieve is nonzero can have its witness extracted.
+// Results are bit-identical to the same query run alone: fingerprints depend only on
+// (seed, tag, indices), never on lanes or steps.
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <map>
+#include <memory>
 #include <mutex>
 #include <thread>
+#include <vector>
 
 #include "tpm_internal.h"
 
@@ -32,6 +46,9 @@ tpm_status guarded2(F &&f) {
     } catch (const Error &e) {
         set_error(e.msg);
         return e.code;
+    } catch (const std::bad_alloc &) {
+        set_error("host allocation failed");
+        return TPM_ENOMEM;
     } catch (const std::exception &e) {
         set_error(e.what());
         return TPM_EDEVICE;
@@ -43,7 +60,22 @@ double now_ms() {
     return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
 }
 
-void run_one(const Graph &G, const tpm_query &q, tpm_result &r, hipStream_t st) {
+void check_query(const Graph &G, const tpm_query &q) {
+    TPM_REQUIRE(q.multiset != nullptr, "query multiset must not be NULL");
+    TPM_REQUIRE(q.k >= 1 && q.k <= 16, "k must be in [1, 16]");
+    for (int i = 0; i < q.k; ++i)
+        TPM_REQUIRE(q.multiset[i] >= 0 && q.multiset[i] < G.q, "multiset colour out of range");
+}
+
+void extract_into(const Graph &G, const tpm_query &q, tpm_result &r, hipStream_t st) {
+    int64_t pe[16];
+    int32_t pv[16];
+    r.path_status = extract_path(G, q.multiset, q.k, q.seed, 8, pv, pe, st);
+    for (int i = 0; i < q.k; ++i) r.path_vertices[i] = pv[i];
+    for (int i = 0; i + 1 < q.k; ++i) r.path_edges[i] = pe[i];
+}
+
+void run_alone(const Graph &G, const tpm_query &q, tpm_result &r, hipStream_t st) {
     SieveRequest req;
     req.multiset = q.multiset;
     req.k = q.k;
@@ -52,12 +84,13 @@ void run_one(const Graph &G, const tpm_query &q, tpm_result &r, hipStream_t st) 
     run_sieve(G, req, res, st);
     r.total = res.total;
     r.found = res.total != 0;
-    r.path_status = 0;
-    if (q.want_path && r.found) {
-        int64_t pe[16];
-        r.path_status = extract_path(G, q.multiset, q.k, q.seed, 8, r.path_vertices, pe, st);
-        for (int i = 0; i + 1 < q.k; ++i) r.path_edges[i] = pe[i];
-    }
+}
+
+// lane-group geometry of a query of size k on rows with W dwords per lane
+int group_points(int k, int W) {
+    const int pts = 1 << k;
+    const int unit = 4 * W;
+    return std::max(pts, unit);  // padded to whole lanes; padded points are ignored
 }
 
 }  // namespace
@@ -69,67 +102,259 @@ tpm_status tpm_batch_run(const tpm_graph *g, int32_t nq, const tpm_query *q, tpm
     return guarded2([&]() -> tpm_status {
         TPM_REQUIRE(g && (nq == 0 || (q && out)), "NULL argument");
         TPM_REQUIRE(nq >= 0, "nq must be >= 0");
+        const Graph &G = g->G;
+        for (int32_t i = 0; i < nq; ++i) check_query(G, q[i]);
+        for (int32_t i = 0; i < nq; ++i) std::memset(&out[i], 0, sizeof(tpm_result));
+        const int max_pts = (tune && tune->chunk) ? tune->chunk : 1024;
+        TPM_REQUIRE(max_pts >= 256 && max_pts <= 1024 && (max_pts & (max_pts - 1)) == 0,
+                    "batch row width (chunk) must be 256, 512 or 1024");
+        hipStream_t st = nullptr;
+
+        // queries that fill a row on their own, or k = 1, take the single-query path
+        std::map<int, std::vector<int32_t>> by_k;
         for (int32_t i = 0; i < nq; ++i) {
-            std::memset(&out[i], 0, sizeof(tpm_result));
-            run_one(g->G, q[i], out[i], nullptr);
+            if (q[i].k == 1 || (1 << q[i].k) >= max_pts) {
+                run_alone(G, q[i], out[i], st);
+            } else {
+                by_k[q[i].k].push_back(i);
+            }
         }
+        if (!by_k.empty() && G.m > 0) {
+            WorkspaceLease lease(G);
+            for (auto &kv : by_k) {
+                const int k = kv.first;
+                const auto &ids = kv.second;
+                const int W = std::min(4, std::max(1, (1 << k) / 4));
+                const int W_row = std::min(W, max_pts / 256);
+                const int gpts = group_points(k, W_row);
+                const int lpg = gpts / (4 * W_row);  // lanes per query
+                const int per_pass = 64 / lpg;
+                for (size_t a = 0; a < ids.size(); a += per_pass) {
+                    const int cnt = (int)std::min<size_t>(per_pass, ids.size() - a);
+                    MultiRow row;
+                    row.W = W_row;
+                    row.lanes = cnt * lpg;
+                    row.ws = lease.ws;
+                    multi_init(G, row, st);
+                    for (int j = 0; j < cnt; ++j) {
+                        const tpm_query &qq = q[ids[a + j]];
+                        multi_prepare(G, row, j * lpg, gpts, qq.multiset, k, qq.seed, 0, nullptr, st);
+                    }
+                    std::vector<StepLane> lanes((size_t)row.lanes);
+                    for (int l = 2; l <= k; ++l) {
+                        uint32_t flags = kLaneActive | (l == 2 ? kLaneFromX : 0u) | (l == k ? kLaneAcc : 0u);
+                        for (int j = 0; j < cnt; ++j)
+                            for (int t = 0; t < lpg; ++t)
+                                lanes[(size_t)(j * lpg + t)] = {q[ids[a + j]].seed, (uint32_t)(l - 1), flags};
+                        multi_step(G, row, lanes.data(), st);
+                    }
+                    std::vector<uint8_t> pp((size_t)row.rowb());
+                    multi_read(G, row, 0, row.lanes, pp.data(), st);
+                    for (int j = 0; j < cnt; ++j) {
+                        uint8_t t = 0;
+                        for (int b = 0; b < (1 << k); ++b) t ^= pp[(size_t)j * gpts + b];
+                        out[ids[a + j]].total = t;
+                        out[ids[a + j]].found = t != 0;
+                    }
+                }
+            }
+        }
+        for (int32_t i = 0; i < nq; ++i)
+            if (q[i].want_path && out[i].found) extract_into(G, q[i], out[i], st);
         return TPM_OK;
     });
 }
 
+}  // extern "C"
+
+// ------------------------------------------------------------------ serving loop
 struct tpm_server {
     const tpm_graph *g = nullptr;
     tpm_server_config cfg{};
     std::mutex mu;
     std::condition_variable cv;
-    struct Item {
+    struct Req {
         tpm_query q;
         std::vector<int32_t> ms;
-        uint64_t ticket;
-        double t_submit;
+        uint64_t ticket = 0;
+        double t_submit = 0, t_start = -1;
+        int chunks_left = 0;     // chunks not yet finished
+        int next_chunk = 0;      // next chunk to admit
+        uint8_t total = 0;
     };
-    std::deque<Item> queue;
+    std::deque<std::shared_ptr<Req>> queue;
     std::deque<tpm_result> done;
     uint64_t next_ticket = 1;
     bool stop = false;
+    std::string error;
     std::thread worker;
+    // row geometry
+    int W = 1, lanes = 64;
+    uint64_t steps = 0;
 };
+
+namespace {
+
+struct Group {
+    std::shared_ptr<tpm_server::Req> req;
+    int lane0 = 0, nl = 0, gpts = 0, level = 2, chunk = 0;
+};
+
+void serve_loop(tpm_server *s) {
+    const Graph &G = s->g->G;
+    (void)hipSetDevice(G.device);
+    hipStream_t st = nullptr;
+    try {
+        WorkspaceLease lease(G);
+        MultiRow row;
+        row.W = s->W;
+        row.lanes = s->lanes;
+        row.ws = lease.ws;
+        multi_init(G, row, st);
+        int rowpts = 1;  // largest power of two of points that fits the row
+        while (rowpts * 2 <= row.rowb()) rowpts *= 2;
+        std::vector<Group> groups;
+        std::vector<char> used((size_t)row.lanes, 0);
+        auto alloc_lanes = [&](int nl) -> int {
+            for (int a = 0; a + nl <= row.lanes; ++a) {
+                bool ok = true;
+                for (int t = a; t < a + nl && ok; ++t) ok = !used[(size_t)t];
+                if (ok) {
+                    for (int t = a; t < a + nl; ++t) used[(size_t)t] = 1;
+                    return a;
+                }
+            }
+            return -1;
+        };
+        auto finish = [&](const std::shared_ptr<tpm_server::Req> &rq) {
+            tpm_result r;
+            std::memset(&r, 0, sizeof(r));
+            r.ticket = rq->ticket;
+            r.total = rq->total;
+            r.found = rq->total != 0;
+            r.t_submit_ms = rq->t_submit;
+            r.t_start_ms = rq->t_start;
+            rq->q.multiset = rq->ms.data();
+            if (r.found && (rq->q.want_path || s->cfg.extract_paths)) extract_into(G, rq->q, r, st);
+            r.t_done_ms = now_ms();
+            std::lock_guard<std::mutex> lk(s->mu);
+            s->done.push_back(r);
+        };
+        for (;;) {
+            // ---- admission: requests enter free lanes (chunks of large queries in order)
+            {
+                std::unique_lock<std::mutex> lk(s->mu);
+                if (groups.empty())
+                    s->cv.wait(lk, [&] { return s->stop || !s->queue.empty(); });
+                if (s->stop) return;
+            }
+            for (;;) {
+                std::shared_ptr<tpm_server::Req> rq;
+                {
+                    std::lock_guard<std::mutex> lk(s->mu);
+                    if (s->queue.empty()) break;
+                    rq = s->queue.front();
+                }
+                if (rq->q.k == 1 || G.m == 0) {  // no levels to run: single-query path
+                    {
+                        std::lock_guard<std::mutex> lk(s->mu);
+                        s->queue.pop_front();
+                    }
+                    rq->t_start = now_ms();
+                    tpm_result r0;
+                    std::memset(&r0, 0, sizeof(r0));
+                    rq->q.multiset = rq->ms.data();
+                    run_alone(G, rq->q, r0, st);
+                    rq->total = r0.total;
+                    finish(rq);
+                    continue;
+                }
+                const int pts = 1 << rq->q.k;
+                const int gpts = std::min(rowpts, group_points(rq->q.k, row.W));
+                const int nl = gpts / (4 * row.W);
+                const int a = alloc_lanes(nl);
+                if (a < 0) break;  // row full: wait for lanes to free up
+                if (rq->t_start < 0) {
+                    rq->t_start = now_ms();
+                    rq->chunks_left = std::max(1, pts / gpts);
+                }
+                Group gr;
+                gr.req = rq;
+                gr.lane0 = a;
+                gr.nl = nl;
+                gr.gpts = gpts;
+                gr.chunk = rq->next_chunk++;
+                multi_prepare(G, row, a, gpts, rq->ms.data(), rq->q.k, rq->q.seed,
+                              (uint32_t)(gr.chunk * gpts), nullptr, st);
+                groups.push_back(gr);
+                if (rq->next_chunk * gpts >= pts) {
+                    std::lock_guard<std::mutex> lk(s->mu);
+                    s->queue.pop_front();
+                }
+            }
+            if (groups.empty()) continue;
+            // ---- one step: every group advances one level
+            std::vector<StepLane> lanes((size_t)row.lanes, StepLane{0, 0, 0});
+            for (const Group &gr : groups) {
+                const int k = gr.req->q.k;
+                uint32_t flags = kLaneActive | (gr.level == 2 ? kLaneFromX : 0u) |
+                                 (gr.level == k ? kLaneAcc : 0u);
+                for (int t = 0; t < gr.nl; ++t)
+                    lanes[(size_t)(gr.lane0 + t)] = {gr.req->q.seed, (uint32_t)(gr.level - 1), flags};
+            }
+            multi_step(G, row, lanes.data(), st);
+            s->steps++;
+            // ---- retire groups that ran their last level
+            std::vector<Group> keep;
+            for (Group &gr : groups) {
+                if (gr.level == gr.req->q.k) {
+                    std::vector<uint8_t> pp((size_t)gr.gpts);
+                    multi_read(G, row, gr.lane0, gr.nl, pp.data(), st);
+                    const int pts = 1 << gr.req->q.k;
+                    for (int b = 0; b < std::min(pts, gr.gpts); ++b) gr.req->total ^= pp[(size_t)b];
+                    for (int t = gr.lane0; t < gr.lane0 + gr.nl; ++t) used[(size_t)t] = 0;
+                    if (--gr.req->chunks_left == 0) finish(gr.req);
+                } else {
+                    gr.level++;
+                    keep.push_back(gr);
+                }
+            }
+            groups.swap(keep);
+        }
+    } catch (const Error &e) {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->error = e.msg;
+    } catch (const std::exception &e) {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->error = e.what();
+    }
+}
+
+}  // namespace
+
+extern "C" {
 
 tpm_status tpm_server_create(const tpm_graph *g, const tpm_server_config *cfg, tpm_server **out) {
     return guarded2([&]() -> tpm_status {
         TPM_REQUIRE(g && out, "NULL argument");
+        *out = nullptr;
         auto *s = new tpm_server();
         s->g = g;
         if (cfg) s->cfg = *cfg;
-        s->worker = std::thread([s]() {
-            int dev = s->g->G.device;
-            (void)hipSetDevice(dev);
-            for (;;) {
-                tpm_server::Item it;
-                {
-                    std::unique_lock<std::mutex> lk(s->mu);
-                    s->cv.wait(lk, [&] { return s->stop || !s->queue.empty(); });
-                    if (s->queue.empty()) return;
-                    it = std::move(s->queue.front());
-                    s->queue.pop_front();
-                }
-                tpm_result r;
-                std::memset(&r, 0, sizeof(r));
-                r.ticket = it.ticket;
-                r.t_submit_ms = it.t_submit;
-                r.t_start_ms = now_ms();
-                it.q.multiset = it.ms.data();
-                it.q.want_path = it.q.want_path || s->cfg.extract_paths;
-                try {
-                    run_one(s->g->G, it.q, r, nullptr);
-                } catch (const Error &e) {
-                    r.path_status = e.code;
-                }
-                r.t_done_ms = now_ms();
-                std::lock_guard<std::mutex> lk(s->mu);
-                s->done.push_back(r);
-            }
-        });
+        const Graph &G = g->G;
+        // row width: the widest of 1024 / 512 / 256 points whose two level buffers and
+        // vertex rows fit the state budget (default: 70 % of free device memory)
+        size_t freeb = 0, totalb = 0;
+        TPM_HIP(hipMemGetInfo(&freeb, &totalb));
+        double budget = s->cfg.state_bytes > 0 ? (double)s->cfg.state_bytes : 0.7 * (double)freeb;
+        int W = 4;
+        while (W > 1 && (double)(2 * G.R + G.n + 2 * G.nslots) * (256.0 * W) > budget) W >>= 1;
+        TPM_REQUIRE((double)(2 * G.R + G.n + 2 * G.nslots) * 256.0 <= budget,
+                    "not enough device memory for a 256-point serving row");
+        s->W = W;
+        s->lanes = 64;
+        if (s->cfg.max_lanes > 0) s->lanes = std::min(64, s->cfg.max_lanes);
+        s->worker = std::thread(serve_loop, s);
         *out = s;
         return TPM_OK;
     });
@@ -137,20 +362,19 @@ tpm_status tpm_server_create(const tpm_graph *g, const tpm_server_config *cfg, t
 
 tpm_status tpm_server_submit(tpm_server *s, const tpm_query *q, uint64_t *ticket) {
     return guarded2([&]() -> tpm_status {
-        TPM_REQUIRE(s && q && q->multiset, "NULL argument");
-        TPM_REQUIRE(q->k >= 1 && q->k <= 16, "k must be in [1, 16]");
-        for (int i = 0; i < q->k; ++i)
-            TPM_REQUIRE(q->multiset[i] >= 0 && q->multiset[i] < s->g->G.q, "multiset colour out of range");
-        tpm_server::Item it;
-        it.q = *q;
-        it.ms.assign(q->multiset, q->multiset + q->k);
-        it.t_submit = now_ms();
+        TPM_REQUIRE(s && q, "NULL argument");
+        check_query(s->g->G, *q);
+        auto rq = std::make_shared<tpm_server::Req>();
+        rq->q = *q;
+        rq->ms.assign(q->multiset, q->multiset + q->k);
+        rq->t_submit = now_ms();
         {
             std::lock_guard<std::mutex> lk(s->mu);
             if (s->stop) return TPM_ECLOSED;
-            it.ticket = s->next_ticket++;
-            if (ticket) *ticket = it.ticket;
-            s->queue.push_back(std::move(it));
+            if (!s->error.empty()) throw Error{TPM_EDEVICE, "server stopped: " + s->error};
+            rq->ticket = s->next_ticket++;
+            if (ticket) *ticket = rq->ticket;
+            s->queue.push_back(rq);
         }
         s->cv.notify_one();
         return TPM_OK;
@@ -167,6 +391,7 @@ tpm_status tpm_server_poll(tpm_server *s, tpm_result *out, int32_t max, int32_t 
             s->done.pop_front();
         }
         *n_out = n;
+        if (n == 0 && !s->error.empty()) throw Error{TPM_EDEVICE, "server stopped: " + s->error};
         return n ? TPM_OK : TPM_PENDING;
     });
 }

@@ -181,6 +181,34 @@ void run_sieve(const Graph &G, const SieveRequest &req, SieveResult &res, hipStr
 void run_sieve_loc_all(const Graph &G, const SieveRequest &req, SieveResult &res,
                        uint8_t *loc_by_edge, hipStream_t stream);
 
+// ------------------------------------------------------------------ multi-query steps
+// Per-lane role in a multi-query step (device table, one entry per lane).
+struct StepLane {
+    uint64_t seed;
+    uint32_t ylevel;  // walk position of y at this step = level - 1
+    uint32_t flags;   // kLaneActive | kLaneFromX (level 2) | kLaneAcc (last level)
+};
+constexpr uint32_t kLaneActive = 1, kLaneFromX = 2, kLaneAcc = 4;
+
+// A multi-query row: W dwords per lane, `lanes` lanes, buffers from a workspace.
+struct MultiRow {
+    int W = 1, lanes = 64;
+    int rowb() const { return 4 * W * lanes; }
+    int parity = 0;  // steps read level buffer `parity` and write the other one
+    Workspace *ws = nullptr;
+};
+
+// Sizes the buffers of `row` for graph G (W, lanes already set).
+void multi_init(const Graph &G, MultiRow &row, hipStream_t st);
+// Computes the x rows of query (M, k, seed) for points [base, base + npts) into lanes
+// [lane0, lane0 + npts / (4 W)) and clears their accumulators.
+void multi_prepare(const Graph &G, MultiRow &row, int lane0, int npts, const int32_t *M, int32_t k,
+                   uint64_t seed, uint32_t base, const uint8_t *vertex_mask, hipStream_t st);
+// One level for every lane group (lanes[i] for lane i; inactive lanes have flags 0).
+void multi_step(const Graph &G, MultiRow &row, const StepLane *lanes, hipStream_t st);
+// Copies the accumulators of lanes [lane0, lane0 + nl) (4 W bytes per lane) to host.
+void multi_read(const Graph &G, MultiRow &row, int lane0, int nl, uint8_t *out, hipStream_t st);
+
 // ------------------------------------------------------------------ profiling
 bool profile_on();
 // brackets a level kernel launch with events when profiling is enabled

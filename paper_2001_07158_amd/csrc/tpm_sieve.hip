@@ -85,6 +85,21 @@ struct LevelParams {
     int32_t lanes;           // lanes holding points = rowb / (4 W)
 };
 
+struct StepParams {
+    const int32_t *psrc, *gsrc, *pdst, *peid, *orow;
+    const uint8_t *xt;   // per-vertex rows of x for every lane group
+    const uint8_t *sin;  // rows written by the previous step
+    uint8_t *sout;       // rows written by this step
+    const int32_t *tile_p0, *tile_pub, *tile_lb;
+    int32_t ntiles;
+    unsigned long long *pub;
+    Ctl *ctl;
+    uint32_t *fin;               // per-point accumulators of groups at their last level
+    const uint8_t *lds_image;
+    int32_t rowb, lanes;
+    StepLane tab[64];            // per lane: seed, level, role
+};
+
 // SplitMix64 output function (Steele, Lea, Flood 2014).
 __device__ __forceinline__ uint64_t mix64(uint64_t z) {
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
@@ -479,11 +494,12 @@ __global__ void k_z(int32_t n, int32_t k, const int32_t *color, QuerySlots qs, c
     ((uint4 *)z)[u] = make_uint4(out[0], out[1], out[2], out[3]);
 }
 
-// Row of x_u^A = sum_{j in A} z_{u,j} for the chunk's points A = base + b.  A thread
-// writes 16 points: x^A = x^(A with its low 4 bits cleared) + x^(A's low 4 bits).
-__global__ void k_xt(int32_t n, int32_t k, int32_t rowb, uint32_t base, const uint8_t *z,
-                     uint8_t *xt) {
-    const int32_t per_row = (rowb + 15) >> 4;  // threads per vertex row
+// x_u^A = sum_{j in A} z_{u,j} for the points A = base + b, b in [0, npts), written to
+// bytes [col, col + npts) of vertex u's row (stride bytes per row).  A thread writes
+// 16 points: x^A = x^(A with its low 4 bits cleared) + x^(A's low 4 bits).
+__global__ void k_xt(int32_t n, int32_t k, int32_t npts, int32_t stride, int32_t col, uint32_t base,
+                     const uint8_t *z, uint8_t *xt) {
+    const int32_t per_row = (npts + 15) >> 4;  // threads per vertex row
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= (int64_t)n * per_row) return;
     int64_t u = i / per_row;
@@ -501,18 +517,18 @@ __global__ void k_xt(int32_t n, int32_t k, int32_t rowb, uint32_t base, const ui
         int j = __builtin_ctz(b);
         lo[b] = lo[b & (b - 1)] ^ (j < k ? zj(j) : 0u);
     }
-    const int npts = min(16, rowb - part * 16);
+    const int cnt = min(16, npts - part * 16);
     uint32_t out[4] = {0, 0, 0, 0};
-    for (int b = 0; b < npts; ++b) {
+    for (int b = 0; b < cnt; ++b) {
         uint32_t A = A0 + (uint32_t)b;
         uint32_t x = ((A >> 4) == (A0 >> 4)) ? (hi ^ lo[A & 15u]) : 0u;
         out[b >> 2] |= x << (8 * (b & 3));
     }
-    uint8_t *row = xt + u * (int64_t)rowb + (int64_t)part * 16;
-    if (npts == 16) {
+    uint8_t *row = xt + u * (int64_t)stride + col + (int64_t)part * 16;
+    if (cnt == 16 && ((stride | col) & 15) == 0) {
         *(uint4 *)row = make_uint4(out[0], out[1], out[2], out[3]);
     } else {
-        for (int b = 0; b < npts; b += 4) *(uint32_t *)(row + b) = out[b >> 2];
+        for (int b = 0; b < cnt; b += 4) *(uint32_t *)(row + b) = out[b >> 2];
     }
 }
 
@@ -551,6 +567,215 @@ inline unsigned grid_for(int64_t work, int block = 256) {
     return (unsigned)std::max<int64_t>(1, (work + block - 1) / block);
 }
 
+// ---------------------------------------------------------------------------------
+// Multi-query step.  The row holds several lane groups, each a (query, chunk) with
+// its own seed and its own level: a group at level 2 gathers the x row of the edge's
+// source, later levels gather the previous step's rows, and a group at its last
+// level accumulates instead of storing.  One launch advances every group one level,
+// so groups can start and finish independently (continuous batching), and queries of
+// any size share one sweep over the graph.
+// ---------------------------------------------------------------------------------
+struct WinS {
+    int32_t g, s, d, o;
+    uint32_t e;  // input edge id
+};
+
+__device__ __forceinline__ WinS load_wins(const StepParams &P, int32_t wb, int32_t p1, int lane) {
+    WinS m{-1, -1, -1, -1, 0};
+    const int32_t q = wb + lane;
+    if (q < p1) {
+        m.g = P.gsrc[q];
+        m.s = P.psrc[q];
+        m.d = P.pdst[q];
+        m.o = P.orow[q];
+        m.e = (uint32_t)P.peid[q];
+    }
+    return m;
+}
+
+template <int W, int U>
+__device__ __forceinline__ void gather_step(const StepParams &P, const WinS &cw, const WinS &nw,
+                                            int32_t wb, int32_t pb, int32_t p1, bool act,
+                                            bool from_x, int lane, uint32_t (&g)[U][W]) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int32_t q = pb + u;
+        int32_t rg = -1, rs = -1;
+        if (q < p1) {
+            const int32_t i = q - wb;  // uniform
+            rg = (i < 64) ? __builtin_amdgcn_readlane(cw.g, i) : __builtin_amdgcn_readlane(nw.g, i - 64);
+            rs = (i < 64) ? __builtin_amdgcn_readlane(cw.s, i) : __builtin_amdgcn_readlane(nw.s, i - 64);
+        }
+        const int32_t r = from_x ? rs : rg;
+        if (r >= 0 && act) {
+            load_row<W>(from_x ? P.xt : P.sin, r, P.rowb, lane, g[u]);
+        } else {
+#pragma unroll
+            for (int w = 0; w < W; ++w) g[u][w] = 0;
+        }
+    }
+}
+
+template <int W>
+__global__ void __launch_bounds__(1024) k_step(StepParams P) {
+    constexpr int U = (W == 4) ? 4 : kU;  // edges per batch (register budget)
+    __shared__ __attribute__((aligned(16))) uint8_t lds[kLdsBytes];
+    {
+        const uint4 *src = (const uint4 *)P.lds_image;
+        uint4 *dst = (uint4 *)lds;
+        for (int i = threadIdx.x; i < kLdsBytes / 16; i += blockDim.x) dst[i] = src[i];
+    }
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63;
+    StepLane L{0, 0, 0};
+    if (lane < P.lanes) L = P.tab[lane];
+    const bool act = (L.flags & kLaneActive) != 0;
+    const bool from_x = (L.flags & kLaneFromX) != 0;
+    const bool accm = (L.flags & kLaneAcc) != 0;
+    const int rowd = P.rowb >> 2;
+    const uint32_t lanebits = (uint32_t)(lane & 31) << 2;
+    const uint32_t xbase = (uint32_t)kExpBase + lanebits;
+    const uint32_t zc = (uint32_t)kExpBase + ((uint32_t)kClampRow << 7) + lanebits;
+    const uint32_t epoch = __hip_atomic_load(&P.ctl->epoch, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT) & 0x3FFFFFFFu;
+    uint32_t fin[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) fin[w] = 0;
+
+    uint32_t tk = 0;
+    if (lane == 0) tk = atomicAdd(&P.ctl->ticket, 1u);
+    tk = __builtin_amdgcn_readfirstlane(__shfl(tk, 0));
+    for (;;) {
+        const int32_t tile = (int32_t)tk;
+        if (tile >= P.ntiles) break;
+        const int32_t p0 = P.tile_p0[tile], p1 = P.tile_p0[tile + 1];
+        const int32_t pubslot = P.tile_pub[tile], lbslot = P.tile_lb[tile];
+        const bool cont = lbslot >= 0;
+
+        int32_t wb = p0;
+        WinS cw = load_wins(P, wb, p1, lane);
+        WinS nw = load_wins(P, wb + 64, p1, lane);
+
+        const int32_t d0 = __builtin_amdgcn_readfirstlane(cw.d);
+        int32_t cur_dst = -1, nxt_dst = d0;
+        uint32_t lx7[4 * W], acc[W], xn[W];
+        if (act) {
+            load_row<W>(P.xt, d0, P.rowb, lane, xn);
+        } else {
+#pragma unroll
+            for (int w = 0; w < W; ++w) xn[w] = 0;
+        }
+#pragma unroll
+        for (int w = 0; w < W; ++w) acc[w] = 0;
+#pragma unroll
+        for (int i = 0; i < 4 * W; ++i) lx7[i] = kZero7;
+
+        auto process = [&](const uint32_t (&g)[U][W], int32_t pb) {
+            const int nb = min(U, p1 - pb);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (u >= nb) break;
+                const int32_t p = pb + u;
+                const int32_t i = p - wb;
+                const int32_t d = __builtin_amdgcn_readlane(cw.d, i);
+                if (d != cur_dst) {
+                    if (d != nxt_dst && act) load_row<W>(P.xt, d, P.rowb, lane, xn);
+#pragma unroll
+                    for (int w = 0; w < W; ++w) {
+                        lx7[4 * w + 0] = lds32(lds, log_addr<0>(lanebits, xn[w])) + xbase;
+                        lx7[4 * w + 1] = lds32(lds, log_addr<1>(lanebits, xn[w])) + xbase;
+                        lx7[4 * w + 2] = lds32(lds, log_addr<2>(lanebits, xn[w])) + xbase;
+                        lx7[4 * w + 3] = lds32(lds, log_addr<3>(lanebits, xn[w])) + xbase;
+                        acc[w] = 0;
+                    }
+                    cur_dst = d;
+                    uint64_t later = __ballot(cw.d != d && cw.d >= 0 && lane > i);
+                    int32_t nd = -1;
+                    if (later) {
+                        nd = __builtin_amdgcn_readlane(cw.d, __ffsll((long long)later) - 1);
+                    } else {
+                        uint64_t l2 = __ballot(nw.d != d && nw.d >= 0);
+                        if (l2) nd = __builtin_amdgcn_readlane(nw.d, __ffsll((long long)l2) - 1);
+                    }
+                    nxt_dst = nd;
+                    if (nd >= 0 && act) load_row<W>(P.xt, nd, P.rowb, lane, xn);
+                }
+                // y_{e, level-1} of this lane's query
+                const uint32_t eid = __builtin_amdgcn_readlane(cw.e, i);
+                const uint32_t y = fp8(L.seed, 1u, L.ylevel, eid);
+                const uint32_t ly7 = lds32(lds, (y << 8) | lanebits);
+                uint32_t c[W];
+#pragma unroll
+                for (int w = 0; w < W; ++w) c[w] = mul4(lds, lanebits, g[u][w], &lx7[4 * w], ly7, zc);
+                if (accm) {
+#pragma unroll
+                    for (int w = 0; w < W; ++w) fin[w] ^= c[w];
+                } else {
+#pragma unroll
+                    for (int w = 0; w < W; ++w) acc[w] ^= c[w];
+                }
+                const int32_t orow = __builtin_amdgcn_readlane(cw.o, i);
+                if (orow >= 0 && act && !accm) store_row<W>(P.sout, orow, P.rowb, lane, acc);
+            }
+            if (pb + U - wb == 64 && pb + U < p1) {
+                wb += 64;
+                cw = nw;
+                nw = load_wins(P, wb + 64, p1, lane);
+            }
+        };
+
+        uint32_t ga[U][W], gb[U][W];
+        gather_step<W, U>(P, cw, nw, wb, p0, p1, act, from_x, lane, ga);
+        for (int32_t pb = p0; pb < p1;) {
+            gather_step<W, U>(P, cw, nw, wb, pb + U, p1, act, from_x, lane, gb);
+            process(ga, pb);
+            pb += U;
+            if (pb >= p1) break;
+            gather_step<W, U>(P, cw, nw, wb, pb + U, p1, act, from_x, lane, ga);
+            process(gb, pb);
+            pb += U;
+        }
+
+        if (lane < P.lanes) {
+            if (pubslot >= 0)
+                publish<W>(P.pub, pubslot, rowd, P.lanes, lane, cont ? kAgg : kInc, epoch, acc);
+            if (cont) {
+                uint32_t carry[W];
+                lookback<W>(P.pub, lbslot, rowd, P.lanes, lane, epoch, P.ctl, carry);
+                if (pubslot >= 0) {
+                    uint32_t inc[W];
+#pragma unroll
+                    for (int w = 0; w < W; ++w) inc[w] = acc[w] ^ carry[w];
+                    publish<W>(P.pub, pubslot, rowd, P.lanes, lane, kInc, epoch, inc);
+                }
+                if (act && !accm) {
+                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+                    for (int32_t p = p0; p < p1; ++p) {
+                        const int32_t orow = P.orow[p];
+                        if (orow >= 0) {
+                            uint32_t v[W];
+                            load_row<W>(P.sout, orow, P.rowb, lane, v);
+#pragma unroll
+                            for (int w = 0; w < W; ++w) v[w] ^= carry[w];
+                            store_row<W>(P.sout, orow, P.rowb, lane, v);
+                        }
+                    }
+                }
+            }
+        }
+        uint32_t tk_next = 0;
+        if (lane == 0) tk_next = atomicAdd(&P.ctl->ticket, 1u);
+        tk = __builtin_amdgcn_readfirstlane(__shfl(tk_next, 0));
+    }
+
+    if (act && accm) {
+#pragma unroll
+        for (int w = 0; w < W; ++w)
+            if (fin[w]) atomicXor(&P.fin[lane * W + w], fin[w]);
+    }
+}
+
 QuerySlots make_slots(const Graph &G, const int32_t *M, int32_t k) {
     TPM_REQUIRE(M != nullptr, "multiset must not be NULL");
     TPM_REQUIRE(k >= 1 && k <= 16, "k must be in [1, 16]");
@@ -584,6 +809,12 @@ void launch_level_w(int W, bool fin, const Graph &G, const LevelParams &P, hipSt
     if (W == 4) fin ? launch_level<4, true>(G, P, st) : launch_level<4, false>(G, P, st);
     else if (W == 2) fin ? launch_level<2, true>(G, P, st) : launch_level<2, false>(G, P, st);
     else fin ? launch_level<1, true>(G, P, st) : launch_level<1, false>(G, P, st);
+}
+
+void launch_step_w(int W, const Graph &G, const StepParams &P, hipStream_t st) {
+    if (W == 4) hipLaunchKernelGGL((k_step<4>), dim3((unsigned)G.num_cu), dim3(1024), 0, st, P);
+    else if (W == 2) hipLaunchKernelGGL((k_step<2>), dim3((unsigned)G.num_cu), dim3(1024), 0, st, P);
+    else hipLaunchKernelGGL((k_step<1>), dim3((unsigned)G.num_cu), dim3(1024), 0, st, P);
 }
 
 int pick_chunk(const Graph &G, int32_t k, int32_t requested) {
@@ -670,7 +901,7 @@ void run_sieve_impl(const Graph &G, const SieveRequest &req, SieveResult &res, b
         }
         for (int64_t base = 0; base < npts; base += rowb) {
             k_xt<<<grid_for((int64_t)G.n * ((rowb + 15) / 16)), 256, 0, st>>>(
-                G.n, k, rowb, (uint32_t)base, z.as<uint8_t>(), xt.as<uint8_t>());
+                G.n, k, rowb, rowb, 0, (uint32_t)base, z.as<uint8_t>(), xt.as<uint8_t>());
             for (int l = 2; l <= k; ++l) {
                 const bool fin = (l == k);
                 LevelParams P{};
@@ -750,6 +981,91 @@ void run_sieve_loc_all(const Graph &G, const SieveRequest &req, SieveResult &res
         TPM_HIP(hipMemcpy(peid.data(), G.peid, sizeof(int32_t) * G.m, hipMemcpyDeviceToHost));
         for (int64_t p = 0; p < G.m; ++p) loc_by_edge[peid[p]] = bypos[p];
     }
+}
+
+// ---------------------------------------------------------------- multi-query rows
+void multi_init(const Graph &G, MultiRow &row, hipStream_t st) {
+    TPM_REQUIRE(row.ws != nullptr, "multi-query row without workspace");
+    TPM_REQUIRE(row.W == 1 || row.W == 2 || row.W == 4, "W must be 1, 2 or 4");
+    TPM_REQUIRE(row.lanes >= 1 && row.lanes <= 64, "lanes must be in [1, 64]");
+    Workspace &ws = *row.ws;
+    const int rowb = row.rowb(), rowd = rowb / 4;
+    ws.ctl.alloc(sizeof(Ctl), st);
+    TPM_HIP(hipMemsetAsync(ws.ctl.p, 0, sizeof(Ctl), st));
+    ws.z.alloc((size_t)G.n * 16, st);
+    ws.xt.alloc((size_t)G.n * rowb, st);
+    ws.s0.alloc((size_t)std::max<int64_t>(1, G.R) * rowb, st);
+    ws.s1.alloc((size_t)std::max<int64_t>(1, G.R) * rowb, st);
+    if (G.nslots) {
+        ws.pub.alloc((size_t)G.nslots * rowd * 8, st);
+        TPM_HIP(hipMemsetAsync(ws.pub.p, 0, (size_t)G.nslots * rowd * 8, st));
+    }
+    ws.pp.alloc((size_t)rowb, st);
+    TPM_HIP(hipMemsetAsync(ws.pp.p, 0, (size_t)rowb, st));
+    row.parity = 0;
+}
+
+void multi_prepare(const Graph &G, MultiRow &row, int lane0, int npts, const int32_t *M, int32_t k,
+                   uint64_t seed, uint32_t base, const uint8_t *vertex_mask, hipStream_t st) {
+    TPM_REQUIRE(k >= 2, "multi-query rows need k >= 2");
+    TPM_REQUIRE(npts % (4 * row.W) == 0 && npts > 0, "group size must be whole lanes");
+    TPM_REQUIRE(lane0 >= 0 && lane0 + npts / (4 * row.W) <= row.lanes, "group outside the row");
+    TPM_REQUIRE(vertex_mask == nullptr, "vertex masks are not supported in multi-query rows");
+    Workspace &ws = *row.ws;
+    QuerySlots qs = make_slots(G, M, k);
+    const int rowb = row.rowb();
+    const int col = lane0 * 4 * row.W;
+    k_z<<<grid_for(G.n), 256, 0, st>>>(G.n, k, G.color, qs, nullptr, seed, ws.z.as<uint8_t>());
+    k_xt<<<grid_for((int64_t)G.n * ((npts + 15) / 16)), 256, 0, st>>>(
+        G.n, k, npts, rowb, col, base, ws.z.as<uint8_t>(), ws.xt.as<uint8_t>());
+    TPM_HIP(hipMemsetAsync(ws.pp.as<uint8_t>() + col, 0, (size_t)npts, st));
+    TPM_HIP(hipGetLastError());
+}
+
+void multi_step(const Graph &G, MultiRow &row, const StepLane *lanes, hipStream_t st) {
+    if (G.m == 0) return;
+    Workspace &ws = *row.ws;
+    StepParams P{};
+    P.psrc = G.psrc;
+    P.gsrc = G.gsrc;
+    P.pdst = G.pdst;
+    P.peid = G.peid;
+    P.orow = G.orow;
+    P.xt = ws.xt.as<uint8_t>();
+    P.sin = (row.parity ? ws.s1 : ws.s0).as<uint8_t>();
+    P.sout = (row.parity ? ws.s0 : ws.s1).as<uint8_t>();
+    P.tile_p0 = G.tile_p0;
+    P.tile_pub = G.tile_pub;
+    P.tile_lb = G.tile_lb;
+    P.ntiles = (int32_t)G.ntiles;
+    P.pub = ws.pub.as<unsigned long long>();
+    P.ctl = ws.ctl.as<Ctl>();
+    P.fin = ws.pp.as<uint32_t>();
+    P.lds_image = G.lds_image;
+    P.rowb = row.rowb();
+    P.lanes = row.lanes;
+    for (int i = 0; i < 64; ++i) P.tab[i] = (i < row.lanes) ? lanes[i] : StepLane{0, 0, 0};
+    k_prep<<<1, 1, 0, st>>>(ws.ctl.as<Ctl>(), 1);
+    {
+        ProfileScope prof(st, 3, 0, row.rowb());
+        launch_step_w(row.W, G, P, st);
+    }
+    TPM_HIP(hipGetLastError());
+    row.parity ^= 1;
+}
+
+void multi_read(const Graph &G, MultiRow &row, int lane0, int nl, uint8_t *out, hipStream_t st) {
+    (void)G;
+    const int lb = 4 * row.W;
+    Ctl hctl{};
+    TPM_HIP(hipMemcpyAsync(out, row.ws->pp.as<uint8_t>() + lane0 * lb, (size_t)nl * lb,
+                           hipMemcpyDeviceToHost, st));
+    TPM_HIP(hipMemcpyAsync(&hctl, row.ws->ctl.p, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+    TPM_HIP(hipStreamSynchronize(st));
+    profile_collect();
+    if (hctl.err)
+        throw Error{TPM_EDEVICE, "step kernel reported a look-back failure (code " +
+                                     std::to_string(hctl.err) + ")"};
 }
 
 }  // namespace tpm

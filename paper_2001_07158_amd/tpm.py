@@ -326,3 +326,37 @@ class Graph:
 
     def __del__(self):
         self.close()
+
+
+class Server:
+    """Owner of a serving loop over a resident graph (tpm_server_*)."""
+
+    def __init__(self, graph: Graph, state_bytes=0, max_lanes=0, extract_paths=0):
+        self.graph = graph
+        self.h = tpm_server_create(graph.h, state_bytes, max_lanes, extract_paths)
+
+    def submit(self, multiset, seed, want_path=0) -> int:
+        return tpm_server_submit(self.h, multiset, seed, want_path)
+
+    def poll(self, max_results=64):
+        return tpm_server_poll(self.h, max_results)
+
+    def drain(self, n, timeout_s=600.0):
+        """Poll until n results arrived (or raise on timeout)."""
+        import time
+        got, t0 = [], time.monotonic()
+        while len(got) < n:
+            got += self.poll(256)
+            if len(got) < n:
+                if time.monotonic() - t0 > timeout_s:
+                    raise TimeoutError(f"{len(got)} of {n} results after {timeout_s}s")
+                time.sleep(0.001)
+        return got
+
+    def close(self):
+        if getattr(self, "h", None):
+            tpm_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
