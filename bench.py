@@ -56,8 +56,15 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="k10", choices=["k10", "k5", "tiny"])
+    ap.add_argument("--workload", default="k10", choices=["k10", "k5", "tiny", "batched", "serving"])
+    ap.add_argument("--queries", type=int, default=0,
+                    help="batched/serving: number of queries (default 256 / 120)")
+    ap.add_argument("--scale", type=float, default=1.0,
+                    help="batched/serving: shrink n and m (1.0 = the named workload)")
+    ap.add_argument("--load", type=float, default=0.8,
+                    help="serving: arrival rate as a fraction of the measured capacity")
     ap.add_argument("--chunk", type=int, default=0)
+    ap.add_argument("--tile-edges", type=int, default=0, help="work tile size of the index (0 = default)")
     ap.add_argument("--cpu-points", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -78,6 +85,11 @@ def main() -> int:
     from paper_2001_07158_amd import tpm
     from synth import CONFIGS, make_config_graph, make_config_query
 
+    if args.workload == "batched":
+        return bench_batched(args)
+    if args.workload == "serving":
+        return bench_serving(args)
+
     cfg = CONFIGS[args.workload]
     t_gen = time.perf_counter()
     g = make_config_graph(args.workload)
@@ -88,7 +100,7 @@ def main() -> int:
           f"{t_gen:.1f}s)", file=sys.stderr, flush=True)
 
     t_idx = time.perf_counter()
-    G = tpm.Graph.from_temporal(g)
+    G = tpm.Graph.from_temporal(g, tile_edges=args.tile_edges)
     st = G.stats()
     t_idx = time.perf_counter() - t_idx
     print(f"# index built in {t_idx:.2f}s: rows={st['rows']} tiles={st['tiles']} "
@@ -214,6 +226,131 @@ def main() -> int:
     print(json.dumps(line), flush=True)
     G.close()
     return 0
+
+
+def _log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def bench_batched(args) -> int:
+    """256 queries of uneven size k ~ U{3..10} against one resident Chung-Lu graph
+    (n = 2e6, m = 1e8): one query at a time through tpm_sieve versus tpm_batch_run;
+    every batched total must equal the same query run alone."""
+    import numpy as np
+    import torch
+    from paper_2001_07158_amd import tpm
+    from synth import CONFIGS, make_config_graph, make_config_query
+
+    cfg = CONFIGS["batched"]
+    nq = args.queries or cfg["nq"]
+    g = make_config_graph("batched", scale=args.scale)
+    qs = [{"multiset": [int(c) for c in make_config_query("batched", i)],
+           "seed": 20010715 + 7919 * i} for i in range(nq)]
+    ks = [len(q["multiset"]) for q in qs]
+    _log(f"# batched: n={g.n} m={g.m} queries={nq} k-histogram={np.bincount(ks).tolist()}")
+    G = tpm.Graph.from_temporal(g)
+    st = G.stats()
+    # warm-up: one query of each size both ways
+    warm = [qs[ks.index(k)] for k in sorted(set(ks))]
+    for q in warm:
+        G.sieve(q["multiset"], q["seed"])
+    G.batch(warm)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    alone = [G.sieve(q["multiset"], q["seed"])[1] for q in qs]
+    torch.cuda.synchronize()
+    t_alone = time.perf_counter() - t0
+    _log(f"# one-at-a-time: {t_alone:.2f}s")
+    t0 = time.perf_counter()
+    res = G.batch(qs)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    _log(f"# batched: {t_batch:.2f}s")
+    same = all(r["total"] == a for r, a in zip(res, alone))
+    units = float(sum(g.m * k * (1 << k) for k in ks))
+    line = {
+        "metric": "batched queries/s (256 queries, k ~ U{3..10}), GF(2^8) sieve",
+        "value": nq / t_batch, "unit": "queries/s", "n_gpus": 1, "higher_is_better": True,
+        "one_at_a_time_qps": nq / t_alone, "speedup_vs_one_at_a_time": t_alone / t_batch,
+        "edge_updates_per_s_batched": units / t_batch,
+        "edge_updates_per_s_one_at_a_time": units / t_alone,
+        "all_totals_equal_alone": same, "found": int(sum(r["found"] for r in res)),
+        "dtype": "u8", "data": "synthetic",
+        "config": {"workload": f"batched: directed Chung-Lu n={g.n} m={g.m} beta=2.5 "
+                               f"t=[1,{cfg['t']}] q={cfg['q']}, {nq} queries k~U{{3..10}}",
+                   "rows_stored": st["rows"]},
+    }
+    print(json.dumps(line), flush=True)
+    G.close()
+    return 0 if same else 1
+
+
+def bench_serving(args) -> int:
+    """A Poisson stream of queries (k ~ U{3..10}) against a resident Chung-Lu graph
+    (n = 1e7, m = 1e9) through the serving loop: capacity from a closed-loop burst,
+    then arrivals at `load` x capacity; queries/s and p50/p99 latency (submit to
+    result, host clock)."""
+    import numpy as np
+    from paper_2001_07158_amd import tpm
+    from synth import CONFIGS, make_config_graph, make_config_query
+
+    cfg = CONFIGS["serving"]
+    nq = args.queries or 120
+    t_gen = time.perf_counter()
+    g = make_config_graph("serving", scale=args.scale)
+    _log(f"# serving: n={g.n} m={g.m} generated in {time.perf_counter() - t_gen:.1f}s")
+    G = tpm.Graph.from_temporal(g)
+    st = G.stats()
+    _log(f"# index: rows={st['rows']} tiles={st['tiles']}")
+    qs = [{"multiset": [int(c) for c in make_config_query("serving", i)],
+           "seed": 90001 + 7919 * i} for i in range(nq)]
+    srv = tpm.Server(G)
+    # capacity: a closed-loop burst of the first third of the stream
+    nb = max(8, nq // 3)
+    t0 = time.perf_counter()
+    for q in qs[:nb]:
+        srv.submit(q["multiset"], q["seed"])
+    burst = srv.drain(nb, timeout_s=3000)
+    cap = nb / (time.perf_counter() - t0)
+    _log(f"# capacity {cap:.3f} queries/s from a burst of {nb}")
+    # open loop: Poisson arrivals at load x capacity for the rest of the stream
+    rate = args.load * cap
+    rng = np.random.default_rng(17)
+    gaps = rng.exponential(1.0 / rate, nq - nb)
+    t_start = time.perf_counter()
+    next_t = t_start
+    results = []
+    for i, q in enumerate(qs[nb:]):
+        next_t += gaps[i]
+        while time.perf_counter() < next_t:
+            results += srv.poll(256)
+            time.sleep(0.0005)
+        srv.submit(q["multiset"], q["seed"])
+    results += srv.drain(nq - nb - len(results), timeout_s=3000)
+    t_total = time.perf_counter() - t_start
+    srv.close()
+    lat = np.array([r["t_done_ms"] - r["t_submit_ms"] for r in results])
+    # spot check: a few streamed results against the same query run alone
+    by_ticket = {r["ticket"]: r for r in results}
+    check = sorted(by_ticket)[:4]
+    same = True
+    for t in check:
+        q = qs[nb + (t - nb - 1)]
+        same &= by_ticket[t]["total"] == G.sieve(q["multiset"], q["seed"])[1]
+    line = {
+        "metric": "serving queries/s and p50/p99 latency (Poisson arrivals), GF(2^8) sieve",
+        "value": len(results) / t_total, "unit": "queries/s", "n_gpus": 1, "higher_is_better": True,
+        "latency_ms_p50": float(np.percentile(lat, 50)), "latency_ms_p99": float(np.percentile(lat, 99)),
+        "capacity_qps_closed_loop": cap, "arrival_rate_qps": rate, "streamed_queries": len(results),
+        "burst_queries": nb, "found": int(sum(r["found"] for r in results + burst)),
+        "spot_check_equal_alone": bool(same), "dtype": "u8", "data": "synthetic",
+        "config": {"workload": f"serving: directed Chung-Lu n={g.n} m={g.m} beta=2.5 "
+                               f"t=[1,{cfg['t']}] q={cfg['q']}, stream prefix of {nq} queries "
+                               f"k~U{{3..10}}", "rows_stored": st["rows"]},
+    }
+    print(json.dumps(line), flush=True)
+    G.close()
+    return 0 if same else 1
 
 
 if __name__ == "__main__":

@@ -62,7 +62,7 @@ typedef int32_t tpm_status;
 typedef struct tpm_graph tpm_graph;
 
 /* Work-tile shape of the in-edge index, fixed at graph creation.
- * tile_edges: most CSR positions per tile (1..4096, default 256).  In-lists no
+ * tile_edges: most CSR positions per tile (1..4096, default 1024).  In-lists no
  *             longer than a tile are packed whole; longer ones are cut into pieces
  *             that add the running value of their predecessors by look-back.
  * tile_held:  reserved, must be 0.  Zero fields take the default. */

@@ -190,7 +190,7 @@ void build_graph(Graph &G, int32_t n, int64_t m, const int32_t *src, const int32
     TPM_REQUIRE(num_colors >= 1, "num_colors must be >= 1");
     TPM_REQUIRE(m == 0 || (src && dst && tau), "edge arrays must not be NULL");
     TPM_REQUIRE(color != nullptr, "color must not be NULL");
-    int T = 256;
+    int T = 1024;
     if (opt && opt->tile_edges) T = opt->tile_edges;
     TPM_REQUIRE(T >= 1 && T <= 4096, "tile_edges must be in [1, 4096]");
     TPM_REQUIRE(!opt || opt->tile_held == 0, "tile_held is reserved and must be 0");

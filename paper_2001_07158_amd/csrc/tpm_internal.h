@@ -114,7 +114,7 @@ struct Graph {
     int64_t m = 0;
     int32_t q = 0;
     int32_t tmax = 0;
-    int32_t tile_edges = 256;
+    int32_t tile_edges = 1024;
     int64_t R = 0;        // stored rows per level
     int64_t ntiles = 0;
     int64_t nslots = 0;

@@ -97,6 +97,7 @@ struct StepParams {
     uint32_t *fin;               // per-point accumulators of groups at their last level
     const uint8_t *lds_image;
     int32_t rowb, lanes;
+    int32_t shared_level;        // 1: every active lane has tab[0].ylevel
     StepLane tab[64];            // per lane: seed, level, role
 };
 
@@ -577,11 +578,14 @@ inline unsigned grid_for(int64_t work, int block = 256) {
 // ---------------------------------------------------------------------------------
 struct WinS {
     int32_t g, s, d, o;
-    uint32_t e;  // input edge id
+    uint32_t e;         // input edge id
+    uint32_t hlo, hhi;  // inner fingerprint hash of (y, ylevel, e) when every group
+                        // of the step shares one level (else unused)
 };
 
-__device__ __forceinline__ WinS load_wins(const StepParams &P, int32_t wb, int32_t p1, int lane) {
-    WinS m{-1, -1, -1, -1, 0};
+__device__ __forceinline__ WinS load_wins(const StepParams &P, int32_t wb, int32_t p1, int lane,
+                                          bool shared_level, uint32_t ylevel) {
+    WinS m{-1, -1, -1, -1, 0, 0, 0};
     const int32_t q = wb + lane;
     if (q < p1) {
         m.g = P.gsrc[q];
@@ -589,6 +593,11 @@ __device__ __forceinline__ WinS load_wins(const StepParams &P, int32_t wb, int32
         m.d = P.pdst[q];
         m.o = P.orow[q];
         m.e = (uint32_t)P.peid[q];
+        if (shared_level) {
+            const uint64_t h = mix64((1ull << 56) ^ ((uint64_t)ylevel << 32) ^ (uint64_t)m.e);
+            m.hlo = (uint32_t)h;
+            m.hhi = (uint32_t)(h >> 32);
+        }
     }
     return m;
 }
@@ -633,6 +642,9 @@ __global__ void __launch_bounds__(1024) k_step(StepParams P) {
     const bool act = (L.flags & kLaneActive) != 0;
     const bool from_x = (L.flags & kLaneFromX) != 0;
     const bool accm = (L.flags & kLaneAcc) != 0;
+    // one level for every active group: the inner half of y's fingerprint is shared
+    const uint32_t lvl0 = P.tab[0].ylevel;
+    const bool shared_level = P.shared_level != 0;
     const int rowd = P.rowb >> 2;
     const uint32_t lanebits = (uint32_t)(lane & 31) << 2;
     const uint32_t xbase = (uint32_t)kExpBase + lanebits;
@@ -654,8 +666,8 @@ __global__ void __launch_bounds__(1024) k_step(StepParams P) {
         const bool cont = lbslot >= 0;
 
         int32_t wb = p0;
-        WinS cw = load_wins(P, wb, p1, lane);
-        WinS nw = load_wins(P, wb + 64, p1, lane);
+        WinS cw = load_wins(P, wb, p1, lane, shared_level, lvl0);
+        WinS nw = load_wins(P, wb + 64, p1, lane, shared_level, lvl0);
 
         const int32_t d0 = __builtin_amdgcn_readfirstlane(cw.d);
         int32_t cur_dst = -1, nxt_dst = d0;
@@ -702,8 +714,16 @@ __global__ void __launch_bounds__(1024) k_step(StepParams P) {
                     if (nd >= 0 && act) load_row<W>(P.xt, nd, P.rowb, lane, xn);
                 }
                 // y_{e, level-1} of this lane's query
-                const uint32_t eid = __builtin_amdgcn_readlane(cw.e, i);
-                const uint32_t y = fp8(L.seed, 1u, L.ylevel, eid);
+                uint32_t y;
+                if (shared_level) {
+                    const uint64_t inner =
+                        ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(cw.hhi, i) << 32) |
+                        (uint64_t)(uint32_t)__builtin_amdgcn_readlane(cw.hlo, i);
+                    y = (uint32_t)(mix64(L.seed ^ inner) & 0xFFu);
+                } else {
+                    const uint32_t eid = __builtin_amdgcn_readlane(cw.e, i);
+                    y = fp8(L.seed, 1u, L.ylevel, eid);
+                }
                 const uint32_t ly7 = lds32(lds, (y << 8) | lanebits);
                 uint32_t c[W];
 #pragma unroll
@@ -721,7 +741,7 @@ __global__ void __launch_bounds__(1024) k_step(StepParams P) {
             if (pb + U - wb == 64 && pb + U < p1) {
                 wb += 64;
                 cw = nw;
-                nw = load_wins(P, wb + 64, p1, lane);
+                nw = load_wins(P, wb + 64, p1, lane, shared_level, lvl0);
             }
         };
 
@@ -1045,6 +1065,16 @@ void multi_step(const Graph &G, MultiRow &row, const StepLane *lanes, hipStream_
     P.rowb = row.rowb();
     P.lanes = row.lanes;
     for (int i = 0; i < 64; ++i) P.tab[i] = (i < row.lanes) ? lanes[i] : StepLane{0, 0, 0};
+    // the shared inner hash needs one level for all active lanes, stored in tab[0]
+    int32_t lvl = -1;
+    bool same = true;
+    for (int i = 0; i < row.lanes; ++i)
+        if (lanes[i].flags & kLaneActive) {
+            if (lvl < 0) lvl = (int32_t)lanes[i].ylevel;
+            else same &= (int32_t)lanes[i].ylevel == lvl;
+        }
+    P.shared_level = (same && lvl >= 0) ? 1 : 0;
+    if (P.shared_level) P.tab[0].ylevel = (uint32_t)lvl;
     k_prep<<<1, 1, 0, st>>>(ws.ctl.as<Ctl>(), 1);
     {
         ProfileScope prof(st, 3, 0, row.rowb());
