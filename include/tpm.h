@@ -85,12 +85,16 @@ typedef struct {
     int64_t segments;      /* non-empty in-lists */
 } tpm_graph_stats;
 
-/* Per-call tuning.  chunk: sieve points per pass (power of two, 4..1024; 0 =
- * min(2^k, 1024)).  waves_per_cu: reserved (0).  Every admissible setting gives
- * bit-identical results. */
+/* Per-call tuning.  Every admissible setting gives bit-identical results.
+ * chunk:     sieve points per pass (power of two, 4..1024; 0 = min(2^k, 1024));
+ *            for tpm_batch_run the row width (256, 512 or 1024; 0 = 1024).
+ * use_graph: tpm_batch_run only: 1 = each pass replays its level launches from a
+ *            HIP graph captured once per row shape (lane tables live in device
+ *            memory), on a stream the call creates; 0 = plain launches on the
+ *            null stream. */
 typedef struct {
     int32_t chunk;
-    int32_t waves_per_cu;
+    int32_t use_graph;
 } tpm_tuning;
 
 /* ---------------------------------------------------------------- graph --- */
@@ -107,6 +111,31 @@ tpm_status tpm_graph_create(int32_t n, int64_t m, const int32_t *src, const int3
 tpm_status tpm_graph_create_ex(int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
                                const int32_t *tau, const int32_t *color, int32_t num_colors,
                                uint32_t flags, const tpm_graph_options *opt, tpm_graph **out);
+
+/* Rebuild the work tiles with at most tile_edges (1..4096) CSR positions each; the
+ * sieve's results do not depend on it.  Waits for the device and must not run
+ * while another call uses the same graph.  Errors: TPM_EINVAL, TPM_ENOMEM,
+ * TPM_EDEVICE (the old tiles are kept on error). */
+tpm_status tpm_graph_retile(tpm_graph *g, int32_t tile_edges);
+
+/* Autotuner for the sieve on one graph (the launch shape is this project's, not
+ * the paper's).  Times one chunk of a probe query of size k (colours 0, 1, ...,
+ * taken modulo num_colors; seed `seed`) for every candidate pair of tile size
+ * {256, 512, 1024, 2048} and chunk {256, 512, 1024} (chunks above 2^k dropped; for
+ * 2^k < 256 the chunk is 2^k), after one untimed run per pair, and checks that
+ * every candidate gives the same per-point bytes.  The fastest tile size is applied
+ * to the graph (as tpm_graph_retile) and reported with the fastest chunk; pass
+ * that chunk in tpm_tuning.  Same concurrency rule as tpm_graph_retile.
+ * Errors: TPM_EINVAL (k outside 2..16), TPM_EDEVICE (a candidate disagreed). */
+typedef struct {
+    int32_t tile_edges;      /* chosen and applied */
+    int32_t chunk;           /* chosen */
+    int32_t ncand;           /* candidates timed (<= 12) */
+    int32_t cand_tile[12];
+    int32_t cand_chunk[12];
+    double cand_rate[12];    /* edge-level-point updates per second: m (k-1) C / time */
+} tpm_autotune_report;
+tpm_status tpm_autotune(tpm_graph *g, int32_t k, uint64_t seed, tpm_autotune_report *out);
 
 /* Free a graph and everything it owns.  NULL is accepted. */
 void tpm_graph_destroy(tpm_graph *g);

@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <chrono>
 #include <cstring>
 #include <mutex>
 #include <set>
@@ -258,6 +259,11 @@ tpm_status extract_path(const Graph &G, const int32_t *M, int32_t k, uint64_t se
     return TPM_OK;
 }
 
+static double now_ms_api() {
+    using namespace std::chrono;
+    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
 }  // namespace tpm
 
 using namespace tpm;
@@ -320,6 +326,80 @@ void tpm_graph_destroy(tpm_graph *g) {
     free_graph(g->G);
     if (prev >= 0 && prev != g->G.device) (void)hipSetDevice(prev);
     delete g;
+}
+
+tpm_status tpm_graph_retile(tpm_graph *g, int32_t tile_edges) {
+    return guarded([&]() -> tpm_status {
+        TPM_REQUIRE(g != nullptr, "graph must not be NULL");
+        DeviceScope ds(g->G.device);
+        retile_graph(g->G, tile_edges);
+        return TPM_OK;
+    });
+}
+
+tpm_status tpm_autotune(tpm_graph *g, int32_t k, uint64_t seed, tpm_autotune_report *out) {
+    return guarded([&]() -> tpm_status {
+        TPM_REQUIRE(g && out, "NULL argument");
+        TPM_REQUIRE(k >= 2 && k <= 16, "k must be in [2, 16]");
+        DeviceScope ds(g->G.device);
+        Graph &G = g->G;
+        std::memset(out, 0, sizeof(*out));
+        int32_t M[16];
+        for (int i = 0; i < k; ++i) M[i] = i % G.q;
+        const int64_t npts = int64_t(1) << k;
+        std::vector<int32_t> chunks;
+        if (npts < 256) chunks.push_back((int32_t)npts);
+        for (int32_t c : {256, 512, 1024})
+            if (c <= npts) chunks.push_back(c);
+        const int32_t tiles[4] = {256, 512, 1024, 2048};
+        const int32_t cmp = chunks.front();  // points every candidate computes
+        const int32_t orig_T = G.tile_edges;
+        std::vector<uint8_t> first;
+        double best = -1.0;
+        try {
+            for (int32_t T : tiles) {
+                retile_graph(G, T);
+                for (int32_t C : chunks) {
+                    SieveRequest req;
+                    req.multiset = M;
+                    req.k = k;
+                    req.seed = seed;
+                    req.chunk = C;
+                    req.max_chunks = 1;
+                    SieveResult res;
+                    run_sieve(G, req, res, nullptr);  // untimed: sizes the workspace
+                    const double t0 = now_ms_api();
+                    run_sieve(G, req, res, nullptr);
+                    const double ms = std::max(now_ms_api() - t0, 1e-6);
+                    if (first.empty()) {
+                        first.assign(res.per_point.begin(), res.per_point.begin() + cmp);
+                    } else if (!std::equal(first.begin(), first.end(), res.per_point.begin())) {
+                        throw Error{TPM_EDEVICE, "autotune candidates disagree (tile " +
+                                                     std::to_string(T) + ", chunk " +
+                                                     std::to_string(C) + ")"};
+                    }
+                    const double rate = (double)G.m * (double)(k - 1) * (double)C / (ms * 1e-3);
+                    const int i = out->ncand++;
+                    out->cand_tile[i] = T;
+                    out->cand_chunk[i] = C;
+                    out->cand_rate[i] = rate;
+                    if (rate > best) {
+                        best = rate;
+                        out->tile_edges = T;
+                        out->chunk = C;
+                    }
+                }
+            }
+            retile_graph(G, out->tile_edges);
+        } catch (...) {
+            try {
+                retile_graph(G, orig_T);
+            } catch (...) {
+            }
+            throw;
+        }
+        return TPM_OK;
+    });
 }
 
 tpm_status tpm_graph_stats_get(const tpm_graph *g, tpm_graph_stats *out) {

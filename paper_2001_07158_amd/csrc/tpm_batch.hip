@@ -55,6 +55,19 @@ tpm_status guarded2(F &&f) {
     }
 }
 
+struct OwnedStream {
+    hipStream_t s = nullptr;
+    OwnedStream() = default;
+    OwnedStream(const OwnedStream &) = delete;
+    OwnedStream &operator=(const OwnedStream &) = delete;
+    ~OwnedStream() {
+        if (s) {
+            (void)hipStreamSynchronize(s);
+            (void)hipStreamDestroy(s);
+        }
+    }
+};
+
 double now_ms() {
     using namespace std::chrono;
     return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
@@ -108,7 +121,13 @@ tpm_status tpm_batch_run(const tpm_graph *g, int32_t nq, const tpm_query *q, tpm
         const int max_pts = (tune && tune->chunk) ? tune->chunk : 1024;
         TPM_REQUIRE(max_pts >= 256 && max_pts <= 1024 && (max_pts & (max_pts - 1)) == 0,
                     "batch row width (chunk) must be 256, 512 or 1024");
-        hipStream_t st = nullptr;
+        TPM_REQUIRE(!tune || tune->use_graph == 0 || tune->use_graph == 1, "use_graph must be 0 or 1");
+        const bool use_graph = tune && tune->use_graph;
+        // graph replay needs a created stream; everything of this call runs on it
+        OwnedStream own;
+        if (use_graph) TPM_HIP(hipStreamCreateWithFlags(&own.s, hipStreamNonBlocking));
+        hipStream_t st = own.s;
+        std::map<std::pair<int, int>, std::unique_ptr<StepGraph>> graphs;
 
         // queries that fill a row on their own, or k = 1, take the single-query path
         std::map<int, std::vector<int32_t>> by_k;
@@ -140,13 +159,23 @@ tpm_status tpm_batch_run(const tpm_graph *g, int32_t nq, const tpm_query *q, tpm
                         const tpm_query &qq = q[ids[a + j]];
                         multi_prepare(G, row, j * lpg, gpts, qq.multiset, k, qq.seed, 0, nullptr, st);
                     }
-                    std::vector<StepLane> lanes((size_t)row.lanes);
+                    // lane tables of levels 2..k, 64 entries per level
+                    std::vector<StepLane> lanes((size_t)(k - 1) * 64, StepLane{0, 0, 0});
                     for (int l = 2; l <= k; ++l) {
                         uint32_t flags = kLaneActive | (l == 2 ? kLaneFromX : 0u) | (l == k ? kLaneAcc : 0u);
                         for (int j = 0; j < cnt; ++j)
                             for (int t = 0; t < lpg; ++t)
-                                lanes[(size_t)(j * lpg + t)] = {q[ids[a + j]].seed, (uint32_t)(l - 1), flags};
-                        multi_step(G, row, lanes.data(), st);
+                                lanes[(size_t)(l - 2) * 64 + (size_t)(j * lpg + t)] = {
+                                    q[ids[a + j]].seed, (uint32_t)(l - 1), flags};
+                    }
+                    if (use_graph) {
+                        multi_upload_tabs(row, lanes.data(), k - 1, st);
+                        auto &sg = graphs[{k, row.lanes}];
+                        if (!sg) sg.reset(new StepGraph);
+                        multi_steps_graph(G, row, k - 1, *sg, st);
+                    } else {
+                        for (int l = 2; l <= k; ++l)
+                            multi_step(G, row, lanes.data() + (size_t)(l - 2) * 64, st);
                     }
                     std::vector<uint8_t> pp((size_t)row.rowb());
                     multi_read(G, row, 0, row.lanes, pp.data(), st);

@@ -380,4 +380,44 @@ void build_graph(Graph &G, int32_t n, int64_t m, const int32_t *src, const int32
     cleanup_tmp();
 }
 
+void retile_graph(Graph &G, int32_t T) {
+    TPM_REQUIRE(T >= 1 && T <= 4096, "tile_edges must be in [1, 4096]");
+    if (T == G.tile_edges) return;
+    TPM_HIP(hipSetDevice(G.device));
+    std::vector<int32_t> tp0, tpub, tlb;
+    int64_t nslots = 0;
+    build_tiles(G.h_inptr, T, tp0, tpub, tlb, nslots);
+    const int64_t nt = (int64_t)tpub.size();
+    int64_t acct = 0;
+    int32_t *p0 = nullptr, *pb = nullptr, *lb = nullptr;
+    try {
+        p0 = dalloc<int32_t>(nt + 1, acct);
+        pb = dalloc<int32_t>(nt, acct);
+        lb = dalloc<int32_t>(nt, acct);
+        TPM_HIP(hipMemcpy(p0, tp0.data(), sizeof(int32_t) * tp0.size(), hipMemcpyHostToDevice));
+        if (nt) {
+            TPM_HIP(hipMemcpy(pb, tpub.data(), sizeof(int32_t) * tpub.size(), hipMemcpyHostToDevice));
+            TPM_HIP(hipMemcpy(lb, tlb.data(), sizeof(int32_t) * tlb.size(), hipMemcpyHostToDevice));
+        }
+    } catch (...) {
+        for (void *q : {(void *)p0, (void *)pb, (void *)lb})
+            if (q) (void)hipFree(q);
+        throw;
+    }
+    // the old tile arrays may still be read by work queued on other streams
+    TPM_HIP(hipDeviceSynchronize());
+    const int64_t old_bytes = (int64_t)sizeof(int32_t) * (2 * G.ntiles + 1);
+    for (int32_t **q : {&G.tile_p0, &G.tile_pub, &G.tile_lb}) {
+        if (*q) (void)hipFree(*q);
+    }
+    G.tile_p0 = p0;
+    G.tile_pub = pb;
+    G.tile_lb = lb;
+    G.ntiles = nt;
+    G.nslots = nslots;
+    G.h_tile_p0 = std::move(tp0);
+    G.tile_edges = T;
+    G.device_bytes += acct - old_bytes;
+}
+
 }  // namespace tpm

@@ -91,7 +91,7 @@ struct DBuf {
 
 // Device memory of one sieve call: level buffers, per-vertex rows, control words.
 struct Workspace {
-    DBuf ctl, z, xt, s0, s1, pub, pp, tot, mask, loc, pick;
+    DBuf ctl, z, xt, s0, s1, pub, pp, tot, mask, loc, pick, tabs;
 };
 
 // Workspaces of a graph: a call takes one (creating it if none is free) and
@@ -153,6 +153,9 @@ void build_graph(Graph &G, int32_t n, int64_t m, const int32_t *src, const int32
                  const int32_t *tau, const int32_t *color, int32_t num_colors, uint32_t flags,
                  const tpm_graph_options *opt);
 void free_graph(Graph &G);
+// Rebuilds the work tiles with at most T positions each (results do not depend on
+// T).  Waits for the device; must not overlap other calls on the same graph.
+void retile_graph(Graph &G, int32_t T);
 
 // ------------------------------------------------------------------ sieve
 struct SieveRequest {
@@ -167,6 +170,8 @@ struct SieveRequest {
     // localise over the contributing positions and pick the one with nonzero
     // localisation and the smallest input edge id
     bool want_pick = false;
+    // run only the first chunk of sieve points (timing probes); 0 = all chunks
+    int32_t max_chunks = 0;
 };
 
 struct SieveResult {
@@ -206,6 +211,26 @@ void multi_prepare(const Graph &G, MultiRow &row, int lane0, int npts, const int
                    uint64_t seed, uint32_t base, const uint8_t *vertex_mask, hipStream_t st);
 // One level for every lane group (lanes[i] for lane i; inactive lanes have flags 0).
 void multi_step(const Graph &G, MultiRow &row, const StepLane *lanes, hipStream_t st);
+// Device-resident lane tables: StepLane entries per step = 64 lanes + 1 header whose
+// ylevel is the level shared by every active lane and whose flags is 1 when there is
+// one (0 otherwise).
+constexpr int kTabStride = 65;
+// Copies the lane tables of nsteps steps (lanes[s * 64 + lane]) into the workspace.
+// `lanes` must stay valid until the stream has passed the copy.
+void multi_upload_tabs(MultiRow &row, const StepLane *lanes, int nsteps, hipStream_t st);
+// nsteps steps whose lane tables were uploaded, replayed from a HIP graph that holds
+// the (k_prep, k_step) launches; the graph is captured on first use and again when
+// the row's geometry or buffers change.  st must not be the legacy null stream.
+struct StepGraph {
+    hipGraphExec_t exec = nullptr;
+    int W = 0, lanes = 0, nsteps = 0, parity = 0;
+    const void *key[8] = {};
+    StepGraph() = default;
+    StepGraph(const StepGraph &) = delete;
+    StepGraph &operator=(const StepGraph &) = delete;
+    ~StepGraph();
+};
+void multi_steps_graph(const Graph &G, MultiRow &row, int nsteps, StepGraph &sg, hipStream_t st);
 // Copies the accumulators of lanes [lane0, lane0 + nl) (4 W bytes per lane) to host.
 void multi_read(const Graph &G, MultiRow &row, int lane0, int nl, uint8_t *out, hipStream_t st);
 

@@ -98,6 +98,8 @@ struct StepParams {
     const uint8_t *lds_image;
     int32_t rowb, lanes;
     int32_t shared_level;        // 1: every active lane has tab[0].ylevel
+    const StepLane *dtab;        // non-null: lane table in device memory (64 lanes +
+                                 // header), used instead of tab / shared_level
     StepLane tab[64];            // per lane: seed, level, role
 };
 
@@ -638,13 +640,21 @@ __global__ void __launch_bounds__(1024) k_step(StepParams P) {
 
     const int lane = threadIdx.x & 63;
     StepLane L{0, 0, 0};
-    if (lane < P.lanes) L = P.tab[lane];
+    uint32_t lvl0;
+    bool shared_level;
+    if (P.dtab) {
+        if (lane < P.lanes) L = P.dtab[lane];
+        lvl0 = P.dtab[64].ylevel;
+        shared_level = P.dtab[64].flags != 0;
+    } else {
+        if (lane < P.lanes) L = P.tab[lane];
+        lvl0 = P.tab[0].ylevel;
+        shared_level = P.shared_level != 0;
+    }
     const bool act = (L.flags & kLaneActive) != 0;
     const bool from_x = (L.flags & kLaneFromX) != 0;
     const bool accm = (L.flags & kLaneAcc) != 0;
     // one level for every active group: the inner half of y's fingerprint is shared
-    const uint32_t lvl0 = P.tab[0].ylevel;
-    const bool shared_level = P.shared_level != 0;
     const int rowd = P.rowb >> 2;
     const uint32_t lanebits = (uint32_t)(lane & 31) << 2;
     const uint32_t xbase = (uint32_t)kExpBase + lanebits;
@@ -919,7 +929,9 @@ void run_sieve_impl(const Graph &G, const SieveRequest &req, SieveResult &res, b
             fin_tlo = std::max(0, fin_tlo);
             fin_thi = std::min<int32_t>((int32_t)G.ntiles, fin_thi);
         }
-        for (int64_t base = 0; base < npts; base += rowb) {
+        const int64_t pts_end =
+            req.max_chunks > 0 ? std::min<int64_t>(npts, (int64_t)req.max_chunks * rowb) : npts;
+        for (int64_t base = 0; base < pts_end; base += rowb) {
             k_xt<<<grid_for((int64_t)G.n * ((rowb + 15) / 16)), 256, 0, st>>>(
                 G.n, k, rowb, rowb, 0, (uint32_t)base, z.as<uint8_t>(), xt.as<uint8_t>());
             for (int l = 2; l <= k; ++l) {
@@ -1042,10 +1054,9 @@ void multi_prepare(const Graph &G, MultiRow &row, int lane0, int npts, const int
     TPM_HIP(hipGetLastError());
 }
 
-void multi_step(const Graph &G, MultiRow &row, const StepLane *lanes, hipStream_t st) {
-    if (G.m == 0) return;
+namespace {
+void fill_step_params(const Graph &G, const MultiRow &row, StepParams &P) {
     Workspace &ws = *row.ws;
-    StepParams P{};
     P.psrc = G.psrc;
     P.gsrc = G.gsrc;
     P.pdst = G.pdst;
@@ -1064,16 +1075,30 @@ void multi_step(const Graph &G, MultiRow &row, const StepLane *lanes, hipStream_
     P.lds_image = G.lds_image;
     P.rowb = row.rowb();
     P.lanes = row.lanes;
-    for (int i = 0; i < 64; ++i) P.tab[i] = (i < row.lanes) ? lanes[i] : StepLane{0, 0, 0};
-    // the shared inner hash needs one level for all active lanes, stored in tab[0]
+    P.dtab = nullptr;
+}
+
+// the level shared by every active lane, or -1
+int32_t shared_level_of(const StepLane *lanes, int nl) {
     int32_t lvl = -1;
-    bool same = true;
-    for (int i = 0; i < row.lanes; ++i)
+    for (int i = 0; i < nl; ++i)
         if (lanes[i].flags & kLaneActive) {
             if (lvl < 0) lvl = (int32_t)lanes[i].ylevel;
-            else same &= (int32_t)lanes[i].ylevel == lvl;
+            else if ((int32_t)lanes[i].ylevel != lvl) return -1;
         }
-    P.shared_level = (same && lvl >= 0) ? 1 : 0;
+    return lvl;
+}
+}  // namespace
+
+void multi_step(const Graph &G, MultiRow &row, const StepLane *lanes, hipStream_t st) {
+    if (G.m == 0) return;
+    Workspace &ws = *row.ws;
+    StepParams P{};
+    fill_step_params(G, row, P);
+    for (int i = 0; i < 64; ++i) P.tab[i] = (i < row.lanes) ? lanes[i] : StepLane{0, 0, 0};
+    // the shared inner hash needs one level for all active lanes, stored in tab[0]
+    const int32_t lvl = shared_level_of(lanes, row.lanes);
+    P.shared_level = lvl >= 0 ? 1 : 0;
     if (P.shared_level) P.tab[0].ylevel = (uint32_t)lvl;
     k_prep<<<1, 1, 0, st>>>(ws.ctl.as<Ctl>(), 1);
     {
@@ -1082,6 +1107,73 @@ void multi_step(const Graph &G, MultiRow &row, const StepLane *lanes, hipStream_
     }
     TPM_HIP(hipGetLastError());
     row.parity ^= 1;
+}
+
+void multi_upload_tabs(MultiRow &row, const StepLane *lanes, int nsteps, hipStream_t st) {
+    TPM_REQUIRE(nsteps >= 1 && nsteps <= 16, "steps per upload must be in [1, 16]");
+    Workspace &ws = *row.ws;
+    ws.tabs.alloc(sizeof(StepLane) * kTabStride * 16, st);
+    thread_local std::vector<StepLane> host;
+    host.assign((size_t)kTabStride * nsteps, StepLane{0, 0, 0});
+    for (int s = 0; s < nsteps; ++s) {
+        const StepLane *src = lanes + (size_t)s * 64;
+        for (int i = 0; i < row.lanes; ++i) host[(size_t)s * kTabStride + i] = src[i];
+        const int32_t lvl = shared_level_of(src, row.lanes);
+        host[(size_t)s * kTabStride + 64] = StepLane{0, lvl >= 0 ? (uint32_t)lvl : 0u, lvl >= 0 ? 1u : 0u};
+    }
+    TPM_HIP(hipMemcpyAsync(ws.tabs.p, host.data(), sizeof(StepLane) * host.size(),
+                           hipMemcpyHostToDevice, st));
+    // the host table is reused by the next upload on this thread
+    TPM_HIP(hipStreamSynchronize(st));
+}
+
+StepGraph::~StepGraph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+}
+
+void multi_steps_graph(const Graph &G, MultiRow &row, int nsteps, StepGraph &sg, hipStream_t st) {
+    if (G.m == 0) return;
+    TPM_REQUIRE(st != nullptr, "graph replay needs a created stream");
+    TPM_REQUIRE(nsteps >= 1 && nsteps <= 16, "steps per graph must be in [1, 16]");
+    Workspace &ws = *row.ws;
+    TPM_REQUIRE(ws.tabs.p != nullptr, "lane tables were not uploaded");
+    const void *key[8] = {ws.xt.p, ws.s0.p, ws.s1.p, ws.pub.p, ws.ctl.p, ws.pp.p, ws.tabs.p,
+                          G.tile_p0};
+    bool same = sg.exec && sg.W == row.W && sg.lanes == row.lanes && sg.nsteps == nsteps &&
+                sg.parity == row.parity;
+    for (int i = 0; i < 8 && same; ++i) same = sg.key[i] == key[i];
+    if (!same) {
+        if (sg.exec) TPM_HIP(hipGraphExecDestroy(sg.exec));
+        sg.exec = nullptr;
+        // only kernels are recorded (no memset or copy nodes)
+        TPM_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        hipGraph_t graph = nullptr;
+        hipError_t err = hipSuccess;
+        int parity = row.parity;
+        for (int s = 0; s < nsteps && err == hipSuccess; ++s) {
+            StepParams P{};
+            MultiRow r2 = row;
+            r2.parity = parity;
+            fill_step_params(G, r2, P);
+            P.dtab = ws.tabs.as<StepLane>() + (size_t)s * kTabStride;
+            k_prep<<<1, 1, 0, st>>>(ws.ctl.as<Ctl>(), 1);
+            launch_step_w(row.W, G, P, st);
+            err = hipGetLastError();
+            parity ^= 1;
+        }
+        hipError_t e2 = hipStreamEndCapture(st, &graph);
+        if (err == hipSuccess) err = e2;
+        if (err == hipSuccess) err = hipGraphInstantiate(&sg.exec, graph, nullptr, nullptr, 0);
+        if (graph) (void)hipGraphDestroy(graph);
+        TPM_HIP(err);
+        sg.W = row.W;
+        sg.lanes = row.lanes;
+        sg.nsteps = nsteps;
+        sg.parity = row.parity;
+        for (int i = 0; i < 8; ++i) sg.key[i] = key[i];
+    }
+    TPM_HIP(hipGraphLaunch(sg.exec, st));
+    row.parity ^= (nsteps & 1);
 }
 
 void multi_read(const Graph &G, MultiRow &row, int lane0, int nl, uint8_t *out, hipStream_t st) {

@@ -55,7 +55,13 @@ class tpm_kernel_time(ctypes.Structure):
 
 
 class tpm_tuning(ctypes.Structure):
-    _fields_ = [("chunk", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32)]
+    _fields_ = [("chunk", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
+
+
+class tpm_autotune_report(ctypes.Structure):
+    _fields_ = [("tile_edges", ctypes.c_int32), ("chunk", ctypes.c_int32),
+                ("ncand", ctypes.c_int32), ("cand_tile", ctypes.c_int32 * 12),
+                ("cand_chunk", ctypes.c_int32 * 12), ("cand_rate", ctypes.c_double * 12)]
 
 
 class tpm_query(ctypes.Structure):
@@ -91,6 +97,9 @@ _sig("tpm_graph_create_ex", ctypes.c_int32,
       ctypes.POINTER(tpm_graph_options), ctypes.POINTER(_vp)])
 _sig("tpm_graph_destroy", None, [_vp])
 _sig("tpm_graph_stats_get", ctypes.c_int32, [_vp, ctypes.POINTER(tpm_graph_stats)])
+_sig("tpm_graph_retile", ctypes.c_int32, [_vp, ctypes.c_int32])
+_sig("tpm_autotune", ctypes.c_int32, [_vp, ctypes.c_int32, ctypes.c_uint64,
+                                     ctypes.POINTER(tpm_autotune_report)])
 _sig("tpm_sieve", ctypes.c_int32, [_vp, _i32p, ctypes.c_int32, ctypes.c_uint64, _u8p, _u8p, _u8p,
                                   _vp])
 _sig("tpm_sieve_ex", ctypes.c_int32, [_vp, _i32p, ctypes.c_int32, ctypes.c_uint64, _u8p,
@@ -112,6 +121,7 @@ _sig("tpm_last_error", ctypes.c_char_p, [])
 _sig("tpm_version", ctypes.c_char_p, [])
 
 EXPORTED = ["tpm_graph_create", "tpm_graph_create_ex", "tpm_graph_destroy", "tpm_graph_stats_get",
+            "tpm_graph_retile", "tpm_autotune",
             "tpm_sieve", "tpm_sieve_ex", "tpm_decide", "tpm_extract", "tpm_batch_run",
             "tpm_server_create", "tpm_server_submit", "tpm_server_poll", "tpm_server_destroy",
             "tpm_profile_enable", "tpm_profile_read", "tpm_last_error", "tpm_version"]
@@ -244,10 +254,22 @@ def _result_dict(r: tpm_result) -> dict:
             "t_done_ms": r.t_done_ms}
 
 
-def tpm_batch_run(h, queries, chunk=0):
+def tpm_graph_retile(h, tile_edges) -> None:
+    _check(_lib.tpm_graph_retile(h, int(tile_edges)))
+
+
+def tpm_autotune(h, k, seed=1) -> dict:
+    rep = tpm_autotune_report()
+    _check(_lib.tpm_autotune(h, int(k), int(seed) & (2**64 - 1), ctypes.byref(rep)))
+    return {"tile_edges": rep.tile_edges, "chunk": rep.chunk,
+            "candidates": [{"tile_edges": rep.cand_tile[i], "chunk": rep.cand_chunk[i],
+                            "rate": rep.cand_rate[i]} for i in range(rep.ncand)]}
+
+
+def tpm_batch_run(h, queries, chunk=0, use_graph=False):
     arr, _keep = _make_queries(queries)
     out = (tpm_result * len(queries))()
-    tune = tpm_tuning(int(chunk), 0)
+    tune = tpm_tuning(int(chunk), 1 if use_graph else 0)
     _check(_lib.tpm_batch_run(h, len(queries), arr, out, ctypes.byref(tune)))
     return [_result_dict(out[i]) for i in range(len(queries))]
 
@@ -316,8 +338,14 @@ class Graph:
     def extract(self, multiset, seed, max_reps=8):
         return tpm_extract(self.h, multiset, seed, max_reps)
 
-    def batch(self, queries, chunk=0):
-        return tpm_batch_run(self.h, queries, chunk)
+    def batch(self, queries, chunk=0, use_graph=False):
+        return tpm_batch_run(self.h, queries, chunk, use_graph)
+
+    def retile(self, tile_edges) -> None:
+        tpm_graph_retile(self.h, tile_edges)
+
+    def autotune(self, k, seed=1) -> dict:
+        return tpm_autotune(self.h, k, seed)
 
     def close(self):
         if getattr(self, "h", None):

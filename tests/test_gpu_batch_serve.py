@@ -55,6 +55,29 @@ def test_batch_totals_match_oracle(tpm, graph, chunk):
     Gd.close()
 
 
+@pytest.mark.parametrize("chunk", [0, 256])
+def test_batch_graph_replay_matches_plain_and_oracle(tpm, graph, chunk):
+    """Passes of one row shape replay one captured HIP graph; eager work (x rows,
+    clears, reads with a synchronisation) runs between the replays.  Every pass is
+    checked against plain launches and the oracle."""
+    rng = np.random.default_rng(300 + chunk)
+    # 37 queries of k = 6 (several passes of one shape, then a shorter last pass),
+    # plus mixed sizes
+    qs = [{"multiset": [int(c) for c in rng.integers(0, graph.num_colors, 6)],
+           "seed": int(rng.integers(0, 2**62))} for _ in range(37)]
+    qs += _queries(rng, 20, graph.num_colors, 2, 9)
+    say(f"case batch graph chunk={chunk}: {len(qs)} queries")
+    Gd = tpm.Graph.from_temporal(graph)
+    plain = Gd.batch(qs, chunk=chunk)
+    for rep in range(2):
+        res = Gd.batch(qs, chunk=chunk, use_graph=True)
+        for i, (q, a, b) in enumerate(zip(qs, plain, res)):
+            assert a["total"] == b["total"], (rep, i, q)
+    for q, r in zip(qs, plain):
+        assert r["total"] == oracle.sieve_total(graph, q["multiset"], q["seed"])
+    Gd.close()
+
+
 def test_batch_with_paths(tpm):
     g = G.uniform_graph(300, 3000, 40, 3, 5)
     rng = np.random.default_rng(2)

@@ -202,6 +202,48 @@ def test_graph_stats(tpm):
     Gd.close()
 
 
+def test_retile_is_bit_identical(tpm):
+    g = G.chung_lu_graph(3000, 60000, 2.5, 50, 3, 77)
+    M = [0, 1, 2, 0, 1, 2, 0]
+    want = oracle.sieve(g, M, 13)
+    Gd = tpm.Graph.from_temporal(g)
+    for T in (1, 3, 64, 1024, 4096, 200):
+        say(f"case retile T={T}")
+        Gd.retile(T)
+        st = Gd.stats()
+        Gf = tpm.Graph.from_temporal(g, tile_edges=T)
+        assert st["tiles"] == Gf.stats()["tiles"] and st["slots"] == Gf.stats()["slots"]
+        Gf.close()
+        pp, tot = Gd.sieve(M, 13)
+        assert np.array_equal(pp, want), T
+    with pytest.raises(tpm.TpmError):
+        Gd.retile(0)
+    assert np.array_equal(Gd.sieve(M, 13)[0], want)  # the failed retile kept the tiles
+    Gd.close()
+
+
+@pytest.mark.parametrize("k", [5, 9])
+def test_autotune_applies_a_candidate_and_keeps_results(tpm, k):
+    g = G.chung_lu_graph(20000, 400000, 2.5, 200, 4, 31)
+    M = [int(c) for c in np.random.default_rng(k).integers(0, 4, k)]
+    Gd = tpm.Graph.from_temporal(g, tile_edges=7)
+    say(f"case autotune k={k}")
+    rep = Gd.autotune(k, seed=5)
+    cands = rep["candidates"]
+    chunks = [min(2**k, 256)] if 2**k < 256 else [c for c in (256, 512, 1024) if c <= 2**k]
+    assert len(cands) == 4 * len(chunks)
+    assert {(c["tile_edges"], c["chunk"]) for c in cands} == {
+        (t, c) for t in (256, 512, 1024, 2048) for c in chunks}
+    best = max(cands, key=lambda c: c["rate"])
+    assert (rep["tile_edges"], rep["chunk"]) == (best["tile_edges"], best["chunk"])
+    Gf = tpm.Graph.from_temporal(g, tile_edges=rep["tile_edges"])
+    assert Gd.stats()["tiles"] == Gf.stats()["tiles"]
+    Gf.close()
+    pp, _ = Gd.sieve(M, 3, chunk=rep["chunk"])
+    assert np.array_equal(pp, oracle.sieve(g, M, 3))
+    Gd.close()
+
+
 @pytest.mark.timeout(600)
 def test_k10_full_size_sampled_points(tpm):
     """The k = 10 workload at full size (n = 1e6, m = 1e8), in the launch
