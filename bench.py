@@ -317,18 +317,32 @@ def bench_serving(args) -> int:
     t_gen = time.perf_counter()
     g = make_config_graph("serving", scale=args.scale)
     _log(f"# serving: n={g.n} m={g.m} generated in {time.perf_counter() - t_gen:.1f}s")
+    t_idx = time.perf_counter()
     G = tpm.Graph.from_temporal(g)
     st = G.stats()
-    _log(f"# index: rows={st['rows']} tiles={st['tiles']}")
+    _log(f"# index: rows={st['rows']} tiles={st['tiles']} built in {time.perf_counter() - t_idx:.1f}s")
     qs = [{"multiset": [int(c) for c in make_config_query("serving", i)],
            "seed": 90001 + 7919 * i} for i in range(nq)]
     srv = tpm.Server(G)
+
+    def drain(n, got=None):
+        """Poll until n results arrived, printing progress every 20 s."""
+        got = [] if got is None else got
+        t_last = time.perf_counter()
+        while len(got) < n:
+            got += srv.poll(256)
+            if time.perf_counter() - t_last > 20:
+                _log(f"# {len(got)} of {n} results")
+                t_last = time.perf_counter()
+            time.sleep(0.001)
+        return got
+
     # capacity: a closed-loop burst of the first third of the stream
     nb = max(8, nq // 3)
     t0 = time.perf_counter()
     for q in qs[:nb]:
         srv.submit(q["multiset"], q["seed"])
-    burst = srv.drain(nb, timeout_s=3000)
+    burst = drain(nb)
     cap = nb / (time.perf_counter() - t0)
     _log(f"# capacity {cap:.3f} queries/s from a burst of {nb}")
     # open loop: Poisson arrivals at load x capacity for the rest of the stream
@@ -338,13 +352,17 @@ def bench_serving(args) -> int:
     t_start = time.perf_counter()
     next_t = t_start
     results = []
+    t_last = t_start
     for i, q in enumerate(qs[nb:]):
         next_t += gaps[i]
         while time.perf_counter() < next_t:
             results += srv.poll(256)
             time.sleep(0.0005)
         srv.submit(q["multiset"], q["seed"])
-    results += srv.drain(nq - nb - len(results), timeout_s=3000)
+        if time.perf_counter() - t_last > 20:
+            _log(f"# submitted {i + 1}, {len(results)} results")
+            t_last = time.perf_counter()
+    results = drain(nq - nb, results)
     t_total = time.perf_counter() - t_start
     srv.close()
     lat = np.array([r["t_done_ms"] - r["t_submit_ms"] for r in results])

@@ -222,7 +222,9 @@ void tpm_server_destroy(tpm_server *s);
 /* When enabled (process-wide), every sieve level kernel is bracketed by HIP events
  * recorded on the stream it is launched on; tpm_profile_read drains the measured
  * durations.  kind: 0 = level 2 (reads the per-vertex rows), 1 = a middle level
- * (3..k-1), 2 = the last level (reduction).  Timing adds no device work. */
+ * (3..k-1), 2 = the last level (reduction), 3 = a multi-query step (batched form
+ * with plain launches, serving loop; chunk_points = row width).  Timing adds no
+ * device work. */
 typedef struct {
     int32_t kind;
     int32_t level;

@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -376,13 +377,16 @@ tpm_status tpm_server_create(const tpm_graph *g, const tpm_server_config *cfg, t
         size_t freeb = 0, totalb = 0;
         TPM_HIP(hipMemGetInfo(&freeb, &totalb));
         double budget = s->cfg.state_bytes > 0 ? (double)s->cfg.state_bytes : 0.7 * (double)freeb;
+        // bytes per lane-dword of a row: both level buffers, vertex rows, look-back words
+        const double per_dword = (double)(2 * G.R + G.n + 2 * G.nslots) * 4.0;
         int W = 4;
-        while (W > 1 && (double)(2 * G.R + G.n + 2 * G.nslots) * (256.0 * W) > budget) W >>= 1;
-        TPM_REQUIRE((double)(2 * G.R + G.n + 2 * G.nslots) * 256.0 <= budget,
-                    "not enough device memory for a 256-point serving row");
+        while (W > 1 && per_dword * (64.0 * W) > budget) W >>= 1;
+        // narrower rows (fewer lanes) when even one dword per lane does not fit
+        const int fit = (int)std::min(64.0, std::floor(budget / per_dword));
+        TPM_REQUIRE(fit >= 1, "not enough device memory for one serving lane");
         s->W = W;
-        s->lanes = 64;
-        if (s->cfg.max_lanes > 0) s->lanes = std::min(64, s->cfg.max_lanes);
+        s->lanes = W > 1 ? 64 : fit;
+        if (s->cfg.max_lanes > 0) s->lanes = std::min(s->lanes, s->cfg.max_lanes);
         s->worker = std::thread(serve_loop, s);
         *out = s;
         return TPM_OK;

@@ -194,6 +194,10 @@ struct StepLane {
     uint32_t flags;   // kLaneActive | kLaneFromX (level 2) | kLaneAcc (last level)
 };
 constexpr uint32_t kLaneActive = 1, kLaneFromX = 2, kLaneAcc = 4;
+// bits 8..10 of a lane's flags: its group in the step's fingerprint table (set by the
+// library, ignored on input)
+constexpr uint32_t kLaneGroupShift = 8;
+constexpr int kMaxYGroups = 8;
 
 // A multi-query row: W dwords per lane, `lanes` lanes, buffers from a workspace.
 struct MultiRow {
@@ -211,10 +215,9 @@ void multi_prepare(const Graph &G, MultiRow &row, int lane0, int npts, const int
                    uint64_t seed, uint32_t base, const uint8_t *vertex_mask, hipStream_t st);
 // One level for every lane group (lanes[i] for lane i; inactive lanes have flags 0).
 void multi_step(const Graph &G, MultiRow &row, const StepLane *lanes, hipStream_t st);
-// Device-resident lane tables: StepLane entries per step = 64 lanes + 1 header whose
-// ylevel is the level shared by every active lane and whose flags is 1 when there is
-// one (0 otherwise).
-constexpr int kTabStride = 65;
+// Device-resident lane tables, per step: 64 lanes, then a header (ylevel = shared
+// level, flags = ymode | ngroups << 8), then kMaxYGroups (seed, level) group entries.
+constexpr int kTabStride = 64 + 1 + kMaxYGroups;
 // Copies the lane tables of nsteps steps (lanes[s * 64 + lane]) into the workspace.
 // `lanes` must stay valid until the stream has passed the copy.
 void multi_upload_tabs(MultiRow &row, const StepLane *lanes, int nsteps, hipStream_t st);

@@ -97,9 +97,16 @@ struct StepParams {
     uint32_t *fin;               // per-point accumulators of groups at their last level
     const uint8_t *lds_image;
     int32_t rowb, lanes;
-    int32_t shared_level;        // 1: every active lane has tab[0].ylevel
-    const StepLane *dtab;        // non-null: lane table in device memory (64 lanes +
-                                 // header), used instead of tab / shared_level
+    // How a lane finds y_{e, level} (see StepYPlan): 0 = its own full hash, 1 = the
+    // inner hash is shared (one level, ylevel0), 2 = table of up to 8 (seed, level)
+    // groups hashed once per 64 positions; the lane's group is in flags bits 8..10.
+    int32_t ymode;
+    uint32_t ylevel0;
+    int32_t ngroups;
+    uint32_t glevel[kMaxYGroups];
+    uint64_t gseed[kMaxYGroups];
+    const StepLane *dtab;        // non-null: lane table and plan in device memory
+                                 // (kTabStride entries), used instead of the above
     StepLane tab[64];            // per lane: seed, level, role
 };
 
@@ -580,13 +587,21 @@ inline unsigned grid_for(int64_t work, int block = 256) {
 // ---------------------------------------------------------------------------------
 struct WinS {
     int32_t g, s, d, o;
-    uint32_t e;         // input edge id
-    uint32_t hlo, hhi;  // inner fingerprint hash of (y, ylevel, e) when every group
-                        // of the step shares one level (else unused)
+    uint32_t e;       // input edge id
+    uint32_t h0, h1;  // ymode 1: inner fingerprint hash of (tag y, ylevel0, e), low and
+                      // high words; ymode 2: log y of groups 0..3 and 4..7, one byte
+                      // each (255 for y = 0)
+};
+
+struct YPlan {
+    int ymode, ngroups;
+    uint32_t ylevel0;
+    const uint64_t *gs;  // group seeds and levels, in LDS (shared by the workgroup)
+    const uint32_t *gl;
 };
 
 __device__ __forceinline__ WinS load_wins(const StepParams &P, int32_t wb, int32_t p1, int lane,
-                                          bool shared_level, uint32_t ylevel) {
+                                          const YPlan &Y, const uint8_t *lds, uint32_t lanebits) {
     WinS m{-1, -1, -1, -1, 0, 0, 0};
     const int32_t q = wb + lane;
     if (q < p1) {
@@ -595,10 +610,25 @@ __device__ __forceinline__ WinS load_wins(const StepParams &P, int32_t wb, int32
         m.d = P.pdst[q];
         m.o = P.orow[q];
         m.e = (uint32_t)P.peid[q];
-        if (shared_level) {
-            const uint64_t h = mix64((1ull << 56) ^ ((uint64_t)ylevel << 32) ^ (uint64_t)m.e);
-            m.hlo = (uint32_t)h;
-            m.hhi = (uint32_t)(h >> 32);
+        if (Y.ymode == 1) {
+            const uint64_t h = mix64((1ull << 56) ^ ((uint64_t)Y.ylevel0 << 32) ^ (uint64_t)m.e);
+            m.h0 = (uint32_t)h;
+            m.h1 = (uint32_t)(h >> 32);
+        } else if (Y.ymode == 2) {
+            // groups are sorted by level: the inner hash changes only with the level
+            uint64_t inner = 0;
+            uint32_t prev = ~0u;
+#pragma unroll 1
+            for (int g = 0; g < Y.ngroups; ++g) {
+                const uint32_t lv = Y.gl[g];
+                if (lv != prev) inner = mix64((1ull << 56) ^ ((uint64_t)lv << 32) ^ (uint64_t)m.e);
+                prev = lv;
+                const uint32_t y = (uint32_t)(mix64(Y.gs[g] ^ inner) & 0xFFu);
+                const uint32_t l7 = lds32(lds, (y << 8) | lanebits);
+                const uint32_t lb = l7 >= kZero7 ? 255u : (l7 >> 7);
+                if (g < 4) m.h0 |= lb << (8 * g);
+                else m.h1 |= lb << (8 * (g - 4));
+            }
         }
     }
     return m;
@@ -617,9 +647,12 @@ __device__ __forceinline__ void gather_step(const StepParams &P, const WinS &cw,
             rg = (i < 64) ? __builtin_amdgcn_readlane(cw.g, i) : __builtin_amdgcn_readlane(nw.g, i - 64);
             rs = (i < 64) ? __builtin_amdgcn_readlane(cw.s, i) : __builtin_amdgcn_readlane(nw.s, i - 64);
         }
-        const int32_t r = from_x ? rs : rg;
-        if (r >= 0 && act) {
-            load_row<W>(from_x ? P.xt : P.sin, r, P.rowb, lane, g[u]);
+        // both candidate rows are uniform: form their addresses in scalar registers
+        // and let each lane pick by its role
+        const uint8_t *px = P.xt + (int64_t)rs * P.rowb;
+        const uint8_t *ps = P.sin + (int64_t)rg * P.rowb;
+        if ((from_x ? rs : rg) >= 0 && act) {
+            load_row<W>(from_x ? px : ps, 0, P.rowb, lane, g[u]);
         } else {
 #pragma unroll
             for (int w = 0; w < W; ++w) g[u][w] = 0;
@@ -631,30 +664,43 @@ template <int W>
 __global__ void __launch_bounds__(1024) k_step(StepParams P) {
     constexpr int U = (W == 4) ? 4 : kU;  // edges per batch (register budget)
     __shared__ __attribute__((aligned(16))) uint8_t lds[kLdsBytes];
+    __shared__ uint64_t s_gseed[kMaxYGroups];
+    __shared__ uint32_t s_glevel[kMaxYGroups];
     {
         const uint4 *src = (const uint4 *)P.lds_image;
         uint4 *dst = (uint4 *)lds;
         for (int i = threadIdx.x; i < kLdsBytes / 16; i += blockDim.x) dst[i] = src[i];
+        if (threadIdx.x < kMaxYGroups) {
+            const int g = threadIdx.x;
+            s_gseed[g] = P.dtab ? P.dtab[65 + g].seed : P.gseed[g];
+            s_glevel[g] = P.dtab ? P.dtab[65 + g].ylevel : P.glevel[g];
+        }
     }
     __syncthreads();
 
     const int lane = threadIdx.x & 63;
     StepLane L{0, 0, 0};
-    uint32_t lvl0;
-    bool shared_level;
+    YPlan Y;
+    Y.gs = s_gseed;
+    Y.gl = s_glevel;
     if (P.dtab) {
         if (lane < P.lanes) L = P.dtab[lane];
-        lvl0 = P.dtab[64].ylevel;
-        shared_level = P.dtab[64].flags != 0;
+        const StepLane h = P.dtab[64];
+        Y.ymode = (int)(h.flags & 0xFFu);
+        Y.ngroups = (int)(h.flags >> 8);
+        Y.ylevel0 = h.ylevel;
     } else {
         if (lane < P.lanes) L = P.tab[lane];
-        lvl0 = P.tab[0].ylevel;
-        shared_level = P.shared_level != 0;
+        Y.ymode = P.ymode;
+        Y.ngroups = P.ngroups;
+        Y.ylevel0 = P.ylevel0;
     }
     const bool act = (L.flags & kLaneActive) != 0;
     const bool from_x = (L.flags & kLaneFromX) != 0;
     const bool accm = (L.flags & kLaneAcc) != 0;
-    // one level for every active group: the inner half of y's fingerprint is shared
+    const uint32_t grp = (L.flags >> kLaneGroupShift) & (kMaxYGroups - 1);
+    const bool grp_hi = grp >= 4;
+    const uint32_t grp_shift = 8 * (grp & 3);
     const int rowd = P.rowb >> 2;
     const uint32_t lanebits = (uint32_t)(lane & 31) << 2;
     const uint32_t xbase = (uint32_t)kExpBase + lanebits;
@@ -676,8 +722,8 @@ __global__ void __launch_bounds__(1024) k_step(StepParams P) {
         const bool cont = lbslot >= 0;
 
         int32_t wb = p0;
-        WinS cw = load_wins(P, wb, p1, lane, shared_level, lvl0);
-        WinS nw = load_wins(P, wb + 64, p1, lane, shared_level, lvl0);
+        WinS cw = load_wins(P, wb, p1, lane, Y, lds, lanebits);
+        WinS nw = load_wins(P, wb + 64, p1, lane, Y, lds, lanebits);
 
         const int32_t d0 = __builtin_amdgcn_readfirstlane(cw.d);
         int32_t cur_dst = -1, nxt_dst = d0;
@@ -724,17 +770,25 @@ __global__ void __launch_bounds__(1024) k_step(StepParams P) {
                     if (nd >= 0 && act) load_row<W>(P.xt, nd, P.rowb, lane, xn);
                 }
                 // y_{e, level-1} of this lane's query
-                uint32_t y;
-                if (shared_level) {
-                    const uint64_t inner =
-                        ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(cw.hhi, i) << 32) |
-                        (uint64_t)(uint32_t)__builtin_amdgcn_readlane(cw.hlo, i);
-                    y = (uint32_t)(mix64(L.seed ^ inner) & 0xFFu);
+                uint32_t ly7;
+                if (Y.ymode == 2) {
+                    const uint32_t w0 = (uint32_t)__builtin_amdgcn_readlane(cw.h0, i);
+                    const uint32_t w1 = (uint32_t)__builtin_amdgcn_readlane(cw.h1, i);
+                    const uint32_t lb = ((grp_hi ? w1 : w0) >> grp_shift) & 0xFFu;
+                    ly7 = lb == 255u ? kZero7 : (lb << 7);
                 } else {
-                    const uint32_t eid = __builtin_amdgcn_readlane(cw.e, i);
-                    y = fp8(L.seed, 1u, L.ylevel, eid);
+                    uint32_t y;
+                    if (Y.ymode == 1) {
+                        const uint64_t inner =
+                            ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(cw.h1, i) << 32) |
+                            (uint64_t)(uint32_t)__builtin_amdgcn_readlane(cw.h0, i);
+                        y = (uint32_t)(mix64(L.seed ^ inner) & 0xFFu);
+                    } else {
+                        const uint32_t eid = __builtin_amdgcn_readlane(cw.e, i);
+                        y = fp8(L.seed, 1u, L.ylevel, eid);
+                    }
+                    ly7 = lds32(lds, (y << 8) | lanebits);
                 }
-                const uint32_t ly7 = lds32(lds, (y << 8) | lanebits);
                 uint32_t c[W];
 #pragma unroll
                 for (int w = 0; w < W; ++w) c[w] = mul4(lds, lanebits, g[u][w], &lx7[4 * w], ly7, zc);
@@ -751,7 +805,7 @@ __global__ void __launch_bounds__(1024) k_step(StepParams P) {
             if (pb + U - wb == 64 && pb + U < p1) {
                 wb += 64;
                 cw = nw;
-                nw = load_wins(P, wb + 64, p1, lane, shared_level, lvl0);
+                nw = load_wins(P, wb + 64, p1, lane, Y, lds, lanebits);
             }
         };
 
@@ -1078,15 +1132,49 @@ void fill_step_params(const Graph &G, const MultiRow &row, StepParams &P) {
     P.dtab = nullptr;
 }
 
-// the level shared by every active lane, or -1
-int32_t shared_level_of(const StepLane *lanes, int nl) {
+// How the lanes of one step find their y fingerprints: up to kMaxYGroups distinct
+// (seed, level) pairs become a table that the kernel hashes once per window of 64
+// positions (ymode 2, group index written into each lane's flags); otherwise a shared
+// level lets lanes share the inner hash (ymode 1); otherwise every lane hashes alone.
+struct StepYPlan {
+    int32_t ymode = 0, ngroups = 0;
+    uint32_t ylevel0 = 0;
+    uint32_t glevel[kMaxYGroups] = {};
+    uint64_t gseed[kMaxYGroups] = {};
+};
+
+StepYPlan plan_y(StepLane *lanes, int nl) {
+    StepYPlan Y;
+    std::vector<std::pair<uint32_t, uint64_t>> groups;  // (level, seed)
     int32_t lvl = -1;
-    for (int i = 0; i < nl; ++i)
-        if (lanes[i].flags & kLaneActive) {
-            if (lvl < 0) lvl = (int32_t)lanes[i].ylevel;
-            else if ((int32_t)lanes[i].ylevel != lvl) return -1;
+    bool same = true;
+    for (int i = 0; i < nl; ++i) {
+        lanes[i].flags &= ~(uint32_t)((kMaxYGroups - 1) << kLaneGroupShift);
+        if (!(lanes[i].flags & kLaneActive)) continue;
+        if (lvl < 0) lvl = (int32_t)lanes[i].ylevel;
+        else same &= (int32_t)lanes[i].ylevel == lvl;
+        const std::pair<uint32_t, uint64_t> key{lanes[i].ylevel, lanes[i].seed};
+        if (std::find(groups.begin(), groups.end(), key) == groups.end()) groups.push_back(key);
+    }
+    if (!groups.empty() && groups.size() <= (size_t)kMaxYGroups) {
+        std::sort(groups.begin(), groups.end());
+        Y.ymode = 2;
+        Y.ngroups = (int32_t)groups.size();
+        for (int g = 0; g < Y.ngroups; ++g) {
+            Y.glevel[g] = groups[(size_t)g].first;
+            Y.gseed[g] = groups[(size_t)g].second;
         }
-    return lvl;
+        for (int i = 0; i < nl; ++i) {
+            if (!(lanes[i].flags & kLaneActive)) continue;
+            const std::pair<uint32_t, uint64_t> key{lanes[i].ylevel, lanes[i].seed};
+            const uint32_t g = (uint32_t)(std::find(groups.begin(), groups.end(), key) - groups.begin());
+            lanes[i].flags |= g << kLaneGroupShift;
+        }
+    } else if (same && lvl >= 0) {
+        Y.ymode = 1;
+        Y.ylevel0 = (uint32_t)lvl;
+    }
+    return Y;
 }
 }  // namespace
 
@@ -1096,10 +1184,14 @@ void multi_step(const Graph &G, MultiRow &row, const StepLane *lanes, hipStream_
     StepParams P{};
     fill_step_params(G, row, P);
     for (int i = 0; i < 64; ++i) P.tab[i] = (i < row.lanes) ? lanes[i] : StepLane{0, 0, 0};
-    // the shared inner hash needs one level for all active lanes, stored in tab[0]
-    const int32_t lvl = shared_level_of(lanes, row.lanes);
-    P.shared_level = lvl >= 0 ? 1 : 0;
-    if (P.shared_level) P.tab[0].ylevel = (uint32_t)lvl;
+    const StepYPlan Y = plan_y(P.tab, row.lanes);
+    P.ymode = Y.ymode;
+    P.ngroups = Y.ngroups;
+    P.ylevel0 = Y.ylevel0;
+    for (int g = 0; g < kMaxYGroups; ++g) {
+        P.glevel[g] = Y.glevel[g];
+        P.gseed[g] = Y.gseed[g];
+    }
     k_prep<<<1, 1, 0, st>>>(ws.ctl.as<Ctl>(), 1);
     {
         ProfileScope prof(st, 3, 0, row.rowb());
@@ -1116,10 +1208,12 @@ void multi_upload_tabs(MultiRow &row, const StepLane *lanes, int nsteps, hipStre
     thread_local std::vector<StepLane> host;
     host.assign((size_t)kTabStride * nsteps, StepLane{0, 0, 0});
     for (int s = 0; s < nsteps; ++s) {
+        StepLane *dst = host.data() + (size_t)s * kTabStride;
         const StepLane *src = lanes + (size_t)s * 64;
-        for (int i = 0; i < row.lanes; ++i) host[(size_t)s * kTabStride + i] = src[i];
-        const int32_t lvl = shared_level_of(src, row.lanes);
-        host[(size_t)s * kTabStride + 64] = StepLane{0, lvl >= 0 ? (uint32_t)lvl : 0u, lvl >= 0 ? 1u : 0u};
+        for (int i = 0; i < row.lanes; ++i) dst[i] = src[i];
+        const StepYPlan Y = plan_y(dst, row.lanes);
+        dst[64] = StepLane{0, Y.ylevel0, (uint32_t)Y.ymode | ((uint32_t)Y.ngroups << 8)};
+        for (int g = 0; g < kMaxYGroups; ++g) dst[65 + g] = StepLane{Y.gseed[g], Y.glevel[g], 0};
     }
     TPM_HIP(hipMemcpyAsync(ws.tabs.p, host.data(), sizeof(StepLane) * host.size(),
                            hipMemcpyHostToDevice, st));

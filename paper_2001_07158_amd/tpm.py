@@ -300,7 +300,7 @@ def tpm_server_destroy(s) -> None:
     _lib.tpm_server_destroy(s)
 
 
-KERNEL_KINDS = {0: "level2", 1: "middle", 2: "last"}
+KERNEL_KINDS = {0: "level2", 1: "middle", 2: "last", 3: "step"}
 
 
 def tpm_profile_enable(on: bool) -> None:

@@ -78,6 +78,24 @@ def test_batch_graph_replay_matches_plain_and_oracle(tpm, graph, chunk):
     Gd.close()
 
 
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_batch_fingerprint_plans(tpm, graph, use_graph):
+    """A step finds y either from a table of <= 8 (seed, level) groups hashed once
+    per 64 positions, or from a shared inner hash (one level, many seeds), or per
+    lane: rows of 6 (table), 12 and 40 (shared inner) queries of one size."""
+    rng = np.random.default_rng(55)
+    qs = []
+    for k, cnt in ((6, 6), (5, 12), (4, 40), (7, 3)):
+        qs += [{"multiset": [int(c) for c in rng.integers(0, graph.num_colors, k)],
+                "seed": int(rng.integers(0, 2**62))} for _ in range(cnt)]
+    say(f"case fingerprint plans graph={use_graph}")
+    Gd = tpm.Graph.from_temporal(graph)
+    res = Gd.batch(qs, use_graph=use_graph)
+    for q, r in zip(qs, res):
+        assert r["total"] == oracle.sieve_total(graph, q["multiset"], q["seed"]), q
+    Gd.close()
+
+
 def test_batch_with_paths(tpm):
     g = G.uniform_graph(300, 3000, 40, 3, 5)
     rng = np.random.default_rng(2)
