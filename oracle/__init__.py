@@ -143,6 +143,50 @@ def sieve_total(g, M, seed: int, mask=None, nthreads: int = 0) -> int:
     return int(np.bitwise_xor.reduce(pp)) if pp.size else 0
 
 
+def vertex_sieve(g, M, seed: int, mask=None, nthreads: int = 0) -> np.ndarray:
+    """Vertex-localised sieve (section "Vertex-localization"): Q_u = sum over all
+    sieve points A of P_{u,k,t}(z^A).  P_{u,k,t} is the sum of the last-level
+    contributions of u's in-edges, so Q_u is the XOR of the per-edge localisation
+    over the edges that end at u.  k >= 2."""
+    if len(M) < 2:
+        raise ValueError("vertex localisation needs k >= 2")
+    _, lc = sieve(g, M, seed, mask=mask, loc=True, nthreads=nthreads)
+    q = np.zeros(g.n, dtype=np.uint8)
+    np.bitwise_xor.at(q, np.asarray(g.dst, dtype=np.int64), lc)
+    return q
+
+
+def time_buckets(g, M, seed: int, mask=None, nthreads: int = 0):
+    """Per-timestamp split of the sieve: for each distinct timestamp t (ascending),
+    B(t) = XOR of the per-edge localisation over the edges with timestamp t.  A
+    walk's last edge carries its largest timestamp, so the XOR of B over times <= t
+    is the sieve restricted to walks that finish by t.  k >= 2."""
+    if len(M) < 2:
+        raise ValueError("time buckets need k >= 2")
+    _, lc = sieve(g, M, seed, mask=mask, loc=True, nthreads=nthreads)
+    times, inv = np.unique(np.asarray(g.tau, dtype=np.int64), return_inverse=True)
+    b = np.zeros(times.shape[0], dtype=np.uint8)
+    np.bitwise_xor.at(b, inv, lc)
+    return times.astype(np.int32), b
+
+
+def optimum_time(g, M, seed: int, reps: int = 1, nthreads: int = 0) -> int:
+    """Section "Finding optimum timestamp": the smallest t such that the sieve over
+    walks finishing by t is nonzero, minimised over `reps` seeds (seed_r = seed +
+    r * 0x9E3779B97F4A7C15, as for decide); -1 if none.  The prefix XOR of the time
+    buckets is zero before the first nonzero bucket, so that bucket's time is the
+    first t with a nonzero prefix."""
+    best = -1
+    for r in range(reps):
+        sr = (seed + r * 0x9E3779B97F4A7C15) & 0xFFFFFFFFFFFFFFFF
+        times, b = time_buckets(g, M, sr, nthreads=nthreads)
+        nz = np.nonzero(b)[0]
+        if nz.size:
+            t = int(times[nz[0]])
+            best = t if best < 0 else min(best, t)
+    return best
+
+
 class Index:
     """Reusable oracle index (in-lists sorted by time) for repeated evaluations;
     keeps references to the arrays it borrows."""

@@ -205,6 +205,39 @@ def brute_paths_total(g, M, seed: int, mask=None) -> int:
     return tot
 
 
+def brute_paths_by_end(g, M, seed: int, mask=None):
+    """Per end vertex u: sum over temporal paths P ending at u of y(P) det(Z_P);
+    and per last-edge time t: the same sum over paths whose last edge has time t.
+    Returns (per_vertex [n], {t: value})."""
+    k = len(M)
+    z = zvals(g, M, seed, mask)
+    per_v = np.zeros(g.n, dtype=np.uint8)
+    per_t = {}
+    for verts, edges in temporal_walks(g, k):
+        if len(set(verts)) != k:
+            continue
+        y = 1
+        for l, e in enumerate(edges, start=1):
+            y = gmul(y, fp(seed, TAG_Y, l, e))
+        v = gmul(y, det([z[u] for u in verts]))
+        per_v[verts[-1]] ^= v
+        t = int(g.tau[edges[-1]])
+        per_t[t] = per_t.get(t, 0) ^ v
+    return per_v, per_t
+
+
+def brute_optimum_time(g, M) -> int:
+    """Smallest possible largest timestamp over temporal paths matching M (-1 if
+    none): exhaustive search."""
+    want = sorted(int(c) for c in M)
+    best = -1
+    for verts, edges in temporal_walks(g, len(M)):
+        if len(set(verts)) == len(verts) and sorted(int(g.color[u]) for u in verts) == want:
+            t = int(g.tau[edges[-1]])
+            best = t if best < 0 else min(best, t)
+    return best
+
+
 def literal_eq3_table(g, M, seed: int, mask=None, X=None) -> np.ndarray:
     """Eq. (3) exactly as written, over (length l, vertex u, time i), i = 0..t:
     P[1][u][i] = x_u;  P[l][u][0] = 0 for l >= 2;

@@ -202,6 +202,71 @@ def test_localisation_sums_to_total():
         assert np.array_equal(loc, want)
 
 
+def test_vertex_localisation_is_paths_ending_at_u():
+    """Q_u of the vertex-localised sieve = sum over temporal paths ending at u of
+    y(P) det(Z_P) (brute force), and the Q_u add up to the sieve total."""
+    rng = np.random.default_rng(81)
+    for _ in range(40):
+        g = G.random_tiny_graph(rng, n_max=10, m_max=30)
+        k = int(rng.integers(2, 5))
+        M = [int(c) for c in rng.integers(0, g.num_colors, k)]
+        q = oracle.vertex_sieve(g, M, 9)
+        want, _ = pyref.brute_paths_by_end(g, M, 9)
+        assert np.array_equal(q, want)
+        assert int(np.bitwise_xor.reduce(q)) == oracle.sieve_total(g, M, 9)
+
+
+def test_time_prefix_equals_sieve_of_truncated_graph():
+    """The XOR of the time buckets up to t equals a fresh sieve of the graph keeping
+    only edges with timestamp <= t (same input edge ids, so the same fingerprints),
+    and each bucket is the brute-force sum over paths whose last edge has time t."""
+    rng = np.random.default_rng(82)
+    for it in range(40):
+        g = G.random_tiny_graph(rng, n_max=10, m_max=30, t_max=6)
+        k = int(rng.integers(2, 5))
+        M = [int(c) for c in rng.integers(0, g.num_colors, k)]
+        if g.m == 0:
+            continue
+        times, b = oracle.time_buckets(g, M, 4 + it)
+        assert np.array_equal(times, np.unique(g.tau))
+        _, per_t = pyref.brute_paths_by_end(g, M, 4 + it)
+        for t, v in zip(times, b):
+            assert v == per_t.get(int(t), 0)
+        pref = 0
+        for t, v in zip(times, b):
+            pref ^= int(v)
+            # truncated graph: edges at times > t made unreachable by masking nothing but
+            # moving them past every walk would change ids, so drop them by giving them
+            # an isolated pair of fresh vertices instead (ids and endpoints of kept
+            # edges unchanged)
+            keep = g.tau <= t
+            src = np.where(keep, g.src, g.n).astype(np.int32)
+            dst = np.where(keep, g.dst, g.n + 1).astype(np.int32)
+            col = np.concatenate([g.color, [0, 0]]).astype(np.int32)
+            mask = np.ones(g.n + 2, dtype=np.uint8)
+            mask[g.n:] = 0
+            h = G.TemporalGraph(g.n + 2, src, dst, g.tau.astype(np.int32), col, g.num_colors)
+            assert pref == oracle.sieve_total(h, M, 4 + it, mask=mask), (it, t)
+
+
+def test_optimum_time_never_below_and_usually_exact():
+    rng = np.random.default_rng(83)
+    exact = total = 0
+    for it in range(60):
+        g = G.random_tiny_graph(rng, n_max=10, m_max=30, t_max=8)
+        k = int(rng.integers(2, 5))
+        M = [int(c) for c in rng.integers(0, g.num_colors, k)]
+        best = pyref.brute_optimum_time(g, M)
+        got = oracle.optimum_time(g, M, 100 + it, reps=3)
+        if best < 0:
+            assert got == -1  # no false positives
+            continue
+        total += 1
+        assert got == -1 or got >= best
+        exact += got == best
+    assert total > 10 and exact >= total - 2
+
+
 # --------------------------------------------------------------------------- one-sided error
 def test_no_false_positives():
     rng = np.random.default_rng(31)
