@@ -83,6 +83,7 @@ typedef struct {
     int64_t device_bytes;  /* device memory held by the index */
     int64_t gathers;       /* edges whose source has an earlier in-edge (rows read per level) */
     int64_t segments;      /* non-empty in-lists */
+    int64_t times;         /* distinct timestamps (length of tpm_time_buckets output) */
 } tpm_graph_stats;
 
 /* Per-call tuning.  Every admissible setting gives bit-identical results.
@@ -178,6 +179,32 @@ tpm_status tpm_decide(const tpm_graph *g, const int32_t *multiset, int32_t k, ui
  * per step.  Deterministic for a fixed seed. */
 tpm_status tpm_extract(const tpm_graph *g, const int32_t *multiset, int32_t k, uint64_t seed,
                        int32_t max_reps, int32_t *path_vertices, int64_t *path_edges);
+
+/* ------------------------------------------------------ localised sieves --- */
+/* Vertex-localised sieve (section "Vertex-localization"): q[u] = sum over all 2^k
+ * sieve points A of P_{u,k,t}(z^A), for every vertex u (q: n bytes, host).  q[u] != 0
+ * certifies a matching temporal path that ends at u; the q[u] XOR to the sieve total.
+ * Computed from the per-edge localisation (XOR over u's in-edges).  2 <= k <= 16;
+ * vertex_mask as tpm_sieve.  Errors: TPM_EINVAL, TPM_ENOMEM, TPM_EDEVICE. */
+tpm_status tpm_sieve_vertex(const tpm_graph *g, const int32_t *multiset, int32_t k, uint64_t seed,
+                            const uint8_t *vertex_mask, uint8_t *q);
+
+/* The sieve split by the time of a walk's last edge: times[i] = i-th distinct
+ * timestamp (ascending), buckets[i] = XOR of the per-edge localisation over the
+ * edges with timestamp times[i].  The XOR of buckets[0..i] is the sieve over walks
+ * whose edges all have timestamps <= times[i].  Both arrays hold
+ * tpm_graph_stats.times entries (host).  2 <= k <= 16. */
+tpm_status tpm_time_buckets(const tpm_graph *g, const int32_t *multiset, int32_t k, uint64_t seed,
+                            int32_t *times, uint8_t *buckets);
+
+/* Optimum timestamp (section "Finding optimum timestamp"): the smallest t such that
+ * the sieve over walks finishing by t is nonzero, minimised over `reps` seeds
+ * seed_r = seed + r * 0x9E3779B97F4A7C15 (one localised sieve per seed instead of a
+ * binary search of decides); *t_out = -1 if no seed found a path.  A returned t is
+ * certain (a matching path with all timestamps <= t exists); it exceeds the optimum
+ * only if every seed misses the optimal paths (one-sided error, as decide). */
+tpm_status tpm_optimum_time(const tpm_graph *g, const int32_t *multiset, int32_t k, uint64_t seed,
+                            int32_t reps, int32_t *t_out);
 
 /* ---------------------------------------------------------------- batch --- */
 typedef struct {

@@ -417,6 +417,7 @@ tpm_status tpm_graph_stats_get(const tpm_graph *g, tpm_graph_stats *out) {
         out->device_bytes = G.device_bytes;
         out->gathers = G.gathers;
         out->segments = G.segments;
+        out->times = G.ntimes;
         return TPM_OK;
     });
 }

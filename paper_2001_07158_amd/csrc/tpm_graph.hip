@@ -180,6 +180,8 @@ void free_graph(Graph &G) {
     }
     if (G.lds_image) (void)hipFree(G.lds_image);
     G.lds_image = nullptr;
+    if (G.ttab) (void)hipFree(G.ttab);
+    G.ttab = nullptr;
 }
 
 void build_graph(Graph &G, int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
@@ -225,12 +227,13 @@ void build_graph(Graph &G, int32_t n, int64_t m, const int32_t *src, const int32
     int64_t tmp = 0;
     uint64_t *keys = nullptr, *keys2 = nullptr;
     int32_t *vals = nullptr, *vals2 = nullptr, *gpos = nullptr, *needed = nullptr,
-            *rowof = nullptr;
+            *rowof = nullptr, *tsort = nullptr, *tuniq = nullptr;
+    int64_t *tcount = nullptr;
     void *scratch = nullptr;
     auto cleanup_tmp = [&]() {
         for (void *p : {(void *)d_src, (void *)d_dst, (void *)d_tau, (void *)keys, (void *)keys2,
                         (void *)vals, (void *)vals2, (void *)gpos, (void *)needed, (void *)rowof,
-                        scratch})
+                        (void *)tsort, (void *)tuniq, (void *)tcount, scratch})
             if (p) (void)hipFree(p);
     };
     try {
@@ -292,6 +295,35 @@ void build_graph(Graph &G, int32_t n, int64_t m, const int32_t *src, const int32
             keys2 = nullptr;
             (void)hipFree(scratch);
             scratch = nullptr;
+        }
+        if (m) {
+            // ---- distinct timestamps, ascending (per-time splits of the sieve)
+            const int tbits = bits_for((uint64_t)tmax);
+            tsort = dalloc<int32_t>(m, tmp);
+            tuniq = dalloc<int32_t>(m, tmp);
+            tcount = dalloc<int64_t>(1, tmp);
+            size_t sbytes = 0, ubytes = 0;
+            TPM_HIP(rocprim::radix_sort_keys(nullptr, sbytes, d_tau, tsort, (size_t)m, 0,
+                                             (unsigned)tbits, st));
+            TPM_HIP(rocprim::unique(nullptr, ubytes, tsort, tuniq, tcount, (size_t)m,
+                                    rocprim::equal_to<int32_t>(), st));
+            TPM_HIP(hipMalloc(&scratch, std::max<size_t>(std::max(sbytes, ubytes), 16)));
+            TPM_HIP(rocprim::radix_sort_keys(scratch, sbytes, d_tau, tsort, (size_t)m, 0,
+                                             (unsigned)tbits, st));
+            TPM_HIP(rocprim::unique(scratch, ubytes, tsort, tuniq, tcount, (size_t)m,
+                                    rocprim::equal_to<int32_t>(), st));
+            int64_t nt = 0;
+            TPM_HIP(hipMemcpy(&nt, tcount, sizeof(nt), hipMemcpyDeviceToHost));
+            G.ntimes = nt;
+            G.ttab = dalloc<int32_t>(nt, acct);
+            TPM_HIP(hipMemcpy(G.ttab, tuniq, sizeof(int32_t) * (size_t)nt, hipMemcpyDeviceToDevice));
+            G.h_ttab.resize((size_t)nt);
+            TPM_HIP(hipMemcpy(G.h_ttab.data(), tuniq, sizeof(int32_t) * (size_t)nt,
+                              hipMemcpyDeviceToHost));
+            for (void **q : {(void **)&tsort, (void **)&tuniq, (void **)&tcount, &scratch}) {
+                (void)hipFree(*q);
+                *q = nullptr;
+            }
         }
         k_inptr<<<grid_for(m + 1), 256, 0, st>>>(m, n, G.pdst, G.inptr);
         if (m) {

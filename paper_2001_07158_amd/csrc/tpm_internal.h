@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <new>
+#include <stdexcept>
 #include <string>
 #include <vector>
 
@@ -18,6 +20,44 @@ void clear_error();
 struct Error {
     tpm_status code;
     std::string msg;
+};
+
+// Runs an entry point body: exceptions become status codes and tpm_last_error text.
+template <class F>
+tpm_status guarded_call(F &&f) {
+    try {
+        clear_error();
+        return f();
+    } catch (const Error &e) {
+        set_error(e.msg);
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        set_error("host allocation failed");
+        return TPM_ENOMEM;
+    } catch (const std::exception &e) {
+        set_error(e.what());
+        return TPM_EDEVICE;
+    } catch (...) {
+        set_error("unknown error");
+        return TPM_EDEVICE;
+    }
+}
+
+// Makes `dev` current for a scope (restores the previous device).
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) == hipSuccess && prev != dev) {
+            if (hipSetDevice(dev) != hipSuccess) prev = -1;
+        } else {
+            prev = -1;
+        }
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+    DeviceGuard(const DeviceGuard &) = delete;
+    DeviceGuard &operator=(const DeviceGuard &) = delete;
 };
 
 #define TPM_HIP(expr)                                                                 \
@@ -91,7 +131,7 @@ struct DBuf {
 
 // Device memory of one sieve call: level buffers, per-vertex rows, control words.
 struct Workspace {
-    DBuf ctl, z, xt, s0, s1, pub, pp, tot, mask, loc, pick, tabs;
+    DBuf ctl, z, xt, s0, s1, pub, pp, tot, mask, loc, pick, tabs, aux, aux2;
 };
 
 // Workspaces of a graph: a call takes one (creating it if none is free) and
@@ -139,6 +179,8 @@ struct Graph {
     int32_t *tile_pub = nullptr;  // [ntiles] slot this tile publishes to, -1 if none
     int32_t *tile_lb = nullptr;   // [ntiles] slot its look-back starts at, -1 if none
     uint8_t *lds_image = nullptr; // [kLdsBytes]
+    int32_t *ttab = nullptr;      // [ntimes] distinct timestamps, ascending
+    int64_t ntimes = 0;
 
     WorkspacePool *pool = nullptr;  // owned
 
@@ -146,6 +188,7 @@ struct Graph {
     std::vector<int32_t> h_inptr;   // [n+1]
     std::vector<int32_t> h_color;   // [n]
     std::vector<int32_t> h_tile_p0; // [ntiles+1]
+    std::vector<int32_t> h_ttab;    // [ntimes]
 };
 
 // Builds all of the above; throws Error.
@@ -181,6 +224,19 @@ struct SieveResult {
 };
 
 void run_sieve(const Graph &G, const SieveRequest &req, SieveResult &res, hipStream_t stream);
+
+// Consumes the per-position localisation of a sieve (positions [lo, hi), device
+// memory) on the sieve's stream, before the call's final synchronisation; results go
+// to host memory the sink owns (copied asynchronously on st).  Scratch: ws.aux, ws.aux2.
+struct LocSink {
+    virtual ~LocSink() = default;
+    virtual void consume(const Graph &G, Workspace &ws, const uint8_t *dloc, int64_t lo,
+                         int64_t hi, hipStream_t st) = 0;
+};
+// Sieve with localisation over the positions req.fin_lo..fin_hi (all when empty),
+// handed to `sink`.
+void run_sieve_sink(const Graph &G, const SieveRequest &req, SieveResult &res, LocSink &sink,
+                    hipStream_t st);
 
 // Per-edge localisation over all edges, indexed by input edge id.
 void run_sieve_loc_all(const Graph &G, const SieveRequest &req, SieveResult &res,

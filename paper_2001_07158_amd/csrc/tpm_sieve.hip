@@ -922,7 +922,7 @@ int pick_chunk(const Graph &G, int32_t k, int32_t requested) {
 // the contributing position with nonzero localisation and the smallest input edge id
 // (-1 if none).
 void run_sieve_impl(const Graph &G, const SieveRequest &req, SieveResult &res, bool want_loc,
-                    uint8_t *loc_host, hipStream_t st) {
+                    uint8_t *loc_host, hipStream_t st, LocSink *sink = nullptr) {
     const int32_t k = req.k;
     QuerySlots qs = make_slots(G, req.multiset, k);
     const int64_t npts = int64_t(1) << k;
@@ -1030,6 +1030,7 @@ void run_sieve_impl(const Graph &G, const SieveRequest &req, SieveResult &res, b
                                                   pick.as<unsigned long long>());
         TPM_HIP(hipMemcpyAsync(&hpick, pick.p, sizeof(hpick), hipMemcpyDeviceToHost, st));
     }
+    if (sink && want_loc) sink->consume(G, ws, loc.as<uint8_t>(), lo, hi, st);
     TPM_HIP(hipGetLastError());
     res.per_point.resize((size_t)npts);
     Ctl hctl{};
@@ -1053,6 +1054,11 @@ void run_sieve_impl(const Graph &G, const SieveRequest &req, SieveResult &res, b
 
 void run_sieve(const Graph &G, const SieveRequest &req, SieveResult &res, hipStream_t st) {
     run_sieve_impl(G, req, res, req.want_pick, nullptr, st);
+}
+
+void run_sieve_sink(const Graph &G, const SieveRequest &req, SieveResult &res, LocSink &sink,
+                    hipStream_t st) {
+    run_sieve_impl(G, req, res, true, nullptr, st, &sink);
 }
 
 void run_sieve_loc_all(const Graph &G, const SieveRequest &req, SieveResult &res,

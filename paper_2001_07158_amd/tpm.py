@@ -46,7 +46,7 @@ class tpm_graph_stats(ctypes.Structure):
                 ("tmax", ctypes.c_int32), ("rows", ctypes.c_int64), ("tiles", ctypes.c_int64),
                 ("slots", ctypes.c_int64), ("max_in_degree", ctypes.c_int64),
                 ("device_bytes", ctypes.c_int64), ("gathers", ctypes.c_int64),
-                ("segments", ctypes.c_int64)]
+                ("segments", ctypes.c_int64), ("times", ctypes.c_int64)]
 
 
 class tpm_kernel_time(ctypes.Structure):
@@ -98,6 +98,10 @@ _sig("tpm_graph_create_ex", ctypes.c_int32,
 _sig("tpm_graph_destroy", None, [_vp])
 _sig("tpm_graph_stats_get", ctypes.c_int32, [_vp, ctypes.POINTER(tpm_graph_stats)])
 _sig("tpm_graph_retile", ctypes.c_int32, [_vp, ctypes.c_int32])
+_sig("tpm_sieve_vertex", ctypes.c_int32, [_vp, _i32p, ctypes.c_int32, ctypes.c_uint64, _u8p, _u8p])
+_sig("tpm_time_buckets", ctypes.c_int32, [_vp, _i32p, ctypes.c_int32, ctypes.c_uint64, _i32p, _u8p])
+_sig("tpm_optimum_time", ctypes.c_int32, [_vp, _i32p, ctypes.c_int32, ctypes.c_uint64,
+                                         ctypes.c_int32, _i32p])
 _sig("tpm_autotune", ctypes.c_int32, [_vp, ctypes.c_int32, ctypes.c_uint64,
                                      ctypes.POINTER(tpm_autotune_report)])
 _sig("tpm_sieve", ctypes.c_int32, [_vp, _i32p, ctypes.c_int32, ctypes.c_uint64, _u8p, _u8p, _u8p,
@@ -121,7 +125,8 @@ _sig("tpm_last_error", ctypes.c_char_p, [])
 _sig("tpm_version", ctypes.c_char_p, [])
 
 EXPORTED = ["tpm_graph_create", "tpm_graph_create_ex", "tpm_graph_destroy", "tpm_graph_stats_get",
-            "tpm_graph_retile", "tpm_autotune",
+            "tpm_graph_retile", "tpm_autotune", "tpm_sieve_vertex", "tpm_time_buckets",
+            "tpm_optimum_time",
             "tpm_sieve", "tpm_sieve_ex", "tpm_decide", "tpm_extract", "tpm_batch_run",
             "tpm_server_create", "tpm_server_submit", "tpm_server_poll", "tpm_server_destroy",
             "tpm_profile_enable", "tpm_profile_read", "tpm_last_error", "tpm_version"]
@@ -254,6 +259,34 @@ def _result_dict(r: tpm_result) -> dict:
             "t_done_ms": r.t_done_ms}
 
 
+def tpm_sieve_vertex(h, multiset, seed, mask=None):
+    st = tpm_graph_stats_get(h)
+    M = _i32(multiset)
+    q = np.empty(st["n"], dtype=np.uint8)
+    mk = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8)
+    _check(_lib.tpm_sieve_vertex(h, _ptr(M, _i32p), len(M), int(seed) & (2**64 - 1),
+                                 _ptr(mk, _u8p), _ptr(q, _u8p)))
+    return q
+
+
+def tpm_time_buckets(h, multiset, seed):
+    st = tpm_graph_stats_get(h)
+    M = _i32(multiset)
+    times = np.empty(st["times"], dtype=np.int32)
+    b = np.empty(st["times"], dtype=np.uint8)
+    _check(_lib.tpm_time_buckets(h, _ptr(M, _i32p), len(M), int(seed) & (2**64 - 1),
+                                 _ptr(times, _i32p), _ptr(b, _u8p)))
+    return times, b
+
+
+def tpm_optimum_time(h, multiset, seed, reps=1) -> int:
+    M = _i32(multiset)
+    t = ctypes.c_int32(0)
+    _check(_lib.tpm_optimum_time(h, _ptr(M, _i32p), len(M), int(seed) & (2**64 - 1),
+                                 int(reps), ctypes.byref(t)))
+    return int(t.value)
+
+
 def tpm_graph_retile(h, tile_edges) -> None:
     _check(_lib.tpm_graph_retile(h, int(tile_edges)))
 
@@ -340,6 +373,15 @@ class Graph:
 
     def batch(self, queries, chunk=0, use_graph=False):
         return tpm_batch_run(self.h, queries, chunk, use_graph)
+
+    def sieve_vertex(self, multiset, seed, mask=None):
+        return tpm_sieve_vertex(self.h, multiset, seed, mask)
+
+    def time_buckets(self, multiset, seed):
+        return tpm_time_buckets(self.h, multiset, seed)
+
+    def optimum_time(self, multiset, seed, reps=1) -> int:
+        return tpm_optimum_time(self.h, multiset, seed, reps)
 
     def retile(self, tile_edges) -> None:
         tpm_graph_retile(self.h, tile_edges)

@@ -85,7 +85,8 @@ def test_null_handles_are_errors():
         tpm.tpm_graph_stats_get(None)
     with pytest.raises(tpm.TpmError):
         tpm.tpm_decide(None, [0, 1], 1)
-    for call in (lambda: tpm.tpm_graph_retile(None, 256), lambda: tpm.tpm_autotune(None, 4)):
+    for call in (lambda: tpm.tpm_graph_retile(None, 256), lambda: tpm.tpm_autotune(None, 4),
+                 lambda: tpm.tpm_optimum_time(None, [0, 1], 1)):
         with pytest.raises(tpm.TpmError) as ei:
             call()
         assert ei.value.code == tpm.TPM_EINVAL
