@@ -84,6 +84,8 @@ typedef struct {
     int64_t gathers;       /* edges whose source has an earlier in-edge (rows read per level) */
     int64_t segments;      /* non-empty in-lists */
     int64_t times;         /* distinct timestamps (length of tpm_time_buckets output) */
+    int64_t edge_ids;      /* input edge ids are < edge_ids: m, or the parent's m for a
+                              graph made by tpm_graph_prune */
 } tpm_graph_stats;
 
 /* Per-call tuning.  Every admissible setting gives bit-identical results.
@@ -138,6 +140,17 @@ typedef struct {
 } tpm_autotune_report;
 tpm_status tpm_autotune(tpm_graph *g, int32_t k, uint64_t seed, tpm_autotune_report *out);
 
+/* Colour pruning (the paper's preprocessing step (i), section "Implementation"): a
+ * new graph holding the edges of g whose two endpoints both have a colour in
+ * colors[0..ncolors).  Vertex ids, colours and input edge ids (those of g) are kept,
+ * so for a multiset whose colours are all in the set every result (per-point values,
+ * totals, localisation, extraction) equals g's bit for bit: a vertex of another
+ * colour has z = 0 and no walk through it contributes.  Built on the device from
+ * g's sorted index (no sort).  The new graph is independent of g afterwards.
+ * Errors: TPM_EINVAL (colour out of range, ncolors < 1), TPM_ENOMEM, TPM_EDEVICE. */
+tpm_status tpm_graph_prune(const tpm_graph *g, const int32_t *colors, int32_t ncolors,
+                           tpm_graph **out);
+
 /* Free a graph and everything it owns.  NULL is accepted. */
 void tpm_graph_destroy(tpm_graph *g);
 
@@ -157,9 +170,10 @@ tpm_status tpm_sieve(const tpm_graph *g, const int32_t *multiset, int32_t k, uin
                      void *hip_stream);
 
 /* As tpm_sieve, plus tuning (nullable) and the per-edge localisation
- * loc[e] = sum over A of the level-k term of edge e (nullable, m bytes, indexed by
- * input edge id): loc[e] != 0 certifies a matching path whose last edge is e
- * (the edge-level form of the paper's vertex-localisation). */
+ * loc[e] = sum over A of the level-k term of edge e (nullable; tpm_graph_stats.edge_ids
+ * bytes indexed by input edge id, zero for ids not in the graph): loc[e] != 0
+ * certifies a matching path whose last edge is e (the edge-level form of the
+ * paper's vertex-localisation). */
 tpm_status tpm_sieve_ex(const tpm_graph *g, const int32_t *multiset, int32_t k, uint64_t seed,
                         const uint8_t *vertex_mask, const tpm_tuning *tune, uint8_t *per_point,
                         uint8_t *total, uint8_t *loc, void *hip_stream);

@@ -328,6 +328,31 @@ void tpm_graph_destroy(tpm_graph *g) {
     delete g;
 }
 
+tpm_status tpm_graph_prune(const tpm_graph *g, const int32_t *colors, int32_t ncolors,
+                           tpm_graph **out) {
+    return guarded([&]() -> tpm_status {
+        TPM_REQUIRE(g && colors && out, "NULL argument");
+        *out = nullptr;
+        TPM_REQUIRE(ncolors >= 1, "ncolors must be >= 1");
+        std::vector<uint8_t> keep((size_t)g->G.q, 0);
+        for (int32_t i = 0; i < ncolors; ++i) {
+            TPM_REQUIRE(colors[i] >= 0 && colors[i] < g->G.q, "colour out of range");
+            keep[(size_t)colors[i]] = 1;
+        }
+        DeviceScope ds(g->G.device);
+        auto *h = new tpm_graph();
+        try {
+            prune_graph(g->G, keep.data(), h->G);
+            h->G.pool = new_workspace_pool();
+        } catch (...) {
+            delete h;
+            throw;
+        }
+        *out = h;
+        return TPM_OK;
+    });
+}
+
 tpm_status tpm_graph_retile(tpm_graph *g, int32_t tile_edges) {
     return guarded([&]() -> tpm_status {
         TPM_REQUIRE(g != nullptr, "graph must not be NULL");
@@ -418,6 +443,7 @@ tpm_status tpm_graph_stats_get(const tpm_graph *g, tpm_graph_stats *out) {
         out->gathers = G.gathers;
         out->segments = G.segments;
         out->times = G.ntimes;
+        out->edge_ids = G.edge_ids;
         return TPM_OK;
     });
 }

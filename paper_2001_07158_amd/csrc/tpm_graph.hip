@@ -102,6 +102,35 @@ __global__ void k_rows(int64_t m, const int32_t *gpos, const int32_t *needed,
     gsrc[p] = q >= 0 ? rowof[q] : -1;
 }
 
+__global__ void k_count_nonneg(int64_t m, const int32_t *a, unsigned long long *out) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    unsigned long long c = 0;
+    for (; i < m; i += stride) c += a[i] >= 0;
+    for (int off = 32; off >= 1; off >>= 1) c += __shfl_xor(c, off);
+    if ((threadIdx.x & 63) == 0 && c) atomicAdd(out, c);
+}
+
+// keep[p] = 1 when both endpoints of the edge at position p have a kept colour
+__global__ void k_keep(int64_t m, const int32_t *psrc, const int32_t *pdst, const int32_t *color,
+                       const uint8_t *keepc, int32_t *keep) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < m) keep[p] = (keepc[color[psrc[p]]] && keepc[color[pdst[p]]]) ? 1 : 0;
+}
+
+__global__ void k_compact(int64_t m, const int32_t *keep, const int32_t *at, const int32_t *psrc,
+                          const int32_t *pdst, const int32_t *ptau, const int32_t *peid,
+                          int32_t *qsrc, int32_t *qdst, int32_t *qtau, int32_t *qeid) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < m && keep[p]) {
+        const int32_t q = at[p];
+        qsrc[q] = psrc[p];
+        qdst[q] = pdst[p];
+        qtau[q] = ptau[p];
+        qeid[q] = peid[p];
+    }
+}
+
 inline unsigned grid_for(int64_t work, int block = 256) {
     int64_t g = (work + block - 1) / block;
     return (unsigned)std::max<int64_t>(1, g);
@@ -184,6 +213,145 @@ void free_graph(Graph &G) {
     G.ttab = nullptr;
 }
 
+// Everything of the index that follows from the CSR arrays (pdst, psrc, ptau, peid
+// sorted by (dst, tau, input id)), G.color and G.tmax: distinct timestamps, in-list
+// offsets, gathered and stored rows, host copies, tiles and the LDS image.  taus:
+// the m timestamps in any order (device).
+void finish_index(Graph &G, int64_t &acct, const int32_t *taus) {
+    const int64_t m = G.m;
+    const int32_t n = G.n;
+    const int32_t tmax = G.tmax;
+    const int32_t T = G.tile_edges;
+    hipStream_t st = nullptr;
+    int64_t tmp = 0;
+    int32_t *gpos = nullptr, *needed = nullptr, *rowof = nullptr, *tsort = nullptr,
+            *tuniq = nullptr;
+    int64_t *tcount = nullptr;
+    unsigned long long *cnt = nullptr;
+    void *scratch = nullptr;
+    auto cleanup = [&]() {
+        for (void *p : {(void *)gpos, (void *)needed, (void *)rowof, (void *)tsort, (void *)tuniq,
+                        (void *)tcount, (void *)cnt, scratch})
+            if (p) (void)hipFree(p);
+    };
+    try {
+        if (m) {
+            // ---- distinct timestamps, ascending (per-time splits of the sieve)
+            const int tbits = bits_for((uint64_t)tmax);
+            tsort = dalloc<int32_t>(m, tmp);
+            tuniq = dalloc<int32_t>(m, tmp);
+            tcount = dalloc<int64_t>(1, tmp);
+            size_t sbytes = 0, ubytes = 0;
+            TPM_HIP(rocprim::radix_sort_keys(nullptr, sbytes, taus, tsort, (size_t)m, 0,
+                                             (unsigned)tbits, st));
+            TPM_HIP(rocprim::unique(nullptr, ubytes, tsort, tuniq, tcount, (size_t)m,
+                                    rocprim::equal_to<int32_t>(), st));
+            TPM_HIP(hipMalloc(&scratch, std::max<size_t>(std::max(sbytes, ubytes), 16)));
+            TPM_HIP(rocprim::radix_sort_keys(scratch, sbytes, taus, tsort, (size_t)m, 0,
+                                             (unsigned)tbits, st));
+            TPM_HIP(rocprim::unique(scratch, ubytes, tsort, tuniq, tcount, (size_t)m,
+                                    rocprim::equal_to<int32_t>(), st));
+            int64_t nt = 0;
+            TPM_HIP(hipMemcpy(&nt, tcount, sizeof(nt), hipMemcpyDeviceToHost));
+            G.ntimes = nt;
+            G.ttab = dalloc<int32_t>(nt, acct);
+            TPM_HIP(hipMemcpy(G.ttab, tuniq, sizeof(int32_t) * (size_t)nt, hipMemcpyDeviceToDevice));
+            G.h_ttab.resize((size_t)nt);
+            TPM_HIP(hipMemcpy(G.h_ttab.data(), tuniq, sizeof(int32_t) * (size_t)nt,
+                              hipMemcpyDeviceToHost));
+            for (void **q : {(void **)&tsort, (void **)&tuniq, (void **)&tcount, &scratch}) {
+                (void)hipFree(*q);
+                *q = nullptr;
+            }
+        }
+        k_inptr<<<grid_for(m + 1), 256, 0, st>>>(m, n, G.pdst, G.inptr);
+        if (m) {
+            gpos = dalloc<int32_t>(m, tmp);
+            needed = dalloc<int32_t>(m, tmp);
+            rowof = dalloc<int32_t>(m, tmp);
+            TPM_HIP(hipMemsetAsync(needed, 0, sizeof(int32_t) * m, st));
+            k_gpos<<<grid_for(m), 256, 0, st>>>(m, G.psrc, G.ptau, G.inptr, gpos, needed);
+            size_t sbytes = 0;
+            TPM_HIP(rocprim::exclusive_scan(nullptr, sbytes, needed, rowof, 0, (size_t)m,
+                                            rocprim::plus<int32_t>(), st));
+            TPM_HIP(hipMalloc(&scratch, std::max<size_t>(sbytes, 16)));
+            TPM_HIP(rocprim::exclusive_scan(scratch, sbytes, needed, rowof, 0, (size_t)m,
+                                            rocprim::plus<int32_t>(), st));
+            k_rows<<<grid_for(m), 256, 0, st>>>(m, gpos, needed, rowof, G.orow, G.gsrc);
+            int32_t last_row = 0, last_needed = 0;
+            TPM_HIP(hipMemcpy(&last_row, rowof + (m - 1), sizeof(int32_t), hipMemcpyDeviceToHost));
+            TPM_HIP(hipMemcpy(&last_needed, needed + (m - 1), sizeof(int32_t),
+                              hipMemcpyDeviceToHost));
+            G.R = (int64_t)last_row + last_needed;
+        }
+        G.h_color.resize((size_t)n);
+        TPM_HIP(hipMemcpy(G.h_color.data(), G.color, sizeof(int32_t) * (size_t)n,
+                          hipMemcpyDeviceToHost));
+        G.h_inptr.resize((size_t)n + 1);
+        TPM_HIP(hipMemcpy(G.h_inptr.data(), G.inptr, sizeof(int32_t) * ((size_t)n + 1),
+                          hipMemcpyDeviceToHost));
+        for (int32_t u = 0; u < n; ++u) {
+            int64_t d = G.h_inptr[u + 1] - G.h_inptr[u];
+            G.max_in_degree = std::max<int64_t>(G.max_in_degree, d);
+            G.segments += d > 0;
+        }
+        if (m) {
+            cnt = dalloc<unsigned long long>(1, tmp);
+            TPM_HIP(hipMemsetAsync(cnt, 0, sizeof(unsigned long long), st));
+            k_count_nonneg<<<std::min<unsigned>(grid_for(m), 4096), 256, 0, st>>>(m, G.gsrc, cnt);
+            unsigned long long h = 0;
+            TPM_HIP(hipMemcpy(&h, cnt, sizeof(h), hipMemcpyDeviceToHost));
+            G.gathers = (int64_t)h;
+        }
+
+        {
+            std::vector<int32_t> sn((size_t)n, -1);
+            int32_t nextv = -1;
+            for (int32_t u = n - 1; u >= 0; --u) {
+                sn[u] = nextv;
+                if (G.h_inptr[u + 1] > G.h_inptr[u]) nextv = u;
+            }
+            G.segnext = dalloc<int32_t>(n, acct);
+            TPM_HIP(hipMemcpy(G.segnext, sn.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice));
+        }
+        std::vector<int32_t> tp0, tpub, tlb;
+        build_tiles(G.h_inptr, T, tp0, tpub, tlb, G.nslots);
+        G.ntiles = (int64_t)tpub.size();
+        G.h_tile_p0 = tp0;
+        G.tile_p0 = dalloc<int32_t>(G.ntiles + 1, acct);
+        G.tile_pub = dalloc<int32_t>(G.ntiles, acct);
+        G.tile_lb = dalloc<int32_t>(G.ntiles, acct);
+        TPM_HIP(hipMemcpy(G.tile_p0, tp0.data(), sizeof(int32_t) * tp0.size(),
+                          hipMemcpyHostToDevice));
+        if (G.ntiles) {
+            TPM_HIP(hipMemcpy(G.tile_pub, tpub.data(), sizeof(int32_t) * tpub.size(),
+                              hipMemcpyHostToDevice));
+            TPM_HIP(hipMemcpy(G.tile_lb, tlb.data(), sizeof(int32_t) * tlb.size(),
+                              hipMemcpyHostToDevice));
+        }
+
+        // ---- LDS table image (see kLdsBytes)
+        std::vector<uint8_t> img(kLdsBytes, 0);
+        auto put32 = [&](size_t off, uint32_t v) { std::memcpy(img.data() + off, &v, 4); };
+        for (int v = 0; v < 256; ++v) {
+            uint32_t l7 = v ? ((uint32_t)kGf.log[v] << 7) : kZero7;
+            for (int c = 0; c < 32; ++c) put32((size_t)v * 256 + c * 4, l7);
+        }
+        for (int s = 0; s < kExpRows; ++s) {
+            uint32_t e = (s <= 762) ? kGf.exp[s % 255] : 0u;
+            for (int c = 0; c < 32; ++c) put32((size_t)kExpBase + (size_t)s * 128 + c * 4, e);
+        }
+        G.lds_image = (uint8_t *)dalloc<uint8_t>(kLdsBytes, acct);
+        TPM_HIP(hipMemcpy(G.lds_image, img.data(), kLdsBytes, hipMemcpyHostToDevice));
+        TPM_HIP(hipDeviceSynchronize());
+        TPM_HIP(hipDeviceSynchronize());
+    } catch (...) {
+        cleanup();
+        throw;
+    }
+    cleanup();
+}
+
 void build_graph(Graph &G, int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
                  const int32_t *tau, const int32_t *color, int32_t num_colors, uint32_t flags,
                  const tpm_graph_options *opt) {
@@ -220,20 +388,18 @@ void build_graph(Graph &G, int32_t n, int64_t m, const int32_t *src, const int32
     G.m = m;
     G.q = num_colors;
     G.tile_edges = T;
+    G.edge_ids = m;
     int64_t acct = 0;
     hipStream_t st = nullptr;
 
     int32_t *d_src = nullptr, *d_dst = nullptr, *d_tau = nullptr;
     int64_t tmp = 0;
     uint64_t *keys = nullptr, *keys2 = nullptr;
-    int32_t *vals = nullptr, *vals2 = nullptr, *gpos = nullptr, *needed = nullptr,
-            *rowof = nullptr, *tsort = nullptr, *tuniq = nullptr;
-    int64_t *tcount = nullptr;
+    int32_t *vals = nullptr, *vals2 = nullptr;
     void *scratch = nullptr;
     auto cleanup_tmp = [&]() {
         for (void *p : {(void *)d_src, (void *)d_dst, (void *)d_tau, (void *)keys, (void *)keys2,
-                        (void *)vals, (void *)vals2, (void *)gpos, (void *)needed, (void *)rowof,
-                        (void *)tsort, (void *)tuniq, (void *)tcount, scratch})
+                        (void *)vals, (void *)vals2, scratch})
             if (p) (void)hipFree(p);
     };
     try {
@@ -296,113 +462,7 @@ void build_graph(Graph &G, int32_t n, int64_t m, const int32_t *src, const int32
             (void)hipFree(scratch);
             scratch = nullptr;
         }
-        if (m) {
-            // ---- distinct timestamps, ascending (per-time splits of the sieve)
-            const int tbits = bits_for((uint64_t)tmax);
-            tsort = dalloc<int32_t>(m, tmp);
-            tuniq = dalloc<int32_t>(m, tmp);
-            tcount = dalloc<int64_t>(1, tmp);
-            size_t sbytes = 0, ubytes = 0;
-            TPM_HIP(rocprim::radix_sort_keys(nullptr, sbytes, d_tau, tsort, (size_t)m, 0,
-                                             (unsigned)tbits, st));
-            TPM_HIP(rocprim::unique(nullptr, ubytes, tsort, tuniq, tcount, (size_t)m,
-                                    rocprim::equal_to<int32_t>(), st));
-            TPM_HIP(hipMalloc(&scratch, std::max<size_t>(std::max(sbytes, ubytes), 16)));
-            TPM_HIP(rocprim::radix_sort_keys(scratch, sbytes, d_tau, tsort, (size_t)m, 0,
-                                             (unsigned)tbits, st));
-            TPM_HIP(rocprim::unique(scratch, ubytes, tsort, tuniq, tcount, (size_t)m,
-                                    rocprim::equal_to<int32_t>(), st));
-            int64_t nt = 0;
-            TPM_HIP(hipMemcpy(&nt, tcount, sizeof(nt), hipMemcpyDeviceToHost));
-            G.ntimes = nt;
-            G.ttab = dalloc<int32_t>(nt, acct);
-            TPM_HIP(hipMemcpy(G.ttab, tuniq, sizeof(int32_t) * (size_t)nt, hipMemcpyDeviceToDevice));
-            G.h_ttab.resize((size_t)nt);
-            TPM_HIP(hipMemcpy(G.h_ttab.data(), tuniq, sizeof(int32_t) * (size_t)nt,
-                              hipMemcpyDeviceToHost));
-            for (void **q : {(void **)&tsort, (void **)&tuniq, (void **)&tcount, &scratch}) {
-                (void)hipFree(*q);
-                *q = nullptr;
-            }
-        }
-        k_inptr<<<grid_for(m + 1), 256, 0, st>>>(m, n, G.pdst, G.inptr);
-        if (m) {
-            gpos = vals;  // reuse
-            vals = nullptr;
-            needed = dalloc<int32_t>(m, tmp);
-            rowof = dalloc<int32_t>(m, tmp);
-            TPM_HIP(hipMemsetAsync(needed, 0, sizeof(int32_t) * m, st));
-            k_gpos<<<grid_for(m), 256, 0, st>>>(m, G.psrc, G.ptau, G.inptr, gpos, needed);
-            size_t sbytes = 0;
-            TPM_HIP(rocprim::exclusive_scan(nullptr, sbytes, needed, rowof, 0, (size_t)m,
-                                            rocprim::plus<int32_t>(), st));
-            TPM_HIP(hipMalloc(&scratch, std::max<size_t>(sbytes, 16)));
-            TPM_HIP(rocprim::exclusive_scan(scratch, sbytes, needed, rowof, 0, (size_t)m,
-                                            rocprim::plus<int32_t>(), st));
-            k_rows<<<grid_for(m), 256, 0, st>>>(m, gpos, needed, rowof, G.orow, G.gsrc);
-            int32_t last_row = 0, last_needed = 0;
-            TPM_HIP(hipMemcpy(&last_row, rowof + (m - 1), sizeof(int32_t), hipMemcpyDeviceToHost));
-            TPM_HIP(hipMemcpy(&last_needed, needed + (m - 1), sizeof(int32_t),
-                              hipMemcpyDeviceToHost));
-            G.R = (int64_t)last_row + last_needed;
-        }
-        G.h_color.resize((size_t)n);
-        TPM_HIP(hipMemcpy(G.h_color.data(), G.color, sizeof(int32_t) * (size_t)n,
-                          hipMemcpyDeviceToHost));
-        G.h_inptr.resize((size_t)n + 1);
-        TPM_HIP(hipMemcpy(G.h_inptr.data(), G.inptr, sizeof(int32_t) * ((size_t)n + 1),
-                          hipMemcpyDeviceToHost));
-        for (int32_t u = 0; u < n; ++u) {
-            int64_t d = G.h_inptr[u + 1] - G.h_inptr[u];
-            G.max_in_degree = std::max<int64_t>(G.max_in_degree, d);
-            G.segments += d > 0;
-        }
-        if (m) {
-            std::vector<int32_t> gs((size_t)m);
-            TPM_HIP(hipMemcpy(gs.data(), G.gsrc, sizeof(int32_t) * m, hipMemcpyDeviceToHost));
-            for (int64_t i = 0; i < m; ++i) G.gathers += gs[i] >= 0;
-        }
-
-        {
-            std::vector<int32_t> sn((size_t)n, -1);
-            int32_t nextv = -1;
-            for (int32_t u = n - 1; u >= 0; --u) {
-                sn[u] = nextv;
-                if (G.h_inptr[u + 1] > G.h_inptr[u]) nextv = u;
-            }
-            G.segnext = dalloc<int32_t>(n, acct);
-            TPM_HIP(hipMemcpy(G.segnext, sn.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice));
-        }
-        std::vector<int32_t> tp0, tpub, tlb;
-        build_tiles(G.h_inptr, T, tp0, tpub, tlb, G.nslots);
-        G.ntiles = (int64_t)tpub.size();
-        G.h_tile_p0 = tp0;
-        G.tile_p0 = dalloc<int32_t>(G.ntiles + 1, acct);
-        G.tile_pub = dalloc<int32_t>(G.ntiles, acct);
-        G.tile_lb = dalloc<int32_t>(G.ntiles, acct);
-        TPM_HIP(hipMemcpy(G.tile_p0, tp0.data(), sizeof(int32_t) * tp0.size(),
-                          hipMemcpyHostToDevice));
-        if (G.ntiles) {
-            TPM_HIP(hipMemcpy(G.tile_pub, tpub.data(), sizeof(int32_t) * tpub.size(),
-                              hipMemcpyHostToDevice));
-            TPM_HIP(hipMemcpy(G.tile_lb, tlb.data(), sizeof(int32_t) * tlb.size(),
-                              hipMemcpyHostToDevice));
-        }
-
-        // ---- LDS table image (see kLdsBytes)
-        std::vector<uint8_t> img(kLdsBytes, 0);
-        auto put32 = [&](size_t off, uint32_t v) { std::memcpy(img.data() + off, &v, 4); };
-        for (int v = 0; v < 256; ++v) {
-            uint32_t l7 = v ? ((uint32_t)kGf.log[v] << 7) : kZero7;
-            for (int c = 0; c < 32; ++c) put32((size_t)v * 256 + c * 4, l7);
-        }
-        for (int s = 0; s < kExpRows; ++s) {
-            uint32_t e = (s <= 762) ? kGf.exp[s % 255] : 0u;
-            for (int c = 0; c < 32; ++c) put32((size_t)kExpBase + (size_t)s * 128 + c * 4, e);
-        }
-        G.lds_image = (uint8_t *)dalloc<uint8_t>(kLdsBytes, acct);
-        TPM_HIP(hipMemcpy(G.lds_image, img.data(), kLdsBytes, hipMemcpyHostToDevice));
-        TPM_HIP(hipDeviceSynchronize());
+        finish_index(G, acct, d_tau);
         G.device_bytes = acct;
     } catch (...) {
         cleanup_tmp();
@@ -410,6 +470,70 @@ void build_graph(Graph &G, int32_t n, int64_t m, const int32_t *src, const int32
         throw;
     }
     cleanup_tmp();
+}
+
+void prune_graph(const Graph &P, const uint8_t *keep_color, Graph &G) {
+    TPM_HIP(hipSetDevice(P.device));
+    G.device = P.device;
+    G.num_cu = P.num_cu;
+    G.n = P.n;
+    G.q = P.q;
+    G.tmax = P.tmax;
+    G.tile_edges = P.tile_edges;
+    G.edge_ids = P.edge_ids;
+    int64_t acct = 0, tmp = 0;
+    hipStream_t st = nullptr;
+    uint8_t *keepc = nullptr;
+    int32_t *keep = nullptr, *at = nullptr;
+    void *scratch = nullptr;
+    auto cleanup = [&]() {
+        for (void *p : {(void *)keepc, (void *)keep, (void *)at, scratch})
+            if (p) (void)hipFree(p);
+    };
+    try {
+        G.color = dalloc<int32_t>(P.n, acct);
+        TPM_HIP(hipMemcpy(G.color, P.color, sizeof(int32_t) * (size_t)P.n, hipMemcpyDeviceToDevice));
+        int64_t mk = 0;
+        if (P.m) {
+            keepc = dalloc<uint8_t>(P.q, tmp);
+            TPM_HIP(hipMemcpy(keepc, keep_color, (size_t)P.q, hipMemcpyHostToDevice));
+            keep = dalloc<int32_t>(P.m, tmp);
+            at = dalloc<int32_t>(P.m, tmp);
+            k_keep<<<grid_for(P.m), 256, 0, st>>>(P.m, P.psrc, P.pdst, P.color, keepc, keep);
+            size_t sbytes = 0;
+            TPM_HIP(rocprim::exclusive_scan(nullptr, sbytes, keep, at, 0, (size_t)P.m,
+                                            rocprim::plus<int32_t>(), st));
+            TPM_HIP(hipMalloc(&scratch, std::max<size_t>(sbytes, 16)));
+            TPM_HIP(rocprim::exclusive_scan(scratch, sbytes, keep, at, 0, (size_t)P.m,
+                                            rocprim::plus<int32_t>(), st));
+            int32_t last_at = 0, last_keep = 0;
+            TPM_HIP(hipMemcpy(&last_at, at + (P.m - 1), sizeof(int32_t), hipMemcpyDeviceToHost));
+            TPM_HIP(hipMemcpy(&last_keep, keep + (P.m - 1), sizeof(int32_t), hipMemcpyDeviceToHost));
+            mk = (int64_t)last_at + last_keep;
+        }
+        G.m = mk;
+        G.pdst = dalloc<int32_t>(mk, acct);
+        G.psrc = dalloc<int32_t>(mk, acct);
+        G.ptau = dalloc<int32_t>(mk, acct);
+        G.peid = dalloc<int32_t>(mk, acct);
+        G.gsrc = dalloc<int32_t>(mk, acct);
+        G.orow = dalloc<int32_t>(mk, acct);
+        G.inptr = dalloc<int32_t>((int64_t)G.n + 1, acct);
+        if (mk)  // kept positions stay in (dst, tau, id) order
+            k_compact<<<grid_for(P.m), 256, 0, st>>>(P.m, keep, at, P.psrc, P.pdst, P.ptau, P.peid,
+                                                      G.psrc, G.pdst, G.ptau, G.peid);
+        TPM_HIP(hipDeviceSynchronize());
+        cleanup();
+        keepc = nullptr;
+        keep = at = nullptr;
+        scratch = nullptr;
+        finish_index(G, acct, G.ptau);
+        G.device_bytes = acct;
+    } catch (...) {
+        cleanup();
+        free_graph(G);
+        throw;
+    }
 }
 
 void retile_graph(Graph &G, int32_t T) {

@@ -181,6 +181,8 @@ struct Graph {
     uint8_t *lds_image = nullptr; // [kLdsBytes]
     int32_t *ttab = nullptr;      // [ntimes] distinct timestamps, ascending
     int64_t ntimes = 0;
+    int64_t edge_ids = 0;         // input edge ids are < edge_ids (m, or the parent's m
+                                  // for a colour-pruned graph)
 
     WorkspacePool *pool = nullptr;  // owned
 
@@ -199,6 +201,11 @@ void free_graph(Graph &G);
 // Rebuilds the work tiles with at most T positions each (results do not depend on
 // T).  Waits for the device; must not overlap other calls on the same graph.
 void retile_graph(Graph &G, int32_t T);
+// Builds G as the subgraph of P on the edges whose two endpoints have a colour c with
+// keep_color[c] != 0 (host, P.q bytes).  Vertex ids, colours and input edge ids are
+// kept, so every fingerprint, and every sieve whose colours are all kept, is
+// unchanged.  G must be empty; on error G is freed.
+void prune_graph(const Graph &P, const uint8_t *keep_color, Graph &G);
 
 // ------------------------------------------------------------------ sieve
 struct SieveRequest {

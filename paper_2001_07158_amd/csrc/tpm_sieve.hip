@@ -1068,6 +1068,7 @@ void run_sieve_loc_all(const Graph &G, const SieveRequest &req, SieveResult &res
     r2.fin_lo = 0;
     r2.fin_hi = 0;
     run_sieve_impl(G, r2, res, true, bypos.data(), st);
+    std::memset(loc_by_edge, 0, (size_t)G.edge_ids);
     if (G.m) {
         std::vector<int32_t> peid((size_t)G.m);
         TPM_HIP(hipMemcpy(peid.data(), G.peid, sizeof(int32_t) * G.m, hipMemcpyDeviceToHost));

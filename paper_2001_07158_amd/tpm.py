@@ -46,7 +46,8 @@ class tpm_graph_stats(ctypes.Structure):
                 ("tmax", ctypes.c_int32), ("rows", ctypes.c_int64), ("tiles", ctypes.c_int64),
                 ("slots", ctypes.c_int64), ("max_in_degree", ctypes.c_int64),
                 ("device_bytes", ctypes.c_int64), ("gathers", ctypes.c_int64),
-                ("segments", ctypes.c_int64), ("times", ctypes.c_int64)]
+                ("segments", ctypes.c_int64), ("times", ctypes.c_int64),
+                ("edge_ids", ctypes.c_int64)]
 
 
 class tpm_kernel_time(ctypes.Structure):
@@ -98,6 +99,7 @@ _sig("tpm_graph_create_ex", ctypes.c_int32,
 _sig("tpm_graph_destroy", None, [_vp])
 _sig("tpm_graph_stats_get", ctypes.c_int32, [_vp, ctypes.POINTER(tpm_graph_stats)])
 _sig("tpm_graph_retile", ctypes.c_int32, [_vp, ctypes.c_int32])
+_sig("tpm_graph_prune", ctypes.c_int32, [_vp, _i32p, ctypes.c_int32, ctypes.POINTER(_vp)])
 _sig("tpm_sieve_vertex", ctypes.c_int32, [_vp, _i32p, ctypes.c_int32, ctypes.c_uint64, _u8p, _u8p])
 _sig("tpm_time_buckets", ctypes.c_int32, [_vp, _i32p, ctypes.c_int32, ctypes.c_uint64, _i32p, _u8p])
 _sig("tpm_optimum_time", ctypes.c_int32, [_vp, _i32p, ctypes.c_int32, ctypes.c_uint64,
@@ -125,7 +127,7 @@ _sig("tpm_last_error", ctypes.c_char_p, [])
 _sig("tpm_version", ctypes.c_char_p, [])
 
 EXPORTED = ["tpm_graph_create", "tpm_graph_create_ex", "tpm_graph_destroy", "tpm_graph_stats_get",
-            "tpm_graph_retile", "tpm_autotune", "tpm_sieve_vertex", "tpm_time_buckets",
+            "tpm_graph_retile", "tpm_autotune", "tpm_graph_prune", "tpm_sieve_vertex", "tpm_time_buckets",
             "tpm_optimum_time",
             "tpm_sieve", "tpm_sieve_ex", "tpm_decide", "tpm_extract", "tpm_batch_run",
             "tpm_server_create", "tpm_server_submit", "tpm_server_poll", "tpm_server_destroy",
@@ -287,6 +289,13 @@ def tpm_optimum_time(h, multiset, seed, reps=1) -> int:
     return int(t.value)
 
 
+def tpm_graph_prune(h, colors):
+    c = _i32(sorted(set(int(x) for x in colors)))
+    out = ctypes.c_void_p()
+    _check(_lib.tpm_graph_prune(h, _ptr(c, _i32p), len(c), ctypes.byref(out)))
+    return out
+
+
 def tpm_graph_retile(h, tile_edges) -> None:
     _check(_lib.tpm_graph_retile(h, int(tile_edges)))
 
@@ -363,7 +372,17 @@ class Graph:
         return tpm_graph_stats_get(self.h)
 
     def sieve(self, multiset, seed, mask=None, chunk=0, loc=False, stream=None):
-        return tpm_sieve(self.h, multiset, seed, mask, chunk, self.m if loc else None, stream)
+        ids = self.stats()["edge_ids"] if loc else None
+        return tpm_sieve(self.h, multiset, seed, mask, chunk, ids, stream)
+
+    def prune(self, colors) -> "Graph":
+        """Subgraph on the edges whose endpoints both have a colour in `colors`
+        (same vertex ids, colours and input edge ids)."""
+        g = Graph.__new__(Graph)
+        g.h = tpm_graph_prune(self.h, colors)
+        st = tpm_graph_stats_get(g.h)
+        g.n, g.m = st["n"], st["m"]
+        return g
 
     def decide(self, multiset, seed, reps=1) -> bool:
         return tpm_decide(self.h, multiset, seed, reps)

@@ -1,0 +1,93 @@
+"""GPU: colour pruning (preprocessing step (i)) keeps every result bit for bit:
+per-point values, localisation by input edge id, vertex localisation, time
+buckets and extracted paths equal those of the full graph and the oracle."""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import pyref
+from synth import graphs as G
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def tpm():
+    import torch
+    assert torch.cuda.is_available()
+    torch.cuda.set_device(0)
+    from paper_2001_07158_amd import tpm as _tpm
+    return _tpm
+
+
+def _kept(g, colors):
+    keep = np.isin(g.color, list(colors))
+    return int(np.count_nonzero(keep[g.src] & keep[g.dst]))
+
+
+def test_prune_random_graphs(tpm):
+    rng = np.random.default_rng(91)
+    for it in range(40):
+        g = G.random_tiny_graph(rng, n_max=40, m_max=200, t_max=8, q_max=5)
+        k = int(rng.integers(2, 7))
+        M = [int(c) for c in rng.integers(0, g.num_colors, k)]
+        extra = [int(c) for c in rng.integers(0, g.num_colors, int(rng.integers(0, 2)))]
+        seed = int(rng.integers(0, 2**63))
+        say(f"case prune rand{it}: n={g.n} m={g.m} k={k}")
+        Gd = tpm.Graph.from_temporal(g, tile_edges=int(rng.integers(1, 64)))
+        Gp = Gd.prune(set(M) | set(extra))
+        st = Gp.stats()
+        assert st["m"] == _kept(g, set(M) | set(extra)) and st["edge_ids"] == g.m
+        pp, tot, loc = Gp.sieve(M, seed, loc=True)
+        wpp, wloc = oracle.sieve(g, M, seed, loc=True)
+        assert np.array_equal(pp, wpp) and np.array_equal(loc, wloc), it
+        assert np.array_equal(Gp.sieve_vertex(M, seed), oracle.vertex_sieve(g, M, seed))
+        t_full, b_full = oracle.time_buckets(g, M, seed)
+        full = dict(zip(t_full.tolist(), b_full.tolist()))
+        if st["m"]:
+            t, b = Gp.time_buckets(M, seed)
+            for tt, bb in zip(t.tolist(), b.tolist()):
+                assert full[tt] == bb
+            # times present only in the full graph carry no path
+            assert all(v == 0 for tt, v in full.items() if tt not in set(t.tolist()))
+        assert Gp.optimum_time(M, seed, reps=2) == oracle.optimum_time(g, M, seed, reps=2)
+        r1 = Gd.extract(M, seed, max_reps=6)
+        r2 = Gp.extract(M, seed, max_reps=6)
+        assert r1[0] == r2[0] and list(r1[1]) == list(r2[1]) and list(r1[2]) == list(r2[2])
+        if r2[0] == tpm.TPM_OK:
+            assert pyref.check_path(g, M, r2[1], r2[2])
+        Gp.close()
+        Gd.close()
+
+
+def test_prune_hub_graph_and_empty(tpm):
+    g = G.chung_lu_graph(20000, 400000, 2.5, 300, 8, 92)
+    Gd = tpm.Graph.from_temporal(g)
+    for M in ([0, 1, 2, 0, 1, 2, 3], [5, 5, 6]):
+        say(f"case prune hubs M={M}")
+        Gp = Gd.prune(M)
+        assert Gp.stats()["m"] == _kept(g, M)
+        pp, _ = Gp.sieve(M, 17)
+        assert np.array_equal(pp, oracle.sieve(g, M, 17))
+        assert np.array_equal(pp, Gd.sieve(M, 17)[0])
+        Gp.close()
+    # a colour no vertex has: nothing kept
+    g2 = G.uniform_graph(100, 1000, 20, 3, 4)
+    g2.color[:] = np.minimum(g2.color, 1)
+    Gd2 = tpm.Graph.from_temporal(g2)
+    Gp = Gd2.prune([2])
+    assert Gp.stats()["m"] == 0
+    assert Gp.sieve([2, 2], 3)[1] == 0
+    Gp.close()
+    Gd2.close()
+    with pytest.raises(tpm.TpmError):
+        Gd.prune([8])  # colour out of range
+    Gd.close()
