@@ -250,6 +250,9 @@ typedef struct {
     int64_t state_bytes;   /* device memory the server may use for query state (0 = auto) */
     int32_t max_lanes;     /* most sieve lanes resident at once (0 = auto) */
     int32_t extract_paths; /* 1: extract a witness for every YES */
+    int32_t prune_queries; /* 1: each request runs alone on the subgraph of its colours
+                              (as tpm_graph_prune), one request at a time, instead of
+                              sharing a resident multi-query row; results are identical */
 } tpm_server_config;
 
 tpm_status tpm_server_create(const tpm_graph *g, const tpm_server_config *cfg, tpm_server **out);

@@ -221,6 +221,8 @@ struct tpm_server {
     // row geometry
     int W = 1, lanes = 64;
     uint64_t steps = 0;
+    // pruned mode: workspaces shared by the per-request subgraphs
+    WorkspacePool *ppool = nullptr;
 };
 
 namespace {
@@ -229,6 +231,58 @@ struct Group {
     std::shared_ptr<tpm_server::Req> req;
     int lane0 = 0, nl = 0, gpts = 0, level = 2, chunk = 0;
 };
+
+// Pruned mode: requests in arrival order, each on the subgraph of its own colours
+// (preprocessing step (i)); the subgraph's workspaces come from a pool kept for the
+// server's lifetime, so steady state allocates nothing but the subgraph index.
+void serve_pruned(tpm_server *s) {
+    const Graph &G = s->g->G;
+    (void)hipSetDevice(G.device);
+    hipStream_t st = nullptr;
+    try {
+        for (;;) {
+            std::shared_ptr<tpm_server::Req> rq;
+            {
+                std::unique_lock<std::mutex> lk(s->mu);
+                s->cv.wait(lk, [&] { return s->stop || !s->queue.empty(); });
+                if (s->stop) return;
+                rq = s->queue.front();
+                s->queue.pop_front();
+            }
+            rq->t_start = now_ms();
+            rq->q.multiset = rq->ms.data();
+            tpm_result r;
+            std::memset(&r, 0, sizeof(r));
+            std::vector<uint8_t> keep((size_t)G.q, 0);
+            for (int32_t c : rq->ms) keep[(size_t)c] = 1;
+            Graph P;
+            struct Free {
+                Graph &g;
+                ~Free() {
+                    g.pool = nullptr;  // the server owns it
+                    free_graph(g);
+                }
+            } fr{P};
+            prune_graph(G, keep.data(), P);
+            P.pool = s->ppool;
+            run_alone(P, rq->q, r, st);
+            if (r.found && (rq->q.want_path || s->cfg.extract_paths)) extract_into(P, rq->q, r, st);
+            r.ticket = rq->ticket;
+            r.t_submit_ms = rq->t_submit;
+            r.t_start_ms = rq->t_start;
+            r.t_done_ms = now_ms();
+            std::lock_guard<std::mutex> lk(s->mu);
+            s->done.push_back(r);
+            s->steps++;
+        }
+    } catch (const Error &e) {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->error = e.msg;
+    } catch (const std::exception &e) {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->error = e.what();
+    }
+}
 
 void serve_loop(tpm_server *s) {
     const Graph &G = s->g->G;
@@ -372,6 +426,14 @@ tpm_status tpm_server_create(const tpm_graph *g, const tpm_server_config *cfg, t
         s->g = g;
         if (cfg) s->cfg = *cfg;
         const Graph &G = g->G;
+        TPM_REQUIRE(s->cfg.prune_queries == 0 || s->cfg.prune_queries == 1,
+                    "prune_queries must be 0 or 1");
+        if (s->cfg.prune_queries) {
+            s->ppool = new_workspace_pool();
+            s->worker = std::thread(serve_pruned, s);
+            *out = s;
+            return TPM_OK;
+        }
         // row width: the widest of 1024 / 512 / 256 points whose two level buffers and
         // vertex rows fit the state budget (default: 70 % of free device memory)
         size_t freeb = 0, totalb = 0;
@@ -438,6 +500,10 @@ void tpm_server_destroy(tpm_server *s) {
     }
     s->cv.notify_all();
     if (s->worker.joinable()) s->worker.join();
+    if (s->ppool) {
+        (void)hipDeviceSynchronize();
+        delete_workspace_pool(s->ppool);
+    }
     delete s;
 }
 

@@ -138,6 +138,9 @@ struct Workspace {
 // returns it when its stream is synchronised, so concurrent calls never share one.
 struct WorkspacePool;
 struct Graph;
+WorkspacePool *new_workspace_pool();
+void delete_workspace_pool(WorkspacePool *p);
+
 struct WorkspaceLease {
     explicit WorkspaceLease(const Graph &G);
     ~WorkspaceLease();

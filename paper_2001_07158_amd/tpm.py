@@ -80,7 +80,7 @@ class tpm_result(ctypes.Structure):
 
 class tpm_server_config(ctypes.Structure):
     _fields_ = [("state_bytes", ctypes.c_int64), ("max_lanes", ctypes.c_int32),
-                ("extract_paths", ctypes.c_int32)]
+                ("extract_paths", ctypes.c_int32), ("prune_queries", ctypes.c_int32)]
 
 
 def _sig(name, res, args):
@@ -316,8 +316,9 @@ def tpm_batch_run(h, queries, chunk=0, use_graph=False):
     return [_result_dict(out[i]) for i in range(len(queries))]
 
 
-def tpm_server_create(h, state_bytes=0, max_lanes=0, extract_paths=0):
-    cfg = tpm_server_config(int(state_bytes), int(max_lanes), int(extract_paths))
+def tpm_server_create(h, state_bytes=0, max_lanes=0, extract_paths=0, prune_queries=0):
+    cfg = tpm_server_config(int(state_bytes), int(max_lanes), int(extract_paths),
+                            int(prune_queries))
     s = ctypes.c_void_p()
     _check(_lib.tpm_server_create(h, ctypes.byref(cfg), ctypes.byref(s)))
     return s
@@ -420,9 +421,10 @@ class Graph:
 class Server:
     """Owner of a serving loop over a resident graph (tpm_server_*)."""
 
-    def __init__(self, graph: Graph, state_bytes=0, max_lanes=0, extract_paths=0):
+    def __init__(self, graph: Graph, state_bytes=0, max_lanes=0, extract_paths=0,
+                 prune_queries=0):
         self.graph = graph
-        self.h = tpm_server_create(graph.h, state_bytes, max_lanes, extract_paths)
+        self.h = tpm_server_create(graph.h, state_bytes, max_lanes, extract_paths, prune_queries)
 
     def submit(self, multiset, seed, want_path=0) -> int:
         return tpm_server_submit(self.h, multiset, seed, want_path)

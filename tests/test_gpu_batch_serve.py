@@ -158,3 +158,25 @@ def test_server_alone_vs_mix_and_extraction(tpm):
     if alone["found"]:
         assert pyref.check_path(g, probe["multiset"], alone["path_vertices"][:4], alone["path_edges"][:3])
     Gd.close()
+
+
+def test_pruned_server_matches_alone(tpm, graph):
+    """Serving with per-request colour pruning: same totals as the full graph and the
+    oracle, and extracted paths check out."""
+    rng = np.random.default_rng(61)
+    qs = _queries(rng, 25, graph.num_colors, 1, 9)
+    Gd = tpm.Graph.from_temporal(graph)
+    srv = tpm.Server(Gd, prune_queries=1, extract_paths=1)
+    tickets = [srv.submit(q["multiset"], q["seed"]) for q in qs]
+    got = {r["ticket"]: r for r in srv.drain(len(qs), timeout_s=300)}
+    srv.close()
+    for t, q in zip(tickets, qs):
+        r = got[t]
+        want = oracle.sieve_total(graph, q["multiset"], q["seed"])
+        assert r["total"] == want, q
+        if r["found"] and len(q["multiset"]) >= 2:
+            assert r["path_status"] == tpm.TPM_OK
+            k = len(q["multiset"])
+            assert pyref.check_path(graph, q["multiset"], r["path_vertices"][:k],
+                                    r["path_edges"][:k - 1])
+    Gd.close()
