@@ -474,6 +474,238 @@ __global__ void __launch_bounds__(1024) k_level(LevelParams P) {
     }
 }
 
+// ---------------------------------------------------------------------------------
+// Narrow rows: C = 16 LP points (LP = 4..32 lanes per row, 16 points per lane).  A
+// wave processes E = 64 / LP consecutive positions side by side, one per slot of LP
+// lanes, so the per-edge fixed work (metadata, fingerprint, branch, address) is shared
+// by E edges.  The running value of an in-list then comes from an inclusive segmented
+// XOR-scan across the slots of a step (shuffles by multiples of LP lanes, a slot whose
+// destination differs from the previous slot's starts a segment); the last slot's
+// value carries into the next step.  Tiles, look-back and the carry fix-up of
+// continuation pieces are those of k_level.
+// ---------------------------------------------------------------------------------
+template <int LP, bool FIN>
+__global__ void __launch_bounds__(1024) k_narrow(LevelParams P) {
+    constexpr int E = 64 / LP;           // positions per step
+    constexpr int U = (E >= 64) ? 1 : 2;  // steps per batch; two batches in flight
+    static_assert(64 % (U * E) == 0, "batches tile a window");
+    __shared__ __attribute__((aligned(16))) uint8_t lds[kLdsBytes];
+    {
+        const uint4 *src = (const uint4 *)P.lds_image;
+        uint4 *dst = (uint4 *)lds;
+        for (int i = threadIdx.x; i < kLdsBytes / 16; i += blockDim.x) dst[i] = src[i];
+    }
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63;
+    const int slot = lane / LP, sub = lane % LP;
+    const int rowd = P.rowb >> 2;
+    const int64_t subofs = (int64_t)sub * 16;
+    const uint32_t lanebits = (uint32_t)(lane & 31) << 2;
+    const uint32_t xbase = (uint32_t)kExpBase + lanebits;
+    const uint32_t zc = (uint32_t)kExpBase + ((uint32_t)kClampRow << 7) + lanebits;
+    const uint32_t epoch = __hip_atomic_load(&P.ctl->epoch, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT) & 0x3FFFFFFFu;
+    uint32_t fin[4] = {0, 0, 0, 0};
+
+    uint32_t tk = 0;
+    if (lane == 0) tk = atomicAdd(&P.ctl->ticket, 1u);
+    tk = __builtin_amdgcn_readfirstlane(__shfl(tk, 0));
+    for (;;) {
+        const int32_t tile = P.tile_lo + (int32_t)tk;
+        if (tile >= P.tile_hi) break;
+        uint32_t tk_next = 0;
+        if constexpr (FIN) {
+            if (lane == 0) tk_next = atomicAdd(&P.ctl->ticket, 1u);
+        }
+        const int32_t p0 = P.tile_p0[tile], p1 = P.tile_p0[tile + 1];
+        int32_t pubslot = -1, lbslot = -1;
+        if constexpr (!FIN) {
+            pubslot = P.tile_pub[tile];
+            lbslot = P.tile_lb[tile];
+        }
+        const bool cont = lbslot >= 0;
+
+        int32_t wb = p0;
+        Win cw = load_win<FIN>(P, wb, p1, lane);
+        Win nw = load_win<FIN>(P, wb + 64, p1, lane);
+        finish_win(P, lds, cw, wb, p1, lane, lanebits);
+
+        uint32_t run[4] = {0, 0, 0, 0};  // running value after the last step (every slot)
+        int32_t run_d = -1;              // its in-list
+        int32_t cur_d = -1;              // in-list whose x row is in lx7 (per lane)
+        int32_t gprev = -1;              // gather side: this slot's previous destination
+        uint32_t lx7[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) lx7[i] = kZero7;
+
+        // one batch: U steps from position pb; row of the gathered predecessor, and the
+        // x row of the destination where it changes along this slot's positions
+        auto gather = [&](int32_t pb, uint32_t (&g)[U][4], uint32_t (&xr)[U][4]) {
+            const bool in_next = (pb - wb) >= 64;  // uniform
+            const int base = (pb - wb) - (in_next ? 64 : 0);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int32_t q = pb + u * E + slot;
+                const int li = base + u * E + slot;
+                const int32_t r = in_next ? __shfl(nw.g, li) : __shfl(cw.g, li);
+                const int32_t d = in_next ? __shfl(nw.d, li) : __shfl(cw.d, li);
+                const bool valid = q < p1;
+                if (valid && r >= 0) {
+                    const uint4 t = *(const uint4 *)(P.gbase + (int64_t)r * P.rowb + subofs);
+                    g[u][0] = t.x; g[u][1] = t.y; g[u][2] = t.z; g[u][3] = t.w;
+                } else {
+                    g[u][0] = g[u][1] = g[u][2] = g[u][3] = 0;
+                }
+                if (valid && d != gprev) {
+                    const uint4 t = *(const uint4 *)(P.xt + (int64_t)d * P.rowb + subofs);
+                    xr[u][0] = t.x; xr[u][1] = t.y; xr[u][2] = t.z; xr[u][3] = t.w;
+                }
+                if (valid) gprev = d;
+            }
+        };
+
+        auto process = [&](int32_t pb, const uint32_t (&g)[U][4], const uint32_t (&xr)[U][4]) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int32_t sb = pb + u * E;  // first position of the step (uniform)
+                if (sb >= p1) break;
+                const int nvalid = min(E, p1 - sb);
+                const int li = (sb - wb) + slot;
+                const int32_t d = __shfl(cw.d, li);
+                const uint32_t ly7 = __shfl(cw.y, li);
+                const bool valid = slot < nvalid;
+                if (valid && d != cur_d) {
+#pragma unroll
+                    for (int w = 0; w < 4; ++w) {
+                        lx7[4 * w + 0] = lds32(lds, log_addr<0>(lanebits, xr[u][w])) + xbase;
+                        lx7[4 * w + 1] = lds32(lds, log_addr<1>(lanebits, xr[u][w])) + xbase;
+                        lx7[4 * w + 2] = lds32(lds, log_addr<2>(lanebits, xr[u][w])) + xbase;
+                        lx7[4 * w + 3] = lds32(lds, log_addr<3>(lanebits, xr[u][w])) + xbase;
+                    }
+                    cur_d = d;
+                }
+                uint32_t c[4];
+                if (valid && ly7 < kZero7) {
+#pragma unroll
+                    for (int w = 0; w < 4; ++w) c[w] = mul4(lds, lanebits, g[u][w], &lx7[4 * w], ly7, zc);
+                } else {
+                    c[0] = c[1] = c[2] = c[3] = 0;
+                }
+                if constexpr (FIN) {
+                    const int32_t p = sb + slot;
+                    const bool inr = valid && p >= P.pos_lo && p < P.pos_hi;
+                    if (inr) {
+#pragma unroll
+                        for (int w = 0; w < 4; ++w) fin[w] ^= c[w];
+                    }
+                    if (P.loc) {
+                        uint32_t x = inr ? (c[0] ^ c[1] ^ c[2] ^ c[3]) : 0u;
+                        x ^= x >> 16;
+                        x ^= x >> 8;
+                        x &= 0xFFu;
+#pragma unroll
+                        for (int off = LP / 2; off >= 1; off >>= 1) x ^= __shfl_xor(x, off);
+                        if (inr && sub == 0) P.loc[p - P.pos_lo] ^= (uint8_t)x;
+                    }
+                } else {
+                    // inclusive segmented XOR-scan over the slots of this step
+                    const int32_t dprev = __shfl_up(d, LP);
+                    bool f = valid && (slot == 0 ? d != run_d : d != dprev);
+                    uint32_t v[4] = {c[0], c[1], c[2], c[3]};
+#pragma unroll
+                    for (int off = 1; off < E; off <<= 1) {
+                        uint32_t vo[4];
+#pragma unroll
+                        for (int w = 0; w < 4; ++w) vo[w] = __shfl_up(v[w], off * LP);
+                        const int fo = __shfl_up((int)f, off * LP);
+                        if (slot >= off) {
+                            if (!f) {
+#pragma unroll
+                                for (int w = 0; w < 4; ++w) v[w] ^= vo[w];
+                            }
+                            f = f || (fo != 0);
+                        }
+                    }
+                    // slots with no segment start at or below them continue run_d
+                    uint32_t a[4];
+#pragma unroll
+                    for (int w = 0; w < 4; ++w) a[w] = f ? v[w] : (v[w] ^ run[w]);
+                    const int32_t o = __shfl(cw.o, li);
+                    if (valid && o >= 0)
+                        *(uint4 *)(P.sout + (int64_t)o * P.rowb + subofs) = make_uint4(a[0], a[1], a[2], a[3]);
+                    const int last = (nvalid - 1) * LP;
+#pragma unroll
+                    for (int w = 0; w < 4; ++w) run[w] = __shfl(a[w], last + sub);
+                    run_d = __shfl(d, last);
+                }
+            }
+            // advance the window after its last batch
+            if (pb + U * E - wb == 64 && pb + U * E < p1) {
+                wb += 64;
+                cw = nw;
+                finish_win(P, lds, cw, wb, p1, lane, lanebits);
+                nw = load_win<FIN>(P, wb + 64, p1, lane);
+            }
+        };
+
+        uint32_t ga[U][4], gb[U][4], xa[U][4], xb[U][4];
+        gather(p0, ga, xa);
+        for (int32_t pb = p0; pb < p1;) {
+            gather(pb + U * E, gb, xb);
+            process(pb, ga, xa);
+            pb += U * E;
+            if (pb >= p1) break;
+            gather(pb + U * E, ga, xa);
+            process(pb, gb, xb);
+            pb += U * E;
+        }
+
+        if constexpr (!FIN) {
+            if (pubslot >= 0 && lane < LP)
+                publish<4>(P.pub, pubslot, rowd, LP, sub, cont ? kAgg : kInc, epoch, run);
+            if (cont) {
+                uint32_t carry[4] = {0, 0, 0, 0};
+                if (lane < LP) lookback<4>(P.pub, lbslot, rowd, LP, sub, epoch, P.ctl, carry);
+#pragma unroll
+                for (int w = 0; w < 4; ++w) carry[w] = __shfl(carry[w], sub);
+                if (pubslot >= 0 && lane < LP) {
+                    uint32_t inc[4];
+#pragma unroll
+                    for (int w = 0; w < 4; ++w) inc[w] = run[w] ^ carry[w];
+                    publish<4>(P.pub, pubslot, rowd, LP, sub, kInc, epoch, inc);
+                }
+                // rows of a continuation piece were stored without the carry
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+                for (int32_t p = p0 + slot; p < p1; p += E) {
+                    const int32_t orow = P.orow[p];
+                    if (orow >= 0) {
+                        uint4 *q = (uint4 *)(P.sout + (int64_t)orow * P.rowb + subofs);
+                        uint4 t = *q;
+                        t.x ^= carry[0]; t.y ^= carry[1]; t.z ^= carry[2]; t.w ^= carry[3];
+                        *q = t;
+                    }
+                }
+            }
+            if (lane == 0) tk_next = atomicAdd(&P.ctl->ticket, 1u);
+        }
+        tk = __builtin_amdgcn_readfirstlane(__shfl(tk_next, 0));
+    }
+
+    if constexpr (FIN) {
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+#pragma unroll
+            for (int off = LP; off < 64; off <<= 1) fin[w] ^= __shfl_xor(fin[w], off);
+        }
+        if (lane < LP) {
+#pragma unroll
+            for (int w = 0; w < 4; ++w)
+                if (fin[w]) atomicXor(&P.fin[sub * 4 + w], fin[w]);
+        }
+    }
+}
+
 __global__ void k_prep(Ctl *ctl, int bump_epoch) {
     ctl->ticket = 0;
     if (bump_epoch) ctl->epoch = (ctl->epoch + 1u) & 0x3FFFFFFFu;
@@ -895,6 +1127,26 @@ void launch_level_w(int W, bool fin, const Graph &G, const LevelParams &P, hipSt
     else fin ? launch_level<1, true>(G, P, st) : launch_level<1, false>(G, P, st);
 }
 
+template <int LP>
+void launch_narrow(bool fin, const Graph &G, const LevelParams &P, hipStream_t st) {
+    if (fin) hipLaunchKernelGGL((k_narrow<LP, true>), dim3((unsigned)G.num_cu), dim3(1024), 0, st, P);
+    else hipLaunchKernelGGL((k_narrow<LP, false>), dim3((unsigned)G.num_cu), dim3(1024), 0, st, P);
+}
+
+// rows of 64..512 points run edge-parallel (k_narrow); wider and narrower rows k_level
+bool is_narrow(int rowb) { return rowb >= 64 && rowb <= 512; }
+
+void launch_level_any(int rowb, int W, bool fin, const Graph &G, const LevelParams &P,
+                      hipStream_t st) {
+    switch (is_narrow(rowb) ? rowb / 16 : 0) {
+        case 4: launch_narrow<4>(fin, G, P, st); break;
+        case 8: launch_narrow<8>(fin, G, P, st); break;
+        case 16: launch_narrow<16>(fin, G, P, st); break;
+        case 32: launch_narrow<32>(fin, G, P, st); break;
+        default: launch_level_w(W, fin, G, P, st);
+    }
+}
+
 void launch_step_w(int W, const Graph &G, const StepParams &P, hipStream_t st) {
     if (W == 4) hipLaunchKernelGGL((k_step<4>), dim3((unsigned)G.num_cu), dim3(1024), 0, st, P);
     else if (W == 2) hipLaunchKernelGGL((k_step<2>), dim3((unsigned)G.num_cu), dim3(1024), 0, st, P);
@@ -928,7 +1180,9 @@ void run_sieve_impl(const Graph &G, const SieveRequest &req, SieveResult &res, b
     const int64_t npts = int64_t(1) << k;
     const int rowb = (k == 1) ? 4 : pick_chunk(G, k, req.chunk);
     const int W = rowb >= 1024 ? 4 : (rowb >= 512 ? 2 : 1);
-    const int lanes = rowb / (4 * W);
+    // lanes holding points: 64 lanes of 4W points, or one 16-point lane per 16 points of
+    // a narrow row (its E = 1024 / rowb slots repeat the same lanes)
+    const int lanes = is_narrow(rowb) ? rowb / 16 : rowb / (4 * W);
     const int rowd = rowb / 4;
     const int64_t ppbytes = std::max<int64_t>(npts, 4);
 
@@ -1018,7 +1272,7 @@ void run_sieve_impl(const Graph &G, const SieveRequest &req, SieveResult &res, b
                 k_prep<<<1, 1, 0, st>>>(ctl.as<Ctl>(), fin ? 0 : 1);
                 {
                     ProfileScope prof(st, fin ? 2 : (l == 2 ? 0 : 1), l, rowb);
-                    launch_level_w(W, fin, G, P, st);
+                    launch_level_any(rowb, W, fin, G, P, st);
                 }
             }
         }
