@@ -71,6 +71,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-pruned", action="store_true",
                     help="skip the colour-pruned comparison run")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the decide / extraction / optimum-time timings")
     ap.add_argument("--prune", action="store_true",
                     help="serving: run each request alone on the subgraph of its colours")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -197,6 +199,29 @@ def main() -> int:
         },
         "cpu_baseline": None,
     }
+
+    # ---- decide, witness extraction and the optimum timestamp for the same query
+    # (outside the timed region): extraction is the sieve with localisation, then k-2
+    # smaller sieves restricted to one in-list each
+    if not args.no_extras:
+        torch.cuda.synchronize()
+        te = time.perf_counter()
+        found = G.decide(M, seed0, reps=1)
+        t_dec = (time.perf_counter() - te) * 1e3
+        te = time.perf_counter()
+        rc, verts, edges = G.extract(M, seed0, max_reps=8)
+        t_ext = (time.perf_counter() - te) * 1e3
+        ok = rc == tpm.TPM_OK  # the library verifies every path it returns
+        te = time.perf_counter()
+        t_opt_val = G.optimum_time(M, seed0, reps=1)
+        t_opt = (time.perf_counter() - te) * 1e3
+        line["extras"] = {
+            "decide_ms": t_dec, "found": bool(found), "extract_ms": t_ext,
+            "extract_over_decide": t_ext / t_dec, "path_verified": bool(ok),
+            "optimum_time_ms": t_opt, "optimum_time": t_opt_val,
+        }
+        print(f"# decide {t_dec:.1f} ms, extract {t_ext:.1f} ms (path ok={ok}), optimum time "
+              f"{t_opt_val} in {t_opt:.1f} ms", file=sys.stderr, flush=True)
 
     # ---- the same query on the colour-pruned graph (the paper's preprocessing step (i):
     # edges whose endpoints both have a colour of M); outside the timed region and
@@ -397,6 +422,7 @@ def bench_serving(args) -> int:
             t_last = time.perf_counter()
     results = drain(nq - nb, results)
     t_total = time.perf_counter() - t_start
+    sstats = srv.stats()
     srv.close()
     lat = np.array([r["t_done_ms"] - r["t_submit_ms"] for r in results])
     # spot check: a few streamed results against the same query run alone
@@ -414,6 +440,7 @@ def bench_serving(args) -> int:
         "burst_queries": nb, "found": int(sum(r["found"] for r in results + burst)),
         "spot_check_equal_alone": bool(same), "dtype": "u8", "data": "synthetic",
         "mode": "per-request colour pruning" if args.prune else "continuous batching (resident row)",
+        "server_stats": sstats,
         "config": {"workload": f"serving: directed Chung-Lu n={g.n} m={g.m} beta=2.5 "
                                f"t=[1,{cfg['t']}] q={cfg['q']}, stream prefix of {nq} queries "
                                f"k~U{{3..10}}", "rows_stored": st["rows"]},

@@ -262,6 +262,18 @@ tpm_status tpm_server_submit(tpm_server *s, const tpm_query *q, uint64_t *ticket
 tpm_status tpm_server_poll(tpm_server *s, tpm_result *out, int32_t max, int32_t *n_out);
 void tpm_server_destroy(tpm_server *s);
 
+/* Counters of a server since creation (host clock, ms). */
+typedef struct {
+    int64_t completed;     /* results produced */
+    int64_t steps;         /* row steps (batching mode) or requests run (pruned mode) */
+    int32_t row_points;    /* sieve points per resident row (batching mode), else 0 */
+    int32_t lanes;         /* lanes of the resident row (batching mode), else 0 */
+    double prune_ms;       /* building per-request subgraphs (pruned mode) */
+    double sieve_ms;       /* sieving: row steps, or per-request sieves */
+    double extract_ms;     /* witness extraction */
+} tpm_server_stats;
+tpm_status tpm_server_stats_get(tpm_server *s, tpm_server_stats *out);
+
 /* ---------------------------------------------------------- diagnostics --- */
 /* When enabled (process-wide), every sieve level kernel is bracketed by HIP events
  * recorded on the stream it is launched on; tpm_profile_read drains the measured

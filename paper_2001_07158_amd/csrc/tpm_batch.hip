@@ -221,8 +221,11 @@ struct tpm_server {
     // row geometry
     int W = 1, lanes = 64;
     uint64_t steps = 0;
-    // pruned mode: workspaces shared by the per-request subgraphs
+    int64_t completed = 0;
+    double prune_ms = 0, sieve_ms = 0, extract_ms = 0;
+    // pruned mode: workspaces and index memory shared by the per-request subgraphs
     WorkspacePool *ppool = nullptr;
+    GraphArena *arena = nullptr;
 };
 
 namespace {
@@ -263,17 +266,25 @@ void serve_pruned(tpm_server *s) {
                     free_graph(g);
                 }
             } fr{P};
-            prune_graph(G, keep.data(), P);
+            const double t0 = now_ms();
+            prune_graph(G, keep.data(), P, s->arena);
             P.pool = s->ppool;
+            const double t1 = now_ms();
             run_alone(P, rq->q, r, st);
+            const double t2 = now_ms();
             if (r.found && (rq->q.want_path || s->cfg.extract_paths)) extract_into(P, rq->q, r, st);
+            const double t3 = now_ms();
             r.ticket = rq->ticket;
             r.t_submit_ms = rq->t_submit;
             r.t_start_ms = rq->t_start;
-            r.t_done_ms = now_ms();
+            r.t_done_ms = t3;
             std::lock_guard<std::mutex> lk(s->mu);
             s->done.push_back(r);
             s->steps++;
+            s->completed++;
+            s->prune_ms += t1 - t0;
+            s->sieve_ms += t2 - t1;
+            s->extract_ms += t3 - t2;
         }
     } catch (const Error &e) {
         std::lock_guard<std::mutex> lk(s->mu);
@@ -310,6 +321,7 @@ void serve_loop(tpm_server *s) {
             }
             return -1;
         };
+        double ext_in_step = 0;
         auto finish = [&](const std::shared_ptr<tpm_server::Req> &rq) {
             tpm_result r;
             std::memset(&r, 0, sizeof(r));
@@ -319,10 +331,14 @@ void serve_loop(tpm_server *s) {
             r.t_submit_ms = rq->t_submit;
             r.t_start_ms = rq->t_start;
             rq->q.multiset = rq->ms.data();
+            const double te = now_ms();
             if (r.found && (rq->q.want_path || s->cfg.extract_paths)) extract_into(G, rq->q, r, st);
             r.t_done_ms = now_ms();
+            ext_in_step += r.t_done_ms - te;
             std::lock_guard<std::mutex> lk(s->mu);
             s->done.push_back(r);
+            s->completed++;
+            s->extract_ms += r.t_done_ms - te;
         };
         for (;;) {
             // ---- admission: requests enter free lanes (chunks of large queries in order)
@@ -386,6 +402,8 @@ void serve_loop(tpm_server *s) {
                 for (int t = 0; t < gr.nl; ++t)
                     lanes[(size_t)(gr.lane0 + t)] = {gr.req->q.seed, (uint32_t)(gr.level - 1), flags};
             }
+            const double ts = now_ms();
+            ext_in_step = 0;
             multi_step(G, row, lanes.data(), st);
             s->steps++;
             // ---- retire groups that ran their last level
@@ -404,6 +422,10 @@ void serve_loop(tpm_server *s) {
                 }
             }
             groups.swap(keep);
+            {
+                std::lock_guard<std::mutex> lk(s->mu);
+                s->sieve_ms += now_ms() - ts - ext_in_step;
+            }
         }
     } catch (const Error &e) {
         std::lock_guard<std::mutex> lk(s->mu);
@@ -430,6 +452,7 @@ tpm_status tpm_server_create(const tpm_graph *g, const tpm_server_config *cfg, t
                     "prune_queries must be 0 or 1");
         if (s->cfg.prune_queries) {
             s->ppool = new_workspace_pool();
+            s->arena = new_graph_arena();
             s->worker = std::thread(serve_pruned, s);
             *out = s;
             return TPM_OK;
@@ -491,6 +514,24 @@ tpm_status tpm_server_poll(tpm_server *s, tpm_result *out, int32_t max, int32_t 
     });
 }
 
+tpm_status tpm_server_stats_get(tpm_server *s, tpm_server_stats *out) {
+    return guarded2([&]() -> tpm_status {
+        TPM_REQUIRE(s && out, "NULL argument");
+        std::lock_guard<std::mutex> lk(s->mu);
+        out->completed = s->completed;
+        out->steps = (int64_t)s->steps;
+        const bool pruned = s->cfg.prune_queries != 0;
+        out->lanes = pruned ? 0 : s->lanes;
+        int rp = 1;
+        while (!pruned && rp * 2 <= 4 * s->W * s->lanes) rp *= 2;
+        out->row_points = pruned ? 0 : rp;
+        out->prune_ms = s->prune_ms;
+        out->sieve_ms = s->sieve_ms;
+        out->extract_ms = s->extract_ms;
+        return TPM_OK;
+    });
+}
+
 void tpm_server_destroy(tpm_server *s) {
     if (!s) return;
     {
@@ -503,6 +544,7 @@ void tpm_server_destroy(tpm_server *s) {
     if (s->ppool) {
         (void)hipDeviceSynchronize();
         delete_workspace_pool(s->ppool);
+        delete_graph_arena(s->arena);
     }
     delete s;
 }

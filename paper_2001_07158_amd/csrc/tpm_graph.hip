@@ -200,17 +200,76 @@ void build_tiles(const std::vector<int32_t> &inptr, int32_t T, std::vector<int32
 
 }  // namespace
 
+// Slots of a graph arena: one grow-only buffer per index array and per temporary.
+enum ArenaSlot {
+    A_COLOR, A_PDST, A_PSRC, A_PTAU, A_PEID, A_GSRC, A_OROW, A_INPTR, A_SEGNEXT, A_TP0, A_TPUB,
+    A_TLB, A_LDS, A_TTAB, A_KEEPC, A_KEEP, A_AT, A_SCRATCH, A_GPOS, A_NEEDED, A_ROWOF, A_TSORT,
+    A_TUNIQ, A_TCOUNT, A_CNT, A_NSLOTS
+};
+
+struct GraphArena {
+    DBuf s[A_NSLOTS];
+};
+
+GraphArena *new_graph_arena() { return new GraphArena(); }
+void delete_graph_arena(GraphArena *a) { delete a; }
+
+namespace {
+
+// An array of the graph: its own allocation (freed with the graph), or the arena's
+// slot when the graph lives in an arena.
+template <class T>
+T *galloc(Graph &G, int slot, int64_t count, int64_t &acct) {
+    if (G.arena) {
+        DBuf &b = G.arena->s[slot];
+        b.alloc((size_t)std::max<int64_t>(1, count) * sizeof(T), nullptr);
+        acct += (int64_t)b.cap;
+        return (T *)b.p;
+    }
+    return dalloc<T>(count, acct);
+}
+
+// Temporaries of an index build: the arena's slots, or allocations freed at the end.
+struct Temps {
+    GraphArena *arena = nullptr;
+    std::vector<void *> own;
+    explicit Temps(GraphArena *a) : arena(a) {}
+    Temps(const Temps &) = delete;
+    Temps &operator=(const Temps &) = delete;
+    void *raw(int slot, size_t bytes) {
+        bytes = std::max<size_t>(bytes, 16);
+        if (arena) {
+            arena->s[slot].alloc(bytes, nullptr);
+            return arena->s[slot].p;
+        }
+        void *p = nullptr;
+        TPM_HIP(hipMalloc(&p, bytes));
+        own.push_back(p);
+        return p;
+    }
+    template <class T>
+    T *get(int slot, int64_t count) {
+        return (T *)raw(slot, (size_t)std::max<int64_t>(1, count) * sizeof(T));
+    }
+    ~Temps() {
+        if (!own.empty()) (void)hipDeviceSynchronize();
+        for (void *p : own) (void)hipFree(p);
+    }
+};
+
+}  // namespace
+
 void free_graph(Graph &G) {
     int32_t **ptrs[] = {&G.color, &G.pdst,  &G.psrc,    &G.ptau,     &G.peid,   &G.gsrc,
-                        &G.orow,  &G.inptr, &G.segnext, &G.tile_p0, &G.tile_pub, &G.tile_lb};
+                        &G.orow,  &G.inptr, &G.segnext, &G.tile_p0, &G.tile_pub, &G.tile_lb,
+                        &G.ttab};
+    const bool own = G.arena == nullptr;  // arena memory stays with the arena
     for (auto pp : ptrs) {
-        if (*pp) (void)hipFree(*pp);
+        if (*pp && own) (void)hipFree(*pp);
         *pp = nullptr;
     }
-    if (G.lds_image) (void)hipFree(G.lds_image);
+    if (G.lds_image && own) (void)hipFree(G.lds_image);
     G.lds_image = nullptr;
-    if (G.ttab) (void)hipFree(G.ttab);
-    G.ttab = nullptr;
 }
 
 // Everything of the index that follows from the CSR arrays (pdst, psrc, ptau, peid
@@ -223,133 +282,107 @@ void finish_index(Graph &G, int64_t &acct, const int32_t *taus) {
     const int32_t tmax = G.tmax;
     const int32_t T = G.tile_edges;
     hipStream_t st = nullptr;
-    int64_t tmp = 0;
-    int32_t *gpos = nullptr, *needed = nullptr, *rowof = nullptr, *tsort = nullptr,
-            *tuniq = nullptr;
-    int64_t *tcount = nullptr;
-    unsigned long long *cnt = nullptr;
-    void *scratch = nullptr;
-    auto cleanup = [&]() {
-        for (void *p : {(void *)gpos, (void *)needed, (void *)rowof, (void *)tsort, (void *)tuniq,
-                        (void *)tcount, (void *)cnt, scratch})
-            if (p) (void)hipFree(p);
-    };
-    try {
-        if (m) {
-            // ---- distinct timestamps, ascending (per-time splits of the sieve)
-            const int tbits = bits_for((uint64_t)tmax);
-            tsort = dalloc<int32_t>(m, tmp);
-            tuniq = dalloc<int32_t>(m, tmp);
-            tcount = dalloc<int64_t>(1, tmp);
-            size_t sbytes = 0, ubytes = 0;
-            TPM_HIP(rocprim::radix_sort_keys(nullptr, sbytes, taus, tsort, (size_t)m, 0,
-                                             (unsigned)tbits, st));
-            TPM_HIP(rocprim::unique(nullptr, ubytes, tsort, tuniq, tcount, (size_t)m,
-                                    rocprim::equal_to<int32_t>(), st));
-            TPM_HIP(hipMalloc(&scratch, std::max<size_t>(std::max(sbytes, ubytes), 16)));
-            TPM_HIP(rocprim::radix_sort_keys(scratch, sbytes, taus, tsort, (size_t)m, 0,
-                                             (unsigned)tbits, st));
-            TPM_HIP(rocprim::unique(scratch, ubytes, tsort, tuniq, tcount, (size_t)m,
-                                    rocprim::equal_to<int32_t>(), st));
-            int64_t nt = 0;
-            TPM_HIP(hipMemcpy(&nt, tcount, sizeof(nt), hipMemcpyDeviceToHost));
-            G.ntimes = nt;
-            G.ttab = dalloc<int32_t>(nt, acct);
-            TPM_HIP(hipMemcpy(G.ttab, tuniq, sizeof(int32_t) * (size_t)nt, hipMemcpyDeviceToDevice));
-            G.h_ttab.resize((size_t)nt);
-            TPM_HIP(hipMemcpy(G.h_ttab.data(), tuniq, sizeof(int32_t) * (size_t)nt,
-                              hipMemcpyDeviceToHost));
-            for (void **q : {(void **)&tsort, (void **)&tuniq, (void **)&tcount, &scratch}) {
-                (void)hipFree(*q);
-                *q = nullptr;
-            }
-        }
-        k_inptr<<<grid_for(m + 1), 256, 0, st>>>(m, n, G.pdst, G.inptr);
-        if (m) {
-            gpos = dalloc<int32_t>(m, tmp);
-            needed = dalloc<int32_t>(m, tmp);
-            rowof = dalloc<int32_t>(m, tmp);
-            TPM_HIP(hipMemsetAsync(needed, 0, sizeof(int32_t) * m, st));
-            k_gpos<<<grid_for(m), 256, 0, st>>>(m, G.psrc, G.ptau, G.inptr, gpos, needed);
-            size_t sbytes = 0;
-            TPM_HIP(rocprim::exclusive_scan(nullptr, sbytes, needed, rowof, 0, (size_t)m,
-                                            rocprim::plus<int32_t>(), st));
-            TPM_HIP(hipMalloc(&scratch, std::max<size_t>(sbytes, 16)));
-            TPM_HIP(rocprim::exclusive_scan(scratch, sbytes, needed, rowof, 0, (size_t)m,
-                                            rocprim::plus<int32_t>(), st));
-            k_rows<<<grid_for(m), 256, 0, st>>>(m, gpos, needed, rowof, G.orow, G.gsrc);
-            int32_t last_row = 0, last_needed = 0;
-            TPM_HIP(hipMemcpy(&last_row, rowof + (m - 1), sizeof(int32_t), hipMemcpyDeviceToHost));
-            TPM_HIP(hipMemcpy(&last_needed, needed + (m - 1), sizeof(int32_t),
-                              hipMemcpyDeviceToHost));
-            G.R = (int64_t)last_row + last_needed;
-        }
+    Temps tmp(G.arena);
+    if (m) {
+        // ---- distinct timestamps, ascending (per-time splits of the sieve)
+        const int tbits = bits_for((uint64_t)tmax);
+        int32_t *tsort = tmp.get<int32_t>(A_TSORT, m);
+        int32_t *tuniq = tmp.get<int32_t>(A_TUNIQ, m);
+        int64_t *tcount = tmp.get<int64_t>(A_TCOUNT, 1);
+        size_t sbytes = 0, ubytes = 0;
+        TPM_HIP(rocprim::radix_sort_keys(nullptr, sbytes, taus, tsort, (size_t)m, 0,
+                                         (unsigned)tbits, st));
+        TPM_HIP(rocprim::unique(nullptr, ubytes, tsort, tuniq, tcount, (size_t)m,
+                                rocprim::equal_to<int32_t>(), st));
+        void *scratch = tmp.raw(A_SCRATCH, std::max(sbytes, ubytes));
+        TPM_HIP(rocprim::radix_sort_keys(scratch, sbytes, taus, tsort, (size_t)m, 0,
+                                         (unsigned)tbits, st));
+        TPM_HIP(rocprim::unique(scratch, ubytes, tsort, tuniq, tcount, (size_t)m,
+                                rocprim::equal_to<int32_t>(), st));
+        int64_t nt = 0;
+        TPM_HIP(hipMemcpy(&nt, tcount, sizeof(nt), hipMemcpyDeviceToHost));
+        G.ntimes = nt;
+        G.ttab = galloc<int32_t>(G, A_TTAB, nt, acct);
+        TPM_HIP(hipMemcpy(G.ttab, tuniq, sizeof(int32_t) * (size_t)nt, hipMemcpyDeviceToDevice));
+        G.h_ttab.resize((size_t)nt);
+        TPM_HIP(hipMemcpy(G.h_ttab.data(), tuniq, sizeof(int32_t) * (size_t)nt,
+                          hipMemcpyDeviceToHost));
+    }
+    k_inptr<<<grid_for(m + 1), 256, 0, st>>>(m, n, G.pdst, G.inptr);
+    if (m) {
+        int32_t *gpos = tmp.get<int32_t>(A_GPOS, m);
+        int32_t *needed = tmp.get<int32_t>(A_NEEDED, m);
+        int32_t *rowof = tmp.get<int32_t>(A_ROWOF, m);
+        TPM_HIP(hipMemsetAsync(needed, 0, sizeof(int32_t) * m, st));
+        k_gpos<<<grid_for(m), 256, 0, st>>>(m, G.psrc, G.ptau, G.inptr, gpos, needed);
+        size_t sbytes = 0;
+        TPM_HIP(rocprim::exclusive_scan(nullptr, sbytes, needed, rowof, 0, (size_t)m,
+                                        rocprim::plus<int32_t>(), st));
+        void *scratch = tmp.raw(A_SCRATCH, sbytes);
+        TPM_HIP(rocprim::exclusive_scan(scratch, sbytes, needed, rowof, 0, (size_t)m,
+                                        rocprim::plus<int32_t>(), st));
+        k_rows<<<grid_for(m), 256, 0, st>>>(m, gpos, needed, rowof, G.orow, G.gsrc);
+        int32_t last_row = 0, last_needed = 0;
+        TPM_HIP(hipMemcpy(&last_row, rowof + (m - 1), sizeof(int32_t), hipMemcpyDeviceToHost));
+        TPM_HIP(hipMemcpy(&last_needed, needed + (m - 1), sizeof(int32_t), hipMemcpyDeviceToHost));
+        G.R = (int64_t)last_row + last_needed;
+        unsigned long long *cnt = tmp.get<unsigned long long>(A_CNT, 1);
+        TPM_HIP(hipMemsetAsync(cnt, 0, sizeof(unsigned long long), st));
+        k_count_nonneg<<<std::min<unsigned>(grid_for(m), 4096), 256, 0, st>>>(m, G.gsrc, cnt);
+        unsigned long long h = 0;
+        TPM_HIP(hipMemcpy(&h, cnt, sizeof(h), hipMemcpyDeviceToHost));
+        G.gathers = (int64_t)h;
+    }
+    if (G.h_color.size() != (size_t)n) {
         G.h_color.resize((size_t)n);
         TPM_HIP(hipMemcpy(G.h_color.data(), G.color, sizeof(int32_t) * (size_t)n,
                           hipMemcpyDeviceToHost));
-        G.h_inptr.resize((size_t)n + 1);
-        TPM_HIP(hipMemcpy(G.h_inptr.data(), G.inptr, sizeof(int32_t) * ((size_t)n + 1),
-                          hipMemcpyDeviceToHost));
-        for (int32_t u = 0; u < n; ++u) {
-            int64_t d = G.h_inptr[u + 1] - G.h_inptr[u];
-            G.max_in_degree = std::max<int64_t>(G.max_in_degree, d);
-            G.segments += d > 0;
-        }
-        if (m) {
-            cnt = dalloc<unsigned long long>(1, tmp);
-            TPM_HIP(hipMemsetAsync(cnt, 0, sizeof(unsigned long long), st));
-            k_count_nonneg<<<std::min<unsigned>(grid_for(m), 4096), 256, 0, st>>>(m, G.gsrc, cnt);
-            unsigned long long h = 0;
-            TPM_HIP(hipMemcpy(&h, cnt, sizeof(h), hipMemcpyDeviceToHost));
-            G.gathers = (int64_t)h;
-        }
-
-        {
-            std::vector<int32_t> sn((size_t)n, -1);
-            int32_t nextv = -1;
-            for (int32_t u = n - 1; u >= 0; --u) {
-                sn[u] = nextv;
-                if (G.h_inptr[u + 1] > G.h_inptr[u]) nextv = u;
-            }
-            G.segnext = dalloc<int32_t>(n, acct);
-            TPM_HIP(hipMemcpy(G.segnext, sn.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice));
-        }
-        std::vector<int32_t> tp0, tpub, tlb;
-        build_tiles(G.h_inptr, T, tp0, tpub, tlb, G.nslots);
-        G.ntiles = (int64_t)tpub.size();
-        G.h_tile_p0 = tp0;
-        G.tile_p0 = dalloc<int32_t>(G.ntiles + 1, acct);
-        G.tile_pub = dalloc<int32_t>(G.ntiles, acct);
-        G.tile_lb = dalloc<int32_t>(G.ntiles, acct);
-        TPM_HIP(hipMemcpy(G.tile_p0, tp0.data(), sizeof(int32_t) * tp0.size(),
-                          hipMemcpyHostToDevice));
-        if (G.ntiles) {
-            TPM_HIP(hipMemcpy(G.tile_pub, tpub.data(), sizeof(int32_t) * tpub.size(),
-                              hipMemcpyHostToDevice));
-            TPM_HIP(hipMemcpy(G.tile_lb, tlb.data(), sizeof(int32_t) * tlb.size(),
-                              hipMemcpyHostToDevice));
-        }
-
-        // ---- LDS table image (see kLdsBytes)
-        std::vector<uint8_t> img(kLdsBytes, 0);
-        auto put32 = [&](size_t off, uint32_t v) { std::memcpy(img.data() + off, &v, 4); };
-        for (int v = 0; v < 256; ++v) {
-            uint32_t l7 = v ? ((uint32_t)kGf.log[v] << 7) : kZero7;
-            for (int c = 0; c < 32; ++c) put32((size_t)v * 256 + c * 4, l7);
-        }
-        for (int s = 0; s < kExpRows; ++s) {
-            uint32_t e = (s <= 762) ? kGf.exp[s % 255] : 0u;
-            for (int c = 0; c < 32; ++c) put32((size_t)kExpBase + (size_t)s * 128 + c * 4, e);
-        }
-        G.lds_image = (uint8_t *)dalloc<uint8_t>(kLdsBytes, acct);
-        TPM_HIP(hipMemcpy(G.lds_image, img.data(), kLdsBytes, hipMemcpyHostToDevice));
-        TPM_HIP(hipDeviceSynchronize());
-        TPM_HIP(hipDeviceSynchronize());
-    } catch (...) {
-        cleanup();
-        throw;
     }
-    cleanup();
+    G.h_inptr.resize((size_t)n + 1);
+    TPM_HIP(hipMemcpy(G.h_inptr.data(), G.inptr, sizeof(int32_t) * ((size_t)n + 1),
+                      hipMemcpyDeviceToHost));
+    G.max_in_degree = 0;
+    G.segments = 0;
+    std::vector<int32_t> sn((size_t)n, -1);
+    int32_t nextv = -1;
+    for (int32_t u = n - 1; u >= 0; --u) {
+        const int64_t d = G.h_inptr[u + 1] - G.h_inptr[u];
+        G.max_in_degree = std::max<int64_t>(G.max_in_degree, d);
+        G.segments += d > 0;
+        sn[u] = nextv;
+        if (d > 0) nextv = u;
+    }
+    G.segnext = galloc<int32_t>(G, A_SEGNEXT, n, acct);
+    TPM_HIP(hipMemcpy(G.segnext, sn.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice));
+    std::vector<int32_t> tp0, tpub, tlb;
+    build_tiles(G.h_inptr, T, tp0, tpub, tlb, G.nslots);
+    G.ntiles = (int64_t)tpub.size();
+    G.h_tile_p0 = tp0;
+    G.tile_p0 = galloc<int32_t>(G, A_TP0, G.ntiles + 1, acct);
+    G.tile_pub = galloc<int32_t>(G, A_TPUB, G.ntiles, acct);
+    G.tile_lb = galloc<int32_t>(G, A_TLB, G.ntiles, acct);
+    TPM_HIP(hipMemcpy(G.tile_p0, tp0.data(), sizeof(int32_t) * tp0.size(), hipMemcpyHostToDevice));
+    if (G.ntiles) {
+        TPM_HIP(hipMemcpy(G.tile_pub, tpub.data(), sizeof(int32_t) * tpub.size(),
+                          hipMemcpyHostToDevice));
+        TPM_HIP(hipMemcpy(G.tile_lb, tlb.data(), sizeof(int32_t) * tlb.size(),
+                          hipMemcpyHostToDevice));
+    }
+
+    // ---- LDS table image (see kLdsBytes)
+    std::vector<uint8_t> img(kLdsBytes, 0);
+    auto put32 = [&](size_t off, uint32_t v) { std::memcpy(img.data() + off, &v, 4); };
+    for (int v = 0; v < 256; ++v) {
+        uint32_t l7 = v ? ((uint32_t)kGf.log[v] << 7) : kZero7;
+        for (int c = 0; c < 32; ++c) put32((size_t)v * 256 + c * 4, l7);
+    }
+    for (int s2 = 0; s2 < kExpRows; ++s2) {
+        uint32_t e = (s2 <= 762) ? kGf.exp[s2 % 255] : 0u;
+        for (int c = 0; c < 32; ++c) put32((size_t)kExpBase + (size_t)s2 * 128 + c * 4, e);
+    }
+    G.lds_image = galloc<uint8_t>(G, A_LDS, kLdsBytes, acct);
+    TPM_HIP(hipMemcpy(G.lds_image, img.data(), kLdsBytes, hipMemcpyHostToDevice));
+    TPM_HIP(hipDeviceSynchronize());
 }
 
 void build_graph(Graph &G, int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
@@ -472,7 +505,7 @@ void build_graph(Graph &G, int32_t n, int64_t m, const int32_t *src, const int32
     cleanup_tmp();
 }
 
-void prune_graph(const Graph &P, const uint8_t *keep_color, Graph &G) {
+void prune_graph(const Graph &P, const uint8_t *keep_color, Graph &G, GraphArena *arena) {
     TPM_HIP(hipSetDevice(P.device));
     G.device = P.device;
     G.num_cu = P.num_cu;
@@ -481,56 +514,51 @@ void prune_graph(const Graph &P, const uint8_t *keep_color, Graph &G) {
     G.tmax = P.tmax;
     G.tile_edges = P.tile_edges;
     G.edge_ids = P.edge_ids;
-    int64_t acct = 0, tmp = 0;
+    G.arena = arena;
+    G.h_color = P.h_color;
+    int64_t acct = 0;
     hipStream_t st = nullptr;
-    uint8_t *keepc = nullptr;
-    int32_t *keep = nullptr, *at = nullptr;
-    void *scratch = nullptr;
-    auto cleanup = [&]() {
-        for (void *p : {(void *)keepc, (void *)keep, (void *)at, scratch})
-            if (p) (void)hipFree(p);
-    };
     try {
-        G.color = dalloc<int32_t>(P.n, acct);
-        TPM_HIP(hipMemcpy(G.color, P.color, sizeof(int32_t) * (size_t)P.n, hipMemcpyDeviceToDevice));
         int64_t mk = 0;
-        if (P.m) {
-            keepc = dalloc<uint8_t>(P.q, tmp);
-            TPM_HIP(hipMemcpy(keepc, keep_color, (size_t)P.q, hipMemcpyHostToDevice));
-            keep = dalloc<int32_t>(P.m, tmp);
-            at = dalloc<int32_t>(P.m, tmp);
-            k_keep<<<grid_for(P.m), 256, 0, st>>>(P.m, P.psrc, P.pdst, P.color, keepc, keep);
-            size_t sbytes = 0;
-            TPM_HIP(rocprim::exclusive_scan(nullptr, sbytes, keep, at, 0, (size_t)P.m,
-                                            rocprim::plus<int32_t>(), st));
-            TPM_HIP(hipMalloc(&scratch, std::max<size_t>(sbytes, 16)));
-            TPM_HIP(rocprim::exclusive_scan(scratch, sbytes, keep, at, 0, (size_t)P.m,
-                                            rocprim::plus<int32_t>(), st));
-            int32_t last_at = 0, last_keep = 0;
-            TPM_HIP(hipMemcpy(&last_at, at + (P.m - 1), sizeof(int32_t), hipMemcpyDeviceToHost));
-            TPM_HIP(hipMemcpy(&last_keep, keep + (P.m - 1), sizeof(int32_t), hipMemcpyDeviceToHost));
-            mk = (int64_t)last_at + last_keep;
+        int32_t *keep = nullptr, *at = nullptr;
+        {
+            Temps tmp(arena);
+            G.color = galloc<int32_t>(G, A_COLOR, P.n, acct);
+            TPM_HIP(hipMemcpyAsync(G.color, P.color, sizeof(int32_t) * (size_t)P.n,
+                                   hipMemcpyDeviceToDevice, st));
+            if (P.m) {
+                uint8_t *keepc = tmp.get<uint8_t>(A_KEEPC, P.q);
+                TPM_HIP(hipMemcpy(keepc, keep_color, (size_t)P.q, hipMemcpyHostToDevice));
+                keep = tmp.get<int32_t>(A_KEEP, P.m);
+                at = tmp.get<int32_t>(A_AT, P.m);
+                k_keep<<<grid_for(P.m), 256, 0, st>>>(P.m, P.psrc, P.pdst, P.color, keepc, keep);
+                size_t sbytes = 0;
+                TPM_HIP(rocprim::exclusive_scan(nullptr, sbytes, keep, at, 0, (size_t)P.m,
+                                                rocprim::plus<int32_t>(), st));
+                void *scratch = tmp.raw(A_SCRATCH, sbytes);
+                TPM_HIP(rocprim::exclusive_scan(scratch, sbytes, keep, at, 0, (size_t)P.m,
+                                                rocprim::plus<int32_t>(), st));
+                int32_t last_at = 0, last_keep = 0;
+                TPM_HIP(hipMemcpy(&last_at, at + (P.m - 1), sizeof(int32_t), hipMemcpyDeviceToHost));
+                TPM_HIP(hipMemcpy(&last_keep, keep + (P.m - 1), sizeof(int32_t), hipMemcpyDeviceToHost));
+                mk = (int64_t)last_at + last_keep;
+            }
+            G.m = mk;
+            G.pdst = galloc<int32_t>(G, A_PDST, mk, acct);
+            G.psrc = galloc<int32_t>(G, A_PSRC, mk, acct);
+            G.ptau = galloc<int32_t>(G, A_PTAU, mk, acct);
+            G.peid = galloc<int32_t>(G, A_PEID, mk, acct);
+            G.gsrc = galloc<int32_t>(G, A_GSRC, mk, acct);
+            G.orow = galloc<int32_t>(G, A_OROW, mk, acct);
+            G.inptr = galloc<int32_t>(G, A_INPTR, (int64_t)G.n + 1, acct);
+            if (mk)  // kept positions stay in (dst, tau, id) order
+                k_compact<<<grid_for(P.m), 256, 0, st>>>(P.m, keep, at, P.psrc, P.pdst, P.ptau,
+                                                          P.peid, G.psrc, G.pdst, G.ptau, G.peid);
+            TPM_HIP(hipDeviceSynchronize());
         }
-        G.m = mk;
-        G.pdst = dalloc<int32_t>(mk, acct);
-        G.psrc = dalloc<int32_t>(mk, acct);
-        G.ptau = dalloc<int32_t>(mk, acct);
-        G.peid = dalloc<int32_t>(mk, acct);
-        G.gsrc = dalloc<int32_t>(mk, acct);
-        G.orow = dalloc<int32_t>(mk, acct);
-        G.inptr = dalloc<int32_t>((int64_t)G.n + 1, acct);
-        if (mk)  // kept positions stay in (dst, tau, id) order
-            k_compact<<<grid_for(P.m), 256, 0, st>>>(P.m, keep, at, P.psrc, P.pdst, P.ptau, P.peid,
-                                                      G.psrc, G.pdst, G.ptau, G.peid);
-        TPM_HIP(hipDeviceSynchronize());
-        cleanup();
-        keepc = nullptr;
-        keep = at = nullptr;
-        scratch = nullptr;
         finish_index(G, acct, G.ptau);
         G.device_bytes = acct;
     } catch (...) {
-        cleanup();
         free_graph(G);
         throw;
     }

@@ -137,6 +137,7 @@ struct Workspace {
 // Workspaces of a graph: a call takes one (creating it if none is free) and
 // returns it when its stream is synchronised, so concurrent calls never share one.
 struct WorkspacePool;
+struct GraphArena;
 struct Graph;
 WorkspacePool *new_workspace_pool();
 void delete_workspace_pool(WorkspacePool *p);
@@ -188,6 +189,7 @@ struct Graph {
                                   // for a colour-pruned graph)
 
     WorkspacePool *pool = nullptr;  // owned
+    GraphArena *arena = nullptr;    // not owned: device arrays live there when set
 
     // host copies used by extraction
     std::vector<int32_t> h_inptr;   // [n+1]
@@ -208,7 +210,12 @@ void retile_graph(Graph &G, int32_t T);
 // keep_color[c] != 0 (host, P.q bytes).  Vertex ids, colours and input edge ids are
 // kept, so every fingerprint, and every sieve whose colours are all kept, is
 // unchanged.  G must be empty; on error G is freed.
-void prune_graph(const Graph &P, const uint8_t *keep_color, Graph &G);
+// With an arena, G's arrays and the build's temporaries live in the arena's grow-only
+// buffers (reused by the next graph built there; G must be freed before that).
+void prune_graph(const Graph &P, const uint8_t *keep_color, Graph &G,
+                 GraphArena *arena = nullptr);
+GraphArena *new_graph_arena();
+void delete_graph_arena(GraphArena *a);
 
 // ------------------------------------------------------------------ sieve
 struct SieveRequest {

@@ -65,6 +65,13 @@ class tpm_autotune_report(ctypes.Structure):
                 ("cand_chunk", ctypes.c_int32 * 12), ("cand_rate", ctypes.c_double * 12)]
 
 
+class tpm_server_stats(ctypes.Structure):
+    _fields_ = [("completed", ctypes.c_int64), ("steps", ctypes.c_int64),
+                ("row_points", ctypes.c_int32), ("lanes", ctypes.c_int32),
+                ("prune_ms", ctypes.c_double), ("sieve_ms", ctypes.c_double),
+                ("extract_ms", ctypes.c_double)]
+
+
 class tpm_query(ctypes.Structure):
     _fields_ = [("multiset", _i32p), ("k", ctypes.c_int32), ("seed", ctypes.c_uint64),
                 ("want_path", ctypes.c_int32)]
@@ -121,6 +128,7 @@ _sig("tpm_server_create", ctypes.c_int32, [_vp, ctypes.POINTER(tpm_server_config
 _sig("tpm_server_submit", ctypes.c_int32, [_vp, ctypes.POINTER(tpm_query), _u64p])
 _sig("tpm_server_poll", ctypes.c_int32, [_vp, ctypes.POINTER(tpm_result), ctypes.c_int32, _i32p])
 _sig("tpm_server_destroy", None, [_vp])
+_sig("tpm_server_stats_get", ctypes.c_int32, [_vp, ctypes.POINTER(tpm_server_stats)])
 _sig("tpm_profile_enable", ctypes.c_int32, [ctypes.c_int32])
 _sig("tpm_profile_read", ctypes.c_int32, [ctypes.POINTER(tpm_kernel_time), ctypes.c_int32, _i32p])
 _sig("tpm_last_error", ctypes.c_char_p, [])
@@ -131,6 +139,7 @@ EXPORTED = ["tpm_graph_create", "tpm_graph_create_ex", "tpm_graph_destroy", "tpm
             "tpm_optimum_time",
             "tpm_sieve", "tpm_sieve_ex", "tpm_decide", "tpm_extract", "tpm_batch_run",
             "tpm_server_create", "tpm_server_submit", "tpm_server_poll", "tpm_server_destroy",
+            "tpm_server_stats_get",
             "tpm_profile_enable", "tpm_profile_read", "tpm_last_error", "tpm_version"]
 
 
@@ -339,6 +348,12 @@ def tpm_server_poll(s, max_results=64):
     return [_result_dict(out[i]) for i in range(n.value)]
 
 
+def tpm_server_stats_get(s) -> dict:
+    st = tpm_server_stats()
+    _check(_lib.tpm_server_stats_get(s, ctypes.byref(st)))
+    return {f: getattr(st, f) for f, _ in tpm_server_stats._fields_}
+
+
 def tpm_server_destroy(s) -> None:
     _lib.tpm_server_destroy(s)
 
@@ -428,6 +443,9 @@ class Server:
 
     def submit(self, multiset, seed, want_path=0) -> int:
         return tpm_server_submit(self.h, multiset, seed, want_path)
+
+    def stats(self) -> dict:
+        return tpm_server_stats_get(self.h)
 
     def poll(self, max_results=64):
         return tpm_server_poll(self.h, max_results)

@@ -169,7 +169,10 @@ def test_pruned_server_matches_alone(tpm, graph):
     srv = tpm.Server(Gd, prune_queries=1, extract_paths=1)
     tickets = [srv.submit(q["multiset"], q["seed"]) for q in qs]
     got = {r["ticket"]: r for r in srv.drain(len(qs), timeout_s=300)}
+    st = srv.stats()
     srv.close()
+    assert st["completed"] == len(qs) and st["steps"] == len(qs)
+    assert st["prune_ms"] > 0 and st["sieve_ms"] > 0 and st["row_points"] == 0
     for t, q in zip(tickets, qs):
         r = got[t]
         want = oracle.sieve_total(graph, q["multiset"], q["seed"])
