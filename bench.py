@@ -191,7 +191,9 @@ def main() -> int:
         "query_ms_p99": float(np.percentile(lat, 99)),
         "hbm_gbps_algorithmic_query": hbm_alg,
         "roofline": {
-            "bound": "hbm", "kernel": f"k_level (W={4 if C >= 1024 else (2 if C >= 512 else 1)}, {dom})",
+            "bound": "hbm",
+            "kernel": (f"k_level (1024-point rows, {dom} level)" if C >= 1024
+                       else f"k_narrow ({C}-point rows, {dom} level)"),
             "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
             "alg_bytes_per_launch": alg, "avg_launch_ms": avg_ms, "launches": len(kinds.get(dom, [])),

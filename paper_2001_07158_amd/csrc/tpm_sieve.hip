@@ -83,6 +83,8 @@ struct LevelParams {
     uint32_t ylevel;         // walk position of y used at this level (= l - 1)
     int32_t rowb;            // bytes per row = sieve points per chunk
     int32_t lanes;           // lanes holding points = rowb / (4 W)
+    int32_t valid_pts;       // points of the chunk that are sieve points (a row of 16
+                             // points for 2^k < 16 repeats them; localisation skips the rest)
 };
 
 struct StepParams {
@@ -600,7 +602,16 @@ __global__ void __launch_bounds__(1024) k_narrow(LevelParams P) {
                         for (int w = 0; w < 4; ++w) fin[w] ^= c[w];
                     }
                     if (P.loc) {
-                        uint32_t x = inr ? (c[0] ^ c[1] ^ c[2] ^ c[3]) : 0u;
+                        // only this chunk's real sieve points count
+                        const int lim = P.valid_pts - sub * 16;
+                        uint32_t x = 0;
+#pragma unroll
+                        for (int w = 0; w < 4; ++w) {
+                            const int nb = min(4, max(0, lim - 4 * w));
+                            const uint32_t keep = nb >= 4 ? 0xFFFFFFFFu : ((1u << (8 * nb)) - 1u);
+                            x ^= c[w] & keep;
+                        }
+                        if (!inr) x = 0;
                         x ^= x >> 16;
                         x ^= x >> 8;
                         x &= 0xFFu;
@@ -1121,29 +1132,26 @@ void launch_level(const Graph &G, const LevelParams &P, hipStream_t st) {
     hipLaunchKernelGGL((k_level<W, FIN>), dim3((unsigned)G.num_cu), dim3(1024), 0, st, P);
 }
 
-void launch_level_w(int W, bool fin, const Graph &G, const LevelParams &P, hipStream_t st) {
-    if (W == 4) fin ? launch_level<4, true>(G, P, st) : launch_level<4, false>(G, P, st);
-    else if (W == 2) fin ? launch_level<2, true>(G, P, st) : launch_level<2, false>(G, P, st);
-    else fin ? launch_level<1, true>(G, P, st) : launch_level<1, false>(G, P, st);
-}
-
 template <int LP>
 void launch_narrow(bool fin, const Graph &G, const LevelParams &P, hipStream_t st) {
     if (fin) hipLaunchKernelGGL((k_narrow<LP, true>), dim3((unsigned)G.num_cu), dim3(1024), 0, st, P);
     else hipLaunchKernelGGL((k_narrow<LP, false>), dim3((unsigned)G.num_cu), dim3(1024), 0, st, P);
 }
 
-// rows of 64..512 points run edge-parallel (k_narrow); wider and narrower rows k_level
-bool is_narrow(int rowb) { return rowb >= 64 && rowb <= 512; }
+// rows of 16..512 points run edge-parallel (k_narrow), rows of 1024 points k_level
+bool is_narrow(int rowb) { return rowb >= 16 && rowb <= 512; }
 
-void launch_level_any(int rowb, int W, bool fin, const Graph &G, const LevelParams &P,
-                      hipStream_t st) {
+void launch_level_any(int rowb, bool fin, const Graph &G, const LevelParams &P, hipStream_t st) {
     switch (is_narrow(rowb) ? rowb / 16 : 0) {
+        case 1: launch_narrow<1>(fin, G, P, st); break;
+        case 2: launch_narrow<2>(fin, G, P, st); break;
         case 4: launch_narrow<4>(fin, G, P, st); break;
         case 8: launch_narrow<8>(fin, G, P, st); break;
         case 16: launch_narrow<16>(fin, G, P, st); break;
         case 32: launch_narrow<32>(fin, G, P, st); break;
-        default: launch_level_w(W, fin, G, P, st);
+        default:
+            TPM_REQUIRE(rowb == 1024, "sieve rows hold 16..1024 points");
+            fin ? launch_level<4, true>(G, P, st) : launch_level<4, false>(G, P, st);
     }
 }
 
@@ -1157,13 +1165,14 @@ int pick_chunk(const Graph &G, int32_t k, int32_t requested) {
     const int64_t npts = int64_t(1) << k;
     int64_t c = requested > 0 ? requested : std::min<int64_t>(npts, 1024);
     TPM_REQUIRE((c & (c - 1)) == 0 && c >= 4 && c <= 1024, "chunk must be a power of two in [4, 1024]");
-    c = std::min<int64_t>(c, std::max<int64_t>(npts, 4));
+    c = std::min<int64_t>(c, std::max<int64_t>(npts, 16));
     // fit the two level buffers into free device memory
     size_t freeb = 0, totalb = 0;
     if (hipMemGetInfo(&freeb, &totalb) == hipSuccess && requested <= 0) {
-        while (c > 4 && (double)(2 * G.R + G.n + 2 * G.nslots) * c > 0.85 * (double)freeb) c >>= 1;
+        while (c > 16 && (double)(2 * G.R + G.n + 2 * G.nslots) * c > 0.85 * (double)freeb) c >>= 1;
     }
-    return (int)c;
+    // rows hold at least 16 points (one lane): smaller queries repeat their points
+    return (int)std::max<int64_t>(c, 16);
 }
 
 }  // namespace
@@ -1179,12 +1188,11 @@ void run_sieve_impl(const Graph &G, const SieveRequest &req, SieveResult &res, b
     QuerySlots qs = make_slots(G, req.multiset, k);
     const int64_t npts = int64_t(1) << k;
     const int rowb = (k == 1) ? 4 : pick_chunk(G, k, req.chunk);
-    const int W = rowb >= 1024 ? 4 : (rowb >= 512 ? 2 : 1);
-    // lanes holding points: 64 lanes of 4W points, or one 16-point lane per 16 points of
-    // a narrow row (its E = 1024 / rowb slots repeat the same lanes)
-    const int lanes = is_narrow(rowb) ? rowb / 16 : rowb / (4 * W);
+    // lanes holding points: 64 lanes of 16 points for 1024-point rows, else one 16-point
+    // lane per 16 points of a narrow row (its 1024 / rowb slots repeat the same lanes)
+    const int lanes = std::max(1, rowb / 16);
     const int rowd = rowb / 4;
-    const int64_t ppbytes = std::max<int64_t>(npts, 4);
+    const int64_t ppbytes = std::max<int64_t>(npts, rowb);
 
     WorkspaceLease lease(G);
     Workspace &ws = *lease.ws;
@@ -1269,10 +1277,11 @@ void run_sieve_impl(const Graph &G, const SieveRequest &req, SieveResult &res, b
                 P.ylevel = (uint32_t)(l - 1);
                 P.rowb = rowb;
                 P.lanes = lanes;
+                P.valid_pts = (int32_t)std::min<int64_t>(rowb, npts - base);
                 k_prep<<<1, 1, 0, st>>>(ctl.as<Ctl>(), fin ? 0 : 1);
                 {
                     ProfileScope prof(st, fin ? 2 : (l == 2 ? 0 : 1), l, rowb);
-                    launch_level_any(rowb, W, fin, G, P, st);
+                    launch_level_any(rowb, fin, G, P, st);
                 }
             }
         }
