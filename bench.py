@@ -25,25 +25,34 @@ sys.path.insert(0, ROOT)
 
 METRIC = "GF(2^8) sieve edge-updates/s (m·k·2^k) at k=10; HBM GB/s; p50/p99 query ms"
 HBM_PEAK_GBPS = 8000.0
-PMC_FILE = os.path.join(ROOT, "profiles", "k10_level_middle_pmc.txt")
+# committed rocprofv3 PMC summaries of the middle-level kernel, by sieve points per row
+PMC_FILES = {1024: os.path.join(ROOT, "profiles", "k10_level_middle_pmc.txt"),
+             256: os.path.join(ROOT, "profiles", "k10_narrow_c256_middle_pmc.txt")}
 KERNEL_SRC = os.path.join(ROOT, "paper_2001_07158_amd", "csrc", "tpm_sieve.hip")
 
 
-def kernel_hash() -> str:
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+def kernel_hash(points: int = 1024) -> str:
+    """Hash of the level kernel's source for rows of `points` sieve points: the file up
+    to the narrow-row kernel (1024-point rows: parameters, helpers, k_level), or up to
+    the end of the narrow-row kernel (smaller rows)."""
+    text = open(KERNEL_SRC, "rb").read()
+    marker = b"// Narrow rows:" if points >= 1024 else b"__global__ void k_prep"
+    cut = text.find(marker)
+    return hashlib.sha256(text if cut < 0 else text[:cut]).hexdigest()[:16]
 
 
-def read_traffic(bytes_alg: float):
+def read_traffic(points: int):
     """HBM bytes per launch of the middle-level kernel from committed rocprofv3 PMC
-    summaries, if they were taken on the current kernel source."""
-    if not os.path.exists(PMC_FILE):
+    summaries, if they were taken on the current kernel source at this row width."""
+    path = PMC_FILES.get(points)
+    if path is None or not os.path.exists(path):
         return None
     kv = {}
-    for line in open(PMC_FILE):
+    for line in open(path):
         if "=" in line and not line.lstrip().startswith("#"):
             a, b = line.split("=", 1)
             kv[a.strip()] = b.strip()
-    if kv.get("kernel_hash") != kernel_hash():
+    if kv.get("kernel_hash") != kernel_hash(points):
         return None
     try:
         return float(kv["hbm_bytes_per_launch"])
@@ -159,7 +168,7 @@ def main() -> int:
     else:
         alg = st["gathers"] * float(C) + struct
     achieved = alg / (avg_ms / 1e3) / 1e9
-    traffic = read_traffic(alg)
+    traffic = read_traffic(C) if dom == "middle" else None
     # whole-query algorithmic bytes (all levels, all chunks)
     nchunks = max(1, (1 << k) // C)
     q_bytes = nchunks * ((g.m + st["rows"]) * float(C) + struct
@@ -197,7 +206,7 @@ def main() -> int:
             "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
             "alg_bytes_per_launch": alg, "avg_launch_ms": avg_ms, "launches": len(kinds.get(dom, [])),
-            "kernel_hash": kernel_hash(),
+            "kernel_hash": kernel_hash(C),
         },
         "cpu_baseline": None,
     }

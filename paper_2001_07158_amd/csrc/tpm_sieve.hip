@@ -477,7 +477,7 @@ __global__ void __launch_bounds__(1024) k_level(LevelParams P) {
 }
 
 // ---------------------------------------------------------------------------------
-// Narrow rows: C = 16 LP points (LP = 4..32 lanes per row, 16 points per lane).  A
+// Narrow rows: C = 16 LP points (LP = 1..32 lanes per row, 16 points per lane).  A
 // wave processes E = 64 / LP consecutive positions side by side, one per slot of LP
 // lanes, so the per-edge fixed work (metadata, fingerprint, branch, address) is shared
 // by E edges.  The running value of an in-list then comes from an inclusive segmented
