@@ -60,6 +60,10 @@ def lib():
         L.or_sieve.argtypes = [ctypes.c_int32, ctypes.c_int64, _i32p, _i32p, _i32p, _i32p,
                                ctypes.c_int32, _i32p, ctypes.c_int32, ctypes.c_uint64, _u8p,
                                _u32p, ctypes.c_int64, _u8p, _u8p, ctypes.c_int]
+        L.or_sieve_ex.argtypes = [ctypes.c_int32, ctypes.c_int64, _i32p, _i32p, _i32p, _i32p,
+                                  _i32p, _i32p, ctypes.c_int32, _i32p, ctypes.c_int32,
+                                  ctypes.c_uint64, _u8p, _u32p, ctypes.c_int64, _u8p, _u8p,
+                                  ctypes.c_int]
         L.or_colorful_exists.argtypes = [ctypes.c_int32, ctypes.c_int64, _i32p, _i32p, _i32p,
                                          _i32p, ctypes.c_int32, _i32p, ctypes.c_int32]
         L.or_init()
@@ -116,10 +120,14 @@ def zvals(g, M, seed: int, mask=None) -> np.ndarray:
     return z
 
 
-def sieve(g, M, seed: int, points=None, mask=None, loc: bool = False, nthreads: int = 0):
+def sieve(g, M, seed: int, points=None, mask=None, loc: bool = False, nthreads: int = 0,
+          transit=None, delay=None):
     """P(A) for the given sieve points (default: all 2^k).  Returns the per-point
     array, or (per_point, per_edge_localisation) when loc=True (localisation is
-    XOR-ed over the given points)."""
+    XOR-ed over the given points).  transit (per edge) and delay (per vertex) select
+    the variant with transition and delay times (section "Path motif problem with
+    delays"): an edge reaches its head at tau + transit, and a walk leaves a vertex w
+    at time tau only if it arrived by tau - delay(w); defaults 0 and 1."""
     M = _c32(M)
     k = len(M)
     if points is None:
@@ -129,48 +137,59 @@ def sieve(g, M, seed: int, points=None, mask=None, loc: bool = False, nthreads: 
     lc = np.empty(g.m, dtype=np.uint8) if loc else None
     src, dst, tau, color = _c32(g.src), _c32(g.dst), _c32(g.tau), _c32(g.color)
     mk = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8)
-    rc = lib().or_sieve(g.n, g.m, _p(src, _i32p), _p(dst, _i32p), _p(tau, _i32p),
-                        _p(color, _i32p), g.num_colors, _p(M, _i32p), k,
-                        seed & 0xFFFFFFFFFFFFFFFF, _p(mk, _u8p), _p(points, _u32p),
-                        points.shape[0], _p(out, _u8p), _p(lc, _u8p), nthreads)
+    tr = None if transit is None else _c32(transit)
+    dl = None if delay is None else _c32(delay)
+    rc = lib().or_sieve_ex(g.n, g.m, _p(src, _i32p), _p(dst, _i32p), _p(tau, _i32p),
+                           _p(tr, _i32p), _p(dl, _i32p), _p(color, _i32p), g.num_colors,
+                           _p(M, _i32p), k, seed & 0xFFFFFFFFFFFFFFFF, _p(mk, _u8p),
+                           _p(points, _u32p), points.shape[0], _p(out, _u8p), _p(lc, _u8p),
+                           nthreads)
     if rc:
         raise RuntimeError(f"oracle failed ({rc})")
     return (out, lc) if loc else out
 
 
-def sieve_total(g, M, seed: int, mask=None, nthreads: int = 0) -> int:
-    pp = sieve(g, M, seed, mask=mask, nthreads=nthreads)
+def sieve_total(g, M, seed: int, mask=None, nthreads: int = 0, transit=None, delay=None) -> int:
+    pp = sieve(g, M, seed, mask=mask, nthreads=nthreads, transit=transit, delay=delay)
     return int(np.bitwise_xor.reduce(pp)) if pp.size else 0
 
 
-def vertex_sieve(g, M, seed: int, mask=None, nthreads: int = 0) -> np.ndarray:
+def vertex_sieve(g, M, seed: int, mask=None, nthreads: int = 0, transit=None,
+                 delay=None) -> np.ndarray:
     """Vertex-localised sieve (section "Vertex-localization"): Q_u = sum over all
     sieve points A of P_{u,k,t}(z^A).  P_{u,k,t} is the sum of the last-level
     contributions of u's in-edges, so Q_u is the XOR of the per-edge localisation
     over the edges that end at u.  k >= 2."""
     if len(M) < 2:
         raise ValueError("vertex localisation needs k >= 2")
-    _, lc = sieve(g, M, seed, mask=mask, loc=True, nthreads=nthreads)
+    _, lc = sieve(g, M, seed, mask=mask, loc=True, nthreads=nthreads, transit=transit,
+                  delay=delay)
     q = np.zeros(g.n, dtype=np.uint8)
     np.bitwise_xor.at(q, np.asarray(g.dst, dtype=np.int64), lc)
     return q
 
 
-def time_buckets(g, M, seed: int, mask=None, nthreads: int = 0):
-    """Per-timestamp split of the sieve: for each distinct timestamp t (ascending),
-    B(t) = XOR of the per-edge localisation over the edges with timestamp t.  A
-    walk's last edge carries its largest timestamp, so the XOR of B over times <= t
-    is the sieve restricted to walks that finish by t.  k >= 2."""
+def time_buckets(g, M, seed: int, mask=None, nthreads: int = 0, transit=None, delay=None):
+    """Per-timestamp split of the sieve: for each distinct arrival time t (ascending;
+    arrival = timestamp without transition times), B(t) = XOR of the per-edge
+    localisation over the edges arriving at t.  A walk's last edge arrives last, so
+    the XOR of B over times <= t is the sieve restricted to walks that finish by t.
+    k >= 2."""
     if len(M) < 2:
         raise ValueError("time buckets need k >= 2")
-    _, lc = sieve(g, M, seed, mask=mask, loc=True, nthreads=nthreads)
-    times, inv = np.unique(np.asarray(g.tau, dtype=np.int64), return_inverse=True)
+    _, lc = sieve(g, M, seed, mask=mask, loc=True, nthreads=nthreads, transit=transit,
+                  delay=delay)
+    arr = np.asarray(g.tau, dtype=np.int64)
+    if transit is not None:
+        arr = arr + np.asarray(transit, dtype=np.int64)
+    times, inv = np.unique(arr, return_inverse=True)
     b = np.zeros(times.shape[0], dtype=np.uint8)
     np.bitwise_xor.at(b, inv, lc)
     return times.astype(np.int32), b
 
 
-def optimum_time(g, M, seed: int, reps: int = 1, nthreads: int = 0) -> int:
+def optimum_time(g, M, seed: int, reps: int = 1, nthreads: int = 0, transit=None,
+                 delay=None) -> int:
     """Section "Finding optimum timestamp": the smallest t such that the sieve over
     walks finishing by t is nonzero, minimised over `reps` seeds (seed_r = seed +
     r * 0x9E3779B97F4A7C15, as for decide); -1 if none.  The prefix XOR of the time
@@ -179,7 +198,7 @@ def optimum_time(g, M, seed: int, reps: int = 1, nthreads: int = 0) -> int:
     best = -1
     for r in range(reps):
         sr = (seed + r * 0x9E3779B97F4A7C15) & 0xFFFFFFFFFFFFFFFF
-        times, b = time_buckets(g, M, sr, nthreads=nthreads)
+        times, b = time_buckets(g, M, sr, nthreads=nthreads, transit=transit, delay=delay)
         nz = np.nonzero(b)[0]
         if nz.size:
             t = int(times[nz[0]])

@@ -147,9 +147,11 @@ def subset_values(z: np.ndarray) -> np.ndarray:
 
 
 # --------------------------------------------------------------------------- walks
-def temporal_walks(g, k: int):
+def temporal_walks(g, k: int, transit=None, delay=None):
     """All temporal walks with k vertices: lists of edge ids (e_1..e_{k-1}) with
-    dst(e_l) = src(e_{l+1}) and tau strictly increasing.  k = 1: one per vertex."""
+    dst(e_l) = src(e_{l+1}) and tau strictly increasing.  k = 1: one per vertex.
+    With transit (per edge) / delay (per vertex): e_{l+1} may follow e_l through w
+    iff tau(e_l) + transit(e_l) <= tau(e_{l+1}) - delay(w) (defaults 0 and 1)."""
     if k == 1:
         return [((u,), ()) for u in range(g.n)]
     out_edges = [[] for _ in range(g.n)]
@@ -163,8 +165,11 @@ def temporal_walks(g, k: int):
             res.append((verts, tuple(edges)))
             return
         last = edges[-1]
-        for e in out_edges[int(g.dst[last])]:
-            if g.tau[e] > g.tau[last]:
+        w = int(g.dst[last])
+        arr = int(g.tau[last]) + (int(transit[last]) if transit is not None else 0)
+        dl = int(delay[w]) if delay is not None else 1
+        for e in out_edges[w]:
+            if arr <= int(g.tau[e]) - dl:
                 extend(edges + [e])
 
     for e in range(g.m):
@@ -172,14 +177,14 @@ def temporal_walks(g, k: int):
     return res
 
 
-def brute_per_point(g, M, seed: int, mask=None) -> np.ndarray:
+def brute_per_point(g, M, seed: int, mask=None, transit=None, delay=None) -> np.ndarray:
     """P(A) for every A as the sum over temporal walks of their monomials,
     x_{w_1} y_{e_1,1} x_{w_2} ... y_{e_{k-1},k-1} x_{w_k}, evaluated at z^A."""
     k = len(M)
     T = mul_table()
     X = subset_values(zvals(g, M, seed, mask))
     acc = np.zeros(1 << k, dtype=np.uint8)
-    for verts, edges in temporal_walks(g, k):
+    for verts, edges in temporal_walks(g, k, transit, delay):
         v = X[verts[0]].copy()
         for l, e in enumerate(edges, start=1):
             v = T[v, fp(seed, TAG_Y, l, e)]
@@ -278,18 +283,19 @@ def literal_eq3_per_point(g, M, seed: int, mask=None) -> np.ndarray:
     return out
 
 
-def has_matching_path(g, M) -> bool:
+def has_matching_path(g, M, transit=None, delay=None) -> bool:
     want = sorted(int(c) for c in M)
-    for verts, _ in temporal_walks(g, len(M)):
+    for verts, _ in temporal_walks(g, len(M), transit, delay):
         if len(set(verts)) == len(verts) and sorted(int(g.color[u]) for u in verts) == want:
             return True
     return False
 
 
-def check_path(g, M, verts, edges) -> bool:
+def check_path(g, M, verts, edges, transit=None, delay=None) -> bool:
     """Exact check of an extracted witness: k distinct vertices, k-1 edges whose
-    endpoints match consecutive vertices, strictly increasing timestamps, and
-    vertex colours equal to the multiset M."""
+    endpoints match consecutive vertices, strictly increasing timestamps (or, with
+    transition / delay times, each edge leaving after the previous one arrived plus
+    the vertex's delay), and vertex colours equal to the multiset M."""
     k = len(M)
     verts = [int(v) for v in verts]
     edges = [int(e) for e in edges]
@@ -303,8 +309,12 @@ def check_path(g, M, verts, edges) -> bool:
             return False
         if int(g.src[e]) != verts[l] or int(g.dst[e]) != verts[l + 1]:
             return False
-        if l and not (g.tau[e] > g.tau[edges[l - 1]]):
-            return False
+        if l:
+            prev = edges[l - 1]
+            arr = int(g.tau[prev]) + (int(transit[prev]) if transit is not None else 0)
+            dl = int(delay[verts[l]]) if delay is not None else 1
+            if not arr <= int(g.tau[e]) - dl:
+                return False
     return sorted(int(g.color[v]) for v in verts) == sorted(int(c) for c in M)
 
 

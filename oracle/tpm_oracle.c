@@ -166,10 +166,12 @@ typedef struct {
     int32_t n;
     int64_t m;
     const int32_t *src, *dst, *tau;
+    int32_t *arr;   /* [m] arrival times tau + transit (owned; NULL when arrival = tau) */
     int64_t *start; /* [n+1]: in-list of v is order[start[v] .. start[v+1]) */
-    int64_t *order; /* [m]: edge ids, grouped by dst, each group by (tau, id) */
-    int64_t *gpos;  /* [m]: position in `order` of the last in-edge e' of src_e
-                       with tau' < tau_e, or -1 if there is none */
+    int64_t *order; /* [m]: edge ids, grouped by dst, each group by (arrival, id) */
+    int64_t *gpos;  /* [m]: position in `order` of the last in-edge e' of src_e whose
+                       arrival is <= tau_e - delay(src_e) (delay 1: arrival < tau_e),
+                       or -1 if there is none */
 } or_index;
 
 static const int32_t *g_cmp_tau;
@@ -188,12 +190,18 @@ void or_index_free(or_index *ix)
     free(ix->start);
     free(ix->order);
     free(ix->gpos);
+    free(ix->arr);
     free(ix);
 }
 
-/* The arrays are borrowed and must outlive the index. */
-or_index *or_index_build(int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
-                         const int32_t *tau)
+/* Section "Path motif problem with delays": an edge (v -> u, tau) with transition
+ * time eps reaches u at tau + eps, and a walk may leave a vertex w at time tau only
+ * if it arrived at w by tau - delay(w).  transit (per edge, >= 0) and delay (per
+ * vertex, >= 0) are nullable: no transit means arrival = tau, no delay means 1 (the
+ * strictly increasing times of the plain problem).  The arrays are borrowed and must
+ * outlive the index. */
+or_index *or_index_build_ex(int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                            const int32_t *tau, const int32_t *transit, const int32_t *delay)
 {
     or_index *ix = calloc(1, sizeof(or_index));
     if (!ix)
@@ -203,6 +211,17 @@ or_index *or_index_build(int32_t n, int64_t m, const int32_t *src, const int32_t
     ix->src = src;
     ix->dst = dst;
     ix->tau = tau;
+    const int32_t *arr = tau;
+    if (transit) {
+        ix->arr = malloc(sizeof(int32_t) * (size_t)(m ? m : 1));
+        if (!ix->arr) {
+            free(ix);
+            return NULL;
+        }
+        for (int64_t e = 0; e < m; e++)
+            ix->arr[e] = tau[e] + transit[e];
+        arr = ix->arr;
+    }
     ix->start = calloc((size_t)n + 1, sizeof(int64_t));
     ix->order = malloc(sizeof(int64_t) * (size_t)(m ? m : 1));
     ix->gpos = malloc(sizeof(int64_t) * (size_t)(m ? m : 1));
@@ -219,16 +238,18 @@ or_index *or_index_build(int32_t n, int64_t m, const int32_t *src, const int32_t
     for (int64_t e = 0; e < m; e++)
         ix->order[fill[dst[e]]++] = e;
     free(fill);
-    g_cmp_tau = tau; /* single-threaded build */
+    g_cmp_tau = arr; /* single-threaded build */
     for (int32_t v = 0; v < n; v++)
         qsort(ix->order + ix->start[v], (size_t)(ix->start[v + 1] - ix->start[v]),
               sizeof(int64_t), cmp_by_tau_then_id);
     for (int64_t e = 0; e < m; e++) {
-        int32_t v = src[e], t = tau[e];
-        int64_t lo = ix->start[v], hi = ix->start[v + 1]; /* first position with tau >= t */
+        int32_t v = src[e];
+        /* in-edges of v that arrived by tau_e - delay(v): arrival < th */
+        int64_t th = (int64_t)tau[e] - (delay ? delay[v] : 1) + 1;
+        int64_t lo = ix->start[v], hi = ix->start[v + 1]; /* first position with arrival >= th */
         while (lo < hi) {
             int64_t mid = lo + (hi - lo) / 2;
-            if (tau[ix->order[mid]] < t)
+            if ((int64_t)arr[ix->order[mid]] < th)
                 lo = mid + 1;
             else
                 hi = mid;
@@ -236,6 +257,12 @@ or_index *or_index_build(int32_t n, int64_t m, const int32_t *src, const int32_t
         ix->gpos[e] = (lo > ix->start[v]) ? lo - 1 : -1;
     }
     return ix;
+}
+
+or_index *or_index_build(int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                         const int32_t *tau)
+{
+    return or_index_build_ex(n, m, src, dst, tau, NULL, NULL);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -346,11 +373,26 @@ int or_eval(const or_index *ix, const uint8_t *z, int32_t k, uint64_t seed,
     return err;
 }
 
-/* One-shot convenience: index + z + evaluation. */
+/* One-shot convenience: index + z + evaluation, with optional transition times and
+ * delays (as or_index_build_ex). */
+int or_sieve_ex(int32_t n, int64_t m, const int32_t *src, const int32_t *dst, const int32_t *tau,
+                const int32_t *transit, const int32_t *delay, const int32_t *color, int32_t q,
+                const int32_t *M, int32_t k, uint64_t seed, const uint8_t *mask,
+                const uint32_t *points, int64_t npoints, uint8_t *out, uint8_t *loc, int nthreads);
+
 int or_sieve(int32_t n, int64_t m, const int32_t *src, const int32_t *dst, const int32_t *tau,
              const int32_t *color, int32_t q, const int32_t *M, int32_t k, uint64_t seed,
              const uint8_t *mask, const uint32_t *points, int64_t npoints, uint8_t *out,
              uint8_t *loc, int nthreads)
+{
+    return or_sieve_ex(n, m, src, dst, tau, NULL, NULL, color, q, M, k, seed, mask, points,
+                       npoints, out, loc, nthreads);
+}
+
+int or_sieve_ex(int32_t n, int64_t m, const int32_t *src, const int32_t *dst, const int32_t *tau,
+                const int32_t *transit, const int32_t *delay, const int32_t *color, int32_t q,
+                const int32_t *M, int32_t k, uint64_t seed, const uint8_t *mask,
+                const uint32_t *points, int64_t npoints, uint8_t *out, uint8_t *loc, int nthreads)
 {
     or_init();
     if (n < 1 || m < 0 || k < 1 || k > 16)
@@ -363,7 +405,7 @@ int or_sieve(int32_t n, int64_t m, const int32_t *src, const int32_t *dst, const
         free(z);
         return rc;
     }
-    or_index *ix = or_index_build(n, m, src, dst, tau);
+    or_index *ix = or_index_build_ex(n, m, src, dst, tau, transit, delay);
     if (!ix) {
         free(z);
         return -2;

@@ -267,6 +267,43 @@ def test_optimum_time_never_below_and_usually_exact():
     assert total > 10 and exact >= total - 2
 
 
+def test_delays_and_transition_times_match_walk_enumeration():
+    """Variant with transition times (per edge) and delays (per vertex): the oracle
+    equals the brute-force walk sum under the rule arrival(e_l) <= tau(e_{l+1}) -
+    delay(w); transit 0 / delay 1 is the plain problem bit for bit."""
+    rng = np.random.default_rng(84)
+    for it in range(80):
+        g = G.random_tiny_graph(rng, n_max=10, m_max=30, t_max=6)
+        k = int(rng.integers(2, 5))
+        M = [int(c) for c in rng.integers(0, g.num_colors, k)]
+        tr = rng.integers(0, 3, g.m).astype(np.int32)
+        dl = rng.integers(0, 3, g.n).astype(np.int32)
+        seed = 70 + it
+        assert np.array_equal(oracle.sieve(g, M, seed, transit=tr, delay=dl),
+                              pyref.brute_per_point(g, M, seed, transit=tr, delay=dl)), it
+        assert np.array_equal(
+            oracle.sieve(g, M, seed, transit=np.zeros(g.m, np.int32), delay=np.ones(g.n, np.int32)),
+            oracle.sieve(g, M, seed))
+
+
+def test_delays_worked_cases():
+    """Two edges a -> b (time 1) and b -> c (time 2), colours all distinct: with delay
+    0 at b equal times may chain; a transition time of 1 on the first edge makes it
+    arrive at 2, so it chains only with delay 0."""
+    g = G.TemporalGraph(3, np.array([0, 1], np.int32), np.array([1, 2], np.int32),
+                        np.array([1, 2], np.int32), np.array([0, 1, 2], np.int32), 3)
+    M = [0, 1, 2]
+    def exists(tr, dl):
+        return any(oracle.sieve_total(g, M, s, transit=tr, delay=dl) for s in range(8))
+    one = np.ones(3, np.int32)
+    assert exists(None, None) and exists(np.zeros(2, np.int32), one)
+    assert not exists(np.array([1, 0], np.int32), one)           # arrives at 2, leaves at 2
+    assert exists(np.array([1, 0], np.int32), np.array([1, 0, 1], np.int32))  # delay 0 at b
+    assert not exists(None, np.array([1, 2, 1], np.int32))        # must wait 2 at b
+    assert pyref.has_matching_path(g, M, np.array([1, 0], np.int32), np.array([1, 0, 1], np.int32))
+    assert not pyref.has_matching_path(g, M, None, np.array([1, 2, 1], np.int32))
+
+
 # --------------------------------------------------------------------------- one-sided error
 def test_no_false_positives():
     rng = np.random.default_rng(31)
