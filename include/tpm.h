@@ -61,14 +61,24 @@ typedef int32_t tpm_status;
 
 typedef struct tpm_graph tpm_graph;
 
-/* Work-tile shape of the in-edge index, fixed at graph creation.
- * tile_edges: most CSR positions per tile (1..4096, default 1024).  In-lists no
+/* Options of graph creation.  Zero / NULL fields take the default.
+ * tile_edges: most CSR positions per work tile (1..4096, default 1024).  In-lists no
  *             longer than a tile are packed whole; longer ones are cut into pieces
  *             that add the running value of their predecessors by look-back.
- * tile_held:  reserved, must be 0.  Zero fields take the default. */
+ * tile_held:  reserved, must be 0.
+ * transit, delay: the variant with transition and delay times (section "Path motif
+ *             problem with delays"); host arrays even with TPM_DEVICE_PTRS.
+ *             transit[e] >= 0 (m entries): edge e = (u -> v, tau) reaches v at
+ *             tau + transit[e] (< 2^31).  delay[v] >= 0 (n entries): a walk that
+ *             reached v at time a may leave it by an edge of timestamp tau only if
+ *             a <= tau - delay[v].  Defaults 0 and 1 give the plain problem (strictly
+ *             increasing timestamps).  Time outputs (time buckets, optimum time) are
+ *             then arrival times. */
 typedef struct {
     int32_t tile_edges;
     int32_t tile_held;
+    const int32_t *transit;
+    const int32_t *delay;
 } tpm_graph_options;
 
 typedef struct {

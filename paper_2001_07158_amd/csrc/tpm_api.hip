@@ -150,8 +150,9 @@ void delete_workspace_pool(WorkspacePool *p) { delete p; }
 void set_error(const std::string &msg) { t_last_error = msg; }
 void clear_error() { t_last_error.clear(); }
 
-// Verify a path using the device index (strictly increasing times, consecutive
-// endpoints, distinct vertices, colours = M).
+// Verify a path using the device index (consecutive endpoints, distinct vertices,
+// colours = M, and each edge leaving after the previous one arrived plus the
+// vertex's delay: strictly increasing times in the plain problem).
 bool verify_path(const Graph &G, const int32_t *M, int32_t k, const int32_t *verts,
                  const int64_t *edges_pos) {
     std::vector<int32_t> want(M, M + k), have;
@@ -163,17 +164,20 @@ bool verify_path(const Graph &G, const int32_t *M, int32_t k, const int32_t *ver
     std::sort(want.begin(), want.end());
     std::sort(have.begin(), have.end());
     if (want != have) return false;
-    int32_t prev_tau = 0;
+    int64_t prev_arr = 0;
     for (int i = 0; i + 1 < k; ++i) {
-        int32_t s, d, t;
+        int32_t s, d, a, t;
         int64_t p = edges_pos[i];
         if (p < 0 || p >= G.m) return false;
         TPM_HIP(hipMemcpy(&s, G.psrc + p, 4, hipMemcpyDeviceToHost));
         TPM_HIP(hipMemcpy(&d, G.pdst + p, 4, hipMemcpyDeviceToHost));
-        TPM_HIP(hipMemcpy(&t, G.ptau + p, 4, hipMemcpyDeviceToHost));
+        TPM_HIP(hipMemcpy(&a, G.ptau + p, 4, hipMemcpyDeviceToHost));
+        t = a;
+        if (G.pdep) TPM_HIP(hipMemcpy(&t, G.pdep + p, 4, hipMemcpyDeviceToHost));
         if (s != verts[i] || d != verts[i + 1]) return false;
-        if (i > 0 && !(t > prev_tau)) return false;
-        prev_tau = t;
+        const int64_t dl = G.h_delay.empty() ? 1 : G.h_delay[(size_t)s];
+        if (i > 0 && !(prev_arr <= (int64_t)t - dl)) return false;
+        prev_arr = a;
     }
     return true;
 }
@@ -221,10 +225,10 @@ tpm_status extract_path(const Graph &G, const int32_t *M, int32_t k, uint64_t se
             got = res.pick_pos >= 0;
         }
         if (!got) return TPM_NOTFOUND;
-        int32_t v, u, tau;
+        int32_t v, u, tau;  // tau: departure of the picked edge
         TPM_HIP(hipMemcpy(&v, G.psrc + res.pick_pos, 4, hipMemcpyDeviceToHost));
         TPM_HIP(hipMemcpy(&u, G.pdst + res.pick_pos, 4, hipMemcpyDeviceToHost));
-        TPM_HIP(hipMemcpy(&tau, G.ptau + res.pick_pos, 4, hipMemcpyDeviceToHost));
+        TPM_HIP(hipMemcpy(&tau, (G.pdep ? G.pdep : G.ptau) + res.pick_pos, 4, hipMemcpyDeviceToHost));
         if (end_v < 0) rverts.push_back(u);
         rpos.push_back(res.pick_pos);
         reids.push_back(res.pick_eid);
@@ -235,13 +239,17 @@ tpm_status extract_path(const Graph &G, const int32_t *M, int32_t k, uint64_t se
         auto it = std::find(cur.begin(), cur.end(), G.h_color[u]);
         if (it == cur.end()) return TPM_NOTFOUND;  // cannot happen for a certified edge
         cur.erase(it);
-        // next: v's in-edges earlier than tau
+        // next: v's in-edges that arrived by tau - delay(v) (plain problem: earlier
+        // than tau)
         lo = G.h_inptr[v];
         int64_t a = G.h_inptr[v], b = G.h_inptr[v + 1];
         if (b > a) {
             std::vector<int32_t> taus((size_t)(b - a));
             TPM_HIP(hipMemcpy(taus.data(), G.ptau + a, sizeof(int32_t) * (b - a), hipMemcpyDeviceToHost));
-            hi = a + (int64_t)(std::lower_bound(taus.begin(), taus.end(), tau) - taus.begin());
+            const int64_t th = (int64_t)tau - (G.h_delay.empty() ? 1 : G.h_delay[(size_t)v]) + 1;
+            hi = a + (int64_t)(std::lower_bound(taus.begin(), taus.end(), th,
+                                                [](int32_t x, int64_t y) { return (int64_t)x < y; }) -
+                               taus.begin());
         } else {
             hi = a;
         }

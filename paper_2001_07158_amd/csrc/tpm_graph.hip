@@ -54,9 +54,10 @@ __global__ void k_keys(int64_t m, const int32_t *dst, const int32_t *tau, int tb
     }
 }
 
+// tau: the time that orders in-lists (arrival); dep (nullable): departure times
 __global__ void k_apply(int64_t m, const int32_t *order, const int32_t *src, const int32_t *dst,
-                        const int32_t *tau, int32_t *psrc, int32_t *pdst, int32_t *ptau,
-                        int32_t *peid) {
+                        const int32_t *tau, const int32_t *dep, int32_t *psrc, int32_t *pdst,
+                        int32_t *ptau, int32_t *pdep, int32_t *peid) {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p < m) {
         int32_t e = order[p];
@@ -64,7 +65,28 @@ __global__ void k_apply(int64_t m, const int32_t *order, const int32_t *src, con
         psrc[p] = src[e];
         pdst[p] = dst[e];
         ptau[p] = tau[e];
+        if (dep) pdep[p] = dep[e];
     }
+}
+
+// arrival = departure + transition time; flag bit 4 on a negative transition time or an
+// arrival past 2^31 - 1, and the largest arrival in *amax
+__global__ void k_arrival(int64_t m, const int32_t *tau, const int32_t *transit, int32_t *arr,
+                          int32_t *bad, int32_t *amax) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int32_t local = 0;
+    for (; i < m; i += stride) {
+        const int64_t a = (int64_t)tau[i] + transit[i];
+        if (transit[i] < 0 || a > 0x7FFFFFFF) {
+            atomicOr(bad, 4);
+            arr[i] = tau[i];
+        } else {
+            arr[i] = (int32_t)a;
+            local = max(local, (int32_t)a);
+        }
+    }
+    atomicMax(amax, local);
 }
 
 // inptr[u] = first position whose dst >= u; every position writes the entries of
@@ -77,16 +99,20 @@ __global__ void k_inptr(int64_t m, int32_t n, const int32_t *pdst, int32_t *inpt
     for (int32_t u = lo; u <= hi; ++u) inptr[u] = (int32_t)p;
 }
 
-// gpos[p] = last position q of src's in-list with tau[q] < tau[p], or -1.
-__global__ void k_gpos(int64_t m, const int32_t *psrc, const int32_t *ptau, const int32_t *inptr,
-                       int32_t *gpos, int32_t *needed) {
+// gpos[p] = last position q of src's in-list that arrived by the departure of p minus
+// the delay of src (plain problem: arrival = departure = tau, delay 1, so tau[q] <
+// tau[p]), or -1.  pdep, vdelay nullable.
+__global__ void k_gpos(int64_t m, const int32_t *psrc, const int32_t *ptau, const int32_t *pdep,
+                       const int32_t *vdelay, const int32_t *inptr, int32_t *gpos,
+                       int32_t *needed) {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= m) return;
-    int32_t v = psrc[p], t = ptau[p];
+    int32_t v = psrc[p];
+    const int64_t th = (int64_t)(pdep ? pdep[p] : ptau[p]) - (vdelay ? vdelay[v] : 1) + 1;
     int32_t lo = inptr[v], hi = inptr[v + 1], base = lo;
     while (lo < hi) {
         int32_t mid = lo + ((hi - lo) >> 1);
-        if (ptau[mid] < t) lo = mid + 1; else hi = mid;
+        if ((int64_t)ptau[mid] < th) lo = mid + 1; else hi = mid;
     }
     int32_t q = (lo > base) ? lo - 1 : -1;
     gpos[p] = q;
@@ -116,6 +142,12 @@ __global__ void k_keep(int64_t m, const int32_t *psrc, const int32_t *pdst, cons
                        const uint8_t *keepc, int32_t *keep) {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p < m) keep[p] = (keepc[color[psrc[p]]] && keepc[color[pdst[p]]]) ? 1 : 0;
+}
+
+__global__ void k_compact1(int64_t m, const int32_t *keep, const int32_t *at, const int32_t *a,
+                           int32_t *b) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < m && keep[p]) b[at[p]] = a[p];
 }
 
 __global__ void k_compact(int64_t m, const int32_t *keep, const int32_t *at, const int32_t *psrc,
@@ -204,7 +236,7 @@ void build_tiles(const std::vector<int32_t> &inptr, int32_t T, std::vector<int32
 enum ArenaSlot {
     A_COLOR, A_PDST, A_PSRC, A_PTAU, A_PEID, A_GSRC, A_OROW, A_INPTR, A_SEGNEXT, A_TP0, A_TPUB,
     A_TLB, A_LDS, A_TTAB, A_KEEPC, A_KEEP, A_AT, A_SCRATCH, A_GPOS, A_NEEDED, A_ROWOF, A_TSORT,
-    A_TUNIQ, A_TCOUNT, A_CNT, A_NSLOTS
+    A_TUNIQ, A_TCOUNT, A_CNT, A_PDEP, A_VDELAY, A_NSLOTS
 };
 
 struct GraphArena {
@@ -262,7 +294,7 @@ struct Temps {
 void free_graph(Graph &G) {
     int32_t **ptrs[] = {&G.color, &G.pdst,  &G.psrc,    &G.ptau,     &G.peid,   &G.gsrc,
                         &G.orow,  &G.inptr, &G.segnext, &G.tile_p0, &G.tile_pub, &G.tile_lb,
-                        &G.ttab};
+                        &G.ttab,  &G.pdep,  &G.vdelay};
     const bool own = G.arena == nullptr;  // arena memory stays with the arena
     for (auto pp : ptrs) {
         if (*pp && own) (void)hipFree(*pp);
@@ -314,7 +346,8 @@ void finish_index(Graph &G, int64_t &acct, const int32_t *taus) {
         int32_t *needed = tmp.get<int32_t>(A_NEEDED, m);
         int32_t *rowof = tmp.get<int32_t>(A_ROWOF, m);
         TPM_HIP(hipMemsetAsync(needed, 0, sizeof(int32_t) * m, st));
-        k_gpos<<<grid_for(m), 256, 0, st>>>(m, G.psrc, G.ptau, G.inptr, gpos, needed);
+        k_gpos<<<grid_for(m), 256, 0, st>>>(m, G.psrc, G.ptau, G.pdep, G.vdelay, G.inptr, gpos,
+                                            needed);
         size_t sbytes = 0;
         TPM_HIP(rocprim::exclusive_scan(nullptr, sbytes, needed, rowof, 0, (size_t)m,
                                         rocprim::plus<int32_t>(), st));
@@ -400,18 +433,30 @@ void build_graph(Graph &G, int32_t n, int64_t m, const int32_t *src, const int32
     const bool on_dev = (flags & TPM_DEVICE_PTRS) != 0;
     TPM_REQUIRE((flags & ~TPM_DEVICE_PTRS) == 0, "unknown flag bits");
 
+    const int32_t *transit = opt ? opt->transit : nullptr;  // host, per edge
+    const int32_t *delay = opt ? opt->delay : nullptr;      // host, per vertex
+
     // ---- validation of host arrays happens before any device work
-    int32_t tmax = 0;
+    int32_t tmax = 0;  // largest arrival time
     if (!on_dev) {
         for (int64_t e = 0; e < m; ++e) {
             int32_t s = src[e], d = dst[e], t = tau[e];
             TPM_REQUIRE(s >= 0 && s < n && d >= 0 && d < n, "edge endpoint out of range");
             TPM_REQUIRE(t >= 1, "timestamps must be >= 1");
-            tmax = std::max(tmax, t);
+            int64_t a = t;
+            if (transit) {
+                TPM_REQUIRE(transit[e] >= 0, "transition times must be >= 0");
+                a += transit[e];
+                TPM_REQUIRE(a <= 0x7FFFFFFF, "timestamp + transition time must be < 2^31");
+            }
+            tmax = std::max(tmax, (int32_t)a);
         }
         for (int32_t u = 0; u < n; ++u)
             TPM_REQUIRE(color[u] >= 0 && color[u] < num_colors, "colour out of range");
     }
+    if (delay)
+        for (int32_t u = 0; u < n; ++u)
+            TPM_REQUIRE(delay[u] >= 0 && delay[u] <= (1 << 30), "delays must be in [0, 2^30]");
 
     TPM_HIP(hipGetDevice(&G.device));
     hipDeviceProp_t prop;
@@ -425,14 +470,14 @@ void build_graph(Graph &G, int32_t n, int64_t m, const int32_t *src, const int32
     int64_t acct = 0;
     hipStream_t st = nullptr;
 
-    int32_t *d_src = nullptr, *d_dst = nullptr, *d_tau = nullptr;
+    int32_t *d_src = nullptr, *d_dst = nullptr, *d_tau = nullptr, *d_arr = nullptr;
     int64_t tmp = 0;
     uint64_t *keys = nullptr, *keys2 = nullptr;
     int32_t *vals = nullptr, *vals2 = nullptr;
     void *scratch = nullptr;
     auto cleanup_tmp = [&]() {
-        for (void *p : {(void *)d_src, (void *)d_dst, (void *)d_tau, (void *)keys, (void *)keys2,
-                        (void *)vals, (void *)vals2, scratch})
+        for (void *p : {(void *)d_src, (void *)d_dst, (void *)d_tau, (void *)d_arr, (void *)keys,
+                        (void *)keys2, (void *)vals, (void *)vals2, scratch})
             if (p) (void)hipFree(p);
     };
     try {
@@ -461,6 +506,27 @@ void build_graph(Graph &G, int32_t n, int64_t m, const int32_t *src, const int32
             TPM_REQUIRE(!(h[0] & 2), "colour out of range");
             tmax = h[1];
         }
+        // ---- transition times: in-lists are ordered by arrival, departures kept apart
+        if (transit && m) {
+            d_arr = dalloc<int32_t>(m, tmp);
+            int32_t *flagbuf = dalloc<int32_t>(2, tmp);
+            TPM_HIP(hipMemset(flagbuf, 0, 2 * sizeof(int32_t)));
+            TPM_HIP(hipMemcpy(d_arr, transit, sizeof(int32_t) * m, hipMemcpyHostToDevice));
+            k_arrival<<<std::min<unsigned>(grid_for(m), 4096), 256, 0, st>>>(m, d_tau, d_arr, d_arr,
+                                                                            flagbuf, flagbuf + 1);
+            int32_t h[2];
+            TPM_HIP(hipMemcpy(h, flagbuf, sizeof(h), hipMemcpyDeviceToHost));
+            (void)hipFree(flagbuf);
+            TPM_REQUIRE(!(h[0] & 4), "transition times must be >= 0 with timestamp + transition < 2^31");
+            tmax = std::max(tmax, h[1]);
+            G.pdep = dalloc<int32_t>(m, acct);
+        }
+        if (delay) {
+            G.vdelay = dalloc<int32_t>(n, acct);
+            TPM_HIP(hipMemcpy(G.vdelay, delay, sizeof(int32_t) * n, hipMemcpyHostToDevice));
+            G.h_delay.assign(delay, delay + n);
+        }
+        const int32_t *d_order_t = d_arr ? d_arr : d_tau;  // arrival times
         G.tmax = tmax;
 
         G.pdst = dalloc<int32_t>(m, acct);
@@ -479,15 +545,16 @@ void build_graph(Graph &G, int32_t n, int64_t m, const int32_t *src, const int32
             keys2 = dalloc<uint64_t>(m, tmp);
             vals = dalloc<int32_t>(m, tmp);
             vals2 = dalloc<int32_t>(m, tmp);
-            k_keys<<<grid_for(m), 256, 0, st>>>(m, d_dst, d_tau, tbits, keys, vals);
+            k_keys<<<grid_for(m), 256, 0, st>>>(m, d_dst, d_order_t, tbits, keys, vals);
             size_t sbytes = 0;
             TPM_HIP(rocprim::radix_sort_pairs(nullptr, sbytes, keys, keys2, vals, vals2, (size_t)m,
                                               0, (unsigned)(tbits + nbits), st));
             TPM_HIP(hipMalloc(&scratch, std::max<size_t>(sbytes, 16)));
             TPM_HIP(rocprim::radix_sort_pairs(scratch, sbytes, keys, keys2, vals, vals2, (size_t)m,
                                               0, (unsigned)(tbits + nbits), st));
-            k_apply<<<grid_for(m), 256, 0, st>>>(m, vals2, d_src, d_dst, d_tau, G.psrc, G.pdst,
-                                                 G.ptau, G.peid);
+            k_apply<<<grid_for(m), 256, 0, st>>>(m, vals2, d_src, d_dst, d_order_t,
+                                                 d_arr ? d_tau : nullptr, G.psrc, G.pdst, G.ptau,
+                                                 G.pdep, G.peid);
             (void)hipFree(keys);
             keys = nullptr;
             (void)hipFree(keys2);
@@ -495,7 +562,7 @@ void build_graph(Graph &G, int32_t n, int64_t m, const int32_t *src, const int32
             (void)hipFree(scratch);
             scratch = nullptr;
         }
-        finish_index(G, acct, d_tau);
+        finish_index(G, acct, d_order_t);
         G.device_bytes = acct;
     } catch (...) {
         cleanup_tmp();
@@ -516,6 +583,7 @@ void prune_graph(const Graph &P, const uint8_t *keep_color, Graph &G, GraphArena
     G.edge_ids = P.edge_ids;
     G.arena = arena;
     G.h_color = P.h_color;
+    G.h_delay = P.h_delay;
     int64_t acct = 0;
     hipStream_t st = nullptr;
     try {
@@ -551,9 +619,18 @@ void prune_graph(const Graph &P, const uint8_t *keep_color, Graph &G, GraphArena
             G.gsrc = galloc<int32_t>(G, A_GSRC, mk, acct);
             G.orow = galloc<int32_t>(G, A_OROW, mk, acct);
             G.inptr = galloc<int32_t>(G, A_INPTR, (int64_t)G.n + 1, acct);
-            if (mk)  // kept positions stay in (dst, tau, id) order
+            if (P.pdep) G.pdep = galloc<int32_t>(G, A_PDEP, mk, acct);
+            if (P.vdelay) {
+                G.vdelay = galloc<int32_t>(G, A_VDELAY, P.n, acct);
+                TPM_HIP(hipMemcpyAsync(G.vdelay, P.vdelay, sizeof(int32_t) * (size_t)P.n,
+                                       hipMemcpyDeviceToDevice, st));
+            }
+            if (mk) {  // kept positions stay in (dst, arrival, id) order
                 k_compact<<<grid_for(P.m), 256, 0, st>>>(P.m, keep, at, P.psrc, P.pdst, P.ptau,
                                                           P.peid, G.psrc, G.pdst, G.ptau, G.peid);
+                if (P.pdep)
+                    k_compact1<<<grid_for(P.m), 256, 0, st>>>(P.m, keep, at, P.pdep, G.pdep);
+            }
             TPM_HIP(hipDeviceSynchronize());
         }
         finish_index(G, acct, G.ptau);

@@ -183,6 +183,9 @@ struct Graph {
     int32_t *tile_pub = nullptr;  // [ntiles] slot this tile publishes to, -1 if none
     int32_t *tile_lb = nullptr;   // [ntiles] slot its look-back starts at, -1 if none
     uint8_t *lds_image = nullptr; // [kLdsBytes]
+    int32_t *pdep = nullptr;      // [m] departure times when edges have transition times
+                                  //     (ptau then holds arrivals), else null
+    int32_t *vdelay = nullptr;    // [n] per-vertex delays, null = 1 everywhere
     int32_t *ttab = nullptr;      // [ntimes] distinct timestamps, ascending
     int64_t ntimes = 0;
     int64_t edge_ids = 0;         // input edge ids are < edge_ids (m, or the parent's m
@@ -196,6 +199,7 @@ struct Graph {
     std::vector<int32_t> h_color;   // [n]
     std::vector<int32_t> h_tile_p0; // [ntiles+1]
     std::vector<int32_t> h_ttab;    // [ntimes]
+    std::vector<int32_t> h_delay;   // [n] when vdelay is set
 };
 
 // Builds all of the above; throws Error.

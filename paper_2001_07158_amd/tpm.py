@@ -38,7 +38,8 @@ _u64p = ctypes.POINTER(ctypes.c_uint64)
 
 
 class tpm_graph_options(ctypes.Structure):
-    _fields_ = [("tile_edges", ctypes.c_int32), ("tile_held", ctypes.c_int32)]
+    _fields_ = [("tile_edges", ctypes.c_int32), ("tile_held", ctypes.c_int32),
+                ("transit", ctypes.POINTER(ctypes.c_int32)), ("delay", ctypes.POINTER(ctypes.c_int32))]
 
 
 class tpm_graph_stats(ctypes.Structure):
@@ -184,8 +185,10 @@ def _stream_handle(stream):
 
 
 # ------------------------------------------------------------------ C-named wrappers
-def tpm_graph_create(n, src, dst, tau, color, num_colors, flags=0, tile_edges=0, tile_held=0):
-    """Host numpy arrays, or raw device pointers (ints) with flags=TPM_DEVICE_PTRS."""
+def tpm_graph_create(n, src, dst, tau, color, num_colors, flags=0, tile_edges=0, tile_held=0,
+                     transit=None, delay=None):
+    """Host numpy arrays, or raw device pointers (ints) with flags=TPM_DEVICE_PTRS.
+    transit (per edge) and delay (per vertex) are host arrays (nullable)."""
     h = ctypes.c_void_p()
     if flags & TPM_DEVICE_PTRS:
         m = int(src[1])
@@ -196,7 +199,13 @@ def tpm_graph_create(n, src, dst, tau, color, num_colors, flags=0, tile_edges=0,
         if not (dst.shape[0] == m and tau.shape[0] == m and color.shape[0] == n):
             raise ValueError("array lengths do not match n/m")
         ptrs = [_ptr(x) for x in (src, dst, tau, color)]
-    opt = tpm_graph_options(int(tile_edges), int(tile_held))
+    tr = None if transit is None else _i32(transit)
+    dl = None if delay is None else _i32(delay)
+    if tr is not None and tr.shape[0] != m:
+        raise ValueError("transit needs one entry per edge")
+    if dl is not None and dl.shape[0] != n:
+        raise ValueError("delay needs one entry per vertex")
+    opt = tpm_graph_options(int(tile_edges), int(tile_held), _ptr(tr, _i32p), _ptr(dl, _i32p))
     _check(_lib.tpm_graph_create_ex(int(n), m, *ptrs, int(num_colors), int(flags),
                                     ctypes.byref(opt), ctypes.byref(h)))
     return h
@@ -375,10 +384,12 @@ def tpm_profile_read(max_items: int = 4096):
 
 # ------------------------------------------------------------------ owners
 class Graph:
-    def __init__(self, n, src, dst, tau, color, num_colors, tile_edges=0, tile_held=0):
+    def __init__(self, n, src, dst, tau, color, num_colors, tile_edges=0, tile_held=0,
+                 transit=None, delay=None):
         self.n = int(n)
         self.m = int(len(src))
-        self.h = tpm_graph_create(n, src, dst, tau, color, num_colors, 0, tile_edges, tile_held)
+        self.h = tpm_graph_create(n, src, dst, tau, color, num_colors, 0, tile_edges, tile_held,
+                                  transit, delay)
 
     @classmethod
     def from_temporal(cls, g, **kw):

@@ -90,3 +90,21 @@ def test_null_handles_are_errors():
         with pytest.raises(tpm.TpmError) as ei:
             call()
         assert ei.value.code == tpm.TPM_EINVAL
+
+
+@pytest.mark.parametrize("case", ["neg_transit", "overflow", "neg_delay"])
+def test_bad_delay_options_rejected_on_host(case):
+    from paper_2001_07158_amd import tpm
+    src, dst = np.array([0], np.int32), np.array([1], np.int32)
+    kw = {}
+    tau = np.array([2], np.int32)
+    if case == "neg_transit":
+        kw["transit"] = np.array([-1], np.int32)
+    elif case == "overflow":
+        tau = np.array([2**31 - 1], np.int32)
+        kw["transit"] = np.array([1], np.int32)
+    else:
+        kw["delay"] = np.array([0, -1, 0], np.int32)
+    with pytest.raises(tpm.TpmError) as ei:
+        tpm.tpm_graph_create(3, src, dst, tau, np.zeros(3, np.int32), 1, **kw)
+    assert ei.value.code == tpm.TPM_EINVAL
