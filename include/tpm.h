@@ -161,6 +161,16 @@ tpm_status tpm_autotune(tpm_graph *g, int32_t k, uint64_t seed, tpm_autotune_rep
 tpm_status tpm_graph_prune(const tpm_graph *g, const int32_t *colors, int32_t ncolors,
                            tpm_graph **out);
 
+/* As tpm_graph_prune, with an optional colour set (ncolors = 0: every colour) and an
+ * optional timestamp set times[0..ntimes) (ntimes = 0: every timestamp; edges are
+ * matched by their own timestamp, i.e. departure).  With the k - 1 timestamps
+ * j_1 < ... < j_{k-1} of an EC-PATH-MOTIF query (section "Extending the framework":
+ * edges at prescribed times, in order) the plain sieve on the result decides that
+ * query: k - 1 strictly increasing times from a set of k - 1 values are that set in
+ * order.  (With transition or delay times the kept edges follow the graph's rule.) */
+tpm_status tpm_graph_prune_ex(const tpm_graph *g, const int32_t *colors, int32_t ncolors,
+                              const int32_t *times, int32_t ntimes, tpm_graph **out);
+
 /* Free a graph and everything it owns.  NULL is accepted. */
 void tpm_graph_destroy(tpm_graph *g);
 

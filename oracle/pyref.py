@@ -243,6 +243,31 @@ def brute_optimum_time(g, M) -> int:
     return best
 
 
+def ec_per_point(g, M, seed: int, times) -> np.ndarray:
+    """EC-PATH-MOTIF (section "Extending the framework"): the generating polynomial
+    whose level l uses only edges at the prescribed time j_{l-1}, evaluated at every
+    sieve point: P_1(u) = x_u, P_l(u) = x_u * sum over edges (v -> u) at time j_{l-1}
+    of y_{e,l-1} P_{l-1}(v); the value is the sum over u of P_k(u).  times = (j_1 <
+    ... < j_{k-1})."""
+    k = len(M)
+    times = [int(t) for t in times]
+    assert len(times) == k - 1 and all(a < b for a, b in zip(times, times[1:]))
+    T = mul_table()
+    X = subset_values(zvals(g, M, seed))  # [n][2^k]
+    out = np.zeros(1 << k, dtype=np.uint8)
+    for A in range(1 << k):
+        P = X[:, A].copy()
+        for l in range(2, k + 1):
+            nxt = np.zeros(g.n, dtype=np.uint8)
+            for e in range(g.m):
+                if int(g.tau[e]) == times[l - 2]:
+                    u, v = int(g.dst[e]), int(g.src[e])
+                    nxt[u] ^= T[T[X[u, A], fp(seed, TAG_Y, l - 1, e)], P[v]]
+            P = nxt
+        out[A] = np.bitwise_xor.reduce(P) if g.n else 0
+    return out
+
+
 def literal_eq3_table(g, M, seed: int, mask=None, X=None) -> np.ndarray:
     """Eq. (3) exactly as written, over (length l, vertex u, time i), i = 0..t:
     P[1][u][i] = x_u;  P[l][u][0] = 0 for l >= 2;

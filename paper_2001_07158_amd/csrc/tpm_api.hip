@@ -339,18 +339,31 @@ void tpm_graph_destroy(tpm_graph *g) {
 tpm_status tpm_graph_prune(const tpm_graph *g, const int32_t *colors, int32_t ncolors,
                            tpm_graph **out) {
     return guarded([&]() -> tpm_status {
-        TPM_REQUIRE(g && colors && out, "NULL argument");
+        TPM_REQUIRE(colors && ncolors >= 1, "colors must be given (ncolors >= 1)");
+        return tpm_graph_prune_ex(g, colors, ncolors, nullptr, 0, out);
+    });
+}
+
+tpm_status tpm_graph_prune_ex(const tpm_graph *g, const int32_t *colors, int32_t ncolors,
+                              const int32_t *times, int32_t ntimes, tpm_graph **out) {
+    return guarded([&]() -> tpm_status {
+        TPM_REQUIRE(g && out, "NULL argument");
         *out = nullptr;
-        TPM_REQUIRE(ncolors >= 1, "ncolors must be >= 1");
-        std::vector<uint8_t> keep((size_t)g->G.q, 0);
+        TPM_REQUIRE(ncolors >= 0 && ntimes >= 0, "counts must be >= 0");
+        TPM_REQUIRE(ncolors == 0 || colors, "colors must not be NULL");
+        TPM_REQUIRE(ntimes == 0 || times, "times must not be NULL");
+        std::vector<uint8_t> keep((size_t)g->G.q, ncolors ? 0 : 1);
         for (int32_t i = 0; i < ncolors; ++i) {
             TPM_REQUIRE(colors[i] >= 0 && colors[i] < g->G.q, "colour out of range");
             keep[(size_t)colors[i]] = 1;
         }
+        std::vector<int32_t> ts(times, times + ntimes);
+        std::sort(ts.begin(), ts.end());
+        ts.erase(std::unique(ts.begin(), ts.end()), ts.end());
         DeviceScope ds(g->G.device);
         auto *h = new tpm_graph();
         try {
-            prune_graph(g->G, keep.data(), h->G);
+            prune_graph(g->G, keep.data(), ntimes ? ts.data() : nullptr, (int32_t)ts.size(), h->G);
             h->G.pool = new_workspace_pool();
         } catch (...) {
             delete h;

@@ -267,7 +267,7 @@ void serve_pruned(tpm_server *s) {
                 }
             } fr{P};
             const double t0 = now_ms();
-            prune_graph(G, keep.data(), P, s->arena);
+            prune_graph(G, keep.data(), nullptr, 0, P, s->arena);
             P.pool = s->ppool;
             const double t1 = now_ms();
             run_alone(P, rq->q, r, st);

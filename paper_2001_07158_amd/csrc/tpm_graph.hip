@@ -138,10 +138,30 @@ __global__ void k_count_nonneg(int64_t m, const int32_t *a, unsigned long long *
 }
 
 // keep[p] = 1 when both endpoints of the edge at position p have a kept colour
-__global__ void k_keep(int64_t m, const int32_t *psrc, const int32_t *pdst, const int32_t *color,
-                       const uint8_t *keepc, int32_t *keep) {
+// vkeep[u] = 1 when u's colour is kept
+__global__ void k_vkeep(int32_t n, const int32_t *color, const uint8_t *keepc, uint8_t *vkeep) {
+    int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u < n) vkeep[u] = keepc[color[u]];
+}
+
+// keep[p] = 1 when both endpoints of the edge at position p are kept and, with a
+// timestamp set ts[0..nts) (sorted), its timestamp is in the set
+__global__ void k_keep(int64_t m, const int32_t *psrc, const int32_t *pdst, const uint8_t *vkeep,
+                       const int32_t *ptime, const int32_t *ts, int32_t nts, int32_t *keep) {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p < m) keep[p] = (keepc[color[psrc[p]]] && keepc[color[pdst[p]]]) ? 1 : 0;
+    if (p >= m) return;
+    bool k = vkeep[psrc[p]] && vkeep[pdst[p]];
+    if (k && ts) {
+        const int32_t t = ptime[p];
+        int32_t a = 0, b = nts;
+        while (a < b) {
+            const int32_t mid = (a + b) >> 1;
+            if (ts[mid] < t) a = mid + 1;
+            else b = mid;
+        }
+        k = a < nts && ts[a] == t;
+    }
+    keep[p] = k ? 1 : 0;
 }
 
 __global__ void k_compact1(int64_t m, const int32_t *keep, const int32_t *at, const int32_t *a,
@@ -236,7 +256,7 @@ void build_tiles(const std::vector<int32_t> &inptr, int32_t T, std::vector<int32
 enum ArenaSlot {
     A_COLOR, A_PDST, A_PSRC, A_PTAU, A_PEID, A_GSRC, A_OROW, A_INPTR, A_SEGNEXT, A_TP0, A_TPUB,
     A_TLB, A_LDS, A_TTAB, A_KEEPC, A_KEEP, A_AT, A_SCRATCH, A_GPOS, A_NEEDED, A_ROWOF, A_TSORT,
-    A_TUNIQ, A_TCOUNT, A_CNT, A_PDEP, A_VDELAY, A_NSLOTS
+    A_TUNIQ, A_TCOUNT, A_CNT, A_PDEP, A_VDELAY, A_VKEEP, A_TSET, A_NSLOTS
 };
 
 struct GraphArena {
@@ -572,7 +592,8 @@ void build_graph(Graph &G, int32_t n, int64_t m, const int32_t *src, const int32
     cleanup_tmp();
 }
 
-void prune_graph(const Graph &P, const uint8_t *keep_color, Graph &G, GraphArena *arena) {
+void prune_graph(const Graph &P, const uint8_t *keep_color, const int32_t *times, int32_t ntimes,
+                 Graph &G, GraphArena *arena) {
     TPM_HIP(hipSetDevice(P.device));
     G.device = P.device;
     G.num_cu = P.num_cu;
@@ -596,10 +617,23 @@ void prune_graph(const Graph &P, const uint8_t *keep_color, Graph &G, GraphArena
                                    hipMemcpyDeviceToDevice, st));
             if (P.m) {
                 uint8_t *keepc = tmp.get<uint8_t>(A_KEEPC, P.q);
-                TPM_HIP(hipMemcpy(keepc, keep_color, (size_t)P.q, hipMemcpyHostToDevice));
+                if (keep_color) {
+                    TPM_HIP(hipMemcpy(keepc, keep_color, (size_t)P.q, hipMemcpyHostToDevice));
+                } else {
+                    TPM_HIP(hipMemsetAsync(keepc, 1, (size_t)P.q, st));
+                }
+                uint8_t *vkeep = tmp.get<uint8_t>(A_VKEEP, P.n);
+                k_vkeep<<<grid_for(P.n), 256, 0, st>>>(P.n, P.color, keepc, vkeep);
+                int32_t *ts = nullptr;
+                if (times) {
+                    ts = tmp.get<int32_t>(A_TSET, ntimes);
+                    TPM_HIP(hipMemcpy(ts, times, sizeof(int32_t) * (size_t)ntimes, hipMemcpyHostToDevice));
+                }
                 keep = tmp.get<int32_t>(A_KEEP, P.m);
                 at = tmp.get<int32_t>(A_AT, P.m);
-                k_keep<<<grid_for(P.m), 256, 0, st>>>(P.m, P.psrc, P.pdst, P.color, keepc, keep);
+                // timestamps of the edges as given (departures when transit times exist)
+                k_keep<<<grid_for(P.m), 256, 0, st>>>(P.m, P.psrc, P.pdst, vkeep,
+                                                       P.pdep ? P.pdep : P.ptau, ts, ntimes, keep);
                 size_t sbytes = 0;
                 TPM_HIP(rocprim::exclusive_scan(nullptr, sbytes, keep, at, 0, (size_t)P.m,
                                                 rocprim::plus<int32_t>(), st));

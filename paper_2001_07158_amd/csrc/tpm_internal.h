@@ -216,8 +216,10 @@ void retile_graph(Graph &G, int32_t T);
 // unchanged.  G must be empty; on error G is freed.
 // With an arena, G's arrays and the build's temporaries live in the arena's grow-only
 // buffers (reused by the next graph built there; G must be freed before that).
-void prune_graph(const Graph &P, const uint8_t *keep_color, Graph &G,
-                 GraphArena *arena = nullptr);
+// keep_color nullable (all colours kept); times (host, sorted, distinct, nullable):
+// keep only edges whose timestamp (departure) is one of them.
+void prune_graph(const Graph &P, const uint8_t *keep_color, const int32_t *times, int32_t ntimes,
+                 Graph &G, GraphArena *arena = nullptr);
 GraphArena *new_graph_arena();
 void delete_graph_arena(GraphArena *a);
 

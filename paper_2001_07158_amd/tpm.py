@@ -108,6 +108,8 @@ _sig("tpm_graph_destroy", None, [_vp])
 _sig("tpm_graph_stats_get", ctypes.c_int32, [_vp, ctypes.POINTER(tpm_graph_stats)])
 _sig("tpm_graph_retile", ctypes.c_int32, [_vp, ctypes.c_int32])
 _sig("tpm_graph_prune", ctypes.c_int32, [_vp, _i32p, ctypes.c_int32, ctypes.POINTER(_vp)])
+_sig("tpm_graph_prune_ex", ctypes.c_int32, [_vp, _i32p, ctypes.c_int32, _i32p, ctypes.c_int32,
+                                           ctypes.POINTER(_vp)])
 _sig("tpm_sieve_vertex", ctypes.c_int32, [_vp, _i32p, ctypes.c_int32, ctypes.c_uint64, _u8p, _u8p])
 _sig("tpm_time_buckets", ctypes.c_int32, [_vp, _i32p, ctypes.c_int32, ctypes.c_uint64, _i32p, _u8p])
 _sig("tpm_optimum_time", ctypes.c_int32, [_vp, _i32p, ctypes.c_int32, ctypes.c_uint64,
@@ -136,7 +138,7 @@ _sig("tpm_last_error", ctypes.c_char_p, [])
 _sig("tpm_version", ctypes.c_char_p, [])
 
 EXPORTED = ["tpm_graph_create", "tpm_graph_create_ex", "tpm_graph_destroy", "tpm_graph_stats_get",
-            "tpm_graph_retile", "tpm_autotune", "tpm_graph_prune", "tpm_sieve_vertex", "tpm_time_buckets",
+            "tpm_graph_retile", "tpm_autotune", "tpm_graph_prune", "tpm_graph_prune_ex", "tpm_sieve_vertex", "tpm_time_buckets",
             "tpm_optimum_time",
             "tpm_sieve", "tpm_sieve_ex", "tpm_decide", "tpm_extract", "tpm_batch_run",
             "tpm_server_create", "tpm_server_submit", "tpm_server_poll", "tpm_server_destroy",
@@ -307,10 +309,14 @@ def tpm_optimum_time(h, multiset, seed, reps=1) -> int:
     return int(t.value)
 
 
-def tpm_graph_prune(h, colors):
-    c = _i32(sorted(set(int(x) for x in colors)))
+def tpm_graph_prune(h, colors=None, times=None):
+    """Subgraph on the edges whose endpoints both have a colour in `colors` (None: all)
+    and whose timestamp is in `times` (None: all)."""
+    c = None if colors is None else _i32(sorted(set(int(x) for x in colors)))
+    t = None if times is None else _i32(sorted(set(int(x) for x in times)))
     out = ctypes.c_void_p()
-    _check(_lib.tpm_graph_prune(h, _ptr(c, _i32p), len(c), ctypes.byref(out)))
+    _check(_lib.tpm_graph_prune_ex(h, _ptr(c, _i32p), 0 if c is None else len(c),
+                                   _ptr(t, _i32p), 0 if t is None else len(t), ctypes.byref(out)))
     return out
 
 
@@ -402,11 +408,12 @@ class Graph:
         ids = self.stats()["edge_ids"] if loc else None
         return tpm_sieve(self.h, multiset, seed, mask, chunk, ids, stream)
 
-    def prune(self, colors) -> "Graph":
-        """Subgraph on the edges whose endpoints both have a colour in `colors`
-        (same vertex ids, colours and input edge ids)."""
+    def prune(self, colors=None, times=None) -> "Graph":
+        """Subgraph on the edges whose endpoints both have a colour in `colors` and
+        whose timestamp is in `times` (None: no restriction); same vertex ids,
+        colours and input edge ids."""
         g = Graph.__new__(Graph)
-        g.h = tpm_graph_prune(self.h, colors)
+        g.h = tpm_graph_prune(self.h, colors, times)
         st = tpm_graph_stats_get(g.h)
         g.n, g.m = st["n"], st["m"]
         return g

@@ -91,3 +91,30 @@ def test_prune_hub_graph_and_empty(tpm):
     with pytest.raises(tpm.TpmError):
         Gd.prune([8])  # colour out of range
     Gd.close()
+
+
+def test_ec_path_motif_by_time_pruning(tpm):
+    """EC-PATH-MOTIF: the plain sieve on the edges at the prescribed times equals the
+    paper's EC recursion evaluated by the reference, per point."""
+    rng = np.random.default_rng(93)
+    checked = 0
+    for it in range(40):
+        g = G.random_tiny_graph(rng, n_max=30, m_max=150, t_max=7, q_max=4)
+        k = int(rng.integers(2, 6))
+        if g.m == 0 or len(np.unique(g.tau)) < k - 1:
+            continue
+        M = [int(c) for c in rng.integers(0, g.num_colors, k)]
+        times = sorted(int(t) for t in rng.choice(np.unique(g.tau), k - 1, replace=False))
+        say(f"case ec{it}: k={k} times={times}")
+        Gd = tpm.Graph.from_temporal(g)
+        Gp = Gd.prune(times=times)
+        assert Gp.stats()["m"] == int(np.isin(g.tau, times).sum())
+        pp, _ = Gp.sieve(M, 60 + it)
+        assert np.array_equal(pp, pyref.ec_per_point(g, M, 60 + it, times)), it
+        Gc = Gd.prune(colors=set(M), times=times)  # both filters
+        assert np.array_equal(Gc.sieve(M, 60 + it)[0], pp)
+        Gc.close()
+        Gp.close()
+        Gd.close()
+        checked += 1
+    assert checked > 15

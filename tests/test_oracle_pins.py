@@ -304,6 +304,32 @@ def test_delays_worked_cases():
     assert not pyref.has_matching_path(g, M, None, np.array([1, 2, 1], np.int32))
 
 
+def test_ec_recursion_equals_sieve_on_time_filtered_graph():
+    """The EC-PATH-MOTIF recursion (levels at prescribed times) equals the plain sieve
+    of the graph whose edges at other times are moved onto masked vertices (same
+    ids): k - 1 strictly increasing times from a (k-1)-set are that set in order."""
+    rng = np.random.default_rng(85)
+    checked = 0
+    for it in range(60):
+        g = G.random_tiny_graph(rng, n_max=10, m_max=40, t_max=6)
+        k = int(rng.integers(2, 5))
+        if g.m == 0 or len(np.unique(g.tau)) < k - 1:
+            continue
+        M = [int(c) for c in rng.integers(0, g.num_colors, k)]
+        times = sorted(int(t) for t in rng.choice(np.unique(g.tau), k - 1, replace=False))
+        keep = np.isin(g.tau, times)
+        src = np.where(keep, g.src, g.n).astype(np.int32)
+        dst = np.where(keep, g.dst, g.n + 1).astype(np.int32)
+        col = np.concatenate([g.color, [0, 0]]).astype(np.int32)
+        mask = np.ones(g.n + 2, dtype=np.uint8)
+        mask[g.n:] = 0
+        h = G.TemporalGraph(g.n + 2, src, dst, g.tau.astype(np.int32), col, g.num_colors)
+        assert np.array_equal(pyref.ec_per_point(g, M, 40 + it, times),
+                              oracle.sieve(h, M, 40 + it, mask=mask)), it
+        checked += 1
+    assert checked > 20
+
+
 # --------------------------------------------------------------------------- one-sided error
 def test_no_false_positives():
     rng = np.random.default_rng(31)
