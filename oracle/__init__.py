@@ -64,6 +64,9 @@ def lib():
                                   _i32p, _i32p, ctypes.c_int32, _i32p, ctypes.c_int32,
                                   ctypes.c_uint64, _u8p, _u32p, ctypes.c_int64, _u8p, _u8p,
                                   ctypes.c_int]
+        L.or_sieve_vc.argtypes = [ctypes.c_int32, ctypes.c_int64, _i32p, _i32p, _i32p, _i32p,
+                                  _i32p, _i32p, ctypes.c_int32, _i32p, ctypes.c_int32,
+                                  ctypes.c_uint64, _u32p, ctypes.c_int64, _u8p, _u8p, ctypes.c_int]
         L.or_colorful_exists.argtypes = [ctypes.c_int32, ctypes.c_int64, _i32p, _i32p, _i32p,
                                          _i32p, ctypes.c_int32, _i32p, ctypes.c_int32]
         L.or_init()
@@ -144,6 +147,31 @@ def sieve(g, M, seed: int, points=None, mask=None, loc: bool = False, nthreads: 
                            _p(M, _i32p), k, seed & 0xFFFFFFFFFFFFFFFF, _p(mk, _u8p),
                            _p(points, _u32p), points.shape[0], _p(out, _u8p), _p(lc, _u8p),
                            nthreads)
+    if rc:
+        raise RuntimeError(f"oracle failed ({rc})")
+    return (out, lc) if loc else out
+
+
+def vc_sieve(g, C, seed: int, points=None, loc: bool = False, nthreads: int = 0, transit=None,
+             delay=None):
+    """VC-PATH-MOTIF (section "Extending the framework"): C is the ordered tuple of k
+    colours; the polynomial keeps x_u at level 1 only for c(u) = C[0] and level l only
+    edges (v -> u) with c(v) = C[l-2], c(u) = C[l-1]; the substitution is that of the
+    multiset of C.  Returns per-point values (and per-edge localisation)."""
+    C = _c32(C)
+    k = len(C)
+    if points is None:
+        points = np.arange(1 << k, dtype=np.uint32)
+    points = np.ascontiguousarray(points, dtype=np.uint32)
+    out = np.empty(points.shape[0], dtype=np.uint8)
+    lc = np.empty(g.m, dtype=np.uint8) if loc else None
+    src, dst, tau, color = _c32(g.src), _c32(g.dst), _c32(g.tau), _c32(g.color)
+    tr = None if transit is None else _c32(transit)
+    dl = None if delay is None else _c32(delay)
+    rc = lib().or_sieve_vc(g.n, g.m, _p(src, _i32p), _p(dst, _i32p), _p(tau, _i32p),
+                           _p(tr, _i32p), _p(dl, _i32p), _p(color, _i32p), g.num_colors,
+                           _p(C, _i32p), k, seed & 0xFFFFFFFFFFFFFFFF, _p(points, _u32p),
+                           points.shape[0], _p(out, _u8p), _p(lc, _u8p), nthreads)
     if rc:
         raise RuntimeError(f"oracle failed ({rc})")
     return (out, lc) if loc else out

@@ -177,6 +177,32 @@ def temporal_walks(g, k: int, transit=None, delay=None):
     return res
 
 
+def brute_vc_per_point(g, C, seed: int) -> np.ndarray:
+    """VC-PATH-MOTIF by its definition: the sum over temporal walks whose l-th vertex
+    has colour C[l-1] of their monomials, at every sieve point (substitution of the
+    multiset of C)."""
+    k = len(C)
+    T = mul_table()
+    X = subset_values(zvals(g, C, seed))
+    acc = np.zeros(1 << k, dtype=np.uint8)
+    for verts, edges in temporal_walks(g, k):
+        if any(int(g.color[w]) != int(C[l]) for l, w in enumerate(verts)):
+            continue
+        v = X[verts[0]].copy()
+        for l, e in enumerate(edges, start=1):
+            v = T[v, fp(seed, TAG_Y, l, e)]
+            v = T[v, X[verts[l]]]
+        acc ^= v
+    return acc
+
+
+def has_vc_path(g, C) -> bool:
+    for verts, _ in temporal_walks(g, len(C)):
+        if len(set(verts)) == len(verts) and all(int(g.color[w]) == int(C[l]) for l, w in enumerate(verts)):
+            return True
+    return False
+
+
 def brute_per_point(g, M, seed: int, mask=None, transit=None, delay=None) -> np.ndarray:
     """P(A) for every A as the sum over temporal walks of their monomials,
     x_{w_1} y_{e_1,1} x_{w_2} ... y_{e_{k-1},k-1} x_{w_k}, evaluated at z^A."""

@@ -272,8 +272,22 @@ or_index *or_index_build(int32_t n, int64_t m, const int32_t *src, const int32_t
  * out[i] = P(points[i]).  loc (nullable, [m]) receives, XOR-ed over the given
  * points, the contribution c_k[e] of walks whose last edge is e (the per-edge
  * form of vertex-localisation).  nthreads <= 0: OpenMP default. */
+/* vc (nullable, k colours) with color: the VC-PATH-MOTIF polynomial (section "Extending
+ * the framework"): P_{u,1} = x_u only if c(u) = vc[0], and level l takes only edges
+ * (v -> u) with c(v) = vc[l-2], c(u) = vc[l-1]. */
+static int or_eval_impl(const or_index *ix, const uint8_t *z, int32_t k, uint64_t seed,
+                        const uint32_t *points, int64_t npoints, uint8_t *out, uint8_t *loc,
+                        int nthreads, const int32_t *vc, const int32_t *color);
+
 int or_eval(const or_index *ix, const uint8_t *z, int32_t k, uint64_t seed,
             const uint32_t *points, int64_t npoints, uint8_t *out, uint8_t *loc, int nthreads)
+{
+    return or_eval_impl(ix, z, k, seed, points, npoints, out, loc, nthreads, NULL, NULL);
+}
+
+static int or_eval_impl(const or_index *ix, const uint8_t *z, int32_t k, uint64_t seed,
+                        const uint32_t *points, int64_t npoints, uint8_t *out, uint8_t *loc,
+                        int nthreads, const int32_t *vc, const int32_t *color)
 {
     or_init();
     if (k < 1 || k > 16)
@@ -325,13 +339,17 @@ int or_eval(const or_index *ix, const uint8_t *z, int32_t k, uint64_t seed,
                 uint8_t r = 0;
                 if (k == 1) {
                     for (int32_t u = 0; u < n; u++)
-                        r ^= x[u];
+                        if (!vc || color[u] == vc[0])
+                            r ^= x[u];
                     out[i] = r;
                     continue;
                 }
                 /* level 2: P_{src,1,tau-1} = x_src */
-                for (int64_t e = 0; e < m; e++)
+                for (int64_t e = 0; e < m; e++) {
                     prev[e] = OR_MUL[OR_MUL[x[dst[e]]][Y[e]]][x[src[e]]];
+                    if (vc && (color[src[e]] != vc[0] || color[dst[e]] != vc[1]))
+                        prev[e] = 0;
+                }
                 for (int l = 3; l <= k; l++) {
                     /* running sums along each in-list: P_{v,l-1,tau} */
                     for (int32_t v = 0; v < n; v++) {
@@ -345,6 +363,8 @@ int or_eval(const or_index *ix, const uint8_t *z, int32_t k, uint64_t seed,
                     for (int64_t e = 0; e < m; e++) {
                         uint8_t h = ix->gpos[e] >= 0 ? pre[ix->gpos[e]] : 0;
                         cur[e] = OR_MUL[OR_MUL[x[dst[e]]][Yl[e]]][h];
+                        if (vc && (color[src[e]] != vc[l - 2] || color[dst[e]] != vc[l - 1]))
+                            cur[e] = 0;
                     }
                     uint8_t *t = prev;
                     prev = cur;
@@ -505,4 +525,33 @@ int or_colorful_exists(int32_t n, int64_t m, const int32_t *src, const int32_t *
     free(best);
     free(bit);
     return found;
+}
+
+/* VC-PATH-MOTIF: the sieve of the ordered-colour polynomial (see or_eval_impl); the
+ * substitution is that of the multiset of the k colours of vc. */
+int or_sieve_vc(int32_t n, int64_t m, const int32_t *src, const int32_t *dst, const int32_t *tau,
+                const int32_t *transit, const int32_t *delay, const int32_t *color, int32_t q,
+                const int32_t *vc, int32_t k, uint64_t seed, const uint32_t *points,
+                int64_t npoints, uint8_t *out, uint8_t *loc, int nthreads)
+{
+    or_init();
+    if (n < 1 || m < 0 || k < 1 || k > 16)
+        return -1;
+    uint8_t *z = malloc((size_t)n * (size_t)k);
+    if (!z)
+        return -2;
+    int rc = or_z(n, color, q, vc, k, seed, NULL, z);
+    if (rc) {
+        free(z);
+        return rc;
+    }
+    or_index *ix = or_index_build_ex(n, m, src, dst, tau, transit, delay);
+    if (!ix) {
+        free(z);
+        return -2;
+    }
+    rc = or_eval_impl(ix, z, k, seed, points, npoints, out, loc, nthreads, vc, color);
+    or_index_free(ix);
+    free(z);
+    return rc;
 }

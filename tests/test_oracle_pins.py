@@ -330,6 +330,26 @@ def test_ec_recursion_equals_sieve_on_time_filtered_graph():
     assert checked > 20
 
 
+def test_vc_path_motif_matches_walk_enumeration():
+    """VC-PATH-MOTIF: the oracle's ordered-colour recursion equals the brute-force sum
+    over walks whose colours follow the tuple; it is zero whenever no such path
+    exists, and its total detects the ordered paths."""
+    rng = np.random.default_rng(86)
+    found = 0
+    for it in range(80):
+        g = G.random_tiny_graph(rng, n_max=10, m_max=35, t_max=6, q_max=3)
+        k = int(rng.integers(1, 5))
+        C = [int(c) for c in rng.integers(0, g.num_colors, k)]
+        seed = 300 + it
+        pp = oracle.vc_sieve(g, C, seed)
+        assert np.array_equal(pp, pyref.brute_vc_per_point(g, C, seed)), it
+        tot = int(np.bitwise_xor.reduce(pp))
+        if not pyref.has_vc_path(g, C):
+            assert tot == 0
+        found += tot != 0
+    assert found > 10
+
+
 # --------------------------------------------------------------------------- one-sided error
 def test_no_false_positives():
     rng = np.random.default_rng(31)
