@@ -171,6 +171,24 @@ tpm_status tpm_graph_prune(const tpm_graph *g, const int32_t *colors, int32_t nc
 tpm_status tpm_graph_prune_ex(const tpm_graph *g, const int32_t *colors, int32_t ncolors,
                               const int32_t *times, int32_t ntimes, tpm_graph **out);
 
+/* VC-PATH-MOTIF (section "Extending the framework": the path's vertex colours must be
+ * tuple[0], ..., tuple[k-1] in this order).  Builds a layered graph: one vertex per
+ * (layer l, vertex u with colour tuple[l-1]) and the edges (v, l-1) -> (u, l) of g's
+ * edges v -> u with colours (tuple[l-2], tuple[l-1]), with their timestamps,
+ * transition / delay times and input edge ids.  Every copy of u keeps u's
+ * fingerprints, so sieving the result with the tuple as multiset evaluates the paper's
+ * VC polynomial (level-l vertices and edges restricted by colour): a nonzero total
+ * certifies a temporal path whose l-th vertex has colour tuple[l-1].  Its vertex ids
+ * are layer copies (map them with tpm_graph_vertex_ids); tpm_extract on it deletes
+ * every copy of a picked vertex and returns original vertex ids.  Only the edges
+ * between consecutive layers are kept, so it is about (k-1)/q^2 of g for q colours.
+ * Errors: TPM_EINVAL (k outside 1..16, colour out of range), TPM_ENOMEM, TPM_EDEVICE. */
+tpm_status tpm_graph_layer(const tpm_graph *g, const int32_t *tuple, int32_t k, tpm_graph **out);
+
+/* ids[i] = the vertex of the original graph that vertex i stands for (n entries:
+ * identity, except for graphs made by tpm_graph_layer). */
+tpm_status tpm_graph_vertex_ids(const tpm_graph *g, int32_t *ids);
+
 /* Free a graph and everything it owns.  NULL is accepted. */
 void tpm_graph_destroy(tpm_graph *g);
 

@@ -156,9 +156,11 @@ void clear_error() { t_last_error.clear(); }
 bool verify_path(const Graph &G, const int32_t *M, int32_t k, const int32_t *verts,
                  const int64_t *edges_pos) {
     std::vector<int32_t> want(M, M + k), have;
-    std::set<int32_t> seen;
+    std::set<int32_t> seen;  // original vertices (layer copies of one vertex are one)
     for (int i = 0; i < k; ++i) {
-        if (verts[i] < 0 || verts[i] >= G.n || !seen.insert(verts[i]).second) return false;
+        if (verts[i] < 0 || verts[i] >= G.n) return false;
+        const int32_t orig = G.h_fid.empty() ? verts[i] : G.h_fid[(size_t)verts[i]];
+        if (!seen.insert(orig).second) return false;
         have.push_back(G.h_color[verts[i]]);
     }
     std::sort(want.begin(), want.end());
@@ -194,10 +196,11 @@ tpm_status extract_path(const Graph &G, const int32_t *M, int32_t k, uint64_t se
     TPM_REQUIRE(k >= 1 && k <= 16, "k must be in [1, 16]");
     TPM_REQUIRE(max_reps >= 1, "max_reps must be >= 1");
     for (int i = 0; i < k; ++i) TPM_REQUIRE(M[i] >= 0 && M[i] < G.q, "multiset colour out of range");
+    auto orig = [&](int32_t u) { return G.h_fid.empty() ? u : G.h_fid[(size_t)u]; };
     if (k == 1) {
         for (int32_t u = 0; u < G.n; ++u)
             if (G.h_color[u] == M[0]) {
-                path_vertices[0] = u;
+                path_vertices[0] = orig(u);
                 return TPM_OK;
             }
         return TPM_NOTFOUND;
@@ -234,8 +237,11 @@ tpm_status extract_path(const Graph &G, const int32_t *M, int32_t k, uint64_t se
         reids.push_back(res.pick_eid);
         rverts.push_back(v);
         end_v = v;
-        // delete u, drop its colour
+        // delete u (every layer copy of it), drop its colour
         mask[(size_t)u] = 0;
+        if (!G.h_fid.empty())
+            for (int32_t i = 0; i < G.n; ++i)
+                if (G.h_fid[(size_t)i] == G.h_fid[(size_t)u]) mask[(size_t)i] = 0;
         auto it = std::find(cur.begin(), cur.end(), G.h_color[u]);
         if (it == cur.end()) return TPM_NOTFOUND;  // cannot happen for a certified edge
         cur.erase(it);
@@ -262,7 +268,7 @@ tpm_status extract_path(const Graph &G, const int32_t *M, int32_t k, uint64_t se
     std::reverse(reids.begin(), reids.end());
     if (!verify_path(G, M, k, rverts.data(), rpos.data()))
         throw Error{TPM_EDEVICE, "extracted path failed verification"};
-    for (int i = 0; i < k; ++i) path_vertices[i] = rverts[i];
+    for (int i = 0; i < k; ++i) path_vertices[i] = orig(rverts[i]);
     for (int i = 0; i + 1 < k; ++i) path_edges[i] = reids[i];
     return TPM_OK;
 }
@@ -370,6 +376,33 @@ tpm_status tpm_graph_prune_ex(const tpm_graph *g, const int32_t *colors, int32_t
             throw;
         }
         *out = h;
+        return TPM_OK;
+    });
+}
+
+tpm_status tpm_graph_layer(const tpm_graph *g, const int32_t *tuple, int32_t k, tpm_graph **out) {
+    return guarded([&]() -> tpm_status {
+        TPM_REQUIRE(g && tuple && out, "NULL argument");
+        *out = nullptr;
+        DeviceScope ds(g->G.device);
+        auto *h = new tpm_graph();
+        try {
+            layer_graph(g->G, tuple, k, h->G);
+            h->G.pool = new_workspace_pool();
+        } catch (...) {
+            delete h;
+            throw;
+        }
+        *out = h;
+        return TPM_OK;
+    });
+}
+
+tpm_status tpm_graph_vertex_ids(const tpm_graph *g, int32_t *ids) {
+    return guarded([&]() -> tpm_status {
+        TPM_REQUIRE(g && ids, "NULL argument");
+        const Graph &G = g->G;
+        for (int32_t i = 0; i < G.n; ++i) ids[i] = G.h_fid.empty() ? i : G.h_fid[(size_t)i];
         return TPM_OK;
     });
 }

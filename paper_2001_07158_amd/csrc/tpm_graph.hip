@@ -164,6 +164,31 @@ __global__ void k_keep(int64_t m, const int32_t *psrc, const int32_t *pdst, cons
     keep[p] = k ? 1 : 0;
 }
 
+// layer keep: edge at p goes from colour cs to colour cd
+__global__ void k_layer_keep(int64_t m, const int32_t *psrc, const int32_t *pdst,
+                             const int32_t *color, int32_t cs, int32_t cd, int32_t *keep) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < m) keep[p] = (color[psrc[p]] == cs && color[pdst[p]] == cd) ? 1 : 0;
+}
+
+// kept edges of one layer, renumbered: source in layer l-1 (base bs), head in layer l
+// (base bd), placed from position off on
+__global__ void k_layer_compact(int64_t m, const int32_t *keep, const int32_t *at, int32_t off,
+                                const int32_t *psrc, const int32_t *pdst, const int32_t *ptau,
+                                const int32_t *peid, const int32_t *pdep, const int32_t *rank,
+                                int32_t bs, int32_t bd, int32_t *qsrc, int32_t *qdst,
+                                int32_t *qtau, int32_t *qeid, int32_t *qdep) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < m && keep[p]) {
+        const int64_t q = (int64_t)off + at[p];
+        qsrc[q] = bs + rank[psrc[p]];
+        qdst[q] = bd + rank[pdst[p]];
+        qtau[q] = ptau[p];
+        qeid[q] = peid[p];
+        if (pdep) qdep[q] = pdep[p];
+    }
+}
+
 __global__ void k_compact1(int64_t m, const int32_t *keep, const int32_t *at, const int32_t *a,
                            int32_t *b) {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -256,7 +281,7 @@ void build_tiles(const std::vector<int32_t> &inptr, int32_t T, std::vector<int32
 enum ArenaSlot {
     A_COLOR, A_PDST, A_PSRC, A_PTAU, A_PEID, A_GSRC, A_OROW, A_INPTR, A_SEGNEXT, A_TP0, A_TPUB,
     A_TLB, A_LDS, A_TTAB, A_KEEPC, A_KEEP, A_AT, A_SCRATCH, A_GPOS, A_NEEDED, A_ROWOF, A_TSORT,
-    A_TUNIQ, A_TCOUNT, A_CNT, A_PDEP, A_VDELAY, A_VKEEP, A_TSET, A_NSLOTS
+    A_TUNIQ, A_TCOUNT, A_CNT, A_PDEP, A_VDELAY, A_VKEEP, A_TSET, A_FID, A_NSLOTS
 };
 
 struct GraphArena {
@@ -314,7 +339,7 @@ struct Temps {
 void free_graph(Graph &G) {
     int32_t **ptrs[] = {&G.color, &G.pdst,  &G.psrc,    &G.ptau,     &G.peid,   &G.gsrc,
                         &G.orow,  &G.inptr, &G.segnext, &G.tile_p0, &G.tile_pub, &G.tile_lb,
-                        &G.ttab,  &G.pdep,  &G.vdelay};
+                        &G.ttab,  &G.pdep,  &G.vdelay, &G.fid};
     const bool own = G.arena == nullptr;  // arena memory stays with the arena
     for (auto pp : ptrs) {
         if (*pp && own) (void)hipFree(*pp);
@@ -605,6 +630,7 @@ void prune_graph(const Graph &P, const uint8_t *keep_color, const int32_t *times
     G.arena = arena;
     G.h_color = P.h_color;
     G.h_delay = P.h_delay;
+    G.h_fid = P.h_fid;
     int64_t acct = 0;
     hipStream_t st = nullptr;
     try {
@@ -654,6 +680,11 @@ void prune_graph(const Graph &P, const uint8_t *keep_color, const int32_t *times
             G.orow = galloc<int32_t>(G, A_OROW, mk, acct);
             G.inptr = galloc<int32_t>(G, A_INPTR, (int64_t)G.n + 1, acct);
             if (P.pdep) G.pdep = galloc<int32_t>(G, A_PDEP, mk, acct);
+            if (P.fid) {
+                G.fid = galloc<int32_t>(G, A_FID, P.n, acct);
+                TPM_HIP(hipMemcpyAsync(G.fid, P.fid, sizeof(int32_t) * (size_t)P.n,
+                                       hipMemcpyDeviceToDevice, st));
+            }
             if (P.vdelay) {
                 G.vdelay = galloc<int32_t>(G, A_VDELAY, P.n, acct);
                 TPM_HIP(hipMemcpyAsync(G.vdelay, P.vdelay, sizeof(int32_t) * (size_t)P.n,
@@ -670,6 +701,130 @@ void prune_graph(const Graph &P, const uint8_t *keep_color, const int32_t *times
         finish_index(G, acct, G.ptau);
         G.device_bytes = acct;
     } catch (...) {
+        free_graph(G);
+        throw;
+    }
+}
+
+void layer_graph(const Graph &P, const int32_t *tuple, int32_t k, Graph &G) {
+    TPM_REQUIRE(k >= 1 && k <= 16, "k must be in [1, 16]");
+    for (int i = 0; i < k; ++i) TPM_REQUIRE(tuple[i] >= 0 && tuple[i] < P.q, "colour out of range");
+    TPM_HIP(hipSetDevice(P.device));
+    // ---- vertices: layer l holds the vertices of colour tuple[l-1], in id order
+    std::vector<int64_t> cnt((size_t)P.q, 0);
+    std::vector<int32_t> rank((size_t)P.n);
+    for (int32_t u = 0; u < P.n; ++u) rank[(size_t)u] = (int32_t)cnt[(size_t)P.h_color[(size_t)u]]++;
+    std::vector<int64_t> base((size_t)k + 1, 0);
+    for (int l = 0; l < k; ++l) base[(size_t)l + 1] = base[(size_t)l] + cnt[(size_t)tuple[l]];
+    int64_t nn = base[(size_t)k];
+    TPM_REQUIRE(nn < (int64_t(1) << 31), "layered graph too large");
+    G.device = P.device;
+    G.num_cu = P.num_cu;
+    G.q = P.q;
+    G.tmax = P.tmax;
+    G.tile_edges = P.tile_edges;
+    G.edge_ids = P.edge_ids;
+    std::vector<uint8_t> in_tuple((size_t)P.q, 0);
+    for (int l = 0; l < k; ++l) in_tuple[(size_t)tuple[l]] = 1;
+    if (nn == 0) {
+        // no vertex has a colour of the tuple: one vertex of another colour, no edges
+        int32_t other = 0;
+        while (in_tuple[(size_t)other]) ++other;
+        G.h_color.assign(1, other);
+        G.h_fid.assign(1, 0);
+        if (!P.h_delay.empty()) G.h_delay.assign(1, 1);
+        nn = 1;
+    } else {
+        G.h_color.resize((size_t)nn);
+        G.h_fid.resize((size_t)nn);
+        if (!P.h_delay.empty()) G.h_delay.resize((size_t)nn);
+        for (int l = 0; l < k; ++l)
+            for (int32_t u = 0; u < P.n; ++u)
+                if (P.h_color[(size_t)u] == tuple[l]) {
+                    const size_t i = (size_t)(base[(size_t)l] + rank[(size_t)u]);
+                    G.h_color[i] = tuple[l];
+                    G.h_fid[i] = P.h_fid.empty() ? u : P.h_fid[(size_t)u];
+                    if (!P.h_delay.empty()) G.h_delay[i] = P.h_delay[(size_t)u];
+                }
+    }
+    G.n = (int32_t)nn;
+    int64_t acct = 0, tmp = 0;
+    hipStream_t st = nullptr;
+    int32_t *d_rank = nullptr, *keep = nullptr, *at = nullptr;
+    void *scratch = nullptr;
+    auto cleanup = [&]() {
+        for (void *p : {(void *)d_rank, (void *)keep, (void *)at, scratch})
+            if (p) (void)hipFree(p);
+    };
+    try {
+        G.color = dalloc<int32_t>(G.n, acct);
+        G.fid = dalloc<int32_t>(G.n, acct);
+        TPM_HIP(hipMemcpy(G.color, G.h_color.data(), sizeof(int32_t) * (size_t)G.n, hipMemcpyHostToDevice));
+        TPM_HIP(hipMemcpy(G.fid, G.h_fid.data(), sizeof(int32_t) * (size_t)G.n, hipMemcpyHostToDevice));
+        if (!G.h_delay.empty()) {
+            G.vdelay = dalloc<int32_t>(G.n, acct);
+            TPM_HIP(hipMemcpy(G.vdelay, G.h_delay.data(), sizeof(int32_t) * (size_t)G.n,
+                              hipMemcpyHostToDevice));
+        }
+        // ---- edges: layer l (2..k) takes P's edges v -> u with colours (tuple[l-2], tuple[l-1]),
+        // in P's order (sorted by destination, then time), renumbered into the layers
+        std::vector<int64_t> ml((size_t)k + 1, 0), off((size_t)k + 2, 0);
+        if (P.m && nn > 1) {
+            d_rank = dalloc<int32_t>(P.n, tmp);
+            TPM_HIP(hipMemcpy(d_rank, rank.data(), sizeof(int32_t) * (size_t)P.n, hipMemcpyHostToDevice));
+            keep = dalloc<int32_t>(P.m, tmp);
+            at = dalloc<int32_t>(P.m, tmp);
+            size_t sbytes = 0;
+            TPM_HIP(rocprim::exclusive_scan(nullptr, sbytes, keep, at, 0, (size_t)P.m,
+                                            rocprim::plus<int32_t>(), st));
+            TPM_HIP(hipMalloc(&scratch, std::max<size_t>(sbytes, 16)));
+            for (int l = 2; l <= k; ++l) {
+                k_layer_keep<<<grid_for(P.m), 256, 0, st>>>(P.m, P.psrc, P.pdst, P.color,
+                                                             tuple[l - 2], tuple[l - 1], keep);
+                TPM_HIP(rocprim::exclusive_scan(scratch, sbytes, keep, at, 0, (size_t)P.m,
+                                                rocprim::plus<int32_t>(), st));
+                int32_t a = 0, b = 0;
+                TPM_HIP(hipMemcpy(&a, at + (P.m - 1), sizeof(int32_t), hipMemcpyDeviceToHost));
+                TPM_HIP(hipMemcpy(&b, keep + (P.m - 1), sizeof(int32_t), hipMemcpyDeviceToHost));
+                ml[(size_t)l] = (int64_t)a + b;
+            }
+        }
+        for (int l = 2; l <= k; ++l) off[(size_t)l + 1] = off[(size_t)l] + ml[(size_t)l];
+        const int64_t mk = off[(size_t)k + 1];
+        TPM_REQUIRE(mk < (int64_t(1) << 31) - 1, "layered graph has too many edges");
+        G.m = mk;
+        G.pdst = dalloc<int32_t>(mk, acct);
+        G.psrc = dalloc<int32_t>(mk, acct);
+        G.ptau = dalloc<int32_t>(mk, acct);
+        G.peid = dalloc<int32_t>(mk, acct);
+        G.gsrc = dalloc<int32_t>(mk, acct);
+        G.orow = dalloc<int32_t>(mk, acct);
+        G.inptr = dalloc<int32_t>((int64_t)G.n + 1, acct);
+        if (P.pdep) G.pdep = dalloc<int32_t>(mk, acct);
+        if (mk) {
+            size_t sbytes = 0;
+            TPM_HIP(rocprim::exclusive_scan(nullptr, sbytes, keep, at, 0, (size_t)P.m,
+                                            rocprim::plus<int32_t>(), st));
+            for (int l = 2; l <= k; ++l) {
+                if (!ml[(size_t)l]) continue;
+                k_layer_keep<<<grid_for(P.m), 256, 0, st>>>(P.m, P.psrc, P.pdst, P.color,
+                                                             tuple[l - 2], tuple[l - 1], keep);
+                TPM_HIP(rocprim::exclusive_scan(scratch, sbytes, keep, at, 0, (size_t)P.m,
+                                                rocprim::plus<int32_t>(), st));
+                k_layer_compact<<<grid_for(P.m), 256, 0, st>>>(
+                    P.m, keep, at, (int32_t)off[(size_t)l], P.psrc, P.pdst, P.ptau, P.peid, P.pdep,
+                    d_rank, (int32_t)base[(size_t)l - 2], (int32_t)base[(size_t)l - 1], G.psrc,
+                    G.pdst, G.ptau, G.peid, G.pdep);
+            }
+        }
+        TPM_HIP(hipDeviceSynchronize());
+        cleanup();
+        d_rank = keep = at = nullptr;
+        scratch = nullptr;
+        finish_index(G, acct, G.ptau);
+        G.device_bytes = acct;
+    } catch (...) {
+        cleanup();
         free_graph(G);
         throw;
     }

@@ -186,6 +186,8 @@ struct Graph {
     int32_t *pdep = nullptr;      // [m] departure times when edges have transition times
                                   //     (ptau then holds arrivals), else null
     int32_t *vdelay = nullptr;    // [n] per-vertex delays, null = 1 everywhere
+    int32_t *fid = nullptr;       // [n] original vertex of each vertex of a layered graph
+                                  //     (keys its fingerprints), null = identity
     int32_t *ttab = nullptr;      // [ntimes] distinct timestamps, ascending
     int64_t ntimes = 0;
     int64_t edge_ids = 0;         // input edge ids are < edge_ids (m, or the parent's m
@@ -200,6 +202,7 @@ struct Graph {
     std::vector<int32_t> h_tile_p0; // [ntiles+1]
     std::vector<int32_t> h_ttab;    // [ntimes]
     std::vector<int32_t> h_delay;   // [n] when vdelay is set
+    std::vector<int32_t> h_fid;     // [n] when fid is set
 };
 
 // Builds all of the above; throws Error.
@@ -220,6 +223,10 @@ void retile_graph(Graph &G, int32_t T);
 // keep only edges whose timestamp (departure) is one of them.
 void prune_graph(const Graph &P, const uint8_t *keep_color, const int32_t *times, int32_t ntimes,
                  Graph &G, GraphArena *arena = nullptr);
+// VC-PATH-MOTIF: G = the layered graph of P for the colour tuple[0..k): vertex (u, l)
+// for each layer l with c(u) = tuple[l-1] (fingerprints keyed by u), edges
+// (v, l-1) -> (u, l) for P's edges v -> u with matching colours.
+void layer_graph(const Graph &P, const int32_t *tuple, int32_t k, Graph &G);
 GraphArena *new_graph_arena();
 void delete_graph_arena(GraphArena *a);
 

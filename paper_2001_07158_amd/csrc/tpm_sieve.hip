@@ -724,8 +724,10 @@ __global__ void k_prep(Ctl *ctl, int bump_epoch) {
 
 // z[u][j] = sum over slots d of colour c(u) of v_{u,d} * w_{d,j} (Eq. (motif)), rows
 // padded to 16 bytes; zero for a deleted vertex or a colour outside the multiset.
-__global__ void k_z(int32_t n, int32_t k, const int32_t *color, QuerySlots qs, const uint8_t *mask,
-                    uint64_t seed, uint8_t *z) {
+// fid (nullable): the vertex id that keys a vertex's fingerprints (layer copies of a
+// vertex share the original's)
+__global__ void k_z(int32_t n, int32_t k, const int32_t *color, const int32_t *fid, QuerySlots qs,
+                    const uint8_t *mask, uint64_t seed, uint8_t *z) {
     int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (u >= n) return;
     int32_t c = color[u];
@@ -741,7 +743,8 @@ __global__ void k_z(int32_t n, int32_t k, const int32_t *color, QuerySlots qs, c
         uint32_t acc = 0;
         if (live)
             for (int d = off; d < off + mu; ++d)
-                acc ^= gmul(fp8(seed, 2u, (uint32_t)d, (uint32_t)u), fp8(seed, 3u, (uint32_t)d, (uint32_t)j));
+                acc ^= gmul(fp8(seed, 2u, (uint32_t)d, fid ? (uint32_t)fid[u] : (uint32_t)u),
+                            fp8(seed, 3u, (uint32_t)d, (uint32_t)j));
         out[j >> 2] |= acc << (8 * (j & 3));
     }
     ((uint4 *)z)[u] = make_uint4(out[0], out[1], out[2], out[3]);
@@ -1210,7 +1213,7 @@ void run_sieve_impl(const Graph &G, const SieveRequest &req, SieveResult &res, b
         TPM_HIP(hipMemcpyAsync(mask.p, req.vertex_mask, (size_t)G.n, hipMemcpyHostToDevice, st));
         dmask = mask.as<uint8_t>();
     }
-    k_z<<<grid_for(G.n), 256, 0, st>>>(G.n, k, G.color, qs, dmask, req.seed, z.as<uint8_t>());
+    k_z<<<grid_for(G.n), 256, 0, st>>>(G.n, k, G.color, G.fid, qs, dmask, req.seed, z.as<uint8_t>());
 
     int64_t lo = 0, hi = G.m;
     if (req.fin_lo < req.fin_hi) {
@@ -1371,7 +1374,7 @@ void multi_prepare(const Graph &G, MultiRow &row, int lane0, int npts, const int
     QuerySlots qs = make_slots(G, M, k);
     const int rowb = row.rowb();
     const int col = lane0 * 4 * row.W;
-    k_z<<<grid_for(G.n), 256, 0, st>>>(G.n, k, G.color, qs, nullptr, seed, ws.z.as<uint8_t>());
+    k_z<<<grid_for(G.n), 256, 0, st>>>(G.n, k, G.color, G.fid, qs, nullptr, seed, ws.z.as<uint8_t>());
     k_xt<<<grid_for((int64_t)G.n * ((npts + 15) / 16)), 256, 0, st>>>(
         G.n, k, npts, rowb, col, base, ws.z.as<uint8_t>(), ws.xt.as<uint8_t>());
     TPM_HIP(hipMemsetAsync(ws.pp.as<uint8_t>() + col, 0, (size_t)npts, st));

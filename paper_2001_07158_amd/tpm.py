@@ -107,6 +107,8 @@ _sig("tpm_graph_create_ex", ctypes.c_int32,
 _sig("tpm_graph_destroy", None, [_vp])
 _sig("tpm_graph_stats_get", ctypes.c_int32, [_vp, ctypes.POINTER(tpm_graph_stats)])
 _sig("tpm_graph_retile", ctypes.c_int32, [_vp, ctypes.c_int32])
+_sig("tpm_graph_layer", ctypes.c_int32, [_vp, _i32p, ctypes.c_int32, ctypes.POINTER(_vp)])
+_sig("tpm_graph_vertex_ids", ctypes.c_int32, [_vp, _i32p])
 _sig("tpm_graph_prune", ctypes.c_int32, [_vp, _i32p, ctypes.c_int32, ctypes.POINTER(_vp)])
 _sig("tpm_graph_prune_ex", ctypes.c_int32, [_vp, _i32p, ctypes.c_int32, _i32p, ctypes.c_int32,
                                            ctypes.POINTER(_vp)])
@@ -138,7 +140,8 @@ _sig("tpm_last_error", ctypes.c_char_p, [])
 _sig("tpm_version", ctypes.c_char_p, [])
 
 EXPORTED = ["tpm_graph_create", "tpm_graph_create_ex", "tpm_graph_destroy", "tpm_graph_stats_get",
-            "tpm_graph_retile", "tpm_autotune", "tpm_graph_prune", "tpm_graph_prune_ex", "tpm_sieve_vertex", "tpm_time_buckets",
+            "tpm_graph_retile", "tpm_autotune", "tpm_graph_prune", "tpm_graph_prune_ex",
+            "tpm_graph_layer", "tpm_graph_vertex_ids", "tpm_sieve_vertex", "tpm_time_buckets",
             "tpm_optimum_time",
             "tpm_sieve", "tpm_sieve_ex", "tpm_decide", "tpm_extract", "tpm_batch_run",
             "tpm_server_create", "tpm_server_submit", "tpm_server_poll", "tpm_server_destroy",
@@ -320,6 +323,20 @@ def tpm_graph_prune(h, colors=None, times=None):
     return out
 
 
+def tpm_graph_layer(h, tup):
+    t = _i32(list(tup))
+    out = ctypes.c_void_p()
+    _check(_lib.tpm_graph_layer(h, _ptr(t, _i32p), len(t), ctypes.byref(out)))
+    return out
+
+
+def tpm_graph_vertex_ids(h):
+    n = tpm_graph_stats_get(h)["n"]
+    ids = np.empty(n, dtype=np.int32)
+    _check(_lib.tpm_graph_vertex_ids(h, _ptr(ids, _i32p)))
+    return ids
+
+
 def tpm_graph_retile(h, tile_edges) -> None:
     _check(_lib.tpm_graph_retile(h, int(tile_edges)))
 
@@ -407,6 +424,17 @@ class Graph:
     def sieve(self, multiset, seed, mask=None, chunk=0, loc=False, stream=None):
         ids = self.stats()["edge_ids"] if loc else None
         return tpm_sieve(self.h, multiset, seed, mask, chunk, ids, stream)
+
+    def layer(self, tup) -> "Graph":
+        """Layered graph of the ordered colour tuple (VC-PATH-MOTIF)."""
+        g = Graph.__new__(Graph)
+        g.h = tpm_graph_layer(self.h, tup)
+        st = tpm_graph_stats_get(g.h)
+        g.n, g.m = st["n"], st["m"]
+        return g
+
+    def vertex_ids(self):
+        return tpm_graph_vertex_ids(self.h)
 
     def prune(self, colors=None, times=None) -> "Graph":
         """Subgraph on the edges whose endpoints both have a colour in `colors` and
