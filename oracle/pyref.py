@@ -105,12 +105,14 @@ TAG_Y, TAG_V, TAG_W = 1, 2, 3
 
 
 def slots(M, q: int):
-    """Distinct colours of M ascending; colour s owns mu(s) consecutive slots."""
+    """Distinct colours of M ascending; colour s owns mu(s) consecutive slots.  Entries
+    -1 are wildcards: they sort first and own slots 0 .. wc - 1."""
     mu = [0] * q
     for c in M:
-        mu[int(c)] += 1
+        if int(c) >= 0:
+            mu[int(c)] += 1
     off = [-1] * q
-    nxt = 0
+    nxt = sum(1 for c in M if int(c) == -1)
     for s in range(q):
         if mu[s]:
             off[s] = nxt
@@ -123,16 +125,33 @@ def zvals(g, M, seed: int, mask=None) -> np.ndarray:
     off, mu = slots(M, g.num_colors)
     w = [[fp(seed, TAG_W, d, j) for j in range(k)] for d in range(k)]
     z = np.zeros((g.n, k), dtype=np.uint8)
+    wild = list(range(sum(1 for c in M if int(c) == -1)))  # every vertex owns these too
     for u in range(g.n):
         c = int(g.color[u])
-        if (mask is not None and not mask[u]) or mu[c] == 0:
+        if mask is not None and not mask[u]:
             continue
+        mine = wild + list(range(off[c], off[c] + mu[c]))
         for j in range(k):
             acc = 0
-            for d in range(off[c], off[c] + mu[c]):
+            for d in mine:
                 acc ^= gmul(fp(seed, TAG_V, d, u), w[d][j])
             z[u, j] = acc
     return z
+
+
+def colours_match(colours, M) -> bool:
+    """A vertex-colour list matches M when each vertex can take its own colour or a
+    wildcard (-1) so that the multiset is M."""
+    if len(colours) != len(M):
+        return False
+    need = {}
+    for c in M:
+        if int(c) >= 0:
+            need[int(c)] = need.get(int(c), 0) + 1
+    have = {}
+    for c in colours:
+        have[int(c)] = have.get(int(c), 0) + 1
+    return all(have.get(c, 0) >= n for c, n in need.items())
 
 
 def subset_values(z: np.ndarray) -> np.ndarray:
@@ -335,9 +354,8 @@ def literal_eq3_per_point(g, M, seed: int, mask=None) -> np.ndarray:
 
 
 def has_matching_path(g, M, transit=None, delay=None) -> bool:
-    want = sorted(int(c) for c in M)
     for verts, _ in temporal_walks(g, len(M), transit, delay):
-        if len(set(verts)) == len(verts) and sorted(int(g.color[u]) for u in verts) == want:
+        if len(set(verts)) == len(verts) and colours_match([g.color[u] for u in verts], M):
             return True
     return False
 
@@ -366,7 +384,7 @@ def check_path(g, M, verts, edges, transit=None, delay=None) -> bool:
             dl = int(delay[verts[l]]) if delay is not None else 1
             if not arr <= int(g.tau[e]) - dl:
                 return False
-    return sorted(int(g.color[v]) for v in verts) == sorted(int(c) for c in M)
+    return colours_match([g.color[v] for v in verts], M)
 
 
 def unique_witness_detect_prob(M) -> float:

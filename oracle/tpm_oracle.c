@@ -100,7 +100,18 @@ uint8_t or_fp(uint64_t seed, uint32_t tag, uint32_t a, uint32_t b)
 /* Slots S_s and the substitution z (Eq. (motif)).                             */
 /* ------------------------------------------------------------------------- */
 /* Colour s (0 <= s < q) gets mu[s] slots starting at off[s]; colours not in M
- * get mu = 0.  Returns -1 if M names a colour outside [0, q). */
+ * get mu = 0.  Entries -1 of M are wildcards (section "Including wildcard entries":
+ * every vertex also has an extra colour); they take the first slots, 0 .. wc - 1,
+ * since the slots follow the colours of M in ascending order.  Returns -1 if M names
+ * a colour outside [-1, q). */
+int or_wildcards(const int32_t *M, int32_t k)
+{
+    int wc = 0;
+    for (int i = 0; i < k; i++)
+        wc += M[i] == -1;
+    return wc;
+}
+
 int or_slots(const int32_t *M, int32_t k, int32_t q, int32_t *off, int32_t *mu)
 {
     for (int s = 0; s < q; s++) {
@@ -108,11 +119,12 @@ int or_slots(const int32_t *M, int32_t k, int32_t q, int32_t *off, int32_t *mu)
         off[s] = -1;
     }
     for (int i = 0; i < k; i++) {
-        if (M[i] < 0 || M[i] >= q)
+        if (M[i] < -1 || M[i] >= q)
             return -1;
-        mu[M[i]]++;
+        if (M[i] >= 0)
+            mu[M[i]]++;
     }
-    int next = 0;
+    int next = or_wildcards(M, k);
     for (int s = 0; s < q; s++) {
         if (mu[s]) {
             off[s] = next;
@@ -122,8 +134,8 @@ int or_slots(const int32_t *M, int32_t k, int32_t q, int32_t *off, int32_t *mu)
     return 0;
 }
 
-/* z[u*k + j] = sum_{d in S_c(u)} v_{u,d} * w_{d,j}; zero when c(u) is not in M or
- * when the vertex is deleted (mask[u] == 0). */
+/* z[u*k + j] = sum over d in S_c(u), and over the wildcard slots, of v_{u,d} w_{d,j};
+ * zero when the vertex is deleted (mask[u] == 0) or has no slot. */
 int or_z(int32_t n, const int32_t *color, int32_t q, const int32_t *M, int32_t k,
          uint64_t seed, const uint8_t *mask, uint8_t *z)
 {
@@ -139,17 +151,21 @@ int or_z(int32_t n, const int32_t *color, int32_t q, const int32_t *M, int32_t k
     for (int d = 0; d < k; d++)
         for (int j = 0; j < k; j++)
             w[d][j] = or_fp(seed, 3, (uint32_t)d, (uint32_t)j);
+    const int wc = or_wildcards(M, k);
     for (int32_t u = 0; u < n; u++) {
         int32_t c = color[u];
         for (int j = 0; j < k; j++)
             z[(size_t)u * k + j] = 0;
         if (mask && !mask[u])
             continue;
-        if (c < 0 || c >= q || mu[c] == 0)
+        const int own = (c >= 0 && c < q) ? mu[c] : 0;
+        if (own == 0 && wc == 0)
             continue;
         for (int j = 0; j < k; j++) {
             uint8_t acc = 0;
-            for (int d = off[c]; d < off[c] + mu[c]; d++)
+            for (int d = 0; d < wc; d++)
+                acc ^= OR_MUL[or_fp(seed, 2, (uint32_t)d, (uint32_t)u)][w[d][j]];
+            for (int d = own ? off[c] : 0; d < (own ? off[c] + own : 0); d++)
                 acc ^= OR_MUL[or_fp(seed, 2, (uint32_t)d, (uint32_t)u)][w[d][j]];
             z[(size_t)u * k + j] = acc;
         }

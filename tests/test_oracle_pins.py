@@ -350,6 +350,31 @@ def test_vc_path_motif_matches_walk_enumeration():
     assert found > 10
 
 
+def test_wildcards():
+    """Wildcard entries (-1): the substitution equals the independent Python one; the
+    total equals the brute-force path sum of y(P) det(Z_P); an all-wildcard query is
+    the single-colour query on the recoloured graph bit for bit; no path (with
+    wildcard matching) means a zero total."""
+    rng = np.random.default_rng(87)
+    found = 0
+    for it in range(80):
+        g = G.random_tiny_graph(rng, n_max=10, m_max=35, t_max=6, q_max=4)
+        k = int(rng.integers(1, 5))
+        M = [int(c) for c in rng.integers(-1, g.num_colors, k)]
+        seed = 500 + it
+        assert np.array_equal(oracle.zvals(g, M, seed).reshape(g.n, k), pyref.zvals(g, M, seed))
+        tot = oracle.sieve_total(g, M, seed)
+        if k >= 2:
+            assert tot == pyref.brute_paths_total(g, M, seed), it
+        if not pyref.has_matching_path(g, M):
+            assert tot == 0
+        found += tot != 0
+        allw = [-1] * k
+        h = G.TemporalGraph(g.n, g.src, g.dst, g.tau, np.zeros(g.n, np.int32), 1)
+        assert np.array_equal(oracle.sieve(g, allw, seed), oracle.sieve(h, [0] * k, seed))
+    assert found > 10
+
+
 # --------------------------------------------------------------------------- one-sided error
 def test_no_false_positives():
     rng = np.random.default_rng(31)
