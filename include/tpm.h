@@ -59,6 +59,12 @@ typedef int32_t tpm_status;
 /* graph creation flags */
 #define TPM_DEVICE_PTRS 0x1u /* src/dst/tau/color are device pointers */
 
+/* A multiset entry that any vertex may take (section "Including wildcard entries":
+ * every vertex also carries one extra colour).  Multisets hold colours in
+ * [0, num_colors) and TPM_WILDCARD; the path's vertex colours must equal the multiset
+ * after some of them are replaced by wildcards.  Not accepted by tpm_graph_layer. */
+#define TPM_WILDCARD (-1)
+
 typedef struct tpm_graph tpm_graph;
 
 /* Options of graph creation.  Zero / NULL fields take the default.

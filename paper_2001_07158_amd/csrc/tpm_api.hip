@@ -7,6 +7,7 @@
 #include <atomic>
 #include <chrono>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <set>
 #include <string>
@@ -155,17 +156,17 @@ void clear_error() { t_last_error.clear(); }
 // vertex's delay: strictly increasing times in the plain problem).
 bool verify_path(const Graph &G, const int32_t *M, int32_t k, const int32_t *verts,
                  const int64_t *edges_pos) {
-    std::vector<int32_t> want(M, M + k), have;
     std::set<int32_t> seen;  // original vertices (layer copies of one vertex are one)
+    std::map<int32_t, int32_t> have;
     for (int i = 0; i < k; ++i) {
         if (verts[i] < 0 || verts[i] >= G.n) return false;
         const int32_t orig = G.h_fid.empty() ? verts[i] : G.h_fid[(size_t)verts[i]];
         if (!seen.insert(orig).second) return false;
-        have.push_back(G.h_color[verts[i]]);
+        have[G.h_color[verts[i]]]++;
     }
-    std::sort(want.begin(), want.end());
-    std::sort(have.begin(), have.end());
-    if (want != have) return false;
+    // colours = M, where a wildcard entry (-1) may be taken by any vertex
+    for (int i = 0; i < k; ++i)
+        if (M[i] >= 0 && --have[M[i]] < 0) return false;
     int64_t prev_arr = 0;
     for (int i = 0; i + 1 < k; ++i) {
         int32_t s, d, a, t;
@@ -195,11 +196,11 @@ tpm_status extract_path(const Graph &G, const int32_t *M, int32_t k, uint64_t se
                         hipStream_t st) {
     TPM_REQUIRE(k >= 1 && k <= 16, "k must be in [1, 16]");
     TPM_REQUIRE(max_reps >= 1, "max_reps must be >= 1");
-    for (int i = 0; i < k; ++i) TPM_REQUIRE(M[i] >= 0 && M[i] < G.q, "multiset colour out of range");
+    for (int i = 0; i < k; ++i) TPM_REQUIRE(M[i] >= -1 && M[i] < G.q, "multiset colour out of range");
     auto orig = [&](int32_t u) { return G.h_fid.empty() ? u : G.h_fid[(size_t)u]; };
     if (k == 1) {
         for (int32_t u = 0; u < G.n; ++u)
-            if (G.h_color[u] == M[0]) {
+            if (G.h_color[u] == M[0] || M[0] == -1) {
                 path_vertices[0] = orig(u);
                 return TPM_OK;
             }
@@ -243,6 +244,7 @@ tpm_status extract_path(const Graph &G, const int32_t *M, int32_t k, uint64_t se
             for (int32_t i = 0; i < G.n; ++i)
                 if (G.h_fid[(size_t)i] == G.h_fid[(size_t)u]) mask[(size_t)i] = 0;
         auto it = std::find(cur.begin(), cur.end(), G.h_color[u]);
+        if (it == cur.end()) it = std::find(cur.begin(), cur.end(), -1);  // u took a wildcard
         if (it == cur.end()) return TPM_NOTFOUND;  // cannot happen for a certified edge
         cur.erase(it);
         // next: v's in-edges that arrived by tau - delay(v) (plain problem: earlier
@@ -262,7 +264,7 @@ tpm_status extract_path(const Graph &G, const int32_t *M, int32_t k, uint64_t se
         if ((int)cur.size() >= 2 && hi <= lo) return TPM_NOTFOUND;
     }
     // cur has one colour left: it must be v's colour
-    if (cur.size() != 1 || G.h_color[end_v] != cur[0]) return TPM_NOTFOUND;
+    if (cur.size() != 1 || (G.h_color[end_v] != cur[0] && cur[0] != -1)) return TPM_NOTFOUND;
     std::reverse(rverts.begin(), rverts.end());
     std::reverse(rpos.begin(), rpos.end());
     std::reverse(reids.begin(), reids.end());

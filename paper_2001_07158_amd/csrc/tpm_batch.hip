@@ -78,7 +78,7 @@ void check_query(const Graph &G, const tpm_query &q) {
     TPM_REQUIRE(q.multiset != nullptr, "query multiset must not be NULL");
     TPM_REQUIRE(q.k >= 1 && q.k <= 16, "k must be in [1, 16]");
     for (int i = 0; i < q.k; ++i)
-        TPM_REQUIRE(q.multiset[i] >= 0 && q.multiset[i] < G.q, "multiset colour out of range");
+        TPM_REQUIRE(q.multiset[i] >= -1 && q.multiset[i] < G.q, "multiset colour out of range");
 }
 
 void extract_into(const Graph &G, const tpm_query &q, tpm_result &r, hipStream_t st) {
@@ -257,7 +257,12 @@ void serve_pruned(tpm_server *s) {
             tpm_result r;
             std::memset(&r, 0, sizeof(r));
             std::vector<uint8_t> keep((size_t)G.q, 0);
-            for (int32_t c : rq->ms) keep[(size_t)c] = 1;
+            bool wild = false;
+            for (int32_t c : rq->ms) {
+                if (c < 0) wild = true;
+                else keep[(size_t)c] = 1;
+            }
+            if (wild) std::fill(keep.begin(), keep.end(), (uint8_t)1);  // any vertex may match
             Graph P;
             struct Free {
                 Graph &g;

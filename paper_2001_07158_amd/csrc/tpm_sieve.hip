@@ -731,20 +731,25 @@ __global__ void k_z(int32_t n, int32_t k, const int32_t *color, const int32_t *f
     int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (u >= n) return;
     int32_t c = color[u];
-    int32_t off = -1, mu = 0;
+    int32_t off = 0, mu = 0;
     for (int i = 0; i < qs.ncol; ++i)
         if (qs.col[i] == c) {
             off = qs.off[i];
             mu = qs.mu[i];
         }
-    const bool live = (mask == nullptr || mask[u] != 0) && mu > 0;
+    // wildcard entries (colour -1, first slots) belong to every vertex
+    const int32_t wmu = (qs.ncol > 0 && qs.col[0] == -1) ? qs.mu[0] : 0;
+    const bool live = (mask == nullptr || mask[u] != 0) && (mu > 0 || wmu > 0);
+    const uint32_t uid = fid ? (uint32_t)fid[u] : (uint32_t)u;
     uint32_t out[4] = {0, 0, 0, 0};
     for (int j = 0; j < k; ++j) {
         uint32_t acc = 0;
-        if (live)
+        if (live) {
+            for (int d = 0; d < wmu; ++d)
+                acc ^= gmul(fp8(seed, 2u, (uint32_t)d, uid), fp8(seed, 3u, (uint32_t)d, (uint32_t)j));
             for (int d = off; d < off + mu; ++d)
-                acc ^= gmul(fp8(seed, 2u, (uint32_t)d, fid ? (uint32_t)fid[u] : (uint32_t)u),
-                            fp8(seed, 3u, (uint32_t)d, (uint32_t)j));
+                acc ^= gmul(fp8(seed, 2u, (uint32_t)d, uid), fp8(seed, 3u, (uint32_t)d, (uint32_t)j));
+        }
         out[j >> 2] |= acc << (8 * (j & 3));
     }
     ((uint4 *)z)[u] = make_uint4(out[0], out[1], out[2], out[3]);
@@ -1111,8 +1116,8 @@ QuerySlots make_slots(const Graph &G, const int32_t *M, int32_t k) {
     TPM_REQUIRE(k >= 1 && k <= 16, "k must be in [1, 16]");
     int32_t cols[16];
     for (int i = 0; i < k; ++i) {
-        TPM_REQUIRE(M[i] >= 0 && M[i] < G.q, "multiset colour out of range");
-        cols[i] = M[i];
+        TPM_REQUIRE(M[i] >= -1 && M[i] < G.q, "multiset colour out of range");
+        cols[i] = M[i];  // -1: wildcard (sorts first, so it owns the first slots)
     }
     std::sort(cols, cols + k);
     QuerySlots qs{};

@@ -24,6 +24,7 @@ TPM_EDEVICE = -3
 TPM_ECANCELLED = -4
 TPM_ECLOSED = -5
 TPM_DEVICE_PTRS = 0x1
+TPM_WILDCARD = -1
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "

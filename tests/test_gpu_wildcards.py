@@ -1,0 +1,86 @@
+"""GPU: wildcard entries (-1) in the multiset, against the oracle and exhaustive
+search, alone, batched and served."""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import pyref
+from synth import graphs as G
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def tpm():
+    import torch
+    assert torch.cuda.is_available()
+    torch.cuda.set_device(0)
+    from paper_2001_07158_amd import tpm as _tpm
+    return _tpm
+
+
+def test_wildcards_random_small(tpm):
+    rng = np.random.default_rng(141)
+    for it in range(60):
+        g = G.random_tiny_graph(rng, n_max=40, m_max=200, t_max=8, q_max=4)
+        k = int(rng.integers(1, 7))
+        M = [int(c) for c in rng.integers(-1, g.num_colors, k)]
+        seed = int(rng.integers(0, 2**63))
+        say(f"case wild rand{it}: M={M}")
+        Gd = tpm.Graph.from_temporal(g, tile_edges=int(rng.integers(1, 64)))
+        pp, tot = Gd.sieve(M, seed)
+        assert np.array_equal(pp, oracle.sieve(g, M, seed)), it
+        Gd.close()
+
+
+def test_wildcards_extraction(tpm):
+    rng = np.random.default_rng(142)
+    yes = no = 0
+    for it in range(50):
+        g = G.random_tiny_graph(rng, n_max=12, m_max=40, t_max=6, q_max=4)
+        k = int(rng.integers(2, 5))
+        M = [int(c) for c in rng.integers(-1, g.num_colors, k)]
+        exists = pyref.has_matching_path(g, M)
+        Gd = tpm.Graph.from_temporal(g)
+        rc, verts, edges = Gd.extract(M, 31 + it, max_reps=12)
+        if exists:
+            yes += 1
+            assert rc == tpm.TPM_OK, it
+            assert pyref.check_path(g, M, verts, edges)
+        else:
+            no += 1
+            assert rc == tpm.TPM_NOTFOUND
+        Gd.close()
+    assert yes > 5 and no > 3
+
+
+def test_wildcards_batch_and_server(tpm):
+    g = G.chung_lu_graph(3000, 40000, 2.5, 60, 5, 143)
+    rng = np.random.default_rng(144)
+    qs = [{"multiset": [int(c) for c in rng.integers(-1, 5, int(rng.integers(2, 9)))],
+           "seed": int(rng.integers(0, 2**62))} for _ in range(30)]
+    Gd = tpm.Graph.from_temporal(g)
+    res = Gd.batch(qs)
+    for q, r in zip(qs, res):
+        assert r["total"] == oracle.sieve_total(g, q["multiset"], q["seed"]), q
+    for prune in (0, 1):
+        srv = tpm.Server(Gd, prune_queries=prune)
+        tickets = [srv.submit(q["multiset"], q["seed"]) for q in qs[:12]]
+        got = {r["ticket"]: r for r in srv.drain(12, timeout_s=300)}
+        srv.close()
+        for t, q, r0 in zip(tickets, qs, res):
+            assert got[t]["total"] == r0["total"]
+    # all wildcards = one colour for every vertex
+    h = G.TemporalGraph(g.n, g.src, g.dst, g.tau, np.zeros(g.n, np.int32), 1)
+    Gh = tpm.Graph.from_temporal(h)
+    assert np.array_equal(Gd.sieve([-1] * 6, 7)[0], Gh.sieve([0] * 6, 7)[0])
+    Gh.close()
+    Gd.close()
