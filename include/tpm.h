@@ -287,6 +287,16 @@ typedef struct {
 tpm_status tpm_batch_run(const tpm_graph *g, int32_t nq, const tpm_query *q, tpm_result *out,
                          const tpm_tuning *tune);
 
+/* RAINBOW-PATH (section "Extending the framework"): is there a temporal path with k
+ * vertices of k different colours?  Decided, as in the paper, by the PATH-MOTIF
+ * oracle over the C(num_colors, k) colour sets, here run as packed batches of up to
+ * 256 queries with reps seeds each (seed_r as tpm_decide), stopping at the first hit.
+ * On *found = 1, colors[0..k) holds a colour set with a path (certain); *found = 0:
+ * no set was detected.  C(num_colors, k) must not exceed 2^20.
+ * Errors: TPM_EINVAL (k outside 1..16 or > num_colors, too many sets). */
+tpm_status tpm_rainbow_decide(const tpm_graph *g, int32_t k, uint64_t seed, int32_t reps,
+                              int32_t *found, int32_t *colors);
+
 /* ---------------------------------------------------------------- serve --- */
 typedef struct tpm_server tpm_server;
 

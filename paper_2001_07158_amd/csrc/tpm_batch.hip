@@ -195,6 +195,59 @@ tpm_status tpm_batch_run(const tpm_graph *g, int32_t nq, const tpm_query *q, tpm
     });
 }
 
+tpm_status tpm_rainbow_decide(const tpm_graph *g, int32_t k, uint64_t seed, int32_t reps,
+                              int32_t *found, int32_t *colors) {
+    return guarded2([&]() -> tpm_status {
+        TPM_REQUIRE(g && found && colors, "NULL argument");
+        const int32_t q = g->G.q;
+        TPM_REQUIRE(k >= 1 && k <= 16 && k <= q, "k must be in [1, min(16, num_colors)]");
+        TPM_REQUIRE(reps >= 1, "reps must be >= 1");
+        double sets = 1;
+        for (int i = 0; i < k; ++i) sets = sets * (q - i) / (i + 1);
+        TPM_REQUIRE(sets <= (double)(1 << 20), "too many colour sets");
+        *found = 0;
+        std::vector<int32_t> comb((size_t)k);
+        for (int i = 0; i < k; ++i) comb[(size_t)i] = i;
+        bool more = true;
+        auto next_comb = [&]() {  // lexicographic successor of comb, false at the end
+            int i = k - 1;
+            while (i >= 0 && comb[(size_t)i] == q - k + i) --i;
+            if (i < 0) return false;
+            ++comb[(size_t)i];
+            for (int j = i + 1; j < k; ++j) comb[(size_t)j] = comb[(size_t)j - 1] + 1;
+            return true;
+        };
+        while (more) {
+            // one batch: up to 256 (set, repetition) queries
+            std::vector<std::vector<int32_t>> sets_b;
+            while (more && (int)sets_b.size() * reps < 256) {
+                sets_b.push_back(comb);
+                more = next_comb();
+            }
+            std::vector<tpm_query> qs;
+            for (size_t i = 0; i < sets_b.size(); ++i)
+                for (int32_t r = 0; r < reps; ++r) {
+                    tpm_query q1{};
+                    q1.multiset = sets_b[i].data();
+                    q1.k = k;
+                    q1.seed = seed + (uint64_t)r * 0x9E3779B97F4A7C15ull;
+                    qs.push_back(q1);
+                }
+            std::vector<tpm_result> out(qs.size());
+            const tpm_status rc = tpm_batch_run(g, (int32_t)qs.size(), qs.data(), out.data(), nullptr);
+            if (rc != TPM_OK) return rc;
+            for (size_t i = 0; i < qs.size(); ++i)
+                if (out[i].found) {
+                    *found = 1;
+                    const auto &set = sets_b[i / (size_t)reps];
+                    for (int j = 0; j < k; ++j) colors[j] = set[(size_t)j];
+                    return TPM_OK;
+                }
+        }
+        return TPM_OK;
+    });
+}
+
 }  // extern "C"
 
 // ------------------------------------------------------------------ serving loop

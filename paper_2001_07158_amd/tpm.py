@@ -129,6 +129,8 @@ _sig("tpm_extract", ctypes.c_int32, [_vp, _i32p, ctypes.c_int32, ctypes.c_uint64
                                     _i32p, _i64p])
 _sig("tpm_batch_run", ctypes.c_int32, [_vp, ctypes.c_int32, ctypes.POINTER(tpm_query),
                                       ctypes.POINTER(tpm_result), ctypes.POINTER(tpm_tuning)])
+_sig("tpm_rainbow_decide", ctypes.c_int32, [_vp, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int32,
+                                           _i32p, _i32p])
 _sig("tpm_server_create", ctypes.c_int32, [_vp, ctypes.POINTER(tpm_server_config),
                                           ctypes.POINTER(_vp)])
 _sig("tpm_server_submit", ctypes.c_int32, [_vp, ctypes.POINTER(tpm_query), _u64p])
@@ -146,7 +148,7 @@ EXPORTED = ["tpm_graph_create", "tpm_graph_create_ex", "tpm_graph_destroy", "tpm
             "tpm_optimum_time",
             "tpm_sieve", "tpm_sieve_ex", "tpm_decide", "tpm_extract", "tpm_batch_run",
             "tpm_server_create", "tpm_server_submit", "tpm_server_poll", "tpm_server_destroy",
-            "tpm_server_stats_get",
+            "tpm_server_stats_get", "tpm_rainbow_decide",
             "tpm_profile_enable", "tpm_profile_read", "tpm_last_error", "tpm_version"]
 
 
@@ -358,6 +360,15 @@ def tpm_batch_run(h, queries, chunk=0, use_graph=False):
     return [_result_dict(out[i]) for i in range(len(queries))]
 
 
+def tpm_rainbow_decide(h, k, seed=1, reps=1):
+    """(found, colours) for a temporal path with k distinct colours."""
+    found = ctypes.c_int32(0)
+    cols = np.zeros(max(1, int(k)), dtype=np.int32)
+    _check(_lib.tpm_rainbow_decide(h, int(k), int(seed) & (2**64 - 1), int(reps),
+                                   ctypes.byref(found), _ptr(cols, _i32p)))
+    return bool(found.value), [int(c) for c in cols[: int(k)]] if found.value else None
+
+
 def tpm_server_create(h, state_bytes=0, max_lanes=0, extract_paths=0, prune_queries=0):
     cfg = tpm_server_config(int(state_bytes), int(max_lanes), int(extract_paths),
                             int(prune_queries))
@@ -425,6 +436,9 @@ class Graph:
     def sieve(self, multiset, seed, mask=None, chunk=0, loc=False, stream=None):
         ids = self.stats()["edge_ids"] if loc else None
         return tpm_sieve(self.h, multiset, seed, mask, chunk, ids, stream)
+
+    def rainbow(self, k, seed=1, reps=1):
+        return tpm_rainbow_decide(self.h, k, seed, reps)
 
     def layer(self, tup) -> "Graph":
         """Layered graph of the ordered colour tuple (VC-PATH-MOTIF)."""

@@ -84,3 +84,22 @@ def test_wildcards_batch_and_server(tpm):
     assert np.array_equal(Gd.sieve([-1] * 6, 7)[0], Gh.sieve([0] * 6, 7)[0])
     Gh.close()
     Gd.close()
+
+
+def test_rainbow_against_exhaustive_search(tpm):
+    rng = np.random.default_rng(145)
+    yes = no = 0
+    for it in range(30):
+        g = G.random_tiny_graph(rng, n_max=12, m_max=40, t_max=6, q_max=5)
+        k = int(rng.integers(2, min(4, g.num_colors) + 1)) if g.num_colors >= 2 else 1
+        exists = any(len(set(v)) == k and len({int(g.color[u]) for u in v}) == k
+                     for v, _ in pyref.temporal_walks(g, k))
+        Gd = tpm.Graph.from_temporal(g)
+        found, cols = Gd.rainbow(k, seed=3 + it, reps=4)
+        if found:
+            assert pyref.has_matching_path(g, cols) and len(set(cols)) == k
+        assert found == exists, it  # 4 seeds per colour set: a miss is ~1e-5
+        yes += exists
+        no += not exists
+        Gd.close()
+    assert yes > 3 and no > 3
