@@ -334,6 +334,7 @@ def bench_batched(args) -> int:
         G.sieve(q["multiset"], q["seed"])
     G.batch(warm)
     G.batch(warm, use_graph=True)
+    G.batch(warm, prune=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     alone = [G.sieve(q["multiset"], q["seed"])[1] for q in qs]
@@ -350,8 +351,14 @@ def bench_batched(args) -> int:
     torch.cuda.synchronize()
     t_graph = time.perf_counter() - t0
     _log(f"# batched, graph replay: {t_graph:.2f}s")
+    t0 = time.perf_counter()
+    res_p = G.batch(qs, prune=True)
+    torch.cuda.synchronize()
+    t_pruned = time.perf_counter() - t0
+    _log(f"# each query on its colour subgraph: {t_pruned:.2f}s")
     same = all(r["total"] == a for r, a in zip(res, alone))
     same_g = all(r["total"] == a for r, a in zip(res_g, alone))
+    same_p = all(r["total"] == a for r, a in zip(res_p, alone))
     units = float(sum(g.m * k * (1 << k) for k in ks))
     line = {
         "metric": "batched queries/s (256 queries, k ~ U{3..10}), GF(2^8) sieve",
@@ -360,6 +367,7 @@ def bench_batched(args) -> int:
         "edge_updates_per_s_batched": units / t_batch,
         "edge_updates_per_s_one_at_a_time": units / t_alone,
         "graph_replay_qps": nq / t_graph, "graph_replay_totals_equal_alone": same_g,
+        "pruned_qps": nq / t_pruned, "pruned_totals_equal_alone": same_p,
         "all_totals_equal_alone": same, "found": int(sum(r["found"] for r in res)),
         "dtype": "u8", "data": "synthetic",
         "config": {"workload": f"batched: directed Chung-Lu n={g.n} m={g.m} beta=2.5 "
@@ -369,7 +377,7 @@ def bench_batched(args) -> int:
     }
     print(json.dumps(line), flush=True)
     G.close()
-    return 0 if (same and same_g) else 1
+    return 0 if (same and same_g and same_p) else 1
 
 
 def bench_serving(args) -> int:

@@ -110,10 +110,15 @@ typedef struct {
  * use_graph: tpm_batch_run only: 1 = each pass replays its level launches from a
  *            HIP graph captured once per row shape (lane tables live in device
  *            memory), on a stream the call creates; 0 = plain launches on the
- *            null stream. */
+ *            null stream.
+ * prune:     tpm_sieve_ex and tpm_batch_run: 1 = each query runs alone on the
+ *            subgraph of its own colours (as tpm_graph_prune; built in memory the
+ *            graph keeps for this), which gives the same results; queries with
+ *            wildcards run on the whole graph.  tpm_batch_run then does not pack. */
 typedef struct {
     int32_t chunk;
     int32_t use_graph;
+    int32_t prune;
 } tpm_tuning;
 
 /* ---------------------------------------------------------------- graph --- */

@@ -317,6 +317,7 @@ tpm_status tpm_graph_create_ex(int32_t n, int64_t m, const int32_t *src, const i
         try {
             build_graph(g->G, n, m, src, dst, tau, color, num_colors, flags, opt);
             g->G.pool = new_workspace_pool();
+            g->G.apool = new_arena_pool();
         } catch (...) {
             delete g;
             throw;
@@ -339,6 +340,8 @@ void tpm_graph_destroy(tpm_graph *g) {
     (void)hipDeviceSynchronize();
     delete_workspace_pool(g->G.pool);
     g->G.pool = nullptr;
+    delete_arena_pool(g->G.apool);
+    g->G.apool = nullptr;
     free_graph(g->G);
     if (prev >= 0 && prev != g->G.device) (void)hipSetDevice(prev);
     delete g;
@@ -373,6 +376,7 @@ tpm_status tpm_graph_prune_ex(const tpm_graph *g, const int32_t *colors, int32_t
         try {
             prune_graph(g->G, keep.data(), ntimes ? ts.data() : nullptr, (int32_t)ts.size(), h->G);
             h->G.pool = new_workspace_pool();
+            h->G.apool = new_arena_pool();
         } catch (...) {
             delete h;
             throw;
@@ -391,6 +395,7 @@ tpm_status tpm_graph_layer(const tpm_graph *g, const int32_t *tuple, int32_t k, 
         try {
             layer_graph(g->G, tuple, k, h->G);
             h->G.pool = new_workspace_pool();
+            h->G.apool = new_arena_pool();
         } catch (...) {
             delete h;
             throw;
@@ -516,9 +521,11 @@ tpm_status tpm_sieve_ex(const tpm_graph *g, const int32_t *multiset, int32_t k, 
         req.seed = seed;
         req.vertex_mask = vertex_mask;
         req.chunk = tune ? tune->chunk : 0;
+        TPM_REQUIRE(!tune || tune->prune == 0 || tune->prune == 1, "prune must be 0 or 1");
         SieveResult res;
         hipStream_t st = (hipStream_t)hip_stream;
-        if (loc) run_sieve_loc_all(g->G, req, res, loc, st);
+        if (tune && tune->prune) run_sieve_pruned(g->G, req, res, loc, st);
+        else if (loc) run_sieve_loc_all(g->G, req, res, loc, st);
         else run_sieve(g->G, req, res, st);
         if (per_point) std::memcpy(per_point, res.per_point.data(), res.per_point.size());
         if (total) *total = res.total;

@@ -129,6 +129,34 @@ tpm_status tpm_batch_run(const tpm_graph *g, int32_t nq, const tpm_query *q, tpm
         if (use_graph) TPM_HIP(hipStreamCreateWithFlags(&own.s, hipStreamNonBlocking));
         hipStream_t st = own.s;
         std::map<std::pair<int, int>, std::unique_ptr<StepGraph>> graphs;
+        TPM_REQUIRE(!tune || tune->prune == 0 || tune->prune == 1, "prune must be 0 or 1");
+        if (tune && tune->prune) {
+            // each query alone on the subgraph of its colours, extraction there too
+            struct Ctx {
+                const tpm_query *q;
+                tpm_result *r;
+                const SieveResult *res;
+                hipStream_t st;
+            };
+            for (int32_t i = 0; i < nq; ++i) {
+                SieveRequest req;
+                req.multiset = q[i].multiset;
+                req.k = q[i].k;
+                req.seed = q[i].seed;
+                SieveResult res;
+                Ctx ctx{&q[i], &out[i], &res, st};
+                run_sieve_pruned(
+                    G, req, res, nullptr, st,
+                    [](const Graph &P, void *c) {
+                        Ctx &x = *(Ctx *)c;
+                        x.r->total = x.res->total;
+                        x.r->found = x.res->total != 0;
+                        if (x.q->want_path && x.r->found) extract_into(P, *x.q, *x.r, x.st);
+                    },
+                    &ctx);
+            }
+            return TPM_OK;
+        }
 
         // queries that fill a row on their own, or k = 1, take the single-query path
         std::map<int, std::vector<int32_t>> by_k;

@@ -18,6 +18,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 
 #include <rocprim/rocprim.hpp>
 
@@ -290,6 +291,62 @@ struct GraphArena {
 
 GraphArena *new_graph_arena() { return new GraphArena(); }
 void delete_graph_arena(GraphArena *a) { delete a; }
+
+struct ArenaPool {
+    std::mutex mu;
+    std::vector<GraphArena *> all, free_list;
+    ~ArenaPool() {
+        for (GraphArena *a : all) delete a;
+    }
+};
+ArenaPool *new_arena_pool() { return new ArenaPool(); }
+void delete_arena_pool(ArenaPool *p) { delete p; }
+
+void run_sieve_pruned(const Graph &G, const SieveRequest &req, SieveResult &res,
+                      uint8_t *loc_by_edge, hipStream_t st, void (*then)(const Graph &, void *),
+                      void *ctx) {
+    TPM_REQUIRE(req.multiset != nullptr && req.k >= 1 && req.k <= 16, "bad query");
+    std::vector<uint8_t> keep((size_t)G.q, 0);
+    bool wild = false;
+    for (int i = 0; i < req.k; ++i) {
+        TPM_REQUIRE(req.multiset[i] >= -1 && req.multiset[i] < G.q, "multiset colour out of range");
+        if (req.multiset[i] < 0) wild = true;
+        else keep[(size_t)req.multiset[i]] = 1;
+    }
+    if (wild || !G.apool) {  // every vertex may match: nothing to prune
+        if (loc_by_edge) run_sieve_loc_all(G, req, res, loc_by_edge, st);
+        else run_sieve(G, req, res, st);
+        if (then) then(G, ctx);
+        return;
+    }
+    GraphArena *arena = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(G.apool->mu);
+        if (!G.apool->free_list.empty()) {
+            arena = G.apool->free_list.back();
+            G.apool->free_list.pop_back();
+        } else {
+            arena = new GraphArena();
+            G.apool->all.push_back(arena);
+        }
+    }
+    struct Back {
+        ArenaPool *pool;
+        GraphArena *a;
+        Graph P;
+        ~Back() {
+            P.pool = nullptr;  // the parent's
+            free_graph(P);
+            std::lock_guard<std::mutex> lk(pool->mu);
+            pool->free_list.push_back(a);
+        }
+    } b{G.apool, arena, Graph()};
+    prune_graph(G, keep.data(), nullptr, 0, b.P, arena);
+    b.P.pool = G.pool;
+    if (loc_by_edge) run_sieve_loc_all(b.P, req, res, loc_by_edge, st);
+    else run_sieve(b.P, req, res, st);
+    if (then) then(b.P, ctx);
+}
 
 namespace {
 

@@ -142,6 +142,12 @@ struct Graph;
 WorkspacePool *new_workspace_pool();
 void delete_workspace_pool(WorkspacePool *p);
 
+// Arenas for per-query subgraphs of a graph: a call takes one (creating it if none is
+// free) for the lifetime of its subgraph.
+struct ArenaPool;
+ArenaPool *new_arena_pool();
+void delete_arena_pool(ArenaPool *p);
+
 struct WorkspaceLease {
     explicit WorkspaceLease(const Graph &G);
     ~WorkspaceLease();
@@ -193,7 +199,8 @@ struct Graph {
     int64_t edge_ids = 0;         // input edge ids are < edge_ids (m, or the parent's m
                                   // for a colour-pruned graph)
 
-    WorkspacePool *pool = nullptr;  // owned
+    WorkspacePool *pool = nullptr;  // owned (shared, not owned, by per-query subgraphs)
+    ArenaPool *apool = nullptr;     // owned: memory of per-query subgraphs
     GraphArena *arena = nullptr;    // not owned: device arrays live there when set
 
     // host copies used by extraction
@@ -263,6 +270,13 @@ struct LocSink {
     virtual void consume(const Graph &G, Workspace &ws, const uint8_t *dloc, int64_t lo,
                          int64_t hi, hipStream_t st) = 0;
 };
+// The same sieve on the subgraph of the query's colours (preprocessing step (i));
+// loc_by_edge (nullable, edge_ids bytes) as run_sieve_loc_all.  Queries with wildcard
+// entries run on G.  `then` (nullable) runs on the subgraph before it is freed.
+void run_sieve_pruned(const Graph &G, const SieveRequest &req, SieveResult &res,
+                      uint8_t *loc_by_edge, hipStream_t st,
+                      void (*then)(const Graph &, void *) = nullptr, void *ctx = nullptr);
+
 // Sieve with localisation over the positions req.fin_lo..fin_hi (all when empty),
 // handed to `sink`.
 void run_sieve_sink(const Graph &G, const SieveRequest &req, SieveResult &res, LocSink &sink,

@@ -58,7 +58,7 @@ class tpm_kernel_time(ctypes.Structure):
 
 
 class tpm_tuning(ctypes.Structure):
-    _fields_ = [("chunk", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
+    _fields_ = [("chunk", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("prune", ctypes.c_int32)]
 
 
 class tpm_autotune_report(ctypes.Structure):
@@ -229,7 +229,7 @@ def tpm_graph_stats_get(h) -> dict:
     return {f: getattr(st, f) for f, _ in tpm_graph_stats._fields_}
 
 
-def tpm_sieve(h, multiset, seed, mask=None, chunk=0, loc_m=None, stream=None):
+def tpm_sieve(h, multiset, seed, mask=None, chunk=0, loc_m=None, stream=None, prune=False):
     """Returns (per_point uint8[2^k], total int) or, with loc_m = number of edges,
     (per_point, total, loc uint8[m])."""
     M = _i32(multiset)
@@ -238,7 +238,7 @@ def tpm_sieve(h, multiset, seed, mask=None, chunk=0, loc_m=None, stream=None):
     tot = np.zeros(1, dtype=np.uint8)
     mk = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8)
     loc = None if loc_m is None else np.zeros(max(1, int(loc_m)), dtype=np.uint8)
-    tune = tpm_tuning(int(chunk), 0)
+    tune = tpm_tuning(int(chunk), 0, 1 if prune else 0)
     _check(_lib.tpm_sieve_ex(h, M.ctypes.data_as(_i32p), k, int(seed) & (2**64 - 1),
                              _ptr(mk, _u8p), ctypes.byref(tune), pp.ctypes.data_as(_u8p),
                              tot.ctypes.data_as(_u8p), _ptr(loc, _u8p), _stream_handle(stream)))
@@ -352,10 +352,10 @@ def tpm_autotune(h, k, seed=1) -> dict:
                             "rate": rep.cand_rate[i]} for i in range(rep.ncand)]}
 
 
-def tpm_batch_run(h, queries, chunk=0, use_graph=False):
+def tpm_batch_run(h, queries, chunk=0, use_graph=False, prune=False):
     arr, _keep = _make_queries(queries)
     out = (tpm_result * len(queries))()
-    tune = tpm_tuning(int(chunk), 1 if use_graph else 0)
+    tune = tpm_tuning(int(chunk), 1 if use_graph else 0, 1 if prune else 0)
     _check(_lib.tpm_batch_run(h, len(queries), arr, out, ctypes.byref(tune)))
     return [_result_dict(out[i]) for i in range(len(queries))]
 
@@ -433,9 +433,9 @@ class Graph:
     def stats(self) -> dict:
         return tpm_graph_stats_get(self.h)
 
-    def sieve(self, multiset, seed, mask=None, chunk=0, loc=False, stream=None):
+    def sieve(self, multiset, seed, mask=None, chunk=0, loc=False, stream=None, prune=False):
         ids = self.stats()["edge_ids"] if loc else None
-        return tpm_sieve(self.h, multiset, seed, mask, chunk, ids, stream)
+        return tpm_sieve(self.h, multiset, seed, mask, chunk, ids, stream, prune)
 
     def rainbow(self, k, seed=1, reps=1):
         return tpm_rainbow_decide(self.h, k, seed, reps)
@@ -467,8 +467,8 @@ class Graph:
     def extract(self, multiset, seed, max_reps=8):
         return tpm_extract(self.h, multiset, seed, max_reps)
 
-    def batch(self, queries, chunk=0, use_graph=False):
-        return tpm_batch_run(self.h, queries, chunk, use_graph)
+    def batch(self, queries, chunk=0, use_graph=False, prune=False):
+        return tpm_batch_run(self.h, queries, chunk, use_graph, prune)
 
     def sieve_vertex(self, multiset, seed, mask=None):
         return tpm_sieve_vertex(self.h, multiset, seed, mask)

@@ -118,3 +118,27 @@ def test_ec_path_motif_by_time_pruning(tpm):
         Gd.close()
         checked += 1
     assert checked > 15
+
+
+def test_pruned_tuning_in_sieve_and_batch(tpm):
+    """tuning.prune: sieves and batches run each query on its colour subgraph (memory
+    reused across calls) with the same results; wildcard queries use the whole graph."""
+    g = G.chung_lu_graph(5000, 80000, 2.5, 60, 6, 94)
+    rng = np.random.default_rng(95)
+    Gd = tpm.Graph.from_temporal(g)
+    for it in range(8):
+        M = [int(c) for c in rng.integers(-1 if it % 4 == 3 else 0, 6, int(rng.integers(2, 10)))]
+        say(f"case pruned tuning {it}: M={M}")
+        pp, tot, loc = Gd.sieve(M, 11 + it, loc=True, prune=True)
+        wpp, wloc = oracle.sieve(g, M, 11 + it, loc=True)
+        assert np.array_equal(pp, wpp) and np.array_equal(loc, wloc)
+    qs = [{"multiset": [int(c) for c in rng.integers(0, 6, int(rng.integers(2, 9)))],
+           "seed": int(rng.integers(0, 2**62)), "want_path": 1} for _ in range(20)]
+    res = Gd.batch(qs, prune=True)
+    for q, r in zip(qs, res):
+        assert r["total"] == oracle.sieve_total(g, q["multiset"], q["seed"])
+        if r["found"]:
+            k = len(q["multiset"])
+            assert r["path_status"] == tpm.TPM_OK
+            assert pyref.check_path(g, q["multiset"], r["path_vertices"][:k], r["path_edges"][:k - 1])
+    Gd.close()
