@@ -68,9 +68,11 @@ typedef int32_t tpm_status;
 typedef struct tpm_graph tpm_graph;
 
 /* Options of graph creation.  Zero / NULL fields take the default.
- * tile_edges: most CSR positions per work tile (1..4096, default 1024).  In-lists no
- *             longer than a tile are packed whole; longer ones are cut into pieces
- *             that add the running value of their predecessors by look-back.
+ * tile_edges: T, the work-tile size in CSR positions (1..4096, default 1024).
+ *             In-lists longer than T are cut into pieces of T positions that add the
+ *             running value of their predecessors by look-back; shorter ones stay
+ *             whole, grouped by the T-aligned window of their first position (a
+ *             group spans fewer than 2T positions).
  * tile_held:  reserved, must be 0.
  * transit, delay: the variant with transition and delay times (section "Path motif
  *             problem with delays"); host arrays even with TPM_DEVICE_PTRS.

@@ -249,8 +249,10 @@ tpm_status extract_path(const Graph &G, const int32_t *M, int32_t k, uint64_t se
         cur.erase(it);
         // next: v's in-edges that arrived by tau - delay(v) (plain problem: earlier
         // than tau)
-        lo = G.h_inptr[v];
-        int64_t a = G.h_inptr[v], b = G.h_inptr[v + 1];
+        int32_t ab[2];
+        TPM_HIP(hipMemcpy(ab, G.inptr + v, 2 * sizeof(int32_t), hipMemcpyDeviceToHost));
+        lo = ab[0];
+        int64_t a = ab[0], b = ab[1];
         if (b > a) {
             std::vector<int32_t> taus((size_t)(b - a));
             TPM_HIP(hipMemcpy(taus.data(), G.ptau + a, sizeof(int32_t) * (b - a), hipMemcpyDeviceToHost));

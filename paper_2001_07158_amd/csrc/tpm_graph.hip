@@ -9,10 +9,11 @@
 // once per graph by binary search.  Only positions some edge reads ("rows") are ever
 // stored by the sieve kernels; rows are numbered in CSR order.
 //
-// Work tiles: consecutive CSR positions (<= tile_edges).  Whole in-lists are packed
-// into tiles; an in-list longer than a tile is cut into pieces of tile_edges
-// positions.  Pieces of one in-list publish their running values to consecutive
-// "slots" for the look-back.
+// Work tiles: consecutive CSR positions, built on the device (k_tile_*).  An in-list
+// longer than tile_edges (T) is cut into pieces of T positions whose running values
+// are published to consecutive "slots" for the look-back; shorter in-lists are kept
+// whole and grouped by the T-aligned window their first position falls in (a group
+// spans less than 2T positions).
 
 #include <hip/hip_runtime.h>
 
@@ -209,6 +210,74 @@ __global__ void k_compact(int64_t m, const int32_t *keep, const int32_t *at, con
     }
 }
 
+// ---- work tiles on the device.  Per vertex u with an in-list of L positions: a long
+// list (L > T) gives ceil(L / T) pieces of T positions; every piece but the last
+// publishes to a slot, every piece but the first looks back at its predecessor's.  A
+// short list (0 < L <= T) starts a new tile when it is the first non-empty list, when
+// the previous non-empty list is long, or when its first position falls in another
+// T-aligned window than the previous list's; otherwise it joins that list's tile (so a
+// tile of short lists spans less than 2T positions).
+__global__ void k_tile_prev(int32_t n, const int32_t *inptr, int32_t *nz) {
+    int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u < n) nz[u] = inptr[u + 1] > inptr[u] ? (int32_t)u : -1;
+}
+
+__global__ void k_tile_count(int32_t n, const int32_t *inptr, int32_t T, const int32_t *prevmax,
+                             int32_t *tcnt, int32_t *scnt, unsigned long long *stats) {
+    int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int32_t L = 0;
+    if (u < n) {
+        const int32_t a = inptr[u];
+        L = inptr[u + 1] - a;
+        int32_t t = 0, sl = 0;
+        if (L > T) {
+            t = (L + T - 1) / T;
+            sl = t - 1;
+        } else if (L > 0) {
+            const int32_t prev = u > 0 ? prevmax[u - 1] : -1;  // previous non-empty list
+            if (prev < 0) {
+                t = 1;
+            } else {
+                const int32_t pa = inptr[prev], pl = inptr[prev + 1] - pa;
+                t = (pl > T || a / T != pa / T) ? 1 : 0;
+            }
+        }
+        tcnt[u] = t;
+        scnt[u] = sl;
+    }
+    // in-degree statistics: largest and non-empty count
+    unsigned long long mx = (unsigned long long)L, ne = L > 0 ? 1ull : 0ull;
+    for (int off = 32; off >= 1; off >>= 1) {
+        const unsigned long long o = __shfl_xor(mx, off);
+        mx = o > mx ? o : mx;
+        ne += __shfl_xor(ne, off);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicMax(&stats[0], mx);
+        if (ne) atomicAdd(&stats[1], ne);
+    }
+}
+
+__global__ void k_tile_fill(int32_t n, const int32_t *inptr, int32_t T, const int32_t *tcnt,
+                            const int32_t *tbase, const int32_t *sbase, int32_t *p0, int32_t *pub,
+                            int32_t *lb) {
+    int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= n || tcnt[u] == 0) return;
+    const int32_t a = inptr[u], L = inptr[u + 1] - a, tb = tbase[u];
+    if (L > T) {
+        const int32_t np = tcnt[u], sb = sbase[u];
+        for (int32_t j = 0; j < np; ++j) {
+            p0[tb + j] = a + j * T;
+            pub[tb + j] = j + 1 < np ? sb + j : -1;
+            lb[tb + j] = j > 0 ? sb + j - 1 : -1;
+        }
+    } else {
+        p0[tb] = a;
+        pub[tb] = -1;
+        lb[tb] = -1;
+    }
+}
+
 inline unsigned grid_for(int64_t work, int block = 256) {
     int64_t g = (work + block - 1) / block;
     return (unsigned)std::max<int64_t>(1, g);
@@ -229,60 +298,14 @@ int bits_for(uint64_t v) {  // bits needed to represent values 0..v
     return std::max(b, 1);
 }
 
-// Host-side tile builder (see the file comment).
-void build_tiles(const std::vector<int32_t> &inptr, int32_t T, std::vector<int32_t> &p0,
-                 std::vector<int32_t> &pub, std::vector<int32_t> &lb, int64_t &nslots) {
-    const int32_t n = (int32_t)inptr.size() - 1;
-    p0.clear();
-    pub.clear();
-    lb.clear();
-    nslots = 0;
-    int32_t cur_start = -1, cur_len = 0;
-    auto close_pack = [&]() {
-        if (cur_len > 0) {
-            p0.push_back(cur_start);
-            pub.push_back(-1);
-            lb.push_back(-1);
-        }
-        cur_len = 0;
-        cur_start = -1;
-    };
-    for (int32_t u = 0; u < n; ++u) {
-        int32_t a = inptr[u], b = inptr[u + 1], L = b - a;
-        if (L == 0) continue;
-        if (L <= T) {
-            if (cur_len > 0 && cur_len + L > T) close_pack();
-            if (cur_len == 0) cur_start = a;
-            cur_len += L;
-            continue;
-        }
-        close_pack();
-        // first piece: starts at the in-list head and publishes its running value;
-        // every later piece looks back, and all but the last publish as well
-        int32_t prev_slot = (int32_t)nslots++;
-        p0.push_back(a);
-        pub.push_back(prev_slot);
-        lb.push_back(-1);
-        for (int32_t q = a + T; q < b; q += T) {
-            bool last = (q + T >= b);
-            int32_t slot = last ? -1 : (int32_t)nslots++;
-            p0.push_back(q);
-            pub.push_back(slot);
-            lb.push_back(prev_slot);
-            prev_slot = slot;
-        }
-    }
-    close_pack();
-    p0.push_back(inptr[n]);
-}
-
 }  // namespace
 
 // Slots of a graph arena: one grow-only buffer per index array and per temporary.
 enum ArenaSlot {
     A_COLOR, A_PDST, A_PSRC, A_PTAU, A_PEID, A_GSRC, A_OROW, A_INPTR, A_SEGNEXT, A_TP0, A_TPUB,
     A_TLB, A_LDS, A_TTAB, A_KEEPC, A_KEEP, A_AT, A_SCRATCH, A_GPOS, A_NEEDED, A_ROWOF, A_TSORT,
-    A_TUNIQ, A_TCOUNT, A_CNT, A_PDEP, A_VDELAY, A_VKEEP, A_TSET, A_FID, A_NSLOTS
+    A_TUNIQ, A_TCOUNT, A_CNT, A_PDEP, A_VDELAY, A_VKEEP, A_TSET, A_FID, A_TNZ, A_TPM, A_TCNT,
+    A_SCNT, A_TBASE, A_SBASE, A_TSTAT, A_NSLOTS
 };
 
 struct GraphArena {
@@ -391,11 +414,155 @@ struct Temps {
     }
 };
 
+// Greedy tiles on the host (whole graphs, built once): short in-lists are packed
+// while the tile stays within T positions, long ones are cut into pieces of T.  The
+// device builder below groups short lists by window instead (per-query subgraphs,
+// where build time matters); results do not depend on the tiling, and the greedy
+// tiles measured a few percent faster in the level kernels.
+void build_tiles(const std::vector<int32_t> &inptr, int32_t T, std::vector<int32_t> &p0,
+                 std::vector<int32_t> &pub, std::vector<int32_t> &lb, int64_t &nslots) {
+    const int32_t n = (int32_t)inptr.size() - 1;
+    p0.clear();
+    pub.clear();
+    lb.clear();
+    nslots = 0;
+    int32_t cur_start = -1, cur_len = 0;
+    auto close_pack = [&]() {
+        if (cur_len > 0) {
+            p0.push_back(cur_start);
+            pub.push_back(-1);
+            lb.push_back(-1);
+        }
+        cur_len = 0;
+        cur_start = -1;
+    };
+    for (int32_t u = 0; u < n; ++u) {
+        int32_t a = inptr[u], b = inptr[u + 1], L = b - a;
+        if (L == 0) continue;
+        if (L <= T) {
+            if (cur_len > 0 && cur_len + L > T) close_pack();
+            if (cur_len == 0) cur_start = a;
+            cur_len += L;
+            continue;
+        }
+        close_pack();
+        // first piece: starts at the in-list head and publishes its running value;
+        // every later piece looks back, and all but the last publish as well
+        int32_t prev_slot = (int32_t)nslots++;
+        p0.push_back(a);
+        pub.push_back(prev_slot);
+        lb.push_back(-1);
+        for (int32_t q = a + T; q < b; q += T) {
+            bool last = (q + T >= b);
+            int32_t slot = last ? -1 : (int32_t)nslots++;
+            p0.push_back(q);
+            pub.push_back(slot);
+            lb.push_back(prev_slot);
+            prev_slot = slot;
+        }
+    }
+    close_pack();
+    p0.push_back(inptr[n]);
+}
+
+// Builds G.tile_p0/pub/lb (device), G.h_tile_p0, ntiles, nslots, max_in_degree and
+// segments from G.inptr on the device (allocations through galloc unless `own` is set:
+// then plain allocations the caller adopts).
+void build_tiles_device(Graph &G, int32_t T, Temps &tmp, int64_t &acct, int32_t **tp0,
+                        int32_t **tpub, int32_t **tlb, int64_t &ntiles, int64_t &nslots,
+                        bool own, bool greedy) {
+    const int32_t n = G.n;
+    hipStream_t st = nullptr;
+    int32_t *nz = tmp.get<int32_t>(A_TNZ, n);
+    int32_t *pm = tmp.get<int32_t>(A_TPM, n);
+    int32_t *tcnt = tmp.get<int32_t>(A_TCNT, n);
+    int32_t *scnt = tmp.get<int32_t>(A_SCNT, n);
+    int32_t *tbase = tmp.get<int32_t>(A_TBASE, n);
+    int32_t *sbase = tmp.get<int32_t>(A_SBASE, n);
+    unsigned long long *stats = tmp.get<unsigned long long>(A_TSTAT, 2);
+    TPM_HIP(hipMemsetAsync(stats, 0, 2 * sizeof(unsigned long long), st));
+    k_tile_prev<<<grid_for(n), 256, 0, st>>>(n, G.inptr, nz);
+    size_t b1 = 0, b2 = 0;
+    TPM_HIP(rocprim::inclusive_scan(nullptr, b1, nz, pm, (size_t)n, rocprim::maximum<int32_t>(), st));
+    TPM_HIP(rocprim::exclusive_scan(nullptr, b2, tcnt, tbase, 0, (size_t)n, rocprim::plus<int32_t>(), st));
+    void *scratch = tmp.raw(A_SCRATCH, std::max(b1, b2));
+    TPM_HIP(rocprim::inclusive_scan(scratch, b1, nz, pm, (size_t)n, rocprim::maximum<int32_t>(), st));
+    k_tile_count<<<grid_for(n), 256, 0, st>>>(n, G.inptr, T, pm, tcnt, scnt, stats);
+    TPM_HIP(rocprim::exclusive_scan(scratch, b2, tcnt, tbase, 0, (size_t)n, rocprim::plus<int32_t>(), st));
+    TPM_HIP(rocprim::exclusive_scan(scratch, b2, scnt, sbase, 0, (size_t)n, rocprim::plus<int32_t>(), st));
+    int32_t h[4] = {0, 0, 0, 0};
+    TPM_HIP(hipMemcpy(&h[0], tbase + (n - 1), sizeof(int32_t), hipMemcpyDeviceToHost));
+    TPM_HIP(hipMemcpy(&h[1], tcnt + (n - 1), sizeof(int32_t), hipMemcpyDeviceToHost));
+    TPM_HIP(hipMemcpy(&h[2], sbase + (n - 1), sizeof(int32_t), hipMemcpyDeviceToHost));
+    TPM_HIP(hipMemcpy(&h[3], scnt + (n - 1), sizeof(int32_t), hipMemcpyDeviceToHost));
+    unsigned long long hs[2] = {0, 0};
+    TPM_HIP(hipMemcpy(hs, stats, sizeof(hs), hipMemcpyDeviceToHost));
+    ntiles = (int64_t)h[0] + h[1];
+    nslots = (int64_t)h[2] + h[3];
+    G.max_in_degree = (int64_t)hs[0];
+    G.segments = (int64_t)hs[1];
+    if (greedy) {  // whole graph: greedy packing on the host instead
+        std::vector<int32_t> hin((size_t)n + 1), p0, pub, lb;
+        TPM_HIP(hipMemcpy(hin.data(), G.inptr, sizeof(int32_t) * ((size_t)n + 1), hipMemcpyDeviceToHost));
+        build_tiles(hin, T, p0, pub, lb, nslots);
+        ntiles = (int64_t)pub.size();
+        if (own) {
+            *tp0 = dalloc<int32_t>(ntiles + 1, acct);
+            *tpub = dalloc<int32_t>(ntiles, acct);
+            *tlb = dalloc<int32_t>(ntiles, acct);
+        } else {
+            *tp0 = galloc<int32_t>(G, A_TP0, ntiles + 1, acct);
+            *tpub = galloc<int32_t>(G, A_TPUB, ntiles, acct);
+            *tlb = galloc<int32_t>(G, A_TLB, ntiles, acct);
+        }
+        TPM_HIP(hipMemcpy(*tp0, p0.data(), sizeof(int32_t) * p0.size(), hipMemcpyHostToDevice));
+        if (ntiles) {
+            TPM_HIP(hipMemcpy(*tpub, pub.data(), sizeof(int32_t) * pub.size(), hipMemcpyHostToDevice));
+            TPM_HIP(hipMemcpy(*tlb, lb.data(), sizeof(int32_t) * lb.size(), hipMemcpyHostToDevice));
+        }
+        G.h_tile_p0 = std::move(p0);
+        return;
+    }
+    if (own) {
+        *tp0 = dalloc<int32_t>(ntiles + 1, acct);
+        *tpub = dalloc<int32_t>(ntiles, acct);
+        *tlb = dalloc<int32_t>(ntiles, acct);
+    } else {
+        *tp0 = galloc<int32_t>(G, A_TP0, ntiles + 1, acct);
+        *tpub = galloc<int32_t>(G, A_TPUB, ntiles, acct);
+        *tlb = galloc<int32_t>(G, A_TLB, ntiles, acct);
+    }
+    k_tile_fill<<<grid_for(n), 256, 0, st>>>(n, G.inptr, T, tcnt, tbase, sbase, *tp0, *tpub, *tlb);
+    const int32_t mm = (int32_t)G.m;
+    TPM_HIP(hipMemcpy(*tp0 + ntiles, &mm, sizeof(int32_t), hipMemcpyHostToDevice));
+    G.h_tile_p0.resize((size_t)ntiles + 1);
+    TPM_HIP(hipMemcpy(G.h_tile_p0.data(), *tp0, sizeof(int32_t) * ((size_t)ntiles + 1),
+                      hipMemcpyDeviceToHost));
+}
+
+// The bank-replicated LOG/EXP image (kLdsBytes), built once per process.
+const std::vector<uint8_t> &lds_image_host() {
+    static const std::vector<uint8_t> img = [] {
+        std::vector<uint8_t> v(kLdsBytes, 0);
+        auto put32 = [&](size_t off, uint32_t x) { std::memcpy(v.data() + off, &x, 4); };
+        for (int g = 0; g < 256; ++g) {
+            const uint32_t l7 = g ? ((uint32_t)kGf.log[g] << 7) : kZero7;
+            for (int c = 0; c < 32; ++c) put32((size_t)g * 256 + c * 4, l7);
+        }
+        for (int r = 0; r < kExpRows; ++r) {
+            const uint32_t e = (r <= 762) ? kGf.exp[r % 255] : 0u;
+            for (int c = 0; c < 32; ++c) put32((size_t)kExpBase + (size_t)r * 128 + c * 4, e);
+        }
+        return v;
+    }();
+    return img;
+}
+
 }  // namespace
 
 void free_graph(Graph &G) {
     int32_t **ptrs[] = {&G.color, &G.pdst,  &G.psrc,    &G.ptau,     &G.peid,   &G.gsrc,
-                        &G.orow,  &G.inptr, &G.segnext, &G.tile_p0, &G.tile_pub, &G.tile_lb,
+                        &G.orow,  &G.inptr, &G.tile_p0, &G.tile_pub, &G.tile_lb,
                         &G.ttab,  &G.pdep,  &G.vdelay, &G.fid};
     const bool own = G.arena == nullptr;  // arena memory stays with the arena
     for (auto pp : ptrs) {
@@ -410,7 +577,7 @@ void free_graph(Graph &G) {
 // sorted by (dst, tau, input id)), G.color and G.tmax: distinct timestamps, in-list
 // offsets, gathered and stored rows, host copies, tiles and the LDS image.  taus:
 // the m timestamps in any order (device).
-void finish_index(Graph &G, int64_t &acct, const int32_t *taus) {
+void finish_index(Graph &G, int64_t &acct, const int32_t *taus, bool greedy_tiles) {
     const int64_t m = G.m;
     const int32_t n = G.n;
     const int32_t tmax = G.tmax;
@@ -473,50 +640,11 @@ void finish_index(Graph &G, int64_t &acct, const int32_t *taus) {
         TPM_HIP(hipMemcpy(G.h_color.data(), G.color, sizeof(int32_t) * (size_t)n,
                           hipMemcpyDeviceToHost));
     }
-    G.h_inptr.resize((size_t)n + 1);
-    TPM_HIP(hipMemcpy(G.h_inptr.data(), G.inptr, sizeof(int32_t) * ((size_t)n + 1),
-                      hipMemcpyDeviceToHost));
-    G.max_in_degree = 0;
-    G.segments = 0;
-    std::vector<int32_t> sn((size_t)n, -1);
-    int32_t nextv = -1;
-    for (int32_t u = n - 1; u >= 0; --u) {
-        const int64_t d = G.h_inptr[u + 1] - G.h_inptr[u];
-        G.max_in_degree = std::max<int64_t>(G.max_in_degree, d);
-        G.segments += d > 0;
-        sn[u] = nextv;
-        if (d > 0) nextv = u;
-    }
-    G.segnext = galloc<int32_t>(G, A_SEGNEXT, n, acct);
-    TPM_HIP(hipMemcpy(G.segnext, sn.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice));
-    std::vector<int32_t> tp0, tpub, tlb;
-    build_tiles(G.h_inptr, T, tp0, tpub, tlb, G.nslots);
-    G.ntiles = (int64_t)tpub.size();
-    G.h_tile_p0 = tp0;
-    G.tile_p0 = galloc<int32_t>(G, A_TP0, G.ntiles + 1, acct);
-    G.tile_pub = galloc<int32_t>(G, A_TPUB, G.ntiles, acct);
-    G.tile_lb = galloc<int32_t>(G, A_TLB, G.ntiles, acct);
-    TPM_HIP(hipMemcpy(G.tile_p0, tp0.data(), sizeof(int32_t) * tp0.size(), hipMemcpyHostToDevice));
-    if (G.ntiles) {
-        TPM_HIP(hipMemcpy(G.tile_pub, tpub.data(), sizeof(int32_t) * tpub.size(),
-                          hipMemcpyHostToDevice));
-        TPM_HIP(hipMemcpy(G.tile_lb, tlb.data(), sizeof(int32_t) * tlb.size(),
-                          hipMemcpyHostToDevice));
-    }
+    build_tiles_device(G, T, tmp, acct, &G.tile_p0, &G.tile_pub, &G.tile_lb, G.ntiles, G.nslots,
+                       false, greedy_tiles);
 
-    // ---- LDS table image (see kLdsBytes)
-    std::vector<uint8_t> img(kLdsBytes, 0);
-    auto put32 = [&](size_t off, uint32_t v) { std::memcpy(img.data() + off, &v, 4); };
-    for (int v = 0; v < 256; ++v) {
-        uint32_t l7 = v ? ((uint32_t)kGf.log[v] << 7) : kZero7;
-        for (int c = 0; c < 32; ++c) put32((size_t)v * 256 + c * 4, l7);
-    }
-    for (int s2 = 0; s2 < kExpRows; ++s2) {
-        uint32_t e = (s2 <= 762) ? kGf.exp[s2 % 255] : 0u;
-        for (int c = 0; c < 32; ++c) put32((size_t)kExpBase + (size_t)s2 * 128 + c * 4, e);
-    }
     G.lds_image = galloc<uint8_t>(G, A_LDS, kLdsBytes, acct);
-    TPM_HIP(hipMemcpy(G.lds_image, img.data(), kLdsBytes, hipMemcpyHostToDevice));
+    TPM_HIP(hipMemcpy(G.lds_image, lds_image_host().data(), kLdsBytes, hipMemcpyHostToDevice));
     TPM_HIP(hipDeviceSynchronize());
 }
 
@@ -664,7 +792,7 @@ void build_graph(Graph &G, int32_t n, int64_t m, const int32_t *src, const int32
             (void)hipFree(scratch);
             scratch = nullptr;
         }
-        finish_index(G, acct, d_order_t);
+        finish_index(G, acct, d_order_t, true);
         G.device_bytes = acct;
     } catch (...) {
         cleanup_tmp();
@@ -755,7 +883,7 @@ void prune_graph(const Graph &P, const uint8_t *keep_color, const int32_t *times
             }
             TPM_HIP(hipDeviceSynchronize());
         }
-        finish_index(G, acct, G.ptau);
+        finish_index(G, acct, G.ptau, arena == nullptr);
         G.device_bytes = acct;
     } catch (...) {
         free_graph(G);
@@ -878,7 +1006,7 @@ void layer_graph(const Graph &P, const int32_t *tuple, int32_t k, Graph &G) {
         cleanup();
         d_rank = keep = at = nullptr;
         scratch = nullptr;
-        finish_index(G, acct, G.ptau);
+        finish_index(G, acct, G.ptau, true);
         G.device_bytes = acct;
     } catch (...) {
         cleanup();
@@ -890,30 +1018,23 @@ void layer_graph(const Graph &P, const int32_t *tuple, int32_t k, Graph &G) {
 void retile_graph(Graph &G, int32_t T) {
     TPM_REQUIRE(T >= 1 && T <= 4096, "tile_edges must be in [1, 4096]");
     if (T == G.tile_edges) return;
+    TPM_REQUIRE(G.arena == nullptr, "graphs built in an arena are not retiled");
     TPM_HIP(hipSetDevice(G.device));
-    std::vector<int32_t> tp0, tpub, tlb;
-    int64_t nslots = 0;
-    build_tiles(G.h_inptr, T, tp0, tpub, tlb, nslots);
-    const int64_t nt = (int64_t)tpub.size();
-    int64_t acct = 0;
+    int64_t acct = 0, nt = 0, nslots = 0;
     int32_t *p0 = nullptr, *pb = nullptr, *lb = nullptr;
+    std::vector<int32_t> old_h = G.h_tile_p0;
     try {
-        p0 = dalloc<int32_t>(nt + 1, acct);
-        pb = dalloc<int32_t>(nt, acct);
-        lb = dalloc<int32_t>(nt, acct);
-        TPM_HIP(hipMemcpy(p0, tp0.data(), sizeof(int32_t) * tp0.size(), hipMemcpyHostToDevice));
-        if (nt) {
-            TPM_HIP(hipMemcpy(pb, tpub.data(), sizeof(int32_t) * tpub.size(), hipMemcpyHostToDevice));
-            TPM_HIP(hipMemcpy(lb, tlb.data(), sizeof(int32_t) * tlb.size(), hipMemcpyHostToDevice));
-        }
+        Temps tmp(nullptr);
+        build_tiles_device(G, T, tmp, acct, &p0, &pb, &lb, nt, nslots, true, true);
     } catch (...) {
         for (void *q : {(void *)p0, (void *)pb, (void *)lb})
             if (q) (void)hipFree(q);
+        G.h_tile_p0 = std::move(old_h);
         throw;
     }
     // the old tile arrays may still be read by work queued on other streams
     TPM_HIP(hipDeviceSynchronize());
-    const int64_t old_bytes = (int64_t)sizeof(int32_t) * (2 * G.ntiles + 1);
+    const int64_t old_bytes = (int64_t)sizeof(int32_t) * (3 * G.ntiles + 1);
     for (int32_t **q : {&G.tile_p0, &G.tile_pub, &G.tile_lb}) {
         if (*q) (void)hipFree(*q);
     }
@@ -922,7 +1043,6 @@ void retile_graph(Graph &G, int32_t T) {
     G.tile_lb = lb;
     G.ntiles = nt;
     G.nslots = nslots;
-    G.h_tile_p0 = std::move(tp0);
     G.tile_edges = T;
     G.device_bytes += acct - old_bytes;
 }

@@ -184,7 +184,6 @@ struct Graph {
                                //     earlier than tau), -1 if none
     int32_t *orow = nullptr;   // [m] state row written at this position, -1 if none
     int32_t *inptr = nullptr;  // [n+1]
-    int32_t *segnext = nullptr;  // [n] next vertex (in CSR order) with in-edges, -1 if none
     int32_t *tile_p0 = nullptr;   // [ntiles+1]
     int32_t *tile_pub = nullptr;  // [ntiles] slot this tile publishes to, -1 if none
     int32_t *tile_lb = nullptr;   // [ntiles] slot its look-back starts at, -1 if none
@@ -203,8 +202,7 @@ struct Graph {
     ArenaPool *apool = nullptr;     // owned: memory of per-query subgraphs
     GraphArena *arena = nullptr;    // not owned: device arrays live there when set
 
-    // host copies used by extraction
-    std::vector<int32_t> h_inptr;   // [n+1]
+    // host copies
     std::vector<int32_t> h_color;   // [n]
     std::vector<int32_t> h_tile_p0; // [ntiles+1]
     std::vector<int32_t> h_ttab;    // [ntimes]

@@ -65,7 +65,6 @@ struct LevelParams {
     const uint8_t *gbase;  // gathered rows (log domain), rowb bytes each
     const int32_t *pdst;
     const int32_t *peid;
-    const int32_t *segnext;  // per vertex: the next vertex with in-edges (-1: none)
     const int32_t *orow;   // row stored at each position (-1: none)
     uint8_t *sout;         // stored rows
     const uint8_t *xt;     // per-vertex rows of x_u^A (bytes)
@@ -1264,7 +1263,6 @@ void run_sieve_impl(const Graph &G, const SieveRequest &req, SieveResult &res, b
                 P.gidx = (l == 2) ? G.psrc : G.gsrc;
                 P.gbase = (l == 2) ? xt.as<uint8_t>() : ((l & 1) ? s0.as<uint8_t>() : s1.as<uint8_t>());
                 P.pdst = G.pdst;
-                P.segnext = G.segnext;
                 P.peid = G.peid;
                 P.orow = G.orow;
                 P.sout = (l & 1) ? s1.as<uint8_t>() : s0.as<uint8_t>();
