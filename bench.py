@@ -220,15 +220,22 @@ def main() -> int:
         found = G.decide(M, seed0, reps=1)
         t_dec = (time.perf_counter() - te) * 1e3
         te = time.perf_counter()
-        rc, verts, edges = G.extract(M, seed0, max_reps=8)
+        rc, verts, edges, n_ext = G.extract_ex(M, seed0, max_reps=8, method=0)
         t_ext = (time.perf_counter() - te) * 1e3
         ok = rc == tpm.TPM_OK  # the library verifies every path it returns
+        e1 = None
+        if k <= 6:  # the paper's self-reducibility needs O(k log n) decisions
+            te = time.perf_counter()
+            rc1, _, _, n1 = G.extract_ex(M, seed0, max_reps=4, method=1)
+            e1 = {"ms": (time.perf_counter() - te) * 1e3, "sieves": n1,
+                  "found": rc1 == tpm.TPM_OK}
         te = time.perf_counter()
         t_opt_val = G.optimum_time(M, seed0, reps=1)
         t_opt = (time.perf_counter() - te) * 1e3
         line["extras"] = {
             "decide_ms": t_dec, "found": bool(found), "extract_ms": t_ext,
-            "extract_over_decide": t_ext / t_dec, "path_verified": bool(ok),
+            "extract_sieves": n_ext, "extract_over_decide": t_ext / t_dec,
+            "path_verified": bool(ok), "extract_selfreduce": e1,
             "optimum_time_ms": t_opt, "optimum_time": t_opt_val,
         }
         print(f"# decide {t_dec:.1f} ms, extract {t_ext:.1f} ms (path ok={ok}), optimum time "

@@ -245,6 +245,17 @@ tpm_status tpm_decide(const tpm_graph *g, const int32_t *multiset, int32_t k, ui
 tpm_status tpm_extract(const tpm_graph *g, const int32_t *multiset, int32_t k, uint64_t seed,
                        int32_t max_reps, int32_t *path_vertices, int64_t *path_edges);
 
+/* As tpm_extract with a choice of method, and the number of sieves run (nullable).
+ * method 0: the localisation-guided self-reduction of tpm_extract (about k sieves).
+ * method 1: the paper's self-reducibility (section "Extracting a solution", first
+ *           approach): vertices of other colours are dropped, then vertex groups are
+ *           deleted while a decision (max_reps sieves) stays YES, halving groups that
+ *           cannot go (O(k log n) decisions), and a temporal DFS over the surviving
+ *           vertices returns the path.  k >= 2. */
+tpm_status tpm_extract_ex(const tpm_graph *g, const int32_t *multiset, int32_t k, uint64_t seed,
+                          int32_t max_reps, int32_t method, int32_t *path_vertices,
+                          int64_t *path_edges, int64_t *sieves);
+
 /* ------------------------------------------------------ localised sieves --- */
 /* Vertex-localised sieve (section "Vertex-localization"): q[u] = sum over all 2^k
  * sieve points A of P_{u,k,t}(z^A), for every vertex u (q: n bytes, host).  q[u] != 0

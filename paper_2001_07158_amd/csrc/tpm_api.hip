@@ -7,6 +7,7 @@
 #include <atomic>
 #include <chrono>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <set>
@@ -193,7 +194,15 @@ bool verify_path(const Graph &G, const int32_t *M, int32_t k, const int32_t *ver
 // negative, so each step retries with fresh seeds.
 tpm_status extract_path(const Graph &G, const int32_t *M, int32_t k, uint64_t seed,
                         int32_t max_reps, int32_t *path_vertices, int64_t *path_edges,
-                        hipStream_t st) {
+                        hipStream_t st, int64_t *sieves) {
+    int64_t nsieve = 0;
+    struct Count {
+        int64_t *out;
+        int64_t &n;
+        ~Count() {
+            if (out) *out = n;
+        }
+    } count{sieves, nsieve};
     TPM_REQUIRE(k >= 1 && k <= 16, "k must be in [1, 16]");
     TPM_REQUIRE(max_reps >= 1, "max_reps must be >= 1");
     for (int i = 0; i < k; ++i) TPM_REQUIRE(M[i] >= -1 && M[i] < G.q, "multiset colour out of range");
@@ -226,6 +235,7 @@ tpm_status extract_path(const Graph &G, const int32_t *M, int32_t k, uint64_t se
             req.fin_hi = hi;
             req.want_pick = true;
             run_sieve(G, req, res, st);
+            ++nsieve;
             got = res.pick_pos >= 0;
         }
         if (!got) return TPM_NOTFOUND;
@@ -275,6 +285,136 @@ tpm_status extract_path(const Graph &G, const int32_t *M, int32_t k, uint64_t se
     for (int i = 0; i < k; ++i) path_vertices[i] = orig(rverts[i]);
     for (int i = 0; i + 1 < k; ++i) path_edges[i] = reids[i];
     return TPM_OK;
+}
+
+// Self-reducibility (section "Extracting a solution", first approach): delete vertex
+// groups while the decision oracle stays YES, halving a group that cannot go (group
+// testing, O(k log n) decisions), then find the path among the survivors by temporal
+// DFS.  A decision is `reps` sieves with fresh seeds; YES is certain, so a deleted
+// group never held the last matching path, and a false NO only keeps extra vertices.
+tpm_status extract_selfreduce(const Graph &G, const int32_t *M, int32_t k, uint64_t seed,
+                              int32_t reps, int32_t *path_vertices, int64_t *path_edges,
+                              int64_t *sieves) {
+    TPM_REQUIRE(k >= 2 && k <= 16, "k must be in [2, 16]");
+    TPM_REQUIRE(reps >= 1, "max_reps must be >= 1");
+    bool wild = false;
+    std::vector<uint8_t> in_m((size_t)G.q, 0);
+    for (int i = 0; i < k; ++i) {
+        TPM_REQUIRE(M[i] >= -1 && M[i] < G.q, "multiset colour out of range");
+        if (M[i] < 0) wild = true;
+        else in_m[(size_t)M[i]] = 1;
+    }
+    // vertices of other colours are on no matching path
+    std::vector<uint8_t> mask((size_t)G.n, 0);
+    std::vector<int32_t> cand;
+    for (int32_t u = 0; u < G.n; ++u)
+        if (wild || in_m[(size_t)G.h_color[(size_t)u]]) {
+            mask[(size_t)u] = 1;
+            cand.push_back(u);
+        }
+    int64_t calls = 0, nsieve = 0;
+    auto decide = [&]() {
+        for (int32_t r = 0; r < reps; ++r) {
+            SieveRequest req;
+            req.multiset = M;
+            req.k = k;
+            req.seed = step_seed(seed, 2000000 + calls, r);
+            req.vertex_mask = mask.data();
+            SieveResult res;
+            run_sieve(G, req, res, nullptr);
+            ++nsieve;
+            if (res.total) {
+                ++calls;
+                return true;
+            }
+        }
+        ++calls;
+        return false;
+    };
+    struct Count {
+        int64_t *out;
+        int64_t &n;
+        ~Count() {
+            if (out) *out = n;
+        }
+    } count{sieves, nsieve};
+    if (!decide()) return TPM_NOTFOUND;
+    // group testing over the candidates, in halves
+    std::vector<std::pair<size_t, size_t>> todo{{0, cand.size()}};
+    while (!todo.empty()) {
+        auto [a, b] = todo.back();
+        todo.pop_back();
+        if (a >= b) continue;
+        for (size_t i = a; i < b; ++i) mask[(size_t)cand[i]] = 0;
+        if (decide()) continue;  // the group goes
+        for (size_t i = a; i < b; ++i) mask[(size_t)cand[i]] = 1;
+        if (b - a == 1) continue;  // an essential vertex
+        const size_t mid = a + (b - a) / 2;
+        todo.push_back({mid, b});
+        todo.push_back({a, mid});
+    }
+    // ---- temporal DFS among the survivors (host; a handful of vertices)
+    std::vector<int32_t> surv;
+    for (int32_t u = 0; u < G.n; ++u)
+        if (mask[(size_t)u]) surv.push_back(u);
+    struct E {
+        int32_t src, dst, arr, dep;
+        int64_t pos, eid;
+    };
+    std::vector<std::vector<E>> out_edges((size_t)G.n);
+    for (int32_t v : surv) {
+        int32_t ab[2];
+        TPM_HIP(hipMemcpy(ab, G.inptr + v, 2 * sizeof(int32_t), hipMemcpyDeviceToHost));
+        const int64_t len = (int64_t)ab[1] - ab[0];
+        if (len <= 0) continue;
+        std::vector<int32_t> s((size_t)len), a((size_t)len), d((size_t)len), e((size_t)len);
+        TPM_HIP(hipMemcpy(s.data(), G.psrc + ab[0], sizeof(int32_t) * len, hipMemcpyDeviceToHost));
+        TPM_HIP(hipMemcpy(a.data(), G.ptau + ab[0], sizeof(int32_t) * len, hipMemcpyDeviceToHost));
+        TPM_HIP(hipMemcpy(d.data(), (G.pdep ? G.pdep : G.ptau) + ab[0], sizeof(int32_t) * len,
+                          hipMemcpyDeviceToHost));
+        TPM_HIP(hipMemcpy(e.data(), G.peid + ab[0], sizeof(int32_t) * len, hipMemcpyDeviceToHost));
+        for (int64_t i = 0; i < len; ++i)
+            if (mask[(size_t)s[(size_t)i]])
+                out_edges[(size_t)s[(size_t)i]].push_back(
+                    {s[(size_t)i], v, a[(size_t)i], d[(size_t)i], ab[0] + i, e[(size_t)i]});
+    }
+    auto orig = [&](int32_t u) { return G.h_fid.empty() ? u : G.h_fid[(size_t)u]; };
+    std::vector<int32_t> pv;
+    std::vector<int64_t> pp, pe;
+    std::vector<int32_t> used_orig;
+    std::function<bool(int64_t)> dfs = [&](int64_t arr) -> bool {
+        if ((int32_t)pv.size() == k)
+            return verify_path(G, M, k, pv.data(), pp.data());
+        const int32_t w = pv.back();
+        const int64_t dl = G.h_delay.empty() ? 1 : G.h_delay[(size_t)w];
+        for (const E &x : out_edges[(size_t)w]) {
+            if (pv.size() > 1 && !(arr <= (int64_t)x.dep - dl)) continue;
+            const int32_t o = orig(x.dst);
+            if (std::find(used_orig.begin(), used_orig.end(), o) != used_orig.end()) continue;
+            pv.push_back(x.dst);
+            pp.push_back(x.pos);
+            pe.push_back(x.eid);
+            used_orig.push_back(o);
+            if (dfs(x.arr)) return true;
+            pv.pop_back();
+            pp.pop_back();
+            pe.pop_back();
+            used_orig.pop_back();
+        }
+        return false;
+    };
+    for (int32_t u : surv) {
+        pv.assign(1, u);
+        pp.clear();
+        pe.clear();
+        used_orig.assign(1, orig(u));
+        if (dfs(0)) {
+            for (int i = 0; i < k; ++i) path_vertices[i] = orig(pv[(size_t)i]);
+            for (int i = 0; i + 1 < k; ++i) path_edges[i] = pe[(size_t)i];
+            return TPM_OK;
+        }
+    }
+    return TPM_NOTFOUND;  // every group test said YES only by a path the DFS rules out: impossible
 }
 
 static double now_ms_api() {
@@ -562,6 +702,21 @@ tpm_status tpm_decide(const tpm_graph *g, const int32_t *multiset, int32_t k, ui
             }
         }
         return TPM_OK;
+    });
+}
+
+tpm_status tpm_extract_ex(const tpm_graph *g, const int32_t *multiset, int32_t k, uint64_t seed,
+                          int32_t max_reps, int32_t method, int32_t *path_vertices,
+                          int64_t *path_edges, int64_t *sieves) {
+    return guarded([&]() -> tpm_status {
+        TPM_REQUIRE(g && multiset && path_vertices && (k < 2 || path_edges), "NULL argument");
+        TPM_REQUIRE(method == 0 || method == 1, "method must be 0 or 1");
+        DeviceScope ds(g->G.device);
+        if (method == 1 && k >= 2)
+            return extract_selfreduce(g->G, multiset, k, seed, max_reps, path_vertices, path_edges,
+                                      sieves);
+        return extract_path(g->G, multiset, k, seed, max_reps, path_vertices, path_edges, nullptr,
+                            sieves);
     });
 }
 

@@ -29,11 +29,6 @@
 
 #include "tpm_internal.h"
 
-namespace tpm {
-tpm_status extract_path(const Graph &G, const int32_t *M, int32_t k, uint64_t seed,
-                        int32_t max_reps, int32_t *path_vertices, int64_t *path_edges,
-                        hipStream_t st);
-}
 
 using namespace tpm;
 

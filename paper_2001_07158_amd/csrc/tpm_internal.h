@@ -260,6 +260,12 @@ struct SieveResult {
 
 void run_sieve(const Graph &G, const SieveRequest &req, SieveResult &res, hipStream_t stream);
 
+// Witness extraction by localisation-guided self-reduction (tpm_extract); sieves
+// (nullable) receives the number of sieves run.
+tpm_status extract_path(const Graph &G, const int32_t *M, int32_t k, uint64_t seed,
+                        int32_t max_reps, int32_t *path_vertices, int64_t *path_edges,
+                        hipStream_t st, int64_t *sieves = nullptr);
+
 // Consumes the per-position localisation of a sieve (positions [lo, hi), device
 // memory) on the sieve's stream, before the call's final synchronisation; results go
 // to host memory the sink owns (copied asynchronously on st).  Scratch: ws.aux, ws.aux2.

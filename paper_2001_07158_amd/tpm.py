@@ -127,6 +127,8 @@ _sig("tpm_decide", ctypes.c_int32, [_vp, _i32p, ctypes.c_int32, ctypes.c_uint64,
                                    _i32p])
 _sig("tpm_extract", ctypes.c_int32, [_vp, _i32p, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int32,
                                     _i32p, _i64p])
+_sig("tpm_extract_ex", ctypes.c_int32, [_vp, _i32p, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int32,
+                                       ctypes.c_int32, _i32p, _i64p, _i64p])
 _sig("tpm_batch_run", ctypes.c_int32, [_vp, ctypes.c_int32, ctypes.POINTER(tpm_query),
                                       ctypes.POINTER(tpm_result), ctypes.POINTER(tpm_tuning)])
 _sig("tpm_rainbow_decide", ctypes.c_int32, [_vp, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int32,
@@ -146,7 +148,8 @@ EXPORTED = ["tpm_graph_create", "tpm_graph_create_ex", "tpm_graph_destroy", "tpm
             "tpm_graph_retile", "tpm_autotune", "tpm_graph_prune", "tpm_graph_prune_ex",
             "tpm_graph_layer", "tpm_graph_vertex_ids", "tpm_sieve_vertex", "tpm_time_buckets",
             "tpm_optimum_time",
-            "tpm_sieve", "tpm_sieve_ex", "tpm_decide", "tpm_extract", "tpm_batch_run",
+            "tpm_sieve", "tpm_sieve_ex", "tpm_decide", "tpm_extract", "tpm_extract_ex",
+            "tpm_batch_run",
             "tpm_server_create", "tpm_server_submit", "tpm_server_poll", "tpm_server_destroy",
             "tpm_server_stats_get", "tpm_rainbow_decide",
             "tpm_profile_enable", "tpm_profile_read", "tpm_last_error", "tpm_version"]
@@ -265,6 +268,21 @@ def tpm_extract(h, multiset, seed, max_reps=8):
                                  int(max_reps), pv.ctypes.data_as(_i32p), pe.ctypes.data_as(_i64p)),
                 ok=(TPM_OK, TPM_NOTFOUND))
     return rc, pv, pe[: k - 1]
+
+
+def tpm_extract_ex(h, multiset, seed, max_reps=8, method=0):
+    """Returns (status, vertices[k], edges[k-1], sieves run); method 0 = localisation,
+    1 = self-reducibility with temporal DFS."""
+    M = _i32(multiset)
+    k = int(M.shape[0])
+    pv = np.full(k, -1, dtype=np.int32)
+    pe = np.full(max(1, k - 1), -1, dtype=np.int64)
+    ns = ctypes.c_int64(0)
+    rc = _check(_lib.tpm_extract_ex(h, M.ctypes.data_as(_i32p), k, int(seed) & (2**64 - 1),
+                                    int(max_reps), int(method), pv.ctypes.data_as(_i32p),
+                                    pe.ctypes.data_as(_i64p), ctypes.byref(ns)),
+                ok=(TPM_OK, TPM_NOTFOUND))
+    return rc, pv, pe[: k - 1], int(ns.value)
 
 
 def _make_queries(queries):
@@ -466,6 +484,9 @@ class Graph:
 
     def extract(self, multiset, seed, max_reps=8):
         return tpm_extract(self.h, multiset, seed, max_reps)
+
+    def extract_ex(self, multiset, seed, max_reps=8, method=0):
+        return tpm_extract_ex(self.h, multiset, seed, max_reps, method)
 
     def batch(self, queries, chunk=0, use_graph=False, prune=False):
         return tpm_batch_run(self.h, queries, chunk, use_graph, prune)

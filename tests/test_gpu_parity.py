@@ -266,3 +266,38 @@ def test_k10_full_size_sampled_points(tpm):
     idx = oracle.Index(g)
     want = idx.eval(M, seed, pts.astype(np.uint32), nthreads=nthreads)
     assert np.array_equal(pp[pts], want), (pts, pp[pts], want)
+
+
+def test_selfreduce_extraction_against_brute_force(tpm):
+    """The paper's self-reducibility extraction (group testing + temporal DFS) finds
+    a valid path exactly when one exists, also on layered (VC) and delayed graphs."""
+    rng = np.random.default_rng(151)
+    yes = no = 0
+    for it in range(40):
+        g = G.random_tiny_graph(rng, n_max=12, m_max=40, t_max=6, q_max=3)
+        k = int(rng.integers(2, 5))
+        M = [int(c) for c in rng.integers(-1 if it % 5 == 4 else 0, g.num_colors, k)]
+        exists = pyref.has_matching_path(g, M)
+        Gd = tpm.Graph.from_temporal(g)
+        rc, verts, edges, ns = Gd.extract_ex(M, 200 + it, max_reps=6, method=1)
+        if exists:
+            yes += 1
+            assert rc == tpm.TPM_OK, it
+            assert pyref.check_path(g, M, verts, edges)
+        else:
+            no += 1
+            assert rc == tpm.TPM_NOTFOUND
+        rc2, _, _, ns2 = Gd.extract_ex(M, 200 + it, max_reps=6, method=0)
+        assert rc2 == rc
+        Gd.close()
+    assert yes > 5 and no > 5
+    g = G.random_tiny_graph(np.random.default_rng(7), n_max=12, m_max=40, t_max=6, q_max=3)
+    tr = np.ones(g.m, np.int32)
+    dl = np.zeros(g.n, np.int32)
+    for M in ([0, 1], [0, 1, 2], [1, 1, 0]):
+        Gd = tpm.Graph(g.n, g.src, g.dst, g.tau, g.color, g.num_colors, transit=tr, delay=dl)
+        rc, verts, edges, _ = Gd.extract_ex(M, 5, max_reps=6, method=1)
+        assert (rc == tpm.TPM_OK) == pyref.has_matching_path(g, M, tr, dl)
+        if rc == tpm.TPM_OK:
+            assert pyref.check_path(g, M, verts, edges, tr, dl)
+        Gd.close()

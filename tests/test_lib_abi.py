@@ -108,3 +108,12 @@ def test_bad_delay_options_rejected_on_host(case):
     with pytest.raises(tpm.TpmError) as ei:
         tpm.tpm_graph_create(3, src, dst, tau, np.zeros(3, np.int32), 1, **kw)
     assert ei.value.code == tpm.TPM_EINVAL
+
+
+def test_library_resolves_its_own_symbols(lib):
+    """Every symbol of the library's own namespace is defined in the library (a
+    declaration mismatch between translation units would leave one undefined)."""
+    import subprocess
+    out = subprocess.run(["nm", "-D", "--undefined-only", LIB], capture_output=True, text=True,
+                         check=True).stdout
+    assert "_ZN3tpm" not in out, [l for l in out.splitlines() if "_ZN3tpm" in l]
