@@ -301,3 +301,71 @@ def test_selfreduce_extraction_against_brute_force(tpm):
         if rc == tpm.TPM_OK:
             assert pyref.check_path(g, M, verts, edges, tr, dl)
         Gd.close()
+
+
+def test_device_pointer_input(tpm):
+    """Graph creation from device arrays (TPM_DEVICE_PTRS) gives the same index and
+    results as from host arrays; bad device input is rejected on the device."""
+    import torch
+    g = G.chung_lu_graph(2000, 30000, 2.5, 40, 4, 161)
+    dev = [torch.from_numpy(np.ascontiguousarray(a, dtype=np.int32)).cuda()
+           for a in (g.src, g.dst, g.tau, g.color)]
+    torch.cuda.synchronize()
+    h = tpm.tpm_graph_create(g.n, *[(t.data_ptr(), t.numel()) for t in dev], g.num_colors,
+                             flags=tpm.TPM_DEVICE_PTRS)
+    M = [0, 1, 2, 3, 0, 1]
+    pp, tot = tpm.tpm_sieve(h, M, 5)
+    assert np.array_equal(pp, oracle.sieve(g, M, 5))
+    host = tpm.Graph.from_temporal(g)
+    a, b = tpm.tpm_graph_stats_get(h), host.stats()
+    for key in ("rows", "tiles", "slots", "gathers", "segments", "max_in_degree", "tmax"):
+        assert a[key] == b[key], key
+    host.close()
+    tpm.tpm_graph_destroy(h)
+    bad = dev[2].clone()
+    bad[7] = 0  # timestamp < 1
+    with pytest.raises(tpm.TpmError) as ei:
+        tpm.tpm_graph_create(g.n, (dev[0].data_ptr(), g.m), (dev[1].data_ptr(), g.m),
+                             (bad.data_ptr(), g.m), (dev[3].data_ptr(), g.n), g.num_colors,
+                             flags=tpm.TPM_DEVICE_PTRS)
+    assert ei.value.code == tpm.TPM_EINVAL
+
+
+def test_concurrent_sieves_on_streams(tpm):
+    """Sieves on one graph from several host threads, each on its own stream (the
+    graph is immutable; each call leases its own workspace)."""
+    import threading
+    import torch
+    g = G.chung_lu_graph(3000, 50000, 2.5, 50, 4, 162)
+    Gd = tpm.Graph.from_temporal(g)
+    qs = [([0, 1, 2, 3, 0, 1, 2][: 3 + i % 5], 10 + i) for i in range(12)]
+    want = [oracle.sieve(g, M, s) for M, s in qs]
+    got = [None] * len(qs)
+    errs = []
+
+    def work(j):
+        try:
+            torch.cuda.set_device(0)
+            st = torch.cuda.Stream()
+            for i in range(j, len(qs), 3):
+                M, s = qs[i]
+                got[i] = Gd.sieve(M, s, stream=st)[0]
+        except Exception as e:  # reported below
+            errs.append(e)
+
+    th = [threading.Thread(target=work, args=(j,)) for j in range(3)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    assert not errs, errs
+    for i in range(len(qs)):
+        assert np.array_equal(got[i], want[i]), i
+    Gd.close()
+
+
+def test_k16_all_points_tiny(tpm):
+    """The largest query size: 65536 sieve points in 64 chunks of 1024."""
+    g = G.uniform_graph(60, 500, 30, 4, 163)
+    M = [int(c) for c in np.random.default_rng(1).integers(0, 4, 16)]
+    _check(tpm, g, M, 77, label="k=16")
