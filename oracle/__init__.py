@@ -17,6 +17,7 @@ Two independent layers live here:
 from __future__ import annotations
 
 import ctypes
+import dataclasses
 import os
 
 import numpy as np
@@ -64,6 +65,13 @@ def lib():
                                   _i32p, _i32p, ctypes.c_int32, _i32p, ctypes.c_int32,
                                   ctypes.c_uint64, _u8p, _u32p, ctypes.c_int64, _u8p, _u8p,
                                   ctypes.c_int]
+        L.or_sieve_em.argtypes = [ctypes.c_int32, ctypes.c_int64, _i32p, _i32p, _i32p, _i32p,
+                                  _i32p, _u8p, _i32p, ctypes.c_int32, _i32p, ctypes.c_int32,
+                                  ctypes.c_uint64, _u8p, _u32p, ctypes.c_int64, _u8p, _u8p,
+                                  ctypes.c_int]
+        L.or_static_sieve.argtypes = [ctypes.c_int32, ctypes.c_int64, _i32p, _i32p, _i32p,
+                                      ctypes.c_int32, _i32p, ctypes.c_int32, ctypes.c_uint64,
+                                      _u8p, _u8p, ctypes.c_int]
         L.or_sieve_vc.argtypes = [ctypes.c_int32, ctypes.c_int64, _i32p, _i32p, _i32p, _i32p,
                                   _i32p, _i32p, ctypes.c_int32, _i32p, ctypes.c_int32,
                                   ctypes.c_uint64, _u32p, ctypes.c_int64, _u8p, _u8p, ctypes.c_int]
@@ -124,13 +132,15 @@ def zvals(g, M, seed: int, mask=None) -> np.ndarray:
 
 
 def sieve(g, M, seed: int, points=None, mask=None, loc: bool = False, nthreads: int = 0,
-          transit=None, delay=None):
+          transit=None, delay=None, emask=None):
     """P(A) for the given sieve points (default: all 2^k).  Returns the per-point
     array, or (per_point, per_edge_localisation) when loc=True (localisation is
     XOR-ed over the given points).  transit (per edge) and delay (per vertex) select
     the variant with transition and delay times (section "Path motif problem with
     delays"): an edge reaches its head at tau + transit, and a walk leaves a vertex w
-    at time tau only if it arrived by tau - delay(w); defaults 0 and 1."""
+    at time tau only if it arrived by tau - delay(w); defaults 0 and 1.  emask (per
+    edge, nullable): edges with emask 0 are not in the graph (the others keep their
+    index, hence their y)."""
     M = _c32(M)
     k = len(M)
     if points is None:
@@ -142,14 +152,49 @@ def sieve(g, M, seed: int, points=None, mask=None, loc: bool = False, nthreads: 
     mk = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8)
     tr = None if transit is None else _c32(transit)
     dl = None if delay is None else _c32(delay)
-    rc = lib().or_sieve_ex(g.n, g.m, _p(src, _i32p), _p(dst, _i32p), _p(tau, _i32p),
-                           _p(tr, _i32p), _p(dl, _i32p), _p(color, _i32p), g.num_colors,
+    em = None if emask is None else np.ascontiguousarray(emask, dtype=np.uint8)
+    if em is not None and em.shape[0] != g.m:
+        raise ValueError("emask needs one entry per edge")
+    rc = lib().or_sieve_em(g.n, g.m, _p(src, _i32p), _p(dst, _i32p), _p(tau, _i32p),
+                           _p(tr, _i32p), _p(dl, _i32p), _p(em, _u8p), _p(color, _i32p), g.num_colors,
                            _p(M, _i32p), k, seed & 0xFFFFFFFFFFFFFFFF, _p(mk, _u8p),
                            _p(points, _u32p), points.shape[0], _p(out, _u8p), _p(lc, _u8p),
                            nthreads)
     if rc:
         raise RuntimeError(f"oracle failed ({rc})")
     return (out, lc) if loc else out
+
+
+def sd_instance(g, s: int, d: int):
+    """(s,d)-COLORFUL-PATH reduction (section "Solving COLORFUL-PATH and
+    (s,d)-COLORFUL-PATH"): g with colour q on s and q + 1 on d (q + 2 colours), and the
+    edge mask that removes s's in-edges and d's out-edges, so that a matching path of
+    the multiset M + {q, q + 1} starts at s and ends at d.  Returns (graph, emask) for
+    `sieve(..., emask=emask)`."""
+    if not (0 <= s < g.n and 0 <= d < g.n) or s == d:
+        raise ValueError("bad (s, d)")
+    color = np.array(g.color, dtype=np.int32, copy=True)
+    q = int(g.num_colors)
+    color[s], color[d] = q, q + 1
+    emask = ((np.asarray(g.dst) != s) & (np.asarray(g.src) != d)).astype(np.uint8)
+    return dataclasses.replace(g, color=color, num_colors=q + 2), emask
+
+
+def static_sieve(g, M, seed: int, mask=None, nthreads: int = 0) -> np.ndarray:
+    """Static vertex-localised sieve (preprocessing step (ii), Eq. (1)): per vertex u,
+    S_u = sum over the 2^k points and the k walk positions l of F_{u,l} G_{u,l} on the
+    static instance (one arc per ordered pair with a temporal edge, loops dropped, y
+    keyed by the pair's smallest input edge id, tag 4).  Nonzero only at vertices of a
+    static path whose colours match M."""
+    M = _c32(M)
+    S = np.empty(g.n, dtype=np.uint8)
+    mk = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8)
+    rc = lib().or_static_sieve(g.n, g.m, _p(_c32(g.src), _i32p), _p(_c32(g.dst), _i32p),
+                               _p(_c32(g.color), _i32p), g.num_colors, _p(M, _i32p), len(M),
+                               seed & 0xFFFFFFFFFFFFFFFF, _p(mk, _u8p), _p(S, _u8p), nthreads)
+    if rc:
+        raise RuntimeError(f"oracle failed ({rc})")
+    return S
 
 
 def vc_sieve(g, C, seed: int, points=None, loc: bool = False, nthreads: int = 0, transit=None,

@@ -101,7 +101,7 @@ def fp(seed: int, tag: int, a: int, b: int) -> int:
     return mix64((seed & MASK64) ^ mix64(key)) & 0xFF
 
 
-TAG_Y, TAG_V, TAG_W = 1, 2, 3
+TAG_Y, TAG_V, TAG_W, TAG_STATIC = 1, 2, 3, 4
 
 
 def slots(M, q: int):
@@ -222,20 +222,109 @@ def has_vc_path(g, C) -> bool:
     return False
 
 
-def brute_per_point(g, M, seed: int, mask=None, transit=None, delay=None) -> np.ndarray:
+def brute_per_point(g, M, seed: int, mask=None, transit=None, delay=None,
+                    emask=None) -> np.ndarray:
     """P(A) for every A as the sum over temporal walks of their monomials,
-    x_{w_1} y_{e_1,1} x_{w_2} ... y_{e_{k-1},k-1} x_{w_k}, evaluated at z^A."""
+    x_{w_1} y_{e_1,1} x_{w_2} ... y_{e_{k-1},k-1} x_{w_k}, evaluated at z^A.
+    emask (per edge): walks through an edge with emask 0 are left out."""
     k = len(M)
     T = mul_table()
     X = subset_values(zvals(g, M, seed, mask))
     acc = np.zeros(1 << k, dtype=np.uint8)
     for verts, edges in temporal_walks(g, k, transit, delay):
+        if emask is not None and not all(emask[e] for e in edges):
+            continue
         v = X[verts[0]].copy()
         for l, e in enumerate(edges, start=1):
             v = T[v, fp(seed, TAG_Y, l, e)]
             v = T[v, X[verts[l]]]
         acc ^= v
     return acc
+
+
+def sd_paths(g, s: int, d: int, M):
+    """(s,d)-COLORFUL-PATH by its definition: the temporal paths s -> ... -> d with
+    len(M) + 2 vertices whose internal vertices' colours are the multiset M."""
+    k = len(M) + 2
+    res = []
+    for verts, edges in temporal_walks(g, k):
+        if verts[0] == s and verts[-1] == d and len(set(verts)) == k and \
+                colours_match([int(g.color[u]) for u in verts[1:-1]], M):
+            res.append((verts, edges))
+    return res
+
+
+def paths_total(g, paths, M, seed: int) -> int:
+    """Sum of y(P) det(Z_P) over the given paths (Z from the multiset M on g)."""
+    z = zvals(g, M, seed)
+    tot = 0
+    for verts, edges in paths:
+        y = 1
+        for l, e in enumerate(edges, start=1):
+            y = gmul(y, fp(seed, TAG_Y, l, e))
+        tot ^= gmul(y, det([z[u] for u in verts]))
+    return tot
+
+
+def static_arcs(g) -> dict:
+    """The static instance: one arc (v, u) per ordered pair joined by a temporal edge,
+    v != u, mapped to the smallest input edge id among those edges."""
+    arcs = {}
+    for e in range(g.m):
+        v, u = int(g.src[e]), int(g.dst[e])
+        if v != u and (v, u) not in arcs:
+            arcs[(v, u)] = e
+    return arcs
+
+
+def static_walks(g, k: int):
+    """All walks with k vertices along the static arcs (vertex tuples)."""
+    arcs = static_arcs(g)
+    out = [[] for _ in range(g.n)]
+    for (v, u) in arcs:
+        out[v].append(u)
+    walks = [(u,) for u in range(g.n)]
+    for _ in range(k - 1):
+        walks = [w + (u,) for w in walks for u in out[w[-1]]]
+    return walks, arcs
+
+
+def brute_static_vertex(g, M, seed: int):
+    """Per vertex u: the sum over static paths P with k = len(M) vertices through u
+    of y(P) det(Z_P), y(P) = prod_l fp(seed, 4, l, arc id of the l-th arc)."""
+    k = len(M)
+    z = zvals(g, M, seed)
+    walks, arcs = static_walks(g, k)
+    S = np.zeros(g.n, dtype=np.uint8)
+    for w in walks:
+        if len(set(w)) != k:
+            continue
+        y = 1
+        for l in range(1, k):
+            y = gmul(y, fp(seed, TAG_STATIC, l, arcs[(w[l - 1], w[l])]))
+        v = gmul(y, det([z[u] for u in w]))
+        for u in w:
+            S[u] ^= v
+    return S
+
+
+def brute_static_visits(g, M, seed: int):
+    """Per vertex u: sum over points A and over static walks W with k vertices of
+    (number of visits of W to u) * (the monomial of W at z^A)."""
+    k = len(M)
+    T = mul_table()
+    X = subset_values(zvals(g, M, seed))
+    walks, arcs = static_walks(g, k)
+    S = np.zeros(g.n, dtype=np.uint8)
+    for w in walks:
+        v = X[w[0]].copy()
+        for l in range(1, k):
+            v = T[v, fp(seed, TAG_STATIC, l, arcs[(w[l - 1], w[l])])]
+            v = T[v, X[w[l]]]
+        tot = int(np.bitwise_xor.reduce(v))
+        for u in w:
+            S[u] ^= tot
+    return S
 
 
 def brute_paths_total(g, M, seed: int, mask=None) -> int:

@@ -188,6 +188,8 @@ typedef struct {
     int64_t *gpos;  /* [m]: position in `order` of the last in-edge e' of src_e whose
                        arrival is <= tau_e - delay(src_e) (delay 1: arrival < tau_e),
                        or -1 if there is none */
+    const uint8_t *emask; /* [m] or NULL (borrowed): emask[e] == 0 removes edge e from
+                             the graph (it keeps its index, so y of the others is as is) */
 } or_index;
 
 static const int32_t *g_cmp_tau;
@@ -365,6 +367,8 @@ static int or_eval_impl(const or_index *ix, const uint8_t *z, int32_t k, uint64_
                     prev[e] = OR_MUL[OR_MUL[x[dst[e]]][Y[e]]][x[src[e]]];
                     if (vc && (color[src[e]] != vc[0] || color[dst[e]] != vc[1]))
                         prev[e] = 0;
+                    if (ix->emask && !ix->emask[e])
+                        prev[e] = 0;
                 }
                 for (int l = 3; l <= k; l++) {
                     /* running sums along each in-list: P_{v,l-1,tau} */
@@ -380,6 +384,8 @@ static int or_eval_impl(const or_index *ix, const uint8_t *z, int32_t k, uint64_
                         uint8_t h = ix->gpos[e] >= 0 ? pre[ix->gpos[e]] : 0;
                         cur[e] = OR_MUL[OR_MUL[x[dst[e]]][Yl[e]]][h];
                         if (vc && (color[src[e]] != vc[l - 2] || color[dst[e]] != vc[l - 1]))
+                            cur[e] = 0;
+                        if (ix->emask && !ix->emask[e])
                             cur[e] = 0;
                     }
                     uint8_t *t = prev;
@@ -425,10 +431,28 @@ int or_sieve(int32_t n, int64_t m, const int32_t *src, const int32_t *dst, const
                        npoints, out, loc, nthreads);
 }
 
+int or_sieve_em(int32_t n, int64_t m, const int32_t *src, const int32_t *dst, const int32_t *tau,
+                const int32_t *transit, const int32_t *delay, const uint8_t *emask,
+                const int32_t *color, int32_t q, const int32_t *M, int32_t k, uint64_t seed,
+                const uint8_t *mask, const uint32_t *points, int64_t npoints, uint8_t *out,
+                uint8_t *loc, int nthreads);
+
 int or_sieve_ex(int32_t n, int64_t m, const int32_t *src, const int32_t *dst, const int32_t *tau,
                 const int32_t *transit, const int32_t *delay, const int32_t *color, int32_t q,
                 const int32_t *M, int32_t k, uint64_t seed, const uint8_t *mask,
                 const uint32_t *points, int64_t npoints, uint8_t *out, uint8_t *loc, int nthreads)
+{
+    return or_sieve_em(n, m, src, dst, tau, transit, delay, NULL, color, q, M, k, seed, mask,
+                       points, npoints, out, loc, nthreads);
+}
+
+/* As or_sieve_ex on the graph without the edges e with emask[e] == 0 (the others keep
+ * their indices, hence their y). */
+int or_sieve_em(int32_t n, int64_t m, const int32_t *src, const int32_t *dst, const int32_t *tau,
+                const int32_t *transit, const int32_t *delay, const uint8_t *emask,
+                const int32_t *color, int32_t q, const int32_t *M, int32_t k, uint64_t seed,
+                const uint8_t *mask, const uint32_t *points, int64_t npoints, uint8_t *out,
+                uint8_t *loc, int nthreads)
 {
     or_init();
     if (n < 1 || m < 0 || k < 1 || k > 16)
@@ -446,6 +470,7 @@ int or_sieve_ex(int32_t n, int64_t m, const int32_t *src, const int32_t *dst, co
         free(z);
         return -2;
     }
+    ix->emask = emask;
     rc = or_eval(ix, z, k, seed, points, npoints, out, loc, nthreads);
     or_index_free(ix);
     free(z);
@@ -570,4 +595,162 @@ int or_sieve_vc(int32_t n, int64_t m, const int32_t *src, const int32_t *dst, co
     or_index_free(ix);
     free(z);
     return rc;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Static vertex-localised sieve (section "Preprocessing", step (ii), with the */
+/* static generating polynomial Eq. (1)).                                      */
+/*                                                                             */
+/* The static instance has one arc (v -> u) per ordered pair with at least one */
+/* temporal edge v -> u, v != u (a path never uses a loop); the arc's variables */
+/* y_{vu,l} are keyed by its smallest input edge id r:                          */
+/*     y_{vu,l} = fp(seed, 4, l, r),  l = 1..k-1,                              */
+/* and x_u is the temporal sieve's (same substitution, same seed).              */
+/* Eq. (1) read forward gives F_{u,1} = x_u and                                */
+/*     F_{u,l} = x_u * sum_{arcs v -> u} y_{vu,l-1} F_{v,l-1};                 */
+/* the same walks read backward give G_{u,k} = 1 and                           */
+/*     G_{u,l} = sum_{arcs u -> w} y_{uw,l} x_w G_{w,l+1},                     */
+/* so F_{u,l} G_{u,l} sums the monomials of the k-vertex walks whose l-th       */
+/* vertex is u.  S_u = sum over points A and over l of F_{u,l} G_{u,l} is the   */
+/* sieve of the walks through u counted once per visit: a path through u counts */
+/* once, every other walk cancels, so S_u != 0 certifies a static path through  */
+/* u whose colours match M (the property the section asks of the vertex-        */
+/* localised sieve: nonzero at vertices that are part of a match).             */
+/* S[n] receives S_u.  Returns 0, or -1 / -2 on bad input / no memory.          */
+/* ------------------------------------------------------------------------- */
+static const int32_t *g_arc_src, *g_arc_dst;
+static int cmp_arc(const void *pa, const void *pb)
+{
+    int64_t a = *(const int64_t *)pa, b = *(const int64_t *)pb;
+    if (g_arc_src[a] != g_arc_src[b])
+        return g_arc_src[a] < g_arc_src[b] ? -1 : 1;
+    if (g_arc_dst[a] != g_arc_dst[b])
+        return g_arc_dst[a] < g_arc_dst[b] ? -1 : 1;
+    return a < b ? -1 : (a > b);
+}
+
+int or_static_sieve(int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                    const int32_t *color, int32_t q, const int32_t *M, int32_t k, uint64_t seed,
+                    const uint8_t *mask, uint8_t *S, int nthreads)
+{
+    or_init();
+    if (n < 1 || m < 0 || k < 1 || k > 16)
+        return -1;
+    uint8_t *z = malloc((size_t)n * (size_t)k);
+    if (!z)
+        return -2;
+    int rc = or_z(n, color, q, M, k, seed, mask, z);
+    if (rc) {
+        free(z);
+        return rc;
+    }
+    /* arcs: edges sorted by (src, dst, id); the first of each pair is its
+       representative */
+    int64_t *ord = malloc(sizeof(int64_t) * (size_t)(m ? m : 1));
+    int32_t *as = malloc(sizeof(int32_t) * (size_t)(m ? m : 1));
+    int32_t *ad = malloc(sizeof(int32_t) * (size_t)(m ? m : 1));
+    int64_t *ar = malloc(sizeof(int64_t) * (size_t)(m ? m : 1));
+    if (!ord || !as || !ad || !ar) {
+        free(z); free(ord); free(as); free(ad); free(ar);
+        return -2;
+    }
+    for (int64_t e = 0; e < m; e++)
+        ord[e] = e;
+    g_arc_src = src;
+    g_arc_dst = dst;
+    qsort(ord, (size_t)m, sizeof(int64_t), cmp_arc);
+    int64_t na = 0;
+    for (int64_t i = 0; i < m; i++) {
+        int64_t e = ord[i];
+        if (src[e] == dst[e])
+            continue;
+        if (na > 0 && as[na - 1] == src[e] && ad[na - 1] == dst[e])
+            continue;
+        as[na] = src[e];
+        ad[na] = dst[e];
+        ar[na] = e;
+        na++;
+    }
+    free(ord);
+    /* y_{arc,l}, level-major */
+    uint8_t *Y = malloc((size_t)(k > 1 ? k - 1 : 1) * (size_t)(na ? na : 1));
+    if (!Y) {
+        free(z); free(as); free(ad); free(ar);
+        return -2;
+    }
+    for (int l = 1; l <= k - 1; l++)
+        for (int64_t a = 0; a < na; a++)
+            Y[(size_t)(l - 1) * na + a] = or_fp(seed, 4, (uint32_t)l, (uint32_t)ar[a]);
+    memset(S, 0, (size_t)n);
+    int err = 0;
+    if (nthreads <= 0)
+        nthreads = omp_get_max_threads();
+    const int64_t npoints = (int64_t)1 << k;
+#pragma omp parallel num_threads(nthreads)
+    {
+        uint8_t *x = malloc((size_t)n);
+        uint8_t *F = malloc((size_t)k * (size_t)n); /* F[l-1][u] */
+        uint8_t *Gc = malloc((size_t)n), *Gn = malloc((size_t)n);
+        uint8_t *myS = calloc((size_t)n, 1);
+        int ok = x && F && Gc && Gn && myS;
+        if (!ok) {
+#pragma omp atomic write
+            err = -2;
+        }
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t A = 0; A < npoints; A++) {
+            if (!ok)
+                continue;
+            for (int32_t u = 0; u < n; u++) {
+                uint8_t s = 0;
+                for (int j = 0; j < k; j++)
+                    if ((A >> j) & 1)
+                        s ^= z[(size_t)u * k + j];
+                x[u] = s;
+            }
+            memcpy(F, x, (size_t)n);
+            for (int l = 2; l <= k; l++) {
+                uint8_t *Fl = F + (size_t)(l - 1) * n;
+                const uint8_t *Fp = F + (size_t)(l - 2) * n;
+                const uint8_t *Yl = Y + (size_t)(l - 2) * na; /* y_{.,l-1} */
+                memset(Fl, 0, (size_t)n);
+                for (int64_t a = 0; a < na; a++)
+                    Fl[ad[a]] ^= OR_MUL[Yl[a]][Fp[as[a]]];
+                for (int32_t u = 0; u < n; u++)
+                    Fl[u] = OR_MUL[x[u]][Fl[u]];
+            }
+            /* l = k: G = 1 */
+            for (int32_t u = 0; u < n; u++) {
+                Gc[u] = 1;
+                myS[u] ^= F[(size_t)(k - 1) * n + u];
+            }
+            for (int l = k - 1; l >= 1; l--) {
+                const uint8_t *Yl = Y + (size_t)(l - 1) * na; /* y_{.,l} */
+                memset(Gn, 0, (size_t)n);
+                for (int64_t a = 0; a < na; a++)
+                    Gn[as[a]] ^= OR_MUL[Yl[a]][OR_MUL[x[ad[a]]][Gc[ad[a]]]];
+                for (int32_t u = 0; u < n; u++)
+                    myS[u] ^= OR_MUL[F[(size_t)(l - 1) * n + u]][Gn[u]];
+                uint8_t *t = Gc;
+                Gc = Gn;
+                Gn = t;
+            }
+        }
+        if (ok) {
+#pragma omp critical
+            for (int32_t u = 0; u < n; u++)
+                S[u] ^= myS[u];
+        }
+        free(x);
+        free(F);
+        free(Gc);
+        free(Gn);
+        free(myS);
+    }
+    free(Y);
+    free(z);
+    free(as);
+    free(ad);
+    free(ar);
+    return err;
 }

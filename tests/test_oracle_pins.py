@@ -484,3 +484,104 @@ def test_path_checker():
                 bad[0] = (bad[0] + 1) % (g.num_colors + 1)
                 assert not pyref.check_path(g, bad, verts, edges)
     assert n_ok > 50
+
+
+def test_edge_mask_matches_walk_enumeration():
+    """Removing edges by mask (they keep their indices, so every other y stays) equals
+    the walk sum without them; the localisation of a removed edge is 0."""
+    rng = np.random.default_rng(91)
+    for it in range(40):
+        g = G.random_tiny_graph(rng, n_max=9, m_max=30, t_max=6)
+        k = int(rng.integers(2, 5))
+        M = [int(c) for c in rng.integers(0, g.num_colors, k)]
+        em = (rng.random(g.m) < 0.7).astype(np.uint8)
+        pp, lc = oracle.sieve(g, M, 70 + it, emask=em, loc=True)
+        assert np.array_equal(pp, pyref.brute_per_point(g, M, 70 + it, emask=em)), it
+        assert not lc[em == 0].any()
+        assert np.array_equal(oracle.sieve(g, M, 70 + it, emask=np.ones(g.m, np.uint8)),
+                              oracle.sieve(g, M, 70 + it)), it
+
+
+def test_sd_instance_sieves_exactly_the_sd_paths():
+    """(s,d)-COLORFUL-PATH: on the recoloured instance without s's in-edges and d's
+    out-edges, the sieve with M + {q, q+1} is the sum over the temporal paths
+    s -> ... -> d whose internal colours are M (brute force), so it is 0 when there is
+    none and is nonzero for most seeds when there is one."""
+    rng = np.random.default_rng(93)
+    with_paths = detected = 0
+    for it in range(80):
+        g = G.random_tiny_graph(rng, n_max=9, m_max=36, t_max=7)
+        if g.n < 3:
+            continue
+        k = int(rng.integers(1, 4))
+        M = [int(c) for c in rng.integers(0, g.num_colors, k)]
+        s, d = (int(x) for x in rng.choice(g.n, 2, replace=False))
+        walks = [w for w, _ in pyref.temporal_walks(g, k + 2) if len(set(w)) == k + 2]
+        if walks and it % 3:  # most instances: (s, d, M) of an existing path
+            w = walks[int(rng.integers(0, len(walks)))]
+            s, d, M = w[0], w[-1], [int(g.color[u]) for u in w[1:-1]]
+        gs, em = oracle.sd_instance(g, s, d)
+        Mp = M + [g.num_colors, g.num_colors + 1]
+        paths = pyref.sd_paths(g, s, d, M)
+        hit = False
+        for r in range(3):
+            seed = 1000 * it + r
+            tot = int(np.bitwise_xor.reduce(oracle.sieve(gs, Mp, seed, emask=em)))
+            assert tot == pyref.paths_total(gs, paths, Mp, seed), (it, r)
+            hit |= tot != 0
+        if paths:
+            with_paths += 1
+            detected += hit
+        else:
+            assert not hit
+    assert with_paths >= 10 and detected >= 0.8 * with_paths, (with_paths, detected)
+
+
+def test_static_sieve_is_paths_through_u():
+    """Static vertex-localised sieve (Eq. (1) forward, the same walks backward): S_u
+    equals the sum over static paths through u of y(P) det(Z_P), and the sum over
+    walks of visits to u times their monomials, on random tiny graphs."""
+    rng = np.random.default_rng(97)
+    nonzero = 0
+    for it in range(60):
+        g = G.random_tiny_graph(rng, n_max=8, m_max=26, t_max=5)
+        k = int(rng.integers(1, 5))
+        M = [int(c) for c in rng.integers(0, g.num_colors, k)]
+        S = oracle.static_sieve(g, M, 300 + it)
+        assert np.array_equal(S, pyref.brute_static_vertex(g, M, 300 + it)), it
+        assert np.array_equal(S, pyref.brute_static_visits(g, M, 300 + it)), it
+        nonzero += int(S.any())
+    assert nonzero > 10
+
+
+def test_static_prefilter_keeps_every_temporal_path():
+    """A temporal path is a static path, so its vertices have S_u != 0 for most seeds;
+    whenever the kept set (S_u != 0 for one of 3 seeds) holds every vertex of every
+    temporal match, the temporal sieve total on the kept subgraph is the full one's
+    for every seed (the other walks cancel either way)."""
+    rng = np.random.default_rng(99)
+    covered = 0
+    for it in range(60):
+        g = G.random_tiny_graph(rng, n_max=9, m_max=30, t_max=6)
+        k = int(rng.integers(2, 5))
+        M = [int(c) for c in rng.integers(0, g.num_colors, k)]
+        keep = np.zeros(g.n, dtype=bool)
+        for r in range(3):
+            keep |= oracle.static_sieve(g, M, 500 + 7 * it + r) != 0
+        on_path = set()
+        for verts, _ in pyref.temporal_walks(g, k):
+            if len(set(verts)) == k and pyref.colours_match([int(g.color[u]) for u in verts], M):
+                on_path |= set(verts)
+        static_on_path = set()
+        for w in pyref.static_walks(g, k)[0]:
+            if len(set(w)) == k and pyref.colours_match([int(g.color[u]) for u in w], M):
+                static_on_path |= set(w)
+        assert on_path <= static_on_path
+        assert set(np.nonzero(keep)[0].tolist()) <= static_on_path
+        if on_path <= set(np.nonzero(keep)[0].tolist()):
+            covered += 1
+            em = (keep[g.src] & keep[g.dst]).astype(np.uint8)
+            for s2 in range(3):
+                a = int(np.bitwise_xor.reduce(oracle.sieve(g, M, s2, emask=em)))
+                assert a == int(np.bitwise_xor.reduce(oracle.sieve(g, M, s2))), (it, s2)
+    assert covered > 40
