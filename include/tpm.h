@@ -198,6 +198,17 @@ tpm_status tpm_graph_prune_ex(const tpm_graph *g, const int32_t *colors, int32_t
  * Errors: TPM_EINVAL (k outside 1..16, colour out of range), TPM_ENOMEM, TPM_EDEVICE. */
 tpm_status tpm_graph_layer(const tpm_graph *g, const int32_t *tuple, int32_t k, tpm_graph **out);
 
+/* (s,d)-COLORFUL-PATH (section "Solving COLORFUL-PATH and (s,d)-COLORFUL-PATH"): the
+ * instance in which s gets the new colour num_colors and d the new colour
+ * num_colors + 1 (the result has num_colors + 2 colours), s loses its in-edges and d
+ * its out-edges.  Sieving it with M' = M + {num_colors, num_colors + 1} (k + 2 entries)
+ * decides whether a temporal path s -> ... -> d exists whose k internal vertices have
+ * the colours M: the new colours put s and d on the path exactly once, and the removed
+ * edges make them its first and last vertex.  Every other vertex, edge, timestamp,
+ * transition / delay time and input edge id is g's; tpm_extract on it returns such a
+ * path.  Errors: TPM_EINVAL (s or d out of range, s == d), TPM_ENOMEM, TPM_EDEVICE. */
+tpm_status tpm_graph_sd(const tpm_graph *g, int32_t s, int32_t d, tpm_graph **out);
+
 /* ids[i] = the vertex of the original graph that vertex i stands for (n entries:
  * identity, except for graphs made by tpm_graph_layer). */
 tpm_status tpm_graph_vertex_ids(const tpm_graph *g, int32_t *ids);
@@ -281,6 +292,32 @@ tpm_status tpm_time_buckets(const tpm_graph *g, const int32_t *multiset, int32_t
  * only if every seed misses the optimal paths (one-sided error, as decide). */
 tpm_status tpm_optimum_time(const tpm_graph *g, const int32_t *multiset, int32_t k, uint64_t seed,
                             int32_t reps, int32_t *t_out);
+
+/* Static vertex-localised sieve (section "Preprocessing", step (ii), on the static
+ * generating polynomial Eq. (1)).  The static instance has one arc v -> u per ordered
+ * pair of vertices joined by a temporal edge (v != u), whose variables y_{vu,l} are
+ * keyed by the smallest input edge id among those edges; x_u is the temporal
+ * sieve's.  s[u] (host, n bytes) = sum over the 2^k points and the k walk positions l
+ * of F_{u,l} G_{u,l}, where F runs Eq. (1) forward from F_{u,1} = x_u and G runs the
+ * same walks backward from G_{u,k} = 1: the sieve of the k-vertex walks through u,
+ * counted once per visit.  Paths through u count once and all other walks cancel,
+ * so s[u] != 0 certifies a static path through u whose colours match the multiset
+ * (and every temporal match is a static one).  1 <= k <= 16.
+ * Errors: TPM_EINVAL, TPM_ENOMEM, TPM_EDEVICE. */
+tpm_status tpm_static_sieve(const tpm_graph *g, const int32_t *multiset, int32_t k, uint64_t seed,
+                            uint8_t *s);
+
+/* Preprocessing steps (i) and (ii) together: the subgraph of g on the vertices u with
+ * s[u] != 0 for some of `reps` seeds seed_r = seed + r * 0x9E3779B97F4A7C15
+ * (tpm_static_sieve; a vertex of a colour outside the multiset always has s[u] = 0).
+ * Vertex ids, colours, timestamps and input edge ids are g's.  When every vertex of
+ * every temporal match is kept, the sieve total of the multiset on the result equals
+ * g's for every seed; a vertex of a match is dropped only if all `reps` static sieves
+ * miss it (probability at most ((2k - 1) / 256)^reps per vertex, the one-sided error
+ * of the sieve).  Errors: TPM_EINVAL (bad multiset, reps < 1), TPM_ENOMEM,
+ * TPM_EDEVICE. */
+tpm_status tpm_graph_prune_static(const tpm_graph *g, const int32_t *multiset, int32_t k,
+                                  uint64_t seed, int32_t reps, tpm_graph **out);
 
 /* ---------------------------------------------------------------- batch --- */
 typedef struct {

@@ -547,6 +547,25 @@ tpm_status tpm_graph_layer(const tpm_graph *g, const int32_t *tuple, int32_t k, 
     });
 }
 
+tpm_status tpm_graph_sd(const tpm_graph *g, int32_t s, int32_t d, tpm_graph **out) {
+    return guarded([&]() -> tpm_status {
+        TPM_REQUIRE(g && out, "NULL argument");
+        *out = nullptr;
+        DeviceScope ds(g->G.device);
+        auto *h = new tpm_graph();
+        try {
+            sd_graph(g->G, s, d, h->G);
+            h->G.pool = new_workspace_pool();
+            h->G.apool = new_arena_pool();
+        } catch (...) {
+            delete h;
+            throw;
+        }
+        *out = h;
+        return TPM_OK;
+    });
+}
+
 tpm_status tpm_graph_vertex_ids(const tpm_graph *g, int32_t *ids) {
     return guarded([&]() -> tpm_status {
         TPM_REQUIRE(g && ids, "NULL argument");

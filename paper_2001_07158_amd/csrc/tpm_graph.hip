@@ -146,13 +146,21 @@ __global__ void k_vkeep(int32_t n, const int32_t *color, const uint8_t *keepc, u
     if (u < n) vkeep[u] = keepc[color[u]];
 }
 
+__global__ void k_vand(int32_t n, const uint8_t *a, uint8_t *b) {
+    int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u < n) b[u] = (a[u] != 0 && b[u] != 0) ? 1 : 0;
+}
+
 // keep[p] = 1 when both endpoints of the edge at position p are kept and, with a
 // timestamp set ts[0..nts) (sorted), its timestamp is in the set
+// (cut_in: a vertex whose in-edges go, cut_out: one whose out-edges go; -1 for none)
 __global__ void k_keep(int64_t m, const int32_t *psrc, const int32_t *pdst, const uint8_t *vkeep,
-                       const int32_t *ptime, const int32_t *ts, int32_t nts, int32_t *keep) {
+                       const int32_t *ptime, const int32_t *ts, int32_t nts, int32_t cut_in,
+                       int32_t cut_out, int32_t *keep) {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= m) return;
-    bool k = vkeep[psrc[p]] && vkeep[pdst[p]];
+    const int32_t s = psrc[p], d = pdst[p];
+    bool k = vkeep[s] && vkeep[d] && d != cut_in && s != cut_out;
     if (k && ts) {
         const int32_t t = ptime[p];
         int32_t a = 0, b = nts;
@@ -803,7 +811,8 @@ void build_graph(Graph &G, int32_t n, int64_t m, const int32_t *src, const int32
 }
 
 void prune_graph(const Graph &P, const uint8_t *keep_color, const int32_t *times, int32_t ntimes,
-                 Graph &G, GraphArena *arena) {
+                 Graph &G, GraphArena *arena, int32_t cut_in, int32_t cut_out,
+                 const uint8_t *vkeep_in) {
     TPM_HIP(hipSetDevice(P.device));
     G.device = P.device;
     G.num_cu = P.num_cu;
@@ -835,6 +844,8 @@ void prune_graph(const Graph &P, const uint8_t *keep_color, const int32_t *times
                 }
                 uint8_t *vkeep = tmp.get<uint8_t>(A_VKEEP, P.n);
                 k_vkeep<<<grid_for(P.n), 256, 0, st>>>(P.n, P.color, keepc, vkeep);
+                if (vkeep_in)
+                    k_vand<<<grid_for(P.n), 256, 0, st>>>(P.n, vkeep_in, vkeep);
                 int32_t *ts = nullptr;
                 if (times) {
                     ts = tmp.get<int32_t>(A_TSET, ntimes);
@@ -844,7 +855,8 @@ void prune_graph(const Graph &P, const uint8_t *keep_color, const int32_t *times
                 at = tmp.get<int32_t>(A_AT, P.m);
                 // timestamps of the edges as given (departures when transit times exist)
                 k_keep<<<grid_for(P.m), 256, 0, st>>>(P.m, P.psrc, P.pdst, vkeep,
-                                                       P.pdep ? P.pdep : P.ptau, ts, ntimes, keep);
+                                                       P.pdep ? P.pdep : P.ptau, ts, ntimes,
+                                                       cut_in, cut_out, keep);
                 size_t sbytes = 0;
                 TPM_HIP(rocprim::exclusive_scan(nullptr, sbytes, keep, at, 0, (size_t)P.m,
                                                 rocprim::plus<int32_t>(), st));
@@ -885,6 +897,24 @@ void prune_graph(const Graph &P, const uint8_t *keep_color, const int32_t *times
         }
         finish_index(G, acct, G.ptau, arena == nullptr);
         G.device_bytes = acct;
+    } catch (...) {
+        free_graph(G);
+        throw;
+    }
+}
+
+void sd_graph(const Graph &P, int32_t s, int32_t d, Graph &G) {
+    TPM_REQUIRE(s >= 0 && s < P.n && d >= 0 && d < P.n, "vertex out of range");
+    TPM_REQUIRE(s != d, "s and d must differ");
+    TPM_REQUIRE(P.q <= (int32_t)0x7FFFFFFD, "too many colours");
+    prune_graph(P, nullptr, nullptr, 0, G, nullptr, s, d);
+    try {
+        G.q = P.q + 2;
+        const int32_t cs = P.q, cd = P.q + 1;
+        TPM_HIP(hipMemcpy(G.color + s, &cs, sizeof(int32_t), hipMemcpyHostToDevice));
+        TPM_HIP(hipMemcpy(G.color + d, &cd, sizeof(int32_t), hipMemcpyHostToDevice));
+        G.h_color[(size_t)s] = cs;
+        G.h_color[(size_t)d] = cd;
     } catch (...) {
         free_graph(G);
         throw;
@@ -1045,6 +1075,182 @@ void retile_graph(Graph &G, int32_t T) {
     G.nslots = nslots;
     G.tile_edges = T;
     G.device_bytes += acct - old_bytes;
+}
+
+
+// ------------------------------------------------------------------ static instance
+namespace {
+
+// live[p] = 1 for a position whose edge joins two live vertices and is not a loop
+__global__ void k_arc_flag(int64_t m, const int32_t *psrc, const int32_t *pdst,
+                           const uint8_t *vlive, int32_t *flag) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < m) {
+        const int32_t s = psrc[p], d = pdst[p];
+        flag[p] = (s != d && vlive[s] && vlive[d]) ? 1 : 0;
+    }
+}
+
+// key (head << bt | tail) and input id of each flagged position, compacted
+__global__ void k_arc_keys(int64_t m, const int32_t *psrc, const int32_t *pdst, const int32_t *peid,
+                           const int32_t *flag, const int32_t *at, int bt, uint64_t *keys,
+                           int32_t *ids) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < m && flag[p]) {
+        const int32_t q = at[p];
+        keys[q] = ((uint64_t)(uint32_t)pdst[p] << bt) | (uint64_t)(uint32_t)psrc[p];
+        ids[q] = peid[p];
+    }
+}
+
+__global__ void k_arc_mark(int64_t na, const uint64_t *keys, int bt, int32_t *on) {
+    int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a < na) {
+        const uint64_t key = keys[a];
+        on[key >> bt] = 1;
+        on[key & ((uint64_t(1) << bt) - 1)] = 1;
+    }
+}
+
+__global__ void k_vid(int32_t n, const int32_t *on, const int32_t *cid, int32_t *vid) {
+    int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u < n && on[u]) vid[cid[u]] = (int32_t)u;
+}
+
+// by-head list in compact ids, and the swapped keys for the by-tail order
+__global__ void k_arc_in(int64_t na, const uint64_t *keys, const int32_t *ids, const int32_t *cid,
+                         int bt, int32_t *seg, int32_t *gat, int32_t *key, uint64_t *rkeys,
+                         int32_t *ridx) {
+    int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a < na) {
+        const uint64_t k = keys[a];
+        const uint64_t head = k >> bt, tail = k & ((uint64_t(1) << bt) - 1);
+        seg[a] = cid[head];
+        gat[a] = cid[tail];
+        key[a] = ids[a];
+        rkeys[a] = (tail << bt) | head;
+        ridx[a] = (int32_t)a;
+    }
+}
+
+__global__ void k_arc_out(int64_t na, const uint64_t *rkeys, const int32_t *ridx, const int32_t *cid,
+                          const int32_t *in_key, int bt, int32_t *seg, int32_t *gat, int32_t *key) {
+    int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a < na) {
+        const uint64_t k = rkeys[a];
+        seg[a] = cid[k >> bt];
+        gat[a] = cid[k & ((uint64_t(1) << bt) - 1)];
+        key[a] = in_key[ridx[a]];
+    }
+}
+
+}  // namespace
+
+void free_static(StaticGraph &S) {
+    for (int32_t **q : {&S.vid, &S.in_seg, &S.in_gat, &S.in_key, &S.out_seg, &S.out_gat, &S.out_key}) {
+        if (*q) (void)hipFree(*q);
+        *q = nullptr;
+    }
+    S.n = 0;
+    S.m = 0;
+}
+
+void build_static(const Graph &G, const uint8_t *vlive, StaticGraph &S) {
+    TPM_HIP(hipSetDevice(G.device));
+    hipStream_t st = nullptr;
+    const int bt = std::max(1, bits_for((uint64_t)std::max<int32_t>(1, G.n - 1)));
+    int64_t acct = 0;
+    try {
+        Temps tmp(nullptr);
+        int64_t na = 0;
+        uint64_t *keys = nullptr;
+        int32_t *ids = nullptr;
+        if (G.m) {
+            int32_t *flag = tmp.get<int32_t>(0, G.m), *at = tmp.get<int32_t>(0, G.m);
+            k_arc_flag<<<grid_for(G.m), 256, 0, st>>>(G.m, G.psrc, G.pdst, vlive, flag);
+            size_t sb = 0;
+            TPM_HIP(rocprim::exclusive_scan(nullptr, sb, flag, at, 0, (size_t)G.m,
+                                            rocprim::plus<int32_t>(), st));
+            void *scratch = tmp.raw(0, sb);
+            TPM_HIP(rocprim::exclusive_scan(scratch, sb, flag, at, 0, (size_t)G.m,
+                                            rocprim::plus<int32_t>(), st));
+            int32_t h[2];
+            TPM_HIP(hipMemcpy(&h[0], at + (G.m - 1), sizeof(int32_t), hipMemcpyDeviceToHost));
+            TPM_HIP(hipMemcpy(&h[1], flag + (G.m - 1), sizeof(int32_t), hipMemcpyDeviceToHost));
+            const int64_t ne = (int64_t)h[0] + h[1];
+            if (ne) {
+                uint64_t *k0 = tmp.get<uint64_t>(0, ne), *k1 = tmp.get<uint64_t>(0, ne);
+                int32_t *v0 = tmp.get<int32_t>(0, ne), *v1 = tmp.get<int32_t>(0, ne);
+                k_arc_keys<<<grid_for(G.m), 256, 0, st>>>(G.m, G.psrc, G.pdst, G.peid, flag, at,
+                                                          bt, k0, v0);
+                size_t rb = 0;
+                TPM_HIP(rocprim::radix_sort_pairs(nullptr, rb, k0, k1, v0, v1, (size_t)ne, 0,
+                                                  (unsigned)(2 * bt), st));
+                void *rs = tmp.raw(0, rb);
+                TPM_HIP(rocprim::radix_sort_pairs(rs, rb, k0, k1, v0, v1, (size_t)ne, 0,
+                                                  (unsigned)(2 * bt), st));
+                // one arc per (head, tail): the smallest input id of its edges
+                int32_t *cnt = tmp.get<int32_t>(0, 1);
+                size_t ub = 0;
+                TPM_HIP(rocprim::reduce_by_key(nullptr, ub, k1, v1, (size_t)ne, k0, v0, cnt,
+                                               rocprim::minimum<int32_t>(),
+                                               rocprim::equal_to<uint64_t>(), st));
+                void *us = tmp.raw(0, ub);
+                TPM_HIP(rocprim::reduce_by_key(us, ub, k1, v1, (size_t)ne, k0, v0, cnt,
+                                               rocprim::minimum<int32_t>(),
+                                               rocprim::equal_to<uint64_t>(), st));
+                int32_t c = 0;
+                TPM_HIP(hipMemcpy(&c, cnt, sizeof(int32_t), hipMemcpyDeviceToHost));
+                na = c;
+                keys = k0;
+                ids = v0;
+            }
+        }
+        S.m = na;
+        if (na == 0) {
+            S.n = 0;
+            TPM_HIP(hipDeviceSynchronize());
+            return;
+        }
+        // compact ids of the vertices on an arc
+        int32_t *on = tmp.get<int32_t>(0, G.n), *cid = tmp.get<int32_t>(0, G.n);
+        TPM_HIP(hipMemsetAsync(on, 0, sizeof(int32_t) * (size_t)G.n, st));
+        k_arc_mark<<<grid_for(na), 256, 0, st>>>(na, keys, bt, on);
+        size_t sb = 0;
+        TPM_HIP(rocprim::exclusive_scan(nullptr, sb, on, cid, 0, (size_t)G.n,
+                                        rocprim::plus<int32_t>(), st));
+        void *scratch = tmp.raw(0, sb);
+        TPM_HIP(rocprim::exclusive_scan(scratch, sb, on, cid, 0, (size_t)G.n,
+                                        rocprim::plus<int32_t>(), st));
+        int32_t h[2];
+        TPM_HIP(hipMemcpy(&h[0], cid + (G.n - 1), sizeof(int32_t), hipMemcpyDeviceToHost));
+        TPM_HIP(hipMemcpy(&h[1], on + (G.n - 1), sizeof(int32_t), hipMemcpyDeviceToHost));
+        S.n = h[0] + h[1];
+        S.vid = dalloc<int32_t>(S.n, acct);
+        k_vid<<<grid_for(G.n), 256, 0, st>>>(G.n, on, cid, S.vid);
+        S.in_seg = dalloc<int32_t>(na, acct);
+        S.in_gat = dalloc<int32_t>(na, acct);
+        S.in_key = dalloc<int32_t>(na, acct);
+        S.out_seg = dalloc<int32_t>(na, acct);
+        S.out_gat = dalloc<int32_t>(na, acct);
+        S.out_key = dalloc<int32_t>(na, acct);
+        uint64_t *r0 = tmp.get<uint64_t>(0, na), *r1 = tmp.get<uint64_t>(0, na);
+        int32_t *i0 = tmp.get<int32_t>(0, na), *i1 = tmp.get<int32_t>(0, na);
+        k_arc_in<<<grid_for(na), 256, 0, st>>>(na, keys, ids, cid, bt, S.in_seg, S.in_gat, S.in_key,
+                                               r0, i0);
+        size_t rb = 0;
+        TPM_HIP(rocprim::radix_sort_pairs(nullptr, rb, r0, r1, i0, i1, (size_t)na, 0,
+                                          (unsigned)(2 * bt), st));
+        void *rs = tmp.raw(0, rb);
+        TPM_HIP(rocprim::radix_sort_pairs(rs, rb, r0, r1, i0, i1, (size_t)na, 0,
+                                          (unsigned)(2 * bt), st));
+        k_arc_out<<<grid_for(na), 256, 0, st>>>(na, r1, i1, cid, S.in_key, bt, S.out_seg,
+                                                S.out_gat, S.out_key);
+        TPM_HIP(hipDeviceSynchronize());
+    } catch (...) {
+        free_static(S);
+        throw;
+    }
 }
 
 }  // namespace tpm

@@ -226,8 +226,14 @@ void retile_graph(Graph &G, int32_t T);
 // buffers (reused by the next graph built there; G must be freed before that).
 // keep_color nullable (all colours kept); times (host, sorted, distinct, nullable):
 // keep only edges whose timestamp (departure) is one of them.
+// cut_in / cut_out (-1: none): a vertex whose in-edges / out-edges are dropped.
+// vkeep_in (device [P.n], nullable): keep only edges between vertices it marks.
 void prune_graph(const Graph &P, const uint8_t *keep_color, const int32_t *times, int32_t ntimes,
-                 Graph &G, GraphArena *arena = nullptr);
+                 Graph &G, GraphArena *arena = nullptr, int32_t cut_in = -1, int32_t cut_out = -1,
+                 const uint8_t *vkeep_in = nullptr);
+// (s,d)-COLORFUL-PATH: G = P with colour q on s and q + 1 on d (q + 2 colours), s's
+// in-edges and d's out-edges removed.
+void sd_graph(const Graph &P, int32_t s, int32_t d, Graph &G);
 // VC-PATH-MOTIF: G = the layered graph of P for the colour tuple[0..k): vertex (u, l)
 // for each layer l with c(u) = tuple[l-1] (fingerprints keyed by u), edges
 // (v, l-1) -> (u, l) for P's edges v -> u with matching colours.
@@ -289,6 +295,32 @@ void run_sieve_sink(const Graph &G, const SieveRequest &req, SieveResult &res, L
 // Per-edge localisation over all edges, indexed by input edge id.
 void run_sieve_loc_all(const Graph &G, const SieveRequest &req, SieveResult &res,
                        uint8_t *loc_by_edge, hipStream_t stream);
+
+// ------------------------------------------------------------------ static instance
+// The static instance of a temporal graph restricted to its live vertices (section
+// "Preprocessing", step (ii)): one arc v -> u per ordered pair of live vertices with a
+// temporal edge v -> u, v != u, keyed by the smallest input edge id among those
+// edges.  Vertices on an arc get compact ids 0..n-1.  Arcs are listed twice: by
+// (head, tail) for the forward pass of Eq. (1) and by (tail, head) for the backward
+// pass; in each list, seg is the vertex whose row a position adds to, gat the vertex
+// whose row it reads.
+struct StaticGraph {
+    int32_t n = 0;
+    int64_t m = 0;
+    int32_t *vid = nullptr;                                    // [n] vertex of compact id
+    int32_t *in_seg = nullptr, *in_gat = nullptr, *in_key = nullptr;    // [m] by head
+    int32_t *out_seg = nullptr, *out_gat = nullptr, *out_key = nullptr; // [m] by tail
+};
+// vlive: device [G.n], nonzero for live vertices.
+void build_static(const Graph &G, const uint8_t *vlive, StaticGraph &S);
+void free_static(StaticGraph &S);
+// XOR-accumulates S_u (the static vertex-localised sieve: the sum over the 2^k points
+// and the k walk positions l of F_{u,l} G_{u,l}) into sv[u] (device, G.n bytes) for
+// the vertices of S.  x values are the temporal sieve's (same substitution and seed);
+// arc variables y_{arc,l} = fp(seed, 4, l, arc key).  budget: bytes the level rows
+// may take (rows get narrower when needed).
+void static_sieve(const Graph &G, const StaticGraph &S, const int32_t *M, int32_t k, uint64_t seed,
+                  uint8_t *sv, size_t budget, hipStream_t st);
 
 // ------------------------------------------------------------------ multi-query steps
 // Per-lane role in a multi-query step (device table, one entry per lane).

@@ -111,6 +111,47 @@ struct TimeSink : LocSink {
 
 void check_k(int32_t k) { TPM_REQUIRE(k >= 2 && k <= 16, "k must be in [2, 16]"); }
 
+__global__ void k_live(int32_t n, const int32_t *color, const uint8_t *keepc, uint8_t *live) {
+    int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u < n) live[u] = keepc[color[u]];
+}
+
+__global__ void k_or_nonzero(int32_t n, const uint8_t *s, uint8_t *keep) {
+    int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u < n && s[u]) keep[u] = 1;
+}
+
+// live vertices of a multiset: a colour of it, or every vertex with a wildcard entry
+void live_vertices(const Graph &G, const int32_t *M, int32_t k, uint8_t *live) {
+    TPM_REQUIRE(M != nullptr, "multiset must not be NULL");
+    TPM_REQUIRE(k >= 1 && k <= 16, "k must be in [1, 16]");
+    std::vector<uint8_t> keepc((size_t)G.q, 0);
+    bool wild = false;
+    for (int i = 0; i < k; ++i) {
+        TPM_REQUIRE(M[i] >= -1 && M[i] < G.q, "multiset colour out of range");
+        if (M[i] < 0) wild = true;
+        else keepc[(size_t)M[i]] = 1;
+    }
+    if (wild) std::fill(keepc.begin(), keepc.end(), (uint8_t)1);
+    DBuf kc;
+    kc.alloc(std::max<size_t>(1, keepc.size()), nullptr);
+    TPM_HIP(hipMemcpy(kc.p, keepc.data(), keepc.size(), hipMemcpyHostToDevice));
+    k_live<<<grid_of(G.n), 256>>>(G.n, G.color, kc.as<uint8_t>(), live);
+    TPM_HIP(hipDeviceSynchronize());
+}
+
+// room for the static sieve's rows: half of the free device memory
+size_t static_budget() {
+    size_t freeb = 0, totalb = 0;
+    if (hipMemGetInfo(&freeb, &totalb) != hipSuccess) return size_t(1) << 30;
+    return freeb / 2;
+}
+
+struct StaticHolder {
+    StaticGraph S;
+    ~StaticHolder() { free_static(S); }
+};
+
 }  // namespace
 }  // namespace tpm
 
@@ -192,6 +233,64 @@ tpm_status tpm_optimum_time(const tpm_graph *g, const int32_t *multiset, int32_t
                 if (*t_out < 0 || t < *t_out) *t_out = t;
             }
         }
+        return TPM_OK;
+    });
+}
+
+tpm_status tpm_static_sieve(const tpm_graph *g, const int32_t *multiset, int32_t k, uint64_t seed,
+                            uint8_t *s) {
+    return guarded_call([&]() -> tpm_status {
+        TPM_REQUIRE(g && s, "NULL argument");
+        DeviceGuard dg(g->G.device);
+        const Graph &G = g->G;
+        DBuf live, sv;
+        live.alloc((size_t)std::max<int32_t>(1, G.n), nullptr);
+        live_vertices(G, multiset, k, live.as<uint8_t>());
+        StaticHolder h;
+        if (k >= 2) build_static(G, live.as<uint8_t>(), h.S);
+        sv.alloc((size_t)std::max<int32_t>(1, G.n), nullptr);
+        TPM_HIP(hipMemset(sv.p, 0, (size_t)G.n));
+        static_sieve(G, h.S, multiset, k, seed, sv.as<uint8_t>(), static_budget(), nullptr);
+        TPM_HIP(hipMemcpy(s, sv.p, (size_t)G.n, hipMemcpyDeviceToHost));
+        return TPM_OK;
+    });
+}
+
+tpm_status tpm_graph_prune_static(const tpm_graph *g, const int32_t *multiset, int32_t k,
+                                  uint64_t seed, int32_t reps, tpm_graph **out) {
+    return guarded_call([&]() -> tpm_status {
+        TPM_REQUIRE(g && out, "NULL argument");
+        TPM_REQUIRE(reps >= 1, "reps must be >= 1");
+        *out = nullptr;
+        DeviceGuard dg(g->G.device);
+        const Graph &G = g->G;
+        DBuf live, sv, keep;
+        live.alloc((size_t)std::max<int32_t>(1, G.n), nullptr);
+        live_vertices(G, multiset, k, live.as<uint8_t>());
+        sv.alloc((size_t)std::max<int32_t>(1, G.n), nullptr);
+        keep.alloc((size_t)std::max<int32_t>(1, G.n), nullptr);
+        TPM_HIP(hipMemset(keep.p, 0, (size_t)G.n));
+        {
+            StaticHolder h;
+            if (k >= 2) build_static(G, live.as<uint8_t>(), h.S);
+            for (int32_t r = 0; r < reps; ++r) {
+                TPM_HIP(hipMemset(sv.p, 0, (size_t)G.n));
+                static_sieve(G, h.S, multiset, k, seed + (uint64_t)r * 0x9E3779B97F4A7C15ull,
+                             sv.as<uint8_t>(), static_budget(), nullptr);
+                k_or_nonzero<<<grid_of(G.n), 256>>>(G.n, sv.as<uint8_t>(), keep.as<uint8_t>());
+            }
+            TPM_HIP(hipDeviceSynchronize());
+        }
+        auto *hnd = new tpm_graph();
+        try {
+            prune_graph(G, nullptr, nullptr, 0, hnd->G, nullptr, -1, -1, keep.as<uint8_t>());
+            hnd->G.pool = new_workspace_pool();
+            hnd->G.apool = new_arena_pool();
+        } catch (...) {
+            delete hnd;
+            throw;
+        }
+        *out = hnd;
         return TPM_OK;
     });
 }

@@ -1110,6 +1110,185 @@ __global__ void __launch_bounds__(1024) k_step(StepParams P) {
     }
 }
 
+// ---------------------------------------------------------------------------------
+// Static instance (preprocessing step (ii)): each vertex of the instance has a row of
+// rowb sieve points (lanes * 4 W bytes), stored in compact vertex order.
+// ---------------------------------------------------------------------------------
+constexpr int kStaticTile = 256;  // positions per tile of k_sgather
+
+// Product of two dwords of field elements, byte by byte, through the LDS tables.
+__device__ __forceinline__ uint32_t gmul4(const uint8_t *lds, uint32_t lanebits, uint32_t a,
+                                          uint32_t b, uint32_t xbase, uint32_t zc) {
+    uint32_t s0 = min(lds32(lds, log_addr<0>(lanebits, a)) + lds32(lds, log_addr<0>(lanebits, b)) + xbase, zc);
+    uint32_t s1 = min(lds32(lds, log_addr<1>(lanebits, a)) + lds32(lds, log_addr<1>(lanebits, b)) + xbase, zc);
+    uint32_t s2 = min(lds32(lds, log_addr<2>(lanebits, a)) + lds32(lds, log_addr<2>(lanebits, b)) + xbase, zc);
+    uint32_t s3 = min(lds32(lds, log_addr<3>(lanebits, a)) + lds32(lds, log_addr<3>(lanebits, b)) + xbase, zc);
+    return (uint32_t)lds[s0] | ((uint32_t)lds[s1] << 8) | ((uint32_t)lds[s2] << 16) |
+           ((uint32_t)lds[s3] << 24);
+}
+
+__device__ __forceinline__ void load_lds_image(uint8_t *lds, const uint8_t *image) {
+    const uint4 *src = (const uint4 *)image;
+    uint4 *dst = (uint4 *)lds;
+    for (int i = threadIdx.x; i < kLdsBytes / 16; i += blockDim.x) dst[i] = src[i];
+    __syncthreads();
+}
+
+// sum[seg] = sum over the positions p of seg's list of y_{key[p], ylevel} * rows[gat[p]]
+// (the sum of Eq. (1) before the factor x; ylevel is the walk position of the arc).
+// One wave per tile of kStaticTile positions.  A list that a tile boundary cuts adds
+// its parts with atomic XOR into a row the caller cleared; a list inside one tile is
+// stored.
+template <int W>
+__global__ void __launch_bounds__(1024) k_sgather(int64_t m, const int32_t *seg, const int32_t *gat,
+                                                  const int32_t *key, const uint8_t *rows,
+                                                  uint8_t *sum, int32_t rowb, int32_t lanes,
+                                                  uint64_t seed, uint32_t ylevel,
+                                                  const uint8_t *lds_image) {
+    __shared__ __attribute__((aligned(16))) uint8_t lds[kLdsBytes];
+    load_lds_image(lds, lds_image);
+    const int lane = threadIdx.x & 63;
+    const bool act = lane < lanes;
+    const uint32_t lanebits = (uint32_t)(lane & 31) << 2;
+    const uint32_t xbase = (uint32_t)kExpBase + lanebits;
+    const uint32_t zc = (uint32_t)kExpBase + ((uint32_t)kClampRow << 7) + lanebits;
+    uint32_t lx7[4 * W];
+#pragma unroll
+    for (int i = 0; i < 4 * W; ++i) lx7[i] = xbase;  // x = 1
+    const int64_t ntiles = (m + kStaticTile - 1) / kStaticTile;
+    const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x >> 6);
+    auto flush = [&](int32_t d, const uint32_t (&acc)[W], bool shared) {
+        if (!act) return;
+        if (shared) {
+            uint32_t *row = (uint32_t *)(sum + (int64_t)d * rowb + (int64_t)lane * (4 * W));
+#pragma unroll
+            for (int w = 0; w < W; ++w)
+                if (acc[w]) atomicXor(row + w, acc[w]);
+        } else {
+            store_row<W>(sum, d, rowb, lane, acc);
+        }
+    };
+    for (int64_t t = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); t < ntiles;
+         t += nwaves) {
+        const int64_t p0 = t * kStaticTile, p1 = min(p0 + (int64_t)kStaticTile, m);
+        const int32_t sfirst = seg[p0], slast = seg[p1 - 1];
+        const bool open_l = p0 > 0 && seg[p0 - 1] == sfirst;
+        const bool open_r = p1 < m && seg[p1] == slast;
+        uint32_t acc[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) acc[w] = 0;
+        int32_t cur = sfirst;
+        bool shared = open_l;
+        for (int64_t wb = p0; wb < p1; wb += 64) {
+            const int nb = (int)min<int64_t>(64, p1 - wb);
+            int32_t ms = -1, mg = -1;
+            uint32_t ly = kZero7;
+            if (lane < nb) {
+                ms = seg[wb + lane];
+                mg = gat[wb + lane];
+                const uint32_t y = fp8(seed, 4u, ylevel, (uint32_t)key[wb + lane]);
+                ly = lds32(lds, (y << 8) | lanebits);
+            }
+            for (int i0 = 0; i0 < nb; i0 += kU) {
+                uint32_t g[kU][W];
+#pragma unroll
+                for (int u = 0; u < kU; ++u) {
+                    const int i = min(i0 + u, 63);
+                    const int32_t r = __builtin_amdgcn_readlane(mg, i);
+                    if (i0 + u < nb && r >= 0 && act) {
+                        load_row<W>(rows, r, rowb, lane, g[u]);
+                    } else {
+#pragma unroll
+                        for (int w = 0; w < W; ++w) g[u][w] = 0;
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < kU; ++u) {
+                    if (i0 + u >= nb) break;
+                    const int i = i0 + u;
+                    const int32_t d = __builtin_amdgcn_readlane(ms, i);
+                    if (d != cur) {
+                        flush(cur, acc, shared);
+#pragma unroll
+                        for (int w = 0; w < W; ++w) acc[w] = 0;
+                        cur = d;
+                        shared = false;
+                    }
+                    const uint32_t ly7 = __builtin_amdgcn_readlane(ly, i);
+#pragma unroll
+                    for (int w = 0; w < W; ++w) acc[w] ^= mul4(lds, lanebits, g[u][w], &lx7[4 * w], ly7, zc);
+                }
+            }
+        }
+        flush(cur, acc, shared || open_r);
+    }
+}
+
+// Per vertex u of the instance (one wave per row): prod = x_u * g_u with g_u = sum[u]
+// (1 when sum is null); out[u] = prod (out nullable); sv[vid[u]] ^= the XOR over the
+// row's points of prod (with_prod) and of fin[u] * g_u (fin nullable).
+template <int W>
+__global__ void __launch_bounds__(1024) k_svertex(int32_t n, const uint8_t *sum, const uint8_t *x,
+                                                  const uint8_t *fin, uint8_t *out, int with_prod,
+                                                  const int32_t *vid, uint8_t *sv, int32_t rowb,
+                                                  int32_t lanes, const uint8_t *lds_image) {
+    __shared__ __attribute__((aligned(16))) uint8_t lds[kLdsBytes];
+    load_lds_image(lds, lds_image);
+    const int lane = threadIdx.x & 63;
+    const bool act = lane < lanes;
+    const uint32_t lanebits = (uint32_t)(lane & 31) << 2;
+    const uint32_t xbase = (uint32_t)kExpBase + lanebits;
+    const uint32_t zc = (uint32_t)kExpBase + ((uint32_t)kClampRow << 7) + lanebits;
+    const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t u = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); u < n; u += nwaves) {
+        uint32_t r = 0;
+        if (act) {
+            uint32_t xv[W], gv[W], pv[W];
+            load_row<W>(x, u, rowb, lane, xv);
+            if (sum) {
+                load_row<W>(sum, u, rowb, lane, gv);
+#pragma unroll
+                for (int w = 0; w < W; ++w) pv[w] = gmul4(lds, lanebits, xv[w], gv[w], xbase, zc);
+            } else {
+#pragma unroll
+                for (int w = 0; w < W; ++w) {
+                    gv[w] = 0x01010101u;
+                    pv[w] = xv[w];
+                }
+            }
+            if (out) store_row<W>(out, u, rowb, lane, pv);
+            if (with_prod) {
+#pragma unroll
+                for (int w = 0; w < W; ++w) r ^= pv[w];
+            }
+            if (fin) {
+                uint32_t fv[W];
+                load_row<W>(fin, u, rowb, lane, fv);
+#pragma unroll
+                for (int w = 0; w < W; ++w) r ^= gmul4(lds, lanebits, fv[w], gv[w], xbase, zc);
+            }
+        }
+        r ^= r >> 16;
+        r ^= r >> 8;
+        r &= 0xFFu;
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) r ^= __shfl_xor(r, off);
+        if (lane == 0 && r) sv[vid[u]] ^= (uint8_t)r;
+    }
+}
+
+// zs[i] = z[vid[i]] (16-byte rows)
+__global__ void k_zgather(int32_t n, const int32_t *vid, const uint8_t *z, uint8_t *zs) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) ((uint4 *)zs)[i] = ((const uint4 *)z)[vid[i]];
+}
+
+// k = 1: sv[u] ^= x_u at the point {0} = z_{u,0}
+__global__ void k_single_v(int32_t n, const uint8_t *z, uint8_t *sv) {
+    int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u < n) sv[u] ^= z[u * 16];
+}
+
 QuerySlots make_slots(const Graph &G, const int32_t *M, int32_t k) {
     TPM_REQUIRE(M != nullptr, "multiset must not be NULL");
     TPM_REQUIRE(k >= 1 && k <= 16, "k must be in [1, 16]");
@@ -1343,6 +1522,103 @@ void run_sieve_loc_all(const Graph &G, const SieveRequest &req, SieveResult &res
         TPM_HIP(hipMemcpy(peid.data(), G.peid, sizeof(int32_t) * G.m, hipMemcpyDeviceToHost));
         for (int64_t p = 0; p < G.m; ++p) loc_by_edge[peid[p]] = bypos[p];
     }
+}
+
+// ---------------------------------------------------------------- static instance
+namespace {
+unsigned static_grid(const Graph &G, int64_t waves) {
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(G.num_cu, (waves + 15) / 16));
+}
+}  // namespace
+
+void static_sieve(const Graph &G, const StaticGraph &S, const int32_t *M, int32_t k, uint64_t seed,
+                  uint8_t *sv, size_t budget, hipStream_t st) {
+    QuerySlots qs = make_slots(G, M, k);
+    TPM_HIP(hipSetDevice(G.device));
+    DBuf z;
+    z.alloc((size_t)std::max<int32_t>(1, G.n) * 16, st);
+    k_z<<<grid_for(G.n), 256, 0, st>>>(G.n, k, G.color, G.fid, qs, nullptr, seed, z.as<uint8_t>());
+    if (k == 1) {  // one-vertex paths: S_u = sum over A of x_u^A = z_{u,0}
+        k_single_v<<<grid_for(G.n), 256, 0, st>>>(G.n, z.as<uint8_t>(), sv);
+        TPM_HIP(hipStreamSynchronize(st));
+        return;
+    }
+    if (S.n == 0 || S.m == 0) {
+        TPM_HIP(hipStreamSynchronize(st));
+        return;
+    }
+    const int64_t npts = int64_t(1) << k;
+    int64_t C = std::min<int64_t>(std::max<int64_t>(npts, 16), 1024);
+    // rows: x, the sum, two backward rows and the forward rows F_2 .. F_{k-1}
+    const int64_t nrows = (int64_t)k + 2;
+    while (C > 16 && (double)nrows * S.n * C > (double)budget) C >>= 1;
+    const int W = C >= 1024 ? 4 : (C >= 512 ? 2 : 1);
+    const int lanes = (int)(C / (4 * W));
+    const int64_t valid = std::min<int64_t>(npts, C);
+    const size_t rowbytes = (size_t)S.n * (size_t)C;
+    DBuf zs, X, sum, H0, H1, F;
+    zs.alloc((size_t)S.n * 16, st);
+    X.alloc(rowbytes, st);
+    sum.alloc(rowbytes, st);
+    H0.alloc(rowbytes, st);
+    H1.alloc(rowbytes, st);
+    F.alloc(rowbytes * (size_t)std::max(1, k - 2), st);
+    k_zgather<<<grid_for(S.n), 256, 0, st>>>(S.n, S.vid, z.as<uint8_t>(), zs.as<uint8_t>());
+    auto Frow = [&](int l) { return F.as<uint8_t>() + rowbytes * (size_t)(l - 2); };  // l = 2..k-1
+    const uint8_t *lds_image = G.lds_image;
+    auto gather = [&](bool fwd, const uint8_t *rows, uint32_t ylevel) {
+        TPM_HIP(hipMemsetAsync(sum.p, 0, rowbytes, st));
+        const int32_t *sg = fwd ? S.in_seg : S.out_seg, *gt = fwd ? S.in_gat : S.out_gat,
+                      *ky = fwd ? S.in_key : S.out_key;
+        const dim3 grid(static_grid(G, (S.m + kStaticTile - 1) / kStaticTile)), block(1024);
+        uint8_t *sm = sum.as<uint8_t>();
+        const int32_t rb = (int32_t)C;
+        if (W == 4)
+            hipLaunchKernelGGL((k_sgather<4>), grid, block, 0, st, S.m, sg, gt, ky, rows, sm, rb, lanes, seed, ylevel, lds_image);
+        else if (W == 2)
+            hipLaunchKernelGGL((k_sgather<2>), grid, block, 0, st, S.m, sg, gt, ky, rows, sm, rb, lanes, seed, ylevel, lds_image);
+        else
+            hipLaunchKernelGGL((k_sgather<1>), grid, block, 0, st, S.m, sg, gt, ky, rows, sm, rb, lanes, seed, ylevel, lds_image);
+        TPM_HIP(hipGetLastError());
+    };
+    auto vertex = [&](const uint8_t *fin, uint8_t *out, int with_prod) {
+        const uint8_t *sm = sum.as<uint8_t>(), *xr = X.as<uint8_t>();
+        const dim3 grid(static_grid(G, S.n)), block(1024);
+        const int32_t rb = (int32_t)C;
+        if (W == 4)
+            hipLaunchKernelGGL((k_svertex<4>), grid, block, 0, st, S.n, sm, xr, fin, out, with_prod, S.vid, sv, rb, lanes, lds_image);
+        else if (W == 2)
+            hipLaunchKernelGGL((k_svertex<2>), grid, block, 0, st, S.n, sm, xr, fin, out, with_prod, S.vid, sv, rb, lanes, lds_image);
+        else
+            hipLaunchKernelGGL((k_svertex<1>), grid, block, 0, st, S.n, sm, xr, fin, out, with_prod, S.vid, sv, rb, lanes, lds_image);
+        TPM_HIP(hipGetLastError());
+    };
+    for (int64_t base = 0; base < npts; base += C) {
+        if (valid < C) TPM_HIP(hipMemsetAsync(X.p, 0, rowbytes, st));
+        const int32_t per_row = (int32_t)((valid + 15) / 16);
+        k_xt<<<grid_for((int64_t)S.n * per_row), 256, 0, st>>>(S.n, k, (int32_t)valid, (int32_t)C, 0,
+                                                                (uint32_t)base, zs.as<uint8_t>(),
+                                                                X.as<uint8_t>());
+        // forward, Eq. (1): F_l = x * sum over in-arcs of y_{., l-1} F_{l-1}; the last
+        // level adds sum_A F_k (G_k = 1)
+        const uint8_t *prev = X.as<uint8_t>();
+        for (int l = 2; l <= k; ++l) {
+            gather(true, prev, (uint32_t)(l - 1));
+            uint8_t *out = (l < k) ? Frow(l) : nullptr;
+            vertex(nullptr, out, l == k ? 1 : 0);
+            prev = out;
+        }
+        // backward: G_l = sum over out-arcs of y_{., l} x_w G_{w, l+1}, with H_l = x G_l
+        // (H_k = x); adds sum_A F_l G_l
+        const uint8_t *h = X.as<uint8_t>();
+        for (int l = k - 1; l >= 1; --l) {
+            gather(false, h, (uint32_t)l);
+            uint8_t *hout = (l >= 2) ? ((l & 1) ? H1.as<uint8_t>() : H0.as<uint8_t>()) : nullptr;
+            vertex(l == 1 ? X.as<uint8_t>() : Frow(l), hout, 0);
+            h = hout;
+        }
+    }
+    TPM_HIP(hipStreamSynchronize(st));
 }
 
 // ---------------------------------------------------------------- multi-query rows

@@ -110,6 +110,10 @@ _sig("tpm_graph_stats_get", ctypes.c_int32, [_vp, ctypes.POINTER(tpm_graph_stats
 _sig("tpm_graph_retile", ctypes.c_int32, [_vp, ctypes.c_int32])
 _sig("tpm_graph_layer", ctypes.c_int32, [_vp, _i32p, ctypes.c_int32, ctypes.POINTER(_vp)])
 _sig("tpm_graph_vertex_ids", ctypes.c_int32, [_vp, _i32p])
+_sig("tpm_graph_sd", ctypes.c_int32, [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(_vp)])
+_sig("tpm_static_sieve", ctypes.c_int32, [_vp, _i32p, ctypes.c_int32, ctypes.c_uint64, _u8p])
+_sig("tpm_graph_prune_static", ctypes.c_int32, [_vp, _i32p, ctypes.c_int32, ctypes.c_uint64,
+                                               ctypes.c_int32, ctypes.POINTER(_vp)])
 _sig("tpm_graph_prune", ctypes.c_int32, [_vp, _i32p, ctypes.c_int32, ctypes.POINTER(_vp)])
 _sig("tpm_graph_prune_ex", ctypes.c_int32, [_vp, _i32p, ctypes.c_int32, _i32p, ctypes.c_int32,
                                            ctypes.POINTER(_vp)])
@@ -146,8 +150,8 @@ _sig("tpm_version", ctypes.c_char_p, [])
 
 EXPORTED = ["tpm_graph_create", "tpm_graph_create_ex", "tpm_graph_destroy", "tpm_graph_stats_get",
             "tpm_graph_retile", "tpm_autotune", "tpm_graph_prune", "tpm_graph_prune_ex",
-            "tpm_graph_layer", "tpm_graph_vertex_ids", "tpm_sieve_vertex", "tpm_time_buckets",
-            "tpm_optimum_time",
+            "tpm_graph_layer", "tpm_graph_sd", "tpm_graph_vertex_ids", "tpm_sieve_vertex", "tpm_time_buckets",
+            "tpm_optimum_time", "tpm_static_sieve", "tpm_graph_prune_static",
             "tpm_sieve", "tpm_sieve_ex", "tpm_decide", "tpm_extract", "tpm_extract_ex",
             "tpm_batch_run",
             "tpm_server_create", "tpm_server_submit", "tpm_server_poll", "tpm_server_destroy",
@@ -351,6 +355,30 @@ def tpm_graph_layer(h, tup):
     return out
 
 
+def tpm_graph_sd(h, s, d):
+    out = ctypes.c_void_p()
+    _check(_lib.tpm_graph_sd(h, int(s), int(d), ctypes.byref(out)))
+    return out
+
+
+def tpm_static_sieve(h, multiset, seed):
+    """Per-vertex static vertex-localised sieve values (uint8[n])."""
+    M = _i32(multiset)
+    n = tpm_graph_stats_get(h)["n"]
+    out = np.zeros(n, dtype=np.uint8)
+    _check(_lib.tpm_static_sieve(h, _ptr(M, _i32p), len(M), int(seed) & (2**64 - 1),
+                                 _ptr(out, _u8p)))
+    return out
+
+
+def tpm_graph_prune_static(h, multiset, seed, reps=1):
+    M = _i32(multiset)
+    out = ctypes.c_void_p()
+    _check(_lib.tpm_graph_prune_static(h, _ptr(M, _i32p), len(M), int(seed) & (2**64 - 1),
+                                       int(reps), ctypes.byref(out)))
+    return out
+
+
 def tpm_graph_vertex_ids(h):
     n = tpm_graph_stats_get(h)["n"]
     ids = np.empty(n, dtype=np.int32)
@@ -462,6 +490,28 @@ class Graph:
         """Layered graph of the ordered colour tuple (VC-PATH-MOTIF)."""
         g = Graph.__new__(Graph)
         g.h = tpm_graph_layer(self.h, tup)
+        st = tpm_graph_stats_get(g.h)
+        g.n, g.m = st["n"], st["m"]
+        return g
+
+    def sd(self, s, d) -> "Graph":
+        """(s,d)-COLORFUL-PATH instance: s and d recoloured with num_colors and
+        num_colors + 1, s's in-edges and d's out-edges removed.  Sieve it with the
+        internal colours plus those two."""
+        g = Graph.__new__(Graph)
+        g.h = tpm_graph_sd(self.h, s, d)
+        st = tpm_graph_stats_get(g.h)
+        g.n, g.m = st["n"], st["m"]
+        return g
+
+    def static_sieve(self, multiset, seed):
+        return tpm_static_sieve(self.h, multiset, seed)
+
+    def prune_static(self, multiset, seed, reps=1) -> "Graph":
+        """Preprocessing steps (i) + (ii): the subgraph on the vertices the static
+        vertex-localised sieve marks for one of `reps` seeds."""
+        g = Graph.__new__(Graph)
+        g.h = tpm_graph_prune_static(self.h, multiset, seed, reps)
         st = tpm_graph_stats_get(g.h)
         g.n, g.m = st["n"], st["m"]
         return g
