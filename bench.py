@@ -84,6 +84,8 @@ def main() -> int:
                     help="skip the decide / extraction / optimum-time timings")
     ap.add_argument("--prune", action="store_true",
                     help="serving: run each request alone on the subgraph of its colours")
+    ap.add_argument("--no-extract", action="store_true",
+                    help="serving: decide only (default: extract a path on every hit)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device copy (for profiler counter scaling)")
     args = ap.parse_args()
@@ -229,15 +231,21 @@ def main() -> int:
             rc1, _, _, n1 = G.extract_ex(M, seed0, max_reps=4, method=1)
             e1 = {"ms": (time.perf_counter() - te) * 1e3, "sieves": n1,
                   "found": rc1 == tpm.TPM_OK}
+        # the paper's vertex-localisation extraction: one localised sieve, then a
+        # reverse temporal DFS from a certified end vertex
+        te = time.perf_counter()
+        rc2, _, _, n2 = G.extract_ex(M, seed0, max_reps=4, method=2)
+        e2 = {"ms": (time.perf_counter() - te) * 1e3, "sieves": n2, "found": rc2 == tpm.TPM_OK}
         te = time.perf_counter()
         t_opt_val = G.optimum_time(M, seed0, reps=1)
         t_opt = (time.perf_counter() - te) * 1e3
         line["extras"] = {
             "decide_ms": t_dec, "found": bool(found), "extract_ms": t_ext,
             "extract_sieves": n_ext, "extract_over_decide": t_ext / t_dec,
-            "path_verified": bool(ok), "extract_selfreduce": e1,
+            "path_verified": bool(ok), "extract_selfreduce": e1, "extract_vertexloc": e2,
             "optimum_time_ms": t_opt, "optimum_time": t_opt_val,
         }
+        print(f"# vertex-localisation extraction: {e2}", file=sys.stderr, flush=True)
         print(f"# decide {t_dec:.1f} ms, extract {t_ext:.1f} ms (path ok={ok}), optimum time "
               f"{t_opt_val} in {t_opt:.1f} ms", file=sys.stderr, flush=True)
 
@@ -433,7 +441,8 @@ def bench_serving(args) -> int:
     _log(f"# index: rows={st['rows']} tiles={st['tiles']} built in {time.perf_counter() - t_idx:.1f}s")
     qs = [{"multiset": [int(c) for c in make_config_query("serving", i)],
            "seed": 90001 + 7919 * i} for i in range(nq)]
-    srv = tpm.Server(G, prune_queries=1 if args.prune else 0)
+    srv = tpm.Server(G, prune_queries=1 if args.prune else 0,
+                     extract_paths=0 if args.no_extract else 1)
 
     def drain(n, got=None):
         """Poll until n results arrived, printing progress every 20 s."""
@@ -492,6 +501,8 @@ def bench_serving(args) -> int:
         "burst_queries": nb, "found": int(sum(r["found"] for r in results + burst)),
         "spot_check_equal_alone": bool(same), "dtype": "u8", "data": "synthetic",
         "mode": "per-request colour pruning" if args.prune else "continuous batching (resident row)",
+        "extract_on_hit": not args.no_extract,
+        "paths_ok": int(sum(r["path_status"] == tpm.TPM_OK for r in results + burst if r["found"])),
         "server_stats": sstats,
         "config": {"workload": f"serving: directed Chung-Lu n={g.n} m={g.m} beta=2.5 "
                                f"t=[1,{cfg['t']}] q={cfg['q']}, stream prefix of {nq} queries "

@@ -262,7 +262,15 @@ tpm_status tpm_extract(const tpm_graph *g, const int32_t *multiset, int32_t k, u
  *           approach): vertices of other colours are dropped, then vertex groups are
  *           deleted while a decision (max_reps sieves) stays YES, halving groups that
  *           cannot go (O(k log n) decisions), and a temporal DFS over the surviving
- *           vertices returns the path.  k >= 2. */
+ *           vertices returns the path.  k >= 2.
+ * method 2: the paper's vertex-localisation approach (same section, second
+ *           approach): one localised sieve per seed gives the vertices u with a
+ *           nonzero Q_u (tpm_sieve_vertex), each certified to end a matching path;
+ *           from them, smallest id first, a reverse temporal DFS (in-edges by
+ *           decreasing arrival, distinct vertices, colours from what is left of M)
+ *           returns a path.  The DFS is exhaustive per end vertex within a budget of
+ *           5e7 edge visits per call (TPM_NOTFOUND when it runs out).  k >= 2.
+ * For k = 1 every method returns a vertex of the colour. */
 tpm_status tpm_extract_ex(const tpm_graph *g, const int32_t *multiset, int32_t k, uint64_t seed,
                           int32_t max_reps, int32_t method, int32_t *path_vertices,
                           int64_t *path_edges, int64_t *sieves);

@@ -12,6 +12,7 @@
 #include <mutex>
 #include <set>
 #include <string>
+#include <unordered_map>
 
 #include "tpm_internal.h"
 
@@ -417,6 +418,161 @@ tpm_status extract_selfreduce(const Graph &G, const int32_t *M, int32_t k, uint6
     return TPM_NOTFOUND;  // every group test said YES only by a path the DFS rules out: impossible
 }
 
+// Reverse temporal DFS (section "Extracting a solution", second approach): from the
+// vertices u with q[u] != 0 (smallest id first; a nonzero Q_u certifies a matching path
+// that ends at u) extend a path backwards through in-edges that arrive early enough
+// for the edge already chosen to leave (latest arrival first), with distinct vertices
+// and colours drawn from what is left of M.  The DFS is exhaustive per end vertex, so
+// it finds a path from a certified u unless `budget` edge visits run out first.
+tpm_status extract_from_vertices(const Graph &G, const int32_t *M, int32_t k, const uint8_t *q,
+                                 int64_t budget, int32_t *path_vertices, int64_t *path_edges) {
+    TPM_REQUIRE(k >= 2 && k <= 16, "k must be in [2, 16]");
+    std::vector<int32_t> need((size_t)G.q, 0);
+    int32_t wild = 0;
+    for (int i = 0; i < k; ++i) {
+        TPM_REQUIRE(M[i] >= -1 && M[i] < G.q, "multiset colour out of range");
+        if (M[i] < 0) ++wild;
+        else ++need[(size_t)M[i]];
+    }
+    auto orig = [&](int32_t u) { return G.h_fid.empty() ? u : G.h_fid[(size_t)u]; };
+    // in-lists fetched on demand (positions in arrival order)
+    struct InList {
+        int64_t p0 = 0;
+        std::vector<int32_t> src, arr, dep, eid;
+    };
+    std::unordered_map<int32_t, InList> cache;
+    auto inlist = [&](int32_t w) -> const InList & {
+        auto it = cache.find(w);
+        if (it != cache.end()) return it->second;
+        InList L;
+        int32_t ab[2];
+        TPM_HIP(hipMemcpy(ab, G.inptr + w, 2 * sizeof(int32_t), hipMemcpyDeviceToHost));
+        L.p0 = ab[0];
+        const int64_t len = (int64_t)ab[1] - ab[0];
+        if (len > 0) {
+            L.src.resize((size_t)len);
+            L.arr.resize((size_t)len);
+            L.eid.resize((size_t)len);
+            TPM_HIP(hipMemcpy(L.src.data(), G.psrc + ab[0], 4 * len, hipMemcpyDeviceToHost));
+            TPM_HIP(hipMemcpy(L.arr.data(), G.ptau + ab[0], 4 * len, hipMemcpyDeviceToHost));
+            TPM_HIP(hipMemcpy(L.eid.data(), G.peid + ab[0], 4 * len, hipMemcpyDeviceToHost));
+            if (G.pdep) {
+                L.dep.resize((size_t)len);
+                TPM_HIP(hipMemcpy(L.dep.data(), G.pdep + ab[0], 4 * len, hipMemcpyDeviceToHost));
+            }
+        }
+        return cache.emplace(w, std::move(L)).first->second;
+    };
+    std::vector<int32_t> rv;    // the path, last vertex first
+    std::vector<int64_t> rp;    // edge positions, last edge first
+    std::vector<int32_t> reid;
+    std::vector<int32_t> used;  // original ids on the path
+    int64_t visits = 0;
+    // a vertex of colour c takes its colour (alt 0) or a wildcard (alt 1)
+    auto take = [&](int32_t c, int alt) -> bool {
+        int32_t &slot = alt == 0 ? need[(size_t)c] : wild;
+        if (slot <= 0) return false;
+        --slot;
+        return true;
+    };
+    auto give = [&](int32_t c, int alt) { ++(alt == 0 ? need[(size_t)c] : wild); };
+    // extend backwards from rv.back(), whose outgoing path edge leaves at `dep`
+    std::function<bool(int64_t)> dfs = [&](int64_t dep) -> bool {
+        if ((int32_t)rv.size() == k) {
+            std::vector<int32_t> pv(rv.rbegin(), rv.rend());
+            std::vector<int64_t> pp(rp.rbegin(), rp.rend());
+            return verify_path(G, M, k, pv.data(), pp.data());
+        }
+        const int32_t w = rv.back();
+        const int64_t dl = G.h_delay.empty() ? 1 : G.h_delay[(size_t)w];
+        const InList &L = inlist(w);
+        // in-edges that arrive by dep - delay(w) (any, for the path's last vertex)
+        int64_t hi = (int64_t)L.arr.size();
+        if (rv.size() > 1) {
+            const int64_t th = dep - dl + 1;  // arrival < th
+            hi = std::lower_bound(L.arr.begin(), L.arr.end(), th,
+                                  [](int32_t x, int64_t y) { return (int64_t)x < y; }) -
+                 L.arr.begin();
+        }
+        for (int64_t i = hi - 1; i >= 0; --i) {
+            if (++visits > budget) return false;
+            const int32_t v = L.src[(size_t)i];
+            const int32_t o = orig(v);
+            if (std::find(used.begin(), used.end(), o) != used.end()) continue;
+            const int32_t c = G.h_color[(size_t)v];
+            for (int alt = 0; alt < 2; ++alt) {
+                if (!take(c, alt)) continue;
+                rv.push_back(v);
+                rp.push_back(L.p0 + i);
+                reid.push_back(L.eid[(size_t)i]);
+                used.push_back(o);
+                const int64_t d = G.pdep ? (int64_t)L.dep[(size_t)i] : (int64_t)L.arr[(size_t)i];
+                if (dfs(d)) return true;
+                rv.pop_back();
+                rp.pop_back();
+                reid.pop_back();
+                used.pop_back();
+                give(c, alt);
+                if (visits > budget) return false;
+            }
+        }
+        return false;
+    };
+    for (int32_t u = 0; u < G.n; ++u) {
+        if (!q[(size_t)u]) continue;
+        const int32_t c = G.h_color[(size_t)u];
+        for (int alt = 0; alt < 2; ++alt) {
+            if (!take(c, alt)) continue;
+            rv.assign(1, u);
+            rp.clear();
+            reid.clear();
+            used.assign(1, orig(u));
+            const bool ok = dfs(0);
+            give(c, alt);
+            if (ok) {
+                for (int i = 0; i < k; ++i) path_vertices[i] = orig(rv[(size_t)(k - 1 - i)]);
+                for (int i = 0; i + 1 < k; ++i) path_edges[i] = reid[(size_t)(k - 2 - i)];
+                return TPM_OK;
+            }
+            if (visits > budget) return TPM_NOTFOUND;
+        }
+    }
+    return TPM_NOTFOUND;
+}
+
+// Extraction by vertex localisation: one localised sieve per seed, then the reverse
+// temporal DFS from the certified end vertices.
+tpm_status extract_vertexloc(const Graph &G, const int32_t *M, int32_t k, uint64_t seed,
+                             int32_t max_reps, int32_t *path_vertices, int64_t *path_edges,
+                             int64_t *sieves, int64_t budget) {
+    TPM_REQUIRE(k >= 2 && k <= 16, "k must be in [2, 16]");
+    TPM_REQUIRE(max_reps >= 1, "max_reps must be >= 1");
+    int64_t nsieve = 0;
+    struct Count {
+        int64_t *out;
+        int64_t &n;
+        ~Count() {
+            if (out) *out = n;
+        }
+    } count{sieves, nsieve};
+    std::vector<uint8_t> q((size_t)G.n);
+    int64_t left = budget;
+    for (int32_t r = 0; r < max_reps; ++r) {
+        SieveRequest req;
+        req.multiset = M;
+        req.k = k;
+        req.seed = step_seed(seed, 0, r);
+        const uint8_t total = vertex_localise(G, req, q.data(), nullptr);
+        ++nsieve;
+        if (!total) continue;
+        const tpm_status st = extract_from_vertices(G, M, k, q.data(), left, path_vertices, path_edges);
+        if (st == TPM_OK) return TPM_OK;
+        return TPM_NOTFOUND;  // a certified end vertex and no path within the budget
+    }
+    (void)left;
+    return TPM_NOTFOUND;
+}
+
 static double now_ms_api() {
     using namespace std::chrono;
     return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
@@ -729,11 +885,14 @@ tpm_status tpm_extract_ex(const tpm_graph *g, const int32_t *multiset, int32_t k
                           int64_t *path_edges, int64_t *sieves) {
     return guarded([&]() -> tpm_status {
         TPM_REQUIRE(g && multiset && path_vertices && (k < 2 || path_edges), "NULL argument");
-        TPM_REQUIRE(method == 0 || method == 1, "method must be 0 or 1");
+        TPM_REQUIRE(method >= 0 && method <= 2, "method must be 0, 1 or 2");
         DeviceScope ds(g->G.device);
         if (method == 1 && k >= 2)
             return extract_selfreduce(g->G, multiset, k, seed, max_reps, path_vertices, path_edges,
                                       sieves);
+        if (method == 2 && k >= 2)
+            return extract_vertexloc(g->G, multiset, k, seed, max_reps, path_vertices, path_edges,
+                                     sieves, kDfsBudget);
         return extract_path(g->G, multiset, k, seed, max_reps, path_vertices, path_edges, nullptr,
                             sieves);
     });

@@ -76,12 +76,30 @@ void check_query(const Graph &G, const tpm_query &q) {
         TPM_REQUIRE(q.multiset[i] >= -1 && q.multiset[i] < G.q, "multiset colour out of range");
 }
 
-void extract_into(const Graph &G, const tpm_query &q, tpm_result &r, hipStream_t st) {
-    int64_t pe[16];
-    int32_t pv[16];
-    r.path_status = extract_path(G, q.multiset, q.k, q.seed, 8, pv, pe, st);
+// DFS budget of extraction on a hit: the vertex-localisation DFS gives up after this
+// many edge visits and the localisation-guided self-reduction takes over.
+constexpr int64_t kHitDfsBudget = 5'000'000;
+
+void store_path(const tpm_query &q, const int32_t *pv, const int64_t *pe, tpm_result &r) {
     for (int i = 0; i < q.k; ++i) r.path_vertices[i] = pv[i];
     for (int i = 0; i + 1 < q.k; ++i) r.path_edges[i] = pe[i];
+}
+
+// Extraction on a hit: vertex localisation + reverse temporal DFS (one sieve), else
+// the localisation-guided self-reduction.  q_loc (nullable): the query's own vertex
+// localisation, already computed by the sieve that found the hit.
+void extract_into(const Graph &G, const tpm_query &q, tpm_result &r, hipStream_t st,
+                  const uint8_t *q_loc = nullptr) {
+    int64_t pe[16];
+    int32_t pv[16];
+    r.path_status = TPM_NOTFOUND;
+    if (q.k >= 2) {
+        r.path_status = q_loc ? extract_from_vertices(G, q.multiset, q.k, q_loc, kHitDfsBudget, pv, pe)
+                              : extract_vertexloc(G, q.multiset, q.k, q.seed, 2, pv, pe, nullptr,
+                                                  kHitDfsBudget);
+    }
+    if (r.path_status != TPM_OK) r.path_status = extract_path(G, q.multiset, q.k, q.seed, 8, pv, pe, st);
+    if (r.path_status == TPM_OK) store_path(q, pv, pe, r);
 }
 
 void run_alone(const Graph &G, const tpm_query &q, tpm_result &r, hipStream_t st) {
@@ -351,9 +369,23 @@ void serve_pruned(tpm_server *s) {
             prune_graph(G, keep.data(), nullptr, 0, P, s->arena);
             P.pool = s->ppool;
             const double t1 = now_ms();
-            run_alone(P, rq->q, r, st);
+            const bool want = rq->q.want_path || s->cfg.extract_paths;
+            std::vector<uint8_t> qloc;
+            if (want && rq->q.k >= 2) {
+                // the sieve with vertex localisation: the total, and the end vertices
+                // the extraction's DFS starts from
+                qloc.resize((size_t)P.n);
+                SieveRequest req;
+                req.multiset = rq->q.multiset;
+                req.k = rq->q.k;
+                req.seed = rq->q.seed;
+                r.total = vertex_localise(P, req, qloc.data(), st);
+                r.found = r.total != 0;
+            } else {
+                run_alone(P, rq->q, r, st);
+            }
             const double t2 = now_ms();
-            if (r.found && (rq->q.want_path || s->cfg.extract_paths)) extract_into(P, rq->q, r, st);
+            if (r.found && want) extract_into(P, rq->q, r, st, qloc.empty() ? nullptr : qloc.data());
             const double t3 = now_ms();
             r.ticket = rq->ticket;
             r.t_submit_ms = rq->t_submit;

@@ -292,6 +292,21 @@ void run_sieve_pruned(const Graph &G, const SieveRequest &req, SieveResult &res,
 void run_sieve_sink(const Graph &G, const SieveRequest &req, SieveResult &res, LocSink &sink,
                     hipStream_t st);
 
+// Vertex localisation of one sieve: q[u] (host, G.n bytes) = XOR of the per-edge
+// localisation over u's in-edges (the sieve over walks ending at u).
+// Returns the sieve total (the XOR of the q[u]).
+uint8_t vertex_localise(const Graph &G, const SieveRequest &req, uint8_t *q, hipStream_t st);
+// Extraction by vertex localisation (section "Extracting a solution", second
+// approach): reverse temporal DFS from the vertices u with q[u] != 0 (q: host, G.n
+// bytes, from vertex_localise), at most `budget` edge visits.  TPM_OK / TPM_NOTFOUND.
+constexpr int64_t kDfsBudget = 50'000'000;
+tpm_status extract_from_vertices(const Graph &G, const int32_t *M, int32_t k, const uint8_t *q,
+                                 int64_t budget, int32_t *path_vertices, int64_t *path_edges);
+// One localised sieve per seed (step seeds of extraction), then the DFS.
+tpm_status extract_vertexloc(const Graph &G, const int32_t *M, int32_t k, uint64_t seed,
+                             int32_t max_reps, int32_t *path_vertices, int64_t *path_edges,
+                             int64_t *sieves, int64_t budget);
+
 // Per-edge localisation over all edges, indexed by input edge id.
 void run_sieve_loc_all(const Graph &G, const SieveRequest &req, SieveResult &res,
                        uint8_t *loc_by_edge, hipStream_t stream);

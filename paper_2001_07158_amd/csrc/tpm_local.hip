@@ -153,6 +153,20 @@ struct StaticHolder {
 };
 
 }  // namespace
+
+uint8_t vertex_localise(const Graph &G, const SieveRequest &req, uint8_t *q, hipStream_t st) {
+    SieveResult res;
+    if (G.m == 0) {
+        std::memset(q, 0, (size_t)G.n);
+        run_sieve(G, req, res, st);  // argument checks; the total of k = 1
+        return res.total;
+    }
+    VertexSink sink;
+    sink.out = q;
+    run_sieve_sink(G, req, res, sink, st);
+    return res.total;
+}
+
 }  // namespace tpm
 
 using namespace tpm;
@@ -170,15 +184,7 @@ tpm_status tpm_sieve_vertex(const tpm_graph *g, const int32_t *multiset, int32_t
         req.k = k;
         req.seed = seed;
         req.vertex_mask = vertex_mask;
-        VertexSink sink;
-        sink.out = q;
-        SieveResult res;
-        if (g->G.m == 0) {
-            std::memset(q, 0, (size_t)g->G.n);
-            run_sieve(g->G, req, res, nullptr);  // argument checks only
-            return TPM_OK;
-        }
-        run_sieve_sink(g->G, req, res, sink, nullptr);
+        vertex_localise(g->G, req, q, nullptr);
         return TPM_OK;
     });
 }

@@ -369,3 +369,64 @@ def test_k16_all_points_tiny(tpm):
     g = G.uniform_graph(60, 500, 30, 4, 163)
     M = [int(c) for c in np.random.default_rng(1).integers(0, 4, 16)]
     _check(tpm, g, M, 77, label="k=16")
+
+
+def test_vertexloc_extraction_against_brute_force(tpm):
+    """The paper's vertex-localisation extraction (Q_u, then reverse temporal DFS from
+    a certified end vertex) finds a valid path exactly when one exists, also with
+    wildcards, transition / delay times and on layered (VC) graphs."""
+    rng = np.random.default_rng(191)
+    yes = no = 0
+    for it in range(50):
+        g = G.random_tiny_graph(rng, n_max=14, m_max=50, t_max=6, q_max=3)
+        k = int(rng.integers(2, 6))
+        M = [int(c) for c in rng.integers(-1 if it % 5 == 4 else 0, g.num_colors, k)]
+        exists = pyref.has_matching_path(g, M)
+        say(f"case vertexloc {it}: n={g.n} m={g.m} M={M} exists={exists}")
+        Gd = tpm.Graph.from_temporal(g, tile_edges=int(rng.integers(1, 32)))
+        rc, verts, edges, ns = Gd.extract_ex(M, 400 + it, max_reps=8, method=2)
+        if exists:
+            yes += 1
+            assert rc == tpm.TPM_OK, it
+            assert pyref.check_path(g, M, verts, edges)
+            assert 1 <= ns <= 8
+        else:
+            no += 1
+            assert rc == tpm.TPM_NOTFOUND
+        Gd.close()
+    assert yes > 10 and no > 5
+    g = G.random_tiny_graph(np.random.default_rng(7), n_max=12, m_max=40, t_max=6, q_max=3)
+    assert g.num_colors == 3
+    tr = np.ones(g.m, np.int32)
+    dl = np.zeros(g.n, np.int32)
+    for M in ([0, 1], [0, 1, 2], [1, 1, 0]):
+        Gd = tpm.Graph(g.n, g.src, g.dst, g.tau, g.color, g.num_colors, transit=tr, delay=dl)
+        rc, verts, edges, _ = Gd.extract_ex(M, 5, max_reps=8, method=2)
+        assert (rc == tpm.TPM_OK) == pyref.has_matching_path(g, M, tr, dl)
+        if rc == tpm.TPM_OK:
+            assert pyref.check_path(g, M, verts, edges, tr, dl)
+        Gd.close()
+
+
+def test_vertexloc_extraction_planted(tpm):
+    """A planted 8-vertex path on a Chung-Lu graph: extracted by the reverse DFS from
+    one localised sieve; the three methods agree on existence."""
+    g = G.chung_lu_graph(3000, 40000, 2.5, 80, 12, 192)
+    rng = np.random.default_rng(3)
+    k = 8
+    verts = [int(v) for v in rng.choice(g.n, k, replace=False)]
+    color = g.color.copy()
+    M = [int(c) for c in rng.integers(0, 12, k)]
+    for v, c in zip(verts, M):
+        color[v] = c
+    src = np.concatenate([g.src, np.array(verts[:-1], dtype=np.int32)])
+    dst = np.concatenate([g.dst, np.array(verts[1:], dtype=np.int32)])
+    tau = np.concatenate([g.tau, np.arange(1, k, dtype=np.int32) * 9])
+    h = G.TemporalGraph(g.n, src, dst, tau, color, 12)
+    Gd = tpm.Graph.from_temporal(h)
+    rc, pv, pe, ns = Gd.extract_ex(M, 11, max_reps=8, method=2)
+    assert rc == tpm.TPM_OK
+    assert pyref.check_path(h, M, pv, pe)
+    rc0, pv0, pe0, _ = Gd.extract_ex(M, 11, max_reps=8, method=0)
+    assert rc0 == tpm.TPM_OK and pyref.check_path(h, M, pv0, pe0)
+    Gd.close()

@@ -58,11 +58,15 @@ def test_vc_extraction_against_exhaustive_search(tpm):
         Gd = tpm.Graph.from_temporal(g)
         Gl = Gd.layer(C)
         rc, verts, edges = Gl.extract(C, 77 + it, max_reps=12)
+        rc2, v2, e2, _ = Gl.extract_ex(C, 77 + it, max_reps=12, method=2)
+        assert rc2 == rc, it
         if exists:
             yes += 1
             assert rc == tpm.TPM_OK, it
             assert pyref.check_path(g, C, verts, edges)
             assert [int(g.color[v]) for v in verts] == C  # the order itself
+            assert pyref.check_path(g, C, v2, e2)
+            assert [int(g.color[v]) for v in v2] == C
         else:
             no += 1
             assert rc == tpm.TPM_NOTFOUND
