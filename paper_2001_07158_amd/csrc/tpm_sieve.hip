@@ -347,6 +347,11 @@ __global__ void __launch_bounds__(1024) k_level(LevelParams P) {
 
         auto process = [&](const uint32_t (&g)[kU][W], int32_t pb) {
             const int nb = min(kU, p1 - pb);
+            // last level with localisation: this lane's XOR of each position's points,
+            // one byte per position, four positions to a dword
+            uint32_t lp[kU / 4];
+#pragma unroll
+            for (int h = 0; h < kU / 4; ++h) lp[h] = 0;
 #pragma unroll
             for (int u = 0; u < kU; ++u) {
                 if (u >= nb) break;
@@ -396,10 +401,7 @@ __global__ void __launch_bounds__(1024) k_level(LevelParams P) {
                             for (int w = 0; w < W; ++w) x ^= c[w];
                             x ^= x >> 16;
                             x ^= x >> 8;
-                            x &= 0xFFu;
-#pragma unroll
-                            for (int off = 32; off >= 1; off >>= 1) x ^= __shfl_xor(x, off);
-                            if (lane == 0) P.loc[p - P.pos_lo] ^= (uint8_t)x;
+                            lp[u >> 2] |= (x & 0xFFu) << (8 * (u & 3));
                         }
                     }
                 } else {
@@ -407,6 +409,21 @@ __global__ void __launch_bounds__(1024) k_level(LevelParams P) {
                     for (int w = 0; w < W; ++w) acc[w] ^= c[w];
                     const int32_t orow = __builtin_amdgcn_readlane(cw.o, i);
                     if (orow >= 0 && act) store_row<W>(P.sout, orow, P.rowb, lane, acc);
+                }
+            }
+            if constexpr (FIN) {
+                if (P.loc) {
+                    // XOR across the wave, four positions at a time; lane j < nb then
+                    // adds position pb + j's byte
+#pragma unroll
+                    for (int h = 0; h < kU / 4; ++h) {
+                        if (4 * h >= nb) break;
+#pragma unroll
+                        for (int off = 32; off >= 1; off >>= 1) lp[h] ^= __shfl_xor(lp[h], off);
+                    }
+                    const int32_t p = pb + lane;
+                    if (lane < nb && p >= P.pos_lo && p < P.pos_hi)
+                        P.loc[p - P.pos_lo] ^= (uint8_t)(lp[(lane >> 2) & (kU / 4 - 1)] >> (8 * (lane & 3)));
                 }
             }
             // advance the window after its last batch
