@@ -153,14 +153,31 @@ __global__ void k_vand(int32_t n, const uint8_t *a, uint8_t *b) {
 
 // keep[p] = 1 when both endpoints of the edge at position p are kept and, with a
 // timestamp set ts[0..nts) (sorted), its timestamp is in the set
+// vbits: one bit per vertex (bit u & 31 of word u >> 5), so that the random lookups of
+// the sources stay in cache
+__global__ void k_vbits(int32_t n, const uint8_t *vkeep, uint32_t *vbits) {
+    int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= ((int64_t)n + 31) / 32) return;
+    uint32_t b = 0;
+    for (int j = 0; j < 32; ++j) {
+        const int64_t u = w * 32 + j;
+        if (u < n && vkeep[u]) b |= 1u << j;
+    }
+    vbits[w] = b;
+}
+
+__device__ __forceinline__ bool vbit(const uint32_t *vbits, int32_t u) {
+    return (vbits[u >> 5] >> (u & 31)) & 1u;
+}
+
 // (cut_in: a vertex whose in-edges go, cut_out: one whose out-edges go; -1 for none)
-__global__ void k_keep(int64_t m, const int32_t *psrc, const int32_t *pdst, const uint8_t *vkeep,
+__global__ void k_keep(int64_t m, const int32_t *psrc, const int32_t *pdst, const uint32_t *vbits,
                        const int32_t *ptime, const int32_t *ts, int32_t nts, int32_t cut_in,
                        int32_t cut_out, int32_t *keep) {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= m) return;
     const int32_t s = psrc[p], d = pdst[p];
-    bool k = vkeep[s] && vkeep[d] && d != cut_in && s != cut_out;
+    bool k = vbit(vbits, s) && vbit(vbits, d) && d != cut_in && s != cut_out;
     if (k && ts) {
         const int32_t t = ptime[p];
         int32_t a = 0, b = nts;
@@ -310,10 +327,10 @@ int bits_for(uint64_t v) {  // bits needed to represent values 0..v
 
 // Slots of a graph arena: one grow-only buffer per index array and per temporary.
 enum ArenaSlot {
-    A_COLOR, A_PDST, A_PSRC, A_PTAU, A_PEID, A_GSRC, A_OROW, A_INPTR, A_SEGNEXT, A_TP0, A_TPUB,
+    A_COLOR, A_PDST, A_PSRC, A_PTAU, A_PEID, A_GSRC, A_OROW, A_INPTR, A_TP0, A_TPUB,
     A_TLB, A_LDS, A_TTAB, A_KEEPC, A_KEEP, A_AT, A_SCRATCH, A_GPOS, A_NEEDED, A_ROWOF, A_TSORT,
     A_TUNIQ, A_TCOUNT, A_CNT, A_PDEP, A_VDELAY, A_VKEEP, A_TSET, A_FID, A_TNZ, A_TPM, A_TCNT,
-    A_SCNT, A_TBASE, A_SBASE, A_TSTAT, A_NSLOTS
+    A_SCNT, A_TBASE, A_SBASE, A_TSTAT, A_VBITS, A_NSLOTS
 };
 
 struct GraphArena {
@@ -846,6 +863,8 @@ void prune_graph(const Graph &P, const uint8_t *keep_color, const int32_t *times
                 k_vkeep<<<grid_for(P.n), 256, 0, st>>>(P.n, P.color, keepc, vkeep);
                 if (vkeep_in)
                     k_vand<<<grid_for(P.n), 256, 0, st>>>(P.n, vkeep_in, vkeep);
+                uint32_t *vbits = tmp.get<uint32_t>(A_VBITS, ((int64_t)P.n + 31) / 32);
+                k_vbits<<<grid_for(((int64_t)P.n + 31) / 32), 256, 0, st>>>(P.n, vkeep, vbits);
                 int32_t *ts = nullptr;
                 if (times) {
                     ts = tmp.get<int32_t>(A_TSET, ntimes);
@@ -854,7 +873,7 @@ void prune_graph(const Graph &P, const uint8_t *keep_color, const int32_t *times
                 keep = tmp.get<int32_t>(A_KEEP, P.m);
                 at = tmp.get<int32_t>(A_AT, P.m);
                 // timestamps of the edges as given (departures when transit times exist)
-                k_keep<<<grid_for(P.m), 256, 0, st>>>(P.m, P.psrc, P.pdst, vkeep,
+                k_keep<<<grid_for(P.m), 256, 0, st>>>(P.m, P.psrc, P.pdst, vbits,
                                                        P.pdep ? P.pdep : P.ptau, ts, ntimes,
                                                        cut_in, cut_out, keep);
                 size_t sbytes = 0;

@@ -832,12 +832,19 @@ __global__ void k_total(int32_t npts, const uint8_t *pp, uint8_t *total) {
     }
 }
 
-// smallest (input edge id, position) over positions whose localisation is nonzero
+// smallest (input edge id, position) over positions whose localisation is nonzero;
+// each wave reduces its 64 candidates first, so the shared word sees one atomic per wave
 __global__ void k_pick(int32_t lo, int32_t hi, const uint8_t *loc, const int32_t *peid,
                        unsigned long long *best) {
     int64_t p = (int64_t)lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long v = ~0ull;
     if (p < hi && loc[p - lo])
-        atomicMin(best, ((unsigned long long)(uint32_t)peid[p] << 32) | (unsigned long long)p);
+        v = ((unsigned long long)(uint32_t)peid[p] << 32) | (unsigned long long)p;
+    for (int off = 32; off >= 1; off >>= 1) {
+        const unsigned long long o = __shfl_xor(v, off);
+        v = o < v ? o : v;
+    }
+    if ((threadIdx.x & 63) == 0 && v != ~0ull) atomicMin(best, v);
 }
 
 inline unsigned grid_for(int64_t work, int block = 256) {
@@ -1490,7 +1497,7 @@ void run_sieve_impl(const Graph &G, const SieveRequest &req, SieveResult &res, b
     }
     k_total<<<1, 256, 0, st>>>((int32_t)npts, pp.as<uint8_t>(), tot.as<uint8_t>());
     unsigned long long hpick = ~0ull;
-    if (want_loc && hi > lo) {
+    if (want_loc && req.want_pick && hi > lo) {
         k_pick<<<grid_for(hi - lo), 256, 0, st>>>((int32_t)lo, (int32_t)hi, loc.as<uint8_t>(), G.peid,
                                                   pick.as<unsigned long long>());
         TPM_HIP(hipMemcpyAsync(&hpick, pick.p, sizeof(hpick), hipMemcpyDeviceToHost, st));
