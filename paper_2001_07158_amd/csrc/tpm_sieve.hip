@@ -1348,17 +1348,24 @@ void launch_narrow(bool fin, const Graph &G, const LevelParams &P, hipStream_t s
     else hipLaunchKernelGGL((k_narrow<LP, false>), dim3((unsigned)G.num_cu), dim3(1024), 0, st, P);
 }
 
-// rows of 16..512 points run edge-parallel (k_narrow), rows of 1024 points k_level
-bool is_narrow(int rowb) { return rowb >= 16 && rowb <= 512; }
+// rows of 16..256 points run edge-parallel (k_narrow); rows of 512 and 1024 points run
+// one position per wave (k_level with 2 or 4 dwords a lane), which measured faster at
+// 512 points (15.0 against 16.9 ms per middle level of a 1e8-edge graph)
+bool is_narrow(int rowb) { return rowb >= 16 && rowb <= 256; }
 
 void launch_level_any(int rowb, bool fin, const Graph &G, const LevelParams &P, hipStream_t st) {
+    if (rowb == 512) {  // one position per wave, 8 points per lane
+        LevelParams Q = P;
+        Q.lanes = 64;
+        fin ? launch_level<2, true>(G, Q, st) : launch_level<2, false>(G, Q, st);
+        return;
+    }
     switch (is_narrow(rowb) ? rowb / 16 : 0) {
         case 1: launch_narrow<1>(fin, G, P, st); break;
         case 2: launch_narrow<2>(fin, G, P, st); break;
         case 4: launch_narrow<4>(fin, G, P, st); break;
         case 8: launch_narrow<8>(fin, G, P, st); break;
         case 16: launch_narrow<16>(fin, G, P, st); break;
-        case 32: launch_narrow<32>(fin, G, P, st); break;
         default:
             TPM_REQUIRE(rowb == 1024, "sieve rows hold 16..1024 points");
             fin ? launch_level<4, true>(G, P, st) : launch_level<4, false>(G, P, st);
