@@ -216,6 +216,36 @@ __global__ void k_layer_compact(int64_t m, const int32_t *keep, const int32_t *a
     }
 }
 
+// rowpos[orow[p]] = p
+__global__ void k_rowpos(int64_t m, const int32_t *orow, int32_t *rowpos) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < m && orow[p] >= 0) rowpos[orow[p]] = (int32_t)p;
+}
+
+// The read position of a kept edge in the subgraph: the last kept position at or before
+// its parent read position g (positions keep their order), if that is still in the
+// source's in-list.  at = exclusive count of kept positions.
+__global__ void k_gpos_remap(int64_t m, const int32_t *keep, const int32_t *at, const int32_t *gsrc,
+                             const int32_t *rowpos, const int32_t *psrc, const int32_t *inptr,
+                             int32_t *gpos) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= m || !keep[p]) return;
+    int32_t q = -1;
+    const int32_t r = gsrc[p];
+    if (r >= 0) {
+        const int32_t g = rowpos[r];
+        const int32_t last = at[g] + keep[g] - 1;
+        const int32_t first = at[inptr[psrc[p]]];
+        if (last >= first) q = last;
+    }
+    gpos[at[p]] = q;
+}
+
+__global__ void k_needed(int64_t m, const int32_t *gpos, int32_t *needed) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < m && gpos[p] >= 0) needed[gpos[p]] = 1;  // every writer stores the same value
+}
+
 __global__ void k_compact1(int64_t m, const int32_t *keep, const int32_t *at, const int32_t *a,
                            int32_t *b) {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -330,7 +360,7 @@ enum ArenaSlot {
     A_COLOR, A_PDST, A_PSRC, A_PTAU, A_PEID, A_GSRC, A_OROW, A_INPTR, A_TP0, A_TPUB,
     A_TLB, A_LDS, A_TTAB, A_KEEPC, A_KEEP, A_AT, A_SCRATCH, A_GPOS, A_NEEDED, A_ROWOF, A_TSORT,
     A_TUNIQ, A_TCOUNT, A_CNT, A_PDEP, A_VDELAY, A_VKEEP, A_TSET, A_FID, A_TNZ, A_TPM, A_TCNT,
-    A_SCNT, A_TBASE, A_SBASE, A_TSTAT, A_VBITS, A_NSLOTS
+    A_SCNT, A_TBASE, A_SBASE, A_TSTAT, A_VBITS, A_ROWPOS, A_GPOSP, A_NSLOTS
 };
 
 struct GraphArena {
@@ -588,7 +618,7 @@ const std::vector<uint8_t> &lds_image_host() {
 void free_graph(Graph &G) {
     int32_t **ptrs[] = {&G.color, &G.pdst,  &G.psrc,    &G.ptau,     &G.peid,   &G.gsrc,
                         &G.orow,  &G.inptr, &G.tile_p0, &G.tile_pub, &G.tile_lb,
-                        &G.ttab,  &G.pdep,  &G.vdelay, &G.fid};
+                        &G.ttab,  &G.pdep,  &G.vdelay, &G.fid,      &G.rowpos};
     const bool own = G.arena == nullptr;  // arena memory stays with the arena
     for (auto pp : ptrs) {
         if (*pp && own) (void)hipFree(*pp);
@@ -602,7 +632,9 @@ void free_graph(Graph &G) {
 // sorted by (dst, tau, input id)), G.color and G.tmax: distinct timestamps, in-list
 // offsets, gathered and stored rows, host copies, tiles and the LDS image.  taus:
 // the m timestamps in any order (device).
-void finish_index(Graph &G, int64_t &acct, const int32_t *taus, bool greedy_tiles) {
+// gpos_pre (nullable, device [m]): read positions already known (pruned graphs)
+void finish_index(Graph &G, int64_t &acct, const int32_t *taus, bool greedy_tiles,
+                  const int32_t *gpos_pre = nullptr) {
     const int64_t m = G.m;
     const int32_t n = G.n;
     const int32_t tmax = G.tmax;
@@ -636,12 +668,18 @@ void finish_index(Graph &G, int64_t &acct, const int32_t *taus, bool greedy_tile
     }
     k_inptr<<<grid_for(m + 1), 256, 0, st>>>(m, n, G.pdst, G.inptr);
     if (m) {
-        int32_t *gpos = tmp.get<int32_t>(A_GPOS, m);
         int32_t *needed = tmp.get<int32_t>(A_NEEDED, m);
         int32_t *rowof = tmp.get<int32_t>(A_ROWOF, m);
         TPM_HIP(hipMemsetAsync(needed, 0, sizeof(int32_t) * m, st));
-        k_gpos<<<grid_for(m), 256, 0, st>>>(m, G.psrc, G.ptau, G.pdep, G.vdelay, G.inptr, gpos,
-                                            needed);
+        const int32_t *gpos = gpos_pre;
+        if (gpos) {
+            k_needed<<<grid_for(m), 256, 0, st>>>(m, gpos, needed);
+        } else {
+            int32_t *gp = tmp.get<int32_t>(A_GPOS, m);
+            k_gpos<<<grid_for(m), 256, 0, st>>>(m, G.psrc, G.ptau, G.pdep, G.vdelay, G.inptr, gp,
+                                                needed);
+            gpos = gp;
+        }
         size_t sbytes = 0;
         TPM_HIP(rocprim::exclusive_scan(nullptr, sbytes, needed, rowof, 0, (size_t)m,
                                         rocprim::plus<int32_t>(), st));
@@ -659,6 +697,10 @@ void finish_index(Graph &G, int64_t &acct, const int32_t *taus, bool greedy_tile
         unsigned long long h = 0;
         TPM_HIP(hipMemcpy(&h, cnt, sizeof(h), hipMemcpyDeviceToHost));
         G.gathers = (int64_t)h;
+        if (!G.arena) {  // whole graphs keep the row -> position map for pruning
+            G.rowpos = galloc<int32_t>(G, A_ROWPOS, std::max<int64_t>(1, G.R), acct);
+            k_rowpos<<<grid_for(m), 256, 0, st>>>(m, G.orow, G.rowpos);
+        }
     }
     if (G.h_color.size() != (size_t)n) {
         G.h_color.resize((size_t)n);
@@ -847,6 +889,8 @@ void prune_graph(const Graph &P, const uint8_t *keep_color, const int32_t *times
     try {
         int64_t mk = 0;
         int32_t *keep = nullptr, *at = nullptr;
+        Temps outer(arena);
+        int32_t *gpos_pre = nullptr;  // read positions mapped from the parent's
         {
             Temps tmp(arena);
             G.color = galloc<int32_t>(G, A_COLOR, P.n, acct);
@@ -911,10 +955,15 @@ void prune_graph(const Graph &P, const uint8_t *keep_color, const int32_t *times
                                                           P.peid, G.psrc, G.pdst, G.ptau, G.peid);
                 if (P.pdep)
                     k_compact1<<<grid_for(P.m), 256, 0, st>>>(P.m, keep, at, P.pdep, G.pdep);
+                if (P.rowpos) {
+                    gpos_pre = outer.get<int32_t>(A_GPOSP, mk);
+                    k_gpos_remap<<<grid_for(P.m), 256, 0, st>>>(P.m, keep, at, P.gsrc, P.rowpos,
+                                                                P.psrc, P.inptr, gpos_pre);
+                }
             }
             TPM_HIP(hipDeviceSynchronize());
         }
-        finish_index(G, acct, G.ptau, arena == nullptr);
+        finish_index(G, acct, G.ptau, arena == nullptr, gpos_pre);
         G.device_bytes = acct;
     } catch (...) {
         free_graph(G);

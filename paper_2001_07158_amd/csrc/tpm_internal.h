@@ -183,6 +183,8 @@ struct Graph {
     int32_t *gsrc = nullptr;   // [m] state row read by the edge (last in-edge of src
                                //     earlier than tau), -1 if none
     int32_t *orow = nullptr;   // [m] state row written at this position, -1 if none
+    int32_t *rowpos = nullptr; // [R] position that writes each state row (whole graphs
+                               //     only: pruning maps gsrc through it)
     int32_t *inptr = nullptr;  // [n+1]
     int32_t *tile_p0 = nullptr;   // [ntiles+1]
     int32_t *tile_pub = nullptr;  // [ntiles] slot this tile publishes to, -1 if none
