@@ -58,6 +58,9 @@ typedef int32_t tpm_status;
 
 /* graph creation flags */
 #define TPM_DEVICE_PTRS 0x1u /* src/dst/tau/color are device pointers */
+#define TPM_UNDIRECTED 0x2u  /* edge e is also the arc dst -> src at the same time (and
+                                transition time), with input edge id e + m; needs
+                                2m < 2^31 - 1 (the paper supports both kinds of graph) */
 
 /* A multiset entry that any vertex may take (section "Including wildcard entries":
  * every vertex also carries one extra colour).  Multisets hold colours in
@@ -326,6 +329,17 @@ tpm_status tpm_static_sieve(const tpm_graph *g, const int32_t *multiset, int32_t
  * TPM_EDEVICE. */
 tpm_status tpm_graph_prune_static(const tpm_graph *g, const int32_t *multiset, int32_t k,
                                   uint64_t seed, int32_t reps, tpm_graph **out);
+
+/* An optimum solution (sections "Finding optimum timestamp" and "Extracting a
+ * solution"): *t_out = tpm_optimum_time(g, multiset, k, seed, reps); then a path is
+ * extracted by `method` (as tpm_extract_ex, max_reps = reps, seeds derived from seed)
+ * on the subgraph of the edges that arrive by *t_out, so the path finishes by *t_out,
+ * the earliest finishing time unless every seed missed the earliest paths.  Returns
+ * TPM_NOTFOUND with *t_out = -1 when no seed finds a path, or when extraction misses on
+ * the subgraph.  2 <= k <= 16.  Errors: TPM_EINVAL, TPM_ENOMEM, TPM_EDEVICE. */
+tpm_status tpm_extract_optimum(const tpm_graph *g, const int32_t *multiset, int32_t k,
+                               uint64_t seed, int32_t reps, int32_t method, int32_t *t_out,
+                               int32_t *path_vertices, int64_t *path_edges);
 
 /* ---------------------------------------------------------------- batch --- */
 typedef struct {

@@ -672,7 +672,11 @@ tpm_status tpm_graph_prune_ex(const tpm_graph *g, const int32_t *colors, int32_t
         DeviceScope ds(g->G.device);
         auto *h = new tpm_graph();
         try {
-            prune_graph(g->G, keep.data(), ntimes ? ts.data() : nullptr, (int32_t)ts.size(), h->G);
+            PruneSpec spec;
+            spec.keep_color = keep.data();
+            spec.times = ntimes ? ts.data() : nullptr;
+            spec.ntimes = (int32_t)ts.size();
+            prune_graph(g->G, spec, h->G);
             h->G.pool = new_workspace_pool();
             h->G.apool = new_arena_pool();
         } catch (...) {
@@ -700,6 +704,40 @@ tpm_status tpm_graph_layer(const tpm_graph *g, const int32_t *tuple, int32_t k, 
         }
         *out = h;
         return TPM_OK;
+    });
+}
+
+tpm_status tpm_extract_optimum(const tpm_graph *g, const int32_t *multiset, int32_t k,
+                               uint64_t seed, int32_t reps, int32_t method, int32_t *t_out,
+                               int32_t *path_vertices, int64_t *path_edges) {
+    return guarded([&]() -> tpm_status {
+        TPM_REQUIRE(g && multiset && t_out && path_vertices && path_edges, "NULL argument");
+        TPM_REQUIRE(method >= 0 && method <= 2, "method must be 0, 1 or 2");
+        DeviceScope ds(g->G.device);
+        const Graph &G = g->G;
+        *t_out = optimum_time(G, multiset, k, seed, reps);
+        if (*t_out < 0) return TPM_NOTFOUND;
+        // the subgraph of the edges that arrive by the optimum: every path in it finishes
+        // by then, and it holds the optimal paths (same ids, so their fingerprints)
+        Graph P;
+        struct Own {
+            Graph &g;
+            ~Own() {
+                g.pool = nullptr;  // borrowed
+                free_graph(g);
+            }
+        } own{P};
+        PruneSpec spec;
+        spec.tcut = *t_out;
+        prune_graph(G, spec, P);
+        P.pool = G.pool;
+        const uint64_t s2 = seed + 0x5851F42D4C957F2Dull;  // fresh seeds for the extraction
+        if (method == 1)
+            return extract_selfreduce(P, multiset, k, s2, reps, path_vertices, path_edges, nullptr);
+        if (method == 2)
+            return extract_vertexloc(P, multiset, k, s2, reps, path_vertices, path_edges, nullptr,
+                                     kDfsBudget);
+        return extract_path(P, multiset, k, s2, reps, path_vertices, path_edges, nullptr);
     });
 }
 

@@ -366,7 +366,9 @@ void serve_pruned(tpm_server *s) {
                 }
             } fr{P};
             const double t0 = now_ms();
-            prune_graph(G, keep.data(), nullptr, 0, P, s->arena);
+            PruneSpec spec;
+            spec.keep_color = keep.data();
+            prune_graph(G, spec, P, s->arena);
             P.pool = s->ppool;
             const double t1 = now_ms();
             const bool want = rq->q.want_path || s->cfg.extract_paths;

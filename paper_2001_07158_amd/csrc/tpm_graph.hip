@@ -170,14 +170,15 @@ __device__ __forceinline__ bool vbit(const uint32_t *vbits, int32_t u) {
     return (vbits[u >> 5] >> (u & 31)) & 1u;
 }
 
-// (cut_in: a vertex whose in-edges go, cut_out: one whose out-edges go; -1 for none)
+// (cut_in: a vertex whose in-edges go, cut_out: one whose out-edges go; -1 for none;
+// parr: arrival times, kept up to tcut)
 __global__ void k_keep(int64_t m, const int32_t *psrc, const int32_t *pdst, const uint32_t *vbits,
                        const int32_t *ptime, const int32_t *ts, int32_t nts, int32_t cut_in,
-                       int32_t cut_out, int32_t *keep) {
+                       int32_t cut_out, const int32_t *parr, int32_t tcut, int32_t *keep) {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= m) return;
     const int32_t s = psrc[p], d = pdst[p];
-    bool k = vbit(vbits, s) && vbit(vbits, d) && d != cut_in && s != cut_out;
+    bool k = vbit(vbits, s) && vbit(vbits, d) && d != cut_in && s != cut_out && parr[p] <= tcut;
     if (k && ts) {
         const int32_t t = ptime[p];
         int32_t a = 0, b = nts;
@@ -419,7 +420,9 @@ void run_sieve_pruned(const Graph &G, const SieveRequest &req, SieveResult &res,
             pool->free_list.push_back(a);
         }
     } b{G.apool, arena, Graph()};
-    prune_graph(G, keep.data(), nullptr, 0, b.P, arena);
+    PruneSpec spec;
+    spec.keep_color = keep.data();
+    prune_graph(G, spec, b.P, arena);
     b.P.pool = G.pool;
     if (loc_by_edge) run_sieve_loc_all(b.P, req, res, loc_by_edge, st);
     else run_sieve(b.P, req, res, st);
@@ -728,7 +731,10 @@ void build_graph(Graph &G, int32_t n, int64_t m, const int32_t *src, const int32
     TPM_REQUIRE(T >= 1 && T <= 4096, "tile_edges must be in [1, 4096]");
     TPM_REQUIRE(!opt || opt->tile_held == 0, "tile_held is reserved and must be 0");
     const bool on_dev = (flags & TPM_DEVICE_PTRS) != 0;
-    TPM_REQUIRE((flags & ~TPM_DEVICE_PTRS) == 0, "unknown flag bits");
+    const bool undirected = (flags & TPM_UNDIRECTED) != 0;
+    TPM_REQUIRE((flags & ~(TPM_DEVICE_PTRS | TPM_UNDIRECTED)) == 0, "unknown flag bits");
+    TPM_REQUIRE(!undirected || 2 * m < (int64_t(1) << 31) - 1,
+                "an undirected graph needs 2m < 2^31 - 1");
 
     const int32_t *transit = opt ? opt->transit : nullptr;  // host, per edge
     const int32_t *delay = opt ? opt->delay : nullptr;      // host, per vertex
@@ -754,6 +760,17 @@ void build_graph(Graph &G, int32_t n, int64_t m, const int32_t *src, const int32
     if (delay)
         for (int32_t u = 0; u < n; ++u)
             TPM_REQUIRE(delay[u] >= 0 && delay[u] <= (1 << 30), "delays must be in [0, 2^30]");
+    // undirected: edge e is also the arc dst -> src, input id e + m, same time
+    const int64_t m_in = m;
+    std::vector<int32_t> transit2;
+    if (undirected) {
+        if (transit) {
+            transit2.assign(transit, transit + m_in);
+            transit2.insert(transit2.end(), transit, transit + m_in);
+            transit = transit2.data();
+        }
+        m = 2 * m_in;
+    }
 
     TPM_HIP(hipGetDevice(&G.device));
     hipDeviceProp_t prop;
@@ -784,10 +801,15 @@ void build_graph(Graph &G, int32_t n, int64_t m, const int32_t *src, const int32
         d_tau = dalloc<int32_t>(m, tmp);
         hipMemcpyKind kind = on_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
         TPM_HIP(hipMemcpy(G.color, color, sizeof(int32_t) * n, kind));
-        if (m) {
-            TPM_HIP(hipMemcpy(d_src, src, sizeof(int32_t) * m, kind));
-            TPM_HIP(hipMemcpy(d_dst, dst, sizeof(int32_t) * m, kind));
-            TPM_HIP(hipMemcpy(d_tau, tau, sizeof(int32_t) * m, kind));
+        if (m_in) {
+            TPM_HIP(hipMemcpy(d_src, src, sizeof(int32_t) * m_in, kind));
+            TPM_HIP(hipMemcpy(d_dst, dst, sizeof(int32_t) * m_in, kind));
+            TPM_HIP(hipMemcpy(d_tau, tau, sizeof(int32_t) * m_in, kind));
+            if (undirected) {
+                TPM_HIP(hipMemcpy(d_src + m_in, dst, sizeof(int32_t) * m_in, kind));
+                TPM_HIP(hipMemcpy(d_dst + m_in, src, sizeof(int32_t) * m_in, kind));
+                TPM_HIP(hipMemcpy(d_tau + m_in, tau, sizeof(int32_t) * m_in, kind));
+            }
         }
         if (on_dev) {
             int32_t *flagbuf = dalloc<int32_t>(2, tmp);
@@ -869,9 +891,10 @@ void build_graph(Graph &G, int32_t n, int64_t m, const int32_t *src, const int32
     cleanup_tmp();
 }
 
-void prune_graph(const Graph &P, const uint8_t *keep_color, const int32_t *times, int32_t ntimes,
-                 Graph &G, GraphArena *arena, int32_t cut_in, int32_t cut_out,
-                 const uint8_t *vkeep_in) {
+void prune_graph(const Graph &P, const PruneSpec &spec, Graph &G, GraphArena *arena) {
+    const uint8_t *keep_color = spec.keep_color, *vkeep_in = spec.vkeep;
+    const int32_t *times = spec.times;
+    const int32_t ntimes = spec.ntimes;
     TPM_HIP(hipSetDevice(P.device));
     G.device = P.device;
     G.num_cu = P.num_cu;
@@ -919,7 +942,8 @@ void prune_graph(const Graph &P, const uint8_t *keep_color, const int32_t *times
                 // timestamps of the edges as given (departures when transit times exist)
                 k_keep<<<grid_for(P.m), 256, 0, st>>>(P.m, P.psrc, P.pdst, vbits,
                                                        P.pdep ? P.pdep : P.ptau, ts, ntimes,
-                                                       cut_in, cut_out, keep);
+                                                       spec.cut_in, spec.cut_out, P.ptau,
+                                                       spec.tcut, keep);
                 size_t sbytes = 0;
                 TPM_HIP(rocprim::exclusive_scan(nullptr, sbytes, keep, at, 0, (size_t)P.m,
                                                 rocprim::plus<int32_t>(), st));
@@ -975,7 +999,10 @@ void sd_graph(const Graph &P, int32_t s, int32_t d, Graph &G) {
     TPM_REQUIRE(s >= 0 && s < P.n && d >= 0 && d < P.n, "vertex out of range");
     TPM_REQUIRE(s != d, "s and d must differ");
     TPM_REQUIRE(P.q <= (int32_t)0x7FFFFFFD, "too many colours");
-    prune_graph(P, nullptr, nullptr, 0, G, nullptr, s, d);
+    PruneSpec spec;
+    spec.cut_in = s;
+    spec.cut_out = d;
+    prune_graph(P, spec, G);
     try {
         G.q = P.q + 2;
         const int32_t cs = P.q, cd = P.q + 1;

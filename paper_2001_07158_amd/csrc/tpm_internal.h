@@ -224,15 +224,19 @@ void retile_graph(Graph &G, int32_t T);
 // keep_color[c] != 0 (host, P.q bytes).  Vertex ids, colours and input edge ids are
 // kept, so every fingerprint, and every sieve whose colours are all kept, is
 // unchanged.  G must be empty; on error G is freed.
+// Which edges a pruned graph keeps: both endpoints kept and every other condition met.
+struct PruneSpec {
+    const uint8_t *keep_color = nullptr;  // host [P.q]; nullable: every colour
+    const int32_t *times = nullptr;       // host, sorted, distinct; nullable: every
+    int32_t ntimes = 0;                   //   timestamp (else departures in the set)
+    int32_t cut_in = -1, cut_out = -1;    // a vertex whose in- / out-edges go (-1: none)
+    const uint8_t *vkeep = nullptr;       // device [P.n]; nullable: every vertex
+    int32_t tcut = 0x7FFFFFFF;            // keep edges that arrive by tcut
+};
 // With an arena, G's arrays and the build's temporaries live in the arena's grow-only
 // buffers (reused by the next graph built there; G must be freed before that).
-// keep_color nullable (all colours kept); times (host, sorted, distinct, nullable):
-// keep only edges whose timestamp (departure) is one of them.
-// cut_in / cut_out (-1: none): a vertex whose in-edges / out-edges are dropped.
-// vkeep_in (device [P.n], nullable): keep only edges between vertices it marks.
-void prune_graph(const Graph &P, const uint8_t *keep_color, const int32_t *times, int32_t ntimes,
-                 Graph &G, GraphArena *arena = nullptr, int32_t cut_in = -1, int32_t cut_out = -1,
-                 const uint8_t *vkeep_in = nullptr);
+// Vertex ids, colours, timestamps and input edge ids are P's.
+void prune_graph(const Graph &P, const PruneSpec &spec, Graph &G, GraphArena *arena = nullptr);
 // (s,d)-COLORFUL-PATH: G = P with colour q on s and q + 1 on d (q + 2 colours), s's
 // in-edges and d's out-edges removed.
 void sd_graph(const Graph &P, int32_t s, int32_t d, Graph &G);
@@ -296,6 +300,9 @@ void run_sieve_sink(const Graph &G, const SieveRequest &req, SieveResult &res, L
 
 // Vertex localisation of one sieve: q[u] (host, G.n bytes) = XOR of the per-edge
 // localisation over u's in-edges (the sieve over walks ending at u).
+// Optimum timestamp (smallest t whose time-restricted sieve is nonzero, minimised over
+// reps seeds seed + r * 0x9E3779B97F4A7C15); -1 if no seed finds a path.
+int32_t optimum_time(const Graph &G, const int32_t *M, int32_t k, uint64_t seed, int32_t reps);
 // Returns the sieve total (the XOR of the q[u]).
 uint8_t vertex_localise(const Graph &G, const SieveRequest &req, uint8_t *q, hipStream_t st);
 // Extraction by vertex localisation (section "Extracting a solution", second

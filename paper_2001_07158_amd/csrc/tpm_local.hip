@@ -154,6 +154,30 @@ struct StaticHolder {
 
 }  // namespace
 
+int32_t optimum_time(const Graph &G, const int32_t *M, int32_t k, uint64_t seed, int32_t reps) {
+    check_k(k);
+    TPM_REQUIRE(reps >= 1, "reps must be >= 1");
+    int32_t best = -1;
+    for (int32_t r = 0; r < reps; ++r) {
+        SieveRequest req;
+        req.multiset = M;
+        req.k = k;
+        req.seed = seed + (uint64_t)r * 0x9E3779B97F4A7C15ull;
+        SieveResult res;
+        if (G.m == 0) {
+            run_sieve(G, req, res, nullptr);
+            continue;
+        }
+        TimeSink sink;
+        run_sieve_sink(G, req, res, sink, nullptr);
+        if (sink.first != ~0ull && (int64_t)sink.first < G.ntimes) {
+            const int32_t t = G.h_ttab[(size_t)sink.first];
+            if (best < 0 || t < best) best = t;
+        }
+    }
+    return best;
+}
+
 uint8_t vertex_localise(const Graph &G, const SieveRequest &req, uint8_t *q, hipStream_t st) {
     SieveResult res;
     if (G.m == 0) {
@@ -217,28 +241,8 @@ tpm_status tpm_optimum_time(const tpm_graph *g, const int32_t *multiset, int32_t
                             int32_t reps, int32_t *t_out) {
     return guarded_call([&]() -> tpm_status {
         TPM_REQUIRE(g && t_out, "NULL argument");
-        check_k(k);
-        TPM_REQUIRE(reps >= 1, "reps must be >= 1");
         DeviceGuard dg(g->G.device);
-        const Graph &G = g->G;
-        *t_out = -1;
-        for (int32_t r = 0; r < reps; ++r) {
-            SieveRequest req;
-            req.multiset = multiset;
-            req.k = k;
-            req.seed = seed + (uint64_t)r * 0x9E3779B97F4A7C15ull;
-            SieveResult res;
-            if (G.m == 0) {
-                run_sieve(G, req, res, nullptr);
-                continue;
-            }
-            TimeSink sink;
-            run_sieve_sink(G, req, res, sink, nullptr);
-            if (sink.first != ~0ull && (int64_t)sink.first < G.ntimes) {
-                const int32_t t = G.h_ttab[(size_t)sink.first];
-                if (*t_out < 0 || t < *t_out) *t_out = t;
-            }
-        }
+        *t_out = optimum_time(g->G, multiset, k, seed, reps);
         return TPM_OK;
     });
 }
@@ -289,7 +293,9 @@ tpm_status tpm_graph_prune_static(const tpm_graph *g, const int32_t *multiset, i
         }
         auto *hnd = new tpm_graph();
         try {
-            prune_graph(G, nullptr, nullptr, 0, hnd->G, nullptr, -1, -1, keep.as<uint8_t>());
+            PruneSpec spec;
+            spec.vkeep = keep.as<uint8_t>();
+            prune_graph(G, spec, hnd->G);
             hnd->G.pool = new_workspace_pool();
             hnd->G.apool = new_arena_pool();
         } catch (...) {

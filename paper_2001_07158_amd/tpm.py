@@ -24,6 +24,7 @@ TPM_EDEVICE = -3
 TPM_ECANCELLED = -4
 TPM_ECLOSED = -5
 TPM_DEVICE_PTRS = 0x1
+TPM_UNDIRECTED = 0x2
 TPM_WILDCARD = -1
 
 if not os.path.exists(LIB_PATH):
@@ -111,6 +112,8 @@ _sig("tpm_graph_retile", ctypes.c_int32, [_vp, ctypes.c_int32])
 _sig("tpm_graph_layer", ctypes.c_int32, [_vp, _i32p, ctypes.c_int32, ctypes.POINTER(_vp)])
 _sig("tpm_graph_vertex_ids", ctypes.c_int32, [_vp, _i32p])
 _sig("tpm_graph_sd", ctypes.c_int32, [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(_vp)])
+_sig("tpm_extract_optimum", ctypes.c_int32, [_vp, _i32p, ctypes.c_int32, ctypes.c_uint64,
+                                            ctypes.c_int32, ctypes.c_int32, _i32p, _i32p, _i64p])
 _sig("tpm_static_sieve", ctypes.c_int32, [_vp, _i32p, ctypes.c_int32, ctypes.c_uint64, _u8p])
 _sig("tpm_graph_prune_static", ctypes.c_int32, [_vp, _i32p, ctypes.c_int32, ctypes.c_uint64,
                                                ctypes.c_int32, ctypes.POINTER(_vp)])
@@ -153,6 +156,7 @@ EXPORTED = ["tpm_graph_create", "tpm_graph_create_ex", "tpm_graph_destroy", "tpm
             "tpm_graph_layer", "tpm_graph_sd", "tpm_graph_vertex_ids", "tpm_sieve_vertex", "tpm_time_buckets",
             "tpm_optimum_time", "tpm_static_sieve", "tpm_graph_prune_static",
             "tpm_sieve", "tpm_sieve_ex", "tpm_decide", "tpm_extract", "tpm_extract_ex",
+            "tpm_extract_optimum",
             "tpm_batch_run",
             "tpm_server_create", "tpm_server_submit", "tpm_server_poll", "tpm_server_destroy",
             "tpm_server_stats_get", "tpm_rainbow_decide",
@@ -272,6 +276,21 @@ def tpm_extract(h, multiset, seed, max_reps=8):
                                  int(max_reps), pv.ctypes.data_as(_i32p), pe.ctypes.data_as(_i64p)),
                 ok=(TPM_OK, TPM_NOTFOUND))
     return rc, pv, pe[: k - 1]
+
+
+def tpm_extract_optimum(h, multiset, seed, reps=4, method=0):
+    """Returns (status, t, vertices[k], edges[k-1]): the optimum finishing time and a
+    path that finishes by it."""
+    M = _i32(multiset)
+    k = int(M.shape[0])
+    t = ctypes.c_int32(-1)
+    pv = np.full(k, -1, dtype=np.int32)
+    pe = np.full(max(1, k - 1), -1, dtype=np.int64)
+    rc = _check(_lib.tpm_extract_optimum(h, M.ctypes.data_as(_i32p), k, int(seed) & (2**64 - 1),
+                                         int(reps), int(method), ctypes.byref(t),
+                                         pv.ctypes.data_as(_i32p), pe.ctypes.data_as(_i64p)),
+                ok=(TPM_OK, TPM_NOTFOUND))
+    return rc, int(t.value), pv, pe[: k - 1]
 
 
 def tpm_extract_ex(h, multiset, seed, max_reps=8, method=0):
@@ -466,10 +485,11 @@ def tpm_profile_read(max_items: int = 4096):
 # ------------------------------------------------------------------ owners
 class Graph:
     def __init__(self, n, src, dst, tau, color, num_colors, tile_edges=0, tile_held=0,
-                 transit=None, delay=None):
+                 transit=None, delay=None, undirected=False):
         self.n = int(n)
-        self.m = int(len(src))
-        self.h = tpm_graph_create(n, src, dst, tau, color, num_colors, 0, tile_edges, tile_held,
+        self.m = int(len(src)) * (2 if undirected else 1)
+        self.h = tpm_graph_create(n, src, dst, tau, color, num_colors,
+                                  TPM_UNDIRECTED if undirected else 0, tile_edges, tile_held,
                                   transit, delay)
 
     @classmethod
@@ -537,6 +557,9 @@ class Graph:
 
     def extract_ex(self, multiset, seed, max_reps=8, method=0):
         return tpm_extract_ex(self.h, multiset, seed, max_reps, method)
+
+    def extract_optimum(self, multiset, seed, reps=4, method=0):
+        return tpm_extract_optimum(self.h, multiset, seed, reps, method)
 
     def batch(self, queries, chunk=0, use_graph=False, prune=False):
         return tpm_batch_run(self.h, queries, chunk, use_graph, prune)

@@ -93,3 +93,30 @@ def test_local_degenerate(tpm):
     with pytest.raises(tpm.TpmError):
         Gd.sieve_vertex([0], 3)  # k = 1 has no edges to localise
     Gd.close()
+
+
+@pytest.mark.parametrize("method", [0, 1, 2])
+def test_extract_optimum_against_exhaustive_search(tpm, method):
+    """An optimum solution: the optimum time, then a path on the subgraph of edges that
+    arrive by it; the path is valid and finishes by that time, which is never below the
+    exhaustive-search optimum and equals it on nearly every instance."""
+    rng = np.random.default_rng(74 + method)
+    exact = total = 0
+    for it in range(30):
+        g = G.random_tiny_graph(rng, n_max=10, m_max=30, t_max=8)
+        k = int(rng.integers(2, 5))
+        M = [int(c) for c in rng.integers(0, g.num_colors, k)]
+        best = pyref.brute_optimum_time(g, M)
+        say(f"case optimum-extract m{method} {it}: n={g.n} m={g.m} M={M} best={best}")
+        Gd = tpm.Graph.from_temporal(g)
+        rc, t, verts, edges = Gd.extract_optimum(M, 700 + it, reps=4, method=method)
+        Gd.close()
+        if best < 0:
+            assert rc == tpm.TPM_NOTFOUND and t == -1
+            continue
+        total += 1
+        if rc == tpm.TPM_OK:
+            assert pyref.check_path(g, M, verts, edges)
+            assert t >= best and int(g.tau[edges[-1]]) <= t
+            exact += int(g.tau[edges[-1]]) == best
+    assert total > 5 and exact >= total - 3

@@ -430,3 +430,30 @@ def test_vertexloc_extraction_planted(tpm):
     rc0, pv0, pe0, _ = Gd.extract_ex(M, 11, max_reps=8, method=0)
     assert rc0 == tpm.TPM_OK and pyref.check_path(h, M, pv0, pe0)
     Gd.close()
+
+
+def test_undirected_graphs(tpm):
+    """TPM_UNDIRECTED: each edge also runs dst -> src (input id e + m); results equal the
+    oracle's on the explicitly doubled edge list, with and without transition times."""
+    rng = np.random.default_rng(195)
+    for it in range(30):
+        g = G.random_tiny_graph(rng, n_max=30, m_max=150, t_max=8, q_max=4)
+        k = int(rng.integers(1, 7))
+        M = [int(c) for c in rng.integers(0, g.num_colors, k)]
+        tr = rng.integers(0, 3, g.m).astype(np.int32) if it % 3 == 2 else None
+        d = G.TemporalGraph(g.n, np.concatenate([g.src, g.dst]), np.concatenate([g.dst, g.src]),
+                            np.concatenate([g.tau, g.tau]), g.color, g.num_colors)
+        tr2 = None if tr is None else np.concatenate([tr, tr])
+        say(f"case undirected {it}: n={g.n} m={g.m} M={M} transit={tr is not None}")
+        Gd = tpm.Graph(g.n, g.src, g.dst, g.tau, g.color, g.num_colors, transit=tr,
+                       undirected=True, tile_edges=int(rng.integers(1, 64)))
+        assert Gd.stats()["m"] == 2 * g.m and Gd.stats()["edge_ids"] == 2 * g.m
+        pp, tot, loc = Gd.sieve(M, 900 + it, loc=True)
+        wpp, wloc = oracle.sieve(d, M, 900 + it, loc=True, transit=tr2)
+        assert np.array_equal(pp, wpp), it
+        assert np.array_equal(loc, wloc), it
+        if k >= 2 and tot:
+            rc, verts, edges = Gd.extract(M, 900 + it)
+            assert rc == tpm.TPM_OK
+            assert pyref.check_path(d, M, verts, edges, tr2)
+        Gd.close()
