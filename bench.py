@@ -65,7 +65,8 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="k10", choices=["k10", "k5", "tiny", "batched", "serving"])
+    ap.add_argument("--workload", default="k10",
+                    choices=["k10", "k5", "tiny", "batched", "serving", "preproc"])
     ap.add_argument("--queries", type=int, default=0,
                     help="batched/serving: number of queries (default 256 / 120)")
     ap.add_argument("--scale", type=float, default=1.0,
@@ -108,6 +109,8 @@ def main() -> int:
         return bench_batched(args)
     if args.workload == "serving":
         return bench_serving(args)
+    if args.workload == "preproc":
+        return bench_preproc(args)
 
     cfg = CONFIGS[args.workload]
     t_gen = time.perf_counter()
@@ -511,6 +514,64 @@ def bench_serving(args) -> int:
     print(json.dumps(line), flush=True)
     G.close()
     return 0 if same else 1
+
+
+def bench_preproc(args) -> int:
+    """The paper's preprocessing / vertex-localisation experiment on its own kind of
+    input: random 20-regular undirected graphs (configuration model), t = 100, k = 8,
+    n = 1e2 .. 1e5.  PATH-MOTIF: 30 colours, a random multiset of 8; COLORFUL-PATH: 8
+    colours, the multiset {0..7}.  Extraction time (median over instances) with the
+    self-reducibility method, with preprocessing step (ii) first (3 seeds), with the
+    vertex-localisation method, and with both."""
+    import numpy as np
+    from paper_2001_07158_amd import tpm
+    from synth import regular_graph
+
+    d, t, k = 20, 100, 8
+    ninst = 3
+    rows = []
+    for problem, q in (("PATH-MOTIF", 30), ("COLORFUL-PATH", k)):
+        for n in (100, 1_000, 10_000, 100_000):
+            res = {"algebraic": [], "pre": [], "vloc": [], "pre+vloc": []}
+            found = {key: 0 for key in res}
+            m_kept = []
+            for inst in range(ninst):
+                seed = 1000 * n + 17 * inst + (0 if problem == "PATH-MOTIF" else 7)
+                g = regular_graph(n, d, t, q, seed)
+                rng = np.random.default_rng(seed)
+                M = ([int(c) for c in rng.integers(0, q, k)] if problem == "PATH-MOTIF"
+                     else list(range(k)))
+                G = tpm.Graph(g.n, g.src, g.dst, g.tau, g.color, q, undirected=True)
+                G.extract_ex(M, 1, max_reps=2, method=2)  # warm-up
+                for key in res:
+                    t0 = time.perf_counter()
+                    H = G
+                    if key.startswith("pre"):
+                        H = G.prune_static(M, seed, reps=3)
+                        if key == "pre":
+                            m_kept.append(H.m)
+                    rc = H.extract_ex(M, seed, max_reps=4, method=2 if key.endswith("vloc") else 1)[0]
+                    res[key].append((time.perf_counter() - t0) * 1e3)
+                    found[key] += rc == tpm.TPM_OK
+                    if H is not G:
+                        H.close()
+                G.close()
+            row = {"problem": problem, "n": n, "m_undirected": n * d // 2, "instances": ninst,
+                   "m_arcs_after_pre_median": float(np.median(m_kept)),
+                   **{f"{key}_ms": float(np.median(v)) for key, v in res.items()},
+                   "found": found}
+            row["speedup_pre"] = row["algebraic_ms"] / row["pre_ms"]
+            row["speedup_vloc"] = row["algebraic_ms"] / row["vloc_ms"]
+            row["speedup_pre_vloc"] = row["algebraic_ms"] / row["pre+vloc_ms"]
+            rows.append(row)
+            _log(f"# {problem} n={n}: " + ", ".join(f"{key} {row[key + '_ms']:.1f} ms" for key in res)
+                 + f", arcs after (ii) {row['m_arcs_after_pre_median']:.0f} of {n * d}, found {found}")
+    line = {"metric": "extraction ms with preprocessing step (ii) and vertex localisation (k = 8)",
+            "unit": "ms", "n_gpus": 1, "higher_is_better": False, "dtype": "u8", "data": "synthetic",
+            "config": {"workload": "preproc: random 20-regular undirected graphs, t = 100, k = 8"},
+            "rows": rows}
+    print(json.dumps(line), flush=True)
+    return 0
 
 
 if __name__ == "__main__":

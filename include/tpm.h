@@ -71,7 +71,10 @@ typedef int32_t tpm_status;
 typedef struct tpm_graph tpm_graph;
 
 /* Options of graph creation.  Zero / NULL fields take the default.
- * tile_edges: T, the work-tile size in CSR positions (1..4096, default 1024).
+ * tile_edges: T, the work-tile size in CSR positions (1..4096; default
+ *             min(1024, max(128, m / 4096)), so that small graphs still have more tiles
+ *             than the GPU has waves; subgraphs built from a graph with the default
+ *             choose it again for their own m).
  *             In-lists longer than T are cut into pieces of T positions that add the
  *             running value of their predecessors by look-back; shorter ones stay
  *             whole, grouped by the T-aligned window of their first position (a

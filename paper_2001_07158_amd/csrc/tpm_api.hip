@@ -288,6 +288,15 @@ tpm_status extract_path(const Graph &G, const int32_t *M, int32_t k, uint64_t se
     return TPM_OK;
 }
 
+// inc[u] = 1 for the endpoints of every edge
+__global__ void k_incident(int64_t m, const int32_t *psrc, const int32_t *pdst, uint8_t *inc) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < m) {
+        inc[psrc[p]] = 1;
+        inc[pdst[p]] = 1;
+    }
+}
+
 // Self-reducibility (section "Extracting a solution", first approach): delete vertex
 // groups while the decision oracle stays YES, halving a group that cannot go (group
 // testing, O(k log n) decisions), then find the path among the survivors by temporal
@@ -305,11 +314,20 @@ tpm_status extract_selfreduce(const Graph &G, const int32_t *M, int32_t k, uint6
         if (M[i] < 0) wild = true;
         else in_m[(size_t)M[i]] = 1;
     }
-    // vertices of other colours are on no matching path
+    // vertices of other colours, and vertices without edges, are on no matching path
+    std::vector<uint8_t> inc((size_t)G.n, 0);
+    if (G.m) {
+        DBuf d;
+        d.alloc((size_t)G.n, nullptr);
+        TPM_HIP(hipMemset(d.p, 0, (size_t)G.n));
+        k_incident<<<(unsigned)std::max<int64_t>(1, (G.m + 255) / 256), 256>>>(
+            G.m, G.psrc, G.pdst, d.as<uint8_t>());
+        TPM_HIP(hipMemcpy(inc.data(), d.p, (size_t)G.n, hipMemcpyDeviceToHost));
+    }
     std::vector<uint8_t> mask((size_t)G.n, 0);
     std::vector<int32_t> cand;
     for (int32_t u = 0; u < G.n; ++u)
-        if (wild || in_m[(size_t)G.h_color[(size_t)u]]) {
+        if (inc[(size_t)u] && (wild || in_m[(size_t)G.h_color[(size_t)u]])) {
             mask[(size_t)u] = 1;
             cand.push_back(u);
         }

@@ -618,6 +618,12 @@ const std::vector<uint8_t> &lds_image_host() {
 
 }  // namespace
 
+int32_t auto_tile_edges(int64_t m) {
+    // a sweep of T = 64..1024 (k = 8 sieves): best 128 at m = 2e4 and 2e5, 512 at 2e6,
+    // 1024 at 1e7 (k = 5) and above
+    return (int32_t)std::min<int64_t>(1024, std::max<int64_t>(128, m / 4096));
+}
+
 void free_graph(Graph &G) {
     int32_t **ptrs[] = {&G.color, &G.pdst,  &G.psrc,    &G.ptau,     &G.peid,   &G.gsrc,
                         &G.orow,  &G.inptr, &G.tile_p0, &G.tile_pub, &G.tile_lb,
@@ -726,9 +732,9 @@ void build_graph(Graph &G, int32_t n, int64_t m, const int32_t *src, const int32
     TPM_REQUIRE(num_colors >= 1, "num_colors must be >= 1");
     TPM_REQUIRE(m == 0 || (src && dst && tau), "edge arrays must not be NULL");
     TPM_REQUIRE(color != nullptr, "color must not be NULL");
-    int T = 1024;
+    int T = 0;  // 0: chosen from m below
     if (opt && opt->tile_edges) T = opt->tile_edges;
-    TPM_REQUIRE(T >= 1 && T <= 4096, "tile_edges must be in [1, 4096]");
+    TPM_REQUIRE(T == 0 || (T >= 1 && T <= 4096), "tile_edges must be in [1, 4096]");
     TPM_REQUIRE(!opt || opt->tile_held == 0, "tile_held is reserved and must be 0");
     const bool on_dev = (flags & TPM_DEVICE_PTRS) != 0;
     const bool undirected = (flags & TPM_UNDIRECTED) != 0;
@@ -779,7 +785,8 @@ void build_graph(Graph &G, int32_t n, int64_t m, const int32_t *src, const int32
     G.n = n;
     G.m = m;
     G.q = num_colors;
-    G.tile_edges = T;
+    G.tile_auto = T == 0;
+    G.tile_edges = T ? T : auto_tile_edges(m);
     G.edge_ids = m;
     int64_t acct = 0;
     hipStream_t st = nullptr;
@@ -956,6 +963,8 @@ void prune_graph(const Graph &P, const PruneSpec &spec, Graph &G, GraphArena *ar
                 mk = (int64_t)last_at + last_keep;
             }
             G.m = mk;
+            G.tile_auto = P.tile_auto;
+            if (P.tile_auto) G.tile_edges = auto_tile_edges(mk);
             G.pdst = galloc<int32_t>(G, A_PDST, mk, acct);
             G.psrc = galloc<int32_t>(G, A_PSRC, mk, acct);
             G.ptau = galloc<int32_t>(G, A_PTAU, mk, acct);
@@ -1103,6 +1112,8 @@ void layer_graph(const Graph &P, const int32_t *tuple, int32_t k, Graph &G) {
         const int64_t mk = off[(size_t)k + 1];
         TPM_REQUIRE(mk < (int64_t(1) << 31) - 1, "layered graph has too many edges");
         G.m = mk;
+        G.tile_auto = P.tile_auto;
+        if (P.tile_auto) G.tile_edges = auto_tile_edges(mk);
         G.pdst = dalloc<int32_t>(mk, acct);
         G.psrc = dalloc<int32_t>(mk, acct);
         G.ptau = dalloc<int32_t>(mk, acct);
@@ -1169,6 +1180,7 @@ void retile_graph(Graph &G, int32_t T) {
     G.ntiles = nt;
     G.nslots = nslots;
     G.tile_edges = T;
+    G.tile_auto = false;
     G.device_bytes += acct - old_bytes;
 }
 

@@ -165,6 +165,7 @@ struct Graph {
     int32_t q = 0;
     int32_t tmax = 0;
     int32_t tile_edges = 1024;
+    bool tile_auto = true;     // tile_edges chosen from m (not set by the caller)
     int64_t R = 0;        // stored rows per level
     int64_t ntiles = 0;
     int64_t nslots = 0;
@@ -217,6 +218,9 @@ void build_graph(Graph &G, int32_t n, int64_t m, const int32_t *src, const int32
                  const int32_t *tau, const int32_t *color, int32_t num_colors, uint32_t flags,
                  const tpm_graph_options *opt);
 void free_graph(Graph &G);
+// Default work-tile size: 1024 positions, fewer for small graphs so that the tiles
+// (each walked by one wave) still outnumber the waves of the GPU.
+int32_t auto_tile_edges(int64_t m);
 // Rebuilds the work tiles with at most T positions each (results do not depend on
 // T).  Waits for the device; must not overlap other calls on the same graph.
 void retile_graph(Graph &G, int32_t T);

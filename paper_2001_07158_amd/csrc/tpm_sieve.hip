@@ -1337,15 +1337,23 @@ QuerySlots make_slots(const Graph &G, const int32_t *M, int32_t k) {
     return qs;
 }
 
+// Persistent grid: one 1024-thread workgroup per CU (a small launch still spreads its
+// tiles over as many CUs as it has)
+unsigned persistent_grid(const Graph &G, int64_t tiles) {
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(G.num_cu, tiles));
+}
+
 template <int W, bool FIN>
 void launch_level(const Graph &G, const LevelParams &P, hipStream_t st) {
-    hipLaunchKernelGGL((k_level<W, FIN>), dim3((unsigned)G.num_cu), dim3(1024), 0, st, P);
+    hipLaunchKernelGGL((k_level<W, FIN>), dim3(persistent_grid(G, P.tile_hi - P.tile_lo)),
+                       dim3(1024), 0, st, P);
 }
 
 template <int LP>
 void launch_narrow(bool fin, const Graph &G, const LevelParams &P, hipStream_t st) {
-    if (fin) hipLaunchKernelGGL((k_narrow<LP, true>), dim3((unsigned)G.num_cu), dim3(1024), 0, st, P);
-    else hipLaunchKernelGGL((k_narrow<LP, false>), dim3((unsigned)G.num_cu), dim3(1024), 0, st, P);
+    const dim3 grid(persistent_grid(G, P.tile_hi - P.tile_lo));
+    if (fin) hipLaunchKernelGGL((k_narrow<LP, true>), grid, dim3(1024), 0, st, P);
+    else hipLaunchKernelGGL((k_narrow<LP, false>), grid, dim3(1024), 0, st, P);
 }
 
 // rows of 16..256 points run edge-parallel (k_narrow); rows of 512 and 1024 points run
@@ -1373,9 +1381,10 @@ void launch_level_any(int rowb, bool fin, const Graph &G, const LevelParams &P, 
 }
 
 void launch_step_w(int W, const Graph &G, const StepParams &P, hipStream_t st) {
-    if (W == 4) hipLaunchKernelGGL((k_step<4>), dim3((unsigned)G.num_cu), dim3(1024), 0, st, P);
-    else if (W == 2) hipLaunchKernelGGL((k_step<2>), dim3((unsigned)G.num_cu), dim3(1024), 0, st, P);
-    else hipLaunchKernelGGL((k_step<1>), dim3((unsigned)G.num_cu), dim3(1024), 0, st, P);
+    const dim3 grid(persistent_grid(G, P.ntiles));
+    if (W == 4) hipLaunchKernelGGL((k_step<4>), grid, dim3(1024), 0, st, P);
+    else if (W == 2) hipLaunchKernelGGL((k_step<2>), grid, dim3(1024), 0, st, P);
+    else hipLaunchKernelGGL((k_step<1>), grid, dim3(1024), 0, st, P);
 }
 
 int pick_chunk(const Graph &G, int32_t k, int32_t requested) {

@@ -9,6 +9,7 @@ from .graphs import (  # noqa: F401
     TemporalGraph,
     uniform_graph,
     chung_lu_graph,
+    regular_graph,
     paper_toy_graph,
     random_tiny_graph,
     relabel_timestamps,

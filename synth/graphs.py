@@ -62,6 +62,25 @@ def uniform_graph(n: int, m: int, t: int, q: int, seed: int,
                          tau.astype(np.int32), color.astype(np.int32), q)
 
 
+def regular_graph(n: int, d: int, t: int, q: int, seed: int) -> TemporalGraph:
+    """Random d-regular undirected multigraph by the configuration model (n d stubs,
+    a uniform random pairing; n d must be even), one timestamp per edge ~ U[1, t],
+    colours ~ U[0, q).  The edge list holds each undirected edge once (u, v); build
+    the device graph with the undirected flag.  The pairing may leave a few loops
+    and parallel edges, as the model does."""
+    if (n * d) % 2:
+        raise ValueError("n d must be even")
+    rng = np.random.default_rng(seed)
+    stubs = np.repeat(np.arange(n, dtype=np.int64), d)
+    rng.shuffle(stubs)
+    src, dst = stubs[0::2], stubs[1::2]
+    m = src.shape[0]
+    tau = rng.integers(1, t + 1, m, dtype=np.int64)
+    color = rng.integers(0, q, n, dtype=np.int64)
+    return TemporalGraph(n, src.astype(np.int32), dst.astype(np.int32), tau.astype(np.int32),
+                         color.astype(np.int32), q)
+
+
 def _alias_sampler(rng, weights: np.ndarray):
     """Draws indices with probability proportional to `weights` (Walker's alias
     method, Vose's construction)."""
