@@ -252,9 +252,11 @@ tpm_status tpm_sieve_ex(const tpm_graph *g, const int32_t *multiset, int32_t k, 
 tpm_status tpm_decide(const tpm_graph *g, const int32_t *multiset, int32_t k, uint64_t seed,
                       int32_t reps, int32_t *found);
 
-/* Extract a matching temporal path by self-reduction (section "Extracting a
- * solution"): localise the last edge (u' -> u, tau), delete u, drop c(u) from
- * M, and repeat on the in-edges of u' earlier than tau until one vertex is left.
+/* Extract a matching temporal path (section "Extracting a solution"): first the
+ * vertex-localisation approach (tpm_extract_ex method 2, with a DFS budget of 5e6
+ * edge visits), then, if that finds nothing, the localisation-guided self-reduction
+ * (method 0: localise the last edge (u' -> u, tau), delete u, drop c(u) from M, and
+ * repeat on the in-edges of u' earlier than tau until one vertex is left).
  * On TPM_OK, path_vertices[0..k) and path_edges[0..k-1) (input edge ids) hold a
  * path that the library has verified (strictly increasing times, distinct
  * vertices, colours = M).  TPM_NOTFOUND: no path found within max_reps seeds
@@ -263,7 +265,7 @@ tpm_status tpm_extract(const tpm_graph *g, const int32_t *multiset, int32_t k, u
                        int32_t max_reps, int32_t *path_vertices, int64_t *path_edges);
 
 /* As tpm_extract with a choice of method, and the number of sieves run (nullable).
- * method 0: the localisation-guided self-reduction of tpm_extract (about k sieves).
+ * method 0: the localisation-guided self-reduction (about k sieves).
  * method 1: the paper's self-reducibility (section "Extracting a solution", first
  *           approach): vertices of other colours are dropped, then vertex groups are
  *           deleted while a decision (max_reps sieves) stays YES, halving groups that

@@ -959,6 +959,11 @@ tpm_status tpm_extract(const tpm_graph *g, const int32_t *multiset, int32_t k, u
     return guarded([&]() -> tpm_status {
         TPM_REQUIRE(g && multiset && path_vertices && (k < 2 || path_edges), "NULL argument");
         DeviceScope ds(g->G.device);
+        // the vertex-localisation DFS (one sieve) with a bounded budget, then the
+        // localisation-guided self-reduction
+        if (k >= 2 && extract_vertexloc(g->G, multiset, k, seed, max_reps, path_vertices,
+                                        path_edges, nullptr, kQuickDfsBudget) == TPM_OK)
+            return TPM_OK;
         return extract_path(g->G, multiset, k, seed, max_reps, path_vertices, path_edges, nullptr);
     });
 }

@@ -76,9 +76,6 @@ void check_query(const Graph &G, const tpm_query &q) {
         TPM_REQUIRE(q.multiset[i] >= -1 && q.multiset[i] < G.q, "multiset colour out of range");
 }
 
-// DFS budget of extraction on a hit: the vertex-localisation DFS gives up after this
-// many edge visits and the localisation-guided self-reduction takes over.
-constexpr int64_t kHitDfsBudget = 5'000'000;
 
 void store_path(const tpm_query &q, const int32_t *pv, const int64_t *pe, tpm_result &r) {
     for (int i = 0; i < q.k; ++i) r.path_vertices[i] = pv[i];
@@ -94,9 +91,9 @@ void extract_into(const Graph &G, const tpm_query &q, tpm_result &r, hipStream_t
     int32_t pv[16];
     r.path_status = TPM_NOTFOUND;
     if (q.k >= 2) {
-        r.path_status = q_loc ? extract_from_vertices(G, q.multiset, q.k, q_loc, kHitDfsBudget, pv, pe)
+        r.path_status = q_loc ? extract_from_vertices(G, q.multiset, q.k, q_loc, kQuickDfsBudget, pv, pe)
                               : extract_vertexloc(G, q.multiset, q.k, q.seed, 2, pv, pe, nullptr,
-                                                  kHitDfsBudget);
+                                                  kQuickDfsBudget);
     }
     if (r.path_status != TPM_OK) r.path_status = extract_path(G, q.multiset, q.k, q.seed, 8, pv, pe, st);
     if (r.path_status == TPM_OK) store_path(q, pv, pe, r);

@@ -313,6 +313,7 @@ uint8_t vertex_localise(const Graph &G, const SieveRequest &req, uint8_t *q, hip
 // approach): reverse temporal DFS from the vertices u with q[u] != 0 (q: host, G.n
 // bytes, from vertex_localise), at most `budget` edge visits.  TPM_OK / TPM_NOTFOUND.
 constexpr int64_t kDfsBudget = 50'000'000;
+constexpr int64_t kQuickDfsBudget = 5'000'000;  // before falling back to self-reduction
 tpm_status extract_from_vertices(const Graph &G, const int32_t *M, int32_t k, const uint8_t *q,
                                  int64_t budget, int32_t *path_vertices, int64_t *path_edges);
 // One localised sieve per seed (step seeds of extraction), then the DFS.
