@@ -110,6 +110,7 @@ typedef struct {
     int64_t times;         /* distinct timestamps (length of tpm_time_buckets output) */
     int64_t edge_ids;      /* input edge ids are < edge_ids: m, or the parent's m for a
                               graph made by tpm_graph_prune */
+    int32_t tile_edges;    /* work-tile size in use */
 } tpm_graph_stats;
 
 /* Per-call tuning.  Every admissible setting gives bit-identical results.

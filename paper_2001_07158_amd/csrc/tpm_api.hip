@@ -878,6 +878,7 @@ tpm_status tpm_graph_stats_get(const tpm_graph *g, tpm_graph_stats *out) {
         out->segments = G.segments;
         out->times = G.ntimes;
         out->edge_ids = G.edge_ids;
+        out->tile_edges = G.tile_edges;
         return TPM_OK;
     });
 }

@@ -50,7 +50,7 @@ class tpm_graph_stats(ctypes.Structure):
                 ("slots", ctypes.c_int64), ("max_in_degree", ctypes.c_int64),
                 ("device_bytes", ctypes.c_int64), ("gathers", ctypes.c_int64),
                 ("segments", ctypes.c_int64), ("times", ctypes.c_int64),
-                ("edge_ids", ctypes.c_int64)]
+                ("edge_ids", ctypes.c_int64), ("tile_edges", ctypes.c_int32)]
 
 
 class tpm_kernel_time(ctypes.Structure):

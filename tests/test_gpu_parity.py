@@ -457,3 +457,24 @@ def test_undirected_graphs(tpm):
             assert rc == tpm.TPM_OK
             assert pyref.check_path(d, M, verts, edges, tr2)
         Gd.close()
+
+
+def test_default_tile_size(tpm):
+    """Default tiles: min(1024, max(128, m / 4096)); subgraphs choose again for their own
+    m; an explicit size or a retile is kept."""
+    want = lambda m: min(1024, max(128, m // 4096))  # noqa: E731
+    g = G.uniform_graph(5000, 2_000_000, 100, 8, 196)
+    Gd = tpm.Graph.from_temporal(g)
+    assert Gd.stats()["tile_edges"] == want(g.m)
+    Gp = Gd.prune([0, 1])
+    assert Gp.stats()["tile_edges"] == want(Gp.stats()["m"])
+    Gp.close()
+    Gd.retile(300)
+    assert Gd.stats()["tile_edges"] == 300
+    Gq = Gd.prune([0, 1])
+    assert Gq.stats()["tile_edges"] == 300
+    Gq.close()
+    Gd.close()
+    Ge = tpm.Graph.from_temporal(g, tile_edges=777)
+    assert Ge.stats()["tile_edges"] == 777
+    Ge.close()
