@@ -505,7 +505,8 @@ def bench_serving(args) -> int:
         "spot_check_equal_alone": bool(same), "dtype": "u8", "data": "synthetic",
         "mode": "per-request colour pruning" if args.prune else "continuous batching (resident row)",
         "extract_on_hit": not args.no_extract,
-        "paths_ok": int(sum(r["path_status"] == tpm.TPM_OK for r in results + burst if r["found"])),
+        "paths_ok": (int(sum(r["path_status"] == tpm.TPM_OK for r in results + burst if r["found"]))
+                     if not args.no_extract else None),
         "server_stats": sstats,
         "config": {"workload": f"serving: directed Chung-Lu n={g.n} m={g.m} beta=2.5 "
                                f"t=[1,{cfg['t']}] q={cfg['q']}, stream prefix of {nq} queries "

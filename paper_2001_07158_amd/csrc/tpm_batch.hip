@@ -199,13 +199,16 @@ tpm_status tpm_batch_run(const tpm_graph *g, int32_t nq, const tpm_query *q, tpm
                         multi_prepare(G, row, j * lpg, gpts, qq.multiset, k, qq.seed, 0, nullptr, st);
                     }
                     // lane tables of levels 2..k, 64 entries per level
-                    std::vector<StepLane> lanes((size_t)(k - 1) * 64, StepLane{0, 0, 0});
+                    std::vector<StepLane> lanes((size_t)(k - 1) * 64, StepLane{0, 0, 0, 0});
                     for (int l = 2; l <= k; ++l) {
                         uint32_t flags = kLaneActive | (l == 2 ? kLaneFromX : 0u) | (l == k ? kLaneAcc : 0u);
-                        for (int j = 0; j < cnt; ++j)
+                        for (int j = 0; j < cnt; ++j) {
+                            const tpm_query &qq = q[ids[a + j]];
+                            const uint64_t cm = colour_mask(G, qq.multiset, k);
                             for (int t = 0; t < lpg; ++t)
                                 lanes[(size_t)(l - 2) * 64 + (size_t)(j * lpg + t)] = {
-                                    q[ids[a + j]].seed, (uint32_t)(l - 1), flags};
+                                    qq.seed, (uint32_t)(l - 1), flags, cm};
+                        }
                     }
                     if (use_graph) {
                         multi_upload_tabs(row, lanes.data(), k - 1, st);
@@ -329,6 +332,36 @@ struct Group {
 // Pruned mode: requests in arrival order, each on the subgraph of its own colours
 // (preprocessing step (i)); the subgraph's workspaces come from a pool kept for the
 // server's lifetime, so steady state allocates nothing but the subgraph index.
+// Extraction for a hit of the batching server: on the subgraph of the query's colours
+// (built in the server's arena, same ids, so the same path certificate), or on the
+// whole graph for queries with wildcards.
+void extract_on_subgraph(tpm_server *s, const Graph &G, const tpm_query &q, tpm_result &r,
+                         hipStream_t st) {
+    bool wild = false;
+    std::vector<uint8_t> keep((size_t)G.q, 0);
+    for (int i = 0; i < q.k; ++i) {
+        if (q.multiset[i] < 0) wild = true;
+        else keep[(size_t)q.multiset[i]] = 1;
+    }
+    if (wild) {
+        extract_into(G, q, r, st);
+        return;
+    }
+    Graph P;
+    struct Free {
+        Graph &g;
+        ~Free() {
+            g.pool = nullptr;  // the server owns it
+            free_graph(g);
+        }
+    } fr{P};
+    PruneSpec spec;
+    spec.keep_color = keep.data();
+    prune_graph(G, spec, P, s->arena);
+    P.pool = s->ppool;
+    extract_into(P, q, r, st);
+}
+
 void serve_pruned(tpm_server *s) {
     const Graph &G = s->g->G;
     (void)hipSetDevice(G.device);
@@ -444,7 +477,8 @@ void serve_loop(tpm_server *s) {
             r.t_start_ms = rq->t_start;
             rq->q.multiset = rq->ms.data();
             const double te = now_ms();
-            if (r.found && (rq->q.want_path || s->cfg.extract_paths)) extract_into(G, rq->q, r, st);
+            if (r.found && (rq->q.want_path || s->cfg.extract_paths))
+                extract_on_subgraph(s, G, rq->q, r, st);
             r.t_done_ms = now_ms();
             ext_in_step += r.t_done_ms - te;
             std::lock_guard<std::mutex> lk(s->mu);
@@ -506,13 +540,14 @@ void serve_loop(tpm_server *s) {
             }
             if (groups.empty()) continue;
             // ---- one step: every group advances one level
-            std::vector<StepLane> lanes((size_t)row.lanes, StepLane{0, 0, 0});
+            std::vector<StepLane> lanes((size_t)row.lanes, StepLane{0, 0, 0, 0});
             for (const Group &gr : groups) {
                 const int k = gr.req->q.k;
                 uint32_t flags = kLaneActive | (gr.level == 2 ? kLaneFromX : 0u) |
                                  (gr.level == k ? kLaneAcc : 0u);
+                const uint64_t cm = colour_mask(G, gr.req->ms.data(), k);
                 for (int t = 0; t < gr.nl; ++t)
-                    lanes[(size_t)(gr.lane0 + t)] = {gr.req->q.seed, (uint32_t)(gr.level - 1), flags};
+                    lanes[(size_t)(gr.lane0 + t)] = {gr.req->q.seed, (uint32_t)(gr.level - 1), flags, cm};
             }
             const double ts = now_ms();
             ext_in_step = 0;
@@ -562,9 +597,11 @@ tpm_status tpm_server_create(const tpm_graph *g, const tpm_server_config *cfg, t
         const Graph &G = g->G;
         TPM_REQUIRE(s->cfg.prune_queries == 0 || s->cfg.prune_queries == 1,
                     "prune_queries must be 0 or 1");
+        // per-request subgraphs (pruned mode, and extraction in batching mode) live in
+        // an arena with their own workspace pool
+        s->ppool = new_workspace_pool();
+        s->arena = new_graph_arena();
         if (s->cfg.prune_queries) {
-            s->ppool = new_workspace_pool();
-            s->arena = new_graph_arena();
             s->worker = std::thread(serve_pruned, s);
             *out = s;
             return TPM_OK;

@@ -217,6 +217,12 @@ __global__ void k_layer_compact(int64_t m, const int32_t *keep, const int32_t *a
     }
 }
 
+__global__ void k_pcol(int64_t m, const int32_t *psrc, const int32_t *pdst, const int32_t *color,
+                       uint16_t *pcol) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < m) pcol[p] = (uint16_t)(color[psrc[p]] | (color[pdst[p]] << 8));
+}
+
 // rowpos[orow[p]] = p
 __global__ void k_rowpos(int64_t m, const int32_t *orow, int32_t *rowpos) {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -635,6 +641,15 @@ void free_graph(Graph &G) {
     }
     if (G.lds_image && own) (void)hipFree(G.lds_image);
     G.lds_image = nullptr;
+    if (G.pcol && own) (void)hipFree(G.pcol);
+    G.pcol = nullptr;
+}
+
+void build_pcol(Graph &G, int64_t &acct) {
+    if (G.arena || G.q > 64 || G.m == 0) return;
+    if (!G.pcol) G.pcol = dalloc<uint16_t>(G.m, acct);
+    k_pcol<<<grid_for(G.m), 256>>>(G.m, G.psrc, G.pdst, G.color, G.pcol);
+    TPM_HIP(hipDeviceSynchronize());
 }
 
 // Everything of the index that follows from the CSR arrays (pdst, psrc, ptau, peid
@@ -722,6 +737,7 @@ void finish_index(Graph &G, int64_t &acct, const int32_t *taus, bool greedy_tile
     G.lds_image = galloc<uint8_t>(G, A_LDS, kLdsBytes, acct);
     TPM_HIP(hipMemcpy(G.lds_image, lds_image_host().data(), kLdsBytes, hipMemcpyHostToDevice));
     TPM_HIP(hipDeviceSynchronize());
+    build_pcol(G, acct);
 }
 
 void build_graph(Graph &G, int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
@@ -1019,6 +1035,13 @@ void sd_graph(const Graph &P, int32_t s, int32_t d, Graph &G) {
         TPM_HIP(hipMemcpy(G.color + d, &cd, sizeof(int32_t), hipMemcpyHostToDevice));
         G.h_color[(size_t)s] = cs;
         G.h_color[(size_t)d] = cd;
+        int64_t acct = 0;
+        if (G.q > 64 && G.pcol) {
+            (void)hipFree(G.pcol);
+            G.pcol = nullptr;
+        }
+        build_pcol(G, acct);
+        G.device_bytes += acct;
     } catch (...) {
         free_graph(G);
         throw;

@@ -186,6 +186,8 @@ struct Graph {
     int32_t *orow = nullptr;   // [m] state row written at this position, -1 if none
     int32_t *rowpos = nullptr; // [R] position that writes each state row (whole graphs
                                //     only: pruning maps gsrc through it)
+    uint16_t *pcol = nullptr;  // [m] colours of the edge's source (low byte) and head
+                               //     (high byte): whole graphs with <= 64 colours
     int32_t *inptr = nullptr;  // [n+1]
     int32_t *tile_p0 = nullptr;   // [ntiles+1]
     int32_t *tile_pub = nullptr;  // [ntiles] slot this tile publishes to, -1 if none
@@ -218,6 +220,8 @@ void build_graph(Graph &G, int32_t n, int64_t m, const int32_t *src, const int32
                  const int32_t *tau, const int32_t *color, int32_t num_colors, uint32_t flags,
                  const tpm_graph_options *opt);
 void free_graph(Graph &G);
+// (Re)computes G.pcol from G.color for a whole graph with at most 64 colours.
+void build_pcol(Graph &G, int64_t &acct);
 // Default work-tile size: 1024 positions, fewer for small graphs so that the tiles
 // (each walked by one wave) still outnumber the waves of the GPU.
 int32_t auto_tile_edges(int64_t m);
@@ -357,7 +361,12 @@ struct StepLane {
     uint64_t seed;
     uint32_t ylevel;  // walk position of y at this step = level - 1
     uint32_t flags;   // kLaneActive | kLaneFromX (level 2) | kLaneAcc (last level)
+    uint64_t cmask;   // colours a vertex of a matching path can have (bit c); an edge
+                      // with an endpoint outside adds nothing for this lane's query
 };
+// The colours of a multiset as a StepLane mask (every colour with a wildcard entry or
+// more than 64 colours).
+uint64_t colour_mask(const Graph &G, const int32_t *M, int32_t k);
 constexpr uint32_t kLaneActive = 1, kLaneFromX = 2, kLaneAcc = 4;
 // bits 8..10 of a lane's flags: its group in the step's fingerprint table (set by the
 // library, ignored on input)

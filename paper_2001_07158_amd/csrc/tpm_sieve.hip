@@ -88,6 +88,7 @@ struct LevelParams {
 
 struct StepParams {
     const int32_t *psrc, *gsrc, *pdst, *peid, *orow;
+    const uint16_t *pcol;  // colours of source and head per position; null: no skipping
     const uint8_t *xt;   // per-vertex rows of x for every lane group
     const uint8_t *sin;  // rows written by the previous step
     uint8_t *sout;       // rows written by this step
@@ -106,6 +107,7 @@ struct StepParams {
     int32_t ngroups;
     uint32_t glevel[kMaxYGroups];
     uint64_t gseed[kMaxYGroups];
+    uint64_t gmask[kMaxYGroups];  // colours the group's queries use (OR of their lanes)
     const StepLane *dtab;        // non-null: lane table and plan in device memory
                                  // (kTabStride entries), used instead of the above
     StepLane tab[64];            // per lane: seed, level, role
@@ -861,45 +863,58 @@ inline unsigned grid_for(int64_t work, int block = 256) {
 // ---------------------------------------------------------------------------------
 struct WinS {
     int32_t g, s, d, o;
+    uint32_t pc;      // colours of source (low byte) and head (high byte)
     uint32_t e;       // input edge id
     uint32_t h0, h1;  // ymode 1: inner fingerprint hash of (tag y, ylevel0, e), low and
                       // high words; ymode 2: log y of groups 0..3 and 4..7, one byte
                       // each (255 for y = 0)
 };
 
+// does a query with colour mask cmask use an edge with colours pc (source low byte,
+// head high byte)
+__device__ __forceinline__ bool lane_uses(uint64_t cmask, uint32_t pc) {
+    return ((cmask >> (pc & 0xFFu)) & (cmask >> (pc >> 8)) & 1ull) != 0;
+}
+
 struct YPlan {
     int ymode, ngroups;
     uint32_t ylevel0;
-    const uint64_t *gs;  // group seeds and levels, in LDS (shared by the workgroup)
-    const uint32_t *gl;
+    const uint64_t *gs;  // group seeds, levels and colour masks, in LDS (shared by the
+    const uint32_t *gl;  // workgroup)
+    const uint64_t *gm;
 };
 
 __device__ __forceinline__ WinS load_wins(const StepParams &P, int32_t wb, int32_t p1, int lane,
                                           const YPlan &Y, const uint8_t *lds, uint32_t lanebits) {
-    WinS m{-1, -1, -1, -1, 0, 0, 0};
+    WinS m{-1, -1, -1, -1, 0, 0, 0, 0};
     const int32_t q = wb + lane;
     if (q < p1) {
         m.g = P.gsrc[q];
         m.s = P.psrc[q];
         m.d = P.pdst[q];
         m.o = P.orow[q];
+        if (P.pcol) m.pc = P.pcol[q];
         m.e = (uint32_t)P.peid[q];
         if (Y.ymode == 1) {
             const uint64_t h = mix64((1ull << 56) ^ ((uint64_t)Y.ylevel0 << 32) ^ (uint64_t)m.e);
             m.h0 = (uint32_t)h;
             m.h1 = (uint32_t)(h >> 32);
         } else if (Y.ymode == 2) {
-            // groups are sorted by level: the inner hash changes only with the level
+            // groups are sorted by level: the inner hash changes only with the level; a
+            // group whose queries do not use this edge's colours gets y = 0 unhashed
             uint64_t inner = 0;
             uint32_t prev = ~0u;
 #pragma unroll 1
             for (int g = 0; g < Y.ngroups; ++g) {
-                const uint32_t lv = Y.gl[g];
-                if (lv != prev) inner = mix64((1ull << 56) ^ ((uint64_t)lv << 32) ^ (uint64_t)m.e);
-                prev = lv;
-                const uint32_t y = (uint32_t)(mix64(Y.gs[g] ^ inner) & 0xFFu);
-                const uint32_t l7 = lds32(lds, (y << 8) | lanebits);
-                const uint32_t lb = l7 >= kZero7 ? 255u : (l7 >> 7);
+                uint32_t lb = 255u;
+                if (!P.pcol || lane_uses(Y.gm[g], m.pc)) {
+                    const uint32_t lv = Y.gl[g];
+                    if (lv != prev) inner = mix64((1ull << 56) ^ ((uint64_t)lv << 32) ^ (uint64_t)m.e);
+                    prev = lv;
+                    const uint32_t y = (uint32_t)(mix64(Y.gs[g] ^ inner) & 0xFFu);
+                    const uint32_t l7 = lds32(lds, (y << 8) | lanebits);
+                    lb = l7 >= kZero7 ? 255u : (l7 >> 7);
+                }
                 if (g < 4) m.h0 |= lb << (8 * g);
                 else m.h1 |= lb << (8 * (g - 4));
             }
@@ -911,21 +926,25 @@ __device__ __forceinline__ WinS load_wins(const StepParams &P, int32_t wb, int32
 template <int W, int U>
 __device__ __forceinline__ void gather_step(const StepParams &P, const WinS &cw, const WinS &nw,
                                             int32_t wb, int32_t pb, int32_t p1, bool act,
-                                            bool from_x, int lane, uint32_t (&g)[U][W]) {
+                                            bool from_x, uint64_t cmask, int lane,
+                                            uint32_t (&g)[U][W]) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const int32_t q = pb + u;
         int32_t rg = -1, rs = -1;
+        uint32_t pc = 0;
         if (q < p1) {
             const int32_t i = q - wb;  // uniform
             rg = (i < 64) ? __builtin_amdgcn_readlane(cw.g, i) : __builtin_amdgcn_readlane(nw.g, i - 64);
             rs = (i < 64) ? __builtin_amdgcn_readlane(cw.s, i) : __builtin_amdgcn_readlane(nw.s, i - 64);
+            pc = (i < 64) ? __builtin_amdgcn_readlane(cw.pc, i) : __builtin_amdgcn_readlane(nw.pc, i - 64);
         }
         // both candidate rows are uniform: form their addresses in scalar registers
-        // and let each lane pick by its role
+        // and let each lane pick by its role; a lane whose query has no vertex of one
+        // of the edge's colours reads nothing (its contribution is zero)
         const uint8_t *px = P.xt + (int64_t)rs * P.rowb;
         const uint8_t *ps = P.sin + (int64_t)rg * P.rowb;
-        if ((from_x ? rs : rg) >= 0 && act) {
+        if ((from_x ? rs : rg) >= 0 && act && lane_uses(cmask, pc)) {
             load_row<W>(from_x ? px : ps, 0, P.rowb, lane, g[u]);
         } else {
 #pragma unroll
@@ -940,6 +959,7 @@ __global__ void __launch_bounds__(1024) k_step(StepParams P) {
     __shared__ __attribute__((aligned(16))) uint8_t lds[kLdsBytes];
     __shared__ uint64_t s_gseed[kMaxYGroups];
     __shared__ uint32_t s_glevel[kMaxYGroups];
+    __shared__ uint64_t s_gmask[kMaxYGroups];
     {
         const uint4 *src = (const uint4 *)P.lds_image;
         uint4 *dst = (uint4 *)lds;
@@ -948,6 +968,7 @@ __global__ void __launch_bounds__(1024) k_step(StepParams P) {
             const int g = threadIdx.x;
             s_gseed[g] = P.dtab ? P.dtab[65 + g].seed : P.gseed[g];
             s_glevel[g] = P.dtab ? P.dtab[65 + g].ylevel : P.glevel[g];
+            s_gmask[g] = P.dtab ? P.dtab[65 + g].cmask : P.gmask[g];
         }
     }
     __syncthreads();
@@ -957,6 +978,7 @@ __global__ void __launch_bounds__(1024) k_step(StepParams P) {
     YPlan Y;
     Y.gs = s_gseed;
     Y.gl = s_glevel;
+    Y.gm = s_gmask;
     if (P.dtab) {
         if (lane < P.lanes) L = P.dtab[lane];
         const StepLane h = P.dtab[64];
@@ -972,6 +994,9 @@ __global__ void __launch_bounds__(1024) k_step(StepParams P) {
     const bool act = (L.flags & kLaneActive) != 0;
     const bool from_x = (L.flags & kLaneFromX) != 0;
     const bool accm = (L.flags & kLaneAcc) != 0;
+    // without colour pairs every edge counts for every lane (the pair 0|0 is tested
+    // against a mask of all colours)
+    const uint64_t cmask = P.pcol ? L.cmask : ~0ull;
     const uint32_t grp = (L.flags >> kLaneGroupShift) & (kMaxYGroups - 1);
     const bool grp_hi = grp >= 4;
     const uint32_t grp_shift = 8 * (grp & 3);
@@ -1043,38 +1068,46 @@ __global__ void __launch_bounds__(1024) k_step(StepParams P) {
                     nxt_dst = nd;
                     if (nd >= 0 && act) load_row<W>(P.xt, nd, P.rowb, lane, xn);
                 }
-                // y_{e, level-1} of this lane's query
-                uint32_t ly7;
-                if (Y.ymode == 2) {
-                    const uint32_t w0 = (uint32_t)__builtin_amdgcn_readlane(cw.h0, i);
-                    const uint32_t w1 = (uint32_t)__builtin_amdgcn_readlane(cw.h1, i);
-                    const uint32_t lb = ((grp_hi ? w1 : w0) >> grp_shift) & 0xFFu;
-                    ly7 = lb == 255u ? kZero7 : (lb << 7);
-                } else {
-                    uint32_t y;
-                    if (Y.ymode == 1) {
-                        const uint64_t inner =
-                            ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(cw.h1, i) << 32) |
-                            (uint64_t)(uint32_t)__builtin_amdgcn_readlane(cw.h0, i);
-                        y = (uint32_t)(mix64(L.seed ^ inner) & 0xFFu);
+                // lanes whose query uses the edge (the others gathered nothing: their
+                // g is zero); a head of a colour outside a query's multiset never feeds
+                // a later edge of that query, so its rows are not stored for it
+                const uint32_t pc = (uint32_t)__builtin_amdgcn_readlane(cw.pc, i);
+                const bool uses = act && lane_uses(cmask, pc);
+                const bool head_used = ((cmask >> (pc >> 8)) & 1ull) != 0;
+                if (__ballot(uses)) {
+                    // y_{e, level-1} of this lane's query
+                    uint32_t ly7;
+                    if (Y.ymode == 2) {
+                        const uint32_t w0 = (uint32_t)__builtin_amdgcn_readlane(cw.h0, i);
+                        const uint32_t w1 = (uint32_t)__builtin_amdgcn_readlane(cw.h1, i);
+                        const uint32_t lb = ((grp_hi ? w1 : w0) >> grp_shift) & 0xFFu;
+                        ly7 = lb == 255u ? kZero7 : (lb << 7);
                     } else {
-                        const uint32_t eid = __builtin_amdgcn_readlane(cw.e, i);
-                        y = fp8(L.seed, 1u, L.ylevel, eid);
+                        uint32_t y;
+                        if (Y.ymode == 1) {
+                            const uint64_t inner =
+                                ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(cw.h1, i) << 32) |
+                                (uint64_t)(uint32_t)__builtin_amdgcn_readlane(cw.h0, i);
+                            y = (uint32_t)(mix64(L.seed ^ inner) & 0xFFu);
+                        } else {
+                            const uint32_t eid = __builtin_amdgcn_readlane(cw.e, i);
+                            y = fp8(L.seed, 1u, L.ylevel, eid);
+                        }
+                        ly7 = lds32(lds, (y << 8) | lanebits);
                     }
-                    ly7 = lds32(lds, (y << 8) | lanebits);
-                }
-                uint32_t c[W];
+                    uint32_t c[W];
 #pragma unroll
-                for (int w = 0; w < W; ++w) c[w] = mul4(lds, lanebits, g[u][w], &lx7[4 * w], ly7, zc);
-                if (accm) {
+                    for (int w = 0; w < W; ++w) c[w] = mul4(lds, lanebits, g[u][w], &lx7[4 * w], ly7, zc);
+                    if (accm) {
 #pragma unroll
-                    for (int w = 0; w < W; ++w) fin[w] ^= c[w];
-                } else {
+                        for (int w = 0; w < W; ++w) fin[w] ^= c[w];
+                    } else {
 #pragma unroll
-                    for (int w = 0; w < W; ++w) acc[w] ^= c[w];
+                        for (int w = 0; w < W; ++w) acc[w] ^= c[w];
+                    }
                 }
                 const int32_t orow = __builtin_amdgcn_readlane(cw.o, i);
-                if (orow >= 0 && act && !accm) store_row<W>(P.sout, orow, P.rowb, lane, acc);
+                if (orow >= 0 && act && !accm && head_used) store_row<W>(P.sout, orow, P.rowb, lane, acc);
             }
             if (pb + U - wb == 64 && pb + U < p1) {
                 wb += 64;
@@ -1084,13 +1117,13 @@ __global__ void __launch_bounds__(1024) k_step(StepParams P) {
         };
 
         uint32_t ga[U][W], gb[U][W];
-        gather_step<W, U>(P, cw, nw, wb, p0, p1, act, from_x, lane, ga);
+        gather_step<W, U>(P, cw, nw, wb, p0, p1, act, from_x, cmask, lane, ga);
         for (int32_t pb = p0; pb < p1;) {
-            gather_step<W, U>(P, cw, nw, wb, pb + U, p1, act, from_x, lane, gb);
+            gather_step<W, U>(P, cw, nw, wb, pb + U, p1, act, from_x, cmask, lane, gb);
             process(ga, pb);
             pb += U;
             if (pb >= p1) break;
-            gather_step<W, U>(P, cw, nw, wb, pb + U, p1, act, from_x, lane, ga);
+            gather_step<W, U>(P, cw, nw, wb, pb + U, p1, act, from_x, cmask, lane, ga);
             process(gb, pb);
             pb += U;
         }
@@ -1540,6 +1573,16 @@ void run_sieve_impl(const Graph &G, const SieveRequest &req, SieveResult &res, b
                                      std::to_string(hctl.err) + ")"};
 }
 
+uint64_t colour_mask(const Graph &G, const int32_t *M, int32_t k) {
+    if (G.q > 64) return ~0ull;
+    uint64_t m = 0;
+    for (int i = 0; i < k; ++i) {
+        if (M[i] < 0) return ~0ull;  // a wildcard: any vertex
+        m |= 1ull << M[i];
+    }
+    return m;
+}
+
 void run_sieve(const Graph &G, const SieveRequest &req, SieveResult &res, hipStream_t st) {
     run_sieve_impl(G, req, res, req.want_pick, nullptr, st);
 }
@@ -1708,6 +1751,7 @@ void fill_step_params(const Graph &G, const MultiRow &row, StepParams &P) {
     P.pdst = G.pdst;
     P.peid = G.peid;
     P.orow = G.orow;
+    P.pcol = G.pcol;
     P.xt = ws.xt.as<uint8_t>();
     P.sin = (row.parity ? ws.s1 : ws.s0).as<uint8_t>();
     P.sout = (row.parity ? ws.s0 : ws.s1).as<uint8_t>();
@@ -1733,6 +1777,7 @@ struct StepYPlan {
     uint32_t ylevel0 = 0;
     uint32_t glevel[kMaxYGroups] = {};
     uint64_t gseed[kMaxYGroups] = {};
+    uint64_t gmask[kMaxYGroups] = {};
 };
 
 StepYPlan plan_y(StepLane *lanes, int nl) {
@@ -1761,6 +1806,7 @@ StepYPlan plan_y(StepLane *lanes, int nl) {
             const std::pair<uint32_t, uint64_t> key{lanes[i].ylevel, lanes[i].seed};
             const uint32_t g = (uint32_t)(std::find(groups.begin(), groups.end(), key) - groups.begin());
             lanes[i].flags |= g << kLaneGroupShift;
+            Y.gmask[g] |= lanes[i].cmask;
         }
     } else if (same && lvl >= 0) {
         Y.ymode = 1;
@@ -1783,6 +1829,7 @@ void multi_step(const Graph &G, MultiRow &row, const StepLane *lanes, hipStream_
     for (int g = 0; g < kMaxYGroups; ++g) {
         P.glevel[g] = Y.glevel[g];
         P.gseed[g] = Y.gseed[g];
+        P.gmask[g] = Y.gmask[g];
     }
     k_prep<<<1, 1, 0, st>>>(ws.ctl.as<Ctl>(), 1);
     {
@@ -1805,7 +1852,8 @@ void multi_upload_tabs(MultiRow &row, const StepLane *lanes, int nsteps, hipStre
         for (int i = 0; i < row.lanes; ++i) dst[i] = src[i];
         const StepYPlan Y = plan_y(dst, row.lanes);
         dst[64] = StepLane{0, Y.ylevel0, (uint32_t)Y.ymode | ((uint32_t)Y.ngroups << 8)};
-        for (int g = 0; g < kMaxYGroups; ++g) dst[65 + g] = StepLane{Y.gseed[g], Y.glevel[g], 0};
+        for (int g = 0; g < kMaxYGroups; ++g)
+            dst[65 + g] = StepLane{Y.gseed[g], Y.glevel[g], 0, Y.gmask[g]};
     }
     TPM_HIP(hipMemcpyAsync(ws.tabs.p, host.data(), sizeof(StepLane) * host.size(),
                            hipMemcpyHostToDevice, st));
