@@ -331,8 +331,43 @@ tpm_status extract_selfreduce(const Graph &G, const int32_t *M, int32_t k, uint6
             mask[(size_t)u] = 1;
             cand.push_back(u);
         }
+    // Decisions run on the subgraph of the vertices still live (rebuilt each time the
+    // live set halves): deleted vertices have z = 0 either way, so every sieve value is
+    // the same, and later decisions touch fewer edges.
+    Graph sub;
+    bool have_sub = false;
+    struct SubOwn {
+        Graph &g;
+        bool &have;
+        ~SubOwn() {
+            if (have) {
+                g.pool = nullptr;  // borrowed
+                free_graph(g);
+            }
+        }
+    } sub_own{sub, have_sub};
+    size_t live = cand.size(), live_at_build = cand.size();
+    auto maybe_shrink = [&]() {
+        if (G.m < 100000 || live * 2 > live_at_build) return;
+        DBuf vk;
+        vk.alloc((size_t)std::max<int32_t>(1, G.n), nullptr);
+        TPM_HIP(hipMemcpy(vk.p, mask.data(), (size_t)G.n, hipMemcpyHostToDevice));
+        Graph ng;
+        PruneSpec spec;
+        spec.vkeep = vk.as<uint8_t>();
+        prune_graph(G, spec, ng);
+        ng.pool = G.pool;
+        if (have_sub) {
+            sub.pool = nullptr;
+            free_graph(sub);
+        }
+        sub = ng;
+        have_sub = true;
+        live_at_build = live;
+    };
     int64_t calls = 0, nsieve = 0;
     auto decide = [&]() {
+        const Graph &Gs = have_sub ? sub : G;
         for (int32_t r = 0; r < reps; ++r) {
             SieveRequest req;
             req.multiset = M;
@@ -340,7 +375,7 @@ tpm_status extract_selfreduce(const Graph &G, const int32_t *M, int32_t k, uint6
             req.seed = step_seed(seed, 2000000 + calls, r);
             req.vertex_mask = mask.data();
             SieveResult res;
-            run_sieve(G, req, res, nullptr);
+            run_sieve(Gs, req, res, nullptr);
             ++nsieve;
             if (res.total) {
                 ++calls;
@@ -365,7 +400,11 @@ tpm_status extract_selfreduce(const Graph &G, const int32_t *M, int32_t k, uint6
         todo.pop_back();
         if (a >= b) continue;
         for (size_t i = a; i < b; ++i) mask[(size_t)cand[i]] = 0;
-        if (decide()) continue;  // the group goes
+        if (decide()) {  // the group goes
+            live -= b - a;
+            maybe_shrink();
+            continue;
+        }
         for (size_t i = a; i < b; ++i) mask[(size_t)cand[i]] = 1;
         if (b - a == 1) continue;  // an essential vertex
         const size_t mid = a + (b - a) / 2;

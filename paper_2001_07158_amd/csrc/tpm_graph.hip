@@ -192,6 +192,29 @@ __global__ void k_keep(int64_t m, const int32_t *psrc, const int32_t *pdst, cons
     keep[p] = k ? 1 : 0;
 }
 
+// k_keep for a colour set only, from the colour pair of each position (2 bytes read
+// per position instead of both endpoints and their vertex bits)
+__global__ void k_keep_pc(int64_t m, const uint16_t *pcol, uint64_t cmask, const int32_t *ptime,
+                          const int32_t *ts, int32_t nts, const int32_t *parr, int32_t tcut,
+                          int32_t *keep) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= m) return;
+    const uint32_t pc = pcol[p];
+    bool k = ((cmask >> (pc & 0xFFu)) & (cmask >> (pc >> 8)) & 1ull) != 0;
+    if (k && tcut < 0x7FFFFFFF) k = parr[p] <= tcut;
+    if (k && ts) {
+        const int32_t t = ptime[p];
+        int32_t a = 0, b = nts;
+        while (a < b) {
+            const int32_t mid = (a + b) >> 1;
+            if (ts[mid] < t) a = mid + 1;
+            else b = mid;
+        }
+        k = a < nts && ts[a] == t;
+    }
+    keep[p] = k ? 1 : 0;
+}
+
 // layer keep: edge at p goes from colour cs to colour cd
 __global__ void k_layer_keep(int64_t m, const int32_t *psrc, const int32_t *pdst,
                              const int32_t *color, int32_t cs, int32_t cd, int32_t *keep) {
@@ -963,10 +986,20 @@ void prune_graph(const Graph &P, const PruneSpec &spec, Graph &G, GraphArena *ar
                 keep = tmp.get<int32_t>(A_KEEP, P.m);
                 at = tmp.get<int32_t>(A_AT, P.m);
                 // timestamps of the edges as given (departures when transit times exist)
-                k_keep<<<grid_for(P.m), 256, 0, st>>>(P.m, P.psrc, P.pdst, vbits,
-                                                       P.pdep ? P.pdep : P.ptau, ts, ntimes,
-                                                       spec.cut_in, spec.cut_out, P.ptau,
-                                                       spec.tcut, keep);
+                if (P.pcol && !vkeep_in && spec.cut_in < 0 && spec.cut_out < 0 && P.q <= 64) {
+                    uint64_t cm = 0;
+                    std::vector<uint8_t> kc((size_t)P.q, 1);
+                    if (keep_color) std::copy(keep_color, keep_color + P.q, kc.begin());
+                    for (int32_t c = 0; c < P.q; ++c)
+                        if (kc[(size_t)c]) cm |= 1ull << c;
+                    k_keep_pc<<<grid_for(P.m), 256, 0, st>>>(P.m, P.pcol, cm, P.pdep ? P.pdep : P.ptau,
+                                                              ts, ntimes, P.ptau, spec.tcut, keep);
+                } else {
+                    k_keep<<<grid_for(P.m), 256, 0, st>>>(P.m, P.psrc, P.pdst, vbits,
+                                                           P.pdep ? P.pdep : P.ptau, ts, ntimes,
+                                                           spec.cut_in, spec.cut_out, P.ptau,
+                                                           spec.tcut, keep);
+                }
                 size_t sbytes = 0;
                 TPM_HIP(rocprim::exclusive_scan(nullptr, sbytes, keep, at, 0, (size_t)P.m,
                                                 rocprim::plus<int32_t>(), st));
