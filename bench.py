@@ -204,6 +204,9 @@ def main() -> int:
         "query_ms_p50": float(np.percentile(lat, 50)),
         "query_ms_p99": float(np.percentile(lat, 99)),
         "hbm_gbps_algorithmic_query": hbm_alg,
+        # the DP's own count: k - 1 edge levels per point (the metric counts k)
+        "edge_level_updates_per_s": float(g.m) * (k - 1) * (1 << k) / (ms_per_step / 1e3),
+        "copy_gbps_reference": copy_gbps(torch),
         "roofline": {
             "bound": "hbm",
             "kernel": (f"k_level (1024-point rows, {dom} level)" if C >= 1024
@@ -341,6 +344,25 @@ def main() -> int:
     print(json.dumps(line), flush=True)
     G.close()
     return 0
+
+
+def copy_gbps(torch) -> float:
+    """Device-to-device copy rate (bytes read + written per second, GB/s) of a 4 GiB
+    buffer: the streaming reference beside the kernel's roofline figures."""
+    a = torch.empty(1 << 32, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(3):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 3
+    del a, b
+    torch.cuda.empty_cache()
+    return 2.0 * (1 << 32) / (ms / 1e3) / 1e9
 
 
 def _log(msg):
