@@ -86,10 +86,22 @@ def test_null_handles_are_errors():
     with pytest.raises(tpm.TpmError):
         tpm.tpm_decide(None, [0, 1], 1)
     for call in (lambda: tpm.tpm_graph_retile(None, 256), lambda: tpm.tpm_autotune(None, 4),
-                 lambda: tpm.tpm_optimum_time(None, [0, 1], 1)):
+                 lambda: tpm.tpm_optimum_time(None, [0, 1], 1),
+                 lambda: tpm.tpm_graph_sd(None, 0, 1),
+                 lambda: tpm.tpm_static_sieve(None, [0, 1], 1),
+                 lambda: tpm.tpm_graph_prune_static(None, [0, 1], 1),
+                 lambda: tpm.tpm_extract_optimum(None, [0, 1], 1)):
         with pytest.raises(tpm.TpmError) as ei:
             call()
         assert ei.value.code == tpm.TPM_EINVAL
+
+
+def test_unknown_creation_flags_rejected():
+    from paper_2001_07158_amd import tpm
+    z = np.zeros(1, dtype=np.int32)
+    with pytest.raises(tpm.TpmError) as ei:
+        tpm.tpm_graph_create(2, z, z + 1, z + 1, np.zeros(2, dtype=np.int32), 1, flags=0x4)
+    assert ei.value.code == tpm.TPM_EINVAL
 
 
 @pytest.mark.parametrize("case", ["neg_transit", "overflow", "neg_delay"])
