@@ -754,8 +754,10 @@ void finish_index(Graph &G, int64_t &acct, const int32_t *taus, bool greedy_tile
         TPM_HIP(hipMemcpy(G.h_color.data(), G.color, sizeof(int32_t) * (size_t)n,
                           hipMemcpyDeviceToHost));
     }
-    build_tiles_device(G, T, tmp, acct, &G.tile_p0, &G.tile_pub, &G.tile_lb, G.ntiles, G.nslots,
-                       false, greedy_tiles);
+    // window grouping makes tiles of up to two windows: windows of T / 2 keep them
+    // within T positions, as the greedy packing does
+    build_tiles_device(G, greedy_tiles ? T : std::max<int32_t>(1, T / 2), tmp, acct, &G.tile_p0,
+                       &G.tile_pub, &G.tile_lb, G.ntiles, G.nslots, false, greedy_tiles);
 
     G.lds_image = galloc<uint8_t>(G, A_LDS, kLdsBytes, acct);
     TPM_HIP(hipMemcpy(G.lds_image, lds_image_host().data(), kLdsBytes, hipMemcpyHostToDevice));
