@@ -1,0 +1,27 @@
+"""CPU: the benchmark's command line (no GPU work)."""
+
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
+
+
+@pytest.mark.parametrize("points", [1024, 256])
+def test_kernel_hash_and_committed_traffic(points):
+    """The committed PMC summaries were taken on the current level-kernel source."""
+    sys.path.insert(0, ROOT)
+    import bench
+    h = bench.kernel_hash(points)
+    assert len(h) == 16
+    assert bench.read_traffic(points) is not None, f"profile for {points}-point rows is stale"
