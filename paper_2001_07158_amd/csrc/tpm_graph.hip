@@ -174,7 +174,7 @@ __device__ __forceinline__ bool vbit(const uint32_t *vbits, int32_t u) {
 // parr: arrival times, kept up to tcut)
 __global__ void k_keep(int64_t m, const int32_t *psrc, const int32_t *pdst, const uint32_t *vbits,
                        const int32_t *ptime, const int32_t *ts, int32_t nts, int32_t cut_in,
-                       int32_t cut_out, const int32_t *parr, int32_t tcut, int32_t *keep) {
+                       int32_t cut_out, const int32_t *parr, int32_t tcut, uint8_t *keep) {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= m) return;
     const int32_t s = psrc[p], d = pdst[p];
@@ -196,7 +196,7 @@ __global__ void k_keep(int64_t m, const int32_t *psrc, const int32_t *pdst, cons
 // per position instead of both endpoints and their vertex bits)
 __global__ void k_keep_pc(int64_t m, const uint16_t *pcol, uint64_t cmask, const int32_t *ptime,
                           const int32_t *ts, int32_t nts, const int32_t *parr, int32_t tcut,
-                          int32_t *keep) {
+                          uint8_t *keep) {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= m) return;
     const uint32_t pc = pcol[p];
@@ -246,27 +246,29 @@ __global__ void k_pcol(int64_t m, const int32_t *psrc, const int32_t *pdst, cons
     if (p < m) pcol[p] = (uint16_t)(color[psrc[p]] | (color[pdst[p]] << 8));
 }
 
-// rowpos[orow[p]] = p
-__global__ void k_rowpos(int64_t m, const int32_t *orow, int32_t *rowpos) {
-    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p < m && orow[p] >= 0) rowpos[orow[p]] = (int32_t)p;
+// In-list starts of the subgraph: the kept positions before the parent's start
+// (at = exclusive count of the m kept flags, mk = their total).
+__global__ void k_sub_inptr(int32_t n, int64_t m, const int32_t *pinptr, const int32_t *at,
+                            int32_t mk, int32_t *inptr) {
+    int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u > n) return;
+    const int32_t x = pinptr[u];
+    inptr[u] = x < m ? at[x] : mk;
 }
 
 // The read position of a kept edge in the subgraph: the last kept position at or before
 // its parent read position g (positions keep their order), if that is still in the
-// source's in-list.  at = exclusive count of kept positions.
-__global__ void k_gpos_remap(int64_t m, const int32_t *keep, const int32_t *at, const int32_t *gsrc,
-                             const int32_t *rowpos, const int32_t *psrc, const int32_t *inptr,
+// source's in-list (sub_inptr: the subgraph's in-list starts).
+__global__ void k_gpos_remap(int64_t m, const uint8_t *keep, const int32_t *at, int32_t mk,
+                             const int32_t *gposw, const int32_t *psrc, const int32_t *sub_inptr,
                              int32_t *gpos) {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= m || !keep[p]) return;
     int32_t q = -1;
-    const int32_t r = gsrc[p];
-    if (r >= 0) {
-        const int32_t g = rowpos[r];
-        const int32_t last = at[g] + keep[g] - 1;
-        const int32_t first = at[inptr[psrc[p]]];
-        if (last >= first) q = last;
+    const int32_t g = gposw[p];
+    if (g >= 0) {
+        const int32_t last = (g + 1 < m ? at[g + 1] : mk) - 1;
+        if (last >= sub_inptr[psrc[p]]) q = last;
     }
     gpos[at[p]] = q;
 }
@@ -276,13 +278,13 @@ __global__ void k_needed(int64_t m, const int32_t *gpos, int32_t *needed) {
     if (p < m && gpos[p] >= 0) needed[gpos[p]] = 1;  // every writer stores the same value
 }
 
-__global__ void k_compact1(int64_t m, const int32_t *keep, const int32_t *at, const int32_t *a,
+__global__ void k_compact1(int64_t m, const uint8_t *keep, const int32_t *at, const int32_t *a,
                            int32_t *b) {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p < m && keep[p]) b[at[p]] = a[p];
 }
 
-__global__ void k_compact(int64_t m, const int32_t *keep, const int32_t *at, const int32_t *psrc,
+__global__ void k_compact(int64_t m, const uint8_t *keep, const int32_t *at, const int32_t *psrc,
                           const int32_t *pdst, const int32_t *ptau, const int32_t *peid,
                           int32_t *qsrc, int32_t *qdst, int32_t *qtau, int32_t *qeid) {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -390,7 +392,7 @@ enum ArenaSlot {
     A_COLOR, A_PDST, A_PSRC, A_PTAU, A_PEID, A_GSRC, A_OROW, A_INPTR, A_TP0, A_TPUB,
     A_TLB, A_LDS, A_TTAB, A_KEEPC, A_KEEP, A_AT, A_SCRATCH, A_GPOS, A_NEEDED, A_ROWOF, A_TSORT,
     A_TUNIQ, A_TCOUNT, A_CNT, A_PDEP, A_VDELAY, A_VKEEP, A_TSET, A_FID, A_TNZ, A_TPM, A_TCNT,
-    A_SCNT, A_TBASE, A_SBASE, A_TSTAT, A_VBITS, A_ROWPOS, A_GPOSP, A_NSLOTS
+    A_SCNT, A_TBASE, A_SBASE, A_TSTAT, A_VBITS, A_GPOSW, A_GPOSP, A_NSLOTS
 };
 
 struct GraphArena {
@@ -656,7 +658,7 @@ int32_t auto_tile_edges(int64_t m) {
 void free_graph(Graph &G) {
     int32_t **ptrs[] = {&G.color, &G.pdst,  &G.psrc,    &G.ptau,     &G.peid,   &G.gsrc,
                         &G.orow,  &G.inptr, &G.tile_p0, &G.tile_pub, &G.tile_lb,
-                        &G.ttab,  &G.pdep,  &G.vdelay, &G.fid,      &G.rowpos};
+                        &G.ttab,  &G.pdep,  &G.vdelay, &G.fid,      &G.gposw};
     const bool own = G.arena == nullptr;  // arena memory stays with the arena
     for (auto pp : ptrs) {
         if (*pp && own) (void)hipFree(*pp);
@@ -744,9 +746,10 @@ void finish_index(Graph &G, int64_t &acct, const int32_t *taus, bool greedy_tile
         unsigned long long h = 0;
         TPM_HIP(hipMemcpy(&h, cnt, sizeof(h), hipMemcpyDeviceToHost));
         G.gathers = (int64_t)h;
-        if (!G.arena) {  // whole graphs keep the row -> position map for pruning
-            G.rowpos = galloc<int32_t>(G, A_ROWPOS, std::max<int64_t>(1, G.R), acct);
-            k_rowpos<<<grid_for(m), 256, 0, st>>>(m, G.orow, G.rowpos);
+        if (!G.arena) {  // whole graphs keep the read positions for pruning
+            G.gposw = galloc<int32_t>(G, A_GPOSW, m, acct);
+            TPM_HIP(hipMemcpyAsync(G.gposw, gpos, sizeof(int32_t) * (size_t)m,
+                                   hipMemcpyDeviceToDevice, st));
         }
     }
     if (G.h_color.size() != (size_t)n) {
@@ -959,7 +962,8 @@ void prune_graph(const Graph &P, const PruneSpec &spec, Graph &G, GraphArena *ar
     hipStream_t st = nullptr;
     try {
         int64_t mk = 0;
-        int32_t *keep = nullptr, *at = nullptr;
+        uint8_t *keep = nullptr;
+        int32_t *at = nullptr;
         Temps outer(arena);
         int32_t *gpos_pre = nullptr;  // read positions mapped from the parent's
         {
@@ -985,7 +989,7 @@ void prune_graph(const Graph &P, const PruneSpec &spec, Graph &G, GraphArena *ar
                     ts = tmp.get<int32_t>(A_TSET, ntimes);
                     TPM_HIP(hipMemcpy(ts, times, sizeof(int32_t) * (size_t)ntimes, hipMemcpyHostToDevice));
                 }
-                keep = tmp.get<int32_t>(A_KEEP, P.m);
+                keep = tmp.get<uint8_t>(A_KEEP, P.m);
                 at = tmp.get<int32_t>(A_AT, P.m);
                 // timestamps of the edges as given (departures when transit times exist)
                 if (P.pcol && !vkeep_in && spec.cut_in < 0 && spec.cut_out < 0 && P.q <= 64) {
@@ -1008,9 +1012,10 @@ void prune_graph(const Graph &P, const PruneSpec &spec, Graph &G, GraphArena *ar
                 void *scratch = tmp.raw(A_SCRATCH, sbytes);
                 TPM_HIP(rocprim::exclusive_scan(scratch, sbytes, keep, at, 0, (size_t)P.m,
                                                 rocprim::plus<int32_t>(), st));
-                int32_t last_at = 0, last_keep = 0;
+                int32_t last_at = 0;
+                uint8_t last_keep = 0;
                 TPM_HIP(hipMemcpy(&last_at, at + (P.m - 1), sizeof(int32_t), hipMemcpyDeviceToHost));
-                TPM_HIP(hipMemcpy(&last_keep, keep + (P.m - 1), sizeof(int32_t), hipMemcpyDeviceToHost));
+                TPM_HIP(hipMemcpy(&last_keep, keep + (P.m - 1), 1, hipMemcpyDeviceToHost));
                 mk = (int64_t)last_at + last_keep;
             }
             G.m = mk;
@@ -1039,10 +1044,12 @@ void prune_graph(const Graph &P, const PruneSpec &spec, Graph &G, GraphArena *ar
                                                           P.peid, G.psrc, G.pdst, G.ptau, G.peid);
                 if (P.pdep)
                     k_compact1<<<grid_for(P.m), 256, 0, st>>>(P.m, keep, at, P.pdep, G.pdep);
-                if (P.rowpos) {
+                if (P.gposw) {
                     gpos_pre = outer.get<int32_t>(A_GPOSP, mk);
-                    k_gpos_remap<<<grid_for(P.m), 256, 0, st>>>(P.m, keep, at, P.gsrc, P.rowpos,
-                                                                P.psrc, P.inptr, gpos_pre);
+                    k_sub_inptr<<<grid_for((int64_t)P.n + 1), 256, 0, st>>>(P.n, P.m, P.inptr, at,
+                                                                            (int32_t)mk, G.inptr);
+                    k_gpos_remap<<<grid_for(P.m), 256, 0, st>>>(P.m, keep, at, (int32_t)mk, P.gposw,
+                                                                P.psrc, G.inptr, gpos_pre);
                 }
             }
             TPM_HIP(hipDeviceSynchronize());

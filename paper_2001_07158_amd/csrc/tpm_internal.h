@@ -184,8 +184,8 @@ struct Graph {
     int32_t *gsrc = nullptr;   // [m] state row read by the edge (last in-edge of src
                                //     earlier than tau), -1 if none
     int32_t *orow = nullptr;   // [m] state row written at this position, -1 if none
-    int32_t *rowpos = nullptr; // [R] position that writes each state row (whole graphs
-                               //     only: pruning maps gsrc through it)
+    int32_t *gposw = nullptr;  // [m] position whose row the edge reads, -1 if none
+                               //     (whole graphs only: pruning remaps it)
     uint16_t *pcol = nullptr;  // [m] colours of the edge's source (low byte) and head
                                //     (high byte): whole graphs with <= 64 colours
     int32_t *inptr = nullptr;  // [n+1]
