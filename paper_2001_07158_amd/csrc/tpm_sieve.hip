@@ -140,6 +140,14 @@ __device__ __forceinline__ uint32_t lds32(const uint8_t *lds, uint32_t addr) {
     return *(const uint32_t *)(lds + addr);
 }
 
+// Four bytes (each zero-extended in a dword) packed low to high: two byte permutes
+// and one shift-or.
+__device__ __forceinline__ uint32_t pack4(uint32_t b0, uint32_t b1, uint32_t b2, uint32_t b3) {
+    const uint32_t lo = __builtin_amdgcn_perm(b1, b0, 0x0C0C0400u);  // b0 | b1 << 8
+    const uint32_t hi = __builtin_amdgcn_perm(b3, b2, 0x0C0C0400u);  // b2 | b3 << 8
+    return lo | (hi << 16);
+}
+
 // x*y*g for the 4 points of dword g: lx7[i] = LOG7[x_i] + kExpBase + lanebits,
 // ly7 = LOG7[y] (uniform), zc = clamp address of this lane.
 __device__ __forceinline__ uint32_t mul4(const uint8_t *lds, uint32_t lanebits, uint32_t g,
@@ -148,8 +156,7 @@ __device__ __forceinline__ uint32_t mul4(const uint8_t *lds, uint32_t lanebits, 
     uint32_t s1 = min(lds32(lds, log_addr<1>(lanebits, g)) + lx7[1] + ly7, zc);
     uint32_t s2 = min(lds32(lds, log_addr<2>(lanebits, g)) + lx7[2] + ly7, zc);
     uint32_t s3 = min(lds32(lds, log_addr<3>(lanebits, g)) + lx7[3] + ly7, zc);
-    return (uint32_t)lds[s0] | ((uint32_t)lds[s1] << 8) | ((uint32_t)lds[s2] << 16) |
-           ((uint32_t)lds[s3] << 24);
+    return pack4(lds[s0], lds[s1], lds[s2], lds[s3]);
 }
 
 template <int W>
@@ -735,6 +742,254 @@ __global__ void __launch_bounds__(1024) k_narrow(LevelParams P) {
     }
 }
 
+// ---------------------------------------------------------------------------------
+// Slot tiles for narrow rows: each of the E = 64 / LP slots of a wave (LP lanes, 16
+// points a lane) runs a tile of its own, one position per step, as k_level runs a
+// tile with a whole wave: the running value of an in-list stays in the slot's lanes,
+// so no scan across slots is needed.  A ticket claims E consecutive tiles.  Per-slot
+// metadata comes from a window of LP positions held one per lane of the slot (the
+// step's lane is the same in every slot); the x row of a slot's destination is
+// fetched in the gather batch whenever the destination changes.  Publication,
+// look-back and the carry fix-up of continuation tiles are k_level's, per slot.
+// ---------------------------------------------------------------------------------
+template <bool FIN>
+__device__ __forceinline__ Win load_slot_win(const LevelParams &P, int32_t q, int32_t p1) {
+    Win m{-1, -1, -1, 0};
+    if (q < p1) {
+        m.g = P.gidx[q];
+        m.d = P.pdst[q];
+        if constexpr (!FIN) m.o = P.orow[q];
+        m.y = (uint32_t)P.peid[q];
+    }
+    return m;
+}
+
+__device__ __forceinline__ void finish_slot_win(const LevelParams &P, const uint8_t *lds, Win &m,
+                                                int32_t q, int32_t p1, uint32_t lanebits) {
+    if (q < p1) {
+        uint32_t y = fp8(P.seed, 1u, P.ylevel, m.y);
+        m.y = lds32(lds, (y << 8) | lanebits);
+    } else {
+        m.y = kZero7;
+    }
+}
+
+template <int LP, bool FIN>
+__global__ void __launch_bounds__(1024) k_slot(LevelParams P) {
+    constexpr int E = 64 / LP;  // slots (tiles) per wave
+    constexpr int U = 2;        // steps per batch; two batches in flight
+    static_assert(LP >= U && LP % U == 0, "batches tile a window");
+    __shared__ __attribute__((aligned(16))) uint8_t lds[kLdsBytes];
+    {
+        const uint4 *src = (const uint4 *)P.lds_image;
+        uint4 *dst = (uint4 *)lds;
+        for (int i = threadIdx.x; i < kLdsBytes / 16; i += blockDim.x) dst[i] = src[i];
+    }
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63;
+    const int slot = lane / LP, sub = lane % LP;
+    const int rowd = P.rowb >> 2;
+    const int64_t subofs = (int64_t)sub * 16;
+    const int sbase = slot * LP * 4;  // ds_bpermute address of the slot's first lane
+    const uint32_t rowb = (uint32_t)P.rowb;
+    const uint8_t *gsub = P.gbase + subofs, *xsub = P.xt + subofs;
+    uint8_t *osub = P.sout + subofs;
+    const uint32_t lanebits = (uint32_t)(lane & 31) << 2;
+    const uint32_t xbase = (uint32_t)kExpBase + lanebits;
+    const uint32_t zc = (uint32_t)kExpBase + ((uint32_t)kClampRow << 7) + lanebits;
+    const uint32_t epoch = __hip_atomic_load(&P.ctl->epoch, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT) & 0x3FFFFFFFu;
+    uint32_t fin[4] = {0, 0, 0, 0};
+
+    uint32_t tk = 0;
+    if (lane == 0) tk = atomicAdd(&P.ctl->ticket, 1u);
+    tk = __builtin_amdgcn_readfirstlane(__shfl(tk, 0));
+    for (;;) {
+        const int32_t tile0 = P.tile_lo + (int32_t)tk * E;
+        if (tile0 >= P.tile_hi) break;
+        uint32_t tk_next = 0;
+        if constexpr (FIN) {
+            if (lane == 0) tk_next = atomicAdd(&P.ctl->ticket, 1u);
+        }
+        const int32_t tile = tile0 + slot;
+        const bool has = tile < P.tile_hi;
+        const int32_t p0 = has ? P.tile_p0[tile] : 0;
+        const int32_t p1 = has ? P.tile_p0[tile + 1] : 0;
+        int32_t pubslot = -1, lbslot = -1;
+        if constexpr (!FIN) {
+            if (has) {
+                pubslot = P.tile_pub[tile];
+                lbslot = P.tile_lb[tile];
+            }
+        }
+        const bool cont = lbslot >= 0;
+        const int32_t len = p1 - p0;
+        int32_t K = len;  // steps: the longest tile of the wave
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) K = max(K, __shfl_xor(K, off));
+        K = __builtin_amdgcn_readfirstlane(K);
+
+        int32_t wb = 0;  // first step of the current window (uniform)
+        Win cw = load_slot_win<FIN>(P, p0 + sub, p1);
+        Win nw = load_slot_win<FIN>(P, p0 + LP + sub, p1);
+        finish_slot_win(P, lds, cw, p0 + sub, p1, lanebits);
+
+        uint32_t acc[4] = {0, 0, 0, 0};  // running value of the slot's in-list
+        int32_t cur_d = -1;               // in-list whose x row is in lx7
+        int32_t gprev = -1;               // gather side: destination of the last step
+        uint32_t lx7[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) lx7[i] = kZero7;
+
+        // one batch: U steps from step kb; the gathered row, and the x row of the
+        // destination where it changes
+        auto gather = [&](int32_t kb, uint32_t (&g)[U][4], uint32_t (&xr)[U][4]) {
+            const bool in_next = (kb - wb) >= LP;  // uniform
+            const int base = (kb - wb) - (in_next ? LP : 0);
+            const int32_t wg = in_next ? nw.g : cw.g, wd = in_next ? nw.d : cw.d;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int a = sbase + 4 * (base + u);
+                const int32_t r = __builtin_amdgcn_ds_bpermute(a, wg);
+                const int32_t d = __builtin_amdgcn_ds_bpermute(a, wd);
+                const bool valid = kb + u < len;
+                if (valid && r >= 0) {
+                    const uint4 t = *(const uint4 *)(gsub + (uint64_t)(uint32_t)r * rowb);
+                    g[u][0] = t.x; g[u][1] = t.y; g[u][2] = t.z; g[u][3] = t.w;
+                } else {
+                    g[u][0] = g[u][1] = g[u][2] = g[u][3] = 0;
+                }
+                if (valid && d != gprev) {
+                    const uint4 t = *(const uint4 *)(xsub + (uint64_t)(uint32_t)d * rowb);
+                    xr[u][0] = t.x; xr[u][1] = t.y; xr[u][2] = t.z; xr[u][3] = t.w;
+                }
+                if (valid) gprev = d;
+            }
+        };
+
+        auto process = [&](int32_t kb, const uint32_t (&g)[U][4], const uint32_t (&xr)[U][4]) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int32_t k = kb + u;
+                if (k >= K) break;
+                const int a = sbase + 4 * (k - wb);
+                const int32_t d = __builtin_amdgcn_ds_bpermute(a, cw.d);
+                const uint32_t ly7 = (uint32_t)__builtin_amdgcn_ds_bpermute(a, (int)cw.y);
+                const bool valid = k < len;
+                if (valid && d != cur_d) {  // a new in-list of this slot's tile
+#pragma unroll
+                    for (int w = 0; w < 4; ++w) {
+                        lx7[4 * w + 0] = lds32(lds, log_addr<0>(lanebits, xr[u][w])) + xbase;
+                        lx7[4 * w + 1] = lds32(lds, log_addr<1>(lanebits, xr[u][w])) + xbase;
+                        lx7[4 * w + 2] = lds32(lds, log_addr<2>(lanebits, xr[u][w])) + xbase;
+                        lx7[4 * w + 3] = lds32(lds, log_addr<3>(lanebits, xr[u][w])) + xbase;
+                        acc[w] = 0;
+                    }
+                    cur_d = d;
+                }
+                // no test needed: y = 0 (LOG7 kZero7, also past the tile's end) and g = 0
+                // both push every sum past the clamp, so the products come out zero
+                uint32_t c[4];
+#pragma unroll
+                for (int w = 0; w < 4; ++w) c[w] = mul4(lds, lanebits, g[u][w], &lx7[4 * w], ly7, zc);
+                if constexpr (FIN) {
+                    const int32_t p = p0 + k;
+                    const bool inr = valid && p >= P.pos_lo && p < P.pos_hi;
+                    if (inr) {
+#pragma unroll
+                        for (int w = 0; w < 4; ++w) fin[w] ^= c[w];
+                    }
+                    if (P.loc) {
+                        // only this chunk's real sieve points count
+                        const int lim = P.valid_pts - sub * 16;
+                        uint32_t x = 0;
+#pragma unroll
+                        for (int w = 0; w < 4; ++w) {
+                            const int nb = min(4, max(0, lim - 4 * w));
+                            const uint32_t keep = nb >= 4 ? 0xFFFFFFFFu : ((1u << (8 * nb)) - 1u);
+                            x ^= c[w] & keep;
+                        }
+                        if (!inr) x = 0;
+                        x ^= x >> 16;
+                        x ^= x >> 8;
+                        x &= 0xFFu;
+#pragma unroll
+                        for (int off = LP / 2; off >= 1; off >>= 1) x ^= __shfl_xor(x, off);
+                        if (inr && sub == 0) P.loc[p - P.pos_lo] ^= (uint8_t)x;
+                    }
+                } else {
+#pragma unroll
+                    for (int w = 0; w < 4; ++w) acc[w] ^= c[w];
+                    const int32_t o = __builtin_amdgcn_ds_bpermute(a, cw.o);
+                    if (valid && o >= 0)
+                        *(uint4 *)(osub + (uint64_t)(uint32_t)o * rowb) = make_uint4(acc[0], acc[1], acc[2], acc[3]);
+                }
+            }
+            // advance the window after its last batch
+            if (kb + U - wb == LP && kb + U < K) {
+                wb += LP;
+                cw = nw;
+                finish_slot_win(P, lds, cw, p0 + wb + sub, p1, lanebits);
+                nw = load_slot_win<FIN>(P, p0 + wb + LP + sub, p1);
+            }
+        };
+
+        uint32_t ga[U][4], gb[U][4], xa[U][4], xb[U][4];
+        gather(0, ga, xa);
+        for (int32_t kb = 0; kb < K;) {
+            gather(kb + U, gb, xb);
+            process(kb, ga, xa);
+            kb += U;
+            if (kb >= K) break;
+            gather(kb + U, ga, xa);
+            process(kb, gb, xb);
+            kb += U;
+        }
+
+        if constexpr (!FIN) {
+            if (pubslot >= 0)
+                publish<4>(P.pub, pubslot, rowd, LP, sub, cont ? kAgg : kInc, epoch, acc);
+            if (cont) {
+                uint32_t carry[4] = {0, 0, 0, 0};
+                lookback<4>(P.pub, lbslot, rowd, LP, sub, epoch, P.ctl, carry);
+                if (pubslot >= 0) {
+                    uint32_t inc[4];
+#pragma unroll
+                    for (int w = 0; w < 4; ++w) inc[w] = acc[w] ^ carry[w];
+                    publish<4>(P.pub, pubslot, rowd, LP, sub, kInc, epoch, inc);
+                }
+                // rows of a continuation tile were stored without the carry
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+                for (int32_t p = p0; p < p1; ++p) {
+                    const int32_t orow = P.orow[p];
+                    if (orow >= 0) {
+                        uint4 *q = (uint4 *)(P.sout + (int64_t)orow * P.rowb + subofs);
+                        uint4 t = *q;
+                        t.x ^= carry[0]; t.y ^= carry[1]; t.z ^= carry[2]; t.w ^= carry[3];
+                        *q = t;
+                    }
+                }
+            }
+            if (lane == 0) tk_next = atomicAdd(&P.ctl->ticket, 1u);
+        }
+        tk = __builtin_amdgcn_readfirstlane(__shfl(tk_next, 0));
+    }
+
+    if constexpr (FIN) {
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+#pragma unroll
+            for (int off = LP; off < 64; off <<= 1) fin[w] ^= __shfl_xor(fin[w], off);
+        }
+        if (lane < LP) {
+#pragma unroll
+            for (int w = 0; w < 4; ++w)
+                if (fin[w]) atomicXor(&P.fin[sub * 4 + w], fin[w]);
+        }
+    }
+}
+
 __global__ void k_prep(Ctl *ctl, int bump_epoch) {
     ctl->ticket = 0;
     if (bump_epoch) ctl->epoch = (ctl->epoch + 1u) & 0x3FFFFFFFu;
@@ -1180,8 +1435,7 @@ __device__ __forceinline__ uint32_t gmul4(const uint8_t *lds, uint32_t lanebits,
     uint32_t s1 = min(lds32(lds, log_addr<1>(lanebits, a)) + lds32(lds, log_addr<1>(lanebits, b)) + xbase, zc);
     uint32_t s2 = min(lds32(lds, log_addr<2>(lanebits, a)) + lds32(lds, log_addr<2>(lanebits, b)) + xbase, zc);
     uint32_t s3 = min(lds32(lds, log_addr<3>(lanebits, a)) + lds32(lds, log_addr<3>(lanebits, b)) + xbase, zc);
-    return (uint32_t)lds[s0] | ((uint32_t)lds[s1] << 8) | ((uint32_t)lds[s2] << 16) |
-           ((uint32_t)lds[s3] << 24);
+    return pack4(lds[s0], lds[s1], lds[s2], lds[s3]);
 }
 
 __device__ __forceinline__ void load_lds_image(uint8_t *lds, const uint8_t *image) {
@@ -1382,16 +1636,28 @@ void launch_level(const Graph &G, const LevelParams &P, hipStream_t st) {
                        dim3(1024), 0, st, P);
 }
 
+// 128- and 256-point rows run slot tiles (k_slot), smaller rows the scan kernel
+// (k_narrow).  Per middle level of a 1e8-edge graph: 256 points 7.5 against 9.5 ms,
+// 128 points 4.6 against 5.4 ms, but 64 points 4.3 against 3.2 ms (sixteen tiles per
+// ticket leave too few tickets per wave to balance).
 template <int LP>
 void launch_narrow(bool fin, const Graph &G, const LevelParams &P, hipStream_t st) {
-    const dim3 grid(persistent_grid(G, P.tile_hi - P.tile_lo));
-    if (fin) hipLaunchKernelGGL((k_narrow<LP, true>), grid, dim3(1024), 0, st, P);
-    else hipLaunchKernelGGL((k_narrow<LP, false>), grid, dim3(1024), 0, st, P);
+    if constexpr (LP >= 8) {
+        constexpr int E = 64 / LP;
+        const dim3 grid(persistent_grid(G, (P.tile_hi - P.tile_lo + E - 1) / E));
+        if (fin) hipLaunchKernelGGL((k_slot<LP, true>), grid, dim3(1024), 0, st, P);
+        else hipLaunchKernelGGL((k_slot<LP, false>), grid, dim3(1024), 0, st, P);
+    } else {
+        const dim3 grid(persistent_grid(G, P.tile_hi - P.tile_lo));
+        if (fin) hipLaunchKernelGGL((k_narrow<LP, true>), grid, dim3(1024), 0, st, P);
+        else hipLaunchKernelGGL((k_narrow<LP, false>), grid, dim3(1024), 0, st, P);
+    }
 }
 
-// rows of 16..256 points run edge-parallel (k_narrow); rows of 512 and 1024 points run
-// one position per wave (k_level with 2 or 4 dwords a lane), which measured faster at
-// 512 points (15.0 against 16.9 ms per middle level of a 1e8-edge graph)
+// rows of 16..256 points run several positions per wave (k_slot, k_narrow); rows of 512
+// and 1024 points run one position per wave (k_level with 2 or 4 dwords a lane), which
+// measured faster at 512 points (15.0 against 16.9 ms per middle level of a 1e8-edge
+// graph)
 bool is_narrow(int rowb) { return rowb >= 16 && rowb <= 256; }
 
 void launch_level_any(int rowb, bool fin, const Graph &G, const LevelParams &P, hipStream_t st) {
