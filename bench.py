@@ -209,7 +209,7 @@ def main() -> int:
         "copy_gbps_reference": copy_gbps(torch),
         "roofline": {
             "bound": "hbm",
-            "kernel": (f"k_level ({C}-point rows, {dom} level)" if C >= 512
+            "kernel": (f"k_level ({C}-point rows, {dom} level)" if C >= 1024
                        else f"k_slot ({C}-point rows, {dom} level)" if C >= 128
                        else f"k_narrow ({C}-point rows, {dom} level)"),
             "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",

@@ -748,9 +748,10 @@ __global__ void __launch_bounds__(1024) k_narrow(LevelParams P) {
 // tile with a whole wave: the running value of an in-list stays in the slot's lanes,
 // so no scan across slots is needed.  A ticket claims E consecutive tiles.  Per-slot
 // metadata comes from a window of LP positions held one per lane of the slot (the
-// step's lane is the same in every slot); the x row of a slot's destination is
-// fetched in the gather batch whenever the destination changes.  Publication,
-// look-back and the carry fix-up of continuation tiles are k_level's, per slot.
+// step's lane is the same in every slot); the x row of the first new destination of a
+// batch is fetched with the batch's gathers, a second one in the same batch when it is
+// reached.  Publication, look-back and the carry fix-up of continuation tiles are
+// k_level's, per slot.
 // ---------------------------------------------------------------------------------
 template <bool FIN>
 __device__ __forceinline__ Win load_slot_win(const LevelParams &P, int32_t q, int32_t p1) {
@@ -777,7 +778,7 @@ __device__ __forceinline__ void finish_slot_win(const LevelParams &P, const uint
 template <int LP, bool FIN>
 __global__ void __launch_bounds__(1024) k_slot(LevelParams P) {
     constexpr int E = 64 / LP;  // slots (tiles) per wave
-    constexpr int U = 2;        // steps per batch; two batches in flight
+    constexpr int U = 4;        // steps per batch; two batches in flight
     static_assert(LP >= U && LP % U == 0, "batches tile a window");
     __shared__ __attribute__((aligned(16))) uint8_t lds[kLdsBytes];
     {
@@ -844,7 +845,8 @@ __global__ void __launch_bounds__(1024) k_slot(LevelParams P) {
 
         // one batch: U steps from step kb; the gathered row, and the x row of the
         // destination where it changes
-        auto gather = [&](int32_t kb, uint32_t (&g)[U][4], uint32_t (&xr)[U][4]) {
+        auto gather = [&](int32_t kb, uint32_t (&g)[U][4], uint32_t (&xr)[4], int32_t &xd) {
+            xd = -1;
             const bool in_next = (kb - wb) >= LP;  // uniform
             const int base = (kb - wb) - (in_next ? LP : 0);
             const int32_t wg = in_next ? nw.g : cw.g, wd = in_next ? nw.d : cw.d;
@@ -860,15 +862,19 @@ __global__ void __launch_bounds__(1024) k_slot(LevelParams P) {
                 } else {
                     g[u][0] = g[u][1] = g[u][2] = g[u][3] = 0;
                 }
-                if (valid && d != gprev) {
+                if (valid && d != gprev && xd < 0) {  // the batch's first new in-list
                     const uint4 t = *(const uint4 *)(xsub + (uint64_t)(uint32_t)d * rowb);
-                    xr[u][0] = t.x; xr[u][1] = t.y; xr[u][2] = t.z; xr[u][3] = t.w;
+                    xr[0] = t.x; xr[1] = t.y; xr[2] = t.z; xr[3] = t.w;
+                    xd = d;
                 }
                 if (valid) gprev = d;
             }
         };
 
-        auto process = [&](int32_t kb, const uint32_t (&g)[U][4], const uint32_t (&xr)[U][4]) {
+        auto process = [&](int32_t kb, const uint32_t (&g)[U][4], const uint32_t (&xr)[4], int32_t xd) {
+            // last level with localisation: this lane's XOR of each step's points, one
+            // byte per step
+            uint32_t lp = 0;
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int32_t k = kb + u;
@@ -878,12 +884,17 @@ __global__ void __launch_bounds__(1024) k_slot(LevelParams P) {
                 const uint32_t ly7 = (uint32_t)__builtin_amdgcn_ds_bpermute(a, (int)cw.y);
                 const bool valid = k < len;
                 if (valid && d != cur_d) {  // a new in-list of this slot's tile
+                    uint32_t x[4] = {xr[0], xr[1], xr[2], xr[3]};
+                    if (d != xd) {  // a second new in-list in the batch: not fetched ahead
+                        const uint4 t = *(const uint4 *)(xsub + (uint64_t)(uint32_t)d * rowb);
+                        x[0] = t.x; x[1] = t.y; x[2] = t.z; x[3] = t.w;
+                    }
 #pragma unroll
                     for (int w = 0; w < 4; ++w) {
-                        lx7[4 * w + 0] = lds32(lds, log_addr<0>(lanebits, xr[u][w])) + xbase;
-                        lx7[4 * w + 1] = lds32(lds, log_addr<1>(lanebits, xr[u][w])) + xbase;
-                        lx7[4 * w + 2] = lds32(lds, log_addr<2>(lanebits, xr[u][w])) + xbase;
-                        lx7[4 * w + 3] = lds32(lds, log_addr<3>(lanebits, xr[u][w])) + xbase;
+                        lx7[4 * w + 0] = lds32(lds, log_addr<0>(lanebits, x[w])) + xbase;
+                        lx7[4 * w + 1] = lds32(lds, log_addr<1>(lanebits, x[w])) + xbase;
+                        lx7[4 * w + 2] = lds32(lds, log_addr<2>(lanebits, x[w])) + xbase;
+                        lx7[4 * w + 3] = lds32(lds, log_addr<3>(lanebits, x[w])) + xbase;
                         acc[w] = 0;
                     }
                     cur_d = d;
@@ -913,10 +924,7 @@ __global__ void __launch_bounds__(1024) k_slot(LevelParams P) {
                         if (!inr) x = 0;
                         x ^= x >> 16;
                         x ^= x >> 8;
-                        x &= 0xFFu;
-#pragma unroll
-                        for (int off = LP / 2; off >= 1; off >>= 1) x ^= __shfl_xor(x, off);
-                        if (inr && sub == 0) P.loc[p - P.pos_lo] ^= (uint8_t)x;
+                        lp |= (x & 0xFFu) << (8 * u);
                     }
                 } else {
 #pragma unroll
@@ -924,6 +932,17 @@ __global__ void __launch_bounds__(1024) k_slot(LevelParams P) {
                     const int32_t o = __builtin_amdgcn_ds_bpermute(a, cw.o);
                     if (valid && o >= 0)
                         *(uint4 *)(osub + (uint64_t)(uint32_t)o * rowb) = make_uint4(acc[0], acc[1], acc[2], acc[3]);
+                }
+            }
+            if constexpr (FIN) {
+                if (P.loc) {
+                    // XOR across the slot's lanes, all steps of the batch at once; lane
+                    // sub < U then adds step kb + sub's byte
+#pragma unroll
+                    for (int off = LP / 2; off >= 1; off >>= 1) lp ^= __shfl_xor(lp, off);
+                    const int32_t p = p0 + kb + sub;
+                    if (sub < U && kb + sub < len && p >= P.pos_lo && p < P.pos_hi)
+                        P.loc[p - P.pos_lo] ^= (uint8_t)(lp >> (8 * (sub & (U - 1))));
                 }
             }
             // advance the window after its last batch
@@ -935,15 +954,16 @@ __global__ void __launch_bounds__(1024) k_slot(LevelParams P) {
             }
         };
 
-        uint32_t ga[U][4], gb[U][4], xa[U][4], xb[U][4];
-        gather(0, ga, xa);
+        uint32_t ga[U][4], gb[U][4], xa[4], xb[4];
+        int32_t xda, xdb;
+        gather(0, ga, xa, xda);
         for (int32_t kb = 0; kb < K;) {
-            gather(kb + U, gb, xb);
-            process(kb, ga, xa);
+            gather(kb + U, gb, xb, xdb);
+            process(kb, ga, xa, xda);
             kb += U;
             if (kb >= K) break;
-            gather(kb + U, ga, xa);
-            process(kb, gb, xb);
+            gather(kb + U, ga, xa, xda);
+            process(kb, gb, xb, xdb);
             kb += U;
         }
 
@@ -1636,10 +1656,12 @@ void launch_level(const Graph &G, const LevelParams &P, hipStream_t st) {
                        dim3(1024), 0, st, P);
 }
 
-// 128- and 256-point rows run slot tiles (k_slot), smaller rows the scan kernel
-// (k_narrow).  Per middle level of a 1e8-edge graph: 256 points 7.5 against 9.5 ms,
-// 128 points 4.6 against 5.4 ms, but 64 points 4.3 against 3.2 ms (sixteen tiles per
-// ticket leave too few tickets per wave to balance).
+// 128- to 512-point rows run slot tiles (k_slot), smaller rows the scan kernel
+// (k_narrow).  Per middle level of a 1e8-edge graph: 512 points 13.3 ms (k_level with
+// 2 dwords a lane: 14.9), 256 points 7.4 ms (k_narrow 9.5), 128 points 4.6 ms (k_narrow
+// 5.4), but 64 points 4.3 against 3.2 ms for k_narrow (sixteen tiles per ticket leave
+// too few tickets per wave to balance).  At 1024 points a single slot matches k_level
+// (25.8 ms) and k_level stays.
 template <int LP>
 void launch_narrow(bool fin, const Graph &G, const LevelParams &P, hipStream_t st) {
     if constexpr (LP >= 8) {
@@ -1654,17 +1676,13 @@ void launch_narrow(bool fin, const Graph &G, const LevelParams &P, hipStream_t s
     }
 }
 
-// rows of 16..256 points run several positions per wave (k_slot, k_narrow); rows of 512
-// and 1024 points run one position per wave (k_level with 2 or 4 dwords a lane), which
-// measured faster at 512 points (15.0 against 16.9 ms per middle level of a 1e8-edge
-// graph)
+// rows of 16..512 points run several positions per wave (k_slot, k_narrow); rows of
+// 1024 points run one position per wave (k_level).  Rows of 16..256 points:
 bool is_narrow(int rowb) { return rowb >= 16 && rowb <= 256; }
 
 void launch_level_any(int rowb, bool fin, const Graph &G, const LevelParams &P, hipStream_t st) {
-    if (rowb == 512) {  // one position per wave, 8 points per lane
-        LevelParams Q = P;
-        Q.lanes = 64;
-        fin ? launch_level<2, true>(G, Q, st) : launch_level<2, false>(G, Q, st);
+    if (rowb == 512) {  // two slots of 32 lanes per wave
+        launch_narrow<32>(fin, G, P, st);
         return;
     }
     switch (is_narrow(rowb) ? rowb / 16 : 0) {
