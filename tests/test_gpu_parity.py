@@ -100,6 +100,35 @@ def test_tile_shapes_with_hubs(tpm, T):
     _check(tpm, g, M, 42, tile_edges=T, label=f"hubs T={T}")
 
 
+@pytest.mark.parametrize("chunk", [128, 256, 512])
+@pytest.mark.parametrize("T", [1, 5, 64])
+def test_slot_tiles_with_hubs(tpm, chunk, T):
+    """Rows of 128..512 points run several tiles per wave, one per slot: hub in-lists
+    split over many tiny tiles put a piece's predecessor in the same wave (look-back
+    within a ticket), tile counts leave idle slots, and tiles of one ticket differ in
+    length."""
+    g = G.chung_lu_graph(3000, 60000, 2.5, 50, 3, 1234)
+    M = [0, 1, 2, 0, 1, 2, 0, 1, 2]  # k = 9, 512 points
+    _check(tpm, g, M, 43, chunk=chunk, tile_edges=T, label=f"slot hubs chunk={chunk} T={T}")
+
+
+@pytest.mark.parametrize("k", [7, 8, 9])
+def test_slot_tiles_localisation(tpm, k):
+    """Per-edge localisation of the last level at 128-, 256- and 512-point rows, where
+    a batch's bytes are reduced across the slot's lanes together."""
+    rng = np.random.default_rng(40 + k)
+    g = G.chung_lu_graph(1500, 30000, 2.5, 40, 3, 300 + k)
+    M = [int(c) for c in rng.integers(0, 3, k)]
+    T = int(rng.integers(1, 40))
+    say(f"case slot loc k={k} T={T} M={M}")
+    Gd = tpm.Graph.from_temporal(g, tile_edges=T)
+    pp, tot, loc = Gd.sieve(M, 17 + k, loc=True)
+    wpp, wloc = oracle.sieve(g, M, 17 + k, loc=True)
+    assert np.array_equal(pp, wpp)
+    assert np.array_equal(loc, wloc)
+    Gd.close()
+
+
 @pytest.mark.parametrize("chunk", [4, 16, 64, 256, 512, 1024])
 def test_chunk_sizes(tpm, chunk):
     g = G.chung_lu_graph(2000, 30000, 2.5, 40, 4, 77)
