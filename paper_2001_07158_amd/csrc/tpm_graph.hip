@@ -39,7 +39,8 @@ __global__ void k_validate(int64_t m, int32_t n, const int32_t *src, const int32
         if (s < 0 || s >= n || d < 0 || d >= n || t < 1) atomicOr(bad, 1);
         local_max = max(local_max, t);
     }
-    atomicMax(tmax, local_max);
+    for (int off = 32; off >= 1; off >>= 1) local_max = max(local_max, __shfl_xor(local_max, off));
+    if ((threadIdx.x & 63) == 0) atomicMax(tmax, local_max);
 }
 
 __global__ void k_validate_color(int32_t n, int32_t q, const int32_t *color, int32_t *bad) {
@@ -88,7 +89,8 @@ __global__ void k_arrival(int64_t m, const int32_t *tau, const int32_t *transit,
             local = max(local, (int32_t)a);
         }
     }
-    atomicMax(amax, local);
+    for (int off = 32; off >= 1; off >>= 1) local = max(local, __shfl_xor(local, off));
+    if ((threadIdx.x & 63) == 0) atomicMax(amax, local);
 }
 
 // inptr[u] = first position whose dst >= u; every position writes the entries of
@@ -256,23 +258,6 @@ __global__ void k_sub_inptr(int32_t n, int64_t m, const int32_t *pinptr, const i
     inptr[u] = x < m ? at[x] : mk;
 }
 
-// The read position of a kept edge in the subgraph: the last kept position at or before
-// its parent read position g (positions keep their order), if that is still in the
-// source's in-list (sub_inptr: the subgraph's in-list starts).
-__global__ void k_gpos_remap(int64_t m, const uint8_t *keep, const int32_t *at, int32_t mk,
-                             const int32_t *gposw, const int32_t *psrc, const int32_t *sub_inptr,
-                             int32_t *gpos) {
-    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= m || !keep[p]) return;
-    int32_t q = -1;
-    const int32_t g = gposw[p];
-    if (g >= 0) {
-        const int32_t last = (g + 1 < m ? at[g + 1] : mk) - 1;
-        if (last >= sub_inptr[psrc[p]]) q = last;
-    }
-    gpos[at[p]] = q;
-}
-
 __global__ void k_needed(int64_t m, const int32_t *gpos, int32_t *needed) {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p < m && gpos[p] >= 0) needed[gpos[p]] = 1;  // every writer stores the same value
@@ -284,16 +269,33 @@ __global__ void k_compact1(int64_t m, const uint8_t *keep, const int32_t *at, co
     if (p < m && keep[p]) b[at[p]] = a[p];
 }
 
-__global__ void k_compact(int64_t m, const uint8_t *keep, const int32_t *at, const int32_t *psrc,
-                          const int32_t *pdst, const int32_t *ptau, const int32_t *peid,
-                          int32_t *qsrc, int32_t *qdst, int32_t *qtau, int32_t *qeid) {
+// Kept positions copied in order (at = exclusive count of the m kept flags, mk = their
+// total).  With gposw (the parent's read positions), also the read position of each
+// kept edge in the subgraph: the last kept position at or before its parent read
+// position g (positions keep their order), if that is still in the source's in-list
+// (sub_inptr: the subgraph's in-list starts); -1 otherwise.
+__global__ void k_compact(int64_t m, const uint8_t *keep, const int32_t *at, int32_t mk,
+                          const int32_t *psrc, const int32_t *pdst, const int32_t *ptau,
+                          const int32_t *peid, const int32_t *gposw, const int32_t *sub_inptr,
+                          int32_t *qsrc, int32_t *qdst, int32_t *qtau, int32_t *qeid,
+                          int32_t *qgpos) {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p < m && keep[p]) {
         const int32_t q = at[p];
-        qsrc[q] = psrc[p];
+        const int32_t s = psrc[p];
+        qsrc[q] = s;
         qdst[q] = pdst[p];
         qtau[q] = ptau[p];
         qeid[q] = peid[p];
+        if (gposw) {
+            int32_t r = -1;
+            const int32_t g = gposw[p];
+            if (g >= 0) {
+                const int32_t last = (g + 1 < m ? at[g + 1] : mk) - 1;
+                if (last >= sub_inptr[s]) r = last;
+            }
+            qgpos[q] = r;
+        }
     }
 }
 
@@ -309,13 +311,15 @@ __global__ void k_tile_prev(int32_t n, const int32_t *inptr, int32_t *nz) {
     if (u < n) nz[u] = inptr[u + 1] > inptr[u] ? (int32_t)u : -1;
 }
 
+// grid-stride over vertices (a bounded grid keeps the two statistics atomics few: one
+// pair per wave)
 __global__ void k_tile_count(int32_t n, const int32_t *inptr, int32_t T, const int32_t *prevmax,
                              int32_t *tcnt, int32_t *scnt, unsigned long long *stats) {
-    int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int32_t L = 0;
-    if (u < n) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    unsigned long long mx = 0, ne = 0;
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += stride) {
         const int32_t a = inptr[u];
-        L = inptr[u + 1] - a;
+        const int32_t L = inptr[u + 1] - a;
         int32_t t = 0, sl = 0;
         if (L > T) {
             t = (L + T - 1) / T;
@@ -331,16 +335,17 @@ __global__ void k_tile_count(int32_t n, const int32_t *inptr, int32_t T, const i
         }
         tcnt[u] = t;
         scnt[u] = sl;
+        // in-degree statistics: largest and non-empty count
+        mx = (unsigned long long)L > mx ? (unsigned long long)L : mx;
+        ne += L > 0 ? 1ull : 0ull;
     }
-    // in-degree statistics: largest and non-empty count
-    unsigned long long mx = (unsigned long long)L, ne = L > 0 ? 1ull : 0ull;
     for (int off = 32; off >= 1; off >>= 1) {
         const unsigned long long o = __shfl_xor(mx, off);
         mx = o > mx ? o : mx;
         ne += __shfl_xor(ne, off);
     }
     if ((threadIdx.x & 63) == 0) {
-        atomicMax(&stats[0], mx);
+        if (mx) atomicMax(&stats[0], mx);
         if (ne) atomicAdd(&stats[1], ne);
     }
 }
@@ -576,7 +581,7 @@ void build_tiles_device(Graph &G, int32_t T, Temps &tmp, int64_t &acct, int32_t 
     TPM_HIP(rocprim::exclusive_scan(nullptr, b2, tcnt, tbase, 0, (size_t)n, rocprim::plus<int32_t>(), st));
     void *scratch = tmp.raw(A_SCRATCH, std::max(b1, b2));
     TPM_HIP(rocprim::inclusive_scan(scratch, b1, nz, pm, (size_t)n, rocprim::maximum<int32_t>(), st));
-    k_tile_count<<<grid_for(n), 256, 0, st>>>(n, G.inptr, T, pm, tcnt, scnt, stats);
+    k_tile_count<<<std::min<unsigned>(grid_for(n), 2048), 256, 0, st>>>(n, G.inptr, T, pm, tcnt, scnt, stats);
     TPM_HIP(rocprim::exclusive_scan(scratch, b2, tcnt, tbase, 0, (size_t)n, rocprim::plus<int32_t>(), st));
     TPM_HIP(rocprim::exclusive_scan(scratch, b2, scnt, sbase, 0, (size_t)n, rocprim::plus<int32_t>(), st));
     int32_t h[4] = {0, 0, 0, 0};
@@ -1040,17 +1045,16 @@ void prune_graph(const Graph &P, const PruneSpec &spec, Graph &G, GraphArena *ar
                                        hipMemcpyDeviceToDevice, st));
             }
             if (mk) {  // kept positions stay in (dst, arrival, id) order
-                k_compact<<<grid_for(P.m), 256, 0, st>>>(P.m, keep, at, P.psrc, P.pdst, P.ptau,
-                                                          P.peid, G.psrc, G.pdst, G.ptau, G.peid);
-                if (P.pdep)
-                    k_compact1<<<grid_for(P.m), 256, 0, st>>>(P.m, keep, at, P.pdep, G.pdep);
-                if (P.gposw) {
+                if (P.gposw) {  // read positions remapped from the parent's
                     gpos_pre = outer.get<int32_t>(A_GPOSP, mk);
                     k_sub_inptr<<<grid_for((int64_t)P.n + 1), 256, 0, st>>>(P.n, P.m, P.inptr, at,
                                                                             (int32_t)mk, G.inptr);
-                    k_gpos_remap<<<grid_for(P.m), 256, 0, st>>>(P.m, keep, at, (int32_t)mk, P.gposw,
-                                                                P.psrc, G.inptr, gpos_pre);
                 }
+                k_compact<<<grid_for(P.m), 256, 0, st>>>(P.m, keep, at, (int32_t)mk, P.psrc, P.pdst,
+                                                          P.ptau, P.peid, P.gposw, G.inptr, G.psrc,
+                                                          G.pdst, G.ptau, G.peid, gpos_pre);
+                if (P.pdep)
+                    k_compact1<<<grid_for(P.m), 256, 0, st>>>(P.m, keep, at, P.pdep, G.pdep);
             }
             TPM_HIP(hipDeviceSynchronize());
         }
