@@ -25,3 +25,13 @@ def test_kernel_hash_and_committed_traffic(points):
     h = bench.kernel_hash(points)
     assert len(h) == 16
     assert bench.read_traffic(points) is not None, f"profile for {points}-point rows is stale"
+
+
+@pytest.mark.parametrize("name,points", [("k10_sieve_kernel_trace.txt", 1024),
+                                         ("k10_narrow_c256_kernel_trace.txt", 256)])
+def test_committed_kernel_traces_match_source(name, points):
+    """The committed kernel-trace summaries name the source hash they were taken on."""
+    sys.path.insert(0, ROOT)
+    import bench
+    text = open(os.path.join(ROOT, "profiles", name)).read()
+    assert f"source hash: {bench.kernel_hash(points)}" in text, f"{name} is stale"
