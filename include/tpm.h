@@ -53,7 +53,7 @@ typedef int32_t tpm_status;
 #define TPM_EINVAL (-1)  /* invalid argument or malformed input */
 #define TPM_ENOMEM (-2)  /* device or host allocation failed */
 #define TPM_EDEVICE (-3) /* HIP runtime error or a kernel-reported fault */
-#define TPM_ECANCELLED (-4)
+#define TPM_ECANCELLED (-4) /* server: the request was cancelled or passed its deadline */
 #define TPM_ECLOSED (-5) /* server is shutting down */
 
 /* graph creation flags */
@@ -116,18 +116,20 @@ typedef struct {
 /* Per-call tuning.  Every admissible setting gives bit-identical results.
  * chunk:     sieve points per pass (power of two, 4..1024; 0 = min(2^k, 1024));
  *            for tpm_batch_run the row width (256, 512 or 1024; 0 = 1024).
- * use_graph: tpm_batch_run only: 1 = each pass replays its level launches from a
- *            HIP graph captured once per row shape (lane tables live in device
- *            memory), on a stream the call creates; 0 = plain launches on the
- *            null stream.
+ * use_graph: tpm_batch_run only: 1 = each row step replays its launches from a HIP
+ *            graph captured once per row shape (lane tables live in device memory),
+ *            on a stream the call creates; 0 = plain launches.
  * prune:     tpm_sieve_ex and tpm_batch_run: 1 = each query runs alone on the
  *            subgraph of its own colours (as tpm_graph_prune; built in memory the
  *            graph keeps for this), which gives the same results; queries with
- *            wildcards run on the whole graph.  tpm_batch_run then does not pack. */
+ *            wildcards run on the whole graph.  tpm_batch_run then runs up to
+ *            `streams` such queries at once instead of packing rows. */
 typedef struct {
     int32_t chunk;
     int32_t use_graph;
     int32_t prune;
+    int32_t streams;  /* tpm_batch_run with prune = 1: queries in flight at once, each on
+                         its own HIP stream (0 = 3, at most 4) */
 } tpm_tuning;
 
 /* ---------------------------------------------------------------- graph --- */
@@ -353,9 +355,22 @@ typedef struct {
     int32_t k;
     uint64_t seed;
     int32_t want_path;       /* 1: extract a path when the sieve is nonzero */
+    uint8_t *per_point;      /* nullable, host, 2^k bytes: receives P_{k,t}(z^A) for every
+                                sieve point A, as tpm_sieve's per_point.  tpm_batch_run
+                                writes it before returning; a server writes it before
+                                tpm_server_poll hands out the result, so the buffer must
+                                stay valid until then (it is left alone on a result whose
+                                status is not TPM_OK) */
+    double deadline_ms;      /* server only: the request ends with status TPM_ECANCELLED
+                                if it has not finished this many ms after its submission
+                                (checked while queued and between level launches; 0 =
+                                no deadline) */
 } tpm_query;
 
 typedef struct {
+    int32_t status;          /* TPM_OK, or (server) TPM_ECANCELLED (tpm_server_cancel or
+                                the deadline), TPM_ENOMEM (the request did not fit the
+                                state budget even alone), TPM_EDEVICE (a device error) */
     int32_t found;           /* 1 iff the sieve total was nonzero */
     uint8_t total;
     int32_t path_status;     /* TPM_OK / TPM_NOTFOUND / 0 when not requested */
@@ -366,7 +381,13 @@ typedef struct {
 } tpm_result;
 
 /* Run nq queries against one graph.  Each result is bit-identical to the same
- * query run alone through tpm_sieve (same seed).  tune may be NULL. */
+ * query run alone through tpm_sieve (same seed), per point when the query asks for
+ * per-point output.  Without pruning the queries share resident multi-query rows
+ * (lane groups of any k side by side; a finished group's lanes are refilled from the
+ * queries still waiting, largest first); with tune->prune each query runs alone on
+ * the subgraph of its colours, up to tune->streams at once on their own streams and
+ * within a device-memory budget (85 % of the memory free at the call).  tune may be
+ * NULL.  Errors: TPM_EINVAL (bad query or tuning), TPM_ENOMEM, TPM_EDEVICE. */
 tpm_status tpm_batch_run(const tpm_graph *g, int32_t nq, const tpm_query *q, tpm_result *out,
                          const tpm_tuning *tune);
 
@@ -383,31 +404,61 @@ tpm_status tpm_rainbow_decide(const tpm_graph *g, int32_t k, uint64_t seed, int3
 /* ---------------------------------------------------------------- serve --- */
 typedef struct tpm_server tpm_server;
 
+/* Two modes, both continuous batching: requests that arrive while others run are
+ * admitted as lanes or memory free up, and their work overlaps on the device.
+ *   Row mode (prune_queries = 0): one resident multi-query row of up to 64 lanes over
+ *     the whole graph; every row step advances each lane group one level, finished
+ *     groups free their lanes and waiting requests (any that fit, not only the oldest)
+ *     take them at the next step.  Extraction runs on its own thread and stream.
+ *   Pruned mode (prune_queries = 1): each request runs alone on the subgraph of its
+ *     colours (as tpm_graph_prune), up to `streams` requests at once, each on its own
+ *     HIP stream and worker thread, admitted when its estimated device memory (subgraph
+ *     index and sieve state, from the exact edge count of its colour pairs) fits the
+ *     state budget; a request that does not fit can be overtaken by later ones that
+ *     do, at most 8 times.  Extraction on a hit is the reverse DFS from the deciding
+ *     sieve's own vertex localisation.
+ * Results are identical in both modes, to the same query run alone. */
 typedef struct {
-    int64_t state_bytes;   /* device memory the server may use for query state (0 = auto) */
-    int32_t max_lanes;     /* most sieve lanes resident at once (0 = auto) */
+    int64_t state_bytes;   /* device memory the server may use for query state (0 = 85 %
+                              of the memory free at creation); pruned mode rejects a
+                              request whose smallest state cannot fit it */
+    int32_t max_lanes;     /* row mode: most sieve lanes resident at once (0 = auto) */
     int32_t extract_paths; /* 1: extract a witness for every YES */
-    int32_t prune_queries; /* 1: each request runs alone on the subgraph of its colours
-                              (as tpm_graph_prune), one request at a time, instead of
-                              sharing a resident multi-query row; results are identical */
+    int32_t prune_queries; /* 1: pruned mode (above) */
+    int32_t streams;       /* pruned mode: requests in flight at once (0 = 3; 1..4) */
 } tpm_server_config;
 
 tpm_status tpm_server_create(const tpm_graph *g, const tpm_server_config *cfg, tpm_server **out);
+/* Queue a request (the multiset is copied).  Errors: TPM_EINVAL (bad query),
+ * TPM_ENOMEM (pruned mode: the request cannot fit the state budget even alone),
+ * TPM_ECLOSED, TPM_EDEVICE (the server stopped on a device error). */
 tpm_status tpm_server_submit(tpm_server *s, const tpm_query *q, uint64_t *ticket);
 /* Copy up to max finished results into out; *n_out = how many. TPM_PENDING if
  * none is ready yet. */
 tpm_status tpm_server_poll(tpm_server *s, tpm_result *out, int32_t max, int32_t *n_out);
+/* Cancel a request that has not finished: it ends with status TPM_ECANCELLED (a queued
+ * request at once, a running one at its next level launch or row step).  TPM_NOTFOUND
+ * if the ticket is unknown or its result is already out. */
+tpm_status tpm_server_cancel(tpm_server *s, uint64_t ticket);
 void tpm_server_destroy(tpm_server *s);
 
 /* Counters of a server since creation (host clock, ms). */
 typedef struct {
-    int64_t completed;     /* results produced */
-    int64_t steps;         /* row steps (batching mode) or requests run (pruned mode) */
-    int32_t row_points;    /* sieve points per resident row (batching mode), else 0 */
-    int32_t lanes;         /* lanes of the resident row (batching mode), else 0 */
-    double prune_ms;       /* building per-request subgraphs (pruned mode) */
-    double sieve_ms;       /* sieving: row steps, or per-request sieves */
-    double extract_ms;     /* witness extraction */
+    int64_t completed;     /* results produced (every status) */
+    int64_t steps;         /* row steps (row mode) or requests run (pruned mode) */
+    int32_t row_points;    /* sieve points per resident row (row mode), else 0 */
+    int32_t lanes;         /* lanes of the resident row (row mode), else 0 */
+    double prune_ms;       /* building per-request subgraphs (pruned mode; summed over
+                              streams) */
+    double sieve_ms;       /* sieving: row steps, or per-request sieves (summed) */
+    double extract_ms;     /* witness extraction (summed) */
+    int64_t cancelled;     /* results with status TPM_ECANCELLED */
+    int64_t rejected;      /* submissions refused with TPM_ENOMEM, plus results with
+                              status TPM_ENOMEM */
+    int32_t streams;       /* pruned mode: worker streams */
+    int32_t inflight_peak; /* most requests running at once */
+    int64_t budget_bytes;  /* state budget */
+    int64_t held_bytes_peak; /* pruned mode: most device bytes held by the workers */
 } tpm_server_stats;
 tpm_status tpm_server_stats_get(tpm_server *s, tpm_server_stats *out);
 

@@ -147,6 +147,43 @@ WorkspaceLease::~WorkspaceLease() {
     pool->free_list.push_back(ws);
 }
 
+int64_t workspace_bytes(const Workspace *w) {
+    if (!w) return 0;
+    int64_t b = 0;
+    for (const DBuf *d : {&w->ctl, &w->z, &w->xt, &w->s0, &w->s1, &w->pub, &w->pp, &w->tot,
+                          &w->mask, &w->loc, &w->pick, &w->tabs, &w->aux, &w->aux2})
+        b += (int64_t)d->cap;
+    return b;
+}
+
+void workspace_trim(Workspace *w) {
+    if (!w || workspace_bytes(w) == 0) return;
+    TPM_HIP(hipDeviceSynchronize());
+    for (DBuf *d : {&w->ctl, &w->z, &w->xt, &w->s0, &w->s1, &w->pub, &w->pp, &w->tot, &w->mask,
+                    &w->loc, &w->pick, &w->tabs, &w->aux, &w->aux2}) {
+        if (d->p) (void)hipFree(d->p);
+        d->p = nullptr;
+        d->cap = 0;
+    }
+}
+
+Workspace *workspace_take(WorkspacePool *p) {
+    std::lock_guard<std::mutex> lk(p->mu);
+    if (!p->free_list.empty()) {
+        Workspace *w = p->free_list.back();
+        p->free_list.pop_back();
+        return w;
+    }
+    Workspace *w = new Workspace();
+    p->all.push_back(w);
+    return w;
+}
+
+void workspace_give(WorkspacePool *p, Workspace *w) {
+    std::lock_guard<std::mutex> lk(p->mu);
+    p->free_list.push_back(w);
+}
+
 WorkspacePool *new_workspace_pool() { return new WorkspacePool(); }
 void delete_workspace_pool(WorkspacePool *p) { delete p; }
 
@@ -164,7 +201,7 @@ bool verify_path(const Graph &G, const int32_t *M, int32_t k, const int32_t *ver
         if (verts[i] < 0 || verts[i] >= G.n) return false;
         const int32_t orig = G.h_fid.empty() ? verts[i] : G.h_fid[(size_t)verts[i]];
         if (!seen.insert(orig).second) return false;
-        have[G.h_color[verts[i]]]++;
+        have[G.h_color()[verts[i]]]++;
     }
     // colours = M, where a wildcard entry (-1) may be taken by any vertex
     for (int i = 0; i < k; ++i)
@@ -210,7 +247,7 @@ tpm_status extract_path(const Graph &G, const int32_t *M, int32_t k, uint64_t se
     auto orig = [&](int32_t u) { return G.h_fid.empty() ? u : G.h_fid[(size_t)u]; };
     if (k == 1) {
         for (int32_t u = 0; u < G.n; ++u)
-            if (G.h_color[u] == M[0] || M[0] == -1) {
+            if (G.h_color()[u] == M[0] || M[0] == -1) {
                 path_vertices[0] = orig(u);
                 return TPM_OK;
             }
@@ -254,7 +291,7 @@ tpm_status extract_path(const Graph &G, const int32_t *M, int32_t k, uint64_t se
         if (!G.h_fid.empty())
             for (int32_t i = 0; i < G.n; ++i)
                 if (G.h_fid[(size_t)i] == G.h_fid[(size_t)u]) mask[(size_t)i] = 0;
-        auto it = std::find(cur.begin(), cur.end(), G.h_color[u]);
+        auto it = std::find(cur.begin(), cur.end(), G.h_color()[u]);
         if (it == cur.end()) it = std::find(cur.begin(), cur.end(), -1);  // u took a wildcard
         if (it == cur.end()) return TPM_NOTFOUND;  // cannot happen for a certified edge
         cur.erase(it);
@@ -277,7 +314,7 @@ tpm_status extract_path(const Graph &G, const int32_t *M, int32_t k, uint64_t se
         if ((int)cur.size() >= 2 && hi <= lo) return TPM_NOTFOUND;
     }
     // cur has one colour left: it must be v's colour
-    if (cur.size() != 1 || (G.h_color[end_v] != cur[0] && cur[0] != -1)) return TPM_NOTFOUND;
+    if (cur.size() != 1 || (G.h_color()[end_v] != cur[0] && cur[0] != -1)) return TPM_NOTFOUND;
     std::reverse(rverts.begin(), rverts.end());
     std::reverse(rpos.begin(), rpos.end());
     std::reverse(reids.begin(), reids.end());
@@ -327,7 +364,7 @@ tpm_status extract_selfreduce(const Graph &G, const int32_t *M, int32_t k, uint6
     std::vector<uint8_t> mask((size_t)G.n, 0);
     std::vector<int32_t> cand;
     for (int32_t u = 0; u < G.n; ++u)
-        if (inc[(size_t)u] && (wild || in_m[(size_t)G.h_color[(size_t)u]])) {
+        if (inc[(size_t)u] && (wild || in_m[(size_t)G.h_color()[(size_t)u]])) {
             mask[(size_t)u] = 1;
             cand.push_back(u);
         }
@@ -556,7 +593,7 @@ tpm_status extract_from_vertices(const Graph &G, const int32_t *M, int32_t k, co
             const int32_t v = L.src[(size_t)i];
             const int32_t o = orig(v);
             if (std::find(used.begin(), used.end(), o) != used.end()) continue;
-            const int32_t c = G.h_color[(size_t)v];
+            const int32_t c = G.h_color()[(size_t)v];
             for (int alt = 0; alt < 2; ++alt) {
                 if (!take(c, alt)) continue;
                 rv.push_back(v);
@@ -577,7 +614,7 @@ tpm_status extract_from_vertices(const Graph &G, const int32_t *M, int32_t k, co
     };
     for (int32_t u = 0; u < G.n; ++u) {
         if (!q[(size_t)u]) continue;
-        const int32_t c = G.h_color[(size_t)u];
+        const int32_t c = G.h_color()[(size_t)u];
         for (int alt = 0; alt < 2; ++alt) {
             if (!take(c, alt)) continue;
             rv.assign(1, u);
@@ -630,7 +667,7 @@ tpm_status extract_vertexloc(const Graph &G, const int32_t *M, int32_t k, uint64
     return TPM_NOTFOUND;
 }
 
-static double now_ms_api() {
+double now_ms() {
     using namespace std::chrono;
     return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
 }
@@ -866,9 +903,9 @@ tpm_status tpm_autotune(tpm_graph *g, int32_t k, uint64_t seed, tpm_autotune_rep
                     req.max_chunks = 1;
                     SieveResult res;
                     run_sieve(G, req, res, nullptr);  // untimed: sizes the workspace
-                    const double t0 = now_ms_api();
+                    const double t0 = now_ms();
                     run_sieve(G, req, res, nullptr);
-                    const double ms = std::max(now_ms_api() - t0, 1e-6);
+                    const double ms = std::max(now_ms() - t0, 1e-6);
                     if (first.empty()) {
                         first.assign(res.per_point.begin(), res.per_point.begin() + cmp);
                     } else if (!std::equal(first.begin(), first.end(), res.per_point.begin())) {

@@ -370,6 +370,8 @@ __global__ void k_tile_fill(int32_t n, const int32_t *inptr, int32_t T, const in
     }
 }
 
+__global__ void k_set1(int32_t *p, int32_t v) { *p = v; }
+
 inline unsigned grid_for(int64_t work, int block = 256) {
     int64_t g = (work + block - 1) / block;
     return (unsigned)std::max<int64_t>(1, g);
@@ -407,6 +409,26 @@ struct GraphArena {
 GraphArena *new_graph_arena() { return new GraphArena(); }
 void delete_graph_arena(GraphArena *a) { delete a; }
 
+int64_t arena_bytes(const GraphArena *a) {
+    int64_t b = 0;
+    if (a)
+        for (const DBuf &d : a->s) b += (int64_t)d.cap;
+    return b;
+}
+
+void arena_trim(GraphArena *a) {
+    if (!a) return;
+    bool any = false;
+    for (DBuf &d : a->s) any |= d.p != nullptr;
+    if (!any) return;
+    TPM_HIP(hipDeviceSynchronize());
+    for (DBuf &d : a->s) {
+        if (d.p) (void)hipFree(d.p);
+        d.p = nullptr;
+        d.cap = 0;
+    }
+}
+
 struct ArenaPool {
     std::mutex mu;
     std::vector<GraphArena *> all, free_list;
@@ -415,6 +437,23 @@ struct ArenaPool {
     }
 };
 ArenaPool *new_arena_pool() { return new ArenaPool(); }
+
+GraphArena *arena_take(ArenaPool *p) {
+    std::lock_guard<std::mutex> lk(p->mu);
+    if (!p->free_list.empty()) {
+        GraphArena *a = p->free_list.back();
+        p->free_list.pop_back();
+        return a;
+    }
+    GraphArena *a = new GraphArena();
+    p->all.push_back(a);
+    return a;
+}
+
+void arena_give(ArenaPool *p, GraphArena *a) {
+    std::lock_guard<std::mutex> lk(p->mu);
+    p->free_list.push_back(a);
+}
 void delete_arena_pool(ArenaPool *p) { delete p; }
 
 void run_sieve_pruned(const Graph &G, const SieveRequest &req, SieveResult &res,
@@ -458,7 +497,8 @@ void run_sieve_pruned(const Graph &G, const SieveRequest &req, SieveResult &res,
     } b{G.apool, arena, Graph()};
     PruneSpec spec;
     spec.keep_color = keep.data();
-    prune_graph(G, spec, b.P, arena);
+    spec.need_times = false;
+    prune_graph(G, spec, b.P, arena, st);
     b.P.pool = G.pool;
     if (loc_by_edge) run_sieve_loc_all(b.P, req, res, loc_by_edge, st);
     else run_sieve(b.P, req, res, st);
@@ -470,10 +510,10 @@ namespace {
 // An array of the graph: its own allocation (freed with the graph), or the arena's
 // slot when the graph lives in an arena.
 template <class T>
-T *galloc(Graph &G, int slot, int64_t count, int64_t &acct) {
+T *galloc(Graph &G, int slot, int64_t count, int64_t &acct, hipStream_t st = nullptr) {
     if (G.arena) {
         DBuf &b = G.arena->s[slot];
-        b.alloc((size_t)std::max<int64_t>(1, count) * sizeof(T), nullptr);
+        b.alloc((size_t)std::max<int64_t>(1, count) * sizeof(T), st);
         acct += (int64_t)b.cap;
         return (T *)b.p;
     }
@@ -483,14 +523,15 @@ T *galloc(Graph &G, int slot, int64_t count, int64_t &acct) {
 // Temporaries of an index build: the arena's slots, or allocations freed at the end.
 struct Temps {
     GraphArena *arena = nullptr;
+    hipStream_t st = nullptr;
     std::vector<void *> own;
-    explicit Temps(GraphArena *a) : arena(a) {}
+    explicit Temps(GraphArena *a, hipStream_t s = nullptr) : arena(a), st(s) {}
     Temps(const Temps &) = delete;
     Temps &operator=(const Temps &) = delete;
     void *raw(int slot, size_t bytes) {
         bytes = std::max<size_t>(bytes, 16);
         if (arena) {
-            arena->s[slot].alloc(bytes, nullptr);
+            arena->s[slot].alloc(bytes, st);
             return arena->s[slot].p;
         }
         void *p = nullptr;
@@ -503,7 +544,7 @@ struct Temps {
         return (T *)raw(slot, (size_t)std::max<int64_t>(1, count) * sizeof(T));
     }
     ~Temps() {
-        if (!own.empty()) (void)hipDeviceSynchronize();
+        if (!own.empty()) (void)hipStreamSynchronize(st);
         for (void *p : own) (void)hipFree(p);
     }
 };
@@ -564,9 +605,8 @@ void build_tiles(const std::vector<int32_t> &inptr, int32_t T, std::vector<int32
 // then plain allocations the caller adopts).
 void build_tiles_device(Graph &G, int32_t T, Temps &tmp, int64_t &acct, int32_t **tp0,
                         int32_t **tpub, int32_t **tlb, int64_t &ntiles, int64_t &nslots,
-                        bool own, bool greedy) {
+                        bool own, bool greedy, hipStream_t st) {
     const int32_t n = G.n;
-    hipStream_t st = nullptr;
     int32_t *nz = tmp.get<int32_t>(A_TNZ, n);
     int32_t *pm = tmp.get<int32_t>(A_TPM, n);
     int32_t *tcnt = tmp.get<int32_t>(A_TCNT, n);
@@ -585,19 +625,22 @@ void build_tiles_device(Graph &G, int32_t T, Temps &tmp, int64_t &acct, int32_t 
     TPM_HIP(rocprim::exclusive_scan(scratch, b2, tcnt, tbase, 0, (size_t)n, rocprim::plus<int32_t>(), st));
     TPM_HIP(rocprim::exclusive_scan(scratch, b2, scnt, sbase, 0, (size_t)n, rocprim::plus<int32_t>(), st));
     int32_t h[4] = {0, 0, 0, 0};
-    TPM_HIP(hipMemcpy(&h[0], tbase + (n - 1), sizeof(int32_t), hipMemcpyDeviceToHost));
-    TPM_HIP(hipMemcpy(&h[1], tcnt + (n - 1), sizeof(int32_t), hipMemcpyDeviceToHost));
-    TPM_HIP(hipMemcpy(&h[2], sbase + (n - 1), sizeof(int32_t), hipMemcpyDeviceToHost));
-    TPM_HIP(hipMemcpy(&h[3], scnt + (n - 1), sizeof(int32_t), hipMemcpyDeviceToHost));
+    TPM_HIP(hipMemcpyAsync(&h[0], tbase + (n - 1), sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    TPM_HIP(hipMemcpyAsync(&h[1], tcnt + (n - 1), sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    TPM_HIP(hipMemcpyAsync(&h[2], sbase + (n - 1), sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    TPM_HIP(hipMemcpyAsync(&h[3], scnt + (n - 1), sizeof(int32_t), hipMemcpyDeviceToHost, st));
     unsigned long long hs[2] = {0, 0};
-    TPM_HIP(hipMemcpy(hs, stats, sizeof(hs), hipMemcpyDeviceToHost));
+    TPM_HIP(hipMemcpyAsync(hs, stats, sizeof(hs), hipMemcpyDeviceToHost, st));
+    TPM_HIP(hipStreamSynchronize(st));
     ntiles = (int64_t)h[0] + h[1];
     nslots = (int64_t)h[2] + h[3];
     G.max_in_degree = (int64_t)hs[0];
     G.segments = (int64_t)hs[1];
     if (greedy) {  // whole graph: greedy packing on the host instead
         std::vector<int32_t> hin((size_t)n + 1), p0, pub, lb;
-        TPM_HIP(hipMemcpy(hin.data(), G.inptr, sizeof(int32_t) * ((size_t)n + 1), hipMemcpyDeviceToHost));
+        TPM_HIP(hipMemcpyAsync(hin.data(), G.inptr, sizeof(int32_t) * ((size_t)n + 1),
+                               hipMemcpyDeviceToHost, st));
+        TPM_HIP(hipStreamSynchronize(st));
         build_tiles(hin, T, p0, pub, lb, nslots);
         ntiles = (int64_t)pub.size();
         if (own) {
@@ -605,15 +648,18 @@ void build_tiles_device(Graph &G, int32_t T, Temps &tmp, int64_t &acct, int32_t 
             *tpub = dalloc<int32_t>(ntiles, acct);
             *tlb = dalloc<int32_t>(ntiles, acct);
         } else {
-            *tp0 = galloc<int32_t>(G, A_TP0, ntiles + 1, acct);
-            *tpub = galloc<int32_t>(G, A_TPUB, ntiles, acct);
-            *tlb = galloc<int32_t>(G, A_TLB, ntiles, acct);
+            *tp0 = galloc<int32_t>(G, A_TP0, ntiles + 1, acct, st);
+            *tpub = galloc<int32_t>(G, A_TPUB, ntiles, acct, st);
+            *tlb = galloc<int32_t>(G, A_TLB, ntiles, acct, st);
         }
-        TPM_HIP(hipMemcpy(*tp0, p0.data(), sizeof(int32_t) * p0.size(), hipMemcpyHostToDevice));
+        TPM_HIP(hipMemcpyAsync(*tp0, p0.data(), sizeof(int32_t) * p0.size(), hipMemcpyHostToDevice, st));
         if (ntiles) {
-            TPM_HIP(hipMemcpy(*tpub, pub.data(), sizeof(int32_t) * pub.size(), hipMemcpyHostToDevice));
-            TPM_HIP(hipMemcpy(*tlb, lb.data(), sizeof(int32_t) * lb.size(), hipMemcpyHostToDevice));
+            TPM_HIP(hipMemcpyAsync(*tpub, pub.data(), sizeof(int32_t) * pub.size(),
+                                   hipMemcpyHostToDevice, st));
+            TPM_HIP(hipMemcpyAsync(*tlb, lb.data(), sizeof(int32_t) * lb.size(),
+                                   hipMemcpyHostToDevice, st));
         }
+        TPM_HIP(hipStreamSynchronize(st));  // the host vectors go out of scope
         G.h_tile_p0 = std::move(p0);
         return;
     }
@@ -622,16 +668,16 @@ void build_tiles_device(Graph &G, int32_t T, Temps &tmp, int64_t &acct, int32_t 
         *tpub = dalloc<int32_t>(ntiles, acct);
         *tlb = dalloc<int32_t>(ntiles, acct);
     } else {
-        *tp0 = galloc<int32_t>(G, A_TP0, ntiles + 1, acct);
-        *tpub = galloc<int32_t>(G, A_TPUB, ntiles, acct);
-        *tlb = galloc<int32_t>(G, A_TLB, ntiles, acct);
+        *tp0 = galloc<int32_t>(G, A_TP0, ntiles + 1, acct, st);
+        *tpub = galloc<int32_t>(G, A_TPUB, ntiles, acct, st);
+        *tlb = galloc<int32_t>(G, A_TLB, ntiles, acct, st);
     }
     k_tile_fill<<<grid_for(n), 256, 0, st>>>(n, G.inptr, T, tcnt, tbase, sbase, *tp0, *tpub, *tlb);
-    const int32_t mm = (int32_t)G.m;
-    TPM_HIP(hipMemcpy(*tp0 + ntiles, &mm, sizeof(int32_t), hipMemcpyHostToDevice));
+    k_set1<<<1, 1, 0, st>>>(*tp0 + ntiles, (int32_t)G.m);
     G.h_tile_p0.resize((size_t)ntiles + 1);
-    TPM_HIP(hipMemcpy(G.h_tile_p0.data(), *tp0, sizeof(int32_t) * ((size_t)ntiles + 1),
-                      hipMemcpyDeviceToHost));
+    TPM_HIP(hipMemcpyAsync(G.h_tile_p0.data(), *tp0, sizeof(int32_t) * ((size_t)ntiles + 1),
+                           hipMemcpyDeviceToHost, st));
+    TPM_HIP(hipStreamSynchronize(st));
 }
 
 // The bank-replicated LOG/EXP image (kLdsBytes), built once per process.
@@ -682,20 +728,65 @@ void build_pcol(Graph &G, int64_t &acct) {
     TPM_HIP(hipDeviceSynchronize());
 }
 
+// Edge counts by (source colour, head colour) from the colour pairs of the positions:
+// one LDS histogram per workgroup, merged with global atomics.
+__global__ void k_pair_hist(int64_t m, const uint16_t *pcol, int32_t q,
+                            unsigned long long *out) {
+    __shared__ unsigned int h[64 * 64];
+    const int nb = q * q;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) h[i] = 0;
+    __syncthreads();
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < m; p += stride) {
+        const uint32_t pc = pcol[p];
+        atomicAdd(&h[(pc & 0xFFu) * q + (pc >> 8)], 1u);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nb; i += blockDim.x)
+        if (h[i]) atomicAdd(&out[i], (unsigned long long)h[i]);
+}
+
+void colour_pair_counts(const Graph &G, std::vector<int64_t> &out, hipStream_t st) {
+    TPM_REQUIRE(G.q <= 64, "colour pair counts need at most 64 colours");
+    const int nb = G.q * G.q;
+    out.assign((size_t)nb, 0);
+    if (G.m == 0) return;
+    TPM_REQUIRE(G.pcol != nullptr, "colour pair counts need the colour pairs of a whole graph");
+    unsigned long long *d = nullptr;
+    TPM_HIP(hipMalloc(&d, sizeof(unsigned long long) * (size_t)nb));
+    std::vector<unsigned long long> h((size_t)nb, 0);
+    hipError_t e = hipMemcpyAsync(d, h.data(), sizeof(unsigned long long) * (size_t)nb,
+                                  hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) {
+        const unsigned grid = std::min<unsigned>(grid_for(G.m), 4 * std::max(1, G.num_cu));
+        k_pair_hist<<<grid, 256, 0, st>>>(G.m, G.pcol, G.q, d);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(h.data(), d, sizeof(unsigned long long) * (size_t)nb,
+                           hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(d);
+    TPM_HIP(e);
+    for (int i = 0; i < nb; ++i) out[(size_t)i] = (int64_t)h[(size_t)i];
+}
+
 // Everything of the index that follows from the CSR arrays (pdst, psrc, ptau, peid
 // sorted by (dst, tau, input id)), G.color and G.tmax: distinct timestamps, in-list
 // offsets, gathered and stored rows, host copies, tiles and the LDS image.  taus:
 // the m timestamps in any order (device).
 // gpos_pre (nullable, device [m]): read positions already known (pruned graphs)
+// lds_shared (nullable): an LDS image to use instead of a new one (subgraphs in an
+// arena use their parent's); need_times = false skips the distinct-timestamp table.
 void finish_index(Graph &G, int64_t &acct, const int32_t *taus, bool greedy_tiles,
-                  const int32_t *gpos_pre = nullptr) {
+                  const int32_t *gpos_pre = nullptr, hipStream_t st = nullptr,
+                  bool need_times = true, uint8_t *lds_shared = nullptr) {
     const int64_t m = G.m;
     const int32_t n = G.n;
     const int32_t tmax = G.tmax;
     const int32_t T = G.tile_edges;
-    hipStream_t st = nullptr;
-    Temps tmp(G.arena);
-    if (m) {
+    Temps tmp(G.arena, st);
+    if (m && need_times) {
         // ---- distinct timestamps, ascending (per-time splits of the sieve)
         const int tbits = bits_for((uint64_t)tmax);
         int32_t *tsort = tmp.get<int32_t>(A_TSORT, m);
@@ -712,13 +803,14 @@ void finish_index(Graph &G, int64_t &acct, const int32_t *taus, bool greedy_tile
         TPM_HIP(rocprim::unique(scratch, ubytes, tsort, tuniq, tcount, (size_t)m,
                                 rocprim::equal_to<int32_t>(), st));
         int64_t nt = 0;
-        TPM_HIP(hipMemcpy(&nt, tcount, sizeof(nt), hipMemcpyDeviceToHost));
+        TPM_HIP(hipMemcpyAsync(&nt, tcount, sizeof(nt), hipMemcpyDeviceToHost, st));
+        TPM_HIP(hipStreamSynchronize(st));
         G.ntimes = nt;
-        G.ttab = galloc<int32_t>(G, A_TTAB, nt, acct);
-        TPM_HIP(hipMemcpy(G.ttab, tuniq, sizeof(int32_t) * (size_t)nt, hipMemcpyDeviceToDevice));
+        G.ttab = galloc<int32_t>(G, A_TTAB, nt, acct, st);
+        TPM_HIP(hipMemcpyAsync(G.ttab, tuniq, sizeof(int32_t) * (size_t)nt, hipMemcpyDeviceToDevice, st));
         G.h_ttab.resize((size_t)nt);
-        TPM_HIP(hipMemcpy(G.h_ttab.data(), tuniq, sizeof(int32_t) * (size_t)nt,
-                          hipMemcpyDeviceToHost));
+        TPM_HIP(hipMemcpyAsync(G.h_ttab.data(), tuniq, sizeof(int32_t) * (size_t)nt,
+                               hipMemcpyDeviceToHost, st));
     }
     k_inptr<<<grid_for(m + 1), 256, 0, st>>>(m, n, G.pdst, G.inptr);
     if (m) {
@@ -742,34 +834,41 @@ void finish_index(Graph &G, int64_t &acct, const int32_t *taus, bool greedy_tile
                                         rocprim::plus<int32_t>(), st));
         k_rows<<<grid_for(m), 256, 0, st>>>(m, gpos, needed, rowof, G.orow, G.gsrc);
         int32_t last_row = 0, last_needed = 0;
-        TPM_HIP(hipMemcpy(&last_row, rowof + (m - 1), sizeof(int32_t), hipMemcpyDeviceToHost));
-        TPM_HIP(hipMemcpy(&last_needed, needed + (m - 1), sizeof(int32_t), hipMemcpyDeviceToHost));
-        G.R = (int64_t)last_row + last_needed;
         unsigned long long *cnt = tmp.get<unsigned long long>(A_CNT, 1);
         TPM_HIP(hipMemsetAsync(cnt, 0, sizeof(unsigned long long), st));
         k_count_nonneg<<<std::min<unsigned>(grid_for(m), 4096), 256, 0, st>>>(m, G.gsrc, cnt);
         unsigned long long h = 0;
-        TPM_HIP(hipMemcpy(&h, cnt, sizeof(h), hipMemcpyDeviceToHost));
+        TPM_HIP(hipMemcpyAsync(&last_row, rowof + (m - 1), sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        TPM_HIP(hipMemcpyAsync(&last_needed, needed + (m - 1), sizeof(int32_t),
+                               hipMemcpyDeviceToHost, st));
+        TPM_HIP(hipMemcpyAsync(&h, cnt, sizeof(h), hipMemcpyDeviceToHost, st));
+        TPM_HIP(hipStreamSynchronize(st));
+        G.R = (int64_t)last_row + last_needed;
         G.gathers = (int64_t)h;
         if (!G.arena) {  // whole graphs keep the read positions for pruning
-            G.gposw = galloc<int32_t>(G, A_GPOSW, m, acct);
+            G.gposw = galloc<int32_t>(G, A_GPOSW, m, acct, st);
             TPM_HIP(hipMemcpyAsync(G.gposw, gpos, sizeof(int32_t) * (size_t)m,
                                    hipMemcpyDeviceToDevice, st));
         }
     }
-    if (G.h_color.size() != (size_t)n) {
-        G.h_color.resize((size_t)n);
-        TPM_HIP(hipMemcpy(G.h_color.data(), G.color, sizeof(int32_t) * (size_t)n,
-                          hipMemcpyDeviceToHost));
+    if (!G.h_color_sp || G.h_color().size() != (size_t)n) {
+        G.h_color_mut().resize((size_t)n);
+        TPM_HIP(hipMemcpyAsync(G.h_color_mut().data(), G.color, sizeof(int32_t) * (size_t)n,
+                               hipMemcpyDeviceToHost, st));
     }
     // window grouping makes tiles of up to two windows: windows of T / 2 keep them
     // within T positions, as the greedy packing does
     build_tiles_device(G, greedy_tiles ? T : std::max<int32_t>(1, T / 2), tmp, acct, &G.tile_p0,
-                       &G.tile_pub, &G.tile_lb, G.ntiles, G.nslots, false, greedy_tiles);
+                       &G.tile_pub, &G.tile_lb, G.ntiles, G.nslots, false, greedy_tiles, st);
 
-    G.lds_image = galloc<uint8_t>(G, A_LDS, kLdsBytes, acct);
-    TPM_HIP(hipMemcpy(G.lds_image, lds_image_host().data(), kLdsBytes, hipMemcpyHostToDevice));
-    TPM_HIP(hipDeviceSynchronize());
+    if (lds_shared) {
+        G.lds_image = lds_shared;  // the parent's (never freed through an arena graph)
+    } else {
+        G.lds_image = galloc<uint8_t>(G, A_LDS, kLdsBytes, acct, st);
+        TPM_HIP(hipMemcpyAsync(G.lds_image, lds_image_host().data(), kLdsBytes,
+                               hipMemcpyHostToDevice, st));
+    }
+    TPM_HIP(hipStreamSynchronize(st));
     build_pcol(G, acct);
 }
 
@@ -947,7 +1046,8 @@ void build_graph(Graph &G, int32_t n, int64_t m, const int32_t *src, const int32
     cleanup_tmp();
 }
 
-void prune_graph(const Graph &P, const PruneSpec &spec, Graph &G, GraphArena *arena) {
+void prune_graph(const Graph &P, const PruneSpec &spec, Graph &G, GraphArena *arena,
+                 hipStream_t st) {
     const uint8_t *keep_color = spec.keep_color, *vkeep_in = spec.vkeep;
     const int32_t *times = spec.times;
     const int32_t ntimes = spec.ntimes;
@@ -960,26 +1060,25 @@ void prune_graph(const Graph &P, const PruneSpec &spec, Graph &G, GraphArena *ar
     G.tile_edges = P.tile_edges;
     G.edge_ids = P.edge_ids;
     G.arena = arena;
-    G.h_color = P.h_color;
+    G.h_color_sp = P.h_color_sp;  // shared: colours are P's
     G.h_delay = P.h_delay;
     G.h_fid = P.h_fid;
     int64_t acct = 0;
-    hipStream_t st = nullptr;
     try {
         int64_t mk = 0;
         uint8_t *keep = nullptr;
         int32_t *at = nullptr;
-        Temps outer(arena);
+        Temps outer(arena, st);
         int32_t *gpos_pre = nullptr;  // read positions mapped from the parent's
         {
-            Temps tmp(arena);
-            G.color = galloc<int32_t>(G, A_COLOR, P.n, acct);
+            Temps tmp(arena, st);
+            G.color = galloc<int32_t>(G, A_COLOR, P.n, acct, st);
             TPM_HIP(hipMemcpyAsync(G.color, P.color, sizeof(int32_t) * (size_t)P.n,
                                    hipMemcpyDeviceToDevice, st));
             if (P.m) {
                 uint8_t *keepc = tmp.get<uint8_t>(A_KEEPC, P.q);
                 if (keep_color) {
-                    TPM_HIP(hipMemcpy(keepc, keep_color, (size_t)P.q, hipMemcpyHostToDevice));
+                    TPM_HIP(hipMemcpyAsync(keepc, keep_color, (size_t)P.q, hipMemcpyHostToDevice, st));
                 } else {
                     TPM_HIP(hipMemsetAsync(keepc, 1, (size_t)P.q, st));
                 }
@@ -992,7 +1091,8 @@ void prune_graph(const Graph &P, const PruneSpec &spec, Graph &G, GraphArena *ar
                 int32_t *ts = nullptr;
                 if (times) {
                     ts = tmp.get<int32_t>(A_TSET, ntimes);
-                    TPM_HIP(hipMemcpy(ts, times, sizeof(int32_t) * (size_t)ntimes, hipMemcpyHostToDevice));
+                    TPM_HIP(hipMemcpyAsync(ts, times, sizeof(int32_t) * (size_t)ntimes,
+                                           hipMemcpyHostToDevice, st));
                 }
                 keep = tmp.get<uint8_t>(A_KEEP, P.m);
                 at = tmp.get<int32_t>(A_AT, P.m);
@@ -1019,28 +1119,29 @@ void prune_graph(const Graph &P, const PruneSpec &spec, Graph &G, GraphArena *ar
                                                 rocprim::plus<int32_t>(), st));
                 int32_t last_at = 0;
                 uint8_t last_keep = 0;
-                TPM_HIP(hipMemcpy(&last_at, at + (P.m - 1), sizeof(int32_t), hipMemcpyDeviceToHost));
-                TPM_HIP(hipMemcpy(&last_keep, keep + (P.m - 1), 1, hipMemcpyDeviceToHost));
+                TPM_HIP(hipMemcpyAsync(&last_at, at + (P.m - 1), sizeof(int32_t), hipMemcpyDeviceToHost, st));
+                TPM_HIP(hipMemcpyAsync(&last_keep, keep + (P.m - 1), 1, hipMemcpyDeviceToHost, st));
+                TPM_HIP(hipStreamSynchronize(st));
                 mk = (int64_t)last_at + last_keep;
             }
             G.m = mk;
             G.tile_auto = P.tile_auto;
             if (P.tile_auto) G.tile_edges = auto_tile_edges(mk);
-            G.pdst = galloc<int32_t>(G, A_PDST, mk, acct);
-            G.psrc = galloc<int32_t>(G, A_PSRC, mk, acct);
-            G.ptau = galloc<int32_t>(G, A_PTAU, mk, acct);
-            G.peid = galloc<int32_t>(G, A_PEID, mk, acct);
-            G.gsrc = galloc<int32_t>(G, A_GSRC, mk, acct);
-            G.orow = galloc<int32_t>(G, A_OROW, mk, acct);
-            G.inptr = galloc<int32_t>(G, A_INPTR, (int64_t)G.n + 1, acct);
-            if (P.pdep) G.pdep = galloc<int32_t>(G, A_PDEP, mk, acct);
+            G.pdst = galloc<int32_t>(G, A_PDST, mk, acct, st);
+            G.psrc = galloc<int32_t>(G, A_PSRC, mk, acct, st);
+            G.ptau = galloc<int32_t>(G, A_PTAU, mk, acct, st);
+            G.peid = galloc<int32_t>(G, A_PEID, mk, acct, st);
+            G.gsrc = galloc<int32_t>(G, A_GSRC, mk, acct, st);
+            G.orow = galloc<int32_t>(G, A_OROW, mk, acct, st);
+            G.inptr = galloc<int32_t>(G, A_INPTR, (int64_t)G.n + 1, acct, st);
+            if (P.pdep) G.pdep = galloc<int32_t>(G, A_PDEP, mk, acct, st);
             if (P.fid) {
-                G.fid = galloc<int32_t>(G, A_FID, P.n, acct);
+                G.fid = galloc<int32_t>(G, A_FID, P.n, acct, st);
                 TPM_HIP(hipMemcpyAsync(G.fid, P.fid, sizeof(int32_t) * (size_t)P.n,
                                        hipMemcpyDeviceToDevice, st));
             }
             if (P.vdelay) {
-                G.vdelay = galloc<int32_t>(G, A_VDELAY, P.n, acct);
+                G.vdelay = galloc<int32_t>(G, A_VDELAY, P.n, acct, st);
                 TPM_HIP(hipMemcpyAsync(G.vdelay, P.vdelay, sizeof(int32_t) * (size_t)P.n,
                                        hipMemcpyDeviceToDevice, st));
             }
@@ -1056,9 +1157,10 @@ void prune_graph(const Graph &P, const PruneSpec &spec, Graph &G, GraphArena *ar
                 if (P.pdep)
                     k_compact1<<<grid_for(P.m), 256, 0, st>>>(P.m, keep, at, P.pdep, G.pdep);
             }
-            TPM_HIP(hipDeviceSynchronize());
+            TPM_HIP(hipStreamSynchronize(st));
         }
-        finish_index(G, acct, G.ptau, arena == nullptr, gpos_pre);
+        finish_index(G, acct, G.ptau, arena == nullptr, gpos_pre, st, spec.need_times,
+                     arena ? P.lds_image : nullptr);
         G.device_bytes = acct;
     } catch (...) {
         free_graph(G);
@@ -1079,8 +1181,10 @@ void sd_graph(const Graph &P, int32_t s, int32_t d, Graph &G) {
         const int32_t cs = P.q, cd = P.q + 1;
         TPM_HIP(hipMemcpy(G.color + s, &cs, sizeof(int32_t), hipMemcpyHostToDevice));
         TPM_HIP(hipMemcpy(G.color + d, &cd, sizeof(int32_t), hipMemcpyHostToDevice));
-        G.h_color[(size_t)s] = cs;
-        G.h_color[(size_t)d] = cd;
+        // own copy: s and d change colour
+        G.h_color_sp = std::make_shared<std::vector<int32_t>>(P.h_color());
+        G.h_color_mut()[(size_t)s] = cs;
+        G.h_color_mut()[(size_t)d] = cd;
         int64_t acct = 0;
         if (G.q > 64 && G.pcol) {
             (void)hipFree(G.pcol);
@@ -1101,7 +1205,7 @@ void layer_graph(const Graph &P, const int32_t *tuple, int32_t k, Graph &G) {
     // ---- vertices: layer l holds the vertices of colour tuple[l-1], in id order
     std::vector<int64_t> cnt((size_t)P.q, 0);
     std::vector<int32_t> rank((size_t)P.n);
-    for (int32_t u = 0; u < P.n; ++u) rank[(size_t)u] = (int32_t)cnt[(size_t)P.h_color[(size_t)u]]++;
+    for (int32_t u = 0; u < P.n; ++u) rank[(size_t)u] = (int32_t)cnt[(size_t)P.h_color()[(size_t)u]]++;
     std::vector<int64_t> base((size_t)k + 1, 0);
     for (int l = 0; l < k; ++l) base[(size_t)l + 1] = base[(size_t)l] + cnt[(size_t)tuple[l]];
     int64_t nn = base[(size_t)k];
@@ -1118,19 +1222,19 @@ void layer_graph(const Graph &P, const int32_t *tuple, int32_t k, Graph &G) {
         // no vertex has a colour of the tuple: one vertex of another colour, no edges
         int32_t other = 0;
         while (in_tuple[(size_t)other]) ++other;
-        G.h_color.assign(1, other);
+        G.h_color_mut().assign(1, other);
         G.h_fid.assign(1, 0);
         if (!P.h_delay.empty()) G.h_delay.assign(1, 1);
         nn = 1;
     } else {
-        G.h_color.resize((size_t)nn);
+        G.h_color_mut().resize((size_t)nn);
         G.h_fid.resize((size_t)nn);
         if (!P.h_delay.empty()) G.h_delay.resize((size_t)nn);
         for (int l = 0; l < k; ++l)
             for (int32_t u = 0; u < P.n; ++u)
-                if (P.h_color[(size_t)u] == tuple[l]) {
+                if (P.h_color()[(size_t)u] == tuple[l]) {
                     const size_t i = (size_t)(base[(size_t)l] + rank[(size_t)u]);
-                    G.h_color[i] = tuple[l];
+                    G.h_color_mut()[i] = tuple[l];
                     G.h_fid[i] = P.h_fid.empty() ? u : P.h_fid[(size_t)u];
                     if (!P.h_delay.empty()) G.h_delay[i] = P.h_delay[(size_t)u];
                 }
@@ -1147,7 +1251,7 @@ void layer_graph(const Graph &P, const int32_t *tuple, int32_t k, Graph &G) {
     try {
         G.color = dalloc<int32_t>(G.n, acct);
         G.fid = dalloc<int32_t>(G.n, acct);
-        TPM_HIP(hipMemcpy(G.color, G.h_color.data(), sizeof(int32_t) * (size_t)G.n, hipMemcpyHostToDevice));
+        TPM_HIP(hipMemcpy(G.color, G.h_color().data(), sizeof(int32_t) * (size_t)G.n, hipMemcpyHostToDevice));
         TPM_HIP(hipMemcpy(G.fid, G.h_fid.data(), sizeof(int32_t) * (size_t)G.n, hipMemcpyHostToDevice));
         if (!G.h_delay.empty()) {
             G.vdelay = dalloc<int32_t>(G.n, acct);
@@ -1230,7 +1334,7 @@ void retile_graph(Graph &G, int32_t T) {
     std::vector<int32_t> old_h = G.h_tile_p0;
     try {
         Temps tmp(nullptr);
-        build_tiles_device(G, T, tmp, acct, &p0, &pb, &lb, nt, nslots, true, true);
+        build_tiles_device(G, T, tmp, acct, &p0, &pb, &lb, nt, nslots, true, true, nullptr);
     } catch (...) {
         for (void *q : {(void *)p0, (void *)pb, (void *)lb})
             if (q) (void)hipFree(q);

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
+#include <memory>
 #include <new>
 #include <stdexcept>
 #include <string>
@@ -148,6 +150,16 @@ struct ArenaPool;
 ArenaPool *new_arena_pool();
 void delete_arena_pool(ArenaPool *p);
 
+// Device bytes held by a workspace, and release of all of them (waits for the device).
+int64_t workspace_bytes(const Workspace *w);
+void workspace_trim(Workspace *w);
+
+// Long leases (a worker's lifetime) of a pool's workspace / arena; returned for reuse.
+Workspace *workspace_take(WorkspacePool *p);
+void workspace_give(WorkspacePool *p, Workspace *w);
+GraphArena *arena_take(ArenaPool *p);
+void arena_give(ArenaPool *p, GraphArena *a);
+
 struct WorkspaceLease {
     explicit WorkspaceLease(const Graph &G);
     ~WorkspaceLease();
@@ -208,11 +220,18 @@ struct Graph {
     GraphArena *arena = nullptr;    // not owned: device arrays live there when set
 
     // host copies
-    std::vector<int32_t> h_color;   // [n]
+    // [n] vertex colours; shared (not copied) by the per-query subgraphs of a graph
+    std::shared_ptr<std::vector<int32_t>> h_color_sp;
     std::vector<int32_t> h_tile_p0; // [ntiles+1]
     std::vector<int32_t> h_ttab;    // [ntimes]
     std::vector<int32_t> h_delay;   // [n] when vdelay is set
     std::vector<int32_t> h_fid;     // [n] when fid is set
+
+    const std::vector<int32_t> &h_color() const { return *h_color_sp; }
+    std::vector<int32_t> &h_color_mut() {
+        if (!h_color_sp) h_color_sp = std::make_shared<std::vector<int32_t>>();
+        return *h_color_sp;
+    }
 };
 
 // Builds all of the above; throws Error.
@@ -240,11 +259,24 @@ struct PruneSpec {
     int32_t cut_in = -1, cut_out = -1;    // a vertex whose in- / out-edges go (-1: none)
     const uint8_t *vkeep = nullptr;       // device [P.n]; nullable: every vertex
     int32_t tcut = 0x7FFFFFFF;            // keep edges that arrive by tcut
+    bool need_times = true;               // build the distinct-timestamp table (time
+                                          // buckets, optimum time); off for subgraphs
+                                          // that only run sieves and extraction
 };
 // With an arena, G's arrays and the build's temporaries live in the arena's grow-only
-// buffers (reused by the next graph built there; G must be freed before that).
+// buffers (reused by the next graph built there; G must be freed before that, and must
+// not outlive P: it shares P's host colours and LDS image).  All device work runs on
+// `st` and the call waits only for that stream, so prunes on other streams overlap.
 // Vertex ids, colours, timestamps and input edge ids are P's.
-void prune_graph(const Graph &P, const PruneSpec &spec, Graph &G, GraphArena *arena = nullptr);
+void prune_graph(const Graph &P, const PruneSpec &spec, Graph &G, GraphArena *arena = nullptr,
+                 hipStream_t st = nullptr);
+// Device bytes held by an arena's buffers.
+int64_t arena_bytes(const GraphArena *a);
+// Releases every buffer of an arena (waits for the device).
+void arena_trim(GraphArena *a);
+// Edge counts by colour pair: out[a * q + b] = edges from a vertex of colour a to one of
+// colour b (q = G.q <= 64; whole graphs only).  Synchronous on st.
+void colour_pair_counts(const Graph &G, std::vector<int64_t> &out, hipStream_t st);
 // (s,d)-COLORFUL-PATH: G = P with colour q on s and q + 1 on d (q + 2 colours), s's
 // in-edges and d's out-edges removed.
 void sd_graph(const Graph &P, int32_t s, int32_t d, Graph &G);
@@ -270,7 +302,18 @@ struct SieveRequest {
     bool want_pick = false;
     // run only the first chunk of sieve points (timing probes); 0 = all chunks
     int32_t max_chunks = 0;
+    // nullable: checked before every level launch; when it is nonzero, or the host
+    // clock (now_ms) has passed deadline_ms, the call stops launching, waits for the
+    // stream and throws TPM_ECANCELLED
+    const std::atomic<int> *cancel = nullptr;
+    double deadline_ms = 0;  // 0 = none
+    // nullable: run in this workspace (owned by the caller, used on one stream at a
+    // time) instead of one leased from the graph's pool
+    Workspace *ws = nullptr;
 };
+
+// Host clock in ms (steady clock), shared by the serving deadlines and timestamps.
+double now_ms();
 
 struct SieveResult {
     std::vector<uint8_t> per_point;  // 2^k
@@ -311,8 +354,10 @@ void run_sieve_sink(const Graph &G, const SieveRequest &req, SieveResult &res, L
 // Optimum timestamp (smallest t whose time-restricted sieve is nonzero, minimised over
 // reps seeds seed + r * 0x9E3779B97F4A7C15); -1 if no seed finds a path.
 int32_t optimum_time(const Graph &G, const int32_t *M, int32_t k, uint64_t seed, int32_t reps);
-// Returns the sieve total (the XOR of the q[u]).
-uint8_t vertex_localise(const Graph &G, const SieveRequest &req, uint8_t *q, hipStream_t st);
+// Returns the sieve total (the XOR of the q[u]); per_point (nullable) receives the
+// 2^k per-point values of the same sieve.
+uint8_t vertex_localise(const Graph &G, const SieveRequest &req, uint8_t *q, hipStream_t st,
+                        std::vector<uint8_t> *per_point = nullptr);
 // Extraction by vertex localisation (section "Extracting a solution", second
 // approach): reverse temporal DFS from the vertices u with q[u] != 0 (q: host, G.n
 // bytes, from vertex_localise), at most `budget` edge visits.  TPM_OK / TPM_NOTFOUND.
@@ -410,6 +455,19 @@ struct StepGraph {
 void multi_steps_graph(const Graph &G, MultiRow &row, int nsteps, StepGraph &sg, hipStream_t st);
 // Copies the accumulators of lanes [lane0, lane0 + nl) (4 W bytes per lane) to host.
 void multi_read(const Graph &G, MultiRow &row, int lane0, int nl, uint8_t *out, hipStream_t st);
+
+// ------------------------------------------------------------------ batch and serving
+// Extraction on a hit (batch and serving): vertex localisation + reverse temporal DFS
+// (q_loc: the query's own vertex localisation when its sieve computed it), else the
+// localisation-guided self-reduction; fills r.path_status and the path.
+void extract_into(const Graph &G, const tpm_query &q, tpm_result &r, hipStream_t st,
+                  const uint8_t *q_loc = nullptr);
+// The continuous-batching engines behind tpm_batch_run: `pruned` runs each query alone
+// on the subgraph of its colours, up to `streams` at once; otherwise queries share
+// resident multi-query rows of row_points points (use_graph: steps replayed from HIP
+// graphs).  Results (and per-point outputs) as tpm_batch_run.
+void batch_through_server(const tpm_graph *g, int32_t nq, const tpm_query *q, tpm_result *out,
+                          bool pruned, int streams, int row_points, bool use_graph);
 
 // ------------------------------------------------------------------ profiling
 bool profile_on();

@@ -178,16 +178,18 @@ int32_t optimum_time(const Graph &G, const int32_t *M, int32_t k, uint64_t seed,
     return best;
 }
 
-uint8_t vertex_localise(const Graph &G, const SieveRequest &req, uint8_t *q, hipStream_t st) {
+uint8_t vertex_localise(const Graph &G, const SieveRequest &req, uint8_t *q, hipStream_t st,
+                        std::vector<uint8_t> *per_point) {
     SieveResult res;
     if (G.m == 0) {
         std::memset(q, 0, (size_t)G.n);
         run_sieve(G, req, res, st);  // argument checks; the total of k = 1
-        return res.total;
+    } else {
+        VertexSink sink;
+        sink.out = q;
+        run_sieve_sink(G, req, res, sink, st);
     }
-    VertexSink sink;
-    sink.out = q;
-    run_sieve_sink(G, req, res, sink, st);
+    if (per_point) per_point->swap(res.per_point);
     return res.total;
 }
 

@@ -1720,6 +1720,17 @@ int pick_chunk(const Graph &G, int32_t k, int32_t requested) {
 
 }  // namespace
 
+// A cancelled (or expired) request stops between launches: the work already queued
+// on the stream completes before the error leaves, so no kernel outlives its buffers.
+void check_cancel(const SieveRequest &req, hipStream_t st) {
+    const bool c = req.cancel && req.cancel->load(std::memory_order_relaxed) != 0;
+    const bool late = req.deadline_ms > 0 && now_ms() > req.deadline_ms;
+    if (c || late) {
+        (void)hipStreamSynchronize(st);
+        throw Error{TPM_ECANCELLED, c ? "request cancelled" : "request deadline passed"};
+    }
+}
+
 // Positions [lo, hi) of the last level contribute (all when fin_lo >= fin_hi).  With
 // want_loc, the per-position localisation over that range is computed on the device;
 // loc_host (nullable, hi - lo bytes) receives it, and res.pick_eid / res.pick_pos get
@@ -1737,8 +1748,9 @@ void run_sieve_impl(const Graph &G, const SieveRequest &req, SieveResult &res, b
     const int rowd = rowb / 4;
     const int64_t ppbytes = std::max<int64_t>(npts, rowb);
 
-    WorkspaceLease lease(G);
-    Workspace &ws = *lease.ws;
+    std::unique_ptr<WorkspaceLease> lease;
+    if (!req.ws) lease.reset(new WorkspaceLease(G));
+    Workspace &ws = req.ws ? *req.ws : *lease->ws;
     DBuf &ctl = ws.ctl, &z = ws.z, &xt = ws.xt, &s0 = ws.s0, &s1 = ws.s1, &pub = ws.pub,
          &pp = ws.pp, &tot = ws.tot, &mask = ws.mask, &loc = ws.loc, &pick = ws.pick;
     ctl.alloc(sizeof(Ctl), st);
@@ -1794,6 +1806,7 @@ void run_sieve_impl(const Graph &G, const SieveRequest &req, SieveResult &res, b
             k_xt<<<grid_for((int64_t)G.n * ((rowb + 15) / 16)), 256, 0, st>>>(
                 G.n, k, rowb, rowb, 0, (uint32_t)base, z.as<uint8_t>(), xt.as<uint8_t>());
             for (int l = 2; l <= k; ++l) {
+                check_cancel(req, st);
                 const bool fin = (l == k);
                 LevelParams P{};
                 P.gidx = (l == 2) ? G.psrc : G.gsrc;

@@ -59,7 +59,8 @@ class tpm_kernel_time(ctypes.Structure):
 
 
 class tpm_tuning(ctypes.Structure):
-    _fields_ = [("chunk", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("prune", ctypes.c_int32)]
+    _fields_ = [("chunk", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("prune", ctypes.c_int32),
+                ("streams", ctypes.c_int32)]
 
 
 class tpm_autotune_report(ctypes.Structure):
@@ -72,16 +73,19 @@ class tpm_server_stats(ctypes.Structure):
     _fields_ = [("completed", ctypes.c_int64), ("steps", ctypes.c_int64),
                 ("row_points", ctypes.c_int32), ("lanes", ctypes.c_int32),
                 ("prune_ms", ctypes.c_double), ("sieve_ms", ctypes.c_double),
-                ("extract_ms", ctypes.c_double)]
+                ("extract_ms", ctypes.c_double), ("cancelled", ctypes.c_int64),
+                ("rejected", ctypes.c_int64), ("streams", ctypes.c_int32),
+                ("inflight_peak", ctypes.c_int32), ("budget_bytes", ctypes.c_int64),
+                ("held_bytes_peak", ctypes.c_int64)]
 
 
 class tpm_query(ctypes.Structure):
     _fields_ = [("multiset", _i32p), ("k", ctypes.c_int32), ("seed", ctypes.c_uint64),
-                ("want_path", ctypes.c_int32)]
+                ("want_path", ctypes.c_int32), ("per_point", _u8p), ("deadline_ms", ctypes.c_double)]
 
 
 class tpm_result(ctypes.Structure):
-    _fields_ = [("found", ctypes.c_int32), ("total", ctypes.c_uint8),
+    _fields_ = [("status", ctypes.c_int32), ("found", ctypes.c_int32), ("total", ctypes.c_uint8),
                 ("path_status", ctypes.c_int32), ("path_vertices", ctypes.c_int32 * 16),
                 ("path_edges", ctypes.c_int64 * 15), ("ticket", ctypes.c_uint64),
                 ("t_submit_ms", ctypes.c_double), ("t_start_ms", ctypes.c_double),
@@ -90,7 +94,8 @@ class tpm_result(ctypes.Structure):
 
 class tpm_server_config(ctypes.Structure):
     _fields_ = [("state_bytes", ctypes.c_int64), ("max_lanes", ctypes.c_int32),
-                ("extract_paths", ctypes.c_int32), ("prune_queries", ctypes.c_int32)]
+                ("extract_paths", ctypes.c_int32), ("prune_queries", ctypes.c_int32),
+                ("streams", ctypes.c_int32)]
 
 
 def _sig(name, res, args):
@@ -144,6 +149,7 @@ _sig("tpm_server_create", ctypes.c_int32, [_vp, ctypes.POINTER(tpm_server_config
                                           ctypes.POINTER(_vp)])
 _sig("tpm_server_submit", ctypes.c_int32, [_vp, ctypes.POINTER(tpm_query), _u64p])
 _sig("tpm_server_poll", ctypes.c_int32, [_vp, ctypes.POINTER(tpm_result), ctypes.c_int32, _i32p])
+_sig("tpm_server_cancel", ctypes.c_int32, [_vp, ctypes.c_uint64])
 _sig("tpm_server_destroy", None, [_vp])
 _sig("tpm_server_stats_get", ctypes.c_int32, [_vp, ctypes.POINTER(tpm_server_stats)])
 _sig("tpm_profile_enable", ctypes.c_int32, [ctypes.c_int32])
@@ -158,7 +164,8 @@ EXPORTED = ["tpm_graph_create", "tpm_graph_create_ex", "tpm_graph_destroy", "tpm
             "tpm_sieve", "tpm_sieve_ex", "tpm_decide", "tpm_extract", "tpm_extract_ex",
             "tpm_extract_optimum",
             "tpm_batch_run",
-            "tpm_server_create", "tpm_server_submit", "tpm_server_poll", "tpm_server_destroy",
+            "tpm_server_create", "tpm_server_submit", "tpm_server_poll", "tpm_server_cancel",
+            "tpm_server_destroy",
             "tpm_server_stats_get", "tpm_rainbow_decide",
             "tpm_profile_enable", "tpm_profile_read", "tpm_last_error", "tpm_version"]
 
@@ -240,6 +247,17 @@ def tpm_graph_stats_get(h) -> dict:
     return {f: getattr(st, f) for f, _ in tpm_graph_stats._fields_}
 
 
+def _mask(h, mask):
+    """The vertex mask as n bytes (the library reads exactly n of them)."""
+    if mask is None:
+        return None
+    mk = np.ascontiguousarray(mask, dtype=np.uint8)
+    n = tpm_graph_stats_get(h)["n"]
+    if mk.ndim != 1 or mk.shape[0] != n:
+        raise ValueError(f"vertex mask needs {n} entries, got {mk.shape}")
+    return mk
+
+
 def tpm_sieve(h, multiset, seed, mask=None, chunk=0, loc_m=None, stream=None, prune=False):
     """Returns (per_point uint8[2^k], total int) or, with loc_m = number of edges,
     (per_point, total, loc uint8[m])."""
@@ -247,9 +265,9 @@ def tpm_sieve(h, multiset, seed, mask=None, chunk=0, loc_m=None, stream=None, pr
     k = int(M.shape[0])
     pp = np.zeros(1 << k, dtype=np.uint8)
     tot = np.zeros(1, dtype=np.uint8)
-    mk = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8)
+    mk = _mask(h, mask)
     loc = None if loc_m is None else np.zeros(max(1, int(loc_m)), dtype=np.uint8)
-    tune = tpm_tuning(int(chunk), 0, 1 if prune else 0)
+    tune = tpm_tuning(int(chunk), 0, 1 if prune else 0, 0)
     _check(_lib.tpm_sieve_ex(h, M.ctypes.data_as(_i32p), k, int(seed) & (2**64 - 1),
                              _ptr(mk, _u8p), ctypes.byref(tune), pp.ctypes.data_as(_u8p),
                              tot.ctypes.data_as(_u8p), _ptr(loc, _u8p), _stream_handle(stream)))
@@ -308,8 +326,10 @@ def tpm_extract_ex(h, multiset, seed, max_reps=8, method=0):
     return rc, pv, pe[: k - 1], int(ns.value)
 
 
-def _make_queries(queries):
-    keep = []
+def _make_queries(queries, per_point=False):
+    """ctypes query array; with per_point, one uint8[2^k] output buffer per query
+    (returned in `pps`, kept alive by the caller until the results are out)."""
+    keep, pps = [], []
     arr = (tpm_query * len(queries))()
     for i, q in enumerate(queries):
         M = _i32(q["multiset"])
@@ -318,21 +338,31 @@ def _make_queries(queries):
         arr[i].k = int(M.shape[0])
         arr[i].seed = int(q.get("seed", 0)) & (2**64 - 1)
         arr[i].want_path = int(q.get("want_path", 0))
-    return arr, keep
+        arr[i].deadline_ms = float(q.get("deadline_ms", 0.0))
+        pp = None
+        if per_point:
+            pp = np.zeros(1 << int(M.shape[0]), dtype=np.uint8)
+            arr[i].per_point = pp.ctypes.data_as(_u8p)
+        pps.append(pp)
+    return arr, keep, pps
 
 
-def _result_dict(r: tpm_result) -> dict:
-    return {"found": bool(r.found), "total": int(r.total), "path_status": int(r.path_status),
-            "path_vertices": list(r.path_vertices), "path_edges": list(r.path_edges),
-            "ticket": int(r.ticket), "t_submit_ms": r.t_submit_ms, "t_start_ms": r.t_start_ms,
-            "t_done_ms": r.t_done_ms}
+def _result_dict(r: tpm_result, per_point=None) -> dict:
+    d = {"status": int(r.status), "found": bool(r.found), "total": int(r.total),
+         "path_status": int(r.path_status),
+         "path_vertices": list(r.path_vertices), "path_edges": list(r.path_edges),
+         "ticket": int(r.ticket), "t_submit_ms": r.t_submit_ms, "t_start_ms": r.t_start_ms,
+         "t_done_ms": r.t_done_ms}
+    if per_point is not None:
+        d["per_point"] = per_point
+    return d
 
 
 def tpm_sieve_vertex(h, multiset, seed, mask=None):
     st = tpm_graph_stats_get(h)
     M = _i32(multiset)
     q = np.empty(st["n"], dtype=np.uint8)
-    mk = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8)
+    mk = _mask(h, mask)
     _check(_lib.tpm_sieve_vertex(h, _ptr(M, _i32p), len(M), int(seed) & (2**64 - 1),
                                  _ptr(mk, _u8p), _ptr(q, _u8p)))
     return q
@@ -417,12 +447,13 @@ def tpm_autotune(h, k, seed=1) -> dict:
                             "rate": rep.cand_rate[i]} for i in range(rep.ncand)]}
 
 
-def tpm_batch_run(h, queries, chunk=0, use_graph=False, prune=False):
-    arr, _keep = _make_queries(queries)
+def tpm_batch_run(h, queries, chunk=0, use_graph=False, prune=False, streams=0, per_point=False):
+    """Results as dicts; with per_point, each carries its query's uint8[2^k] values."""
+    arr, _keep, pps = _make_queries(queries, per_point)
     out = (tpm_result * len(queries))()
-    tune = tpm_tuning(int(chunk), 1 if use_graph else 0, 1 if prune else 0)
+    tune = tpm_tuning(int(chunk), 1 if use_graph else 0, 1 if prune else 0, int(streams))
     _check(_lib.tpm_batch_run(h, len(queries), arr, out, ctypes.byref(tune)))
-    return [_result_dict(out[i]) for i in range(len(queries))]
+    return [_result_dict(out[i], pps[i]) for i in range(len(queries))]
 
 
 def tpm_rainbow_decide(h, k, seed=1, reps=1):
@@ -434,16 +465,24 @@ def tpm_rainbow_decide(h, k, seed=1, reps=1):
     return bool(found.value), [int(c) for c in cols[: int(k)]] if found.value else None
 
 
-def tpm_server_create(h, state_bytes=0, max_lanes=0, extract_paths=0, prune_queries=0):
+def tpm_server_create(h, state_bytes=0, max_lanes=0, extract_paths=0, prune_queries=0, streams=0):
     cfg = tpm_server_config(int(state_bytes), int(max_lanes), int(extract_paths),
-                            int(prune_queries))
+                            int(prune_queries), int(streams))
     s = ctypes.c_void_p()
     _check(_lib.tpm_server_create(h, ctypes.byref(cfg), ctypes.byref(s)))
     return s
 
 
-def tpm_server_submit(s, multiset, seed, want_path=0) -> int:
-    arr, keep = _make_queries([{"multiset": multiset, "seed": seed, "want_path": want_path}])
+def tpm_server_submit(s, multiset, seed, want_path=0, per_point=None, deadline_ms=0.0) -> int:
+    """per_point: None, or a uint8[2^k] numpy array that the server fills before the
+    result is polled (the caller keeps it alive until then)."""
+    arr, keep, _ = _make_queries([{"multiset": multiset, "seed": seed, "want_path": want_path,
+                                   "deadline_ms": deadline_ms}])
+    if per_point is not None:
+        if (not isinstance(per_point, np.ndarray) or per_point.dtype != np.uint8
+                or not per_point.flags["C_CONTIGUOUS"] or per_point.size != (1 << int(arr[0].k))):
+            raise ValueError("per_point must be a contiguous uint8 array of 2^k entries")
+        arr[0].per_point = per_point.ctypes.data_as(_u8p)
     t = ctypes.c_uint64(0)
     _check(_lib.tpm_server_submit(s, ctypes.byref(arr[0]), ctypes.byref(t)))
     del keep
@@ -455,6 +494,11 @@ def tpm_server_poll(s, max_results=64):
     n = ctypes.c_int32(0)
     _check(_lib.tpm_server_poll(s, out, int(max_results), ctypes.byref(n)), ok=(TPM_OK, TPM_PENDING))
     return [_result_dict(out[i]) for i in range(n.value)]
+
+
+def tpm_server_cancel(s, ticket) -> bool:
+    """True if the request was still running or queued (it ends TPM_ECANCELLED)."""
+    return _check(_lib.tpm_server_cancel(s, int(ticket)), ok=(TPM_OK, TPM_NOTFOUND)) == TPM_OK
 
 
 def tpm_server_stats_get(s) -> dict:
@@ -561,8 +605,8 @@ class Graph:
     def extract_optimum(self, multiset, seed, reps=4, method=0):
         return tpm_extract_optimum(self.h, multiset, seed, reps, method)
 
-    def batch(self, queries, chunk=0, use_graph=False, prune=False):
-        return tpm_batch_run(self.h, queries, chunk, use_graph, prune)
+    def batch(self, queries, chunk=0, use_graph=False, prune=False, streams=0, per_point=False):
+        return tpm_batch_run(self.h, queries, chunk, use_graph, prune, streams, per_point)
 
     def sieve_vertex(self, multiset, seed, mask=None):
         return tpm_sieve_vertex(self.h, multiset, seed, mask)
@@ -592,18 +636,33 @@ class Server:
     """Owner of a serving loop over a resident graph (tpm_server_*)."""
 
     def __init__(self, graph: Graph, state_bytes=0, max_lanes=0, extract_paths=0,
-                 prune_queries=0):
+                 prune_queries=0, streams=0):
         self.graph = graph
-        self.h = tpm_server_create(graph.h, state_bytes, max_lanes, extract_paths, prune_queries)
+        self.h = tpm_server_create(graph.h, state_bytes, max_lanes, extract_paths, prune_queries,
+                                   streams)
+        self._pp = {}  # ticket -> per-point buffer the server writes
 
-    def submit(self, multiset, seed, want_path=0) -> int:
-        return tpm_server_submit(self.h, multiset, seed, want_path)
+    def submit(self, multiset, seed, want_path=0, per_point=False, deadline_ms=0.0) -> int:
+        """per_point=True: the polled result carries the uint8[2^k] per-point values."""
+        buf = np.zeros(1 << len(multiset), dtype=np.uint8) if per_point else None
+        t = tpm_server_submit(self.h, multiset, seed, want_path, buf, deadline_ms)
+        if buf is not None:
+            self._pp[t] = buf
+        return t
+
+    def cancel(self, ticket) -> bool:
+        return tpm_server_cancel(self.h, ticket)
 
     def stats(self) -> dict:
         return tpm_server_stats_get(self.h)
 
     def poll(self, max_results=64):
-        return tpm_server_poll(self.h, max_results)
+        res = tpm_server_poll(self.h, max_results)
+        for r in res:
+            buf = self._pp.pop(r["ticket"], None)
+            if buf is not None and r["status"] == TPM_OK:
+                r["per_point"] = buf
+        return res
 
     def drain(self, n, timeout_s=600.0):
         """Poll until n results arrived (or raise on timeout)."""

@@ -276,8 +276,8 @@ def test_autotune_applies_a_candidate_and_keeps_results(tpm, k):
 @pytest.mark.timeout(600)
 def test_k10_full_size_sampled_points(tpm):
     """The k = 10 workload at full size (n = 1e6, m = 1e8), in the launch
-    configuration the bench times (one 1024-point chunk), against the oracle on a
-    sample of sieve points computed one by one."""
+    configuration the bench times (one 1024-point chunk), against the oracle on 64
+    sieve points computed one by one."""
     import os
     g = make_config_graph("k10")
     M = make_config_query("k10")
@@ -288,8 +288,10 @@ def test_k10_full_size_sampled_points(tpm):
     assert tot == int(np.bitwise_xor.reduce(pp))
     st = Gd.stats()
     Gd.close()
-    rng = np.random.default_rng(11)
-    pts = np.unique(np.concatenate([[0, 1, 512, 1023], rng.choice(1024, 8, replace=False)]))
+    # one point per lane (lane L holds points 16 L .. 16 L + 15 of the 1024-point row),
+    # at byte position L mod 16 of the lane: every lane and every byte position of a
+    # lane's 16 points is checked
+    pts = np.array([16 * L + (L % 16) for L in range(64)])
     nthreads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
     say(f"oracle on {pts.size} points, {nthreads} threads (rows={st['rows']})")
     idx = oracle.Index(g)
