@@ -35,10 +35,17 @@ _u32p = ctypes.POINTER(ctypes.c_uint32)
 def lib():
     global _lib
     if _lib is None:
-        path = os.path.join(_HERE, "liboracle.so")
-        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(
-                os.path.join(_HERE, "tpm_oracle.c")):
-            _build.build()
+        # TPM_ORACLE_SANITIZED=1 loads the AddressSanitizer/UBSan build instead (the
+        # process must have libasan preloaded)
+        if os.environ.get("TPM_ORACLE_SANITIZED") == "1":
+            path = _build.SAN_LIB
+            if not os.path.exists(path):
+                _build.build_sanitized()
+        else:
+            path = os.path.join(_HERE, "liboracle.so")
+            if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(
+                    os.path.join(_HERE, "tpm_oracle.c")):
+                _build.build()
         L = ctypes.CDLL(path)
         L.or_init.restype = None
         L.or_gf_mul_bits.restype = ctypes.c_uint8

@@ -13,6 +13,11 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "tpm_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
+# AddressSanitizer + UndefinedBehaviorSanitizer build of the same source (host code
+# only; loaded by the sanitizer test with libasan preloaded)
+SAN_LIB = os.path.join(HERE, "liboracle_san.so")
+SAN_FLAGS = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+             "-fno-sanitize-recover=all"]
 
 
 def build(force: bool = True) -> str:
@@ -24,6 +29,16 @@ def build(force: bool = True) -> str:
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
     return LIB
+
+
+def build_sanitized() -> str:
+    """The oracle with AddressSanitizer and UndefinedBehaviorSanitizer (any report aborts)."""
+    tmp = SAN_LIB + ".tmp"
+    cmd = ["gcc", *SAN_FLAGS, "-std=c11", "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wextra",
+           "-Wno-unused-parameter", SRC, "-o", tmp]
+    subprocess.check_call(cmd)
+    os.replace(tmp, SAN_LIB)
+    return SAN_LIB
 
 
 if __name__ == "__main__":
