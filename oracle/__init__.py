@@ -63,6 +63,7 @@ def lib():
         L.or_index_build.restype = ctypes.c_void_p
         L.or_index_build.argtypes = [ctypes.c_int32, ctypes.c_int64, _i32p, _i32p, _i32p]
         L.or_index_free.argtypes = [ctypes.c_void_p]
+        L.or_index_set_eid.argtypes = [ctypes.c_void_p, _i32p]
         L.or_eval.argtypes = [ctypes.c_void_p, _u8p, ctypes.c_int32, ctypes.c_uint64, _u32p,
                               ctypes.c_int64, _u8p, _u8p, ctypes.c_int]
         L.or_sieve.argtypes = [ctypes.c_int32, ctypes.c_int64, _i32p, _i32p, _i32p, _i32p,
@@ -288,17 +289,40 @@ def optimum_time(g, M, seed: int, reps: int = 1, nthreads: int = 0, transit=None
 
 class Index:
     """Reusable oracle index (in-lists sorted by time) for repeated evaluations;
-    keeps references to the arrays it borrows."""
+    keeps references to the arrays it borrows.
 
-    def __init__(self, g):
+    keep_colours (optional): index only the edges whose two endpoints have one of these
+    colours, the paper's preprocessing step (i).  A vertex whose colour is not in the
+    multiset has z = 0 (Eq. (motif)), so every term of a walk through it vanishes and
+    such edges change no value; the kept edges keep their input indices as fingerprint
+    keys.  eval() then accepts only multisets whose colours are all kept (no
+    wildcards)."""
+
+    def __init__(self, g, keep_colours=None):
         self.g = g
-        self._src, self._dst, self._tau = _c32(g.src), _c32(g.dst), _c32(g.tau)
-        self._h = lib().or_index_build(g.n, g.m, _p(self._src, _i32p), _p(self._dst, _i32p),
+        self.keep = None
+        src, dst, tau = _c32(g.src), _c32(g.dst), _c32(g.tau)
+        self._eid = None
+        if keep_colours is not None:
+            self.keep = set(int(c) for c in keep_colours)
+            incol = np.zeros(max(1, int(g.num_colors)), dtype=bool)
+            incol[sorted(self.keep)] = True
+            color = np.asarray(g.color)
+            sel = np.nonzero(incol[color[src]] & incol[color[dst]])[0]
+            self._eid = sel.astype(np.int32)
+            src, dst, tau = src[sel], dst[sel], tau[sel]
+        self._src, self._dst, self._tau = src, dst, tau
+        self.m = int(src.shape[0])
+        self._h = lib().or_index_build(g.n, self.m, _p(self._src, _i32p), _p(self._dst, _i32p),
                                        _p(self._tau, _i32p))
         if not self._h:
             raise MemoryError("oracle index")
+        if self._eid is not None:
+            lib().or_index_set_eid(ctypes.c_void_p(self._h), _p(self._eid, _i32p))
 
     def eval(self, M, seed: int, points, mask=None, nthreads: int = 0) -> np.ndarray:
+        if self.keep is not None and not all(int(c) in self.keep for c in M):
+            raise ValueError("the multiset has a colour (or a wildcard) whose edges were dropped")
         z = zvals(self.g, M, seed, mask)
         points = np.ascontiguousarray(points, dtype=np.uint32)
         out = np.empty(points.shape[0], dtype=np.uint8)

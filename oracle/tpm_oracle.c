@@ -190,6 +190,8 @@ typedef struct {
                        or -1 if there is none */
     const uint8_t *emask; /* [m] or NULL (borrowed): emask[e] == 0 removes edge e from
                              the graph (it keeps its index, so y of the others is as is) */
+    const int32_t *eid;   /* [m] or NULL (borrowed): the fingerprint key of edge e (its
+                             index in a larger graph this one keeps some edges of) */
 } or_index;
 
 static const int32_t *g_cmp_tau;
@@ -283,6 +285,12 @@ or_index *or_index_build(int32_t n, int64_t m, const int32_t *src, const int32_t
     return or_index_build_ex(n, m, src, dst, tau, NULL, NULL);
 }
 
+/* y_{e,l} of the edge at index e is keyed by eid[e] instead of e (borrowed). */
+void or_index_set_eid(or_index *ix, const int32_t *eid)
+{
+    ix->eid = eid;
+}
+
 /* ------------------------------------------------------------------------- */
 /* Evaluation of P(A) (Eq. (3)) at a list of sieve points.                     */
 /* ------------------------------------------------------------------------- */
@@ -321,7 +329,8 @@ static int or_eval_impl(const or_index *ix, const uint8_t *z, int32_t k, uint64_
             return -2;
         for (int l = 1; l <= k - 1; l++)
             for (int64_t e = 0; e < m; e++)
-                Y[(size_t)(l - 1) * m + e] = or_fp(seed, 1, (uint32_t)l, (uint32_t)e);
+                Y[(size_t)(l - 1) * m + e] =
+                    or_fp(seed, 1, (uint32_t)l, (uint32_t)(ix->eid ? ix->eid[e] : e));
     }
     if (loc)
         memset(loc, 0, (size_t)m);

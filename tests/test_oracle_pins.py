@@ -467,6 +467,28 @@ def test_invariants_bit_exact():
         assert np.array_equal(oracle.sieve(g, M, 9, mask=mask), oracle.sieve(h, M, 9))
 
 
+def test_colour_restricted_index_matches_walk_enumeration():
+    """The oracle index over the edges between vertices of kept colours (preprocessing
+    step (i), fingerprints keyed by input index) gives brute force's per-point values
+    for any multiset over the kept colours, and refuses other multisets."""
+    rng = np.random.default_rng(31)
+    for it in range(200):
+        g = G.random_tiny_graph(rng, n_max=10, m_max=30, t_max=5, q_max=4)
+        k = int(rng.integers(1, 5))
+        M = [int(c) for c in rng.integers(0, g.num_colors, k)]
+        keep = set(M) | set(int(c) for c in rng.integers(0, g.num_colors, int(rng.integers(0, 2))))
+        seed = int(rng.integers(0, 2**62))
+        idx = oracle.Index(g, keep_colours=keep)
+        pts = np.arange(1 << k, dtype=np.uint32)
+        assert np.array_equal(idx.eval(M, seed, pts), pyref.brute_per_point(g, M, seed)), it
+        col = np.asarray(g.color)
+        assert idx.m == int(np.sum(np.isin(col[g.src], list(keep)) & np.isin(col[g.dst], list(keep))))
+        other = [c for c in range(g.num_colors) if c not in keep]
+        if other:
+            with pytest.raises(ValueError):
+                idx.eval(M + [other[0]], seed, pts[:1])
+
+
 def test_path_checker():
     rng = np.random.default_rng(41)
     n_ok = 0
