@@ -249,6 +249,30 @@ tpm_status tpm_sieve_ex(const tpm_graph *g, const int32_t *multiset, int32_t k, 
                         const uint8_t *vertex_mask, const tpm_tuning *tune, uint8_t *per_point,
                         uint8_t *total, uint8_t *loc, void *hip_stream);
 
+/* tpm_sieve for callers that cannot allocate device memory: code under HIP graph
+ * capture, serving loops and harnesses that must not call hipMalloc.  Computes what
+ * tpm_sieve computes (no vertex mask) and allocates nothing: every buffer of the query
+ * lives in one fixed block of 256 MiB of device memory per GPU, reserved when the
+ * library's code is loaded on that GPU and held until the process ends.  Rows are the
+ * widest power of two of sieve points (16 .. 1024) whose buffers fit the block; graphs
+ * whose state does not fit even 16-point rows (about 32 (n + R + S) bytes for k >= 3,
+ * R and S = rows and slots of tpm_graph_stats) are refused with TPM_ENOMEM.
+ * Asynchronous: only enqueues work on hip_stream (NULL = the default stream) and
+ * returns; the outputs are DEVICE pointers, valid once the stream has reached them:
+ *   total        1 byte, the XOR of all 2^k sieve values (required);
+ *   per_point    2^k bytes, per_point[A] = P_{k,t}(z^A) (nullable);
+ *   error_flags  4 bytes, 0, or nonzero if the kernels reported a look-back failure
+ *                (the results are then invalid) (nullable).
+ * Every call on one GPU uses that GPU's block, and a call's buffers keep their contents
+ * until the next call: calls that overlap on one GPU (other host threads, or other
+ * streams whose work has not finished) race and give wrong results; serialise them.
+ * multiset is a host pointer, read before the call returns.
+ * Errors: TPM_EINVAL (NULL graph or total, k out of range, colour out of range),
+ * TPM_ENOMEM (the state does not fit the block), TPM_EDEVICE. */
+tpm_status tpm_sieve_noalloc(const tpm_graph *g, const int32_t *multiset, int32_t k, uint64_t seed,
+                             uint8_t *per_point, uint8_t *total, uint32_t *error_flags,
+                             void *hip_stream);
+
 /* Decide PATH-MOTIF: run up to `reps` sieves with seeds seed_r = seed + r *
  * 0x9E3779B97F4A7C15 and stop at the first nonzero total.  *found = 1 is
  * certain; *found = 0 means no sieve detected a path.  reps >= 1. */

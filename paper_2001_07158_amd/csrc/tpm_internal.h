@@ -370,6 +370,17 @@ tpm_status extract_vertexloc(const Graph &G, const int32_t *M, int32_t k, uint64
                              int32_t max_reps, int32_t *path_vertices, int64_t *path_edges,
                              int64_t *sieves, int64_t budget);
 
+// A whole sieve query enqueued on st with every buffer carved out of the device block
+// [scratch, scratch + cap): no allocation and no host synchronisation.  Outputs go to
+// device memory: *total, per_point[0 .. 2^k) (nullable) and *err (nullable: the
+// look-back failure bits, 0 when none).  Rows are the widest power of two of points
+// whose buffers fit; TPM_ENOMEM when even 16-point rows do not.  No vertex mask.
+void enqueue_sieve_fixed(const Graph &G, const int32_t *M, int32_t k, uint64_t seed,
+                         uint8_t *scratch, size_t cap, uint8_t *per_point, uint8_t *total,
+                         uint32_t *err, hipStream_t st);
+// bytes enqueue_sieve_fixed needs at its narrowest rows
+size_t fixed_scratch_need(const Graph &G, int32_t k);
+
 // Per-edge localisation over all edges, indexed by input edge id.
 void run_sieve_loc_all(const Graph &G, const SieveRequest &req, SieveResult &res,
                        uint8_t *loc_by_edge, hipStream_t stream);

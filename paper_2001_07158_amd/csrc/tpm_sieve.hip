@@ -1109,6 +1109,34 @@ __global__ void k_total(int32_t npts, const uint8_t *pp, uint8_t *total) {
     }
 }
 
+// p[0 .. words) = v (grid-stride); clears device words without a memset node
+__global__ void k_fill32(uint32_t *p, int64_t words, uint32_t v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// Outputs of a sieve on caller buffers: total = XOR of the npts per-point bytes,
+// out[0 .. npts) = pp (out nullable), *err = the look-back failure bits (nullable).
+// One workgroup of 256 threads.
+__global__ void k_fixed_out(int32_t npts, const uint8_t *pp, uint8_t *out, uint8_t *total,
+                            const Ctl *ctl, uint32_t *err) {
+    uint32_t v = 0;
+    for (int32_t i = threadIdx.x; i < npts; i += blockDim.x) {
+        const uint8_t b = pp[i];
+        v ^= b;
+        if (out) out[i] = b;
+    }
+    for (int off = 32; off >= 1; off >>= 1) v ^= __shfl_xor(v, off);
+    __shared__ uint32_t part[4];
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        *total = (uint8_t)(part[0] ^ part[1] ^ part[2] ^ part[3]);
+        if (err) *err = ctl->err;
+    }
+}
+
 // smallest (input edge id, position) over positions whose localisation is nonzero;
 // each wave reduces its 64 candidates first, so the shared word sees one atomic per wave
 __global__ void k_pick(int32_t lo, int32_t hi, const uint8_t *loc, const int32_t *peid,
@@ -1731,6 +1759,71 @@ void check_cancel(const SieveRequest &req, hipStream_t st) {
     }
 }
 
+namespace {
+// Device buffers of one sieve query: per-vertex z and x rows, the two level buffers,
+// published look-back words, control words, per-point accumulators (zeroed by the
+// caller) and, nullable, per-position localisation bytes of the last level.
+struct LevelBufs {
+    uint8_t *z = nullptr, *xt = nullptr, *s0 = nullptr, *s1 = nullptr, *pp = nullptr;
+    unsigned long long *pub = nullptr;
+    Ctl *ctl = nullptr;
+    uint8_t *loc = nullptr;
+};
+
+// Enqueues levels 2..k of every chunk of rowb points in [0, pts_end) on st: the x rows
+// of the chunk, then one level kernel per level, the last one accumulating into
+// pp[base ..] (positions [lo, hi) contribute; its tiles are [fin_tlo, fin_thi)).  z must
+// hold the query's z rows.  With a request, cancellation is checked between launches.
+void enqueue_chunks(const Graph &G, int32_t k, uint64_t seed, int rowb, int64_t pts_end,
+                    const LevelBufs &B, int64_t lo, int64_t hi, int32_t fin_tlo, int32_t fin_thi,
+                    const SieveRequest *req, bool profile, hipStream_t st) {
+    const int64_t npts = int64_t(1) << k;
+    // lanes holding points: 64 lanes of 16 points for 1024-point rows, else one 16-point
+    // lane per 16 points of a narrow row (its 1024 / rowb slots repeat the same lanes)
+    const int lanes = std::max(1, rowb / 16);
+    for (int64_t base = 0; base < pts_end; base += rowb) {
+        k_xt<<<grid_for((int64_t)G.n * ((rowb + 15) / 16)), 256, 0, st>>>(G.n, k, rowb, rowb, 0,
+                                                                           (uint32_t)base, B.z, B.xt);
+        for (int l = 2; l <= k; ++l) {
+            if (req) check_cancel(*req, st);
+            const bool fin = (l == k);
+            LevelParams P{};
+            P.gidx = (l == 2) ? G.psrc : G.gsrc;
+            P.gbase = (l == 2) ? B.xt : ((l & 1) ? B.s0 : B.s1);
+            P.pdst = G.pdst;
+            P.peid = G.peid;
+            P.orow = G.orow;
+            P.sout = (l & 1) ? B.s1 : B.s0;
+            P.xt = B.xt;
+            P.tile_p0 = G.tile_p0;
+            P.tile_pub = G.tile_pub;
+            P.tile_lb = G.tile_lb;
+            P.tile_lo = fin ? fin_tlo : 0;
+            P.tile_hi = fin ? fin_thi : (int32_t)G.ntiles;
+            P.pos_lo = (int32_t)lo;
+            P.pos_hi = (int32_t)hi;
+            P.pub = B.pub;
+            P.ctl = B.ctl;
+            P.fin = (uint32_t *)(B.pp + base);
+            P.loc = B.loc;
+            P.lds_image = G.lds_image;
+            P.seed = seed;
+            P.ylevel = (uint32_t)(l - 1);
+            P.rowb = rowb;
+            P.lanes = lanes;
+            P.valid_pts = (int32_t)std::min<int64_t>(rowb, npts - base);
+            k_prep<<<1, 1, 0, st>>>(B.ctl, fin ? 0 : 1);
+            if (profile) {
+                ProfileScope prof(st, fin ? 2 : (l == 2 ? 0 : 1), l, rowb);
+                launch_level_any(rowb, fin, G, P, st);
+            } else {
+                launch_level_any(rowb, fin, G, P, st);
+            }
+        }
+    }
+}
+}  // namespace
+
 // Positions [lo, hi) of the last level contribute (all when fin_lo >= fin_hi).  With
 // want_loc, the per-position localisation over that range is computed on the device;
 // loc_host (nullable, hi - lo bytes) receives it, and res.pick_eid / res.pick_pos get
@@ -1742,9 +1835,6 @@ void run_sieve_impl(const Graph &G, const SieveRequest &req, SieveResult &res, b
     QuerySlots qs = make_slots(G, req.multiset, k);
     const int64_t npts = int64_t(1) << k;
     const int rowb = (k == 1) ? 4 : pick_chunk(G, k, req.chunk);
-    // lanes holding points: 64 lanes of 16 points for 1024-point rows, else one 16-point
-    // lane per 16 points of a narrow row (its 1024 / rowb slots repeat the same lanes)
-    const int lanes = std::max(1, rowb / 16);
     const int rowd = rowb / 4;
     const int64_t ppbytes = std::max<int64_t>(npts, rowb);
 
@@ -1802,44 +1892,16 @@ void run_sieve_impl(const Graph &G, const SieveRequest &req, SieveResult &res, b
         }
         const int64_t pts_end =
             req.max_chunks > 0 ? std::min<int64_t>(npts, (int64_t)req.max_chunks * rowb) : npts;
-        for (int64_t base = 0; base < pts_end; base += rowb) {
-            k_xt<<<grid_for((int64_t)G.n * ((rowb + 15) / 16)), 256, 0, st>>>(
-                G.n, k, rowb, rowb, 0, (uint32_t)base, z.as<uint8_t>(), xt.as<uint8_t>());
-            for (int l = 2; l <= k; ++l) {
-                check_cancel(req, st);
-                const bool fin = (l == k);
-                LevelParams P{};
-                P.gidx = (l == 2) ? G.psrc : G.gsrc;
-                P.gbase = (l == 2) ? xt.as<uint8_t>() : ((l & 1) ? s0.as<uint8_t>() : s1.as<uint8_t>());
-                P.pdst = G.pdst;
-                P.peid = G.peid;
-                P.orow = G.orow;
-                P.sout = (l & 1) ? s1.as<uint8_t>() : s0.as<uint8_t>();
-                P.xt = xt.as<uint8_t>();
-                P.tile_p0 = G.tile_p0;
-                P.tile_pub = G.tile_pub;
-                P.tile_lb = G.tile_lb;
-                P.tile_lo = fin ? fin_tlo : 0;
-                P.tile_hi = fin ? fin_thi : (int32_t)G.ntiles;
-                P.pos_lo = (int32_t)lo;
-                P.pos_hi = (int32_t)hi;
-                P.pub = pub.as<unsigned long long>();
-                P.ctl = ctl.as<Ctl>();
-                P.fin = (uint32_t *)(pp.as<uint8_t>() + base);
-                P.loc = want_loc ? loc.as<uint8_t>() : nullptr;
-                P.lds_image = G.lds_image;
-                P.seed = req.seed;
-                P.ylevel = (uint32_t)(l - 1);
-                P.rowb = rowb;
-                P.lanes = lanes;
-                P.valid_pts = (int32_t)std::min<int64_t>(rowb, npts - base);
-                k_prep<<<1, 1, 0, st>>>(ctl.as<Ctl>(), fin ? 0 : 1);
-                {
-                    ProfileScope prof(st, fin ? 2 : (l == 2 ? 0 : 1), l, rowb);
-                    launch_level_any(rowb, fin, G, P, st);
-                }
-            }
-        }
+        LevelBufs B;
+        B.z = z.as<uint8_t>();
+        B.xt = xt.as<uint8_t>();
+        B.s0 = s0.as<uint8_t>();
+        B.s1 = s1.as<uint8_t>();
+        B.pp = pp.as<uint8_t>();
+        B.pub = pub.as<unsigned long long>();
+        B.ctl = ctl.as<Ctl>();
+        B.loc = want_loc ? loc.as<uint8_t>() : nullptr;
+        enqueue_chunks(G, k, req.seed, rowb, pts_end, B, lo, hi, fin_tlo, fin_thi, &req, true, st);
     }
     k_total<<<1, 256, 0, st>>>((int32_t)npts, pp.as<uint8_t>(), tot.as<uint8_t>());
     unsigned long long hpick = ~0ull;
@@ -1902,6 +1964,99 @@ void run_sieve_loc_all(const Graph &G, const SieveRequest &req, SieveResult &res
         TPM_HIP(hipMemcpy(peid.data(), G.peid, sizeof(int32_t) * G.m, hipMemcpyDeviceToHost));
         for (int64_t p = 0; p < G.m; ++p) loc_by_edge[peid[p]] = bypos[p];
     }
+}
+
+// ---------------------------------------------------------------- fixed scratch
+namespace {
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// Carving of one sieve query's buffers out of a block of `cap` bytes: the widest row
+// (a power of two of points in [16, min(1024, 2^k)]) whose buffers fit.
+struct FixedLayout {
+    int rowb = 0;
+    size_t ctl = 0, z = 0, xt = 0, s0 = 0, s1 = 0, pub = 0, pp = 0, end = 0;
+};
+
+FixedLayout fixed_layout(const Graph &G, int32_t k, int rowb) {
+    const int64_t npts = int64_t(1) << k;
+    FixedLayout L;
+    L.rowb = rowb;
+    size_t at = 0;
+    auto take = [&](size_t bytes) {
+        const size_t off = at;
+        at = align_up(at + std::max<size_t>(bytes, 1));
+        return off;
+    };
+    L.ctl = take(sizeof(Ctl));
+    L.z = take((size_t)G.n * 16);
+    L.pp = take((size_t)std::max<int64_t>(npts, rowb));
+    if (k >= 2 && G.m > 0) {
+        const size_t R = (size_t)std::max<int64_t>(1, G.R);
+        L.xt = take((size_t)G.n * rowb);
+        L.s0 = take(R * rowb);
+        if (k > 2) L.s1 = take(R * rowb);
+        if (k > 2 && G.nslots) L.pub = take((size_t)G.nslots * (rowb / 4) * 8);
+    }
+    L.end = at;
+    return L;
+}
+
+void fill_words(void *p, size_t bytes, hipStream_t st) {
+    const int64_t words = (int64_t)(bytes / 4);
+    if (words <= 0) return;
+    const unsigned grid = (unsigned)std::min<int64_t>(1024, (words + 255) / 256);
+    k_fill32<<<grid, 256, 0, st>>>((uint32_t *)p, words, 0u);
+}
+}  // namespace
+
+size_t fixed_scratch_need(const Graph &G, int32_t k) {
+    return fixed_layout(G, k, k == 1 ? 4 : 16).end;
+}
+
+void enqueue_sieve_fixed(const Graph &G, const int32_t *M, int32_t k, uint64_t seed,
+                         uint8_t *scratch, size_t cap, uint8_t *per_point, uint8_t *total,
+                         uint32_t *err, hipStream_t st) {
+    TPM_REQUIRE(total != nullptr, "total must not be NULL");
+    QuerySlots qs = make_slots(G, M, k);
+    const int64_t npts = int64_t(1) << k;
+    FixedLayout L;
+    if (k == 1) {
+        L = fixed_layout(G, k, 4);
+    } else {
+        for (int rowb = (int)std::min<int64_t>(1024, std::max<int64_t>(npts, 16)); rowb >= 16; rowb >>= 1) {
+            L = fixed_layout(G, k, rowb);
+            if (L.end <= cap) break;
+        }
+    }
+    if (L.end > cap)
+        throw Error{TPM_ENOMEM, "query needs " + std::to_string(L.end) +
+                                    " bytes of sieve state at its narrowest rows; the fixed scratch holds " +
+                                    std::to_string(cap)};
+    uint8_t *base = scratch;
+    Ctl *ctl = (Ctl *)(base + L.ctl);
+    uint8_t *z = base + L.z, *pp = base + L.pp;
+    const int64_t ppbytes = std::max<int64_t>(npts, L.rowb);
+    // the scratch keeps the previous call's contents: clear what must start at zero
+    fill_words(ctl, sizeof(Ctl), st);
+    fill_words(pp, (size_t)ppbytes, st);
+    k_z<<<grid_for(G.n), 256, 0, st>>>(G.n, k, G.color, G.fid, qs, nullptr, seed, z);
+    if (k == 1) {
+        k_single<<<grid_for(G.n), 256, 0, st>>>(G.n, z, (uint32_t *)pp);
+    } else if (G.m > 0) {
+        if (L.pub) fill_words(base + L.pub, (size_t)G.nslots * (L.rowb / 4) * 8, st);
+        LevelBufs B;
+        B.z = z;
+        B.xt = base + L.xt;
+        B.s0 = base + L.s0;
+        B.s1 = k > 2 ? base + L.s1 : nullptr;
+        B.pp = pp;
+        B.pub = L.pub ? (unsigned long long *)(base + L.pub) : nullptr;
+        B.ctl = ctl;
+        enqueue_chunks(G, k, seed, L.rowb, npts, B, 0, G.m, 0, (int32_t)G.ntiles, nullptr, false, st);
+    }
+    k_fixed_out<<<1, 256, 0, st>>>((int32_t)npts, pp, per_point, total, ctl, err);
+    TPM_HIP(hipGetLastError());
 }
 
 // ---------------------------------------------------------------- static instance

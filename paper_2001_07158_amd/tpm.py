@@ -135,6 +135,8 @@ _sig("tpm_sieve", ctypes.c_int32, [_vp, _i32p, ctypes.c_int32, ctypes.c_uint64, 
                                   _vp])
 _sig("tpm_sieve_ex", ctypes.c_int32, [_vp, _i32p, ctypes.c_int32, ctypes.c_uint64, _u8p,
                                      ctypes.POINTER(tpm_tuning), _u8p, _u8p, _u8p, _vp])
+_sig("tpm_sieve_noalloc", ctypes.c_int32, [_vp, _i32p, ctypes.c_int32, ctypes.c_uint64, _vp, _vp,
+                                              _vp, _vp])
 _sig("tpm_decide", ctypes.c_int32, [_vp, _i32p, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int32,
                                    _i32p])
 _sig("tpm_extract", ctypes.c_int32, [_vp, _i32p, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int32,
@@ -161,7 +163,7 @@ EXPORTED = ["tpm_graph_create", "tpm_graph_create_ex", "tpm_graph_destroy", "tpm
             "tpm_graph_retile", "tpm_autotune", "tpm_graph_prune", "tpm_graph_prune_ex",
             "tpm_graph_layer", "tpm_graph_sd", "tpm_graph_vertex_ids", "tpm_sieve_vertex", "tpm_time_buckets",
             "tpm_optimum_time", "tpm_static_sieve", "tpm_graph_prune_static",
-            "tpm_sieve", "tpm_sieve_ex", "tpm_decide", "tpm_extract", "tpm_extract_ex",
+            "tpm_sieve", "tpm_sieve_ex", "tpm_sieve_noalloc", "tpm_decide", "tpm_extract", "tpm_extract_ex",
             "tpm_extract_optimum",
             "tpm_batch_run",
             "tpm_server_create", "tpm_server_submit", "tpm_server_poll", "tpm_server_cancel",
@@ -274,6 +276,22 @@ def tpm_sieve(h, multiset, seed, mask=None, chunk=0, loc_m=None, stream=None, pr
     if loc is not None:
         return pp, int(tot[0]), loc[: int(loc_m)]
     return pp, int(tot[0])
+
+
+def _dev_ptr(x):
+    """A device address: an int, or a tensor's data_ptr(); None stays NULL."""
+    if x is None:
+        return None
+    return ctypes.c_void_p(int(x) if isinstance(x, int) else int(x.data_ptr()))
+
+
+def tpm_sieve_noalloc(h, multiset, seed, total, per_point=None, error_flags=None, stream=None):
+    """Enqueues the sieve on `stream` with no allocation; total (1 byte), per_point
+    (2^k bytes) and error_flags (4 bytes) are device buffers (tensors or addresses)."""
+    M = _i32(multiset)
+    _check(_lib.tpm_sieve_noalloc(h, M.ctypes.data_as(_i32p), int(M.shape[0]), int(seed) & (2**64 - 1),
+                                  _dev_ptr(per_point), _dev_ptr(total), _dev_ptr(error_flags),
+                                  _stream_handle(stream)))
 
 
 def tpm_decide(h, multiset, seed, reps=1) -> bool:
@@ -546,6 +564,9 @@ class Graph:
     def sieve(self, multiset, seed, mask=None, chunk=0, loc=False, stream=None, prune=False):
         ids = self.stats()["edge_ids"] if loc else None
         return tpm_sieve(self.h, multiset, seed, mask, chunk, ids, stream, prune)
+
+    def sieve_noalloc(self, multiset, seed, total, per_point=None, error_flags=None, stream=None):
+        tpm_sieve_noalloc(self.h, multiset, seed, total, per_point, error_flags, stream)
 
     def rainbow(self, k, seed=1, reps=1):
         return tpm_rainbow_decide(self.h, k, seed, reps)
