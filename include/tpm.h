@@ -129,7 +129,8 @@ typedef struct {
     int32_t use_graph;
     int32_t prune;
     int32_t streams;  /* tpm_batch_run with prune = 1: queries in flight at once, each on
-                         its own HIP stream (0 = 3, at most 4) */
+                         its own HIP stream (0 = 2, at most 4; as the server's pruned
+                         mode, one of them sieves at a time) */
 } tpm_tuning;
 
 /* ---------------------------------------------------------------- graph --- */
@@ -410,7 +411,8 @@ typedef struct {
  * (lane groups of any k side by side; a finished group's lanes are refilled from the
  * queries still waiting, largest first); with tune->prune each query runs alone on
  * the subgraph of its colours, up to tune->streams at once on their own streams and
- * within a device-memory budget (85 % of the memory free at the call).  tune may be
+ * within a device-memory budget (85 % of the memory free at the call), as the
+ * server's pruned mode.  tune may be
  * NULL.  Errors: TPM_EINVAL (bad query or tuning), TPM_ENOMEM, TPM_EDEVICE. */
 tpm_status tpm_batch_run(const tpm_graph *g, int32_t nq, const tpm_query *q, tpm_result *out,
                          const tpm_tuning *tune);
@@ -436,11 +438,17 @@ typedef struct tpm_server tpm_server;
  *     take them at the next step.  Extraction runs on its own thread and stream.
  *   Pruned mode (prune_queries = 1): each request runs alone on the subgraph of its
  *     colours (as tpm_graph_prune), up to `streams` requests at once, each on its own
- *     HIP stream and worker thread, admitted when its estimated device memory (subgraph
- *     index and sieve state, from the exact edge count of its colour pairs) fits the
- *     state budget; a request that does not fit can be overtaken by later ones that
- *     do, at most 8 times.  Extraction on a hit is the reverse DFS from the deciding
- *     sieve's own vertex localisation.
+ *     HIP stream and worker thread with a fixed share (budget / streams) of the state
+ *     budget: a request takes the widest chunk of sieve points whose estimated device
+ *     memory (subgraph index and sieve state, from the exact edge count of its colour
+ *     pairs) fits the share; one larger than a share waits for the device to itself
+ *     and may be overtaken by later requests at most 8 times.  One worker uses the
+ *     device at a time (subgraph build and sieve; every such phase is bound by HBM
+ *     bandwidth, and two at once measured slower than one after the other) while the
+ *     others admit requests and extract paths on the host.  Admission takes the request
+ *     with the least estimated device work first, unless the oldest has waited 750 ms.
+ *     Extraction on a hit is the reverse DFS from the deciding sieve's own vertex
+ *     localisation.
  * Results are identical in both modes, to the same query run alone. */
 typedef struct {
     int64_t state_bytes;   /* device memory the server may use for query state (0 = 85 %
@@ -449,7 +457,7 @@ typedef struct {
     int32_t max_lanes;     /* row mode: most sieve lanes resident at once (0 = auto) */
     int32_t extract_paths; /* 1: extract a witness for every YES */
     int32_t prune_queries; /* 1: pruned mode (above) */
-    int32_t streams;       /* pruned mode: requests in flight at once (0 = 3; 1..4) */
+    int32_t streams;       /* pruned mode: requests in flight at once (0 = 2; 1..4) */
 } tpm_server_config;
 
 tpm_status tpm_server_create(const tpm_graph *g, const tpm_server_config *cfg, tpm_server **out);
@@ -483,6 +491,10 @@ typedef struct {
     int32_t inflight_peak; /* most requests running at once */
     int64_t budget_bytes;  /* state budget */
     int64_t held_bytes_peak; /* pruned mode: most device bytes held by the workers */
+    int64_t trims;         /* pruned mode: times a worker released its device memory
+                              (after a request larger than its share of the budget) */
+    double gpu_wait_ms;    /* pruned mode: time workers waited for the device (one
+                              request uses it at a time; summed) */
 } tpm_server_stats;
 tpm_status tpm_server_stats_get(tpm_server *s, tpm_server_stats *out);
 
@@ -503,6 +515,13 @@ typedef struct {
 
 tpm_status tpm_profile_enable(int32_t on);
 tpm_status tpm_profile_read(tpm_kernel_time *out, int32_t max, int32_t *n_out);
+
+/* A plain streaming read of `bytes` bytes of device memory at `src` (16-byte aligned,
+ * bytes a multiple of 16), each byte read once with 16-byte loads, for scaling
+ * profiler traffic counters against a kernel of known size; *out (device, 8 bytes)
+ * receives the XOR of the buffer's 8-byte words.  Enqueued on hip_stream (NULL = the
+ * default stream).  Errors: TPM_EINVAL (NULL, misaligned or bad size), TPM_EDEVICE. */
+tpm_status tpm_stream_read(const void *src, int64_t bytes, uint64_t *out, void *hip_stream);
 
 /* ---------------------------------------------------------------- misc --- */
 /* Description of the last error on the calling thread ("" if none). */

@@ -672,11 +672,44 @@ double now_ms() {
     return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
 }
 
+// Streaming read for counter calibration: every 16-byte word once (grid-stride), XOR
+// of the words reduced per wave, one atomic per wave.
+__global__ void k_stream_read(const uint4 *src, int64_t words, unsigned long long *out) {
+    unsigned long long v = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const uint4 t = src[i];
+        v ^= ((unsigned long long)t.y << 32 | t.x) ^ ((unsigned long long)t.w << 32 | t.z);
+    }
+    for (int off = 32; off >= 1; off >>= 1) v ^= __shfl_xor(v, off);
+    if ((threadIdx.x & 63) == 0 && v) atomicXor(out, v);
+}
+
+__global__ void k_zero64(unsigned long long *p) { *p = 0; }
+
 }  // namespace tpm
 
 using namespace tpm;
 
 extern "C" {
+
+tpm_status tpm_stream_read(const void *src, int64_t bytes, uint64_t *out, void *hip_stream) {
+    return guarded([&]() -> tpm_status {
+        TPM_REQUIRE(src && out, "NULL argument");
+        TPM_REQUIRE(bytes >= 0 && bytes % 16 == 0, "bytes must be a non-negative multiple of 16");
+        TPM_REQUIRE(((uintptr_t)src & 15) == 0, "src must be 16-byte aligned");
+        hipStream_t st = (hipStream_t)hip_stream;
+        int dev = 0, cus = 0;
+        TPM_HIP(hipGetDevice(&dev));
+        TPM_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        const int64_t words = bytes / 16;
+        const int64_t grid = std::max<int64_t>(1, std::min<int64_t>((int64_t)cus * 8, (words + 255) / 256));
+        k_zero64<<<1, 1, 0, st>>>((unsigned long long *)out);
+        k_stream_read<<<(unsigned)grid, 256, 0, st>>>((const uint4 *)src, words, (unsigned long long *)out);
+        TPM_HIP(hipGetLastError());
+        return TPM_OK;
+    });
+}
 
 const char *tpm_last_error(void) { return t_last_error.c_str(); }
 

@@ -5,7 +5,9 @@
 #include <stdint.h>
 
 #include <atomic>
+#include <functional>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <stdexcept>
 #include <string>
@@ -310,6 +312,9 @@ struct SieveRequest {
     // nullable: run in this workspace (owned by the caller, used on one stream at a
     // time) instead of one leased from the graph's pool
     Workspace *ws = nullptr;
+    // nullable: called on the host before every level launch (after the cancellation
+    // check) with the call's stream; a server lends the device between levels with it
+    const std::function<void(hipStream_t)> *between_levels = nullptr;
 };
 
 // Host clock in ms (steady clock), shared by the serving deadlines and timestamps.
@@ -380,6 +385,7 @@ void enqueue_sieve_fixed(const Graph &G, const int32_t *M, int32_t k, uint64_t s
                          uint32_t *err, hipStream_t st);
 // bytes enqueue_sieve_fixed needs at its narrowest rows
 size_t fixed_scratch_need(const Graph &G, int32_t k);
+
 
 // Per-edge localisation over all edges, indexed by input edge id.
 void run_sieve_loc_all(const Graph &G, const SieveRequest &req, SieveResult &res,

@@ -12,9 +12,12 @@
 //   * Pruned mode: each request runs alone on the subgraph of its own colours (the
 //     paper's preprocessing step (i), section "Implementation"; exact, since a vertex
 //     of another colour has z = 0).  Up to 4 worker threads, each with its own HIP
-//     stream, subgraph arena and sieve workspace, run requests at once; a request is
-//     admitted when the device memory it needs (estimated from the exact edge count of
-//     its colour pairs) fits the state budget beside what the other workers hold.
+//     stream, subgraph arena, sieve workspace and a fixed share of the state budget,
+//     hold requests at once; a request takes the widest chunk whose device memory
+//     (estimated from the exact edge count of its colour pairs) fits the share.  One
+//     worker uses the device at a time, while the others admit requests and extract
+//     paths on the host; admission takes the least device work first unless the
+//     oldest request has waited long.
 // Results are bit-identical to the same query run alone: fingerprints depend only on
 // (seed, tag, indices), never on lanes, steps, streams or subgraphs.
 
@@ -62,6 +65,8 @@ using namespace tpm;
 namespace {
 
 constexpr int kMaxBypass = 8;     // times a waiting request may be overtaken
+constexpr double kAgeMs = 750;    // pruned mode: a request waiting longer goes first
+constexpr double kExpressShare = 0.05;  // serial servers: budget of the express workers
 constexpr int kMaxStreams = 4;    // worker streams (the device serves 4 hardware queues)
 
 struct SReq {
@@ -79,7 +84,9 @@ struct SReq {
     int64_t mk = 0;        // edges of its colour subgraph (whole graph for wildcards)
     bool whole = false;    // runs on the whole graph (wildcards)
     int C = 0;             // sieve points per pass chosen at admission
+    int max_c = 1024;      // widest chunk allowed (halved after a failed allocation)
     int64_t est = 0;       // estimated device bytes at admission
+    double cost = 0;       // estimated device work (bytes moved by its subgraph build and sieve)
     int tries = 0;
     // row mode
     int chunks_left = 0, next_chunk = 0, groups_live = 0;
@@ -130,6 +137,20 @@ struct tpm_server {
     int64_t completed = 0, cancelled = 0, rejected = 0;
     double prune_ms = 0, sieve_ms = 0, extract_ms = 0;
     int inflight = 0, inflight_peak = 0;
+    int64_t trims = 0;  // pruned mode: times a worker gave its device memory back
+    double gpu_wait_ms = 0;
+    // pruned mode, serial device use (servers): one worker uses the device at a time.
+    // Worker 0 takes any request; the others ("express" workers) take only requests
+    // that fit their small share at full width.  Between two levels of a sieve, worker 0
+    // lends the device to a waiting express worker for one whole request, then takes
+    // it back before any other express request.
+    bool serial = false;
+    std::mutex dev_mu;
+    std::condition_variable dev_cv;
+    int dev_owner = -1;      // worker holding the device
+    int dev_exp_waiting = 0; // express workers waiting for it
+    bool dev_lent = false;   // worker 0 has lent it in the middle of a sieve
+    bool dev_back = false;   // the loan ended: worker 0 takes it next
     // row mode
     int W = 1, lanes = 64;
     int row_points_cap = 1024;  // widest row allowed (internal batches: the tuning's chunk)
@@ -140,6 +161,7 @@ struct tpm_server {
     // pruned mode
     int nstreams = 0;
     int64_t budget = 0, held = 0, held_peak = 0;
+    std::vector<int64_t> share;  // per worker: its share of the budget
     std::vector<int64_t> pair_counts;  // q x q edge counts by colour pair (whole graphs)
     std::vector<WorkerMem> wm;
     // memory: pools owned by the server, or borrowed from the graph (internal batches)
@@ -232,6 +254,10 @@ int64_t est_request_bytes(const Graph &G, int64_t mk, bool whole, int k, int C, 
     int64_t arena = 0;
     if (!whole)
         arena = 5 * G.m + 36 * mk + 44 * n + 12 * tiles + (int64_t(16) << 20);
+    // stored rows per kept edge: colour subgraphs of the serving and batched workloads
+    // keep the whole graph's ratio within 3 % (checked on samples); the 50 % margin
+    // leaves room on the device (smaller margins let the largest requests take
+    // 1024-point rows whose buffers filled the device and made regrowth slow)
     const double ratio = G.m ? (double)G.R / (double)G.m : 1.0;
     const int64_t R = whole ? G.R : std::min<int64_t>(mk, (int64_t)std::ceil(1.5 * ratio * (double)mk) + 1024);
     const int64_t rowb = std::max(C, 16);
@@ -266,34 +292,131 @@ void size_request(tpm_server *s, SReq &rq) {
     rq.mk = mk;
 }
 
-int preferred_chunk(int k) { return std::min(1 << k, 1024); }
-
-// Tries to admit `rq` on worker w: the largest chunk size from the preferred one down
-// to floor_c whose estimate fits beside what the other workers hold.  Caller holds
-// s->mu.
-bool admit_pruned(tpm_server *s, int w, SReq &rq, int floor_c) {
-    const Graph &G = s->g->G;
-    const int pref = preferred_chunk(rq.q.k);
-    floor_c = std::min(floor_c, pref);
-    const bool loc = rq.want_path && rq.q.k >= 2;
-    const int64_t others = s->held - s->wm[(size_t)w].accounted;
-    for (int C = pref; C >= floor_c; C >>= 1) {
-        const int64_t est = est_request_bytes(G, rq.mk, rq.whole, rq.q.k, C, loc);
-        const int64_t need = std::max(est, worker_bytes(s->wm[(size_t)w]));
-        if (others + need <= s->budget) {
-            rq.C = C;
-            rq.est = est;
-            s->held = others + need;
-            s->wm[(size_t)w].accounted = need;
-            s->held_peak = std::max(s->held_peak, s->held);
-            return true;
-        }
-    }
-    return false;
+// Device work of a request, for ordering: its subgraph build scans the parent index
+// (about 12 bytes per edge), its sieve moves about (k - 1) C bytes per kept edge and
+// sieve point.
+void cost_request(const Graph &G, SReq &rq) {
+    const int k = rq.q.k;
+    const double pts = (double)std::max(16, 1 << k);
+    rq.cost = (rq.whole ? 0.0 : 12.0 * (double)G.m) + (double)rq.mk * std::max(1, k - 1) * pts;
 }
 
+int preferred_chunk(int k) { return std::max(16, std::min(1 << k, 1024)); }
+
+// Widest chunk a request may take (halved after a failed allocation).
+int max_chunk(const tpm_server *, const SReq &rq) { return std::max(16, std::min(rq.max_c, 1024)); }
+
+// The widest chunk (a power of two of sieve points, from the preferred one down to 16)
+// whose estimated bytes fit `cap`; 0 if none does.
+int chunk_within(const tpm_server *s, const SReq &rq, int64_t cap) {
+    const Graph &G = s->g->G;
+    const bool loc = rq.want_path && rq.q.k >= 2;
+    for (int C = std::min(preferred_chunk(rq.q.k), max_chunk(s, rq)); C >= 16; C >>= 1)
+        if (est_request_bytes(G, rq.mk, rq.whole, rq.q.k, C, loc) <= cap) return C;
+    return 0;
+}
+
+bool is_express(const tpm_server *s, int w) { return s->serial && w > 0; }
+
+// Does the request fit worker 0's share of the budget (at some chunk size)?
+bool fits_share(tpm_server *s, const SReq &rq) { return chunk_within(s, rq, s->share[0]) > 0; }
+
+// Tries to admit `rq` on worker w.  Each worker owns a fixed share of the state budget,
+// so a request sized to the share always fits beside the others and no worker ever
+// waits for, or gives back, memory: it takes the widest chunk whose estimate fits the
+// share.  An express worker takes only requests that fit its share at full width.  A
+// request that does not fit a share at any chunk size runs only with every other
+// worker idle, on whatever the others do not hold.  Caller holds s->mu.
+bool admit_pruned(tpm_server *s, int w, SReq &rq) {
+    const Graph &G = s->g->G;
+    WorkerMem &me = s->wm[(size_t)w];
+    const int64_t others = s->held - me.accounted;
+    int C = chunk_within(s, rq, s->share[(size_t)w]);
+    if (is_express(s, w) && C != std::min(preferred_chunk(rq.q.k), max_chunk(s, rq))) return false;
+    if (C == 0) {
+        for (size_t i = 0; i < s->wm.size(); ++i)
+            if ((int)i != w && s->wm[i].busy) return false;
+        C = chunk_within(s, rq, s->budget - others);
+        if (C == 0) return false;
+    }
+    const bool loc = rq.want_path && rq.q.k >= 2;
+    const int64_t est = est_request_bytes(G, rq.mk, rq.whole, rq.q.k, C, loc);
+    const int64_t need = std::max(est, worker_bytes(me));
+    if (others + need > s->budget) return false;
+    rq.C = C;
+    rq.est = est;
+    s->held = others + need;
+    me.accounted = need;
+    s->held_peak = std::max(s->held_peak, s->held);
+    return true;
+}
+
+// ------------------------------------------------------------------ device token
+// Serial device use: dev_take blocks until worker w may use the device (an express
+// worker waits while a loan is being returned; worker 0 lets waiting express workers go
+// first); dev_give releases it (ending a loan); dev_lend, called by worker 0 between
+// two levels of its sieve, lends it to a waiting express worker for one request and
+// takes it back.
+void dev_take(tpm_server *s, int w) {
+    std::unique_lock<std::mutex> lk(s->dev_mu);
+    const bool exp = is_express(s, w);
+    if (exp) ++s->dev_exp_waiting;
+    s->dev_cv.wait(lk, [&] {
+        return s->stop || (s->dev_owner < 0 && (exp ? !s->dev_back : s->dev_exp_waiting == 0));
+    });
+    if (exp) --s->dev_exp_waiting;
+    if (s->stop) throw Error{TPM_ECANCELLED, "server stopping"};
+    s->dev_owner = w;
+}
+
+void dev_give(tpm_server *s) {
+    std::lock_guard<std::mutex> lk(s->dev_mu);
+    s->dev_owner = -1;
+    if (s->dev_lent) {
+        s->dev_lent = false;
+        s->dev_back = true;
+    }
+    s->dev_cv.notify_all();
+}
+
+void dev_lend(tpm_server *s, int w, hipStream_t st) {
+    {
+        std::lock_guard<std::mutex> lk(s->dev_mu);
+        if (s->dev_exp_waiting == 0) return;
+    }
+    // this worker's queued levels finish before the borrower's work starts
+    TPM_HIP(hipStreamSynchronize(st));
+    std::unique_lock<std::mutex> lk(s->dev_mu);
+    s->dev_owner = -1;
+    s->dev_lent = true;
+    s->dev_cv.notify_all();
+    s->dev_cv.wait(lk, [&] { return s->stop || (s->dev_owner < 0 && !s->dev_lent); });
+    s->dev_back = false;
+    s->dev_owner = w;
+    if (s->stop) throw Error{TPM_ECANCELLED, "server stopping"};
+}
+
+// Holds the device for a scope (serial servers only).
+struct DevHold {
+    tpm_server *s;
+    bool held = false;
+    DevHold(tpm_server *srv, int w) : s(srv) {
+        if (s->serial) {
+            dev_take(s, w);
+            held = true;
+        }
+    }
+    void release() {
+        if (held) dev_give(s);
+        held = false;
+    }
+    ~DevHold() { release(); }
+    DevHold(const DevHold &) = delete;
+    DevHold &operator=(const DevHold &) = delete;
+};
+
 // Runs one request on worker w's stream; returns its result.
-tpm_result run_pruned(tpm_server *s, WorkerMem &wmem, SReq &rq, hipStream_t st) {
+tpm_result run_pruned(tpm_server *s, int w, WorkerMem &wmem, SReq &rq, hipStream_t st) {
     const Graph &G = s->g->G;
     tpm_result r = status_result(TPM_OK);
     rq.q.multiset = rq.ms.data();
@@ -316,34 +439,61 @@ tpm_result run_pruned(tpm_server *s, WorkerMem &wmem, SReq &rq, hipStream_t st) 
     } fr{P};
     const Graph *H = &G;
     const double t0 = now_ms();
-    if (!rq.whole) {
-        std::vector<uint8_t> keep((size_t)G.q, 0);
-        for (int32_t c : rq.ms) keep[(size_t)c] = 1;
-        PruneSpec spec;
-        spec.keep_color = keep.data();
-        spec.need_times = false;
-        prune_graph(G, spec, P, wmem.arena, st);
-        P.pool = s->ppool;
-        H = &P;
-    }
-    const double t1 = now_ms();
     std::vector<uint8_t> qloc;
-    if (loc) {
-        qloc.resize((size_t)H->n);
-        r.total = vertex_localise(*H, req, qloc.data(), st, &rq.pp);
-    } else {
-        SieveResult res;
-        run_sieve(*H, req, res, st);
-        r.total = res.total;
-        rq.pp.swap(res.per_point);
+    double tg, t1, t2;
+    {
+        // serial servers use the device one request at a time: every device phase here
+        // (subgraph build, sieve) is bound by HBM bandwidth, and two requests at once
+        // measured slower than one after the other (two sieves at full serving size:
+        // capacity 7.0 -> 5.2 queries/s; a subgraph build beside a sieve: 7.0 -> 6.1);
+        // worker 0 lends the device between levels to the express workers' short requests
+        DevHold dev(s, w);
+        tg = now_ms();
+        if (!rq.whole) {
+            std::vector<uint8_t> keep((size_t)G.q, 0);
+            for (int32_t c : rq.ms) keep[(size_t)c] = 1;
+            PruneSpec spec;
+            spec.keep_color = keep.data();
+            spec.need_times = false;
+            prune_graph(G, spec, P, wmem.arena, st);
+            P.pool = s->ppool;
+            H = &P;
+        }
+        t1 = now_ms();
+        std::function<void(hipStream_t)> lend = [s, w](hipStream_t sst) { dev_lend(s, w, sst); };
+        if (s->serial && w == 0) req.between_levels = &lend;
+        if (loc) {
+            qloc.resize((size_t)H->n);
+            r.total = vertex_localise(*H, req, qloc.data(), st, &rq.pp);
+        } else {
+            SieveResult res;
+            run_sieve(*H, req, res, st);
+            r.total = res.total;
+            rq.pp.swap(res.per_point);
+        }
+        t2 = now_ms();
     }
     r.found = r.total != 0;
-    const double t2 = now_ms();
-    if (r.found && rq.want_path) extract_into(*H, rq.q, r, st, qloc.empty() ? nullptr : qloc.data());
+    if (r.found && rq.want_path) {
+        // the reverse DFS from the query's own localisation runs on the host; a fallback
+        // that sieves again takes the device
+        int64_t pe[16];
+        int32_t pv[16];
+        r.path_status = TPM_NOTFOUND;
+        if (!qloc.empty())
+            r.path_status = extract_from_vertices(*H, rq.ms.data(), rq.q.k, qloc.data(), kQuickDfsBudget, pv, pe);
+        if (r.path_status == TPM_OK) {
+            store_path_into(rq.q, pv, pe, r);
+        } else {
+            DevHold dev(s, w);
+            extract_into(*H, rq.q, r, st, nullptr);
+        }
+    }
     const double t3 = now_ms();
     std::lock_guard<std::mutex> lk(s->mu);
     s->steps++;
-    s->prune_ms += t1 - t0;
+    s->gpu_wait_ms += tg - t0;
+    s->prune_ms += t1 - tg;
     s->sieve_ms += t2 - t1;
     s->extract_ms += t3 - t2;
     return r;
@@ -368,36 +518,49 @@ void pruned_worker(tpm_server *s, int w) {
                 if (s->stop) break;
                 purge_queue(s, gone);
                 if (!gone.empty()) break;  // results are produced outside the lock
-                // admission: the oldest request that fits; later ones may overtake a
-                // request that does not fit, at most kMaxBypass times.  The oldest may
-                // take smaller chunks once it has waited that long (256 points), or any
-                // chunk size when no worker holds memory.
+                // admission: the oldest request; a request larger than one worker's
+                // share waits for the device to itself, and later requests may overtake
+                // it at most kMaxBypass times
                 bool all_idle = true;
                 for (auto &x : s->wm) all_idle &= !x.busy;
                 const bool empty_dev = all_idle && s->held == me.accounted;
-                for (auto it = s->queue.begin(); it != s->queue.end(); ++it) {
-                    SReq &c = **it;
-                    const bool head = it == s->queue.begin();
-                    const int floor_c = !head ? 1024 : empty_dev ? 16 : c.bypassed >= kMaxBypass ? 256 : 1024;
-                    if (admit_pruned(s, w, c, floor_c)) {
-                        rq = *it;
-                        s->queue.erase(it);
+                // order: the oldest first if it has waited kAgeMs, else the least
+                // device work first (short requests do not wait behind long ones; the
+                // age bound keeps long ones from waiting behind a stream of short ones)
+                std::vector<size_t> order(s->queue.size());
+                for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+                const double tnow = now_ms();
+                const bool aged = !s->queue.empty() && tnow - s->queue.front()->t_submit > kAgeMs;
+                std::stable_sort(order.begin() + (aged ? 1 : 0), order.end(), [&](size_t a, size_t b) {
+                    return s->queue[a]->cost < s->queue[b]->cost;
+                });
+                for (size_t oi = 0; oi < order.size(); ++oi) {
+                    SReq &c = *s->queue[order[oi]];
+                    const bool head = order[oi] == 0;
+                    if (admit_pruned(s, w, c)) {
+                        rq = s->queue[order[oi]];
+                        s->queue.erase(s->queue.begin() + (std::ptrdiff_t)order[oi]);
                         break;
                     }
-                    if (head) {
-                        if (c.bypassed >= kMaxBypass) break;  // nobody overtakes it now
+                    if (head && !fits_share(s, c)) {
+                        // the oldest needs the device's memory to itself: later requests
+                        // may overtake it kMaxBypass times, then nobody does
+                        if (c.bypassed >= kMaxBypass) break;
                         ++c.bypassed;
                     }
                 }
                 if (rq) break;
                 if (!s->queue.empty()) {
-                    // the oldest request does not fit: an idle worker gives its memory
+                    const bool big_head = !fits_share(s, *s->queue.front());
+                    // the oldest needs more than a share: idle workers give their memory
                     // back; with every worker idle and nothing held, it never fits
-                    if (!me.busy && worker_bytes(me) > 0 && !empty_dev) {
+                    if (big_head && !me.busy && worker_bytes(me) > 0 && !empty_dev) {
                         trim = true;
                         break;
                     }
-                    if (empty_dev) {  // not even the smallest chunk fits an idle device
+                    // nothing fits an idle device for worker 0 (which takes any
+                    // request): the oldest never will
+                    if (empty_dev && !is_express(s, w)) {
                         gone.push_back(s->queue.front());
                         s->queue.pop_front();
                         break;
@@ -421,6 +584,7 @@ void pruned_worker(tpm_server *s, int w) {
                 record_error(s, e.msg);
             }
             std::lock_guard<std::mutex> lk(s->mu);
+            s->trims++;
             s->held -= me.accounted;
             me.accounted = 0;
             s->cv.notify_all();
@@ -440,7 +604,7 @@ void pruned_worker(tpm_server *s, int w) {
         tpm_result r;
         bool requeue = false;
         try {
-            r = run_pruned(s, me, *rq, st);
+            r = run_pruned(s, w, me, *rq, st);
         } catch (const Error &e) {
             (void)hipStreamSynchronize(st);
             r = status_result(e.code);
@@ -450,6 +614,18 @@ void pruned_worker(tpm_server *s, int w) {
             (void)hipStreamSynchronize(st);
             r = status_result(TPM_EDEVICE);
             record_error(s, e.what());
+        }
+        if (!requeue && worker_bytes(me) > s->share[(size_t)w]) {
+            // after a request larger than a share: back to at most the share, so that an
+            // idle worker never holds more than its share
+            try {
+                arena_trim(me.arena);
+                workspace_trim(me.ws);
+            } catch (const Error &e) {
+                record_error(s, e.msg);
+            }
+            std::lock_guard<std::mutex> lk(s->mu);
+            s->trims++;
         }
         const int64_t actual = worker_bytes(me);
         {
@@ -461,7 +637,8 @@ void pruned_worker(tpm_server *s, int w) {
             me.accounted = actual;
             s->held_peak = std::max(s->held_peak, s->held);
             if (requeue) {
-                rq->bypassed = kMaxBypass;  // runs next, at the smallest admitted chunk
+                rq->bypassed = kMaxBypass;  // runs next, with half the chunk
+                rq->max_c = std::max(16, rq->C / 2);
                 s->queue.push_front(rq);
             }
             s->cv.notify_all();
@@ -801,7 +978,10 @@ void start_server(tpm_server *s, const tpm_graph *g, const tpm_server_config *cf
     size_t freeb = 0, totalb = 0;
     TPM_HIP(hipMemGetInfo(&freeb, &totalb));
     if (s->pruned) {
-        s->nstreams = s->cfg.streams ? s->cfg.streams : 3;
+        // servers share the device serially (worker 0 and express workers); batches run
+        // their queries on several streams at once
+        s->serial = !internal_batch;
+        s->nstreams = s->cfg.streams ? s->cfg.streams : (s->serial ? 2 : 3);
         if (G.q <= 64 && G.pcol) colour_pair_counts(G, s->pair_counts, nullptr);
         s->wm.resize((size_t)s->nstreams);
         int64_t held = 0;  // memory the borrowed worker buffers already hold
@@ -815,6 +995,13 @@ void start_server(tpm_server *s, const tpm_graph *g, const tpm_server_config *cf
         s->held = held;
         s->budget = s->cfg.state_bytes > 0 ? s->cfg.state_bytes
                                            : (int64_t)(0.85 * (double)freeb) + held;
+        s->share.assign((size_t)s->nstreams, s->budget / s->nstreams);
+        if (s->serial && s->nstreams > 1) {
+            // express workers: 5 % of the budget between them, worker 0 the rest
+            const int64_t ex = (int64_t)(kExpressShare * (double)s->budget) / (s->nstreams - 1);
+            for (int w = 1; w < s->nstreams; ++w) s->share[(size_t)w] = ex;
+            s->share[0] = s->budget - ex * (s->nstreams - 1);
+        }
         for (int w = 0; w < s->nstreams; ++w) s->threads.emplace_back(pruned_worker, s, w);
         return;
     }
@@ -844,6 +1031,10 @@ void stop_server(tpm_server *s) {
     }
     s->cv.notify_all();
     s->ext_cv.notify_all();
+    {
+        std::lock_guard<std::mutex> lk(s->dev_mu);
+        s->dev_cv.notify_all();
+    }
     for (auto &t : s->threads)
         if (t.joinable()) t.join();
     (void)hipDeviceSynchronize();
@@ -876,6 +1067,7 @@ tpm_status submit(tpm_server *s, const tpm_query &q, uint64_t *ticket) {
     rq->want_path = q.want_path || s->cfg.extract_paths;
     if (s->pruned) {
         size_request(s, *rq);
+        cost_request(s->g->G, *rq);
         // the smallest state this request can run with (16-point rows, no other request
         // holding memory) must fit the budget
         const int64_t least = est_request_bytes(s->g->G, rq->mk, rq->whole, rq->q.k,
@@ -1022,6 +1214,8 @@ tpm_status tpm_server_stats_get(tpm_server *s, tpm_server_stats *out) {
         out->inflight_peak = s->inflight_peak;
         out->budget_bytes = s->budget;
         out->held_bytes_peak = s->held_peak;
+        out->trims = s->trims;
+        out->gpu_wait_ms = s->gpu_wait_ms;
         return TPM_OK;
     });
 }

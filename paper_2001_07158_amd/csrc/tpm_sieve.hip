@@ -511,6 +511,62 @@ __global__ void __launch_bounds__(1024) k_level(LevelParams P) {
 // value carries into the next step.  Tiles, look-back and the carry fix-up of
 // continuation pieces are those of k_level.
 // ---------------------------------------------------------------------------------
+// One step of the inclusive segmented XOR-scan, (f, v) <- (f | f', f ? v : v ^ v'),
+// with (f', v') read through DPP control CTRL: a source outside the lane's 16-lane row,
+// or a lane that ROWMASK leaves out, reads (0, 0), the identity of the step.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ void seg_step_dpp(uint32_t (&v)[4], uint32_t &f) {
+    uint32_t vo[4];
+#pragma unroll
+    for (int w = 0; w < 4; ++w)
+        vo[w] = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v[w], CTRL, ROWMASK, 0xF, true);
+    const uint32_t fo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)f, CTRL, ROWMASK, 0xF, true);
+#pragma unroll
+    for (int w = 0; w < 4; ++w) v[w] = f ? v[w] : (v[w] ^ vo[w]);
+    f |= fo;
+}
+
+// The same step across 16-lane rows for slots of LP lanes: a lane of a receiving row
+// (ROWS: bit r set for row r) reads the last slot of row LASTROW of its own row's
+// predecessor (LASTROW = -1: the row just below), lane sub of that slot, by shuffle.
+template <int LP, int ROWS, int LASTROW>
+__device__ __forceinline__ void seg_step_rows(uint32_t (&v)[4], uint32_t &f, int lane) {
+    const int row = lane >> 4, sub = lane % LP;
+    const int srow = LASTROW >= 0 ? LASTROW : row - 1;
+    const int src = ((srow < 0 ? 0 : srow) << 4) + 16 - LP + sub;
+    uint32_t vo[4];
+#pragma unroll
+    for (int w = 0; w < 4; ++w) vo[w] = __shfl(v[w], src);
+    const uint32_t fo = __shfl(f, src);
+    if ((ROWS >> row) & 1) {
+#pragma unroll
+        for (int w = 0; w < 4; ++w) v[w] = f ? v[w] : (v[w] ^ vo[w]);
+        f |= fo;
+    }
+}
+
+// Inclusive segmented XOR-scan over the E = 64 / LP slots of a step (slot s holds lanes
+// [s LP, s LP + LP)), f = 1 at a slot that starts a segment.  Within each 16-lane row:
+// DPP row shifts of LP, 2 LP, .. 8 lanes.  Then across rows, as the last slot of a row
+// holds the row's running value: rows 1 and 3 add the last slot of rows 0 and 2, then
+// rows 2 and 3 add the last slot of row 1 (now rows 0-1): DPP row broadcasts for LP = 1
+// (lane 15, lane 31), lane shuffles for wider slots.
+template <int LP>
+__device__ __forceinline__ void seg_scan(uint32_t (&v)[4], uint32_t &f, int lane) {
+    static_assert(LP == 1 || LP == 2 || LP == 4 || LP == 8, "slots of 1..8 lanes");
+    if constexpr (LP == 1) seg_step_dpp<0x111, 0xF>(v, f);
+    if constexpr (LP <= 2) seg_step_dpp<0x110 + 2, 0xF>(v, f);
+    if constexpr (LP <= 4) seg_step_dpp<0x110 + 4, 0xF>(v, f);
+    if constexpr (LP <= 8) seg_step_dpp<0x110 + 8, 0xF>(v, f);
+    if constexpr (LP == 1) {
+        seg_step_dpp<0x142, 0xA>(v, f);  // row_bcast:15 into rows 1 and 3
+        seg_step_dpp<0x143, 0xC>(v, f);  // row_bcast:31 into rows 2 and 3
+    } else {
+        seg_step_rows<LP, 0xA, -1>(v, f, lane);
+        seg_step_rows<LP, 0xC, 1>(v, f, lane);
+    }
+}
+
 template <int LP, bool FIN>
 __global__ void __launch_bounds__(1024) k_narrow(LevelParams P) {
     constexpr int E = 64 / LP;           // positions per step
@@ -647,22 +703,10 @@ __global__ void __launch_bounds__(1024) k_narrow(LevelParams P) {
                 } else {
                     // inclusive segmented XOR-scan over the slots of this step
                     const int32_t dprev = __shfl_up(d, LP);
-                    bool f = valid && (slot == 0 ? d != run_d : d != dprev);
+                    uint32_t fl = (valid && (slot == 0 ? d != run_d : d != dprev)) ? 1u : 0u;
                     uint32_t v[4] = {c[0], c[1], c[2], c[3]};
-#pragma unroll
-                    for (int off = 1; off < E; off <<= 1) {
-                        uint32_t vo[4];
-#pragma unroll
-                        for (int w = 0; w < 4; ++w) vo[w] = __shfl_up(v[w], off * LP);
-                        const int fo = __shfl_up((int)f, off * LP);
-                        if (slot >= off) {
-                            if (!f) {
-#pragma unroll
-                                for (int w = 0; w < 4; ++w) v[w] ^= vo[w];
-                            }
-                            f = f || (fo != 0);
-                        }
-                    }
+                    seg_scan<LP>(v, fl, lane);
+                    const bool f = fl != 0;
                     // slots with no segment start at or below them continue run_d
                     uint32_t a[4];
 #pragma unroll
@@ -1785,7 +1829,10 @@ void enqueue_chunks(const Graph &G, int32_t k, uint64_t seed, int rowb, int64_t 
         k_xt<<<grid_for((int64_t)G.n * ((rowb + 15) / 16)), 256, 0, st>>>(G.n, k, rowb, rowb, 0,
                                                                            (uint32_t)base, B.z, B.xt);
         for (int l = 2; l <= k; ++l) {
-            if (req) check_cancel(*req, st);
+            if (req) {
+                check_cancel(*req, st);
+                if (req->between_levels) (*req->between_levels)(st);
+            }
             const bool fin = (l == k);
             LevelParams P{};
             P.gidx = (l == 2) ? G.psrc : G.gsrc;

@@ -76,7 +76,8 @@ class tpm_server_stats(ctypes.Structure):
                 ("extract_ms", ctypes.c_double), ("cancelled", ctypes.c_int64),
                 ("rejected", ctypes.c_int64), ("streams", ctypes.c_int32),
                 ("inflight_peak", ctypes.c_int32), ("budget_bytes", ctypes.c_int64),
-                ("held_bytes_peak", ctypes.c_int64)]
+                ("held_bytes_peak", ctypes.c_int64), ("trims", ctypes.c_int64),
+                ("gpu_wait_ms", ctypes.c_double)]
 
 
 class tpm_query(ctypes.Structure):
@@ -156,6 +157,7 @@ _sig("tpm_server_destroy", None, [_vp])
 _sig("tpm_server_stats_get", ctypes.c_int32, [_vp, ctypes.POINTER(tpm_server_stats)])
 _sig("tpm_profile_enable", ctypes.c_int32, [ctypes.c_int32])
 _sig("tpm_profile_read", ctypes.c_int32, [ctypes.POINTER(tpm_kernel_time), ctypes.c_int32, _i32p])
+_sig("tpm_stream_read", ctypes.c_int32, [_vp, ctypes.c_int64, _vp, _vp])
 _sig("tpm_last_error", ctypes.c_char_p, [])
 _sig("tpm_version", ctypes.c_char_p, [])
 
@@ -169,7 +171,8 @@ EXPORTED = ["tpm_graph_create", "tpm_graph_create_ex", "tpm_graph_destroy", "tpm
             "tpm_server_create", "tpm_server_submit", "tpm_server_poll", "tpm_server_cancel",
             "tpm_server_destroy",
             "tpm_server_stats_get", "tpm_rainbow_decide",
-            "tpm_profile_enable", "tpm_profile_read", "tpm_last_error", "tpm_version"]
+            "tpm_profile_enable", "tpm_profile_read", "tpm_stream_read", "tpm_last_error",
+            "tpm_version"]
 
 
 class TpmError(RuntimeError):
@@ -292,6 +295,11 @@ def tpm_sieve_noalloc(h, multiset, seed, total, per_point=None, error_flags=None
     _check(_lib.tpm_sieve_noalloc(h, M.ctypes.data_as(_i32p), int(M.shape[0]), int(seed) & (2**64 - 1),
                                   _dev_ptr(per_point), _dev_ptr(total), _dev_ptr(error_flags),
                                   _stream_handle(stream)))
+
+
+def tpm_stream_read(src, nbytes, out, stream=None) -> None:
+    """Streaming read of nbytes of device memory (src, out: tensors or addresses)."""
+    _check(_lib.tpm_stream_read(_dev_ptr(src), int(nbytes), _dev_ptr(out), _stream_handle(stream)))
 
 
 def tpm_decide(h, multiset, seed, reps=1) -> bool:
