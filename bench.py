@@ -30,7 +30,10 @@ METRIC = "GF(2^8) sieve edge-updates/s (m·k·2^k) at k=10; HBM GB/s; p50/p99 qu
 HBM_PEAK_GBPS = 8000.0
 # committed rocprofv3 PMC summaries of the middle-level kernel, by sieve points per row
 PMC_FILES = {1024: os.path.join(ROOT, "profiles", "k10_level_middle_pmc.txt"),
-             256: os.path.join(ROOT, "profiles", "k10_narrow_c256_middle_pmc.txt")}
+             256: os.path.join(ROOT, "profiles", "k10_narrow_c256_middle_pmc.txt"),
+             64: os.path.join(ROOT, "profiles", "k10_narrow_c64_middle_pmc.txt"),
+             32: os.path.join(ROOT, "profiles", "k10_narrow_c32_middle_pmc.txt"),
+             16: os.path.join(ROOT, "profiles", "k10_narrow_c16_middle_pmc.txt")}
 KERNEL_SRC = os.path.join(ROOT, "paper_2001_07158_amd", "csrc", "tpm_sieve.hip")
 
 
@@ -187,6 +190,16 @@ def main() -> int:
     else:
         alg = st["gathers"] * float(C) + struct
     achieved = alg / (avg_ms / 1e3) / 1e9
+    # each read request to HBM moves a 128-byte line on this GPU (rocprofv3: a 1 GiB
+    # streaming read issues 2^23 TCC_EA0_RDREQ), so a random gather of a row shorter than
+    # 128 bytes moves 128 bytes: the least traffic a launch can have
+    line_b = 128.0
+    if dom == "middle":
+        xfer = st["gathers"] * max(float(C), line_b) + st["rows"] * float(C) + struct
+    elif dom == "level2":
+        xfer = g.m * max(float(C), line_b) + st["rows"] * float(C) + struct
+    else:
+        xfer = st["gathers"] * max(float(C), line_b) + struct
     traffic = read_traffic(C) if dom == "middle" else None
     # whole-query algorithmic bytes (all levels, all chunks)
     nchunks = max(1, (1 << k) // C)
@@ -229,6 +242,11 @@ def main() -> int:
             "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
             "alg_bytes_per_launch": alg, "avg_launch_ms": avg_ms, "launches": len(kinds.get(dom, [])),
+            # the same with every gather charged at least one 128-byte line (rows of
+            # fewer than 128 points): achieved and fraction of peak on that count
+            "min_transfer_bytes_per_launch": xfer,
+            "achieved_min_transfer": xfer / (avg_ms / 1e3) / 1e9,
+            "frac_min_transfer": xfer / (avg_ms / 1e3) / 1e9 / HBM_PEAK_GBPS,
             "kernel_hash": kernel_hash(C),
         },
         "cpu_baseline": None,

@@ -17,7 +17,7 @@ def test_more_than_one_gpu_is_refused():
     assert r.stdout == ""
 
 
-@pytest.mark.parametrize("points", [1024, 256])
+@pytest.mark.parametrize("points", [1024, 256, 64, 32, 16])
 def test_kernel_hash_and_committed_traffic(points):
     """The committed PMC summaries were taken on the current level-kernel source."""
     sys.path.insert(0, ROOT)
