@@ -13,7 +13,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libtpm.so")
+# TPM_LIBRARY: path of another build of the library (the host-sanitizer build of the tests)
+LIB_PATH = os.environ.get("TPM_LIBRARY") or os.path.join(_HERE, "libtpm.so")
 
 TPM_OK = 0
 TPM_NOTFOUND = 1
