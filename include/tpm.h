@@ -161,7 +161,11 @@ tpm_status tpm_graph_retile(tpm_graph *g, int32_t tile_edges);
  * 2^k < 256 the chunk is 2^k), after one untimed run per pair, and checks that
  * every candidate gives the same per-point bytes.  The fastest tile size is applied
  * to the graph (as tpm_graph_retile) and reported with the fastest chunk; pass
- * that chunk in tpm_tuning.  Same concurrency rule as tpm_graph_retile.
+ * that chunk in tpm_tuning.  Same concurrency rule as tpm_graph_retile.  Results are
+ * cached by (GPU architecture, k, floor(log2 m), floor(log2 n)) for the process, and in
+ * the file named by the environment variable TPM_AUTOTUNE_CACHE when it is set (read
+ * at the first call, appended to on each new result); a cached result is applied
+ * without timing (cached = 1, no candidates).
  * Errors: TPM_EINVAL (k outside 2..16), TPM_EDEVICE (a candidate disagreed). */
 typedef struct {
     int32_t tile_edges;      /* chosen and applied */
@@ -170,6 +174,7 @@ typedef struct {
     int32_t cand_tile[12];
     int32_t cand_chunk[12];
     double cand_rate[12];    /* edge-level-point updates per second: m (k-1) C / time */
+    int32_t cached;          /* 1: taken from the autotune cache, nothing timed */
 } tpm_autotune_report;
 tpm_status tpm_autotune(tpm_graph *g, int32_t k, uint64_t seed, tpm_autotune_report *out);
 

@@ -6,12 +6,15 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
 #include <functional>
 #include <map>
 #include <mutex>
 #include <set>
 #include <string>
+#include <tuple>
 #include <unordered_map>
 
 #include "tpm_internal.h"
@@ -672,6 +675,84 @@ double now_ms() {
     return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
 }
 
+// ------------------------------------------------------------------ autotune cache
+// Results of tpm_autotune by (GPU architecture, k, log2 m, log2 n): one process-wide
+// table, also kept in the file named by TPM_AUTOTUNE_CACHE when that is set (one entry
+// a line: arch k log2m log2n tile chunk; read once, appended to on every new entry).
+struct TuneKey {
+    std::string arch;
+    int k = 0, mlog = 0, nlog = 0;
+    bool operator<(const TuneKey &o) const {
+        return std::tie(arch, k, mlog, nlog) < std::tie(o.arch, o.k, o.mlog, o.nlog);
+    }
+};
+struct TuneVal {
+    int tile = 0, chunk = 0;
+};
+
+std::mutex g_tune_mu;
+std::map<TuneKey, TuneVal> g_tune;
+bool g_tune_loaded = false;
+
+int log2_floor(int64_t v) {
+    int b = 0;
+    while (v > 1) {
+        v >>= 1;
+        ++b;
+    }
+    return b;
+}
+
+TuneKey tune_key(const Graph &G, int k) {
+    hipDeviceProp_t prop{};
+    TPM_HIP(hipGetDeviceProperties(&prop, G.device));
+    TuneKey key;
+    key.arch = prop.gcnArchName;
+    key.arch = key.arch.substr(0, key.arch.find(':'));  // gfx950, without feature flags
+    key.k = k;
+    key.mlog = log2_floor(std::max<int64_t>(1, G.m));
+    key.nlog = log2_floor(std::max<int64_t>(1, G.n));
+    return key;
+}
+
+const char *tune_file() {
+    const char *f = std::getenv("TPM_AUTOTUNE_CACHE");
+    return (f && *f) ? f : nullptr;
+}
+
+// caller holds g_tune_mu
+void tune_load() {
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char *f = tune_file();
+    if (!f) return;
+    std::ifstream in(f);
+    TuneKey key;
+    TuneVal val;
+    while (in >> key.arch >> key.k >> key.mlog >> key.nlog >> val.tile >> val.chunk)
+        if (val.tile >= 1 && val.tile <= 4096 && val.chunk >= 4) g_tune[key] = val;
+}
+
+bool tune_lookup(const TuneKey &key, TuneVal &val) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_load();
+    auto it = g_tune.find(key);
+    if (it == g_tune.end()) return false;
+    val = it->second;
+    return true;
+}
+
+void tune_store(const TuneKey &key, const TuneVal &val) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_load();
+    g_tune[key] = val;
+    if (const char *f = tune_file()) {
+        std::ofstream o(f, std::ios::app);
+        o << key.arch << ' ' << key.k << ' ' << key.mlog << ' ' << key.nlog << ' ' << val.tile << ' '
+          << val.chunk << '\n';
+    }
+}
+
 // Streaming read for counter calibration: every 16-byte word once (grid-stride), XOR
 // of the words reduced per wave, one atomic per wave.
 __global__ void k_stream_read(const uint4 *src, int64_t words, unsigned long long *out) {
@@ -912,6 +993,15 @@ tpm_status tpm_autotune(tpm_graph *g, int32_t k, uint64_t seed, tpm_autotune_rep
         DeviceScope ds(g->G.device);
         Graph &G = g->G;
         std::memset(out, 0, sizeof(*out));
+        const TuneKey key = tune_key(G, k);
+        TuneVal hit;
+        if (tune_lookup(key, hit)) {
+            retile_graph(G, hit.tile);
+            out->tile_edges = hit.tile;
+            out->chunk = hit.chunk;
+            out->cached = 1;
+            return TPM_OK;
+        }
         int32_t M[16];
         for (int i = 0; i < k; ++i) M[i] = i % G.q;
         const int64_t npts = int64_t(1) << k;
@@ -959,6 +1049,7 @@ tpm_status tpm_autotune(tpm_graph *g, int32_t k, uint64_t seed, tpm_autotune_rep
                 }
             }
             retile_graph(G, out->tile_edges);
+            tune_store(key, TuneVal{out->tile_edges, out->chunk});
         } catch (...) {
             try {
                 retile_graph(G, orig_T);

@@ -67,7 +67,8 @@ class tpm_tuning(ctypes.Structure):
 class tpm_autotune_report(ctypes.Structure):
     _fields_ = [("tile_edges", ctypes.c_int32), ("chunk", ctypes.c_int32),
                 ("ncand", ctypes.c_int32), ("cand_tile", ctypes.c_int32 * 12),
-                ("cand_chunk", ctypes.c_int32 * 12), ("cand_rate", ctypes.c_double * 12)]
+                ("cand_chunk", ctypes.c_int32 * 12), ("cand_rate", ctypes.c_double * 12),
+                ("cached", ctypes.c_int32)]
 
 
 class tpm_server_stats(ctypes.Structure):
@@ -469,7 +470,7 @@ def tpm_graph_retile(h, tile_edges) -> None:
 def tpm_autotune(h, k, seed=1) -> dict:
     rep = tpm_autotune_report()
     _check(_lib.tpm_autotune(h, int(k), int(seed) & (2**64 - 1), ctypes.byref(rep)))
-    return {"tile_edges": rep.tile_edges, "chunk": rep.chunk,
+    return {"tile_edges": rep.tile_edges, "chunk": rep.chunk, "cached": bool(rep.cached),
             "candidates": [{"tile_edges": rep.cand_tile[i], "chunk": rep.cand_chunk[i],
                             "rate": rep.cand_rate[i]} for i in range(rep.ncand)]}
 

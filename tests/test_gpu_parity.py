@@ -3,6 +3,7 @@
 All sieve values are exact GF(2^8) elements, so the bar is equality of every
 per-point byte (and of the per-edge localisation where it is requested)."""
 
+import os
 import sys
 
 import numpy as np
@@ -270,7 +271,36 @@ def test_autotune_applies_a_candidate_and_keeps_results(tpm, k):
     Gf.close()
     pp, _ = Gd.sieve(M, 3, chunk=rep["chunk"])
     assert np.array_equal(pp, oracle.sieve(g, M, 3))
+    # the same key (architecture, k, log2 m, log2 n) is served from the cache
+    Gd.retile(7)
+    again = Gd.autotune(k, seed=6)
+    assert again["cached"] and not again["candidates"]
+    assert (again["tile_edges"], again["chunk"]) == (rep["tile_edges"], rep["chunk"])
+    assert np.array_equal(Gd.sieve(M, 3, chunk=again["chunk"])[0], pp)
     Gd.close()
+
+
+def test_autotune_cache_file(tmp_path):
+    """TPM_AUTOTUNE_CACHE keeps results across processes: a second process reads the
+    first one's entry and times nothing."""
+    import subprocess
+    import sys
+    cache = tmp_path / "tune.txt"
+    code = ("import sys; sys.path.insert(0, %r); from synth import graphs as G; "
+            "from paper_2001_07158_amd import tpm; "
+            "g = G.chung_lu_graph(3000, 30000, 2.5, 50, 4, 8); "
+            "Gd = tpm.Graph.from_temporal(g); r = Gd.autotune(6, seed=2); "
+            "print(int(r['cached']), r['tile_edges'], r['chunk']); Gd.close()"
+            % os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    env = dict(os.environ, TPM_AUTOTUNE_CACHE=str(cache))
+    say("case autotune cache file")
+    out1 = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=120)
+    assert out1.returncode == 0, out1.stderr[-2000:]
+    c1, t1, ch1 = out1.stdout.split()[-3:]
+    assert c1 == "0" and len(cache.read_text().splitlines()) == 1
+    out2 = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=120)
+    assert out2.returncode == 0, out2.stderr[-2000:]
+    assert out2.stdout.split()[-3:] == ["1", t1, ch1]
 
 
 @pytest.mark.timeout(600)
