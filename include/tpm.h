@@ -500,6 +500,10 @@ typedef struct {
                               (after a request larger than its share of the budget) */
     double gpu_wait_ms;    /* pruned mode: time workers waited for the device (one
                               request uses it at a time; summed) */
+    int32_t queued;        /* requests waiting for admission now */
+    int32_t queued_peak;   /* most requests waiting for admission at once */
+    int32_t inflight;      /* requests admitted and not finished now */
+    int32_t pad;
 } tpm_server_stats;
 tpm_status tpm_server_stats_get(tpm_server *s, tpm_server_stats *out);
 

@@ -137,6 +137,7 @@ struct tpm_server {
     int64_t completed = 0, cancelled = 0, rejected = 0;
     double prune_ms = 0, sieve_ms = 0, extract_ms = 0;
     int inflight = 0, inflight_peak = 0;
+    int queued_peak = 0;  // most requests waiting for admission at once
     int64_t trims = 0;  // pruned mode: times a worker gave its device memory back
     double gpu_wait_ms = 0;
     // pruned mode, serial device use (servers): one worker uses the device at a time.
@@ -1089,6 +1090,7 @@ tpm_status submit(tpm_server *s, const tpm_query &q, uint64_t *ticket) {
         if (ticket) *ticket = rq->ticket;
         s->live[rq->ticket] = rq;
         s->queue.push_back(rq);
+        s->queued_peak = std::max(s->queued_peak, (int)s->queue.size());
     }
     s->cv.notify_all();
     return TPM_OK;
@@ -1215,6 +1217,9 @@ tpm_status tpm_server_stats_get(tpm_server *s, tpm_server_stats *out) {
         out->budget_bytes = s->budget;
         out->held_bytes_peak = s->held_peak;
         out->trims = s->trims;
+        out->queued = (int32_t)s->queue.size();
+        out->queued_peak = s->queued_peak;
+        out->inflight = s->inflight;
         out->gpu_wait_ms = s->gpu_wait_ms;
         return TPM_OK;
     });

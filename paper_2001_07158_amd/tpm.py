@@ -79,7 +79,8 @@ class tpm_server_stats(ctypes.Structure):
                 ("rejected", ctypes.c_int64), ("streams", ctypes.c_int32),
                 ("inflight_peak", ctypes.c_int32), ("budget_bytes", ctypes.c_int64),
                 ("held_bytes_peak", ctypes.c_int64), ("trims", ctypes.c_int64),
-                ("gpu_wait_ms", ctypes.c_double)]
+                ("gpu_wait_ms", ctypes.c_double), ("queued", ctypes.c_int32),
+                ("queued_peak", ctypes.c_int32), ("inflight", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 class tpm_query(ctypes.Structure):

@@ -187,6 +187,8 @@ def test_pruned_server_matches_oracle(tpm, graph, streams):
     assert st["completed"] == len(qs) and st["steps"] == len(qs) and st["streams"] == streams
     assert st["prune_ms"] > 0 and st["sieve_ms"] > 0 and st["row_points"] == 0
     assert 1 <= st["inflight_peak"] <= streams
+    # queue metrics: the burst waited in the queue; all drained at the end
+    assert st["queued_peak"] >= 1 and st["queued"] == 0 and st["inflight"] == 0
     for q, r in zip(qs, res):
         k = len(q["multiset"])
         if r["found"] and k >= 2:
