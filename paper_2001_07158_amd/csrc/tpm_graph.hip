@@ -103,12 +103,115 @@ __global__ void k_inptr(int64_t m, int32_t n, const int32_t *pdst, int32_t *inpt
     for (int32_t u = lo; u <= hi; ++u) inptr[u] = (int32_t)p;
 }
 
+// ---- Position bitmaps with rank, in records of 128 bytes (one memory transfer): word
+// 0 holds the record's base (set bits in the records before it), words 1..31 the flags
+// of 992 positions (bit j of word 1 + i is position 992 r + 32 i + j).  rank(x), the
+// number of set bits below x, then costs one record read; the structure takes m / 7.75
+// bytes, where an int per position (exclusive counts) takes m x 4 and a scan to build.
+constexpr int64_t kRecPos = 992;
+
+int64_t rank_recs(int64_t m) { return (m + kRecPos - 1) / kRecPos; }
+
+__device__ __forceinline__ int64_t rec_word(int64_t x) {
+    const int64_t r = x / kRecPos;
+    return r * 32 + 1 + ((x - r * kRecPos) >> 5);
+}
+
+__device__ __forceinline__ bool bit_at(const uint32_t *rec, int64_t x) {
+    return (rec[rec_word(x)] >> ((x % kRecPos) & 31)) & 1u;
+}
+
+// Set bits below x, 0 <= x <= the bitmap's length (bits past the length are zero);
+// total: the number of all set bits (read only for x at the end of the last record).
+__device__ __forceinline__ int32_t bit_rank(const uint32_t *rec, int64_t nr, const int32_t *total,
+                                            int64_t x) {
+    const int64_t r = x / kRecPos;
+    if (r >= nr) return *total;
+    const int32_t o = (int32_t)(x - r * kRecPos);
+    const int k = o >> 5, j = o & 31;
+    const uint4 *w4 = (const uint4 *)(rec + r * 32);
+    int32_t base = 0, c = 0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const uint4 v = w4[i];
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int wi = 4 * i + t;
+            if (wi == 0) {
+                base = (int32_t)w[t];
+            } else {
+                const int bi = wi - 1;
+                const uint32_t keep = bi < k ? 0xFFFFFFFFu : (bi == k ? (uint32_t)((1ull << j) - 1ull) : 0u);
+                c += __popc(w[t] & keep);
+            }
+        }
+    }
+    return base + c;
+}
+
+// Exclusive rank of this thread's flag within its block of 256 threads.  Every thread
+// of the block must call it.
+__device__ __forceinline__ int32_t block_rank(bool f) {
+    __shared__ int32_t wc[4];
+    const uint64_t b = __ballot(f);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) wc[wv] = __popcll(b);
+    __syncthreads();
+    int32_t r = __popcll(b & ((1ull << lane) - 1ull));
+    for (int i = 0; i < wv; ++i) r += wc[i];
+    return r;
+}
+
+// Blocks of 256 threads over quarters of records: block b covers positions 992 (b / 4) +
+// 256 (b % 4) + t, t < 256 (the last quarter has 224).  The rank of the block's first
+// position among the set bits: the record's base plus the words of the quarters before.
+__device__ __forceinline__ int32_t quarter_base(const uint32_t *rec) {
+    const int64_t r = blockIdx.x >> 2;
+    const int qq = blockIdx.x & 3;
+    const uint32_t *w = rec + r * 32;
+    int32_t c = (int32_t)w[0];
+    for (int i = 1; i <= 8 * qq; ++i) c += __popc(w[i]);
+    return c;
+}
+
+__device__ __forceinline__ int64_t quarter_pos() {
+    return (int64_t)(blockIdx.x >> 2) * kRecPos + 256 * (blockIdx.x & 3) + threadIdx.x;
+}
+
+__device__ __forceinline__ bool quarter_in(int64_t m, int64_t p) {
+    return 256 * (blockIdx.x & 3) + threadIdx.x < kRecPos && p < m;
+}
+
+// Records written one wave per record: lane l < 31 gives word 1 + l (the flags of
+// positions 992 r + 32 l ... + 31); the wave writes the 31 words and the record's count
+// (and the zero count past the last record).  Word 0 (the base) is written by k_put_base
+// after the scan of the counts.
+__device__ __forceinline__ void put_record(uint32_t word, int lane, int64_t r, uint32_t *rec,
+                                           int32_t *cnt, int64_t nr) {
+    if (lane < 31) rec[r * 32 + 1 + lane] = word;
+    int32_t c = __popc(word);
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) c += __shfl_xor(c, off);
+    if (lane == 0) {
+        cnt[r] = c;
+        if (r == nr - 1) cnt[nr] = 0;
+    }
+}
+
+// word 0 of each record: its base, from the exclusive scan of the counts
+__global__ void k_put_base(int64_t nr, const int32_t *base, uint32_t *rec) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < nr) rec[r * 32] = (uint32_t)base[r];
+}
+
 // gpos[p] = last position q of src's in-list that arrived by the departure of p minus
 // the delay of src (plain problem: arrival = departure = tau, delay 1, so tau[q] <
-// tau[p]), or -1.  pdep, vdelay nullable.
+// tau[p]), or -1; needed[q] = 1 (every writer stores the same value).  pdep, vdelay
+// nullable.
 __global__ void k_gpos(int64_t m, const int32_t *psrc, const int32_t *ptau, const int32_t *pdep,
                        const int32_t *vdelay, const int32_t *inptr, int32_t *gpos,
-                       int32_t *needed) {
+                       uint8_t *needed) {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= m) return;
     int32_t v = psrc[p];
@@ -120,16 +223,48 @@ __global__ void k_gpos(int64_t m, const int32_t *psrc, const int32_t *ptau, cons
     }
     int32_t q = (lo > base) ? lo - 1 : -1;
     gpos[p] = q;
-    if (q >= 0) needed[q] = 1;  // every writer stores the same value
+    if (q >= 0) needed[q] = 1;
 }
 
-__global__ void k_rows(int64_t m, const int32_t *gpos, const int32_t *needed,
-                       const int32_t *rowof, int32_t *orow, int32_t *gsrc) {
-    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= m) return;
-    orow[p] = needed[p] ? rowof[p] : -1;
-    int32_t q = gpos[p];
-    gsrc[p] = q >= 0 ? rowof[q] : -1;
+// Rank records of m byte flags, one wave per record (blocks of 256 = 4 records)
+__global__ void __launch_bounds__(256) k_pack(int64_t m, int64_t nr, const uint8_t *flag,
+                                              uint32_t *rec, int32_t *cnt) {
+    const int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (r >= nr) return;
+    const int64_t p0 = r * kRecPos + 32 * (int64_t)lane;
+    uint32_t w = 0;
+    if (lane < 31 && p0 < m) {
+        if (p0 + 32 <= m) {
+            const uint4 *f4 = (const uint4 *)(flag + p0);
+            const uint4 a = f4[0], b = f4[1];
+            const uint32_t v[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if ((v[i] >> (8 * j)) & 0xFFu) w |= 1u << (4 * i + j);
+        } else {
+            for (int j = 0; p0 + j < m; ++j)
+                if (flag[p0 + j]) w |= 1u << j;
+        }
+    }
+    put_record(w, lane, r, rec, cnt, nr);
+}
+
+// Rows are the needed positions, numbered in CSR order: orow[p] = rank of p among them
+// (or -1), gsrc[p] = the row that p reads (or -1).  Blocks of 256 over record quarters.
+__global__ void __launch_bounds__(256) k_rows(int64_t m, const int32_t *gpos, const uint32_t *needed,
+                                              int64_t nr, const int32_t *total, int32_t *orow,
+                                              int32_t *gsrc) {
+    const int64_t p = quarter_pos();
+    const bool in = quarter_in(m, p);
+    const bool f = in && bit_at(needed, p);
+    const int32_t r = quarter_base(needed) + block_rank(f);
+    if (!in) return;
+    orow[p] = f ? r : -1;
+    const int32_t q = gpos[p];
+    gsrc[p] = q >= 0 ? bit_rank(needed, nr, total, q) : -1;
 }
 
 __global__ void k_count_nonneg(int64_t m, const int32_t *a, unsigned long long *out) {
@@ -174,47 +309,84 @@ __device__ __forceinline__ bool vbit(const uint32_t *vbits, int32_t u) {
 
 // (cut_in: a vertex whose in-edges go, cut_out: one whose out-edges go; -1 for none;
 // parr: arrival times, kept up to tcut)
-__global__ void k_keep(int64_t m, const int32_t *psrc, const int32_t *pdst, const uint32_t *vbits,
-                       const int32_t *ptime, const int32_t *ts, int32_t nts, int32_t cut_in,
-                       int32_t cut_out, const int32_t *parr, int32_t tcut, uint8_t *keep) {
-    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= m) return;
-    const int32_t s = psrc[p], d = pdst[p];
-    bool k = vbit(vbits, s) && vbit(vbits, d) && d != cut_in && s != cut_out && parr[p] <= tcut;
-    if (k && ts) {
-        const int32_t t = ptime[p];
-        int32_t a = 0, b = nts;
-        while (a < b) {
-            const int32_t mid = (a + b) >> 1;
-            if (ts[mid] < t) a = mid + 1;
-            else b = mid;
-        }
-        k = a < nts && ts[a] == t;
+__device__ __forceinline__ bool time_in(const int32_t *ts, int32_t nts, int32_t t) {
+    int32_t a = 0, b = nts;
+    while (a < b) {
+        const int32_t mid = (a + b) >> 1;
+        if (ts[mid] < t) a = mid + 1;
+        else b = mid;
     }
-    keep[p] = k ? 1 : 0;
+    return a < nts && ts[a] == t;
+}
+
+// The kept positions as rank records with their counts, one wave per record (blocks of
+// 256 = 4 records), lane l < 31 for the 32 positions of word 1 + l
+__global__ void __launch_bounds__(256) k_keep(int64_t m, int64_t nr, const int32_t *psrc,
+                                              const int32_t *pdst, const uint32_t *vbits,
+                                              const int32_t *ptime, const int32_t *ts, int32_t nts,
+                                              int32_t cut_in, int32_t cut_out, const int32_t *parr,
+                                              int32_t tcut, uint32_t *keep, int32_t *kcnt) {
+    const int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (r >= nr) return;
+    const int64_t p0 = r * kRecPos + 32 * (int64_t)lane;
+    uint32_t w = 0;
+    if (lane < 31)
+        for (int j = 0; j < 32 && p0 + j < m; ++j) {
+            const int64_t p = p0 + j;
+            const int32_t s = psrc[p], d = pdst[p];
+            bool k = vbit(vbits, s) && vbit(vbits, d) && d != cut_in && s != cut_out && parr[p] <= tcut;
+            if (k && ts) k = time_in(ts, nts, ptime[p]);
+            if (k) w |= 1u << j;
+        }
+    put_record(w, lane, r, keep, kcnt, nr);
 }
 
 // k_keep for a colour set only, from the colour pair of each position (2 bytes read
 // per position instead of both endpoints and their vertex bits)
-__global__ void k_keep_pc(int64_t m, const uint16_t *pcol, uint64_t cmask, const int32_t *ptime,
-                          const int32_t *ts, int32_t nts, const int32_t *parr, int32_t tcut,
-                          uint8_t *keep) {
-    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= m) return;
-    const uint32_t pc = pcol[p];
-    bool k = ((cmask >> (pc & 0xFFu)) & (cmask >> (pc >> 8)) & 1ull) != 0;
-    if (k && tcut < 0x7FFFFFFF) k = parr[p] <= tcut;
-    if (k && ts) {
-        const int32_t t = ptime[p];
-        int32_t a = 0, b = nts;
-        while (a < b) {
-            const int32_t mid = (a + b) >> 1;
-            if (ts[mid] < t) a = mid + 1;
-            else b = mid;
+__global__ void __launch_bounds__(256) k_keep_pc(int64_t m, int64_t nr, const uint16_t *pcol,
+                                                 uint64_t cmask, const int32_t *ptime,
+                                                 const int32_t *ts, int32_t nts, const int32_t *parr,
+                                                 int32_t tcut, uint32_t *keep, int32_t *kcnt) {
+    const int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (r >= nr) return;
+    const int64_t p0 = r * kRecPos + 32 * (int64_t)lane;
+    uint32_t w = 0;
+    if (lane < 31 && p0 < m) {
+        const int nv = (int)min<int64_t>(32, m - p0);
+        if (nv == 32) {
+            const uint4 *c4 = (const uint4 *)(pcol + p0);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const uint4 v = c4[i];
+                const uint32_t u[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const uint32_t pc = (u[t] >> (16 * h)) & 0xFFFFu;
+                        if ((cmask >> (pc & 0xFFu)) & (cmask >> (pc >> 8)) & 1ull)
+                            w |= 1u << (8 * i + 2 * t + h);
+                    }
+            }
+        } else {
+            for (int j = 0; j < nv; ++j) {
+                const uint32_t pc = pcol[p0 + j];
+                if ((cmask >> (pc & 0xFFu)) & (cmask >> (pc >> 8)) & 1ull) w |= 1u << j;
+            }
         }
-        k = a < nts && ts[a] == t;
+        if (w && (tcut < 0x7FFFFFFF || ts)) {  // time restrictions, kept candidates only
+            for (int j = 0; j < nv; ++j) {
+                if (!((w >> j) & 1u)) continue;
+                const int64_t p = p0 + j;
+                bool k = tcut >= 0x7FFFFFFF || parr[p] <= tcut;
+                if (k && ts) k = time_in(ts, nts, ptime[p]);
+                if (!k) w &= ~(1u << j);
+            }
+        }
     }
-    keep[p] = k ? 1 : 0;
+    put_record(w, lane, r, keep, kcnt, nr);
 }
 
 // layer keep: edge at p goes from colour cs to colour cd
@@ -249,54 +421,82 @@ __global__ void k_pcol(int64_t m, const int32_t *psrc, const int32_t *pdst, cons
 }
 
 // In-list starts of the subgraph: the kept positions before the parent's start
-// (at = exclusive count of the m kept flags, mk = their total).
-__global__ void k_sub_inptr(int32_t n, int64_t m, const int32_t *pinptr, const int32_t *at,
-                            int32_t mk, int32_t *inptr) {
+// (keep: the kept-position records, nr of them, total: their set bits).
+__global__ void k_sub_inptr(int32_t n, const int32_t *pinptr, const uint32_t *keep, int64_t nr,
+                            const int32_t *total, int32_t *inptr) {
     int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (u > n) return;
-    const int32_t x = pinptr[u];
-    inptr[u] = x < m ? at[x] : mk;
+    inptr[u] = bit_rank(keep, nr, total, pinptr[u]);
 }
 
-__global__ void k_needed(int64_t m, const int32_t *gpos, int32_t *needed) {
+__global__ void k_needed(int64_t m, const int32_t *gpos, uint8_t *needed) {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p < m && gpos[p] >= 0) needed[gpos[p]] = 1;  // every writer stores the same value
+    if (p >= m) return;
+    const int32_t q = gpos[p];
+    if (q >= 0) needed[q] = 1;  // every writer stores the same value
 }
 
-__global__ void k_compact1(int64_t m, const uint8_t *keep, const int32_t *at, const int32_t *a,
-                           int32_t *b) {
-    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p < m && keep[p]) b[at[p]] = a[p];
-}
-
-// Kept positions copied in order (at = exclusive count of the m kept flags, mk = their
-// total).  With gposw (the parent's read positions), also the read position of each
-// kept edge in the subgraph: the last kept position at or before its parent read
-// position g (positions keep their order), if that is still in the source's in-list
-// (sub_inptr: the subgraph's in-list starts); -1 otherwise.
-__global__ void k_compact(int64_t m, const uint8_t *keep, const int32_t *at, int32_t mk,
-                          const int32_t *psrc, const int32_t *pdst, const int32_t *ptau,
-                          const int32_t *peid, const int32_t *gposw, const int32_t *sub_inptr,
-                          int32_t *qsrc, int32_t *qdst, int32_t *qtau, int32_t *qeid,
-                          int32_t *qgpos) {
-    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p < m && keep[p]) {
-        const int32_t q = at[p];
-        const int32_t s = psrc[p];
-        qsrc[q] = s;
+// Kept positions copied in order, one wave per record of `keep` (the kept-position
+// records, nr of them; blocks of 256 = 4 records): the wave lists the record's kept
+// offsets in LDS (lane l those of word 1 + l, at the exclusive count of the lanes
+// before), then its lanes copy one kept position each per round, so that a wave moves
+// only kept edges whatever the density.  pdep nullable; gpar (nullable): the parent's
+// read position of each kept edge (k_remap maps it into the subgraph).
+__global__ void __launch_bounds__(256) k_compact(
+    int64_t nr, const uint32_t *keep, const int32_t *psrc, const int32_t *pdst,
+    const int32_t *ptau, const int32_t *peid, const int32_t *pdep, const int32_t *gposw,
+    int32_t *qsrc, int32_t *qdst, int32_t *qtau, int32_t *qeid, int32_t *qdep, int32_t *gpar) {
+    __shared__ uint16_t lst[4][kRecPos];
+    const int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const bool ok = r < nr;
+    uint32_t w = (ok && lane < 31) ? keep[r * 32 + 1 + lane] : 0u;
+    const int32_t base = ok ? (int32_t)keep[r * 32] : 0;
+    const int32_t c = __popc(w);
+    int32_t x = c;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int32_t y = __shfl_up(x, off);
+        if (lane >= off) x += y;
+    }
+    const int32_t K = __shfl(x, 63);
+    int32_t i = x - c;
+    while (w) {
+        const int j = __ffs(w) - 1;
+        w &= w - 1u;
+        lst[wv][i++] = (uint16_t)(32 * lane + j);
+    }
+    __syncthreads();
+    for (int32_t k = lane; k < K; k += 64) {
+        const int64_t p = r * kRecPos + lst[wv][k];
+        const int32_t q = base + k;
+        qsrc[q] = psrc[p];
         qdst[q] = pdst[p];
         qtau[q] = ptau[p];
         qeid[q] = peid[p];
-        if (gposw) {
-            int32_t r = -1;
-            const int32_t g = gposw[p];
-            if (g >= 0) {
-                const int32_t last = (g + 1 < m ? at[g + 1] : mk) - 1;
-                if (last >= sub_inptr[s]) r = last;
-            }
-            qgpos[q] = r;
-        }
+        if (pdep) qdep[q] = pdep[p];
+        if (gposw) gpar[q] = gposw[p];
     }
+}
+
+// Read positions of the subgraph's mk edges, in place of their parent read positions g:
+// the last kept position at or before g (positions keep their order; keep: the parent's
+// kept-position records, nr of them, total: their set bits), if that is still in the
+// source's in-list (sub_inptr: the subgraph's in-list starts), -1 otherwise; needed[r] =
+// 1 for every position read (one byte each).
+__global__ void k_remap(int64_t mk, const int32_t *qsrc, const uint32_t *keep, int64_t nr,
+                        const int32_t *total, const int32_t *sub_inptr, int32_t *gpos,
+                        uint8_t *needed) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= mk) return;
+    const int32_t g = gpos[q];
+    int32_t r = -1;
+    if (g >= 0) {
+        const int32_t last = bit_rank(keep, nr, total, (int64_t)g + 1) - 1;
+        if (last >= sub_inptr[qsrc[q]]) r = last;
+    }
+    gpos[q] = r;
+    if (r >= 0) needed[r] = 1;  // every writer stores the same value
 }
 
 // ---- work tiles on the device.  Per vertex u with an in-list of L positions: a long
@@ -397,9 +597,9 @@ int bits_for(uint64_t v) {  // bits needed to represent values 0..v
 // Slots of a graph arena: one grow-only buffer per index array and per temporary.
 enum ArenaSlot {
     A_COLOR, A_PDST, A_PSRC, A_PTAU, A_PEID, A_GSRC, A_OROW, A_INPTR, A_TP0, A_TPUB,
-    A_TLB, A_LDS, A_TTAB, A_KEEPC, A_KEEP, A_AT, A_SCRATCH, A_GPOS, A_NEEDED, A_ROWOF, A_TSORT,
-    A_TUNIQ, A_TCOUNT, A_CNT, A_PDEP, A_VDELAY, A_VKEEP, A_TSET, A_FID, A_TNZ, A_TPM, A_TCNT,
-    A_SCNT, A_TBASE, A_SBASE, A_TSTAT, A_VBITS, A_GPOSW, A_GPOSP, A_NSLOTS
+    A_TLB, A_LDS, A_TTAB, A_KEEPC, A_KBITS, A_KCNT, A_KBASE, A_SCRATCH, A_GPOS, A_NBITS, A_NCNT,
+    A_NBASE, A_TSORT, A_TUNIQ, A_TCOUNT, A_CNT, A_PDEP, A_VDELAY, A_VKEEP, A_TSET, A_FID, A_TNZ,
+    A_TPM, A_TCNT, A_SCNT, A_TBASE, A_SBASE, A_TSTAT, A_VBITS, A_GPOSW, A_GPOSP, A_NFLAG, A_NFLAGP, A_NSLOTS
 };
 
 struct GraphArena {
@@ -775,12 +975,14 @@ void colour_pair_counts(const Graph &G, std::vector<int64_t> &out, hipStream_t s
 // sorted by (dst, tau, input id)), G.color and G.tmax: distinct timestamps, in-list
 // offsets, gathered and stored rows, host copies, tiles and the LDS image.  taus:
 // the m timestamps in any order (device).
-// gpos_pre (nullable, device [m]): read positions already known (pruned graphs)
+// gpos_pre (nullable, device [m]): read positions already known (pruned graphs), with
+// needed_pre (nullable, m bytes): the positions they read (1) and the others (0)
 // lds_shared (nullable): an LDS image to use instead of a new one (subgraphs in an
 // arena use their parent's); need_times = false skips the distinct-timestamp table.
 void finish_index(Graph &G, int64_t &acct, const int32_t *taus, bool greedy_tiles,
                   const int32_t *gpos_pre = nullptr, hipStream_t st = nullptr,
-                  bool need_times = true, uint8_t *lds_shared = nullptr) {
+                  bool need_times = true, uint8_t *lds_shared = nullptr,
+                  uint8_t *needed_pre = nullptr) {
     const int64_t m = G.m;
     const int32_t n = G.n;
     const int32_t tmax = G.tmax;
@@ -814,36 +1016,45 @@ void finish_index(Graph &G, int64_t &acct, const int32_t *taus, bool greedy_tile
     }
     k_inptr<<<grid_for(m + 1), 256, 0, st>>>(m, n, G.pdst, G.inptr);
     if (m) {
-        int32_t *needed = tmp.get<int32_t>(A_NEEDED, m);
-        int32_t *rowof = tmp.get<int32_t>(A_ROWOF, m);
-        TPM_HIP(hipMemsetAsync(needed, 0, sizeof(int32_t) * m, st));
+        // needed positions (some edge reads them) as byte flags, then rank records; rows
+        // are their ranks
+        const int64_t nr = rank_recs(m);
+        uint8_t *flags = needed_pre;
+        if (!flags) {
+            uint8_t *nf = tmp.get<uint8_t>(A_NFLAG, m);
+            TPM_HIP(hipMemsetAsync(nf, 0, (size_t)m, st));
+            flags = nf;
+        }
         const int32_t *gpos = gpos_pre;
         if (gpos) {
-            k_needed<<<grid_for(m), 256, 0, st>>>(m, gpos, needed);
+            if (!needed_pre) k_needed<<<grid_for(m), 256, 0, st>>>(m, gpos, flags);
         } else {
             int32_t *gp = tmp.get<int32_t>(A_GPOS, m);
             k_gpos<<<grid_for(m), 256, 0, st>>>(m, G.psrc, G.ptau, G.pdep, G.vdelay, G.inptr, gp,
-                                                needed);
+                                                flags);
             gpos = gp;
         }
+        uint32_t *needed = tmp.get<uint32_t>(A_NBITS, nr * 32);
+        int32_t *ncnt = tmp.get<int32_t>(A_NCNT, nr + 1);
+        int32_t *nbase = tmp.get<int32_t>(A_NBASE, nr + 1);
+        k_pack<<<grid_for(nr * 64), 256, 0, st>>>(m, nr, flags, needed, ncnt);
         size_t sbytes = 0;
-        TPM_HIP(rocprim::exclusive_scan(nullptr, sbytes, needed, rowof, 0, (size_t)m,
+        TPM_HIP(rocprim::exclusive_scan(nullptr, sbytes, ncnt, nbase, 0, (size_t)(nr + 1),
                                         rocprim::plus<int32_t>(), st));
         void *scratch = tmp.raw(A_SCRATCH, sbytes);
-        TPM_HIP(rocprim::exclusive_scan(scratch, sbytes, needed, rowof, 0, (size_t)m,
+        TPM_HIP(rocprim::exclusive_scan(scratch, sbytes, ncnt, nbase, 0, (size_t)(nr + 1),
                                         rocprim::plus<int32_t>(), st));
-        k_rows<<<grid_for(m), 256, 0, st>>>(m, gpos, needed, rowof, G.orow, G.gsrc);
-        int32_t last_row = 0, last_needed = 0;
+        k_put_base<<<grid_for(nr), 256, 0, st>>>(nr, nbase, needed);
+        k_rows<<<(unsigned)(nr * 4), 256, 0, st>>>(m, gpos, needed, nr, nbase + nr, G.orow, G.gsrc);
+        int32_t rows = 0;
         unsigned long long *cnt = tmp.get<unsigned long long>(A_CNT, 1);
         TPM_HIP(hipMemsetAsync(cnt, 0, sizeof(unsigned long long), st));
         k_count_nonneg<<<std::min<unsigned>(grid_for(m), 4096), 256, 0, st>>>(m, G.gsrc, cnt);
         unsigned long long h = 0;
-        TPM_HIP(hipMemcpyAsync(&last_row, rowof + (m - 1), sizeof(int32_t), hipMemcpyDeviceToHost, st));
-        TPM_HIP(hipMemcpyAsync(&last_needed, needed + (m - 1), sizeof(int32_t),
-                               hipMemcpyDeviceToHost, st));
+        TPM_HIP(hipMemcpyAsync(&rows, nbase + nr, sizeof(int32_t), hipMemcpyDeviceToHost, st));
         TPM_HIP(hipMemcpyAsync(&h, cnt, sizeof(h), hipMemcpyDeviceToHost, st));
         TPM_HIP(hipStreamSynchronize(st));
-        G.R = (int64_t)last_row + last_needed;
+        G.R = (int64_t)rows;
         G.gathers = (int64_t)h;
         if (!G.arena) {  // whole graphs keep the read positions for pruning
             G.gposw = galloc<int32_t>(G, A_GPOSW, m, acct, st);
@@ -1066,10 +1277,12 @@ void prune_graph(const Graph &P, const PruneSpec &spec, Graph &G, GraphArena *ar
     int64_t acct = 0;
     try {
         int64_t mk = 0;
-        uint8_t *keep = nullptr;
-        int32_t *at = nullptr;
+        uint32_t *keep = nullptr;  // kept-position records of the parent's m positions
+        int32_t *kbase = nullptr;  // their bases (nrk + 1: the last one the total)
+        const int64_t nrk = rank_recs(P.m);
         Temps outer(arena, st);
         int32_t *gpos_pre = nullptr;  // read positions mapped from the parent's
+        uint8_t *needed_pre = nullptr;  // the positions they read (byte flags)
         {
             Temps tmp(arena, st);
             G.color = galloc<int32_t>(G, A_COLOR, P.n, acct, st);
@@ -1094,8 +1307,9 @@ void prune_graph(const Graph &P, const PruneSpec &spec, Graph &G, GraphArena *ar
                     TPM_HIP(hipMemcpyAsync(ts, times, sizeof(int32_t) * (size_t)ntimes,
                                            hipMemcpyHostToDevice, st));
                 }
-                keep = tmp.get<uint8_t>(A_KEEP, P.m);
-                at = tmp.get<int32_t>(A_AT, P.m);
+                keep = tmp.get<uint32_t>(A_KBITS, nrk * 32);
+                int32_t *kcnt = tmp.get<int32_t>(A_KCNT, nrk + 1);
+                kbase = tmp.get<int32_t>(A_KBASE, nrk + 1);
                 // timestamps of the edges as given (departures when transit times exist)
                 if (P.pcol && !vkeep_in && spec.cut_in < 0 && spec.cut_out < 0 && P.q <= 64) {
                     uint64_t cm = 0;
@@ -1103,26 +1317,27 @@ void prune_graph(const Graph &P, const PruneSpec &spec, Graph &G, GraphArena *ar
                     if (keep_color) std::copy(keep_color, keep_color + P.q, kc.begin());
                     for (int32_t c = 0; c < P.q; ++c)
                         if (kc[(size_t)c]) cm |= 1ull << c;
-                    k_keep_pc<<<grid_for(P.m), 256, 0, st>>>(P.m, P.pcol, cm, P.pdep ? P.pdep : P.ptau,
-                                                              ts, ntimes, P.ptau, spec.tcut, keep);
+                    k_keep_pc<<<grid_for(nrk * 64), 256, 0, st>>>(P.m, nrk, P.pcol, cm,
+                                                                   P.pdep ? P.pdep : P.ptau, ts,
+                                                                   ntimes, P.ptau, spec.tcut, keep,
+                                                                   kcnt);
                 } else {
-                    k_keep<<<grid_for(P.m), 256, 0, st>>>(P.m, P.psrc, P.pdst, vbits,
-                                                           P.pdep ? P.pdep : P.ptau, ts, ntimes,
-                                                           spec.cut_in, spec.cut_out, P.ptau,
-                                                           spec.tcut, keep);
+                    k_keep<<<grid_for(nrk * 64), 256, 0, st>>>(P.m, nrk, P.psrc, P.pdst, vbits,
+                                                                P.pdep ? P.pdep : P.ptau, ts, ntimes,
+                                                                spec.cut_in, spec.cut_out, P.ptau,
+                                                                spec.tcut, keep, kcnt);
                 }
                 size_t sbytes = 0;
-                TPM_HIP(rocprim::exclusive_scan(nullptr, sbytes, keep, at, 0, (size_t)P.m,
+                TPM_HIP(rocprim::exclusive_scan(nullptr, sbytes, kcnt, kbase, 0, (size_t)(nrk + 1),
                                                 rocprim::plus<int32_t>(), st));
                 void *scratch = tmp.raw(A_SCRATCH, sbytes);
-                TPM_HIP(rocprim::exclusive_scan(scratch, sbytes, keep, at, 0, (size_t)P.m,
+                TPM_HIP(rocprim::exclusive_scan(scratch, sbytes, kcnt, kbase, 0, (size_t)(nrk + 1),
                                                 rocprim::plus<int32_t>(), st));
-                int32_t last_at = 0;
-                uint8_t last_keep = 0;
-                TPM_HIP(hipMemcpyAsync(&last_at, at + (P.m - 1), sizeof(int32_t), hipMemcpyDeviceToHost, st));
-                TPM_HIP(hipMemcpyAsync(&last_keep, keep + (P.m - 1), 1, hipMemcpyDeviceToHost, st));
+                k_put_base<<<grid_for(nrk), 256, 0, st>>>(nrk, kbase, keep);
+                int32_t kept = 0;
+                TPM_HIP(hipMemcpyAsync(&kept, kbase + nrk, sizeof(int32_t), hipMemcpyDeviceToHost, st));
                 TPM_HIP(hipStreamSynchronize(st));
-                mk = (int64_t)last_at + last_keep;
+                mk = (int64_t)kept;
             }
             G.m = mk;
             G.tile_auto = P.tile_auto;
@@ -1148,19 +1363,23 @@ void prune_graph(const Graph &P, const PruneSpec &spec, Graph &G, GraphArena *ar
             if (mk) {  // kept positions stay in (dst, arrival, id) order
                 if (P.gposw) {  // read positions remapped from the parent's
                     gpos_pre = outer.get<int32_t>(A_GPOSP, mk);
-                    k_sub_inptr<<<grid_for((int64_t)P.n + 1), 256, 0, st>>>(P.n, P.m, P.inptr, at,
-                                                                            (int32_t)mk, G.inptr);
+                    needed_pre = outer.get<uint8_t>(A_NFLAGP, mk);
+                    TPM_HIP(hipMemsetAsync(needed_pre, 0, (size_t)mk, st));
+                    k_sub_inptr<<<grid_for((int64_t)P.n + 1), 256, 0, st>>>(P.n, P.inptr, keep,
+                                                                            nrk, kbase + nrk, G.inptr);
                 }
-                k_compact<<<grid_for(P.m), 256, 0, st>>>(P.m, keep, at, (int32_t)mk, P.psrc, P.pdst,
-                                                          P.ptau, P.peid, P.gposw, G.inptr, G.psrc,
-                                                          G.pdst, G.ptau, G.peid, gpos_pre);
-                if (P.pdep)
-                    k_compact1<<<grid_for(P.m), 256, 0, st>>>(P.m, keep, at, P.pdep, G.pdep);
+                k_compact<<<grid_for(nrk * 64), 256, 0, st>>>(nrk, keep, P.psrc, P.pdst,
+                                                               P.ptau, P.peid, P.pdep, P.gposw,
+                                                               G.psrc, G.pdst, G.ptau, G.peid,
+                                                               G.pdep, gpos_pre);
+                if (P.gposw)
+                    k_remap<<<grid_for(mk), 256, 0, st>>>(mk, G.psrc, keep, nrk, kbase + nrk, G.inptr,
+                                                          gpos_pre, needed_pre);
             }
             TPM_HIP(hipStreamSynchronize(st));
         }
         finish_index(G, acct, G.ptau, arena == nullptr, gpos_pre, st, spec.need_times,
-                     arena ? P.lds_image : nullptr);
+                     arena ? P.lds_image : nullptr, needed_pre);
         G.device_bytes = acct;
     } catch (...) {
         free_graph(G);

@@ -254,7 +254,11 @@ int64_t est_request_bytes(const Graph &G, int64_t mk, bool whole, int k, int C, 
     const int64_t tiles = 2 * mk / T + std::min<int64_t>(n, mk) + 1;
     int64_t arena = 0;
     if (!whole)
-        arena = 5 * G.m + 36 * mk + 44 * n + 12 * tiles + (int64_t(16) << 20);
+        // parent-sized: the kept-position rank records, their counts and bases (about
+        // m / 7); per kept edge: six index arrays (seven with departure times), the
+        // remapped read positions, the needed-position flags and their rank records; per
+        // vertex: colours, in-list starts, vertex flags
+        arena = G.m / 6 + (G.pdep ? 34 : 30) * mk + 44 * n + 12 * tiles + (int64_t(16) << 20);
     // stored rows per kept edge: colour subgraphs of the serving and batched workloads
     // keep the whole graph's ratio within 3 % (checked on samples); the 50 % margin
     // leaves room on the device (smaller margins let the largest requests take
