@@ -120,8 +120,9 @@ struct WorkspacePool {
 // Growth takes 1/8 more than asked when the device has it: a buffer of tens of GB costs
 // about a second to allocate (measured: 62 GB in 0.7-1.8 s), and requests of a stream
 // ask for sizes a few percent apart, so exact growth reallocated the largest buffers
-// again and again.
-void DBuf::alloc(size_t bytes, hipStream_t st) {
+// again and again.  Buffers sized to a budget (the row engine's) ask for `exact`: with
+// the extra eighth they crowded out the memory the budget leaves to other work.
+void DBuf::alloc(size_t bytes, hipStream_t st, bool exact) {
     bytes = std::max<size_t>(bytes, 16);
     if (bytes <= cap) return;
     if (p) {
@@ -130,13 +131,15 @@ void DBuf::alloc(size_t bytes, hipStream_t st) {
         p = nullptr;
         cap = 0;
     }
-    const size_t roomy = bytes + bytes / 8;
-    if (hipMalloc(&p, roomy) == hipSuccess) {
-        cap = roomy;
-        return;
+    if (!exact) {
+        const size_t roomy = bytes + bytes / 8;
+        if (hipMalloc(&p, roomy) == hipSuccess) {
+            cap = roomy;
+            return;
+        }
+        (void)hipGetLastError();  // clears the failed attempt
+        p = nullptr;
     }
-    (void)hipGetLastError();  // clears the failed attempt
-    p = nullptr;
     TPM_HIP(hipMalloc(&p, bytes));
     cap = bytes;
 }

@@ -150,37 +150,25 @@ __device__ __forceinline__ int32_t bit_rank(const uint32_t *rec, int64_t nr, con
     return base + c;
 }
 
-// Exclusive rank of this thread's flag within its block of 256 threads.  Every thread
-// of the block must call it.
-__device__ __forceinline__ int32_t block_rank(bool f) {
-    __shared__ int32_t wc[4];
-    const uint64_t b = __ballot(f);
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    if (lane == 0) wc[wv] = __popcll(b);
-    __syncthreads();
-    int32_t r = __popcll(b & ((1ull << lane) - 1ull));
-    for (int i = 0; i < wv; ++i) r += wc[i];
-    return r;
-}
-
 // Blocks of 256 threads over quarters of records: block b covers positions 992 (b / 4) +
-// 256 (b % 4) + t, t < 256 (the last quarter has 224).  The rank of the block's first
-// position among the set bits: the record's base plus the words of the quarters before.
-__device__ __forceinline__ int32_t quarter_base(const uint32_t *rec) {
-    const int64_t r = blockIdx.x >> 2;
-    const int qq = blockIdx.x & 3;
-    const uint32_t *w = rec + r * 32;
-    int32_t c = (int32_t)w[0];
-    for (int i = 1; i <= 8 * qq; ++i) c += __popc(w[i]);
-    return c;
-}
-
+// 256 (b % 4) + t, t < 256 (the last quarter has 224).  wave_rank gives a thread's
+// exclusive rank among the set bits from the record's base, the words before its wave's
+// 64 positions and a ballot (no LDS).
 __device__ __forceinline__ int64_t quarter_pos() {
     return (int64_t)(blockIdx.x >> 2) * kRecPos + 256 * (blockIdx.x & 3) + threadIdx.x;
 }
 
 __device__ __forceinline__ bool quarter_in(int64_t m, int64_t p) {
     return 256 * (blockIdx.x & 3) + threadIdx.x < kRecPos && p < m;
+}
+
+__device__ __forceinline__ int32_t wave_rank(const uint32_t *rec, bool f) {
+    const uint32_t *w = rec + (int64_t)(blockIdx.x >> 2) * 32;
+    const int first = 8 * (blockIdx.x & 3) + 2 * (threadIdx.x >> 6);  // bit word of lane 0
+    int32_t c = (int32_t)w[0];
+    for (int i = 0; i < first; ++i) c += __popc(w[1 + i]);
+    const uint64_t b = __ballot(f);
+    return c + __popcll(b & ((1ull << (threadIdx.x & 63)) - 1ull));
 }
 
 // Records written one wave per record: lane l < 31 gives word 1 + l (the flags of
@@ -260,7 +248,7 @@ __global__ void __launch_bounds__(256) k_rows(int64_t m, const int32_t *gpos, co
     const int64_t p = quarter_pos();
     const bool in = quarter_in(m, p);
     const bool f = in && bit_at(needed, p);
-    const int32_t r = quarter_base(needed) + block_rank(f);
+    const int32_t r = wave_rank(needed, f);
     if (!in) return;
     orow[p] = f ? r : -1;
     const int32_t q = gpos[p];
@@ -440,8 +428,10 @@ __global__ void k_needed(int64_t m, const int32_t *gpos, uint8_t *needed) {
 // records, nr of them; blocks of 256 = 4 records): the wave lists the record's kept
 // offsets in LDS (lane l those of word 1 + l, at the exclusive count of the lanes
 // before), then its lanes copy one kept position each per round, so that a wave moves
-// only kept edges whatever the density.  pdep nullable; gpar (nullable): the parent's
-// read position of each kept edge (k_remap maps it into the subgraph).
+// only kept edges whatever the density (a wave walking the record 64 positions at a
+// time without LDS measured 2 ms slower per request on the 1e9-edge graph).  pdep
+// nullable; gpar (nullable): the parent's read position of each kept edge (k_remap maps
+// it into the subgraph).
 __global__ void __launch_bounds__(256) k_compact(
     int64_t nr, const uint32_t *keep, const int32_t *psrc, const int32_t *pdst,
     const int32_t *ptau, const int32_t *peid, const int32_t *pdep, const int32_t *gposw,

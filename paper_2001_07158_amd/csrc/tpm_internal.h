@@ -127,7 +127,9 @@ struct DBuf {
     DBuf() = default;
     DBuf(const DBuf &) = delete;
     DBuf &operator=(const DBuf &) = delete;
-    void alloc(size_t bytes, hipStream_t st);  // ensures capacity (synchronises on growth)
+    // ensures capacity (synchronises on growth); takes 1/8 more when the device has it,
+    // unless `exact` (buffers sized to a budget)
+    void alloc(size_t bytes, hipStream_t st, bool exact = false);
     ~DBuf();
     template <class T>
     T *as() const { return (T *)p; }

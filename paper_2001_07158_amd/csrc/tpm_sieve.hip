@@ -2213,11 +2213,12 @@ void multi_init(const Graph &G, MultiRow &row, hipStream_t st) {
     ws.ctl.alloc(sizeof(Ctl), st);
     TPM_HIP(hipMemsetAsync(ws.ctl.p, 0, sizeof(Ctl), st));
     ws.z.alloc((size_t)G.n * 16, st);
-    ws.xt.alloc((size_t)G.n * rowb, st);
-    ws.s0.alloc((size_t)std::max<int64_t>(1, G.R) * rowb, st);
-    ws.s1.alloc((size_t)std::max<int64_t>(1, G.R) * rowb, st);
+    // sized to the server's state budget: exact
+    ws.xt.alloc((size_t)G.n * rowb, st, true);
+    ws.s0.alloc((size_t)std::max<int64_t>(1, G.R) * rowb, st, true);
+    ws.s1.alloc((size_t)std::max<int64_t>(1, G.R) * rowb, st, true);
     if (G.nslots) {
-        ws.pub.alloc((size_t)G.nslots * rowd * 8, st);
+        ws.pub.alloc((size_t)G.nslots * rowd * 8, st, true);
         TPM_HIP(hipMemsetAsync(ws.pub.p, 0, (size_t)G.nslots * rowd * 8, st));
     }
     ws.pp.alloc((size_t)rowb, st);
