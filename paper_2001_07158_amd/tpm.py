@@ -655,9 +655,11 @@ class Graph:
     def autotune(self, k, seed=1) -> dict:
         return tpm_autotune(self.h, k, seed)
 
-    def close(self):
+    def close(self, _destroy=_lib.tpm_graph_destroy):
+        # the library call is bound at definition: at interpreter exit the module's
+        # globals may already be gone when a graph is collected
         if getattr(self, "h", None):
-            tpm_graph_destroy(self.h)
+            _destroy(self.h)
             self.h = None
 
     def __del__(self):
@@ -708,9 +710,9 @@ class Server:
                 time.sleep(0.001)
         return got
 
-    def close(self):
+    def close(self, _destroy=_lib.tpm_server_destroy):
         if getattr(self, "h", None):
-            tpm_server_destroy(self.h)
+            _destroy(self.h)
             self.h = None
 
     def __del__(self):
