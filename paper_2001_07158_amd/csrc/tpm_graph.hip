@@ -1307,6 +1307,8 @@ void prune_graph(const Graph &P, const PruneSpec &spec, Graph &G, GraphArena *ar
                     if (keep_color) std::copy(keep_color, keep_color + P.q, kc.begin());
                     for (int32_t c = 0; c < P.q; ++c)
                         if (kc[(size_t)c]) cm |= 1ull << c;
+                    // both endpoints of every kept edge have a colour of cm
+                    G.edge_colors = cm;
                     k_keep_pc<<<grid_for(nrk * 64), 256, 0, st>>>(P.m, nrk, P.pcol, cm,
                                                                    P.pdep ? P.pdep : P.ptau, ts,
                                                                    ntimes, P.ptau, spec.tcut, keep,

@@ -205,6 +205,9 @@ struct Graph {
     uint16_t *pcol = nullptr;  // [m] colours of the edge's source (low byte) and head
                                //     (high byte): whole graphs with <= 64 colours
     int32_t *inptr = nullptr;  // [n+1]
+    // colour subgraphs (<= 64 colours): only vertices of these colours have edges, so
+    // the level pipeline computes vertex rows for them alone; 0 = every vertex
+    uint64_t edge_colors = 0;
     int32_t *tile_p0 = nullptr;   // [ntiles+1]
     int32_t *tile_pub = nullptr;  // [ntiles] slot this tile publishes to, -1 if none
     int32_t *tile_lb = nullptr;   // [ntiles] slot its look-back starts at, -1 if none

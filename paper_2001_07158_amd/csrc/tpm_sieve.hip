@@ -1096,11 +1096,13 @@ __global__ void k_z(int32_t n, int32_t k, const int32_t *color, const int32_t *f
 // bytes [col, col + npts) of vertex u's row (stride bytes per row).  A thread writes
 // 16 points: x^A = x^(A with its low 4 bits cleared) + x^(A's low 4 bits).
 __global__ void k_xt(int32_t n, int32_t k, int32_t npts, int32_t stride, int32_t col, uint32_t base,
-                     const uint8_t *z, uint8_t *xt) {
+                     const uint8_t *z, uint8_t *xt, const int32_t *color, uint64_t colors) {
     const int32_t per_row = (npts + 15) >> 4;  // threads per vertex row
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= (int64_t)n * per_row) return;
     int64_t u = i / per_row;
+    // colours != 0: the rows of vertices of other colours are never read (no edges)
+    if (colors && !((colors >> color[u]) & 1ull)) return;
     int32_t part = (int32_t)(i - u * per_row);
     const uint4 zz4 = ((const uint4 *)z)[u];
     const uint32_t zw[4] = {zz4.x, zz4.y, zz4.z, zz4.w};
@@ -1826,8 +1828,8 @@ void enqueue_chunks(const Graph &G, int32_t k, uint64_t seed, int rowb, int64_t 
     // lane per 16 points of a narrow row (its 1024 / rowb slots repeat the same lanes)
     const int lanes = std::max(1, rowb / 16);
     for (int64_t base = 0; base < pts_end; base += rowb) {
-        k_xt<<<grid_for((int64_t)G.n * ((rowb + 15) / 16)), 256, 0, st>>>(G.n, k, rowb, rowb, 0,
-                                                                           (uint32_t)base, B.z, B.xt);
+        k_xt<<<grid_for((int64_t)G.n * ((rowb + 15) / 16)), 256, 0, st>>>(
+            G.n, k, rowb, rowb, 0, (uint32_t)base, B.z, B.xt, G.color, G.edge_colors);
         for (int l = 2; l <= k; ++l) {
             if (req) {
                 check_cancel(*req, st);
@@ -2180,7 +2182,7 @@ void static_sieve(const Graph &G, const StaticGraph &S, const int32_t *M, int32_
         const int32_t per_row = (int32_t)((valid + 15) / 16);
         k_xt<<<grid_for((int64_t)S.n * per_row), 256, 0, st>>>(S.n, k, (int32_t)valid, (int32_t)C, 0,
                                                                 (uint32_t)base, zs.as<uint8_t>(),
-                                                                X.as<uint8_t>());
+                                                                X.as<uint8_t>(), nullptr, 0);
         // forward, Eq. (1): F_l = x * sum over in-arcs of y_{., l-1} F_{l-1}; the last
         // level adds sum_A F_k (G_k = 1)
         const uint8_t *prev = X.as<uint8_t>();
@@ -2238,7 +2240,7 @@ void multi_prepare(const Graph &G, MultiRow &row, int lane0, int npts, const int
     const int col = lane0 * 4 * row.W;
     k_z<<<grid_for(G.n), 256, 0, st>>>(G.n, k, G.color, G.fid, qs, nullptr, seed, ws.z.as<uint8_t>());
     k_xt<<<grid_for((int64_t)G.n * ((npts + 15) / 16)), 256, 0, st>>>(
-        G.n, k, npts, rowb, col, base, ws.z.as<uint8_t>(), ws.xt.as<uint8_t>());
+        G.n, k, npts, rowb, col, base, ws.z.as<uint8_t>(), ws.xt.as<uint8_t>(), nullptr, 0);
     TPM_HIP(hipMemsetAsync(ws.pp.as<uint8_t>() + col, 0, (size_t)npts, st));
     TPM_HIP(hipGetLastError());
 }

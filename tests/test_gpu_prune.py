@@ -142,3 +142,43 @@ def test_pruned_tuning_in_sieve_and_batch(tpm):
             assert r["path_status"] == tpm.TPM_OK
             assert pyref.check_path(g, q["multiset"], r["path_vertices"][:k], r["path_edges"][:k - 1])
     Gd.close()
+
+
+def _host_rows(src, dst, tau, n):
+    """Rows and gathers of an index, recomputed on the host: each edge (u -> v, t) reads
+    the last position of u's in-list (sorted by arrival) with an earlier time; rows are
+    the distinct positions read, gathers the edges that read one."""
+    if src.size == 0:
+        return 0, 0
+    T = int(tau.max()) + 1
+    keys = np.sort(dst.astype(np.int64) * T + tau)
+    q = np.searchsorted(keys, src.astype(np.int64) * T + tau, side="left") - 1
+    lo = np.searchsorted(keys, src.astype(np.int64) * T, side="left")
+    q = np.where(q >= lo, q, -1)
+    read = q[q >= 0]
+    return int(np.unique(read).size), int(read.size)
+
+
+@pytest.mark.parametrize("m", [991, 992, 993, 2976, 2977, 6000])
+def test_prune_record_boundaries(tpm, m):
+    """Kept edges are flagged in records of 992 positions and read positions and rows
+    are ranked through them: edge counts around record boundaries, every colour kept,
+    one colour kept; rows and gathers of the full graph and of each subgraph equal a
+    host recount, and the sieve equals the oracle."""
+    g = G.uniform_graph(60, m, 12, 3, 700 + m)
+    Gd = tpm.Graph.from_temporal(g, tile_edges=64)
+    st = Gd.stats()
+    assert (st["rows"], st["gathers"]) == _host_rows(g.src, g.dst, g.tau, g.n)
+    for colors in ([0, 1, 2], [1], [0, 2]):
+        say(f"case prune records m={m} colours={colors}")
+        keep = np.isin(g.color, colors)
+        e = keep[g.src] & keep[g.dst]
+        Gp = Gd.prune(colors)
+        sp = Gp.stats()
+        assert sp["m"] == int(e.sum())
+        assert (sp["rows"], sp["gathers"]) == _host_rows(g.src[e], g.dst[e], g.tau[e], g.n)
+        M = [colors[0], colors[-1], colors[0]]
+        pp, _ = Gp.sieve(M, 5 + m)
+        assert np.array_equal(pp, oracle.sieve(g, M, 5 + m))
+        Gp.close()
+    Gd.close()
