@@ -1379,6 +1379,31 @@ void prune_graph(const Graph &P, const PruneSpec &spec, Graph &G, GraphArena *ar
     }
 }
 
+namespace {
+struct W2Op {
+    __host__ __device__ W2Agg operator()(const W2Agg &a, const W2Agg &b) const {
+        W2Agg o = b;
+        if (!b.head) {
+            o.v.x ^= a.v.x;
+            o.v.y ^= a.v.y;
+            o.v.z ^= a.v.z;
+            o.v.w ^= a.v.w;
+        }
+        o.head = a.head | b.head;
+        return o;
+    }
+};
+}  // namespace
+
+size_t w2_scan(void *tmp, size_t tmp_bytes, const W2Agg *in, W2Agg *out, int64_t n, hipStream_t st) {
+    size_t bytes = 0;
+    TPM_HIP(rocprim::inclusive_scan(nullptr, bytes, in, out, (size_t)std::max<int64_t>(1, n), W2Op(), st));
+    if (!tmp) return bytes;
+    TPM_REQUIRE(tmp_bytes >= bytes, "scan storage too small");
+    TPM_HIP(rocprim::inclusive_scan(tmp, bytes, in, out, (size_t)n, W2Op(), st));
+    return bytes;
+}
+
 void sd_graph(const Graph &P, int32_t s, int32_t d, Graph &G) {
     TPM_REQUIRE(s >= 0 && s < P.n && d >= 0 && d < P.n, "vertex out of range");
     TPM_REQUIRE(s != d, "s and d must differ");

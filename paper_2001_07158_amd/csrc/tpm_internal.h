@@ -137,7 +137,7 @@ struct DBuf {
 
 // Device memory of one sieve call: level buffers, per-vertex rows, control words.
 struct Workspace {
-    DBuf ctl, z, xt, s0, s1, pub, pp, tot, mask, loc, pick, tabs, aux, aux2;
+    DBuf ctl, z, xt, s0, s1, pub, pp, tot, mask, loc, pick, tabs, aux, aux2, w2;
 };
 
 // Workspaces of a graph: a call takes one (creating it if none is free) and
@@ -295,6 +295,20 @@ GraphArena *new_graph_arena();
 void delete_graph_arena(GraphArena *a);
 
 // ------------------------------------------------------------------ sieve
+// Block aggregate of the segmented XOR scan behind level 2's coefficient form (the
+// sieve kernels): the block's value at its last position (back to its last segment
+// start) and whether a segment starts in it.
+struct W2Agg {
+    uint4 v;
+    uint32_t head;
+    uint32_t pad[3];
+};
+
+// Inclusive scan of n block aggregates under (a, b) -> (b.head ? b.v : a.v ^ b.v,
+// a.head | b.head) on st, in tmp (tmp_bytes); with tmp == nullptr only returns the bytes
+// of temporary storage it needs.
+size_t w2_scan(void *tmp, size_t tmp_bytes, const W2Agg *in, W2Agg *out, int64_t n, hipStream_t st);
+
 struct SieveRequest {
     const int32_t *multiset = nullptr;
     int32_t k = 0;

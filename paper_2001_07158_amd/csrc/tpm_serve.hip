@@ -268,6 +268,8 @@ int64_t est_request_bytes(const Graph &G, int64_t mk, bool whole, int k, int C, 
     const int64_t rowb = std::max(C, 16);
     int64_t ws = 16 * n + n * rowb + (k > 2 ? 2 : 1) * R * rowb + 2 * (mk / T + 1) * rowb +
                  std::max<int64_t>(int64_t(1) << k, rowb) + 2 * n + (int64_t(1) << 20);
+    // level 2's coefficient form: 20 bytes a row, 64 bytes per 256 positions
+    if (k > 2) ws += 20 * R + (mk / 256 + 1) * 64 + (int64_t(1) << 20);
     if (loc) ws += mk;
     return arena + ws;
 }

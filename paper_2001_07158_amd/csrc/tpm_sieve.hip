@@ -1783,10 +1783,12 @@ int pick_chunk(const Graph &G, int32_t k, int32_t requested) {
     int64_t c = requested > 0 ? requested : std::min<int64_t>(npts, 1024);
     TPM_REQUIRE((c & (c - 1)) == 0 && c >= 4 && c <= 1024, "chunk must be a power of two in [4, 1024]");
     c = std::min<int64_t>(c, std::max<int64_t>(npts, 16));
-    // fit the two level buffers into free device memory
+    // fit the two level buffers (and level 2's coefficients, 20 bytes a row) into free
+    // device memory
     size_t freeb = 0, totalb = 0;
     if (hipMemGetInfo(&freeb, &totalb) == hipSuccess && requested <= 0) {
-        while (c > 16 && (double)(2 * G.R + G.n + 2 * G.nslots) * c > 0.85 * (double)freeb) c >>= 1;
+        const double fixed = k > 2 ? 20.0 * (double)G.R : 0.0;
+        while (c > 16 && (double)(2 * G.R + G.n + 2 * G.nslots) * c + fixed > 0.85 * (double)freeb) c >>= 1;
     }
     // rows hold at least 16 points (one lane): smaller queries repeat their points
     return (int)std::max<int64_t>(c, 16);
@@ -1809,12 +1811,341 @@ namespace {
 // Device buffers of one sieve query: per-vertex z and x rows, the two level buffers,
 // published look-back words, control words, per-point accumulators (zeroed by the
 // caller) and, nullable, per-position localisation bytes of the last level.
+// ---------------------------------------------------------------------------------
+// Level 2 from coefficients.  x_u^A = XOR over j in A of z_u[j] is linear in A's
+// indicator, and GF(2^8) multiplication distributes over XOR, so the level-2 running
+// value of v's in-list after position p is
+//     x_v^A * (XOR over j in A of W_p[j]),   W_p[j] = XOR over q <= p in the list of
+//                                                    y_q * z_{src q}[j]:
+// k bytes per position instead of a row of 2^k points.  W is a segmented XOR scan
+// over the in-edge order (a segment per in-list), in blocks of 256 positions whose
+// carries are scanned apart; a stored row is then expanded once per chunk from W, z_v
+// and the LDS tables.  Bit for bit the level kernel's rows, without its gather of the
+// 1 KB x row of every edge's source.
+// ---------------------------------------------------------------------------------
+__device__ __forceinline__ uint4 xor4(uint4 a, uint4 b) {
+    return make_uint4(a.x ^ b.x, a.y ^ b.y, a.z ^ b.z, a.w ^ b.w);
+}
+
+// y_p * z_{src p}, bytewise (z rows hold zeros past byte k - 1)
+__device__ __forceinline__ uint4 w2_term(const int32_t *psrc, const int32_t *peid, const uint8_t *z,
+                                         uint64_t seed, int64_t p) {
+    const uint32_t y = fp8(seed, 1u, 1u, (uint32_t)peid[p]);
+    const uint4 zz = ((const uint4 *)z)[psrc[p]];
+    uint32_t w[4] = {zz.x, zz.y, zz.z, zz.w};
+    if (y == 0) return make_uint4(0, 0, 0, 0);
+    const uint32_t ly = c_gf.log[y];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        uint32_t o = 0;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const uint32_t b = (w[i] >> (8 * t)) & 0xFFu;
+            if (b) o |= (uint32_t)c_gf.exp[ly + c_gf.log[b]] << (8 * t);
+        }
+        w[i] = o;
+    }
+    return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+// Inclusive XOR scan of v over the block of 256 threads within segments (a segment
+// starts where head is set); open: no head from the block's first position to this
+// one.  Every thread of the block must call it.
+__device__ __forceinline__ uint4 w2_block_scan(uint4 v, bool head, bool &open) {
+    __shared__ uint4 wv[4];
+    __shared__ uint32_t wf[4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    bool f = head;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        uint4 o;
+        o.x = __shfl_up(v.x, off);
+        o.y = __shfl_up(v.y, off);
+        o.z = __shfl_up(v.z, off);
+        o.w = __shfl_up(v.w, off);
+        const int of = __shfl_up((int)f, off);
+        if (lane >= off) {
+            if (!f) v = xor4(v, o);
+            f = f || of;
+        }
+    }
+    if (lane == 63) {
+        wv[wave] = v;
+        wf[wave] = f ? 1u : 0u;
+    }
+    __syncthreads();
+    for (int u = wave - 1; u >= 0 && !f; --u) {
+        v = xor4(v, wv[u]);
+        f = wf[u] != 0;
+    }
+    open = !f;
+    return v;
+}
+
+__device__ __forceinline__ uint4 w2_position(int64_t m, const int32_t *pdst, const int32_t *psrc,
+                                             const int32_t *peid, const uint8_t *z, uint64_t seed,
+                                             int64_t p, bool &open) {
+    uint4 v = make_uint4(0, 0, 0, 0);
+    bool head = true;  // past the end: empty segments
+    if (p < m) {
+        v = w2_term(psrc, peid, z, seed, p);
+        head = p == 0 || pdst[p] != pdst[p - 1];
+    }
+    return w2_block_scan(v, head, open);
+}
+
+// per block of 256 positions: its value at its last position and whether a segment
+// starts in it
+__global__ void __launch_bounds__(256) k_w2_blocks(int64_t m, const int32_t *pdst, const int32_t *psrc,
+                                                   const int32_t *peid, const uint8_t *z, uint64_t seed,
+                                                   W2Agg *agg) {
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    bool open;
+    const uint4 v = w2_position(m, pdst, psrc, peid, z, seed, p, open);
+    if (threadIdx.x == 255) {
+        W2Agg a{};
+        a.v = v;
+        a.head = open ? 0u : 1u;
+        agg[blockIdx.x] = a;
+    }
+}
+
+// W and the in-list's vertex at every needed position (row r = orow[p]); scanned: the
+// inclusive scan of the block aggregates (carry into block b: scanned[b - 1])
+__global__ void __launch_bounds__(256) k_w2_final(int64_t m, const int32_t *pdst, const int32_t *psrc,
+                                                  const int32_t *peid, const uint8_t *z, uint64_t seed,
+                                                  const W2Agg *scanned, const int32_t *orow,
+                                                  uint4 *W, int32_t *V) {
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    bool open;
+    uint4 v = w2_position(m, pdst, psrc, peid, z, seed, p, open);
+    if (p >= m) return;
+    if (open && blockIdx.x > 0) v = xor4(v, scanned[blockIdx.x - 1].v);
+    const int32_t r = orow[p];
+    if (r >= 0) {
+        W[r] = v;
+        V[r] = pdst[p];
+    }
+}
+
+// Rows of the chunk of rowb points from base: row r, points A = base + i, byte i =
+// x_{V[r]}^A * (XOR over j in A, j < k, of W[r][j]) (bits of A from k on are ignored,
+// as in the x rows).  Persistent grid of 1024-thread blocks (the LDS tables fill the
+// CU); a thread makes 16 points of a row, four rows' worth of loads in flight (W, V,
+// then z of V: a dependent pair of loads per row that one row at a time left waiting).
+__device__ __forceinline__ uint4 w2_expand(const uint8_t *lds, uint32_t lanebits, uint32_t ebase,
+                                           uint32_t zc, int32_t k, uint32_t A0, uint4 w4, uint4 z4) {
+    const uint32_t ww[4] = {w4.x, w4.y, w4.z, w4.w}, zw[4] = {z4.x, z4.y, z4.z, z4.w};
+    uint32_t xh = 0, sh = 0;
+    for (int j = 4; j < k; ++j)
+        if ((A0 >> j) & 1u) {
+            xh ^= (zw[j >> 2] >> (8 * (j & 3))) & 0xFFu;
+            sh ^= (ww[j >> 2] >> (8 * (j & 3))) & 0xFFu;
+        }
+    uint32_t xl[16], sl[16];
+    xl[0] = sl[0] = 0;
+#pragma unroll
+    for (int b = 1; b < 16; ++b) {
+        const int j = __builtin_ctz(b);  // j < 4: bytes of the first dword
+        const uint32_t zj = j < k ? (zw[0] >> (8 * j)) & 0xFFu : 0u;
+        const uint32_t wj = j < k ? (ww[0] >> (8 * j)) & 0xFFu : 0u;
+        xl[b] = xl[b & (b - 1)] ^ zj;
+        sl[b] = sl[b & (b - 1)] ^ wj;
+    }
+    uint32_t out[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int b = 0; b < 16; ++b) {
+        const uint32_t x = xh ^ xl[b], s = sh ^ sl[b];
+        const uint32_t a = min(lds32(lds, (x << 8) | lanebits) + lds32(lds, (s << 8) | lanebits) + ebase, zc);
+        out[b >> 2] |= (uint32_t)lds[a] << (8 * (b & 3));
+    }
+    return make_uint4(out[0], out[1], out[2], out[3]);
+}
+
+__global__ void __launch_bounds__(1024) k_w2_rows(int64_t R, int32_t k, int32_t rowb, uint32_t base,
+                                                  const uint4 *W, const int32_t *V, const uint8_t *z,
+                                                  const uint8_t *lds_image, uint8_t *rows) {
+    __shared__ __attribute__((aligned(16))) uint8_t lds[kLdsBytes];
+    {
+        const uint4 *src = (const uint4 *)lds_image;
+        uint4 *dst = (uint4 *)lds;
+        for (int i = threadIdx.x; i < kLdsBytes / 16; i += blockDim.x) dst[i] = src[i];
+    }
+    __syncthreads();
+    constexpr int UR = 4;  // rows per thread per round
+    const uint32_t lanebits = (uint32_t)(threadIdx.x & 31) << 2;
+    const uint32_t ebase = (uint32_t)kExpBase + lanebits;
+    const uint32_t zc = (uint32_t)kExpBase + ((uint32_t)kClampRow << 7) + lanebits;
+    const int lp = __builtin_ctz((uint32_t)(rowb >> 4));  // parts per row: a power of two
+    const int64_t items = R << lp;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t it0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; it0 < items; it0 += UR * stride) {
+        uint4 w[UR], zz[UR];
+        int32_t v[UR];
+#pragma unroll
+        for (int u = 0; u < UR; ++u) {
+            const int64_t it = it0 + u * stride;
+            if (it < items) {
+                w[u] = W[it >> lp];
+                v[u] = V[it >> lp];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < UR; ++u)
+            if (it0 + u * stride < items) zz[u] = ((const uint4 *)z)[v[u]];
+#pragma unroll
+        for (int u = 0; u < UR; ++u) {
+            const int64_t it = it0 + u * stride;
+            if (it < items) {
+                const int64_t r = it >> lp;
+                const uint32_t part = (uint32_t)(it & ((1 << lp) - 1));
+                const uint4 o = w2_expand(lds, lanebits, ebase, zc, k, base + part * 16u, w[u], zz[u]);
+                *(uint4 *)(rows + r * (int64_t)rowb + (int64_t)part * 16) = o;
+            }
+        }
+    }
+}
+
+// Rows of 1024 points of a k = 10 query (one chunk).  Lane L makes points A = 16 L + b:
+// the bits of L are variables 4..9 (the lane's part H), those of b variables 0..3 (B),
+// and with x_H = XOR over j in H of z_j, S_H likewise of W_j,
+//   x^A S^A = K + XOR over i in B of L_i + XOR over i < j in B of q_ij,
+//   K = x_H S_H,  L_i = x_H W_i + z_i (S_H + W_i) + ... folded: z_i W_i + x_H W_i + z_i S_H,
+//   q_ij = z_i W_j + z_j W_i,
+// 21 products per lane (15 of them the same on every lane) instead of 16 per lane and
+// point group, then the 16 points by XOR.  A wave makes a row at a time; W, V and z of
+// 64 rows are loaded together, one row per lane, and broadcast row by row, the next 64
+// loaded while these are made.  Products by the LDS tables (persistent grid of
+// 1024-thread blocks).
+__global__ void __launch_bounds__(1024) k_w2_rows_q(int64_t R, const uint4 *W, const int32_t *V,
+                                                    const uint8_t *z, const uint8_t *lds_image,
+                                                    uint8_t *rows) {
+    __shared__ __attribute__((aligned(16))) uint8_t lds[kLdsBytes];
+    {
+        const uint4 *src = (const uint4 *)lds_image;
+        uint4 *dst = (uint4 *)lds;
+        for (int i = threadIdx.x; i < kLdsBytes / 16; i += blockDim.x) dst[i] = src[i];
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const uint32_t lanebits = (uint32_t)(lane & 31) << 2;
+    const uint32_t ebase = (uint32_t)kExpBase + lanebits;
+    const uint32_t zc = (uint32_t)kExpBase + ((uint32_t)kClampRow << 7) + lanebits;
+    auto lg = [&](uint32_t g) -> uint32_t { return lds32(lds, (g << 8) | lanebits); };
+    auto ex = [&](uint32_t l1, uint32_t l2) -> uint32_t { return lds[min(l1 + l2 + ebase, zc)]; };
+    const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    uint4 w4 = make_uint4(0, 0, 0, 0), z4 = make_uint4(0, 0, 0, 0);
+    if (gw * 64 + lane < R) {
+        w4 = W[gw * 64 + lane];
+        z4 = ((const uint4 *)z)[V[gw * 64 + lane]];
+    }
+    for (int64_t bi = gw; bi * 64 < R; bi += nw) {
+        // the next 64 rows' W and V now, their z half-way through these
+        const int64_t rn = (bi + nw) * 64 + lane;
+        const bool hn = rn < R;
+        uint4 wn = make_uint4(0, 0, 0, 0), zn = make_uint4(0, 0, 0, 0);
+        int32_t vn = 0;
+        if (hn) {
+            wn = W[rn];
+            vn = V[rn];
+        }
+        const int nrows = (int)min<int64_t>(64, R - bi * 64);
+        for (int t = 0; t < nrows; ++t) {
+            if (t == 32 && hn) zn = ((const uint4 *)z)[vn];
+            const uint32_t z0 = (uint32_t)__builtin_amdgcn_readlane((int)z4.x, t);
+            const uint32_t z1 = (uint32_t)__builtin_amdgcn_readlane((int)z4.y, t);
+            const uint32_t z2 = (uint32_t)__builtin_amdgcn_readlane((int)z4.z, t);
+            const uint32_t w0 = (uint32_t)__builtin_amdgcn_readlane((int)w4.x, t);
+            const uint32_t w1 = (uint32_t)__builtin_amdgcn_readlane((int)w4.y, t);
+            const uint32_t w2 = (uint32_t)__builtin_amdgcn_readlane((int)w4.z, t);
+            // variables 4..9: bytes 0..3 of dword 1 and 0..1 of dword 2
+            uint32_t xh = 0, sh = 0;
+#pragma unroll
+            for (int h = 0; h < 6; ++h) {
+                const uint32_t zb = ((h < 4 ? z1 : z2) >> (8 * (h & 3))) & 0xFFu;
+                const uint32_t wb = ((h < 4 ? w1 : w2) >> (8 * (h & 3))) & 0xFFu;
+                const bool on = (lane >> h) & 1;
+                xh ^= on ? zb : 0u;
+                sh ^= on ? wb : 0u;
+            }
+            const uint32_t lxh = lg(xh), lsh = lg(sh);
+            uint32_t lz[4], lw[4], Lc[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const uint32_t zi = (z0 >> (8 * i)) & 0xFFu, wi = (w0 >> (8 * i)) & 0xFFu;
+                lz[i] = lg(zi);
+                lw[i] = lg(wi);
+                Lc[i] = ex(lz[i], lg(sh ^ wi)) ^ ex(lxh, lw[i]);
+            }
+            uint32_t q[4][4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = a + 1; b < 4; ++b) q[a][b] = ex(lz[a], lw[b]) ^ ex(lz[b], lw[a]);
+            uint32_t val[16];
+            val[0] = ex(lxh, lsh);
+#pragma unroll
+            for (int b = 1; b < 16; ++b) {
+                const int lo = __builtin_ctz(b), rest = b & (b - 1);
+                uint32_t u2 = Lc[lo];
+#pragma unroll
+                for (int j = lo + 1; j < 4; ++j)
+                    if ((rest >> j) & 1) u2 ^= q[lo][j];
+                val[b] = val[rest] ^ u2;
+            }
+            uint32_t out[4];
+#pragma unroll
+            for (int d = 0; d < 4; ++d)
+                out[d] = pack4(val[4 * d], val[4 * d + 1], val[4 * d + 2], val[4 * d + 3]);
+            *(uint4 *)(rows + (bi * 64 + t) * 1024 + (int64_t)lane * 16) =
+                make_uint4(out[0], out[1], out[2], out[3]);
+        }
+        if (hn && nrows <= 32) zn = ((const uint4 *)z)[vn];
+        w4 = wn;
+        z4 = zn;
+    }
+}
+
 struct LevelBufs {
     uint8_t *z = nullptr, *xt = nullptr, *s0 = nullptr, *s1 = nullptr, *pp = nullptr;
     unsigned long long *pub = nullptr;
     Ctl *ctl = nullptr;
     uint8_t *loc = nullptr;
+    // level 2 from coefficients (nullable: level 2 gathers x rows): W and V per row,
+    // block aggregates and their scan, the scan's temporary storage
+    uint4 *w2W = nullptr;
+    int32_t *w2V = nullptr;
+    W2Agg *w2agg = nullptr, *w2scan = nullptr;
+    void *w2tmp = nullptr;
+    size_t w2tmp_bytes = 0;
 };
+
+// Bytes of the coefficient form of level 2 for a graph: W and V per row, two block
+// aggregates per 256 positions, the scan's temporary storage (aligned).
+size_t w2_bytes(const Graph &G, size_t &tmp_bytes) {
+    const int64_t nb = (G.m + 255) / 256;
+    tmp_bytes = w2_scan(nullptr, 0, nullptr, nullptr, nb, nullptr);
+    return (size_t)std::max<int64_t>(1, G.R) * 20 + 256 + (size_t)nb * 2 * sizeof(W2Agg) + 256 +
+           tmp_bytes;
+}
+
+// Points the LevelBufs at a w2_bytes block.
+void w2_place(const Graph &G, uint8_t *blk, size_t tmp_bytes, LevelBufs &B) {
+    const int64_t nb = (G.m + 255) / 256;
+    const size_t R = (size_t)std::max<int64_t>(1, G.R);
+    auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    size_t o = 0;
+    B.w2W = (uint4 *)(blk + o);
+    o += R * 16;
+    B.w2V = (int32_t *)(blk + o);
+    o = up(o + R * 4);
+    B.w2agg = (W2Agg *)(blk + o);
+    B.w2scan = B.w2agg + nb;
+    o = up(o + (size_t)nb * 2 * sizeof(W2Agg));
+    B.w2tmp = blk + o;
+    B.w2tmp_bytes = tmp_bytes;
+}
 
 // Enqueues levels 2..k of every chunk of rowb points in [0, pts_end) on st: the x rows
 // of the chunk, then one level kernel per level, the last one accumulating into
@@ -1827,6 +2158,15 @@ void enqueue_chunks(const Graph &G, int32_t k, uint64_t seed, int rowb, int64_t 
     // lanes holding points: 64 lanes of 16 points for 1024-point rows, else one 16-point
     // lane per 16 points of a narrow row (its 1024 / rowb slots repeat the same lanes)
     const int lanes = std::max(1, rowb / 16);
+    // level 2 from coefficients: W once for every chunk
+    const bool w2 = B.w2W != nullptr && k >= 3 && G.m > 0;
+    if (w2) {
+        const int64_t nb = (G.m + 255) / 256;
+        k_w2_blocks<<<(unsigned)nb, 256, 0, st>>>(G.m, G.pdst, G.psrc, G.peid, B.z, seed, B.w2agg);
+        w2_scan(B.w2tmp, B.w2tmp_bytes, B.w2agg, B.w2scan, nb, st);
+        k_w2_final<<<(unsigned)nb, 256, 0, st>>>(G.m, G.pdst, G.psrc, G.peid, B.z, seed, B.w2scan,
+                                                  G.orow, B.w2W, B.w2V);
+    }
     for (int64_t base = 0; base < pts_end; base += rowb) {
         k_xt<<<grid_for((int64_t)G.n * ((rowb + 15) / 16)), 256, 0, st>>>(
             G.n, k, rowb, rowb, 0, (uint32_t)base, B.z, B.xt, G.color, G.edge_colors);
@@ -1836,6 +2176,25 @@ void enqueue_chunks(const Graph &G, int32_t k, uint64_t seed, int rowb, int64_t 
                 if (req->between_levels) (*req->between_levels)(st);
             }
             const bool fin = (l == k);
+            if (l == 2 && w2) {  // rows expanded from W into s0, the level-2 output
+                const int64_t items = G.R * (rowb / 16);
+                if (items > 0) {
+                    const unsigned grid = (unsigned)std::max<int64_t>(
+                        1, std::min<int64_t>(G.num_cu, (items + 1023) / 1024));
+                    // k = 10 in 1024-point rows: the quadratic form, a wave a row
+                    const bool quad = k == 10 && rowb == 1024;
+                    const unsigned gq = (unsigned)std::max<int64_t>(
+                        1, std::min<int64_t>(G.num_cu, (G.R + 1023) / 1024));
+                    std::unique_ptr<ProfileScope> prof;
+                    if (profile) prof.reset(new ProfileScope(st, 0, l, rowb));
+                    if (quad)
+                        k_w2_rows_q<<<gq, 1024, 0, st>>>(G.R, B.w2W, B.w2V, B.z, G.lds_image, B.s0);
+                    else
+                        k_w2_rows<<<grid, 1024, 0, st>>>(G.R, k, rowb, (uint32_t)base, B.w2W, B.w2V,
+                                                         B.z, G.lds_image, B.s0);
+                }
+                continue;
+            }
             LevelParams P{};
             P.gidx = (l == 2) ? G.psrc : G.gsrc;
             P.gbase = (l == 2) ? B.xt : ((l & 1) ? B.s0 : B.s1);
@@ -1950,6 +2309,11 @@ void run_sieve_impl(const Graph &G, const SieveRequest &req, SieveResult &res, b
         B.pub = pub.as<unsigned long long>();
         B.ctl = ctl.as<Ctl>();
         B.loc = want_loc ? loc.as<uint8_t>() : nullptr;
+        if (k > 2) {
+            size_t tb = 0;
+            ws.w2.alloc(w2_bytes(G, tb), st);
+            w2_place(G, ws.w2.as<uint8_t>(), tb, B);
+        }
         enqueue_chunks(G, k, req.seed, rowb, pts_end, B, lo, hi, fin_tlo, fin_thi, &req, true, st);
     }
     k_total<<<1, 256, 0, st>>>((int32_t)npts, pp.as<uint8_t>(), tot.as<uint8_t>());
