@@ -183,10 +183,16 @@ def main() -> int:
     avg_ms = float(np.mean(kinds[dom])) if dom in kinds else float("nan")
     C = chunk_pts
     struct = 16.0 * g.m + 12.0 * st["tiles"] + float(st["segments"]) * C
+    # level 2 (k >= 3) from coefficients: a k-byte XOR scan over the positions (two passes
+    # reading dst, src and edge id, 24 bytes a position, and the row index; W and V written
+    # per row, 20 bytes) once a query, then per chunk the expansion (W, V and the z row of
+    # a row read, 36 bytes, the row written)
+    l2_scan = 28.0 * g.m + 20.0 * st["rows"]
+    l2_rows = (float(C) + 36.0) * st["rows"]
     if dom == "middle":
         alg = (st["gathers"] + st["rows"]) * float(C) + struct
     elif dom == "level2":
-        alg = (g.m + st["rows"]) * float(C) + struct
+        alg = l2_rows
     else:
         alg = st["gathers"] * float(C) + struct
     achieved = alg / (avg_ms / 1e3) / 1e9
@@ -197,15 +203,15 @@ def main() -> int:
     if dom == "middle":
         xfer = st["gathers"] * max(float(C), line_b) + st["rows"] * float(C) + struct
     elif dom == "level2":
-        xfer = g.m * max(float(C), line_b) + st["rows"] * float(C) + struct
+        xfer = l2_rows
     else:
         xfer = st["gathers"] * max(float(C), line_b) + struct
     traffic = read_traffic(C) if dom == "middle" else None
     # whole-query algorithmic bytes (all levels, all chunks)
     nchunks = max(1, (1 << k) // C)
-    q_bytes = nchunks * ((g.m + st["rows"]) * float(C) + struct
-                         + max(0, k - 3) * ((st["gathers"] + st["rows"]) * float(C) + struct)
-                         + (st["gathers"] * float(C) + struct))
+    q_bytes = l2_scan + nchunks * (l2_rows
+                                   + max(0, k - 3) * ((st["gathers"] + st["rows"]) * float(C) + struct)
+                                   + (st["gathers"] * float(C) + struct))
     hbm_alg = q_bytes / (ms_per_step / 1e3) / 1e9
 
     line = {
