@@ -2006,20 +2006,19 @@ __global__ void __launch_bounds__(1024) k_w2_rows(int64_t R, int32_t k, int32_t 
     }
 }
 
-// Rows of 1024 points of a k = 10 query (one chunk).  Lane L makes points A = 16 L + b:
-// the bits of L are variables 4..9 (the lane's part H), those of b variables 0..3 (B),
-// and with x_H = XOR over j in H of z_j, S_H likewise of W_j,
+// Rows of P = 2^k points of a query of 4 <= k <= 10 (one chunk).  A row has P / 16
+// lanes; lane l of a row makes points A = 16 l + b: the bits of l are variables 4..k-1
+// (the lane's part H), those of b variables 0..3 (B), and with x_H = XOR over j in H of
+// z_j and S_H likewise of W_j,
 //   x^A S^A = K + XOR over i in B of L_i + XOR over i < j in B of q_ij,
-//   K = x_H S_H,  L_i = x_H W_i + z_i (S_H + W_i) + ... folded: z_i W_i + x_H W_i + z_i S_H,
-//   q_ij = z_i W_j + z_j W_i,
-// 21 products per lane (15 of them the same on every lane) instead of 16 per lane and
-// point group, then the 16 points by XOR.  A wave makes a row at a time; W, V and z of
-// 64 rows are loaded together, one row per lane, and broadcast row by row, the next 64
-// loaded while these are made.  Products by the LDS tables (persistent grid of
-// 1024-thread blocks).
-__global__ void __launch_bounds__(1024) k_w2_rows_q(int64_t R, const uint4 *W, const int32_t *V,
-                                                    const uint8_t *z, const uint8_t *lds_image,
-                                                    uint8_t *rows) {
+//   K = x_H S_H,  L_i = z_i (S_H + W_i) + x_H W_i,  q_ij = z_i W_j + z_j W_i:
+// 21 products a lane instead of 16 per group of 16 points, then the points by XOR.  W,
+// V and z of 64 rows are loaded together, one row per lane, and passed to the lanes of
+// each row by shuffles, the next 64 loaded while these are made.  Products by the LDS
+// tables (persistent grid of 1024-thread blocks).
+__global__ void __launch_bounds__(1024) k_w2_rows_q(int64_t R, int32_t k, const uint4 *W,
+                                                    const int32_t *V, const uint8_t *z,
+                                                    const uint8_t *lds_image, uint8_t *rows) {
     __shared__ __attribute__((aligned(16))) uint8_t lds[kLdsBytes];
     {
         const uint4 *src = (const uint4 *)lds_image;
@@ -2033,6 +2032,11 @@ __global__ void __launch_bounds__(1024) k_w2_rows_q(int64_t R, const uint4 *W, c
     const uint32_t zc = (uint32_t)kExpBase + ((uint32_t)kClampRow << 7) + lanebits;
     auto lg = [&](uint32_t g) -> uint32_t { return lds32(lds, (g << 8) | lanebits); };
     auto ex = [&](uint32_t l1, uint32_t l2) -> uint32_t { return lds[min(l1 + l2 + ebase, zc)]; };
+    const int nh = k - 4;                // variables from the lane's index in its row
+    const int lr = 1 << nh;              // lanes per row
+    const int rpw = 64 >> nh;            // rows a wave makes per round
+    const int grp = lane >> nh, li = lane & (lr - 1);
+    const int64_t P = (int64_t)lr * 16;  // points (bytes) per row
     const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
     uint4 w4 = make_uint4(0, 0, 0, 0), z4 = make_uint4(0, 0, 0, 0);
@@ -2046,26 +2050,29 @@ __global__ void __launch_bounds__(1024) k_w2_rows_q(int64_t R, const uint4 *W, c
         const bool hn = rn < R;
         uint4 wn = make_uint4(0, 0, 0, 0), zn = make_uint4(0, 0, 0, 0);
         int32_t vn = 0;
+        bool zdone = false;
         if (hn) {
             wn = W[rn];
             vn = V[rn];
         }
         const int nrows = (int)min<int64_t>(64, R - bi * 64);
-        for (int t = 0; t < nrows; ++t) {
-            if (t == 32 && hn) zn = ((const uint4 *)z)[vn];
-            const uint32_t z0 = (uint32_t)__builtin_amdgcn_readlane((int)z4.x, t);
-            const uint32_t z1 = (uint32_t)__builtin_amdgcn_readlane((int)z4.y, t);
-            const uint32_t z2 = (uint32_t)__builtin_amdgcn_readlane((int)z4.z, t);
-            const uint32_t w0 = (uint32_t)__builtin_amdgcn_readlane((int)w4.x, t);
-            const uint32_t w1 = (uint32_t)__builtin_amdgcn_readlane((int)w4.y, t);
-            const uint32_t w2 = (uint32_t)__builtin_amdgcn_readlane((int)w4.z, t);
-            // variables 4..9: bytes 0..3 of dword 1 and 0..1 of dword 2
+        for (int t0 = 0; t0 < nrows; t0 += rpw) {
+            if (t0 >= 32 && !zdone) {
+                if (hn) zn = ((const uint4 *)z)[vn];
+                zdone = true;
+            }
+            const int src = t0 + grp;  // the lane that holds this lane's row
+            const uint32_t z0 = (uint32_t)__shfl((int)z4.x, src), z1 = (uint32_t)__shfl((int)z4.y, src);
+            const uint32_t z2 = (uint32_t)__shfl((int)z4.z, src);
+            const uint32_t w0 = (uint32_t)__shfl((int)w4.x, src), w1 = (uint32_t)__shfl((int)w4.y, src);
+            const uint32_t w2 = (uint32_t)__shfl((int)w4.z, src);
+            // variables 4..k-1: bytes 0..3 of dword 1 and 0..1 of dword 2
             uint32_t xh = 0, sh = 0;
 #pragma unroll
             for (int h = 0; h < 6; ++h) {
                 const uint32_t zb = ((h < 4 ? z1 : z2) >> (8 * (h & 3))) & 0xFFu;
                 const uint32_t wb = ((h < 4 ? w1 : w2) >> (8 * (h & 3))) & 0xFFu;
-                const bool on = (lane >> h) & 1;
+                const bool on = h < nh && ((li >> h) & 1);
                 xh ^= on ? zb : 0u;
                 sh ^= on ? wb : 0u;
             }
@@ -2098,10 +2105,11 @@ __global__ void __launch_bounds__(1024) k_w2_rows_q(int64_t R, const uint4 *W, c
 #pragma unroll
             for (int d = 0; d < 4; ++d)
                 out[d] = pack4(val[4 * d], val[4 * d + 1], val[4 * d + 2], val[4 * d + 3]);
-            *(uint4 *)(rows + (bi * 64 + t) * 1024 + (int64_t)lane * 16) =
-                make_uint4(out[0], out[1], out[2], out[3]);
+            if (src < nrows)
+                *(uint4 *)(rows + (bi * 64 + src) * P + (int64_t)li * 16) =
+                    make_uint4(out[0], out[1], out[2], out[3]);
         }
-        if (hn && nrows <= 32) zn = ((const uint4 *)z)[vn];
+        if (hn && !zdone) zn = ((const uint4 *)z)[vn];
         w4 = wn;
         z4 = zn;
     }
@@ -2181,14 +2189,14 @@ void enqueue_chunks(const Graph &G, int32_t k, uint64_t seed, int rowb, int64_t 
                 if (items > 0) {
                     const unsigned grid = (unsigned)std::max<int64_t>(
                         1, std::min<int64_t>(G.num_cu, (items + 1023) / 1024));
-                    // k = 10 in 1024-point rows: the quadratic form, a wave a row
-                    const bool quad = k == 10 && rowb == 1024;
+                    // one chunk of 2^k points, 4 <= k <= 10: the quadratic form per lane
+                    const bool quad = k >= 4 && k <= 10 && rowb == (1 << k);
                     const unsigned gq = (unsigned)std::max<int64_t>(
                         1, std::min<int64_t>(G.num_cu, (G.R + 1023) / 1024));
                     std::unique_ptr<ProfileScope> prof;
                     if (profile) prof.reset(new ProfileScope(st, 0, l, rowb));
                     if (quad)
-                        k_w2_rows_q<<<gq, 1024, 0, st>>>(G.R, B.w2W, B.w2V, B.z, G.lds_image, B.s0);
+                        k_w2_rows_q<<<gq, 1024, 0, st>>>(G.R, k, B.w2W, B.w2V, B.z, G.lds_image, B.s0);
                     else
                         k_w2_rows<<<grid, 1024, 0, st>>>(G.R, k, rowb, (uint32_t)base, B.w2W, B.w2V,
                                                          B.z, G.lds_image, B.s0);
