@@ -168,7 +168,7 @@ int64_t workspace_bytes(const Workspace *w) {
     if (!w) return 0;
     int64_t b = 0;
     for (const DBuf *d : {&w->ctl, &w->z, &w->xt, &w->s0, &w->s1, &w->pub, &w->pp, &w->tot,
-                          &w->mask, &w->loc, &w->pick, &w->tabs, &w->aux, &w->aux2})
+                          &w->mask, &w->loc, &w->pick, &w->tabs, &w->aux, &w->aux2, &w->w2})
         b += (int64_t)d->cap;
     return b;
 }
@@ -177,7 +177,7 @@ void workspace_trim(Workspace *w) {
     if (!w || workspace_bytes(w) == 0) return;
     TPM_HIP(hipDeviceSynchronize());
     for (DBuf *d : {&w->ctl, &w->z, &w->xt, &w->s0, &w->s1, &w->pub, &w->pp, &w->tot, &w->mask,
-                    &w->loc, &w->pick, &w->tabs, &w->aux, &w->aux2}) {
+                    &w->loc, &w->pick, &w->tabs, &w->aux, &w->aux2, &w->w2}) {
         if (d->p) (void)hipFree(d->p);
         d->p = nullptr;
         d->cap = 0;
