@@ -1827,21 +1827,34 @@ __device__ __forceinline__ uint4 xor4(uint4 a, uint4 b) {
     return make_uint4(a.x ^ b.x, a.y ^ b.y, a.z ^ b.z, a.w ^ b.w);
 }
 
+// The field's log and exp tables in LDS for a block (768 bytes; the constant-memory
+// copy costs a vector memory load per lookup).  Every thread must call it.
+struct W2Tabs {
+    uint8_t exp[512];
+    uint8_t log[256];
+};
+
+__device__ __forceinline__ void w2_tabs_load(W2Tabs &t) {
+    for (int i = threadIdx.x; i < 512; i += blockDim.x) t.exp[i] = c_gf.exp[i];
+    for (int i = threadIdx.x; i < 256; i += blockDim.x) t.log[i] = c_gf.log[i];
+    __syncthreads();
+}
+
 // y_p * z_{src p}, bytewise (z rows hold zeros past byte k - 1)
-__device__ __forceinline__ uint4 w2_term(const int32_t *psrc, const int32_t *peid, const uint8_t *z,
-                                         uint64_t seed, int64_t p) {
+__device__ __forceinline__ uint4 w2_term(const W2Tabs &tb, const int32_t *psrc, const int32_t *peid,
+                                         const uint8_t *z, uint64_t seed, int64_t p) {
     const uint32_t y = fp8(seed, 1u, 1u, (uint32_t)peid[p]);
     const uint4 zz = ((const uint4 *)z)[psrc[p]];
     uint32_t w[4] = {zz.x, zz.y, zz.z, zz.w};
     if (y == 0) return make_uint4(0, 0, 0, 0);
-    const uint32_t ly = c_gf.log[y];
+    const uint32_t ly = tb.log[y];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         uint32_t o = 0;
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
             const uint32_t b = (w[i] >> (8 * t)) & 0xFFu;
-            if (b) o |= (uint32_t)c_gf.exp[ly + c_gf.log[b]] << (8 * t);
+            if (b) o |= (uint32_t)tb.exp[ly + tb.log[b]] << (8 * t);
         }
         w[i] = o;
     }
@@ -1885,10 +1898,12 @@ __device__ __forceinline__ uint4 w2_block_scan(uint4 v, bool head, bool &open) {
 __device__ __forceinline__ uint4 w2_position(int64_t m, const int32_t *pdst, const int32_t *psrc,
                                              const int32_t *peid, const uint8_t *z, uint64_t seed,
                                              int64_t p, bool &open) {
+    __shared__ W2Tabs tb;
+    w2_tabs_load(tb);
     uint4 v = make_uint4(0, 0, 0, 0);
     bool head = true;  // past the end: empty segments
     if (p < m) {
-        v = w2_term(psrc, peid, z, seed, p);
+        v = w2_term(tb, psrc, peid, z, seed, p);
         head = p == 0 || pdst[p] != pdst[p - 1];
     }
     return w2_block_scan(v, head, open);
